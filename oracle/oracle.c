@@ -1,0 +1,763 @@
+/*
+ * oracle.c -- plain, slow CPU reference for the cell-list neighbour operators
+ * and the dense kernel sum of Robinson & Bruna, "Particle-based and Meshless
+ * Methods with Aboria" (arXiv:1704.08907).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may include, link or
+ * call this file: only the test-suite, the smoke check and the benchmark's CPU
+ * baseline leg use it.  It shares no code, header, table or constant generator
+ * with the GPU library.
+ *
+ * What it computes (paper citations by section / equation / listing):
+ *   - The problem instance (Section 1): N points in a d-dimensional hypercube
+ *     [lo, hi), each dimension periodic or not; operators defined only by the
+ *     positions and per-particle variables.
+ *   - The cell list (Section 2.2.1, "Aboria Level 1"): a square lattice of
+ *     hypercube cells of width at least the cutoff (the worked example sets the
+ *     width to r_cut, Section 3), each holding zero or more particles.  This
+ *     file builds it twice: as cell ids + a stable counting sort (cell order,
+ *     original index order inside a cell), and as the serial-insertion
+ *     head/next linked list that Section 2.2.1 mentions as the second design.
+ *   - The box search (Section 2.2.2, "Aboria Level 2"): candidates of particle
+ *     i are the particles in i's cell and the adjacent cells.
+ *   - The radius-limited sum (Section 3, eq. (1) and the velocity-update
+ *     listing): y_i = sum over j with 0 < |dx_ij| < r of f_ij, with dx_ij the
+ *     shortest (minimum-image) vector r_j - r_i.  The norm(dx) > 0 condition
+ *     of the listing excludes j = i and coincident points.
+ *   - The dense global kernel sum of the RBF / Gaussian-process methods
+ *     (Section 1 and Section 1.1): y_i = sum_j K(x_i, x_j) w_j over all j.
+ *
+ * Readings the paper leaves open (each listed in the design notes):
+ *   R1 cell count per dimension: n = floor(L/r), then decreased while n > 1 and
+ *      L/n < r + 16 u (|lo| + L), u the unit roundoff of the input precision,
+ *      so that rounding in the cell assignment can never hide a pair.
+ *   R2 cell of a coordinate: clamp(floor(fl(fl(x - lo) * fl(n / L))), 0, n-1);
+ *      linear id = c0 + n0 (c1 + n1 c2); x == hi, x < lo or NaN is a domain
+ *      error.
+ *   R3 pair predicate, evaluated in the input precision P with this exact
+ *      operation order: t_k = fl(x_jk - x_ik); dx_k = fl(t_k + s_k) with
+ *      s_k in {-L, 0, +L} the periodic image shift; d2 = fma chain
+ *      fma(dx2, dx2, fma(dx1, dx1, dx0*dx0)); pair iff 0 < d2 < fl(r*r).
+ *   R4 summands are then evaluated in float64 from the P-rounded data.
+ *   R5 operators: spring F_i = sum k (r - s) u/s with u = x_i - x_j; soft
+ *      sphere e_i = 1/2 sum (1 - s/r)^2; the paper's eq. (1) force
+ *      y_i = sum -c exp(-s) dx/s; a spring with per-particle resting lengths
+ *      y_i = sum k (a_i + a_j - s) u/s (the DEM example of Section 1.1).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_ERR_INVALID 1
+#define OR_ERR_DOMAIN 2
+#define OR_ERR_UNSUPPORTED 3
+#define OR_ERR_NOMEM 4
+
+#define OR_F32 0
+#define OR_F64 1
+
+#define OR_OP_COUNT 0
+#define OR_OP_SPRING 1
+#define OR_OP_SOFT_SPHERE 2
+#define OR_OP_EXP_FORCE 3
+#define OR_OP_DEM_SPRING 4
+
+#define OR_ROUTE_BRUTE 0
+#define OR_ROUTE_CELLS 1
+
+typedef struct or_grid {
+    int32_t d;
+    int32_t dtype;
+    int32_t periodic[3];
+    int32_t n[3];
+    double lo[3];
+    double hi[3];
+    double L[3];
+    double inv_w[3];
+    double r;
+    double r2;
+    int64_t ncells;
+} or_grid;
+
+/* Round a double to the working precision P. */
+static double to_p(int dtype, double v) { return dtype == OR_F32 ? (double)(float)v : v; }
+
+static double unit_roundoff(int dtype) { return dtype == OR_F32 ? ldexp(1.0, -24) : ldexp(1.0, -53); }
+
+/* ------------------------------------------------------------------------ */
+/* Cell grid: readings R1 and R2 above.                                      */
+/* ------------------------------------------------------------------------ */
+
+int or_grid_init(or_grid* g, int32_t d, int32_t dtype, const double* lo, const double* hi,
+                 const int32_t* periodic, double r, const int32_t* ncell_req) {
+    memset(g, 0, sizeof(*g));
+    if (d < 1 || d > 3 || (dtype != OR_F32 && dtype != OR_F64)) return OR_ERR_INVALID;
+    g->d = d;
+    g->dtype = dtype;
+    g->r = to_p(dtype, r);
+    if (!(g->r > 0.0) || isinf(g->r)) return OR_ERR_INVALID;
+    if (dtype == OR_F32) {
+        float rf = (float)g->r;
+        g->r2 = (double)(rf * rf);
+    } else {
+        g->r2 = g->r * g->r;
+    }
+    double u = unit_roundoff(dtype);
+    int64_t total = 1;
+    for (int k = 0; k < 3; ++k) {
+        g->n[k] = 1;
+        g->inv_w[k] = 0.0;
+    }
+    for (int k = 0; k < d; ++k) {
+        g->lo[k] = to_p(dtype, lo[k]);
+        g->hi[k] = to_p(dtype, hi[k]);
+        g->periodic[k] = periodic ? (periodic[k] != 0) : 0;
+        if (!isfinite(g->lo[k]) || !isfinite(g->hi[k]) || !(g->hi[k] > g->lo[k])) return OR_ERR_INVALID;
+        if (dtype == OR_F32)
+            g->L[k] = (double)((float)g->hi[k] - (float)g->lo[k]);
+        else
+            g->L[k] = g->hi[k] - g->lo[k];
+        double guard = g->r + 16.0 * u * (fabs(g->lo[k]) + g->L[k]);
+        double q = floor(g->L[k] / g->r);
+        int64_t nmax = q < 1.0 ? 1 : (q > 2147483647.0 ? 2147483647 : (int64_t)q);
+        while (nmax > 1 && g->L[k] / (double)nmax < guard) --nmax;
+        int64_t nk = nmax;
+        if (ncell_req && ncell_req[k] > 0) {
+            if (ncell_req[k] > nmax) return OR_ERR_INVALID; /* cells narrower than the guard */
+            nk = ncell_req[k];
+        }
+        /* a periodic dimension must hold at most one image of a point within r */
+        if (g->periodic[k] && g->L[k] < 2.0 * guard) return OR_ERR_UNSUPPORTED;
+        g->n[k] = (int32_t)nk;
+        g->inv_w[k] = to_p(dtype, (double)nk / g->L[k]);
+        total *= nk;
+        if (total > 2147483647LL) return OR_ERR_UNSUPPORTED;
+    }
+    g->ncells = total;
+    return OR_OK;
+}
+
+/* Cell coordinate of one P-rounded coordinate value; sets *bad on a domain error. */
+static int32_t cell_coord(const or_grid* g, int k, double xk, int* bad) {
+    if (!(xk >= g->lo[k]) || !(xk < g->hi[k])) *bad = 1;
+    double q;
+    if (g->dtype == OR_F32) {
+        float t = (float)xk - (float)g->lo[k];
+        q = (double)(t * (float)g->inv_w[k]);
+    } else {
+        double t = xk - g->lo[k];
+        q = t * g->inv_w[k];
+    }
+    double f = floor(q);
+    if (!(f >= 0.0)) return 0; /* negative or NaN */
+    if (f > (double)(g->n[k] - 1)) return g->n[k] - 1;
+    return (int32_t)f;
+}
+
+static uint32_t linear_id(const or_grid* g, const int32_t* c) {
+    uint32_t id = (uint32_t)c[0];
+    if (g->d > 1) id += (uint32_t)g->n[0] * (uint32_t)c[1];
+    if (g->d > 2) id += (uint32_t)g->n[0] * (uint32_t)g->n[1] * (uint32_t)c[2];
+    return id;
+}
+
+/* ids[i] = linear cell id of point i.  Returns OR_ERR_DOMAIN (ids still filled, clamped) on bad points. */
+int or_cell_ids(const or_grid* g, int64_t n, const double* x, uint32_t* ids) {
+    int bad = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t c[3] = {0, 0, 0};
+        for (int k = 0; k < g->d; ++k) c[k] = cell_coord(g, k, x[i * g->d + k], &bad);
+        ids[i] = linear_id(g, c);
+    }
+    return bad ? OR_ERR_DOMAIN : OR_OK;
+}
+
+/* Stable counting sort by cell id: perm[s] = original index of the s-th point in
+ * cell order (original index order inside a cell); off[c] = number of points in
+ * cells < c, for c = 0..ncells. */
+int or_sort_cells(const or_grid* g, int64_t n, const uint32_t* ids, uint32_t* perm, uint32_t* off) {
+    int64_t nc = g->ncells;
+    int64_t* cnt = (int64_t*)calloc((size_t)nc + 1, sizeof(int64_t));
+    if (!cnt) return OR_ERR_NOMEM;
+    for (int64_t i = 0; i < n; ++i) cnt[ids[i] + 1] += 1;
+    for (int64_t c = 0; c < nc; ++c) cnt[c + 1] += cnt[c];
+    for (int64_t c = 0; c <= nc; ++c) off[c] = (uint32_t)cnt[c];
+    for (int64_t i = 0; i < n; ++i) perm[cnt[ids[i]]++] = (uint32_t)i;
+    free(cnt);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Pair predicate, reading R3.                                               */
+/* ------------------------------------------------------------------------ */
+
+static int pair_pred(const or_grid* g, const double* xi, const double* xj, const double* s) {
+    if (g->dtype == OR_F32) {
+        float dx[3] = {0.f, 0.f, 0.f};
+        for (int k = 0; k < g->d; ++k) {
+            float t = (float)xj[k] - (float)xi[k];
+            dx[k] = t + (float)s[k];
+        }
+        float d2 = dx[0] * dx[0];
+        if (g->d > 1) d2 = fmaf(dx[1], dx[1], d2);
+        if (g->d > 2) d2 = fmaf(dx[2], dx[2], d2);
+        return d2 > 0.0f && d2 < (float)g->r2;
+    } else {
+        double dx[3] = {0., 0., 0.};
+        for (int k = 0; k < g->d; ++k) {
+            double t = xj[k] - xi[k];
+            dx[k] = t + s[k];
+        }
+        double d2 = dx[0] * dx[0];
+        if (g->d > 1) d2 = fma(dx[1], dx[1], d2);
+        if (g->d > 2) d2 = fma(dx[2], dx[2], d2);
+        return d2 > 0.0 && d2 < g->r2;
+    }
+}
+
+/* Minimum-image shift for the brute-force route: in each periodic dimension the
+ * s in {0, -L, +L} (first one on ties) that minimises |fl(fl(x_j - x_i) + s)|. */
+static void min_image_shift(const or_grid* g, const double* xi, const double* xj, double* s) {
+    for (int k = 0; k < 3; ++k) s[k] = 0.0;
+    for (int k = 0; k < g->d; ++k) {
+        if (!g->periodic[k]) continue;
+        const double cand[3] = {0.0, -g->L[k], g->L[k]};
+        double best = INFINITY;
+        for (int m = 0; m < 3; ++m) {
+            double v;
+            if (g->dtype == OR_F32) {
+                float t = (float)xj[k] - (float)xi[k];
+                v = fabs((double)(t + (float)cand[m]));
+            } else {
+                double t = xj[k] - xi[k];
+                v = fabs(t + cand[m]);
+            }
+            if (v < best) {
+                best = v;
+                s[k] = cand[m];
+            }
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Neighbour enumeration over the two routes.                                */
+/* ------------------------------------------------------------------------ */
+
+typedef void (*visit_fn)(void* ctx, int64_t i, int64_t j, const double* shift);
+
+typedef struct {
+    int32_t* head;
+    int32_t* next;
+} linked_cells;
+
+/* Serial insertion into a head/next list, inserting from the last point to the
+ * first so that a cell's list is traversed in increasing original index. */
+static int build_linked(const or_grid* g, int64_t n, const double* x, linked_cells* lc) {
+    lc->head = (int32_t*)malloc(sizeof(int32_t) * (size_t)g->ncells);
+    lc->next = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    if (!lc->head || !lc->next) return OR_ERR_NOMEM;
+    for (int64_t c = 0; c < g->ncells; ++c) lc->head[c] = -1;
+    int bad = 0;
+    for (int64_t i = n - 1; i >= 0; --i) {
+        int32_t c[3] = {0, 0, 0};
+        for (int k = 0; k < g->d; ++k) c[k] = cell_coord(g, k, x[i * g->d + k], &bad);
+        uint32_t id = linear_id(g, c);
+        lc->next[i] = lc->head[id];
+        lc->head[id] = (int32_t)i;
+    }
+    return bad ? OR_ERR_DOMAIN : OR_OK;
+}
+
+static void free_linked(linked_cells* lc) {
+    free(lc->head);
+    free(lc->next);
+}
+
+/* Box search for point i: its cell and the adjacent cells (3^d offsets).  A
+ * periodic dimension wraps, and the wrap becomes the image shift of the
+ * neighbour cell; a non-periodic dimension drops offsets outside the grid. */
+static void visit_cells(const or_grid* g, const linked_cells* lc, const double* x, int64_t i,
+                        visit_fn fn, void* ctx) {
+    int bad = 0;
+    int32_t c[3] = {0, 0, 0};
+    for (int k = 0; k < g->d; ++k) c[k] = cell_coord(g, k, x[i * g->d + k], &bad);
+    int nstencil = 1;
+    for (int k = 0; k < g->d; ++k) nstencil *= 3;
+    for (int m = 0; m < nstencil; ++m) {
+        int32_t cn[3] = {0, 0, 0};
+        double s[3] = {0.0, 0.0, 0.0};
+        int rest = m, skip = 0;
+        for (int k = 0; k < g->d; ++k) {
+            int o = rest % 3 - 1;
+            rest /= 3;
+            int32_t v = c[k] + o;
+            if (v < 0) {
+                if (!g->periodic[k]) { skip = 1; break; }
+                v += g->n[k];
+                s[k] = -g->L[k];
+            } else if (v >= g->n[k]) {
+                if (!g->periodic[k]) { skip = 1; break; }
+                v -= g->n[k];
+                s[k] = g->L[k];
+            }
+            cn[k] = v;
+        }
+        if (skip) continue;
+        uint32_t id = linear_id(g, cn);
+        for (int32_t j = lc->head[id]; j >= 0; j = lc->next[j]) {
+            if (pair_pred(g, x + i * g->d, x + (int64_t)j * g->d, s)) fn(ctx, i, j, s);
+        }
+    }
+}
+
+static void visit_brute(const or_grid* g, int64_t n, const double* x, int64_t i, visit_fn fn, void* ctx) {
+    for (int64_t j = 0; j < n; ++j) {
+        double s[3];
+        min_image_shift(g, x + i * g->d, x + j * g->d, s);
+        if (pair_pred(g, x + i * g->d, x + j * g->d, s)) fn(ctx, i, j, s);
+    }
+}
+
+/* Visit the accepted neighbours of each requested row by the chosen route. */
+static int for_rows(const or_grid* g, int route, int64_t n, const double* x, int64_t nrows,
+                    const int64_t* rows, visit_fn fn, void** ctxs, void (*row_begin)(void*, int64_t, int64_t),
+                    void* rctx) {
+    linked_cells lc = {0, 0};
+    int st = OR_OK;
+    if (route == OR_ROUTE_CELLS) {
+        st = build_linked(g, n, x, &lc);
+        if (st == OR_ERR_NOMEM) { free_linked(&lc); return st; }
+    }
+    int64_t m = rows ? nrows : n;
+    for (int64_t r = 0; r < m; ++r) {
+        int64_t i = rows ? rows[r] : r;
+        if (i < 0 || i >= n) continue;
+        if (row_begin) row_begin(rctx, r, i);
+        if (route == OR_ROUTE_CELLS)
+            visit_cells(g, &lc, x, i, fn, ctxs[0]);
+        else
+            visit_brute(g, n, x, i, fn, ctxs[0]);
+    }
+    if (route == OR_ROUTE_CELLS) free_linked(&lc);
+    return st;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Pair lists.                                                               */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int64_t count, cap;
+    uint32_t* pi;
+    uint32_t* pj;
+} pair_list_ctx;
+
+static void add_pair(void* vctx, int64_t i, int64_t j, const double* s) {
+    (void)s;
+    pair_list_ctx* c = (pair_list_ctx*)vctx;
+    if (c->count < c->cap) {
+        c->pi[c->count] = (uint32_t)i;
+        c->pj[c->count] = (uint32_t)j;
+    }
+    c->count += 1;
+}
+
+/* All ordered pairs (i, j) by the chosen route; returns the pair count (which
+ * may exceed cap: only the first cap are stored), or -1 on an allocation failure. */
+int64_t or_pairs(const or_grid* g, int32_t route, int64_t n, const double* x, int64_t cap, uint32_t* pi,
+                 uint32_t* pj) {
+    pair_list_ctx c = {0, cap, pi, pj};
+    void* ctxs[1] = {&c};
+    int st = for_rows(g, route, n, x, 0, NULL, add_pair, ctxs, NULL, NULL);
+    if (st == OR_ERR_NOMEM) return -1;
+    return c.count;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Operators (reading R5), summed in float64 (reading R4).                    */
+/* ------------------------------------------------------------------------ */
+
+int32_t or_op_ny(int32_t op, int32_t d) {
+    switch (op) {
+        case OR_OP_COUNT: return 1;
+        case OR_OP_SPRING: return d;
+        case OR_OP_SOFT_SPHERE: return 1;
+        case OR_OP_EXP_FORCE: return d;
+        case OR_OP_DEM_SPRING: return d;
+        default: return -1;
+    }
+}
+
+int32_t or_op_na(int32_t op) { return op == OR_OP_DEM_SPRING ? 1 : 0; }
+
+/* u = x_i - x_j - shift in float64 (x_j + shift is the image of j nearest i). */
+static double pair_u(const or_grid* g, const double* xi, const double* xj, const double* s, double* u) {
+    double s2 = 0.0;
+    for (int k = 0; k < 3; ++k) u[k] = 0.0;
+    for (int k = 0; k < g->d; ++k) {
+        u[k] = (xi[k] - xj[k]) - s[k];
+        s2 += u[k] * u[k];
+    }
+    return sqrt(s2);
+}
+
+/* Radial profile g(s) of the vector operators f = g(s) u, and its derivative. */
+static double radial_g(int op, const double* prm, double r, double s, double ai, double aj, double* dg) {
+    switch (op) {
+        case OR_OP_SPRING: {
+            double k = prm[0];
+            *dg = -k * r / (s * s);
+            return k * (r - s) / s;
+        }
+        case OR_OP_EXP_FORCE: {
+            /* eq. (1): f_ij = -c exp(-|dx|) dx/|dx| with dx = -u, i.e. g = c exp(-s)/s */
+            double c = prm[0];
+            double e = exp(-s);
+            *dg = -c * e * (s + 1.0) / (s * s);
+            return c * e / s;
+        }
+        case OR_OP_DEM_SPRING: {
+            double k = prm[0];
+            double rest = ai + aj;
+            *dg = -k * rest / (s * s);
+            return k * (rest - s) / s;
+        }
+        default:
+            *dg = 0.0;
+            return 0.0;
+    }
+}
+
+typedef struct {
+    const or_grid* g;
+    int op;
+    const double* prm;
+    const double* x;
+    const double* a;
+    int ny;
+    double* yrow;
+    double* srow;
+} sum_ctx;
+
+static void sum_begin(void* vctx, int64_t r, int64_t i) {
+    (void)i;
+    sum_ctx* c = (sum_ctx*)((void**)vctx)[0];
+    double* y = (double*)((void**)vctx)[1];
+    double* sc = (double*)((void**)vctx)[2];
+    c->yrow = y + r * c->ny;
+    c->srow = sc ? sc + r : NULL;
+    for (int m = 0; m < c->ny; ++m) c->yrow[m] = 0.0;
+    if (c->srow) *c->srow = 0.0;
+}
+
+static void sum_pair(void* vctx, int64_t i, int64_t j, const double* s) {
+    sum_ctx* c = (sum_ctx*)vctx;
+    const or_grid* g = c->g;
+    double u[3];
+    double dist = pair_u(g, c->x + i * g->d, c->x + j * g->d, s, u);
+    double ai = c->a ? c->a[i] : 0.0, aj = c->a ? c->a[j] : 0.0;
+    switch (c->op) {
+        case OR_OP_COUNT:
+            c->yrow[0] += 1.0;
+            if (c->srow) *c->srow += 1.0;
+            break;
+        case OR_OP_SOFT_SPHERE: {
+            double v = 1.0 - dist / g->r;
+            double term = 0.5 * v * v;
+            c->yrow[0] += term;
+            if (c->srow) *c->srow += fabs(term);
+            break;
+        }
+        default: {
+            double dg;
+            double gv = radial_g(c->op, c->prm, g->r, dist, ai, aj, &dg);
+            double mx = 0.0;
+            for (int k = 0; k < g->d; ++k) {
+                double t = gv * u[k];
+                c->yrow[k] += t;
+                if (fabs(t) > mx) mx = fabs(t);
+            }
+            if (c->srow) *c->srow += mx;
+            break;
+        }
+    }
+}
+
+/* y[row][ny] = sum over the accepted neighbours of the requested rows (all rows
+ * if rows == NULL); scale[row] = sum of the summands' max-norms (the
+ * absolute-sum scale the tolerance is relative to).  a is [n] or NULL. */
+int or_pair_sum(const or_grid* g, int32_t route, int32_t op, const double* prm, int64_t n, const double* x,
+                const double* a, int64_t nrows, const int64_t* rows, double* y, double* scale) {
+    int ny = or_op_ny(op, g->d);
+    if (ny < 0) return OR_ERR_INVALID;
+    if (or_op_na(op) && !a) return OR_ERR_INVALID;
+    sum_ctx c = {g, op, prm, x, a, ny, NULL, NULL};
+    void* begin_ctx[3] = {&c, y, scale};
+    void* ctxs[1] = {&c};
+    int st = for_rows(g, route, n, x, nrows, rows, sum_pair, ctxs, sum_begin, begin_ctx);
+    return st == OR_ERR_NOMEM ? st : OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Adjoint: gradient of L = sum_i gy_i . y_i with respect to x (and a).      */
+/* For f(x_a, x_b) = g(s) u_ab the Jacobian in x_a is g I + (g'/s) u u^T and  */
+/* the Jacobian in x_b is its negative, so over the symmetric pair set        */
+/*   gx_k = sum_i [ g w + (g'/s)(u_ki . w) u_ki ],  w = gy_k - gy_i.          */
+/* For the soft sphere e_a = 1/2 sum_b phi(s_ab), phi = (1 - s/r)^2:          */
+/*   gx_k = sum_i 1/2 (gy_k + gy_i) phi'(s) u_ki/s.                           */
+/* For the per-particle resting length: ga_k = sum_i k (gy_k - gy_i).u_ki/s.  */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    const or_grid* g;
+    int op;
+    const double* prm;
+    const double* x;
+    const double* a;
+    const double* gy;
+    int ny;
+    double* gxrow;
+    double* garow;
+    double* sxrow;
+    double* sarow;
+} bwd_ctx;
+
+static void bwd_begin(void* vctx, int64_t r, int64_t i) {
+    (void)i;
+    void** v = (void**)vctx;
+    bwd_ctx* c = (bwd_ctx*)v[0];
+    double* gx = (double*)v[1];
+    double* ga = (double*)v[2];
+    double* sx = (double*)v[3];
+    double* sa = (double*)v[4];
+    c->gxrow = gx + r * c->g->d;
+    c->garow = ga ? ga + r : NULL;
+    c->sxrow = sx ? sx + r : NULL;
+    c->sarow = sa ? sa + r : NULL;
+    for (int k = 0; k < c->g->d; ++k) c->gxrow[k] = 0.0;
+    if (c->garow) *c->garow = 0.0;
+    if (c->sxrow) *c->sxrow = 0.0;
+    if (c->sarow) *c->sarow = 0.0;
+}
+
+static void bwd_pair(void* vctx, int64_t k, int64_t i, const double* s) {
+    bwd_ctx* c = (bwd_ctx*)vctx;
+    const or_grid* g = c->g;
+    int d = g->d;
+    double u[3];
+    double dist = pair_u(g, c->x + k * d, c->x + i * d, s, u);
+    const double* gyk = c->gy + k * c->ny;
+    const double* gyi = c->gy + i * c->ny;
+    if (c->op == OR_OP_COUNT) return;
+    if (c->op == OR_OP_SOFT_SPHERE) {
+        double dphi = -(2.0 / g->r) * (1.0 - dist / g->r);
+        double coef = 0.5 * (gyk[0] + gyi[0]) * dphi / dist;
+        double mx = 0.0;
+        for (int m = 0; m < d; ++m) {
+            double t = coef * u[m];
+            c->gxrow[m] += t;
+            if (fabs(t) > mx) mx = fabs(t);
+        }
+        if (c->sxrow) *c->sxrow += mx;
+        return;
+    }
+    double ak = c->a ? c->a[k] : 0.0, ai = c->a ? c->a[i] : 0.0;
+    double dg;
+    double gv = radial_g(c->op, c->prm, g->r, dist, ak, ai, &dg);
+    double w[3] = {0, 0, 0};
+    double uw = 0.0;
+    for (int m = 0; m < d; ++m) {
+        w[m] = gyk[m] - gyi[m];
+        uw += u[m] * w[m];
+    }
+    double mx = 0.0;
+    for (int m = 0; m < d; ++m) {
+        double t = gv * w[m] + (dg / dist) * uw * u[m];
+        c->gxrow[m] += t;
+        double bound = fabs(gv * w[m]) + fabs((dg / dist) * uw * u[m]);
+        if (bound > mx) mx = bound;
+    }
+    if (c->sxrow) *c->sxrow += mx;
+    if (c->op == OR_OP_DEM_SPRING && c->garow) {
+        double t = c->prm[0] * uw / dist;
+        *c->garow += t;
+        if (c->sarow) *c->sarow += fabs(t);
+    }
+}
+
+/* gx[row][d], ga[row] (DEM spring only, else may be NULL); scale_x / scale_a as
+ * in or_pair_sum.  gy is [n][ny] in original order. */
+int or_pair_sum_backward(const or_grid* g, int32_t route, int32_t op, const double* prm, int64_t n,
+                         const double* x, const double* a, const double* gy, int64_t nrows, const int64_t* rows,
+                         double* gx, double* ga, double* scale_x, double* scale_a) {
+    int ny = or_op_ny(op, g->d);
+    if (ny < 0) return OR_ERR_INVALID;
+    if (or_op_na(op) && !a) return OR_ERR_INVALID;
+    bwd_ctx c = {g, op, prm, x, a, gy, ny, NULL, NULL, NULL, NULL};
+    void* begin_ctx[5] = {&c, gx, ga, scale_x, scale_a};
+    void* ctxs[1] = {&c};
+    int st = for_rows(g, route, n, x, nrows, rows, bwd_pair, ctxs, bwd_begin, begin_ctx);
+    return st == OR_ERR_NOMEM ? st : OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Local central finite differences of L = sum_i gy_i . y_i.                 */
+/* The pairs of point k are taken at the unperturbed positions (canonical     */
+/* predicate), then L's dependence on coordinate (k, m) -- or on a_k -- is    */
+/* evaluated in float64 at +h and -h:                                          */
+/*   L_k = sum_{i in P(k)} [ gy_k . f(x_k, x_i) + gy_i . f(x_i, x_k) ].        */
+/* coords[q] < n*d selects x[k][m] with q = k*d + m; coords[q] >= n*d selects  */
+/* a[coords[q] - n*d].                                                         */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int64_t count, cap;
+    int64_t* j;
+    double* s;
+} nb_list;
+
+static void nb_add(void* vctx, int64_t i, int64_t j, const double* s) {
+    (void)i;
+    nb_list* L = (nb_list*)vctx;
+    if (L->count < L->cap) {
+        L->j[L->count] = j;
+        for (int k = 0; k < 3; ++k) L->s[L->count * 3 + k] = s[k];
+    }
+    L->count += 1;
+}
+
+/* one ordered-pair summand f(x_a, x_b) with u = xa - xb - s (float64) dotted with gya */
+static double pair_term_dot(const or_grid* g, int op, const double* prm, const double* xa, const double* xb,
+                            const double* s, double aa, double ab, const double* gya) {
+    double u[3];
+    double dist = pair_u(g, xa, xb, s, u);
+    if (op == OR_OP_COUNT) return gya[0];
+    if (op == OR_OP_SOFT_SPHERE) {
+        double v = 1.0 - dist / g->r;
+        return gya[0] * 0.5 * v * v;
+    }
+    double dg;
+    double gv = radial_g(op, prm, g->r, dist, aa, ab, &dg);
+    double acc = 0.0;
+    for (int m = 0; m < g->d; ++m) acc += gya[m] * gv * u[m];
+    return acc;
+}
+
+int or_fd_grad(const or_grid* g, int32_t op, const double* prm, int64_t n, const double* x, const double* a,
+               const double* gy, int64_t ncoord, const int64_t* coords, double h, double* out) {
+    int d = g->d;
+    int ny = or_op_ny(op, d);
+    if (ny < 0) return OR_ERR_INVALID;
+    linked_cells lc = {0, 0};
+    if (build_linked(g, n, x, &lc) == OR_ERR_NOMEM) { free_linked(&lc); return OR_ERR_NOMEM; }
+    nb_list nb = {0, 0, NULL, NULL};
+    nb.cap = 4096;
+    nb.j = (int64_t*)malloc(sizeof(int64_t) * nb.cap);
+    nb.s = (double*)malloc(sizeof(double) * 3 * nb.cap);
+    int st = OR_OK;
+    for (int64_t q = 0; q < ncoord && st == OR_OK; ++q) {
+        int64_t c = coords[q];
+        int is_a = c >= n * d;
+        int64_t k = is_a ? c - n * d : c / d;
+        int m = is_a ? -1 : (int)(c % d);
+        nb.count = 0;
+        visit_cells(g, &lc, x, k, nb_add, &nb);
+        if (nb.count > nb.cap) { st = OR_ERR_NOMEM; break; }
+        double val[2];
+        for (int side = 0; side < 2; ++side) {
+            double xk[3] = {0, 0, 0};
+            for (int t = 0; t < d; ++t) xk[t] = x[k * d + t];
+            double ak = a ? a[k] : 0.0;
+            double delta = side == 0 ? h : -h;
+            if (is_a) ak += delta; else xk[m] += delta;
+            double acc = 0.0;
+            for (int64_t p = 0; p < nb.count; ++p) {
+                int64_t i = nb.j[p];
+                const double* s = nb.s + p * 3;
+                double ai = a ? a[i] : 0.0;
+                double sneg[3] = {-s[0], -s[1], -s[2]};
+                acc += pair_term_dot(g, op, prm, xk, x + i * d, s, ak, ai, gy + k * ny);
+                acc += pair_term_dot(g, op, prm, x + i * d, xk, sneg, ai, ak, gy + i * ny);
+            }
+            val[side] = acc;
+        }
+        out[q] = (val[0] - val[1]) / (2.0 * h);
+    }
+    free(nb.j);
+    free(nb.s);
+    free_linked(&lc);
+    return st;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Dense Gaussian kernel sum (Section 1 / 1.1, RBF and Gaussian processes):  */
+/*   y_i = sum_j exp(-|x_i - x_j|^2 / (2 sigma^2)) w_j over every source j,   */
+/* j = i included; float64 from the given (P-rounded) inputs.  scale[row] =   */
+/* sum_j |K_ij w_j|.                                                          */
+/* ------------------------------------------------------------------------ */
+
+int or_dense_gauss(int32_t d, int64_t nt, const double* xt, int64_t ns, const double* xs, const double* w,
+                   double sigma, int64_t nrows, const int64_t* rows, double* y, double* scale) {
+    if (d < 1 || d > 3 || !(sigma > 0.0)) return OR_ERR_INVALID;
+    double inv = 1.0 / (2.0 * sigma * sigma);
+    int64_t m = rows ? nrows : nt;
+    for (int64_t r = 0; r < m; ++r) {
+        int64_t i = rows ? rows[r] : r;
+        double acc = 0.0, sc = 0.0;
+        for (int64_t j = 0; j < ns; ++j) {
+            double d2 = 0.0;
+            for (int k = 0; k < d; ++k) {
+                double t = xt[i * d + k] - xs[j * d + k];
+                d2 += t * t;
+            }
+            double term = exp(-d2 * inv) * w[j];
+            acc += term;
+            sc += fabs(term);
+        }
+        y[r] = acc;
+        if (scale) scale[r] = sc;
+    }
+    return OR_OK;
+}
+
+/* Number of ordered pairs that the float64 predicate 0 < |u| < r would classify
+ * differently from the canonical predicate in precision P (informational). */
+int64_t or_tie_band(const or_grid* g, int64_t n, const double* x) {
+    linked_cells lc = {0, 0};
+    if (build_linked(g, n, x, &lc) == OR_ERR_NOMEM) { free_linked(&lc); return -1; }
+    int64_t diff = 0;
+    int d = g->d;
+    for (int64_t i = 0; i < n; ++i) {
+        int bad = 0;
+        int32_t c[3] = {0, 0, 0};
+        for (int k = 0; k < d; ++k) c[k] = cell_coord(g, k, x[i * d + k], &bad);
+        int nst = 1;
+        for (int k = 0; k < d; ++k) nst *= 3;
+        for (int mm = 0; mm < nst; ++mm) {
+            int32_t cn[3] = {0, 0, 0};
+            double s[3] = {0, 0, 0};
+            int rest = mm, skip = 0;
+            for (int k = 0; k < d; ++k) {
+                int o = rest % 3 - 1;
+                rest /= 3;
+                int32_t v = c[k] + o;
+                if (v < 0) { if (!g->periodic[k]) { skip = 1; break; } v += g->n[k]; s[k] = -g->L[k]; }
+                else if (v >= g->n[k]) { if (!g->periodic[k]) { skip = 1; break; } v -= g->n[k]; s[k] = g->L[k]; }
+                cn[k] = v;
+            }
+            if (skip) continue;
+            for (int32_t j = lc.head[linear_id(g, cn)]; j >= 0; j = lc.next[j]) {
+                double u[3];
+                double dist = pair_u(g, x + i * d, x + (int64_t)j * d, s, u);
+                int p64 = dist > 0.0 && dist < g->r;
+                int pp = pair_pred(g, x + i * d, x + (int64_t)j * d, s);
+                if (p64 != pp) ++diff;
+            }
+        }
+    }
+    free_linked(&lc);
+    return diff;
+}

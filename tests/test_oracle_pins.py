@@ -1,0 +1,390 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+None of these re-types the oracle's own formulas: each checks a hand-computed
+value (tests/golden), a closed form, an invariant (Newton's third law,
+translation and relabelling invariance, lattice symmetry), agreement of two
+independent routes (brute force over all pairs vs the linked-list cell list),
+or finite differences.  Each is chosen so that a plausible slip in the oracle
+(a dropped term, a flipped sign, a wrong index or shift) fails at least one.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1704_08907_amd import synthetic as syn
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def load(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+# --------------------------------------------------------------------------
+# hand case
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_hand_case_cells_pairs_and_sums(prec):
+    t = load("t1_hand_case.json")
+    x = np.array(t["x"], dtype=np.float64)
+    g = oracle.grid(t["d"], t["lo"], t["hi"], t["periodic"], t["cutoff"], prec, t["ncell"])
+    ids, st = oracle.cell_ids(g, x)
+    assert st == oracle.OK
+    assert ids.tolist() == t["cell_ids"]
+    perm, off = oracle.sort_cells(g, ids)
+    assert perm.tolist() == t["perm"]
+    assert off[8:13].tolist() == t["offsets_8_to_12"]
+    for route in (oracle.ROUTE_BRUTE, oracle.ROUTE_CELLS):
+        assert oracle.pairs(g, x, route).tolist() == t["pairs"]
+        y, _ = oracle.pair_sum(g, "count", (), x, route=route)
+        assert y[:, 0].tolist() == t["count"]
+        y, _ = oracle.pair_sum(g, "spring", (1.0,), x, route=route)
+        np.testing.assert_array_equal(y, np.array(t["spring_k1"]))
+        e, _ = oracle.pair_sum(g, "soft_sphere", (), x, route=route)
+        np.testing.assert_array_equal(e[:, 0], np.array(t["soft_sphere_energy"]))
+        gx, _, _, _ = oracle.pair_sum_backward(g, "soft_sphere", (), x, np.ones((6, 1)), route=route)
+        np.testing.assert_array_equal(gx, np.array(t["soft_sphere_grad_gy1"]))
+
+
+def test_hand_case_auto_grid_same_pairs():
+    t = load("t1_hand_case.json")
+    x = np.array(t["x"])
+    g = oracle.grid(t["d"], t["lo"], t["hi"], t["periodic"], t["cutoff"], "f64")
+    assert g.ncell == [7, 7]  # floor(1/0.125) = 8 sits exactly on the cutoff: the guard drops it
+    assert oracle.pairs(g, x).tolist() == t["pairs"]
+
+
+# --------------------------------------------------------------------------
+# cell grid rule
+# --------------------------------------------------------------------------
+
+def test_grid_rule_unit_square_r01():
+    g = oracle.grid(2, [0, 0], [1, 1], [1, 1], 0.1, "f64")
+    assert g.ncell == [9, 9]  # L/10 equals r exactly, so the guard takes 9
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.grid(2, [0, 0], [1, 1], [1, 1], 0.1, "f64", ncell=[10, 10])
+    assert e.value.code == oracle.ERR_INVALID
+    g = oracle.grid(2, [0, 0], [1, 1], [1, 1], 0.1, "f64", ncell=[3, 5])
+    assert g.ncell == [3, 5]
+
+
+def test_grid_rule_cube_and_limits():
+    L = syn.side_for_density(1 << 20, 3, 30.0)
+    g = oracle.grid(3, [0] * 3, [L] * 3, [1] * 3, 1.0, "f32")
+    assert g.ncell == [52, 52, 52] and g.ncells == 140608
+    L4 = syn.side_for_density(1 << 18, 3, 40.0)
+    g = oracle.grid(3, [0] * 3, [L4] * 3, [1] * 3, 1.0, "f32")
+    assert g.ncell == [30, 30, 30]
+    # periodic side below 2r: more than one image within r -> unsupported
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.grid(2, [0, 0], [1.9, 3], [1, 1], 1.0, "f32")
+    assert e.value.code == oracle.ERR_UNSUPPORTED
+    # non-periodic side below r is fine: a single cell
+    g = oracle.grid(2, [0, 0], [0.5, 3], [0, 0], 1.0, "f32")
+    assert g.ncell == [1, 2]  # 3/3 equals r exactly: the guard drops to 2
+    for bad in ([1, 0], [0, 0]):
+        with pytest.raises(oracle.OracleError):
+            oracle.grid(2, [0, 0], bad, [0, 0], 0.1, "f32")
+    with pytest.raises(oracle.OracleError):
+        oracle.grid(2, [0, 0], [1, 1], [0, 0], -1.0, "f32")
+
+
+def test_domain_errors():
+    g = oracle.grid(2, [0, 0], [1, 1], [1, 1], 0.1, "f64")
+    _, st = oracle.cell_ids(g, np.array([[0.5, 0.5], [1.0, 0.2]]))
+    assert st == oracle.ERR_DOMAIN  # x == hi lies outside the half-open box
+    _, st = oracle.cell_ids(g, np.array([[0.5, np.nan]]))
+    assert st == oracle.ERR_DOMAIN
+    _, st = oracle.cell_ids(g, np.array([[-1e-9, 0.5]]))
+    assert st == oracle.ERR_DOMAIN
+    ids, st = oracle.cell_ids(g, np.array([[0.0, 0.0], [np.nextafter(1.0, 0), 0.0]]))
+    assert st == oracle.OK and ids.tolist() == [0, 8]
+
+
+# --------------------------------------------------------------------------
+# sort invariants
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_sort_invariants(prec):
+    rng = syn.SplitMix64(11)
+    x = syn.uniform_positions(rng, 3000, [0, 0, 0], [5, 4, 3], prec)
+    g = oracle.grid(3, [0, 0, 0], [5, 4, 3], [1, 0, 1], 0.7, prec)
+    ids, st = oracle.cell_ids(g, x)
+    assert st == oracle.OK
+    perm, off = oracle.sort_cells(g, ids)
+    assert sorted(perm.tolist()) == list(range(3000))
+    k = ids[perm]
+    assert np.all(np.diff(k.astype(np.int64)) >= 0)
+    same = np.diff(k.astype(np.int64)) == 0
+    assert np.all(np.diff(perm.astype(np.int64))[same] > 0)  # stable inside a cell
+    counts = np.bincount(ids, minlength=g.ncells)
+    assert off[0] == 0 and off[-1] == 3000
+    np.testing.assert_array_equal(np.diff(off.astype(np.int64)), counts)
+
+
+# --------------------------------------------------------------------------
+# two independent routes agree; relabelling and translation invariance
+# --------------------------------------------------------------------------
+
+def _near_boundary_points(rng, g, n):
+    """Points placed within a few ulps of cell faces, where rounding decides."""
+    d = g.d
+    x = np.zeros((n, d))
+    prec = np.float32 if g.dtype == oracle.F32 else np.float64
+    for k in range(d):
+        w = g.L[k] / g.n[k]
+        c = np.floor(rng.uniform(n) * g.n[k])
+        base = (g.lo[k] + c * w).astype(prec)
+        ulps = np.floor(rng.uniform(n) * 9).astype(np.int64) - 4
+        col = base.copy()
+        for i in range(n):
+            v = col[i]
+            for _ in range(abs(ulps[i])):
+                v = np.nextafter(v, prec(np.inf) if ulps[i] > 0 else prec(-np.inf))
+            col[i] = v
+        col = np.clip(col, prec(g.lo[k]), np.nextafter(prec(g.hi[k]), prec(-np.inf)))
+        x[:, k] = col
+    return x
+
+
+CASES = [
+    # d, hi, periodic, r, prec, ncell
+    (1, [10.0], [1], 1.0, "f32", None),
+    (1, [3.0], [0], 1.0, "f64", None),
+    (2, [1.0, 1.0], [1, 1], 0.1, "f64", None),
+    (2, [2.1, 2.6], [1, 1], 1.0, "f32", [1, 2]),      # n = 1 and 2 per side: wrapped offsets alias
+    (2, [2.1, 2.6], [1, 1], 1.0, "f64", None),
+    (2, [3.0, 2.0], [0, 1], 0.9, "f32", None),
+    (3, [4.0, 3.0, 5.0], [1, 1, 1], 1.0, "f32", None),
+    (3, [4.0, 3.0, 5.0], [0, 0, 0], 1.0, "f32", None),
+    (3, [4.0, 3.0, 5.0], [1, 0, 1], 0.8, "f64", [2, 3, 4]),
+    (3, [2.2, 2.3, 2.4], [1, 1, 1], 1.0, "f32", None),  # n = 2 everywhere
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_brute_force_equals_cell_list(case):
+    d, hi, per, r, prec, ncell = case
+    g = oracle.grid(d, [0.0] * d, hi, per, r, prec, ncell)
+    rng = syn.SplitMix64(1234 + d)
+    x = syn.uniform_positions(rng, 700, [0.0] * d, hi, prec).astype(np.float64)
+    xb = _near_boundary_points(rng, g, 300)
+    x = np.concatenate([x, xb])
+    pb = oracle.pairs(g, x, oracle.ROUTE_BRUTE)
+    pc = oracle.pairs(g, x, oracle.ROUTE_CELLS)
+    assert pb.shape[0] > 0
+    np.testing.assert_array_equal(pb, pc)
+    # pair sets are symmetric
+    sw = pb[:, ::-1]
+    sw = sw[np.lexsort((sw[:, 1], sw[:, 0]))]
+    np.testing.assert_array_equal(pb, sw)
+    # the sums over the two routes agree to float64 rounding
+    yb, _ = oracle.pair_sum(g, "spring", (1.0,), x, route=oracle.ROUTE_BRUTE)
+    yc, _ = oracle.pair_sum(g, "spring", (1.0,), x, route=oracle.ROUTE_CELLS)
+    np.testing.assert_allclose(yb, yc, rtol=0, atol=1e-12)
+
+
+def test_relabelling_equivariance():
+    L = syn.side_for_density(4000, 3, 30.0)
+    g = oracle.grid(3, [0] * 3, [L] * 3, [1] * 3, 1.0, "f32")
+    rng = syn.SplitMix64(77)
+    x = syn.uniform_positions(rng, 4000, [0] * 3, [L] * 3, "f32").astype(np.float64)
+    p = np.argsort(rng.uniform(4000))
+    pairs = oracle.pairs(g, x)
+    pairs_p = oracle.pairs(g, x[p])
+    inv = np.empty_like(p); inv[p] = np.arange(4000)
+    mapped = np.stack([p[pairs_p[:, 0]], p[pairs_p[:, 1]]], axis=1).astype(np.uint32)
+    mapped = mapped[np.lexsort((mapped[:, 1], mapped[:, 0]))]
+    np.testing.assert_array_equal(mapped, pairs)
+    y, _ = oracle.pair_sum(g, "spring", (1.0,), x)
+    yp, _ = oracle.pair_sum(g, "spring", (1.0,), x[p])
+    np.testing.assert_allclose(yp, y[p], rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_periodic_translation_invariance(prec):
+    # points on a dyadic grid, translated by a dyadic vector and wrapped: exact in P
+    L = 8.0
+    rng = syn.SplitMix64(5150)
+    x = np.floor(syn.SplitMix64(99).uniform(3 * 3000).reshape(3000, 3) * L * 4096) / 4096
+    t = np.array([1.25, 7.5, 3.0625])
+    xt = np.mod(x + t, L)
+    g = oracle.grid(3, [0] * 3, [L] * 3, [1] * 3, 1.0, prec)
+    assert oracle.pairs(g, x).tolist() == oracle.pairs(g, xt).tolist()
+    e, _ = oracle.pair_sum(g, "soft_sphere", (), x)
+    et, _ = oracle.pair_sum(g, "soft_sphere", (), xt)
+    assert abs(e.sum() - et.sum()) <= 1e-12 * e.sum()
+    assert e.sum() > 0 and np.all(e >= 0)
+    f, _ = oracle.pair_sum(g, "spring", (1.0,), x)
+    ft, _ = oracle.pair_sum(g, "spring", (1.0,), xt)
+    np.testing.assert_allclose(f, ft, rtol=0, atol=1e-12)
+    del rng
+
+
+# --------------------------------------------------------------------------
+# closed forms
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_two_particle_closed_forms(d):
+    hi = [4.0] * d
+    g = oracle.grid(d, [0.0] * d, hi, [1] * d, 1.0, "f64")
+    u = np.array([0.3, -0.4, 0.2][:d])
+    xa = np.array([1.0, 2.0, 3.0][:d])
+    x = np.stack([xa, xa - u])  # u = x_0 - x_1
+    s = float(np.linalg.norm(u))
+    k, c = 2.5, 0.75
+    y, _ = oracle.pair_sum(g, "spring", (k,), x)
+    np.testing.assert_allclose(y[0], k * (1.0 - s) * u / s, rtol=1e-14)   # repulsive: along +u
+    np.testing.assert_allclose(y[1], -k * (1.0 - s) * u / s, rtol=1e-14)
+    y, _ = oracle.pair_sum(g, "exp_force", (c,), x)
+    dx = -u  # eq. (1): dx_01 = r_1 - r_0 = -u; f = -c exp(-|dx|) dx/|dx|
+    np.testing.assert_allclose(y[0], -c * math.exp(-s) * dx / s, rtol=1e-14)
+    y, _ = oracle.pair_sum(g, "soft_sphere", (), x)
+    np.testing.assert_allclose(y[:, 0], [0.5 * (1 - s) ** 2] * 2, rtol=1e-14)
+    a = np.array([0.2, 0.35])
+    y, _ = oracle.pair_sum(g, "dem_spring", (k,), x, a=a)
+    np.testing.assert_allclose(y[0], k * (0.55 - s) * u / s, rtol=1e-12)
+    y, _ = oracle.pair_sum(g, "count", (), x)
+    assert y[:, 0].tolist() == [1.0, 1.0]
+
+
+def test_two_particle_across_periodic_face():
+    g = oracle.grid(2, [0, 0], [4, 4], [1, 1], 1.0, "f64")
+    x = np.array([[0.1, 2.0], [3.7, 2.0]])  # separated by 0.4 through the face at 0 == 4
+    y, _ = oracle.pair_sum(g, "spring", (1.0,), x)
+    # u_01 = x_0 - image(x_1) = 0.1 - (3.7 - 4) = +0.4: particle 0 pushed in +x
+    np.testing.assert_allclose(y[0], [0.6, 0.0], rtol=1e-12)
+    np.testing.assert_allclose(y[1], [-0.6, 0.0], rtol=1e-12)
+    gnp = oracle.grid(2, [0, 0], [4, 4], [0, 0], 1.0, "f64")
+    y, _ = oracle.pair_sum(gnp, "spring", (1.0,), x)
+    assert np.all(y == 0)
+
+
+@pytest.mark.parametrize("d,expect", [(2, 8), (3, 18)])
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_lattice_special_case(d, expect, prec):
+    m = 8
+    a = 0.125
+    grid_pts = np.stack(np.meshgrid(*[np.arange(m)] * d, indexing="ij"), -1).reshape(-1, d) * a
+    g = oracle.grid(d, [0.0] * d, [1.0] * d, [1] * d, 1.5 * a, prec)
+    y, _ = oracle.pair_sum(g, "count", (), grid_pts)
+    assert np.all(y[:, 0] == expect)
+    f, _ = oracle.pair_sum(g, "spring", (1.0,), grid_pts)
+    assert np.max(np.abs(f)) < 1e-12
+
+
+@pytest.mark.parametrize("op,params,needs_a", [("spring", (1.0,), False), ("exp_force", (1e-3,), False),
+                                               ("dem_spring", (2.0,), True)])
+def test_newtons_third_law(op, params, needs_a):
+    L = syn.side_for_density(5000, 3, 30.0)
+    g = oracle.grid(3, [0] * 3, [L] * 3, [1] * 3, 1.0, "f32")
+    rng = syn.SplitMix64(31337)
+    x = syn.uniform_positions(rng, 5000, [0] * 3, [L] * 3, "f32")
+    a = rng.uniform(5000) * 0.5 if needs_a else None
+    y, sc = oracle.pair_sum(g, op, params, x, a=a)
+    assert np.abs(y.sum(axis=0)).max() < 1e-11 * sc.sum()
+    assert sc.sum() > 0
+
+
+def test_mean_neighbour_count_matches_density():
+    w = syn.spring_cube(1 << 15)
+    s = w.systems[0]
+    g = oracle.grid_of(s)
+    y, _ = oracle.pair_sum(g, "count", (), s.x)
+    # uniform points: expected neighbours within r = density * ball volume = 30
+    assert abs(y.mean() - 30.0) < 0.3
+
+
+# --------------------------------------------------------------------------
+# adjoint: finite differences and the spring / soft-sphere identity
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("op,params,needs_a", [("spring", (1.0,), False), ("exp_force", (0.7,), False),
+                                               ("soft_sphere", (), False), ("dem_spring", (1.5,), True)])
+@pytest.mark.parametrize("d", [2, 3])
+def test_adjoint_matches_finite_differences(op, params, needs_a, d):
+    n = 1500
+    L = syn.side_for_density(n, d, 30.0)
+    g = oracle.grid(d, [0] * d, [L] * d, [1] * d, 1.0, "f64")
+    rng = syn.SplitMix64(4242 + d)
+    x = syn.uniform_positions(rng, n, [0] * d, [L] * d, "f64")
+    a = rng.uniform(n) * 0.5 if needs_a else None
+    ny = oracle.op_ny(op, d)
+    gy = rng.normal(n * ny).reshape(n, ny)
+    gx, ga, sx, sa = oracle.pair_sum_backward(g, op, params, x, gy, a=a)
+    coords = np.floor(rng.uniform(200) * n * d).astype(np.int64)
+    fd = oracle.fd_grad(g, op, params, x, gy, coords, 1e-6, a=a)
+    an = gx.reshape(-1)[coords]
+    scale = sx[coords // d]
+    assert np.all(np.abs(fd - an) <= 1e-7 * np.maximum(scale, 1e-30) + 1e-9)
+    if needs_a:
+        ca = n * d + np.floor(rng.uniform(100) * n).astype(np.int64)
+        fda = oracle.fd_grad(g, op, params, x, gy, ca, 1e-6, a=a)
+        assert np.all(np.abs(fda - ga[ca - n * d]) <= 1e-7 * np.maximum(sa[ca - n * d], 1e-30) + 1e-9)
+
+
+def test_energy_gradient_is_scaled_spring_force():
+    # E = sum_i e_i with phi = (1 - s/r)^2:  grad E = -(2/(k r^2)) F_spring
+    n = 4000
+    L = syn.side_for_density(n, 3, 40.0)
+    rng = syn.SplitMix64(606)
+    x = syn.uniform_positions(rng, n, [0] * 3, [L] * 3, "f32")
+    g = oracle.grid(3, [0] * 3, [L] * 3, [1] * 3, 1.0, "f32")
+    k = 1.0
+    gx, _, sx, _ = oracle.pair_sum_backward(g, "soft_sphere", (), x, np.ones((n, 1)))
+    f, sf = oracle.pair_sum(g, "spring", (k,), x)
+    np.testing.assert_allclose(gx, -(2.0 / (k * g.r * g.r)) * f, rtol=0, atol=1e-12 * sx.max())
+    assert np.abs(gx.sum(axis=0)).max() < 1e-11 * sx.sum()  # translation invariance of E
+
+
+# --------------------------------------------------------------------------
+# dense Gaussian sum
+# --------------------------------------------------------------------------
+
+def test_dense_special_cases():
+    x, w, sigma = syn.gaussian_square(512)
+    x = x.astype(np.float64); w = w.astype(np.float64)
+    # sigma -> infinity: every kernel value is 1
+    y, _ = oracle.dense_gauss(x, x, w, 1e12)
+    np.testing.assert_allclose(y, np.full(512, w.sum()), rtol=0, atol=1e-9)
+    # one source: closed form
+    y1, _ = oracle.dense_gauss(x, x[3:4], w[3:4], sigma)
+    d2 = ((x - x[3]) ** 2).sum(1)
+    np.testing.assert_allclose(y1, np.exp(-d2 / (2 * sigma ** 2)) * w[3], rtol=1e-12)
+    assert y1[3] == w[3]  # the diagonal term (j = i) is included with kernel value 1
+    # K is symmetric: v.(K w) == w.(K v)
+    v = syn.SplitMix64(8).normal(512)
+    kw, _ = oracle.dense_gauss(x, x, w, sigma)
+    kv, _ = oracle.dense_gauss(x, x, v, sigma)
+    assert abs(v @ kw - w @ kv) < 1e-10 * (np.abs(v) @ np.abs(kw))
+    # rows subset equals the same rows of the full sum
+    rows = np.array([0, 17, 511, 200])
+    yr, _ = oracle.dense_gauss(x, x, w, sigma, rows=rows)
+    np.testing.assert_array_equal(yr, kw[rows])
+
+
+def test_dense_two_points_distance_sigma():
+    x = np.array([[0.0, 0.0], [0.3, 0.4]])
+    y, _ = oracle.dense_gauss(x, x, np.array([1.0, 2.0]), 0.5)
+    # |x0 - x1| = 0.5 = sigma: kernel exp(-1/2)
+    np.testing.assert_allclose(y, [1 + 2 * math.exp(-0.5), math.exp(-0.5) + 2], rtol=1e-15)
+
+
+def test_rows_subset_matches_full_and_tie_band_is_small():
+    w = syn.spring_cube(1 << 14)
+    s = w.systems[0]
+    g = oracle.grid_of(s)
+    y, sc = oracle.pair_sum(g, "spring", (1.0,), s.x)
+    rows = np.array([0, 5, 100, 16383])
+    yb, scb = oracle.pair_sum(g, "spring", (1.0,), s.x, rows=rows, route=oracle.ROUTE_BRUTE)
+    np.testing.assert_allclose(yb, y[rows], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(scb, sc[rows], rtol=1e-12)
+    assert 0 <= oracle.tie_band(g, s.x) < 20
