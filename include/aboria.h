@@ -1,0 +1,248 @@
+/*
+ * aboria.h -- C-ABI of the MI355X (gfx950) library for the hot path of the
+ * particle-based methods of Robinson & Bruna, "Particle-based and Meshless
+ * Methods with Aboria" (arXiv:1704.08907):
+ *
+ *   1. building a uniform cell list over a d-dimensional box whose dimensions
+ *      are each periodic or not (Section 1, property 1; Section 2.2.1, the
+ *      Level 1 cell list with particles reordered into cell order),
+ *   2. evaluating radius-limited pairwise neighbourhood sums over it by box
+ *      search of a particle's cell and its adjacent cells (Section 2.2.2,
+ *      Level 2; Section 3, eq. (1) and the velocity-update listing), with a
+ *      hand-written adjoint, and
+ *   3. the dense all-pairs kernel sum of the RBF / Gaussian-process methods
+ *      (Section 1 and Section 1.1).
+ *
+ * Conventions shared by every entry point:
+ *   - Pointers named *_host point to host memory; every other array pointer is
+ *     a device pointer on the context's device.  The caller owns all arrays it
+ *     passes; the library owns contexts, cell lists and graphs.
+ *   - Work is enqueued on the context's HIP stream and is stream-ordered; a call
+ *     returning ABORIA_OK means the work was enqueued.  Argument errors are
+ *     detected on the host before anything is enqueued, and nothing is
+ *     launched then.  Errors found on the device (a NaN position, a position
+ *     outside [lo, hi)) raise a sticky flag reported by aboria_sync.
+ *   - No C++ exception crosses this boundary.  aboria_last_error returns the
+ *     message of the context's latest failure.
+ *   - Arrays are row-major.  Positions are x[n][d] in the cell list's precision
+ *     (float for ABORIA_F32, double for ABORIA_F64).  Outputs never alias
+ *     inputs: an overlap is an ABORIA_ERR_INVALID_ARG.
+ *   - A context is used by one host thread at a time.
+ */
+#ifndef ABORIA_H
+#define ABORIA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum aboria_status {
+    ABORIA_OK = 0,
+    ABORIA_ERR_INVALID_ARG = 1,   /* bad argument; nothing was enqueued          */
+    ABORIA_ERR_DOMAIN = 2,        /* a position was NaN or outside [lo, hi)      */
+    ABORIA_ERR_UNSUPPORTED = 3,   /* valid but not handled (e.g. periodic L < 2r) */
+    ABORIA_ERR_OUT_OF_MEMORY = 4, /* device allocation failed                    */
+    ABORIA_ERR_DEVICE = 5         /* a HIP runtime call failed                   */
+} aboria_status;
+
+typedef enum aboria_dtype { ABORIA_F32 = 0, ABORIA_F64 = 1 } aboria_dtype;
+
+/*
+ * Pairwise operators y_i = sum_{j in P(i)} f(x_i, x_j, a_i, a_j), P(i) the
+ * canonical neighbour set of i (see aboria_build_cells).  With u = x_i - x_j
+ * (minimum image) and s = |u|:
+ *   COUNT        ny = 1   f = 1                                 (|P(i)|)
+ *   SPRING       ny = d   f = k (r - s) u / s,  params {k}       linear spring of
+ *                         rest length r (Section 1.1, Molecular Dynamics)
+ *   SOFT_SPHERE  ny = 1   f = 1/2 (1 - s/r)^2, no params          pair energy,
+ *                         E = sum_i y_i counts each unordered pair once
+ *   EXP_FORCE    ny = d   f = -c exp(-|dx|) dx/|dx|, dx = -u,  params {c}
+ *                         the paper's eq. (1)
+ *   DEM_SPRING   ny = d   f = k (a_i + a_j - s) u / s, na = 1, params {k}
+ *                         spring with per-particle resting lengths (Section 1.1,
+ *                         Discrete Element Model)
+ */
+typedef enum aboria_op {
+    ABORIA_OP_COUNT = 0,
+    ABORIA_OP_SPRING = 1,
+    ABORIA_OP_SOFT_SPHERE = 2,
+    ABORIA_OP_EXP_FORCE = 3,
+    ABORIA_OP_DEM_SPRING = 4
+} aboria_op;
+
+typedef enum aboria_kernel {
+    ABORIA_K_GAUSSIAN = 0 /* K(x, x') = exp(-|x - x'|^2 / (2 sigma^2)), params {sigma} */
+} aboria_kernel;
+
+/* A hypercube domain [lo, hi) and cutoff (Section 1, property 1; the
+ * init_neighbour_search(lo, hi, width, periodic) call of Section 3).  Entries
+ * beyond d are ignored.  ncell[k] = 0 picks the cell count automatically (the
+ * largest count whose cells are wider than the cutoff by a rounding guard);
+ * an explicit count must not exceed that and is honoured as given. */
+typedef struct aboria_box {
+    int32_t d;           /* 1, 2 or 3                                  */
+    int32_t periodic[3]; /* nonzero = periodic in that dimension       */
+    int32_t ncell[3];    /* 0 = automatic                              */
+    int32_t reserved;
+    double lo[3];
+    double hi[3];
+    double cutoff;       /* r > 0                                      */
+} aboria_box;
+
+typedef struct aboria_ctx aboria_ctx;
+typedef struct aboria_cells aboria_cells;
+typedef struct aboria_graph aboria_graph;
+
+/* Read-only view of a cell list (device pointers stay owned by the cells). */
+typedef struct aboria_cells_view {
+    int32_t nsys;                   /* number of independent systems              */
+    int32_t d;
+    int32_t dtype;                  /* aboria_dtype                               */
+    int32_t reserved;
+    int64_t n;                      /* total particles                            */
+    int64_t ncells;                 /* total cells over all systems               */
+    const uint32_t* perm;           /* device [n]: sorted slot -> original index  */
+    const uint32_t* keys;           /* device [n]: global cell id of each slot    */
+    const uint32_t* cell_offsets;   /* device [ncells + 1]: first slot of a cell  */
+    const void* x_sorted;           /* device [n][pitch]: positions in cell order */
+    int32_t x_pitch;                /* elements per sorted position (4 for d = 3) */
+    int32_t reserved2;
+    const int32_t* ncell_host;      /* host [nsys][3]: cells per dimension        */
+    const uint32_t* cell_base_host; /* host [nsys + 1]: first global cell id      */
+    const int64_t* sys_offsets_host;/* host [nsys + 1]: first particle of a system */
+} aboria_cells_view;
+
+/* ---- context ------------------------------------------------------------- */
+
+/* Creates a context on HIP device `device` that enqueues on `hip_stream` (a
+ * hipStream_t; NULL = the legacy default stream).  *out receives the handle. */
+aboria_status aboria_create(int32_t device, void* hip_stream, aboria_ctx** out);
+/* Releases the context and its scratch memory (waits for its stream first). */
+aboria_status aboria_destroy(aboria_ctx* ctx);
+/* Changes the stream subsequent calls enqueue on. */
+aboria_status aboria_set_stream(aboria_ctx* ctx, void* hip_stream);
+/* Message of the latest failure on this context ("" if none); owned by ctx. */
+const char* aboria_last_error(const aboria_ctx* ctx);
+/* Waits for the context's stream, then reports and clears the device error
+ * flag: ABORIA_ERR_DOMAIN if a position seen by a cell build since the last
+ * sync was NaN or outside [lo, hi). */
+aboria_status aboria_sync(aboria_ctx* ctx);
+
+/* ---- cell list (Section 2.2.1 Level 1, Section 2.2.2 Level 2) ---------------
+ *
+ * Builds the cell list of nsys independent systems whose particles are
+ * concatenated in x: system b owns rows [offsets_host[b], offsets_host[b+1]) of
+ * x[n][d] (n = offsets_host[nsys]; offsets_host = NULL with nsys = 1 means all
+ * rows; total rows < 2^31).  boxes_host[b] is system b's box; all boxes share
+ * d.  The steps: a cell id per particle, a stable LSD radix sort of
+ * (cell id, index) pairs in LDS-ranked passes, a gather of the positions into
+ * cell order, and the cell offsets (first slot of every cell).  Within a cell
+ * particles keep their original index order.
+ *
+ * Canonical rounding (precision P = dtype): cell coordinate
+ * clamp(floor(fl(fl(x - lo) * fl(n/L))), 0, n-1); linear id c0 + n0 (c1 + n1 c2)
+ * plus the system's first global cell id.  The neighbour set of i is every j
+ * in the 3^d cells around i's cell (wrapping with an image shift s_k = -L or +L
+ * in periodic dimensions) with 0 < d2 < fl(r*r), where t_k = fl(x_jk - x_ik),
+ * dx_k = fl(t_k + s_k) and d2 = fma(dx2, dx2, fma(dx1, dx1, dx0 * dx0)); the
+ * norm(dx) > 0 condition of the Section 3 listing is the d2 > 0 test.
+ *
+ * *cells == NULL creates a cell list; otherwise it is rebuilt in place (the
+ * same nsys, d, dtype and n; no allocation, so a rebuild may be captured in a
+ * graph).  The cell list keeps its own sorted copy of the positions: results of
+ * later sums use the positions as they were at build time, and x may be reused
+ * once the stream has passed this call (Section 2.2.1: the search structure is
+ * rebuilt when positions change).
+ * Errors: INVALID_ARG for d outside 1..3, hi <= lo, cutoff <= 0, an explicit
+ * ncell above the automatic one, inconsistent boxes or offsets; UNSUPPORTED for
+ * a periodic side shorter than twice the guarded cutoff, or more than 2^31
+ * cells in total; OUT_OF_MEMORY if the device buffers cannot be allocated. */
+aboria_status aboria_build_cells(aboria_ctx* ctx, aboria_dtype dtype, int32_t nsys,
+                                 const aboria_box* boxes_host, const int64_t* offsets_host,
+                                 const void* x, aboria_cells** cells);
+aboria_status aboria_cells_view_get(const aboria_cells* cells, aboria_cells_view* out);
+aboria_status aboria_cells_destroy(aboria_cells* cells);
+
+/* ---- neighbour sums (Section 3: eq. (1) and the velocity-update listing) ----
+ *
+ * y[n][ny] = sum over the neighbour set of each particle of the operator's
+ * summand (see aboria_op), in the original particle order, computed in the
+ * cell list's precision.  a[n][na] holds per-particle variables in original
+ * order (NULL when the operator takes none).  params_host[nparams] are the
+ * operator's constants; the cutoff r is the cell list's.  y is overwritten.
+ * Errors: INVALID_ARG for an unknown op, ny/na/nparams not those of the op,
+ * NULL or overlapping arrays. */
+aboria_status aboria_pair_sum(aboria_ctx* ctx, const aboria_cells* cells, aboria_op op,
+                              const double* params_host, int32_t nparams, const void* a, int32_t na,
+                              void* y, int32_t ny);
+
+/* Adjoint of aboria_pair_sum: given gy[n][ny] = dL/dy, writes gx[n][d] = dL/dx
+ * and, for operators with per-particle variables, ga[n][na] = dL/da (ga may be
+ * NULL to skip it), all in original order and overwritten.  It gathers over the
+ * same cell list (no stored pair list, no atomics):
+ *   gx_k = sum_{i in P(k)} [ J1(k,i)^T gy_k + J2(i,k)^T gy_i ],
+ * J1, J2 the Jacobians of the summand in its first and second position.  The
+ * pair set is held fixed (the summands are differentiated where they are
+ * smooth).  Errors as for aboria_pair_sum. */
+aboria_status aboria_pair_sum_backward(aboria_ctx* ctx, const aboria_cells* cells, aboria_op op,
+                                       const double* params_host, int32_t nparams, const void* a,
+                                       int32_t na, const void* gy, int32_t ny, void* gx, void* ga);
+
+/* Lists the ordered neighbour pairs (original indices) of the cell list:
+ * pair p is (pi[p], pj[p]) for p < min(total, cap), in an unspecified order;
+ * *total_host receives the pair count.  This call synchronises the stream
+ * (it reads the count back) and allocates, so it cannot be captured.  It is
+ * meant for verification of the pair set. */
+aboria_status aboria_pair_list(aboria_ctx* ctx, const aboria_cells* cells, int64_t cap, uint32_t* pi,
+                               uint32_t* pj, int64_t* total_host);
+
+/* ---- dense kernel sum (Section 1 and 1.1: RBF and Gaussian processes) -------
+ *
+ * y[i] = sum_{j < n_source} K(xt_i, xs_j) w_j for i < n_target, over every
+ * source (j = i included when the sets coincide).  xt[n_target][d],
+ * xs[n_source][d], w[n_source], y[n_target] in dtype; d in 1..3.  Float32 inputs
+ * accumulate in float32 with per-tile partial sums.  Errors: INVALID_ARG for an
+ * unknown kernel, sigma <= 0, d outside 1..3, NULL or overlapping arrays. */
+aboria_status aboria_dense_sum(aboria_ctx* ctx, aboria_dtype dtype, aboria_kernel kernel,
+                               const double* params_host, int32_t nparams, int32_t d, int64_t n_target,
+                               const void* xt, int64_t n_source, const void* xs, const void* w, void* y);
+
+/* ---- graphs ------------------------------------------------------------------
+ * Captures the calls made on ctx between begin and end into one executable
+ * HIP graph (rebuilds with an existing cell list, sums, adjoints and dense sums
+ * allocate nothing and can be captured; a first build, aboria_pair_list and
+ * aboria_sync cannot).  Launch replays it on the context's stream. */
+aboria_status aboria_graph_capture_begin(aboria_ctx* ctx);
+aboria_status aboria_graph_capture_end(aboria_ctx* ctx, aboria_graph** out);
+aboria_status aboria_graph_launch(aboria_ctx* ctx, const aboria_graph* graph);
+aboria_status aboria_graph_destroy(aboria_graph* graph);
+
+/* ---- autotuning ---------------------------------------------------------------
+ * Times the neighbour-sum kernel variants (launch shape and work mapping) for
+ * this cell list and operator with HIP events on the context's stream, keeps the
+ * fastest in the context's cache (keyed by d, dtype, op, size and density
+ * buckets) and makes later sums on matching cell lists use it.  y_scratch is a
+ * device buffer of n * ny elements the trials may overwrite.  *choice_host
+ * receives the chosen variant's index (may be NULL).  Synchronises the stream;
+ * not capturable.  Errors as for aboria_pair_sum. */
+aboria_status aboria_autotune(aboria_ctx* ctx, const aboria_cells* cells, aboria_op op,
+                              const double* params_host, int32_t nparams, const void* a, int32_t na,
+                              void* y_scratch, int32_t ny, int32_t* choice_host);
+
+/* Number of neighbour-sum variants, and a static description of one. */
+int32_t aboria_variant_count(void);
+const char* aboria_variant_name(int32_t variant);
+/* Forces a variant for later sums on ctx (-1 = use the tuned / default one). */
+aboria_status aboria_set_variant(aboria_ctx* ctx, int32_t variant);
+
+/* Summand widths of an operator: ny for dimension d, and na. -1 if unknown. */
+int32_t aboria_op_ny(aboria_op op, int32_t d);
+int32_t aboria_op_na(aboria_op op);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ABORIA_H */

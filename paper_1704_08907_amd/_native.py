@@ -1,0 +1,357 @@
+"""ctypes binding of libaboria_mi355x.so: argument marshalling only.
+
+Every function here has the name of the C entry point it calls (without the
+``aboria_`` prefix) and does no arithmetic of its own: device arrays are torch
+tensors whose data pointers are handed over, and every step of the path runs in
+the HIP kernels.  There is no CPU fallback: if the library is missing, loading
+fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libaboria_mi355x.so")
+
+F32, F64 = 0, 1
+OPS = {"count": 0, "spring": 1, "soft_sphere": 2, "exp_force": 3, "dem_spring": 4}
+KERNELS = {"gaussian": 0}
+STATUS = {0: "OK", 1: "INVALID_ARG", 2: "DOMAIN", 3: "UNSUPPORTED", 4: "OUT_OF_MEMORY", 5: "DEVICE"}
+
+
+class AboriaError(RuntimeError):
+    def __init__(self, code: int, what: str, msg: str):
+        super().__init__("%s: %s (%s)" % (what, STATUS.get(code, code), msg))
+        self.code = code
+        self.status = STATUS.get(code, str(code))
+
+
+class Box(C.Structure):
+    _fields_ = [("d", C.c_int32), ("periodic", C.c_int32 * 3), ("ncell", C.c_int32 * 3),
+                ("reserved", C.c_int32), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
+                ("cutoff", C.c_double)]
+
+
+class CellsView(C.Structure):
+    _fields_ = [("nsys", C.c_int32), ("d", C.c_int32), ("dtype", C.c_int32), ("reserved", C.c_int32),
+                ("n", C.c_int64), ("ncells", C.c_int64), ("perm", C.c_void_p), ("keys", C.c_void_p),
+                ("cell_offsets", C.c_void_p), ("x_sorted", C.c_void_p), ("x_pitch", C.c_int32),
+                ("reserved2", C.c_int32), ("ncell_host", C.POINTER(C.c_int32)),
+                ("cell_base_host", C.POINTER(C.c_uint32)), ("sys_offsets_host", C.POINTER(C.c_int64))]
+
+
+_lib = None
+EXPORTS = ["aboria_create", "aboria_destroy", "aboria_set_stream", "aboria_last_error", "aboria_sync",
+           "aboria_build_cells", "aboria_cells_view_get", "aboria_cells_destroy", "aboria_pair_sum",
+           "aboria_pair_sum_backward", "aboria_pair_list", "aboria_dense_sum",
+           "aboria_graph_capture_begin", "aboria_graph_capture_end", "aboria_graph_launch",
+           "aboria_graph_destroy", "aboria_autotune", "aboria_variant_count", "aboria_variant_name",
+           "aboria_set_variant", "aboria_op_ny", "aboria_op_na"]
+
+
+def lib():
+    """The loaded HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("HIP library %s is missing: run __graft_entry__.build() first" % LIB_PATH)
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        I32, I64 = C.c_int32, C.c_int64
+        sig = {
+            "aboria_create": ([I32, P, C.POINTER(P)], I32),
+            "aboria_destroy": ([P], I32),
+            "aboria_set_stream": ([P, P], I32),
+            "aboria_last_error": ([P], C.c_char_p),
+            "aboria_sync": ([P], I32),
+            "aboria_build_cells": ([P, I32, I32, C.POINTER(Box), C.POINTER(I64), P, C.POINTER(P)], I32),
+            "aboria_cells_view_get": ([P, C.POINTER(CellsView)], I32),
+            "aboria_cells_destroy": ([P], I32),
+            "aboria_pair_sum": ([P, P, I32, C.POINTER(C.c_double), I32, P, I32, P, I32], I32),
+            "aboria_pair_sum_backward": ([P, P, I32, C.POINTER(C.c_double), I32, P, I32, P, I32, P, P], I32),
+            "aboria_pair_list": ([P, P, I64, P, P, C.POINTER(I64)], I32),
+            "aboria_dense_sum": ([P, I32, I32, C.POINTER(C.c_double), I32, I32, I64, P, I64, P, P, P], I32),
+            "aboria_graph_capture_begin": ([P], I32),
+            "aboria_graph_capture_end": ([P, C.POINTER(P)], I32),
+            "aboria_graph_launch": ([P, P], I32),
+            "aboria_graph_destroy": ([P], I32),
+            "aboria_autotune": ([P, P, I32, C.POINTER(C.c_double), I32, P, I32, P, I32, C.POINTER(I32)], I32),
+            "aboria_variant_count": ([], I32),
+            "aboria_variant_name": ([I32], C.c_char_p),
+            "aboria_set_variant": ([P, I32], I32),
+            "aboria_op_ny": ([I32, I32], I32),
+            "aboria_op_na": ([I32], I32),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.float64:
+        return F64
+    raise TypeError("positions must be float32 or float64, got %s" % t.dtype)
+
+
+def _check_dev(t: torch.Tensor, name: str, dtype=None):
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError("%s must be %s" % (name, dtype))
+
+
+class Context:
+    """An aboria_ctx bound to one device and one stream."""
+
+    def __init__(self, device: int = 0, stream: Optional[torch.cuda.Stream] = None):
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        h = C.c_void_p()
+        st = lib().aboria_create(device, C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if st != 0:
+            raise AboriaError(st, "create", "device %d" % device)
+        self.handle = h
+
+    def check(self, st: int, what: str):
+        if st != 0:
+            raise AboriaError(st, what, self.last_error())
+
+    def last_error(self) -> str:
+        m = lib().aboria_last_error(self.handle)
+        return m.decode() if m else ""
+
+    def sync(self):
+        self.check(lib().aboria_sync(self.handle), "sync")
+
+    def set_stream(self, stream: torch.cuda.Stream):
+        self.check(lib().aboria_set_stream(self.handle, C.c_void_p(stream.cuda_stream)), "set_stream")
+        self.stream = stream
+
+    def set_variant(self, v: int):
+        self.check(lib().aboria_set_variant(self.handle, v), "set_variant")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().aboria_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class BoxSpec:
+    d: int
+    lo: Sequence[float]
+    hi: Sequence[float]
+    periodic: Sequence[int]
+    cutoff: float
+    ncell: Optional[Sequence[int]] = None
+
+    def to_c(self) -> Box:
+        b = Box()
+        b.d = self.d
+        for k in range(min(self.d, 3)):
+            b.lo[k] = float(self.lo[k])
+            b.hi[k] = float(self.hi[k])
+            b.periodic[k] = int(bool(self.periodic[k]))
+            b.ncell[k] = int(self.ncell[k]) if self.ncell is not None else 0
+        b.cutoff = float(self.cutoff)
+        return b
+
+
+@dataclass
+class Cells:
+    ctx: Context
+    handle: C.c_void_p
+    n: int
+    d: int
+    dtype: torch.dtype
+    nsys: int
+    boxes: list = field(default_factory=list)
+    offsets: list = field(default_factory=list)
+
+    def view(self) -> CellsView:
+        v = CellsView()
+        st = lib().aboria_cells_view_get(self.handle, C.byref(v))
+        if st != 0:
+            raise AboriaError(st, "cells_view_get", "")
+        return v
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().aboria_cells_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build_cells(ctx: Context, x: torch.Tensor, boxes: Sequence[BoxSpec], offsets: Optional[Sequence[int]] = None,
+                cells: Optional[Cells] = None) -> Cells:
+    """aboria_build_cells: x[n][d] (float32/float64, device); boxes per system."""
+    _check_dev(x, "x")
+    boxes = list(boxes)
+    nsys = len(boxes)
+    n = int(x.shape[0])
+    if offsets is None:
+        if nsys != 1:
+            raise ValueError("offsets are required for more than one system")
+        offsets = [0, n]
+    arr_b = (Box * nsys)(*[b.to_c() for b in boxes])
+    arr_o = (C.c_int64 * (nsys + 1))(*[int(o) for o in offsets])
+    h = C.c_void_p(cells.handle.value) if cells is not None else C.c_void_p()
+    st = lib().aboria_build_cells(ctx.handle, _dtype_code(x), nsys, arr_b, arr_o, _ptr(x), C.byref(h))
+    ctx.check(st, "build_cells")
+    if cells is not None:
+        return cells
+    return Cells(ctx, h, n, boxes[0].d, x.dtype, nsys, boxes, list(offsets))
+
+
+def op_ny(op: str, d: int) -> int:
+    return int(lib().aboria_op_ny(OPS[op], d))
+
+
+def op_na(op: str) -> int:
+    return int(lib().aboria_op_na(OPS[op]))
+
+
+def _params(params):
+    params = [float(p) for p in params]
+    arr = (C.c_double * max(1, len(params)))(*params)
+    return arr, len(params)
+
+
+def pair_sum(ctx: Context, cells: Cells, op: str, params=(), a: Optional[torch.Tensor] = None,
+             y: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """aboria_pair_sum: returns y[n][ny] in original particle order."""
+    ny, na = op_ny(op, cells.d), op_na(op)
+    if y is None:
+        y = torch.empty((cells.n, ny), dtype=cells.dtype, device="cuda:%d" % ctx.device)
+    _check_dev(y, "y", cells.dtype)
+    if a is not None:
+        _check_dev(a, "a", cells.dtype)
+    arr, npar = _params(params)
+    st = lib().aboria_pair_sum(ctx.handle, cells.handle, OPS[op], arr, npar, _ptr(a), na, _ptr(y), ny)
+    ctx.check(st, "pair_sum")
+    return y
+
+
+def pair_sum_backward(ctx: Context, cells: Cells, op: str, params, gy: torch.Tensor,
+                      a: Optional[torch.Tensor] = None, gx: Optional[torch.Tensor] = None,
+                      ga: Optional[torch.Tensor] = None, want_ga: bool = True):
+    """aboria_pair_sum_backward: returns (gx[n][d], ga[n][na] or None)."""
+    ny, na = op_ny(op, cells.d), op_na(op)
+    dev = "cuda:%d" % ctx.device
+    _check_dev(gy, "gy", cells.dtype)
+    if gx is None:
+        gx = torch.empty((cells.n, cells.d), dtype=cells.dtype, device=dev)
+    if ga is None and na > 0 and want_ga:
+        ga = torch.empty((cells.n, na), dtype=cells.dtype, device=dev)
+    arr, npar = _params(params)
+    st = lib().aboria_pair_sum_backward(ctx.handle, cells.handle, OPS[op], arr, npar, _ptr(a), na, _ptr(gy), ny,
+                                        _ptr(gx), _ptr(ga))
+    ctx.check(st, "pair_sum_backward")
+    return gx, ga
+
+
+def pair_list(ctx: Context, cells: Cells):
+    """aboria_pair_list: (pi, pj) uint32->int64 device tensors of all ordered pairs."""
+    total = C.c_int64()
+    st = lib().aboria_pair_list(ctx.handle, cells.handle, 0, None, None, C.byref(total))
+    ctx.check(st, "pair_list")
+    m = int(total.value)
+    dev = "cuda:%d" % ctx.device
+    pi = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
+    pj = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
+    st = lib().aboria_pair_list(ctx.handle, cells.handle, m, _ptr(pi), _ptr(pj), C.byref(total))
+    ctx.check(st, "pair_list")
+    return pi[:m], pj[:m]
+
+
+def dense_sum(ctx: Context, xt: torch.Tensor, xs: torch.Tensor, w: torch.Tensor, sigma: float,
+              y: Optional[torch.Tensor] = None, kernel: str = "gaussian") -> torch.Tensor:
+    """aboria_dense_sum: y[i] = sum_j K(xt_i, xs_j) w_j."""
+    _check_dev(xt, "xt")
+    _check_dev(xs, "xs", xt.dtype)
+    _check_dev(w, "w", xt.dtype)
+    d = int(xt.shape[1])
+    if y is None:
+        y = torch.empty(int(xt.shape[0]), dtype=xt.dtype, device=xt.device)
+    _check_dev(y, "y", xt.dtype)
+    arr, npar = _params([sigma])
+    st = lib().aboria_dense_sum(ctx.handle, _dtype_code(xt), KERNELS[kernel], arr, npar, d, int(xt.shape[0]),
+                                _ptr(xt), int(xs.shape[0]), _ptr(xs), _ptr(w), _ptr(y))
+    ctx.check(st, "dense_sum")
+    return y
+
+
+class Graph:
+    def __init__(self, handle):
+        self.handle = handle
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().aboria_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def graph_capture_begin(ctx: Context):
+    ctx.check(lib().aboria_graph_capture_begin(ctx.handle), "graph_capture_begin")
+
+
+def graph_capture_end(ctx: Context) -> Graph:
+    h = C.c_void_p()
+    ctx.check(lib().aboria_graph_capture_end(ctx.handle, C.byref(h)), "graph_capture_end")
+    return Graph(h)
+
+
+def graph_launch(ctx: Context, g: Graph):
+    ctx.check(lib().aboria_graph_launch(ctx.handle, g.handle), "graph_launch")
+
+
+def autotune(ctx: Context, cells: Cells, op: str, params=(), a: Optional[torch.Tensor] = None) -> int:
+    ny, na = op_ny(op, cells.d), op_na(op)
+    y = torch.empty((cells.n, ny), dtype=cells.dtype, device="cuda:%d" % ctx.device)
+    arr, npar = _params(params)
+    choice = C.c_int32(-1)
+    st = lib().aboria_autotune(ctx.handle, cells.handle, OPS[op], arr, npar, _ptr(a), na, _ptr(y), ny,
+                               C.byref(choice))
+    ctx.check(st, "autotune")
+    return int(choice.value)
+
+
+def variant_count() -> int:
+    return int(lib().aboria_variant_count())
+
+
+def variant_name(v: int) -> str:
+    return lib().aboria_variant_name(v).decode()

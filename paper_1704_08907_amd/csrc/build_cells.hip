@@ -1,0 +1,619 @@
+// Cell-list construction: the Level 1 search structure of Section 2.2.1 in its
+// parallel-insertion form (the particles are reordered into cell order).
+//
+//   k_cell_ids       per particle: global cell id under the canonical rounding
+//   k_radix_hist     per tile of 4096 keys: digit histogram in LDS
+//   k_scan_local,    device-wide exclusive scan of the digit-major
+//   k_scan_top       (digit, tile) counts
+//   k_radix_scatter  stable in-tile ranks from wave ballots, then scatter
+//   k_finalize       cell offsets by boundary detection and the gather of the
+//                    positions into cell order
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "common.hpp"
+
+namespace aboria {
+
+constexpr int kBlock = 256;
+constexpr int kSortIpt = 16;                  // keys per thread per tile
+constexpr int kSortTile = kBlock * kSortIpt;  // 4096 keys per tile
+constexpr int kScanIpt = 16;
+constexpr int kScanTile = kBlock * kScanIpt;  // 4096 values per scan block
+constexpr int kMaxDigitBits = 10;
+
+// ---------------------------------------------------------------------------
+// a1: cell ids
+// ---------------------------------------------------------------------------
+
+// System owning row i: the last b with first[b] <= i (empty systems skipped).
+__device__ __forceinline__ int find_system(const uint32_t* __restrict__ first, int nsys, uint32_t i) {
+    int lo = 0, hi = nsys - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (first[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename T, int D, bool BATCH>
+__global__ __launch_bounds__(kBlock) void k_cell_ids(const T* __restrict__ x, uint32_t n,
+                                                     const SysParams<T>* __restrict__ sp,
+                                                     const uint32_t* __restrict__ sys_part, int nsys,
+                                                     uint32_t* __restrict__ keys, uint32_t* __restrict__ flag) {
+    uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    int b = BATCH ? find_system(sys_part, nsys, i) : 0;
+    const SysParams<T>& P = sp[b];
+    uint32_t id = 0, mul = 1;
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        T xk = x[(size_t)i * D + k];
+        bad |= !(xk >= P.lo[k]) || !(xk < P.hi[k]);
+        T t = xk - P.lo[k];  // contraction is off: two separately rounded operations
+        T q = t * P.inv_w[k];
+        T f = floor(q);
+        int32_t c;
+        if (!(f >= T(0))) c = 0;  // negative or NaN
+        else if (f > T(P.n[k] - 1)) c = P.n[k] - 1;
+        else c = (int32_t)f;
+        id += mul * (uint32_t)c;
+        mul *= (uint32_t)P.n[k];
+    }
+    if (bad) atomicOr(flag, 1u);
+    keys[i] = P.cell_base + id;
+}
+
+// ---------------------------------------------------------------------------
+// device-wide exclusive scan (two kernels; the consumer adds the block prefix)
+// ---------------------------------------------------------------------------
+
+// Exclusive scan of one value per thread across the 256-thread block; returns
+// the block total through *total.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* wsum, uint32_t* total) {
+    const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t t = __shfl_up(incl, o, 64);
+        if (lane >= (uint32_t)o) incl += t;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    uint32_t pre = 0;
+    for (uint32_t q = 0; q < w; ++q) pre += wsum[q];
+    *total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    __syncthreads();
+    return pre + incl - v;
+}
+
+// out[p] = sum of in[q] for q < p within p's 4096-block; block_sums[b] = block total.
+__global__ __launch_bounds__(kBlock) void k_scan_local(const uint32_t* in, uint32_t* out,
+                                                       uint32_t len, uint32_t* __restrict__ block_sums) {
+    __shared__ uint32_t wsum[4];
+    const uint32_t base = blockIdx.x * kScanTile + threadIdx.x * kScanIpt;
+    uint32_t v[kScanIpt];
+    uint32_t tot = 0;
+#pragma unroll
+    for (int k = 0; k < kScanIpt; ++k) {
+        uint32_t idx = base + k;
+        v[k] = idx < len ? in[idx] : 0u;
+        tot += v[k];
+    }
+    uint32_t total;
+    uint32_t ex = block_exclusive_scan(tot, wsum, &total);
+#pragma unroll
+    for (int k = 0; k < kScanIpt; ++k) {
+        uint32_t idx = base + k;
+        if (idx < len) out[idx] = ex;
+        ex += v[k];
+    }
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+}
+
+// In-place exclusive scan of the block totals by one workgroup (any length).
+__global__ __launch_bounds__(kBlock) void k_scan_top(uint32_t* __restrict__ bs, uint32_t nb) {
+    __shared__ uint32_t wsum[4];
+    uint32_t carry = 0;
+    for (uint32_t chunk = 0; chunk < nb; chunk += kScanTile) {
+        const uint32_t base = chunk + threadIdx.x * kScanIpt;
+        uint32_t v[kScanIpt];
+        uint32_t tot = 0;
+#pragma unroll
+        for (int k = 0; k < kScanIpt; ++k) {
+            uint32_t idx = base + k;
+            v[k] = idx < nb ? bs[idx] : 0u;
+            tot += v[k];
+        }
+        uint32_t total;
+        uint32_t ex = carry + block_exclusive_scan(tot, wsum, &total);
+#pragma unroll
+        for (int k = 0; k < kScanIpt; ++k) {
+            uint32_t idx = base + k;
+            if (idx < nb) bs[idx] = ex;
+            ex += v[k];
+        }
+        carry += total;
+    }
+}
+
+// out[p] += block_sums[p / 4096]: completes a scan for consumers that need it whole.
+__global__ __launch_bounds__(kBlock) void k_scan_add(uint32_t* __restrict__ out, uint32_t len,
+                                                     const uint32_t* __restrict__ bs) {
+    uint32_t p = blockIdx.x * kBlock + threadIdx.x;
+    if (p < len) out[p] += bs[p / kScanTile];
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, uint32_t len) {
+    uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < len) p[i] = v;
+}
+
+int64_t scan_block_count(int64_t len) { return (len + kScanTile - 1) / kScanTile; }
+
+aboria_status scan_exclusive_u32(aboria_ctx* ctx, const uint32_t* in, uint32_t* out, int64_t len,
+                                 uint32_t* block_sums, int64_t nblock_sums) {
+    if (len <= 0) return ABORIA_OK;
+    int64_t nb = scan_block_count(len);
+    if (nb > nblock_sums) return fail(ctx, ABORIA_ERR_INVALID_ARG, "scan: block-sum buffer too small");
+    hipLaunchKernelGGL(k_scan_local, dim3((uint32_t)nb), dim3(kBlock), 0, ctx->stream, in, out, (uint32_t)len,
+                       block_sums);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, ctx->stream, block_sums, (uint32_t)nb);
+    ABORIA_HIP(ctx, hipGetLastError());
+    return ABORIA_OK;
+}
+
+aboria_status scan_finish_u32(aboria_ctx* ctx, uint32_t* out, int64_t len, const uint32_t* block_sums) {
+    if (len <= 0) return ABORIA_OK;
+    hipLaunchKernelGGL(k_scan_add, dim3((uint32_t)((len + kBlock - 1) / kBlock)), dim3(kBlock), 0, ctx->stream, out,
+                       (uint32_t)len, block_sums);
+    ABORIA_HIP(ctx, hipGetLastError());
+    return ABORIA_OK;
+}
+
+aboria_status fill_u32(aboria_ctx* ctx, uint32_t* p, uint32_t v, int64_t len) {
+    if (len <= 0) return ABORIA_OK;
+    hipLaunchKernelGGL(k_fill_u32, dim3((uint32_t)((len + kBlock - 1) / kBlock)), dim3(kBlock), 0, ctx->stream, p, v,
+                       (uint32_t)len);
+    ABORIA_HIP(ctx, hipGetLastError());
+    return ABORIA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// a2: LSD radix sort of (cell id, index) pairs
+// ---------------------------------------------------------------------------
+
+// hist[digit * ntiles + tile] = number of keys of the tile with that digit.
+__global__ __launch_bounds__(kBlock) void k_radix_hist(const uint32_t* __restrict__ keys, uint32_t n, int shift,
+                                                       int bits, uint32_t* __restrict__ hist, uint32_t ntiles) {
+    extern __shared__ uint32_t lds[];
+    const uint32_t radix = 1u << bits, mask = radix - 1;
+    for (uint32_t d = threadIdx.x; d < radix; d += kBlock) lds[d] = 0;
+    __syncthreads();
+    const uint32_t tile = blockIdx.x;
+    const uint32_t base = tile * kSortTile;
+#pragma unroll 4
+    for (int k = 0; k < kSortIpt; ++k) {
+        uint32_t idx = base + k * kBlock + threadIdx.x;
+        if (idx < n) atomicAdd(&lds[(keys[idx] >> shift) & mask], 1u);
+    }
+    __syncthreads();
+    for (uint32_t d = threadIdx.x; d < radix; d += kBlock) hist[(size_t)d * ntiles + tile] = lds[d];
+}
+
+// Stable scatter of one tile.  Wave w owns keys [w*1024, (w+1)*1024) of the
+// tile and walks them in 16 steps of 64 consecutive keys.  Lanes holding the
+// same digit find each other with one ballot per digit bit; a lane's rank is
+// the number of such lanes below it plus the wave's running count for the
+// digit (kept in LDS, updated by the lowest such lane).  After all waves are
+// done the per-wave counts become per-wave offsets, and each key goes to
+//   scan[digit, tile] + offset[wave, digit] + rank.
+__global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __restrict__ keys_in,
+                                                          const uint32_t* __restrict__ vals_in,
+                                                          uint32_t* __restrict__ keys_out,
+                                                          uint32_t* __restrict__ vals_out, uint32_t n, int shift,
+                                                          int bits, const uint32_t* __restrict__ hist_scan,
+                                                          const uint32_t* __restrict__ block_sums, uint32_t ntiles) {
+    extern __shared__ uint32_t lds[];
+    const uint32_t radix = 1u << bits, mask = radix - 1;
+    uint32_t* cnt = lds;                 // [4][radix]
+    uint32_t* gbase = lds + 4 * radix;   // [radix]
+    const uint32_t tile = blockIdx.x;
+    for (uint32_t d = threadIdx.x; d < radix; d += kBlock) {
+        cnt[d] = 0;
+        cnt[radix + d] = 0;
+        cnt[2 * radix + d] = 0;
+        cnt[3 * radix + d] = 0;
+        size_t p = (size_t)d * ntiles + tile;
+        gbase[d] = hist_scan[p] + block_sums[p / kScanTile];
+    }
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t* wc = cnt + w * radix;
+    const uint64_t lt = lanemask_lt();
+    const uint32_t wbase = tile * kSortTile + w * (kWave * kSortIpt);
+    uint32_t key[kSortIpt], val[kSortIpt], loc[kSortIpt];
+#pragma unroll
+    for (int s = 0; s < kSortIpt; ++s) {
+        const uint32_t idx = wbase + s * kWave + lane;
+        const bool valid = idx < n;
+        const uint32_t k = valid ? keys_in[idx] : 0u;
+        const uint32_t v = valid ? (vals_in ? vals_in[idx] : idx) : 0u;
+        const uint32_t dg = (k >> shift) & mask;
+        uint64_t peers = __ballot(valid);
+        for (int b = 0; b < bits; ++b) {
+            const bool bit = (dg >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint32_t below = (uint32_t)__popcll(peers & lt);
+        const uint32_t c = valid ? wc[dg] : 0u;
+        if (valid && below == 0) wc[dg] = c + (uint32_t)__popcll(peers);
+        key[s] = k;
+        val[s] = v;
+        loc[s] = c + below;
+    }
+    __syncthreads();
+    for (uint32_t d = threadIdx.x; d < radix; d += kBlock) {
+        uint32_t a0 = cnt[d], a1 = cnt[radix + d], a2 = cnt[2 * radix + d];
+        cnt[d] = 0;
+        cnt[radix + d] = a0;
+        cnt[2 * radix + d] = a0 + a1;
+        cnt[3 * radix + d] = a0 + a1 + a2;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < kSortIpt; ++s) {
+        const uint32_t idx = wbase + s * kWave + lane;
+        if (idx < n) {
+            const uint32_t dg = (key[s] >> shift) & mask;
+            const uint32_t pos = gbase[dg] + wc[dg] + loc[s];
+            if (pos < n) {  // always true for a consistent histogram; keeps a bad one in bounds
+                keys_out[pos] = key[s];
+                vals_out[pos] = val[s];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a3 + a4: cell offsets and the gather into cell order
+// ---------------------------------------------------------------------------
+
+// Thread t < n writes off[c] = t for the cells c in (keys[t-1], keys[t]] (all
+// cells up to keys[0] for t = 0) and copies the position of particle perm[t]
+// to slot t.  Threads t <= ncells past the last key write off[t] = n.
+template <typename T, int D>
+__global__ __launch_bounds__(kBlock) void k_finalize(const uint32_t* __restrict__ keys,
+                                                     const uint32_t* __restrict__ perm, uint32_t n,
+                                                     const T* __restrict__ x, T* __restrict__ xs,
+                                                     uint32_t* __restrict__ off, uint32_t ncells) {
+    constexpr int PITCH = Pitch<D>::value;
+    const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
+    if (t < n) {
+        const uint32_t key = min(keys[t], ncells - 1u);
+        const uint32_t first = t == 0 ? 0u : keys[t - 1] + 1u;
+        for (uint32_t c = first; c <= key; ++c) off[c] = t;
+        const uint32_t p = min(perm[t], n - 1u);
+        VecN<T, PITCH> v;
+#pragma unroll
+        for (int k = 0; k < PITCH; ++k) v.v[k] = k < D ? x[(size_t)p * D + k] : T(0);
+        reinterpret_cast<VecN<T, PITCH>*>(xs)[t] = v;
+    }
+    if (t <= ncells) {
+        if (n == 0) off[t] = 0;
+        else if (t > keys[n - 1]) off[t] = n;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct GridPlan {
+    int32_t n[3] = {1, 1, 1};
+    double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0}, L[3] = {0, 0, 0}, inv_w[3] = {0, 0, 0};
+    double r = 0, r2 = 0;
+    int64_t ncells = 1;
+};
+
+double round_to(int dtype, double v) { return dtype == ABORIA_F32 ? (double)(float)v : v; }
+
+// Cell grid of one box: the largest per-dimension count whose cells are wider
+// than the cutoff by a guard of 16 unit roundoffs of the coordinate magnitude,
+// so that rounding in the cell assignment cannot separate a pair by more than
+// one cell.
+aboria_status plan_grid(aboria_ctx* ctx, int dtype, const aboria_box& b, GridPlan* g) {
+    const double u = dtype == ABORIA_F32 ? std::ldexp(1.0, -24) : std::ldexp(1.0, -53);
+    g->r = round_to(dtype, b.cutoff);
+    if (!(g->r > 0.0) || std::isinf(g->r)) return fail(ctx, ABORIA_ERR_INVALID_ARG, "cutoff must be positive and finite");
+    if (dtype == ABORIA_F32) {
+        float rf = (float)g->r;
+        g->r2 = (double)(rf * rf);
+    } else {
+        g->r2 = g->r * g->r;
+    }
+    int64_t total = 1;
+    for (int k = 0; k < b.d; ++k) {
+        g->lo[k] = round_to(dtype, b.lo[k]);
+        g->hi[k] = round_to(dtype, b.hi[k]);
+        if (!std::isfinite(g->lo[k]) || !std::isfinite(g->hi[k]) || !(g->hi[k] > g->lo[k]))
+            return fail(ctx, ABORIA_ERR_INVALID_ARG, "box needs finite lo < hi in every dimension");
+        g->L[k] = dtype == ABORIA_F32 ? (double)((float)g->hi[k] - (float)g->lo[k]) : g->hi[k] - g->lo[k];
+        const double guard = g->r + 16.0 * u * (std::fabs(g->lo[k]) + g->L[k]);
+        const double q = std::floor(g->L[k] / g->r);
+        int64_t nmax = q < 1.0 ? 1 : (q > 2147483647.0 ? 2147483647 : (int64_t)q);
+        while (nmax > 1 && g->L[k] / (double)nmax < guard) --nmax;
+        int64_t nk = nmax;
+        if (b.ncell[k] > 0) {
+            if (b.ncell[k] > nmax)
+                return fail(ctx, ABORIA_ERR_INVALID_ARG, "explicit ncell gives cells narrower than the guarded cutoff");
+            nk = b.ncell[k];
+        }
+        if (b.periodic[k] && g->L[k] < 2.0 * guard)
+            return fail(ctx, ABORIA_ERR_UNSUPPORTED, "periodic side shorter than twice the guarded cutoff");
+        g->n[k] = (int32_t)nk;
+        g->inv_w[k] = round_to(dtype, (double)nk / g->L[k]);
+        total *= nk;
+        if (total > 2147483647LL) return fail(ctx, ABORIA_ERR_UNSUPPORTED, "more than 2^31 cells");
+    }
+    g->ncells = total;
+    return ABORIA_OK;
+}
+
+template <typename T>
+void fill_params(const std::vector<GridPlan>& plans, const std::vector<aboria_box>& boxes,
+                 const std::vector<uint32_t>& cell_base, const std::vector<int64_t>& off,
+                 std::vector<unsigned char>* out) {
+    const size_t nsys = plans.size();
+    out->assign(nsys * sizeof(SysParams<T>), 0);
+    SysParams<T>* sp = reinterpret_cast<SysParams<T>*>(out->data());
+    for (size_t b = 0; b < nsys; ++b) {
+        SysParams<T> p;
+        std::memset(&p, 0, sizeof(p));
+        for (int k = 0; k < 3; ++k) {
+            p.lo[k] = (T)plans[b].lo[k];
+            p.hi[k] = (T)plans[b].hi[k];
+            p.L[k] = (T)plans[b].L[k];
+            p.inv_w[k] = (T)plans[b].inv_w[k];
+            p.n[k] = plans[b].n[k];
+            p.periodic[k] = k < boxes[b].d ? (boxes[b].periodic[k] != 0) : 0;
+        }
+        p.r = (T)plans[b].r;
+        p.r2 = (T)plans[b].r2;
+        p.cell_base = cell_base[b];
+        p.part_base = (uint32_t)off[b];
+        p.part_end = (uint32_t)off[b + 1];
+        std::memcpy(&sp[b], &p, sizeof(p));
+    }
+}
+
+void free_cells_buffers(aboria_cells* c) {
+    void* ptrs[] = {c->params_dev, c->sys_part_dev, c->keys, c->perm, c->keys_alt, c->perm_alt,
+                    c->off, c->xs, c->work, c->work2, c->hist, c->block_sums};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    c->params_dev = nullptr;
+    c->sys_part_dev = c->keys = c->perm = c->keys_alt = c->perm_alt = c->off = nullptr;
+    c->hist = c->block_sums = nullptr;
+    c->xs = c->work = c->work2 = nullptr;
+}
+
+template <typename T, int D>
+aboria_status launch_build(aboria_ctx* ctx, aboria_cells* c, const void* x) {
+    const uint32_t n = (uint32_t)c->n;
+    const SysParams<T>* sp = reinterpret_cast<const SysParams<T>*>(c->params_dev);
+    hipStream_t st = ctx->stream;
+    uint32_t* k0 = (c->passes % 2 == 1) ? c->keys_alt : c->keys;
+    uint32_t* v0 = (c->passes % 2 == 1) ? c->perm_alt : c->perm;
+    if (n > 0) {
+        const dim3 grid((n + kBlock - 1) / kBlock);
+        if (c->nsys == 1)
+            hipLaunchKernelGGL((k_cell_ids<T, D, false>), grid, dim3(kBlock), 0, st, (const T*)x, n, sp,
+                               c->sys_part_dev, c->nsys, k0, ctx->d_flag);
+        else
+            hipLaunchKernelGGL((k_cell_ids<T, D, true>), grid, dim3(kBlock), 0, st, (const T*)x, n, sp,
+                               c->sys_part_dev, c->nsys, k0, ctx->d_flag);
+        const uint32_t ntiles = (uint32_t)c->ntiles;
+        const uint32_t radix = 1u << c->digit_bits;
+        uint32_t *kin = k0, *vin = nullptr, *kout = (k0 == c->keys) ? c->keys_alt : c->keys;
+        uint32_t* vout = (k0 == c->keys) ? c->perm_alt : c->perm;
+        for (int p = 0; p < c->passes; ++p) {
+            const int shift = p * c->digit_bits;
+            hipLaunchKernelGGL(k_radix_hist, dim3(ntiles), dim3(kBlock), radix * sizeof(uint32_t), st, kin, n, shift,
+                               c->digit_bits, c->hist, ntiles);
+            aboria_status s = scan_exclusive_u32(ctx, c->hist, c->hist, (int64_t)radix * ntiles, c->block_sums,
+                                                 c->nblock_sums);
+            if (s != ABORIA_OK) return s;
+            hipLaunchKernelGGL(k_radix_scatter, dim3(ntiles), dim3(kBlock), 5 * radix * sizeof(uint32_t), st, kin,
+                               vin, kout, vout, n, shift, c->digit_bits, c->hist, c->block_sums, ntiles);
+            std::swap(kin, kout);
+            vin = vout;
+            vout = (vout == c->perm) ? c->perm_alt : c->perm;
+        }
+        (void)v0;
+    }
+    const uint32_t threads = std::max<uint32_t>(n, (uint32_t)c->ncells + 1);
+    hipLaunchKernelGGL((k_finalize<T, D>), dim3((threads + kBlock - 1) / kBlock), dim3(kBlock), 0, st, c->keys,
+                       c->perm, n, (const T*)x, (T*)c->xs, c->off, (uint32_t)c->ncells);
+    ABORIA_HIP(ctx, hipGetLastError());
+    return ABORIA_OK;
+}
+
+template <typename T>
+aboria_status dispatch_build(aboria_ctx* ctx, aboria_cells* c, const void* x) {
+    switch (c->d) {
+        case 1: return launch_build<T, 1>(ctx, c, x);
+        case 2: return launch_build<T, 2>(ctx, c, x);
+        default: return launch_build<T, 3>(ctx, c, x);
+    }
+}
+
+}  // namespace
+
+}  // namespace aboria
+
+using namespace aboria;
+
+extern "C" aboria_status aboria_build_cells(aboria_ctx* ctx, aboria_dtype dtype, int32_t nsys,
+                                            const aboria_box* boxes_host, const int64_t* offsets_host,
+                                            const void* x, aboria_cells** cells) {
+    if (!ctx) return ABORIA_ERR_INVALID_ARG;
+    try {
+        if (!cells) return fail(ctx, ABORIA_ERR_INVALID_ARG, "cells out-pointer is NULL");
+        if (dtype != ABORIA_F32 && dtype != ABORIA_F64) return fail(ctx, ABORIA_ERR_INVALID_ARG, "unknown dtype");
+        if (nsys < 1 || !boxes_host || !offsets_host)
+            return fail(ctx, ABORIA_ERR_INVALID_ARG, "need nsys >= 1, boxes and offsets");
+        const int32_t d = boxes_host[0].d;
+        if (d < 1 || d > 3) return fail(ctx, ABORIA_ERR_INVALID_ARG, "d must be 1, 2 or 3");
+        if (offsets_host[0] != 0) return fail(ctx, ABORIA_ERR_INVALID_ARG, "offsets must start at 0");
+        for (int32_t b = 0; b < nsys; ++b) {
+            if (boxes_host[b].d != d) return fail(ctx, ABORIA_ERR_INVALID_ARG, "all boxes must share d");
+            if (offsets_host[b + 1] < offsets_host[b]) return fail(ctx, ABORIA_ERR_INVALID_ARG, "offsets must not decrease");
+        }
+        const int64_t n = offsets_host[nsys];
+        if (n >= (int64_t)1 << 31) return fail(ctx, ABORIA_ERR_UNSUPPORTED, "at most 2^31 - 1 particles");
+        if (n > 0 && !x) return fail(ctx, ABORIA_ERR_INVALID_ARG, "x is NULL");
+        std::vector<GridPlan> plans((size_t)nsys);
+        std::vector<uint32_t> cell_base((size_t)nsys + 1, 0);
+        int64_t total_cells = 0;
+        for (int32_t b = 0; b < nsys; ++b) {
+            aboria_status s = plan_grid(ctx, dtype, boxes_host[b], &plans[b]);
+            if (s != ABORIA_OK) return s;
+            cell_base[b] = (uint32_t)total_cells;
+            total_cells += plans[b].ncells;
+            if (total_cells > 2147483647LL) return fail(ctx, ABORIA_ERR_UNSUPPORTED, "more than 2^31 cells in total");
+        }
+        cell_base[nsys] = (uint32_t)total_cells;
+        std::vector<aboria_box> boxes(boxes_host, boxes_host + nsys);
+        std::vector<int64_t> off(offsets_host, offsets_host + nsys + 1);
+        std::vector<unsigned char> params;
+        if (dtype == ABORIA_F32) fill_params<float>(plans, boxes, cell_base, off, &params);
+        else fill_params<double>(plans, boxes, cell_base, off, &params);
+
+        aboria_cells* c = *cells;
+        const bool create = c == nullptr;
+        if (!create) {
+            if (c->nsys != nsys || c->d != d || c->dtype != dtype || c->n != n)
+                return fail(ctx, ABORIA_ERR_INVALID_ARG, "rebuild must keep nsys, d, dtype and n");
+            if (c->ncells != total_cells || c->sys_off != off)
+                return fail(ctx, ABORIA_ERR_INVALID_ARG, "rebuild must keep the cell counts and system offsets");
+        }
+        if (create) {
+            if (ctx->capturing) return fail(ctx, ABORIA_ERR_UNSUPPORTED, "a first build allocates and cannot be captured");
+            ABORIA_HIP(ctx, hipSetDevice(ctx->device));
+            c = new (std::nothrow) aboria_cells();
+            if (!c) return fail(ctx, ABORIA_ERR_OUT_OF_MEMORY, "host allocation failed");
+            c->device = ctx->device;
+            c->dtype = dtype;
+            c->d = d;
+            c->nsys = nsys;
+            c->n = n;
+            c->ncells = total_cells;
+            c->pitch = d == 3 ? 4 : d;
+            c->sys_off = off;
+            int32_t bits = 1;
+            while (bits < 32 && ((int64_t)1 << bits) < total_cells) ++bits;
+            c->key_bits = bits;
+            c->passes = (bits + kMaxDigitBits - 1) / kMaxDigitBits;
+            c->digit_bits = (bits + c->passes - 1) / c->passes;
+            c->ntiles = (n + kSortTile - 1) / kSortTile;
+            c->hist_len = ((int64_t)1 << c->digit_bits) * std::max<int64_t>(c->ntiles, 1);
+            c->nblock_sums = std::max<int64_t>(scan_block_count(c->hist_len), 1);
+            const size_t tsz = dtype == ABORIA_F32 ? 4 : 8;
+            const size_t nn = (size_t)std::max<int64_t>(n, 1);
+            struct Alloc { void** p; size_t bytes; } allocs[] = {
+                {&c->params_dev, params.size()},
+                {(void**)&c->sys_part_dev, sizeof(uint32_t) * ((size_t)nsys + 1)},
+                {(void**)&c->keys, sizeof(uint32_t) * nn},
+                {(void**)&c->perm, sizeof(uint32_t) * nn},
+                {(void**)&c->keys_alt, sizeof(uint32_t) * nn},
+                {(void**)&c->perm_alt, sizeof(uint32_t) * nn},
+                {(void**)&c->off, sizeof(uint32_t) * ((size_t)total_cells + 1)},
+                {&c->xs, tsz * (size_t)c->pitch * nn},
+                {&c->work, tsz * 4 * nn},
+                {&c->work2, tsz * 4 * nn},
+                {(void**)&c->hist, sizeof(uint32_t) * (size_t)c->hist_len},
+                {(void**)&c->block_sums, sizeof(uint32_t) * (size_t)c->nblock_sums},
+            };
+            for (auto& a : allocs) {
+                if (hipMalloc(a.p, a.bytes) != hipSuccess) {
+                    (void)hipGetLastError();
+                    free_cells_buffers(c);
+                    delete c;
+                    return fail(ctx, ABORIA_ERR_OUT_OF_MEMORY, "device allocation for the cell list failed");
+                }
+            }
+            std::vector<uint32_t> part((size_t)nsys + 1);
+            for (int32_t b = 0; b <= nsys; ++b) part[b] = (uint32_t)off[b];
+            hipError_t e = hipMemcpyAsync(c->sys_part_dev, part.data(), part.size() * sizeof(uint32_t),
+                                          hipMemcpyHostToDevice, ctx->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+            if (e != hipSuccess) {
+                free_cells_buffers(c);
+                delete c;
+                return hip_fail(ctx, e, "upload of system offsets");
+            }
+        }
+        if (create || c->params_host != params) {
+            if (ctx->capturing) return fail(ctx, ABORIA_ERR_UNSUPPORTED, "changing boxes inside a graph capture");
+            hipError_t e = hipMemcpyAsync(c->params_dev, params.data(), params.size(), hipMemcpyHostToDevice,
+                                          ctx->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+            if (e != hipSuccess) {
+                if (create) { free_cells_buffers(c); delete c; }
+                return hip_fail(ctx, e, "upload of box parameters");
+            }
+            c->params_host = params;
+            c->boxes = boxes;
+            c->cell_base = cell_base;
+            c->ncell_host.assign((size_t)nsys * 3, 1);
+            for (int32_t b = 0; b < nsys; ++b)
+                for (int k = 0; k < 3; ++k) c->ncell_host[(size_t)b * 3 + k] = plans[b].n[k];
+        }
+        aboria_status s = dtype == ABORIA_F32 ? dispatch_build<float>(ctx, c, x) : dispatch_build<double>(ctx, c, x);
+        if (s != ABORIA_OK) {
+            if (create) { free_cells_buffers(c); delete c; }
+            return s;
+        }
+        *cells = c;
+        return ABORIA_OK;
+    } catch (...) {
+        return fail(ctx, ABORIA_ERR_OUT_OF_MEMORY, "host exception during build");
+    }
+}
+
+extern "C" aboria_status aboria_cells_view_get(const aboria_cells* c, aboria_cells_view* out) {
+    if (!c || !out) return ABORIA_ERR_INVALID_ARG;
+    std::memset(out, 0, sizeof(*out));
+    out->nsys = c->nsys;
+    out->d = c->d;
+    out->dtype = c->dtype;
+    out->n = c->n;
+    out->ncells = c->ncells;
+    out->perm = c->perm;
+    out->keys = c->keys;
+    out->cell_offsets = c->off;
+    out->x_sorted = c->xs;
+    out->x_pitch = c->pitch;
+    out->ncell_host = c->ncell_host.data();
+    out->cell_base_host = c->cell_base.data();
+    out->sys_offsets_host = c->sys_off.data();
+    return ABORIA_OK;
+}
+
+extern "C" aboria_status aboria_cells_destroy(aboria_cells* c) {
+    if (!c) return ABORIA_OK;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    free_cells_buffers(c);
+    delete c;
+    return ABORIA_OK;
+}

@@ -1,0 +1,163 @@
+// Internal definitions shared by the HIP sources of the library (not part of
+// the C-ABI).  Everything here is written for gfx950: wave64, 256 compute
+// units in 8 XCDs, LDS per workgroup.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/aboria.h"
+
+namespace aboria {
+
+constexpr int kWave = 64;
+constexpr int kNumXcd = 8;
+
+// Per-system cell-grid parameters in the working precision T, uploaded once per
+// build.  The rounded values follow the canonical rules of aboria_build_cells.
+template <typename T>
+struct SysParams {
+    T lo[3];
+    T hi[3];
+    T L[3];
+    T inv_w[3];
+    T r;
+    T r2;
+    int32_t n[3];
+    int32_t periodic[3];
+    uint32_t cell_base;  // first global cell id of the system
+    uint32_t part_base;  // first sorted slot (= first row) of the system
+    uint32_t part_end;   // one past its last slot
+    uint32_t pad;
+};
+
+// Aligned small vector so that one global load fetches a whole point.
+template <typename T, int N>
+struct alignas(sizeof(T) * N) VecN {
+    T v[N];
+};
+
+// Elements stored per particle in the cell-ordered position array: 3-d points
+// are padded to 4 so that one 16-byte (float) or 32-byte (double) load fetches
+// a point.
+template <int D>
+struct Pitch {
+    static constexpr int value = D == 3 ? 4 : D;
+};
+
+// Maps a hardware workgroup index to a logical tile so that consecutive tiles
+// land on the same XCD (the dispatcher deals workgroups round-robin over the 8
+// XCDs, each with its own L2): XCD x gets the contiguous tile range
+// [x * per, (x + 1) * per).  Neighbouring tiles of a cell-ordered array then
+// share an L2.  Valid for any grid size; the tail that does not divide evenly
+// keeps the identity mapping.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t bid, uint32_t nblocks) {
+    uint32_t per = nblocks / kNumXcd;
+    uint32_t full = per * kNumXcd;
+    if (bid >= full) return bid;
+    return (bid % kNumXcd) * per + bid / kNumXcd;
+}
+
+// Bit mask of lanes below the calling lane within the wave.
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    uint32_t lane = __lane_id();
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+struct Status {
+    aboria_status code = ABORIA_OK;
+    std::string msg;
+};
+
+}  // namespace aboria
+
+// Context and cell-list objects behind the opaque handles of the C-ABI.
+struct aboria_ctx {
+    int32_t device = 0;
+    hipStream_t stream = nullptr;
+    std::string last_error;
+    uint32_t* d_flag = nullptr;      // device error flag (bit 0: domain error)
+    uint32_t* h_flag = nullptr;      // pinned host copy
+    bool capturing = false;
+    void* scratch = nullptr;         // grow-only scratch for dense partial sums
+    size_t scratch_bytes = 0;
+    int32_t variant_forced = -1;
+    std::vector<std::pair<uint64_t, int32_t>> tune_cache;  // (key, variant)
+};
+
+struct aboria_cells {
+    int32_t device = 0;
+    int32_t dtype = 0;
+    int32_t d = 0;
+    int32_t nsys = 0;
+    int32_t pitch = 0;
+    int64_t n = 0;
+    int64_t ncells = 0;
+    std::vector<aboria_box> boxes;
+    std::vector<int64_t> sys_off;       // [nsys + 1]
+    std::vector<int32_t> ncell_host;    // [nsys * 3]
+    std::vector<uint32_t> cell_base;    // [nsys + 1]
+    std::vector<unsigned char> params_host;  // SysParams<T>[nsys] as uploaded
+    void* params_dev = nullptr;
+    uint32_t* sys_part_dev = nullptr;   // [nsys + 1] first slot of each system
+    uint32_t* keys = nullptr;           // [n] final sorted keys
+    uint32_t* perm = nullptr;           // [n] final permutation
+    uint32_t* keys_alt = nullptr;       // [n] radix ping-pong buffers
+    uint32_t* perm_alt = nullptr;
+    uint32_t* off = nullptr;            // [ncells + 1]
+    void* xs = nullptr;                 // [n][pitch] positions in cell order
+    void* work = nullptr;               // [n][4] gathered per-particle inputs
+    void* work2 = nullptr;              // [n][4]
+    uint32_t* hist = nullptr;           // radix histograms / scans
+    uint32_t* block_sums = nullptr;
+    int32_t key_bits = 0;
+    int32_t passes = 0;
+    int32_t digit_bits = 0;
+    int64_t ntiles = 0;
+    int64_t hist_len = 0;
+    int64_t nblock_sums = 0;
+};
+
+namespace aboria {
+
+// Error helpers used by the host code (sets ctx->last_error).
+aboria_status fail(aboria_ctx* ctx, aboria_status code, const std::string& msg);
+aboria_status hip_fail(aboria_ctx* ctx, hipError_t e, const char* what);
+
+#define ABORIA_HIP(ctx, call)                                        \
+    do {                                                             \
+        hipError_t _e = (call);                                      \
+        if (_e != hipSuccess) return ::aboria::hip_fail((ctx), _e, #call); \
+    } while (0)
+
+// Host launch helpers implemented in the .hip files.
+aboria_status scan_exclusive_u32(aboria_ctx* ctx, const uint32_t* in, uint32_t* out, int64_t len,
+                                 uint32_t* block_sums, int64_t nblock_sums);
+aboria_status scan_finish_u32(aboria_ctx* ctx, uint32_t* out, int64_t len, const uint32_t* block_sums);
+int64_t scan_block_count(int64_t len);
+aboria_status fill_u32(aboria_ctx* ctx, uint32_t* p, uint32_t v, int64_t len);
+
+// True if [a, a+na) and [b, b+nb) overlap (byte ranges).
+inline bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+    if (!a || !b || na == 0 || nb == 0) return false;
+    uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+    return a0 < b0 + nb && b0 < a0 + na;
+}
+
+int32_t op_ny(int32_t op, int32_t d);
+int32_t op_na(int32_t op);
+int32_t op_nparams(int32_t op);
+
+// Neighbour-sum variants (work mappings) selectable by the autotuner.
+int32_t variant_count();
+const char* variant_name(int32_t v);
+int32_t pick_variant(aboria_ctx* ctx, const aboria_cells* cells, int32_t op);
+uint64_t tune_key(const aboria_cells* cells, int32_t op);
+
+aboria_status pair_sum_impl(aboria_ctx* ctx, const aboria_cells* cells, int32_t op, const double* params,
+                            int32_t nparams, const void* a, int32_t na, void* y, int32_t ny, int32_t variant);
+
+}  // namespace aboria

@@ -1,0 +1,430 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle.
+
+Bit-exact: cell ids, permutation, cell offsets, sorted positions and pair sets.
+Float32 sums: per element within 1e-5 of the absolute-sum scale and normwise
+within 1e-5 of the float64 oracle.  Float64 sums: within 1e-12.
+"""
+import json
+import os
+import zlib
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1704_08907_amd as A
+from paper_1704_08907_amd import synthetic as syn
+from _parity import (TOL_F32, TOL_F64, box_of, cells_state, check_close, dev, gpu_pairs_sorted, to_dev,
+                     torch_dtype)
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+OPS = [("count", ()), ("spring", (1.0,)), ("soft_sphere", ()), ("exp_force", (0.7,)), ("dem_spring", (1.5,))]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = A.Context(0)
+    yield c
+    c.close()
+
+
+def tol_of(prec):
+    return TOL_F32 if prec == "f32" else TOL_F64
+
+
+def near_boundary(rng, g, n, prec):
+    d = g.d
+    x = np.zeros((n, d))
+    pt = np.float32 if prec == "f32" else np.float64
+    for k in range(d):
+        w = g.L[k] / g.n[k]
+        c = np.floor(rng.uniform(n) * g.n[k])
+        col = (g.lo[k] + c * w).astype(pt)
+        steps = np.floor(rng.uniform(n) * 7).astype(np.int64) - 3
+        for i in range(n):
+            v = col[i]
+            for _ in range(abs(steps[i])):
+                v = np.nextafter(v, pt(np.inf) if steps[i] > 0 else pt(-np.inf))
+            col[i] = v
+        col = np.clip(col, pt(g.lo[k]), np.nextafter(pt(g.hi[k]), pt(-np.inf)))
+        x[:, k] = col
+    return x.astype(pt)
+
+
+CASES = [
+    # id, d, hi, periodic, r, prec, ncell, n
+    ("d1_periodic", 1, [50.0], [1], 1.0, "f32", None, 5000),
+    ("d2_unit_f64", 2, [1.0, 1.0], [1, 1], 0.1, "f64", None, 1000),
+    ("d2_n1_n2", 2, [2.1, 2.6], [1, 1], 1.0, "f32", [1, 2], 700),
+    ("d2_mixed_tiles", 2, [30.0, 20.0], [0, 1], 0.9, "f32", None, 9000),
+    ("d3_periodic", 3, [12.0, 9.0, 15.0], [1, 1, 1], 1.0, "f32", None, 20000),
+    ("d3_open_f64", 3, [12.0, 9.0, 15.0], [0, 0, 0], 1.0, "f64", None, 10001),
+    ("d3_n2", 3, [2.2, 2.3, 2.4], [1, 1, 1], 1.0, "f32", None, 300),
+    ("d3_sparse", 3, [40.0, 40.0, 40.0], [1, 1, 1], 1.0, "f32", None, 30000),
+]
+
+
+def make_case(case):
+    name, d, hi, per, r, prec, ncell, n = case
+    g = oracle.grid(d, [0.0] * d, hi, per, r, prec, ncell)
+    rng = syn.SplitMix64(zlib.crc32(name.encode()))
+    x = syn.uniform_positions(rng, n - n // 5, [0.0] * d, hi, prec)
+    xb = near_boundary(rng, g, n // 5, prec)
+    x = np.ascontiguousarray(np.concatenate([x, xb]))
+    box = A.BoxSpec(d, [0.0] * d, hi, per, r, ncell)
+    return g, x, box, prec
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_cells_and_pairs_bit_exact(ctx, case):
+    g, x, box, prec = make_case(case)
+    print("case", case[0], flush=True)
+    cells = A.build_cells(ctx, to_dev(x), [box])
+    ctx.sync()
+    keys, perm, off, xs = cells_state(cells)
+    ids, st = oracle.cell_ids(g, x)
+    assert st == oracle.OK
+    operm, ooff = oracle.sort_cells(g, ids)
+    np.testing.assert_array_equal(perm, operm)
+    np.testing.assert_array_equal(keys, ids[operm])
+    np.testing.assert_array_equal(off, ooff)
+    np.testing.assert_array_equal(xs[:, :g.d], x[operm])
+    np.testing.assert_array_equal(gpu_pairs_sorted(ctx, cells), oracle.pairs(g, x.astype(np.float64)))
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("op,params", OPS, ids=[o[0] for o in OPS])
+def test_pair_sum_and_adjoint(ctx, case, op, params):
+    g, x, box, prec = make_case(case)
+    n, d = x.shape
+    print("case", case[0], op, flush=True)
+    rng = syn.SplitMix64(99)
+    tdt = torch_dtype(prec)
+    a = (0.2 + 0.3 * rng.uniform(n)).astype(x.dtype).reshape(n, 1) if op == "dem_spring" else None
+    ny = A.op_ny(op, d)
+    gy = rng.normal(n * ny).astype(x.dtype).reshape(n, ny)
+    cells = A.build_cells(ctx, to_dev(x), [box])
+    a_d = to_dev(a) if a is not None else None
+    y = A.pair_sum(ctx, cells, op, params, a_d)
+    gx, ga = A.pair_sum_backward(ctx, cells, op, params, to_dev(gy), a_d)
+    ctx.sync()
+    x64 = x.astype(np.float64)
+    yo, so = oracle.pair_sum(g, op, params, x64, a=a)
+    if op == "count":
+        np.testing.assert_array_equal(y.cpu().numpy()[:, 0], yo[:, 0])
+    else:
+        check_close(y.cpu().numpy(), yo, so, tol_of(prec), "forward " + op)
+    gxo, gao, sxo, sao = oracle.pair_sum_backward(g, op, params, x64, gy, a=a)
+    if op == "count":
+        assert torch.all(gx == 0)
+    else:
+        check_close(gx.cpu().numpy(), gxo, sxo, tol_of(prec), "adjoint " + op)
+    if op == "dem_spring":
+        check_close(ga.cpu().numpy(), gao.reshape(-1, 1), sao, tol_of(prec), "adjoint a")
+    assert y.dtype == tdt
+
+
+def test_hand_case(ctx):
+    with open(os.path.join(GOLD, "t1_hand_case.json")) as f:
+        t = json.load(f)
+    for prec in ("f32", "f64"):
+        x = np.array(t["x"], dtype=np.float32 if prec == "f32" else np.float64)
+        box = A.BoxSpec(2, t["lo"], t["hi"], t["periodic"], t["cutoff"], t["ncell"])
+        cells = A.build_cells(ctx, to_dev(x), [box])
+        keys, perm, off, _ = cells_state(cells)
+        assert perm.tolist() == t["perm"]
+        assert keys.tolist() == [t["cell_ids"][p] for p in t["perm"]]
+        assert off[8:13].tolist() == t["offsets_8_to_12"]
+        assert gpu_pairs_sorted(ctx, cells).tolist() == t["pairs"]
+        y = A.pair_sum(ctx, cells, "spring", (1.0,))
+        np.testing.assert_allclose(y.cpu().numpy(), np.array(t["spring_k1"]), rtol=0, atol=1e-6)
+        e = A.pair_sum(ctx, cells, "soft_sphere", ())
+        np.testing.assert_allclose(e.cpu().numpy()[:, 0], t["soft_sphere_energy"], rtol=1e-6, atol=1e-7)
+        gx, _ = A.pair_sum_backward(ctx, cells, "soft_sphere", (), torch.ones((6, 1), dtype=y.dtype, device=dev()))
+        np.testing.assert_allclose(gx.cpu().numpy(), t["soft_sphere_grad_gy1"], rtol=1e-5, atol=1e-5)
+        c = A.pair_sum(ctx, cells, "count", ())
+        assert c.cpu().numpy()[:, 0].tolist() == t["count"]
+
+
+# ---------------------------------------------------------------------------
+# the benchmark workloads at full size
+# ---------------------------------------------------------------------------
+
+def test_md_square_f64_vs_brute_force(ctx):
+    w = syn.md_square()
+    s = w.systems[0]
+    g = oracle.grid_of(s)
+    cells = A.build_cells(ctx, to_dev(s.x), [box_of(s)])
+    assert g.ncell == [9, 9]
+    np.testing.assert_array_equal(gpu_pairs_sorted(ctx, cells), oracle.pairs(g, s.x, oracle.ROUTE_BRUTE))
+    y = A.pair_sum(ctx, cells, "spring", (1.0,))
+    yo, so = oracle.pair_sum(g, "spring", (1.0,), s.x, route=oracle.ROUTE_BRUTE)
+    check_close(y.cpu().numpy(), yo, so, TOL_F64, "md square spring")
+    assert abs(y.sum(0)).max().item() < 1e-12 * so.sum()
+
+
+def test_spring_cube_full_size(ctx):
+    w = syn.spring_cube()
+    s = w.systems[0]
+    g = oracle.grid_of(s)
+    x_d = to_dev(s.x)
+    cells = A.build_cells(ctx, x_d, [box_of(s)])
+    y = A.pair_sum(ctx, cells, "spring", (1.0,))
+    gx, _ = A.pair_sum_backward(ctx, cells, "spring", (1.0,), to_dev(w.extra["gy"]))
+    cnt = A.pair_sum(ctx, cells, "count", ())
+    ctx.sync()
+    keys, perm, off, _ = cells_state(cells)
+    ids, _ = oracle.cell_ids(g, s.x)
+    operm, ooff = oracle.sort_cells(g, ids)
+    np.testing.assert_array_equal(perm, operm)
+    np.testing.assert_array_equal(off, ooff)
+    yo, so = oracle.pair_sum(g, "count", (), s.x)
+    np.testing.assert_array_equal(cnt.cpu().numpy()[:, 0], yo[:, 0])
+    yo, so = oracle.pair_sum(g, "spring", (1.0,), s.x)
+    check_close(y.cpu().numpy(), yo, so, TOL_F32, "spring cube forward")
+    gxo, _, sxo, _ = oracle.pair_sum_backward(g, "spring", (1.0,), s.x, w.extra["gy"])
+    check_close(gx.cpu().numpy(), gxo, sxo, TOL_F32, "spring cube adjoint")
+    rows = np.floor(syn.SplitMix64(5).uniform(128) * s.n).astype(np.int64)
+    yb, sb = oracle.pair_sum(g, "spring", (1.0,), s.x, rows=rows, route=oracle.ROUTE_BRUTE)
+    check_close(y.cpu().numpy()[rows], yb, sb, TOL_F32, "spring cube vs brute force rows")
+
+
+def test_soft_sphere_cube_full_size(ctx):
+    w = syn.soft_sphere_cube()
+    s = w.systems[0]
+    g = oracle.grid_of(s)
+    x_d = to_dev(s.x).requires_grad_(True)
+    from paper_1704_08907_amd.autograd import pair_sum as diff_pair_sum
+    e = diff_pair_sum(x_d, ctx, [box_of(s)], "soft_sphere")
+    E = e.sum()
+    (gx,) = torch.autograd.grad(E, x_d)
+    ctx.sync()
+    eo, so = oracle.pair_sum(g, "soft_sphere", (), s.x)
+    check_close(e.detach().cpu().numpy(), eo, so, TOL_F32, "soft sphere energy")
+    gxo, _, sxo, _ = oracle.pair_sum_backward(g, "soft_sphere", (), s.x, np.ones((s.n, 1)))
+    check_close(gx.cpu().numpy(), gxo, sxo, TOL_F32, "soft sphere gradient")
+    # finite differences of the oracle pin its analytic gradient; spot-check the GPU against them too
+    coords = np.floor(syn.SplitMix64(6).uniform(64) * s.n * 3).astype(np.int64)
+    fd = oracle.fd_grad(g, "soft_sphere", (), s.x.astype(np.float64), np.ones((s.n, 1)), coords, 1e-6)
+    got = gx.cpu().numpy().reshape(-1)[coords].astype(np.float64)
+    assert np.all(np.abs(got - fd) <= TOL_F32 * np.maximum(sxo[coords // 3], 1e-30) + 1e-6)
+
+
+def test_dense_gaussian_full_size(ctx):
+    x, wt, sigma = syn.gaussian_square()
+    y = A.dense_sum(ctx, to_dev(x), to_dev(x), to_dev(wt), sigma)
+    rows = np.floor(syn.SplitMix64(7).uniform(512) * x.shape[0]).astype(np.int64)
+    rows = np.concatenate([rows, [0, x.shape[0] - 1]])
+    yo, so = oracle.dense_gauss(x, x, wt, sigma, rows=rows)
+    got = y.cpu().numpy()[rows]
+    err = np.abs(got - yo)
+    assert np.all(err <= TOL_F32 * so), err.max()
+    assert np.linalg.norm(got - yo) <= TOL_F32 * np.linalg.norm(yo)
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_dense_small_all_rows(ctx, d, prec):
+    rng = syn.SplitMix64(100 + d)
+    nt, ns = 1000 + 37 * d, 3001
+    xt = syn.uniform_positions(rng, nt, [0.0] * d, [1.0] * d, prec)
+    xs = syn.uniform_positions(rng, ns, [0.0] * d, [1.0] * d, prec)
+    w = rng.normal(ns).astype(xt.dtype)
+    y = A.dense_sum(ctx, to_dev(xt), to_dev(xs), to_dev(w), 0.15)
+    yo, so = oracle.dense_gauss(xt, xs, w, 0.15)
+    tol = TOL_F32 if prec == "f32" else TOL_F64
+    assert np.all(np.abs(y.cpu().numpy() - yo) <= tol * so)
+
+
+def test_batch_uneven_systems(ctx):
+    w = syn.batch_cubes()
+    xs_all = np.concatenate([s.x for s in w.systems])
+    offsets = np.concatenate([[0], np.cumsum([s.n for s in w.systems])]).tolist()
+    boxes = [box_of(s) for s in w.systems]
+    cells = A.build_cells(ctx, to_dev(xs_all), boxes, offsets)
+    y = A.pair_sum(ctx, cells, "spring", (1.0,))
+    cnt = A.pair_sum(ctx, cells, "count", ())
+    gx, _ = A.pair_sum_backward(ctx, cells, "soft_sphere", (), to_dev(w.extra["gy"]))
+    ctx.sync()
+    keys, perm, off, _ = cells_state(cells)
+    v = cells.view()
+    cell_base = [v.cell_base_host[b] for b in range(len(boxes) + 1)]
+    y_h, c_h, gx_h = y.cpu().numpy(), cnt.cpu().numpy()[:, 0], gx.cpu().numpy()
+    check_rows = set(range(0, 512, 16)) | {int(np.argmin([s.n for s in w.systems])),
+                                           int(np.argmax([s.n for s in w.systems]))}
+    for b, s in enumerate(w.systems):
+        g = oracle.grid_of(s)
+        lo, hi = offsets[b], offsets[b + 1]
+        ids, st = oracle.cell_ids(g, s.x)
+        assert st == oracle.OK
+        operm, ooff = oracle.sort_cells(g, ids)
+        np.testing.assert_array_equal(perm[lo:hi], operm + lo)
+        np.testing.assert_array_equal(keys[lo:hi], ids[operm] + cell_base[b])
+        np.testing.assert_array_equal(off[cell_base[b]:cell_base[b + 1] + 1], ooff + lo)
+        if b in check_rows:
+            yo, so = oracle.pair_sum(g, "spring", (1.0,), s.x)
+            check_close(y_h[lo:hi], yo, so, TOL_F32, "batch spring system %d" % b)
+            co, _ = oracle.pair_sum(g, "count", (), s.x)
+            np.testing.assert_array_equal(c_h[lo:hi], co[:, 0])
+            go, _, sgo, _ = oracle.pair_sum_backward(g, "soft_sphere", (), s.x, np.ones((s.n, 1)))
+            check_close(gx_h[lo:hi], go, sgo, TOL_F32, "batch soft sphere adjoint system %d" % b)
+
+
+# ---------------------------------------------------------------------------
+# edge cases and the error model
+# ---------------------------------------------------------------------------
+
+def test_empty_and_single(ctx):
+    box = A.BoxSpec(3, [0, 0, 0], [5, 5, 5], [1, 1, 1], 1.0)
+    x = torch.zeros((0, 3), dtype=torch.float32, device=dev())
+    cells = A.build_cells(ctx, x, [box])
+    y = A.pair_sum(ctx, cells, "spring", (1.0,))
+    assert y.shape == (0, 3)
+    keys, perm, off, _ = cells_state(cells)
+    assert np.all(off == 0)
+    gx, _ = A.pair_sum_backward(ctx, cells, "spring", (1.0,), torch.zeros((0, 3), device=dev()))
+    assert gx.shape == (0, 3)
+    pi, pj = A.pair_list(ctx, cells)
+    assert pi.numel() == 0
+    x1 = torch.tensor([[1.0, 2.0, 3.0]], device=dev())
+    cells = A.build_cells(ctx, x1, [box])
+    assert A.pair_sum(ctx, cells, "count", ()).item() == 0
+    yd = A.dense_sum(ctx, x1, x1[:0], torch.zeros(0, device=dev()), 0.3)
+    assert yd.item() == 0.0
+    ctx.sync()
+
+
+def test_coincident_and_clustered(ctx):
+    # two coincident points are not neighbours (the listing's norm(dx) > 0); a
+    # dense cluster puts hundreds of points in one cell
+    rng = syn.SplitMix64(2024)
+    L = 10.0
+    clus = 4.0 + rng.uniform(600 * 3).reshape(600, 3) * 0.9
+    x = np.concatenate([clus, [[1.0, 1.0, 1.0], [1.0, 1.0, 1.0], [1.5, 1.0, 1.0]]]).astype(np.float32)
+    g = oracle.grid(3, [0] * 3, [L] * 3, [1, 1, 1], 1.0, "f32")
+    box = A.BoxSpec(3, [0] * 3, [L] * 3, [1, 1, 1], 1.0)
+    cells = A.build_cells(ctx, to_dev(x), [box])
+    np.testing.assert_array_equal(gpu_pairs_sorted(ctx, cells), oracle.pairs(g, x.astype(np.float64)))
+    y = A.pair_sum(ctx, cells, "spring", (1.0,))
+    yh = y.cpu().numpy()
+    assert np.all(np.isfinite(yh))
+    yo, so = oracle.pair_sum(g, "spring", (1.0,), x)
+    check_close(yh, yo, so, TOL_F32, "clustered spring")
+    c = A.pair_sum(ctx, cells, "count", ()).cpu().numpy()[:, 0]
+    assert c[600] == 1 and c[601] == 1 and c[602] == 2
+
+
+def test_domain_errors_reported_by_sync(ctx):
+    box = A.BoxSpec(2, [0, 0], [1, 1], [1, 1], 0.1)
+    for bad in ([[0.5, 0.5], [1.0, 0.2]], [[0.5, float("nan")]], [[-0.25, 0.5]]):
+        x = torch.tensor(bad, dtype=torch.float64, device=dev())
+        cells = A.build_cells(ctx, x, [box])
+        with pytest.raises(A.AboriaError) as e:
+            ctx.sync()
+        assert e.value.status == "DOMAIN"
+        cells.close()
+    ctx.sync()  # the flag was cleared
+
+
+def test_invalid_arguments_rejected_on_host(ctx):
+    x = torch.rand((100, 2), dtype=torch.float32, device=dev())
+    cases = [
+        (A.BoxSpec(2, [0, 0], [1, 1], [1, 1], 0.0), "INVALID_ARG"),
+        (A.BoxSpec(2, [0, 0], [1, 1], [1, 1], 0.6), "UNSUPPORTED"),
+        (A.BoxSpec(2, [0, 0], [1, 1], [0, 0], 0.1, [10, 10]), "INVALID_ARG"),
+        (A.BoxSpec(2, [0, 1], [1, 1], [0, 0], 0.1), "INVALID_ARG"),
+        (A.BoxSpec(4, [0, 0], [1, 1], [0, 0], 0.1), "INVALID_ARG"),
+    ]
+    for box, status in cases:
+        with pytest.raises(A.AboriaError) as e:
+            A.build_cells(ctx, x, [box])
+        assert e.value.status == status, (box, e.value)
+    cells = A.build_cells(ctx, x, [A.BoxSpec(2, [0, 0], [1, 1], [0, 0], 0.1)])
+    y = torch.empty((100, 2), device=dev())
+    a_alias = y.view(-1)[:100].view(100, 1)   # shares memory with y
+    with pytest.raises(A.AboriaError) as e:
+        A.pair_sum(ctx, cells, "dem_spring", (1.0,), a=a_alias, y=y)
+    assert e.value.status == "INVALID_ARG"
+    gy = torch.zeros((100, 2), device=dev())
+    with pytest.raises(A.AboriaError) as e:   # gx aliases gy
+        A.pair_sum_backward(ctx, cells, "spring", (1.0,), gy, gx=gy)
+    assert e.value.status == "INVALID_ARG"
+    with pytest.raises(A.AboriaError):
+        A.pair_sum(ctx, cells, "spring", ())   # missing k
+    ctx.sync()
+
+
+def test_rebuild_in_place_matches_fresh_build(ctx):
+    w = syn.spring_cube(50000)
+    s = w.systems[0]
+    x0 = to_dev(s.x)
+    cells = A.build_cells(ctx, x0, [box_of(s)])
+    L = float(s.hi[0])
+    x1 = torch.remainder(x0 + 0.37, L)
+    x1 = torch.where(x1 >= L, torch.zeros_like(x1), x1)
+    A.build_cells(ctx, x1, [box_of(s)], cells=cells)
+    y_re = A.pair_sum(ctx, cells, "spring", (1.0,))
+    fresh = A.build_cells(ctx, x1.clone(), [box_of(s)])
+    y_fr = A.pair_sum(ctx, fresh, "spring", (1.0,))
+    ctx.sync()
+    assert torch.equal(y_re, y_fr)
+    for a, b in zip(cells_state(cells), cells_state(fresh)):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_deterministic_and_variants_agree(ctx):
+    w = syn.spring_cube(60000)
+    s = w.systems[0]
+    cells = A.build_cells(ctx, to_dev(s.x), [box_of(s)])
+    ref = A.pair_sum(ctx, cells, "spring", (1.0,)).clone()
+    again = A.pair_sum(ctx, cells, "spring", (1.0,))
+    assert torch.equal(ref, again)
+    for v in range(A.variant_count()):
+        ctx.set_variant(v)
+        yv = A.pair_sum(ctx, cells, "spring", (1.0,))
+        assert torch.equal(yv, ref), A.variant_name(v)
+    ctx.set_variant(-1)
+    choice = A.autotune(ctx, cells, "spring", (1.0,))
+    assert 0 <= choice < A.variant_count()
+    assert torch.equal(A.pair_sum(ctx, cells, "spring", (1.0,)), ref)
+
+
+def test_graph_replay_matches_eager():
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        gctx = A.Context(0, stream)
+        w = syn.batch_cubes(nsys=24, nmax=8192)
+        xs_all = np.concatenate([s.x for s in w.systems])
+        offsets = np.concatenate([[0], np.cumsum([s.n for s in w.systems])]).tolist()
+        boxes = [box_of(s) for s in w.systems]
+        x = to_dev(xs_all)
+        gy = to_dev(w.extra["gy"])
+        cells = A.build_cells(gctx, x, boxes, offsets)
+        y = torch.empty((x.shape[0], 3), device=dev())
+        gx = torch.empty((x.shape[0], 3), device=dev())
+        A.pair_sum(gctx, cells, "spring", (1.0,), y=y)
+        A.pair_sum_backward(gctx, cells, "soft_sphere", (), gy, gx=gx)
+        stream.synchronize()
+        y_ref, gx_ref = y.clone(), gx.clone()
+        A.graph_capture_begin(gctx)
+        A.build_cells(gctx, x, boxes, offsets, cells=cells)
+        A.pair_sum(gctx, cells, "spring", (1.0,), y=y)
+        A.pair_sum_backward(gctx, cells, "soft_sphere", (), gy, gx=gx)
+        graph = A.graph_capture_end(gctx)
+        for rep in range(3):
+            y.zero_()
+            gx.zero_()
+            stream.synchronize()
+            A.graph_launch(gctx, graph)
+            stream.synchronize()
+            assert torch.equal(y, y_ref), rep
+            assert torch.equal(gx, gx_ref), rep
+            tmp = A.pair_sum(gctx, cells, "count", ())  # eager work between replays
+            stream.synchronize()
+            assert tmp.sum().item() > 0
+        graph.close()
+        gctx.sync()
+        gctx.close()
