@@ -1,0 +1,275 @@
+"""Benchmark of the cell-list neighbour operators on one MI355X.
+
+A step is one pass of the whole hot path over the 2^20-particle periodic cube
+(spring force, ~30 neighbours within r = 1, float32): rebuild the cell list
+from the original-order positions (cell ids, radix sort, offsets, gather),
+the neighbour-sum forward, and its adjoint for a seeded upstream gradient.  The
+step is captured once as a HIP graph and replayed.  The headline value is
+ordered pair interactions per second of the forward+adjoint step.
+
+Besides the JSON line's roofline (dominant kernel, HIP-event timed) and the
+CPU baseline (the C oracle, single thread, bounded sample), the line carries
+the per-phase breakdown and the other workloads: the dense Gaussian sum, the
+soft-sphere forward+adjoint, and 512 uneven systems in one graph.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X peaks used as roofline denominators
+HBM_PEAK_GBS = 8000.0
+# plain VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one lane-op per
+# lane per clock; packed fp32 is not used), in 10^12 lane-operations per second
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+# algorithmic VALU lane-operations: per candidate of the 3^d box search
+# (3 sub, 1 mul, 2 fma, 1 compare) and per accepted pair (spring forward:
+# rsqrt, 1 fma for g, 3 fma; spring adjoint: rsqrt, 3 sub, 3 fma for w.dx,
+# 2 mul for 1/s^3, 1 fma for g, 2 mul for g'/s and h, 6 fma)
+OPS_PER_CANDIDATE = 7
+OPS_PER_PAIR = {"fwd": 5, "bwd": 18}
+
+METRIC = "pair interactions/s (fwd and fwd+bwd) at stated tol; % HBM roofline"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def hip_download(ptr: int, count: int, dtype) -> np.ndarray:
+    out = np.zeros(max(count, 1), dtype=dtype)
+    if count:
+        hip = C.CDLL("libamdhip64.so")
+        hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+        assert hip.hipMemcpy(out.ctypes.data_as(C.c_void_p), C.c_void_p(ptr), count * out.itemsize, 2) == 0
+    return out[:count]
+
+
+def candidate_count(cells) -> int:
+    """Candidates the 3^3 box search tests: sum over cells of count(c) * count(3^3 around c)."""
+    v = cells.view()
+    off = hip_download(v.cell_offsets, int(v.ncells) + 1, np.uint32).astype(np.int64)
+    n = [v.ncell_host[k] for k in range(3)]
+    cnt = np.diff(off).reshape(n[2], n[1], n[0])
+    s = np.zeros_like(cnt)
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                s += np.roll(cnt, (dz, dy, dx), axis=(0, 1, 2))
+    return int((cnt * s).sum())
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the secondary workloads")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1704_08907_amd as A
+    from paper_1704_08907_amd import synthetic as syn
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(dev)
+    torch.cuda.set_stream(stream)
+    ctx = A.Context(0, stream)
+
+    # ---------------- headline workload: spring cube, build + fwd + bwd ----------------
+    w = syn.spring_cube()
+    s = w.systems[0]
+    box = A.BoxSpec(3, s.lo, s.hi, s.periodic, s.cutoff)
+    x = torch.from_numpy(s.x).to(dev)
+    gy = torch.from_numpy(w.extra["gy"]).to(dev)
+    n = s.n
+    cells = A.build_cells(ctx, x, [box])
+    y = torch.empty((n, 3), device=dev)
+    gx = torch.empty((n, 3), device=dev)
+    cnt = A.pair_sum(ctx, cells, "count", ())
+    ctx.sync()
+    pairs = int(cnt.sum().item())
+    cand = candidate_count(cells)
+    log("spring cube: n=%d pairs=%d candidates=%d (%.1f/particle)" % (n, pairs, cand, cand / n))
+
+    def step():
+        A.build_cells(ctx, x, [box], cells=cells)
+        A.pair_sum(ctx, cells, "spring", (1.0,), y=y)
+        A.pair_sum_backward(ctx, cells, "spring", (1.0,), gy, gx=gx)
+
+    step()
+    stream.synchronize()
+    A.graph_capture_begin(ctx)
+    step()
+    graph = A.graph_capture_end(ctx)
+
+    for _ in range(args.warmup):
+        A.graph_launch(ctx, graph)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        A.graph_launch(ctx, graph)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.sync()
+    wall_ms = (t1 - t0) * 1e3 / args.steps
+    ev_ms = ev0.elapsed_time(ev1) / args.steps
+    ms = max(wall_ms, ev_ms)
+    value = pairs / (ms * 1e-3)
+    log("step: %.3f ms (events %.3f ms, wall %.3f ms) -> %.3e pairs/s" % (ms, ev_ms, wall_ms, value))
+
+    # ---------------- per-phase breakdown (eager, HIP events on the context stream) -----
+    def timed(fn, reps=20):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    t_build = timed(lambda: A.build_cells(ctx, x, [box], cells=cells))
+    t_fwd = timed(lambda: A.pair_sum(ctx, cells, "spring", (1.0,), y=y))
+    t_bwd = timed(lambda: A.pair_sum_backward(ctx, cells, "spring", (1.0,), gy, gx=gx))
+    ctx.sync()
+    ops_fwd = cand * OPS_PER_CANDIDATE + pairs * OPS_PER_PAIR["fwd"]
+    ops_bwd = cand * OPS_PER_CANDIDATE + pairs * OPS_PER_PAIR["bwd"]
+    # the adjoint call also gathers gy into cell order (a small copy kernel)
+    dominant = "bwd" if t_bwd >= t_fwd else "fwd"
+    t_dom = t_bwd if dominant == "bwd" else t_fwd
+    ops_dom = ops_bwd if dominant == "bwd" else ops_fwd
+    achieved = ops_dom / (t_dom * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": "k_pair_%s<float,3,SPRING>" % dominant, "achieved": achieved,
+                "peak": VALU_PEAK_TOPS, "unit": "Tops/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                "algorithmic_ops_per_launch": ops_dom, "avg_launch_ms": t_dom}
+    # build bytes: x in (12 B), keys+perm through 2 radix passes, offsets, sorted x out (16 B)
+    build_bytes = n * (12 + 4 + 2 * (4 + 4 + 8 + 8) + 4 + 16) + 4 * (int(cells.view().ncells) + 1)
+    breakdown = {"build_ms": t_build, "fwd_ms": t_fwd, "bwd_ms": t_bwd,
+                 "build_hbm_frac": build_bytes / (t_build * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                 "fwd_pairs_per_s": pairs / ((t_build + t_fwd) * 1e-3),
+                 "fwd_only_pairs_per_s": pairs / (t_fwd * 1e-3),
+                 "fwd_valu_frac": ops_fwd / (t_fwd * 1e-3) / 1e12 / VALU_PEAK_TOPS,
+                 "bwd_valu_frac": ops_bwd / (t_bwd * 1e-3) / 1e12 / VALU_PEAK_TOPS,
+                 "candidates_per_step": cand}
+    log("breakdown", json.dumps(breakdown))
+
+    # ---------------- other workloads ----------------
+    extra = {}
+    if not args.no_extra:
+        # dense Gaussian sum, N = 65536, d = 2
+        xd, wd, sigma = syn.gaussian_square()
+        xd_t = torch.from_numpy(xd).to(dev)
+        wd_t = torch.from_numpy(wd).to(dev)
+        yd = torch.empty(xd.shape[0], device=dev)
+        t_dense = timed(lambda: A.dense_sum(ctx, xd_t, xd_t, wd_t, sigma, y=yd), reps=10)
+        npair = float(xd.shape[0]) ** 2
+        # per pair: 2 sub, 1 mul, 1 fma, 1 exp2, 1 fma
+        extra["dense_gaussian_n65536"] = {"ms": t_dense, "pairs_per_s": npair / (t_dense * 1e-3),
+                                          "valu_frac": npair * 6 / (t_dense * 1e-3) / 1e12 / VALU_PEAK_TOPS}
+        del xd_t, wd_t, yd
+        # soft sphere N = 2^18 forward + adjoint (energy gradient)
+        w4 = syn.soft_sphere_cube()
+        s4 = w4.systems[0]
+        box4 = A.BoxSpec(3, s4.lo, s4.hi, s4.periodic, s4.cutoff)
+        x4 = torch.from_numpy(s4.x).to(dev)
+        g4 = torch.from_numpy(w4.extra["gy"]).to(dev)
+        c4 = A.build_cells(ctx, x4, [box4])
+        e4 = torch.empty((s4.n, 1), device=dev)
+        gx4 = torch.empty((s4.n, 3), device=dev)
+        p4 = int(A.pair_sum(ctx, c4, "count", ()).sum().item())
+
+        def step4():
+            A.build_cells(ctx, x4, [box4], cells=c4)
+            A.pair_sum(ctx, c4, "soft_sphere", (), y=e4)
+            A.pair_sum_backward(ctx, c4, "soft_sphere", (), g4, gx=gx4)
+
+        t4 = timed(step4, reps=10)
+        extra["soft_sphere_n262144_fwd_bwd"] = {"ms": t4, "pairs": p4, "pairs_per_s": p4 / (t4 * 1e-3)}
+        # 512 uneven systems: spring forward + soft-sphere adjoint in one graph
+        w5 = syn.batch_cubes()
+        xs5 = np.concatenate([q.x for q in w5.systems])
+        off5 = np.concatenate([[0], np.cumsum([q.n for q in w5.systems])]).tolist()
+        boxes5 = [A.BoxSpec(3, q.lo, q.hi, q.periodic, q.cutoff) for q in w5.systems]
+        x5 = torch.from_numpy(xs5).to(dev)
+        g5 = torch.from_numpy(w5.extra["gy"]).to(dev)
+        c5 = A.build_cells(ctx, x5, boxes5, off5)
+        y5 = torch.empty((x5.shape[0], 3), device=dev)
+        gx5 = torch.empty((x5.shape[0], 3), device=dev)
+        p5 = int(A.pair_sum(ctx, c5, "count", ()).sum().item())
+        A.autotune(ctx, c5, "spring", (1.0,))
+
+        def step5():
+            A.build_cells(ctx, x5, boxes5, off5, cells=c5)
+            A.pair_sum(ctx, c5, "spring", (1.0,), y=y5)
+            A.pair_sum_backward(ctx, c5, "soft_sphere", (), g5, gx=gx5)
+
+        step5()
+        stream.synchronize()
+        A.graph_capture_begin(ctx)
+        step5()
+        g5graph = A.graph_capture_end(ctx)
+        t5 = timed(lambda: A.graph_launch(ctx, g5graph), reps=10)
+        ctx.sync()
+        # the same systems' single-system rate reference: the headline cube's step rate
+        extra["batch_512_systems"] = {"ms": t5, "particles": int(x5.shape[0]), "pairs": p5,
+                                      "pairs_per_s": p5 / (t5 * 1e-3),
+                                      "ratio_to_single_cube": (p5 / t5) / (pairs / ms)}
+        log("extra", json.dumps(extra))
+
+    # ---------------- CPU baseline: the oracle on the host ----------------
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        g = oracle.grid_of(s)
+        gy_h = w.extra["gy"].astype(np.float64)
+        x64 = s.x.astype(np.float64)
+        times = []
+        t_start = time.perf_counter()
+        while len(times) < 3 and (time.perf_counter() - t_start) < 20.0:
+            c0 = time.perf_counter()
+            ids, _ = oracle.cell_ids(g, x64)
+            oracle.sort_cells(g, ids)
+            oracle.pair_sum(g, "spring", (1.0,), x64)
+            oracle.pair_sum_backward(g, "spring", (1.0,), x64, gy_h)
+            times.append(time.perf_counter() - c0)
+        tc = float(np.median(times))
+        cpu = {"value": pairs / tc, "unit": "pair interactions/s", "cores": 1, "kind": "oracle",
+               "sample": "full spring cube (N=2^20): cell ids + counting sort + linked-list spring forward "
+                         "+ adjoint in float64, single thread, median of %d runs (%.2f s each)" % (len(times), tc)}
+        log("cpu baseline", json.dumps(cpu))
+
+    out = {"metric": METRIC, "value": value, "unit": "pair interactions/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": w.name, "n": n, "box_side": float(s.hi[0]), "cutoff": 1.0,
+                      "pairs_per_step": pairs, "step": "cell rebuild + spring forward + adjoint, one hipGraph",
+                      "parallelism": "single GPU"},
+           "roofline": roofline, "cpu_baseline": cpu, "breakdown": breakdown, "other_workloads": extra}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

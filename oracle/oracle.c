@@ -43,6 +43,12 @@
  *      sphere e_i = 1/2 sum (1 - s/r)^2; the paper's eq. (1) force
  *      y_i = sum -c exp(-s) dx/s; a spring with per-particle resting lengths
  *      y_i = sum k (a_i + a_j - s) u/s (the DEM example of Section 1.1).
+ *   R6 the error scale of a row (what "relative tolerance" is relative to): the
+ *      sum over its summands of their max-norm plus their first-order change
+ *      under a relative change of the pair displacement.  A summand that
+ *      cancels near the cutoff (k (r - s) as s -> r) cannot be evaluated in
+ *      float32 more accurately than its distance is rounded, so its own
+ *      magnitude alone is not a usable scale.
  */
 #include <math.h>
 #include <stdint.h>
@@ -431,6 +437,36 @@ static double radial_g(int op, const double* prm, double r, double s, double ai,
     }
 }
 
+/* Forward summand of one ordered pair, u = x_i - (x_j + shift), in float64. */
+static void fwd_term(const or_grid* g, int op, const double* prm, const double* u, double ai, double aj,
+                     double* t) {
+    double s2 = 0.0;
+    for (int k = 0; k < g->d; ++k) s2 += u[k] * u[k];
+    double dist = sqrt(s2);
+    switch (op) {
+        case OR_OP_COUNT:
+            t[0] = 1.0;
+            break;
+        case OR_OP_SOFT_SPHERE: {
+            double v = 1.0 - dist / g->r;
+            t[0] = 0.5 * v * v;
+            break;
+        }
+        default: {
+            double dg;
+            double gv = radial_g(op, prm, g->r, dist, ai, aj, &dg);
+            for (int k = 0; k < g->d; ++k) t[k] = gv * u[k];
+            break;
+        }
+    }
+}
+
+/* Relative step used to measure how strongly a summand reacts to a relative
+ * change of its pair displacement (what rounding of the pair distance does to
+ * a computed summand).  The tolerance scale of a row adds this first-order
+ * sensitivity to the summands' magnitudes. */
+#define OR_SENS_EPS 1e-6
+
 typedef struct {
     const or_grid* g;
     int op;
@@ -456,39 +492,29 @@ static void sum_begin(void* vctx, int64_t r, int64_t i) {
 static void sum_pair(void* vctx, int64_t i, int64_t j, const double* s) {
     sum_ctx* c = (sum_ctx*)vctx;
     const or_grid* g = c->g;
-    double u[3];
-    double dist = pair_u(g, c->x + i * g->d, c->x + j * g->d, s, u);
+    double u[3], up[3], t[3] = {0, 0, 0}, tp[3] = {0, 0, 0};
+    pair_u(g, c->x + i * g->d, c->x + j * g->d, s, u);
     double ai = c->a ? c->a[i] : 0.0, aj = c->a ? c->a[j] : 0.0;
-    switch (c->op) {
-        case OR_OP_COUNT:
-            c->yrow[0] += 1.0;
-            if (c->srow) *c->srow += 1.0;
-            break;
-        case OR_OP_SOFT_SPHERE: {
-            double v = 1.0 - dist / g->r;
-            double term = 0.5 * v * v;
-            c->yrow[0] += term;
-            if (c->srow) *c->srow += fabs(term);
-            break;
+    fwd_term(g, c->op, c->prm, u, ai, aj, t);
+    for (int k = 0; k < c->ny; ++k) c->yrow[k] += t[k];
+    if (c->srow) {
+        for (int k = 0; k < 3; ++k) up[k] = u[k] * (1.0 + OR_SENS_EPS);
+        fwd_term(g, c->op, c->prm, up, ai, aj, tp);
+        double mx = 0.0, sens = 0.0;
+        for (int k = 0; k < c->ny; ++k) {
+            if (fabs(t[k]) > mx) mx = fabs(t[k]);
+            double dk = fabs(tp[k] - t[k]) / OR_SENS_EPS;
+            if (dk > sens) sens = dk;
         }
-        default: {
-            double dg;
-            double gv = radial_g(c->op, c->prm, g->r, dist, ai, aj, &dg);
-            double mx = 0.0;
-            for (int k = 0; k < g->d; ++k) {
-                double t = gv * u[k];
-                c->yrow[k] += t;
-                if (fabs(t) > mx) mx = fabs(t);
-            }
-            if (c->srow) *c->srow += mx;
-            break;
-        }
+        *c->srow += mx + sens;
     }
 }
 
 /* y[row][ny] = sum over the accepted neighbours of the requested rows (all rows
- * if rows == NULL); scale[row] = sum of the summands' max-norms (the
- * absolute-sum scale the tolerance is relative to).  a is [n] or NULL. */
+ * if rows == NULL).  scale[row] = sum over the row's summands of their max-norm
+ * plus their first-order sensitivity to a relative change of the pair
+ * displacement: the scale a float32 evaluation's error is measured against.
+ * a is [n] or NULL. */
 int or_pair_sum(const or_grid* g, int32_t route, int32_t op, const double* prm, int64_t n, const double* x,
                 const double* a, int64_t nrows, const int64_t* rows, double* y, double* scale) {
     int ny = or_op_ny(op, g->d);
@@ -543,49 +569,58 @@ static void bwd_begin(void* vctx, int64_t r, int64_t i) {
     if (c->sarow) *c->sarow = 0.0;
 }
 
-static void bwd_pair(void* vctx, int64_t k, int64_t i, const double* s) {
-    bwd_ctx* c = (bwd_ctx*)vctx;
-    const or_grid* g = c->g;
+/* Adjoint contribution of the ordered pair (k, i), u = x_k - (x_i + shift). */
+static void bwd_term(const or_grid* g, int op, const double* prm, const double* u, double ak, double ai,
+                     const double* gyk, const double* gyi, double* gx, double* ga) {
     int d = g->d;
-    double u[3];
-    double dist = pair_u(g, c->x + k * d, c->x + i * d, s, u);
-    const double* gyk = c->gy + k * c->ny;
-    const double* gyi = c->gy + i * c->ny;
-    if (c->op == OR_OP_COUNT) return;
-    if (c->op == OR_OP_SOFT_SPHERE) {
+    double s2 = 0.0;
+    for (int m = 0; m < d; ++m) s2 += u[m] * u[m];
+    double dist = sqrt(s2);
+    for (int m = 0; m < 3; ++m) gx[m] = 0.0;
+    *ga = 0.0;
+    if (op == OR_OP_COUNT) return;
+    if (op == OR_OP_SOFT_SPHERE) {
         double dphi = -(2.0 / g->r) * (1.0 - dist / g->r);
         double coef = 0.5 * (gyk[0] + gyi[0]) * dphi / dist;
-        double mx = 0.0;
-        for (int m = 0; m < d; ++m) {
-            double t = coef * u[m];
-            c->gxrow[m] += t;
-            if (fabs(t) > mx) mx = fabs(t);
-        }
-        if (c->sxrow) *c->sxrow += mx;
+        for (int m = 0; m < d; ++m) gx[m] = coef * u[m];
         return;
     }
-    double ak = c->a ? c->a[k] : 0.0, ai = c->a ? c->a[i] : 0.0;
     double dg;
-    double gv = radial_g(c->op, c->prm, g->r, dist, ak, ai, &dg);
+    double gv = radial_g(op, prm, g->r, dist, ak, ai, &dg);
     double w[3] = {0, 0, 0};
     double uw = 0.0;
     for (int m = 0; m < d; ++m) {
         w[m] = gyk[m] - gyi[m];
         uw += u[m] * w[m];
     }
-    double mx = 0.0;
-    for (int m = 0; m < d; ++m) {
-        double t = gv * w[m] + (dg / dist) * uw * u[m];
-        c->gxrow[m] += t;
-        double bound = fabs(gv * w[m]) + fabs((dg / dist) * uw * u[m]);
-        if (bound > mx) mx = bound;
+    for (int m = 0; m < d; ++m) gx[m] = gv * w[m] + (dg / dist) * uw * u[m];
+    if (op == OR_OP_DEM_SPRING) *ga = prm[0] * uw / dist;
+}
+
+static void bwd_pair(void* vctx, int64_t k, int64_t i, const double* s) {
+    bwd_ctx* c = (bwd_ctx*)vctx;
+    const or_grid* g = c->g;
+    int d = g->d;
+    double u[3], up[3], t[3], tp[3], ta, tap;
+    pair_u(g, c->x + k * d, c->x + i * d, s, u);
+    const double* gyk = c->gy + k * c->ny;
+    const double* gyi = c->gy + i * c->ny;
+    double ak = c->a ? c->a[k] : 0.0, ai = c->a ? c->a[i] : 0.0;
+    bwd_term(g, c->op, c->prm, u, ak, ai, gyk, gyi, t, &ta);
+    for (int m = 0; m < d; ++m) c->gxrow[m] += t[m];
+    if (c->garow) *c->garow += ta;
+    for (int m = 0; m < 3; ++m) up[m] = u[m] * (1.0 + OR_SENS_EPS);
+    bwd_term(g, c->op, c->prm, up, ak, ai, gyk, gyi, tp, &tap);
+    if (c->sxrow) {
+        double mx = 0.0, sens = 0.0;
+        for (int m = 0; m < d; ++m) {
+            if (fabs(t[m]) > mx) mx = fabs(t[m]);
+            double dm = fabs(tp[m] - t[m]) / OR_SENS_EPS;
+            if (dm > sens) sens = dm;
+        }
+        *c->sxrow += mx + sens;
     }
-    if (c->sxrow) *c->sxrow += mx;
-    if (c->op == OR_OP_DEM_SPRING && c->garow) {
-        double t = c->prm[0] * uw / dist;
-        *c->garow += t;
-        if (c->sarow) *c->sarow += fabs(t);
-    }
+    if (c->sarow) *c->sarow += fabs(ta) + fabs(tap - ta) / OR_SENS_EPS;
 }
 
 /* gx[row][d], ga[row] (DEM spring only, else may be NULL); scale_x / scale_a as
