@@ -44,8 +44,9 @@
  *      y_i = sum -c exp(-s) dx/s; a spring with per-particle resting lengths
  *      y_i = sum k (a_i + a_j - s) u/s (the DEM example of Section 1.1).
  *   R6 the error scale of a row (what "relative tolerance" is relative to): the
- *      sum over its summands of their max-norm plus their first-order change
- *      under a relative change of the pair displacement.  A summand that
+ *      sum over its summands of the magnitudes of the products each summand is
+ *      made of (the usual forward-error scale of a sum) plus the summand's
+ *      first-order change under a relative change of the pair displacement.  A summand that
  *      cancels near the cutoff (k (r - s) as s -> r) cannot be evaluated in
  *      float32 more accurately than its distance is rounded, so its own
  *      magnitude alone is not a usable scale.
@@ -569,20 +570,24 @@ static void bwd_begin(void* vctx, int64_t r, int64_t i) {
     if (c->sarow) *c->sarow = 0.0;
 }
 
-/* Adjoint contribution of the ordered pair (k, i), u = x_k - (x_i + shift). */
+/* Adjoint contribution of the ordered pair (k, i), u = x_k - (x_i + shift);
+ * mag[m] receives the summed magnitudes of the products that make up gx[m]. */
 static void bwd_term(const or_grid* g, int op, const double* prm, const double* u, double ak, double ai,
-                     const double* gyk, const double* gyi, double* gx, double* ga) {
+                     const double* gyk, const double* gyi, double* gx, double* ga, double* mag) {
     int d = g->d;
     double s2 = 0.0;
     for (int m = 0; m < d; ++m) s2 += u[m] * u[m];
     double dist = sqrt(s2);
-    for (int m = 0; m < 3; ++m) gx[m] = 0.0;
+    for (int m = 0; m < 3; ++m) gx[m] = mag[m] = 0.0;
     *ga = 0.0;
     if (op == OR_OP_COUNT) return;
     if (op == OR_OP_SOFT_SPHERE) {
         double dphi = -(2.0 / g->r) * (1.0 - dist / g->r);
         double coef = 0.5 * (gyk[0] + gyi[0]) * dphi / dist;
-        for (int m = 0; m < d; ++m) gx[m] = coef * u[m];
+        for (int m = 0; m < d; ++m) {
+            gx[m] = coef * u[m];
+            mag[m] = fabs(gx[m]);
+        }
         return;
     }
     double dg;
@@ -593,7 +598,10 @@ static void bwd_term(const or_grid* g, int op, const double* prm, const double* 
         w[m] = gyk[m] - gyi[m];
         uw += u[m] * w[m];
     }
-    for (int m = 0; m < d; ++m) gx[m] = gv * w[m] + (dg / dist) * uw * u[m];
+    for (int m = 0; m < d; ++m) {
+        gx[m] = gv * w[m] + (dg / dist) * uw * u[m];
+        mag[m] = fabs(gv * w[m]) + fabs((dg / dist) * uw * u[m]);
+    }
     if (op == OR_OP_DEM_SPRING) *ga = prm[0] * uw / dist;
 }
 
@@ -601,20 +609,20 @@ static void bwd_pair(void* vctx, int64_t k, int64_t i, const double* s) {
     bwd_ctx* c = (bwd_ctx*)vctx;
     const or_grid* g = c->g;
     int d = g->d;
-    double u[3], up[3], t[3], tp[3], ta, tap;
+    double u[3], up[3], t[3], tp[3], mag[3], magp[3], ta, tap;
     pair_u(g, c->x + k * d, c->x + i * d, s, u);
     const double* gyk = c->gy + k * c->ny;
     const double* gyi = c->gy + i * c->ny;
     double ak = c->a ? c->a[k] : 0.0, ai = c->a ? c->a[i] : 0.0;
-    bwd_term(g, c->op, c->prm, u, ak, ai, gyk, gyi, t, &ta);
+    bwd_term(g, c->op, c->prm, u, ak, ai, gyk, gyi, t, &ta, mag);
     for (int m = 0; m < d; ++m) c->gxrow[m] += t[m];
     if (c->garow) *c->garow += ta;
     for (int m = 0; m < 3; ++m) up[m] = u[m] * (1.0 + OR_SENS_EPS);
-    bwd_term(g, c->op, c->prm, up, ak, ai, gyk, gyi, tp, &tap);
+    bwd_term(g, c->op, c->prm, up, ak, ai, gyk, gyi, tp, &tap, magp);
     if (c->sxrow) {
         double mx = 0.0, sens = 0.0;
         for (int m = 0; m < d; ++m) {
-            if (fabs(t[m]) > mx) mx = fabs(t[m]);
+            if (mag[m] > mx) mx = mag[m];
             double dm = fabs(tp[m] - t[m]) / OR_SENS_EPS;
             if (dm > sens) sens = dm;
         }
