@@ -44,9 +44,11 @@
  *      y_i = sum -c exp(-s) dx/s; a spring with per-particle resting lengths
  *      y_i = sum k (a_i + a_j - s) u/s (the DEM example of Section 1.1).
  *   R6 the error scale of a row (what "relative tolerance" is relative to): the
- *      sum over its summands of the magnitudes of the products each summand is
- *      made of (the usual forward-error scale of a sum) plus the summand's
- *      first-order change under a relative change of the pair displacement.  A summand that
+ *      sum over its summands of (a) the summand's formula evaluated with every
+ *      input and intermediate replaced by its magnitude -- the componentwise
+ *      forward-error scale of a floating-point evaluation -- plus (b) the
+ *      summand's first-order change under a relative change of the pair
+ *      displacement, which rounding of the pair distance causes.  A summand that
  *      cancels near the cutoff (k (r - s) as s -> r) cannot be evaluated in
  *      float32 more accurately than its distance is rounded, so its own
  *      magnitude alone is not a usable scale.
@@ -438,25 +440,44 @@ static double radial_g(int op, const double* prm, double r, double s, double ai,
     }
 }
 
-/* Forward summand of one ordered pair, u = x_i - (x_j + shift), in float64. */
+/* |g(s)| evaluated with every operand of its subtractions taken by magnitude
+ * (k (r + s)/s for k (r - s)/s): the size of the quantities a floating-point
+ * evaluation of g combines. */
+static double radial_g_mag(int op, const double* prm, double r, double s, double ai, double aj) {
+    switch (op) {
+        case OR_OP_SPRING: return fabs(prm[0]) * (r + s) / s;
+        case OR_OP_EXP_FORCE: return fabs(prm[0]) * exp(-s) / s;
+        case OR_OP_DEM_SPRING: return fabs(prm[0]) * (fabs(ai) + fabs(aj) + s) / s;
+        default: return 0.0;
+    }
+}
+
+/* Forward summand of one ordered pair, u = x_i - (x_j + shift), in float64;
+ * mag[k] is the same formula evaluated on magnitudes. */
 static void fwd_term(const or_grid* g, int op, const double* prm, const double* u, double ai, double aj,
-                     double* t) {
+                     double* t, double* mag) {
     double s2 = 0.0;
     for (int k = 0; k < g->d; ++k) s2 += u[k] * u[k];
     double dist = sqrt(s2);
     switch (op) {
         case OR_OP_COUNT:
-            t[0] = 1.0;
+            t[0] = mag[0] = 1.0;
             break;
         case OR_OP_SOFT_SPHERE: {
             double v = 1.0 - dist / g->r;
+            double va = 1.0 + dist / g->r;
             t[0] = 0.5 * v * v;
+            mag[0] = 0.5 * va * va;
             break;
         }
         default: {
             double dg;
             double gv = radial_g(op, prm, g->r, dist, ai, aj, &dg);
-            for (int k = 0; k < g->d; ++k) t[k] = gv * u[k];
+            double gm = radial_g_mag(op, prm, g->r, dist, ai, aj);
+            for (int k = 0; k < g->d; ++k) {
+                t[k] = gv * u[k];
+                mag[k] = gm * fabs(u[k]);
+            }
             break;
         }
     }
@@ -493,17 +514,17 @@ static void sum_begin(void* vctx, int64_t r, int64_t i) {
 static void sum_pair(void* vctx, int64_t i, int64_t j, const double* s) {
     sum_ctx* c = (sum_ctx*)vctx;
     const or_grid* g = c->g;
-    double u[3], up[3], t[3] = {0, 0, 0}, tp[3] = {0, 0, 0};
+    double u[3], up[3], t[3] = {0, 0, 0}, tp[3] = {0, 0, 0}, mag[3] = {0, 0, 0}, magp[3];
     pair_u(g, c->x + i * g->d, c->x + j * g->d, s, u);
     double ai = c->a ? c->a[i] : 0.0, aj = c->a ? c->a[j] : 0.0;
-    fwd_term(g, c->op, c->prm, u, ai, aj, t);
+    fwd_term(g, c->op, c->prm, u, ai, aj, t, mag);
     for (int k = 0; k < c->ny; ++k) c->yrow[k] += t[k];
     if (c->srow) {
         for (int k = 0; k < 3; ++k) up[k] = u[k] * (1.0 + OR_SENS_EPS);
-        fwd_term(g, c->op, c->prm, up, ai, aj, tp);
+        fwd_term(g, c->op, c->prm, up, ai, aj, tp, magp);
         double mx = 0.0, sens = 0.0;
         for (int k = 0; k < c->ny; ++k) {
-            if (fabs(t[k]) > mx) mx = fabs(t[k]);
+            if (mag[k] > mx) mx = mag[k];
             double dk = fabs(tp[k] - t[k]) / OR_SENS_EPS;
             if (dk > sens) sens = dk;
         }
@@ -573,52 +594,60 @@ static void bwd_begin(void* vctx, int64_t r, int64_t i) {
 /* Adjoint contribution of the ordered pair (k, i), u = x_k - (x_i + shift);
  * mag[m] receives the summed magnitudes of the products that make up gx[m]. */
 static void bwd_term(const or_grid* g, int op, const double* prm, const double* u, double ak, double ai,
-                     const double* gyk, const double* gyi, double* gx, double* ga, double* mag) {
+                     const double* gyk, const double* gyi, double* gx, double* ga, double* mag,
+                     double* gamag) {
     int d = g->d;
     double s2 = 0.0;
     for (int m = 0; m < d; ++m) s2 += u[m] * u[m];
     double dist = sqrt(s2);
     for (int m = 0; m < 3; ++m) gx[m] = mag[m] = 0.0;
-    *ga = 0.0;
+    *ga = *gamag = 0.0;
     if (op == OR_OP_COUNT) return;
     if (op == OR_OP_SOFT_SPHERE) {
         double dphi = -(2.0 / g->r) * (1.0 - dist / g->r);
         double coef = 0.5 * (gyk[0] + gyi[0]) * dphi / dist;
+        double cmag = 0.5 * (fabs(gyk[0]) + fabs(gyi[0])) * (2.0 / g->r) * (1.0 + dist / g->r) / dist;
         for (int m = 0; m < d; ++m) {
             gx[m] = coef * u[m];
-            mag[m] = fabs(gx[m]);
+            mag[m] = cmag * fabs(u[m]);
         }
         return;
     }
     double dg;
     double gv = radial_g(op, prm, g->r, dist, ak, ai, &dg);
-    double w[3] = {0, 0, 0};
-    double uw = 0.0;
+    double gm = radial_g_mag(op, prm, g->r, dist, ak, ai);
+    double w[3] = {0, 0, 0}, wm[3] = {0, 0, 0};
+    double uw = 0.0, uwm = 0.0;
     for (int m = 0; m < d; ++m) {
         w[m] = gyk[m] - gyi[m];
+        wm[m] = fabs(gyk[m]) + fabs(gyi[m]);
         uw += u[m] * w[m];
+        uwm += fabs(u[m]) * wm[m];
     }
     for (int m = 0; m < d; ++m) {
         gx[m] = gv * w[m] + (dg / dist) * uw * u[m];
-        mag[m] = fabs(gv * w[m]) + fabs((dg / dist) * uw * u[m]);
+        mag[m] = gm * wm[m] + fabs(dg / dist) * uwm * fabs(u[m]);
     }
-    if (op == OR_OP_DEM_SPRING) *ga = prm[0] * uw / dist;
+    if (op == OR_OP_DEM_SPRING) {
+        *ga = prm[0] * uw / dist;
+        *gamag = fabs(prm[0]) * uwm / dist;
+    }
 }
 
 static void bwd_pair(void* vctx, int64_t k, int64_t i, const double* s) {
     bwd_ctx* c = (bwd_ctx*)vctx;
     const or_grid* g = c->g;
     int d = g->d;
-    double u[3], up[3], t[3], tp[3], mag[3], magp[3], ta, tap;
+    double u[3], up[3], t[3], tp[3], mag[3], magp[3], ta, tap, tam, tamp;
     pair_u(g, c->x + k * d, c->x + i * d, s, u);
     const double* gyk = c->gy + k * c->ny;
     const double* gyi = c->gy + i * c->ny;
     double ak = c->a ? c->a[k] : 0.0, ai = c->a ? c->a[i] : 0.0;
-    bwd_term(g, c->op, c->prm, u, ak, ai, gyk, gyi, t, &ta, mag);
+    bwd_term(g, c->op, c->prm, u, ak, ai, gyk, gyi, t, &ta, mag, &tam);
     for (int m = 0; m < d; ++m) c->gxrow[m] += t[m];
     if (c->garow) *c->garow += ta;
     for (int m = 0; m < 3; ++m) up[m] = u[m] * (1.0 + OR_SENS_EPS);
-    bwd_term(g, c->op, c->prm, up, ak, ai, gyk, gyi, tp, &tap, magp);
+    bwd_term(g, c->op, c->prm, up, ak, ai, gyk, gyi, tp, &tap, magp, &tamp);
     if (c->sxrow) {
         double mx = 0.0, sens = 0.0;
         for (int m = 0; m < d; ++m) {
@@ -628,7 +657,7 @@ static void bwd_pair(void* vctx, int64_t k, int64_t i, const double* s) {
         }
         *c->sxrow += mx + sens;
     }
-    if (c->sarow) *c->sarow += fabs(ta) + fabs(tap - ta) / OR_SENS_EPS;
+    if (c->sarow) *c->sarow += tam + fabs(tap - ta) / OR_SENS_EPS;
 }
 
 /* gx[row][d], ga[row] (DEM spring only, else may be NULL); scale_x / scale_a as
