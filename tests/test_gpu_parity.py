@@ -336,7 +336,7 @@ def test_invalid_arguments_rejected_on_host(ctx):
         (A.BoxSpec(2, [0, 0], [1, 1], [1, 1], 0.6), "UNSUPPORTED"),
         (A.BoxSpec(2, [0, 0], [1, 1], [0, 0], 0.1, [10, 10]), "INVALID_ARG"),
         (A.BoxSpec(2, [0, 1], [1, 1], [0, 0], 0.1), "INVALID_ARG"),
-        (A.BoxSpec(4, [0, 0], [1, 1], [0, 0], 0.1), "INVALID_ARG"),
+        (A.BoxSpec(4, [0] * 4, [1] * 4, [0] * 4, 0.1), "INVALID_ARG"),
     ]
     for box, status in cases:
         with pytest.raises(A.AboriaError) as e:
