@@ -396,12 +396,12 @@ void fill_params(const std::vector<GridPlan>& plans, const std::vector<aboria_bo
 }
 
 void free_cells_buffers(aboria_cells* c) {
-    void* ptrs[] = {c->params_dev, c->sys_part_dev, c->keys, c->perm, c->keys_alt, c->perm_alt,
-                    c->off, c->xs, c->work, c->work2, c->hist, c->block_sums};
+    void* ptrs[] = {c->params_dev, c->sys_part_dev, c->cell_base_dev, c->keys, c->perm, c->keys_alt,
+                    c->perm_alt, c->off, c->xs, c->work, c->work2, c->hist, c->block_sums};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     c->params_dev = nullptr;
-    c->sys_part_dev = c->keys = c->perm = c->keys_alt = c->perm_alt = c->off = nullptr;
+    c->sys_part_dev = c->cell_base_dev = c->keys = c->perm = c->keys_alt = c->perm_alt = c->off = nullptr;
     c->hist = c->block_sums = nullptr;
     c->xs = c->work = c->work2 = nullptr;
 }
@@ -532,6 +532,7 @@ extern "C" aboria_status aboria_build_cells(aboria_ctx* ctx, aboria_dtype dtype,
             struct Alloc { void** p; size_t bytes; } allocs[] = {
                 {&c->params_dev, params.size()},
                 {(void**)&c->sys_part_dev, sizeof(uint32_t) * ((size_t)nsys + 1)},
+                {(void**)&c->cell_base_dev, sizeof(uint32_t) * ((size_t)nsys + 1)},
                 {(void**)&c->keys, sizeof(uint32_t) * nn},
                 {(void**)&c->perm, sizeof(uint32_t) * nn},
                 {(void**)&c->keys_alt, sizeof(uint32_t) * nn},
@@ -566,6 +567,9 @@ extern "C" aboria_status aboria_build_cells(aboria_ctx* ctx, aboria_dtype dtype,
             if (ctx->capturing) return fail(ctx, ABORIA_ERR_UNSUPPORTED, "changing boxes inside a graph capture");
             hipError_t e = hipMemcpyAsync(c->params_dev, params.data(), params.size(), hipMemcpyHostToDevice,
                                           ctx->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(c->cell_base_dev, cell_base.data(), cell_base.size() * sizeof(uint32_t),
+                                   hipMemcpyHostToDevice, ctx->stream);
             if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
             if (e != hipSuccess) {
                 if (create) { free_cells_buffers(c); delete c; }

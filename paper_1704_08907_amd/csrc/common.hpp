@@ -103,6 +103,7 @@ struct aboria_cells {
     std::vector<unsigned char> params_host;  // SysParams<T>[nsys] as uploaded
     void* params_dev = nullptr;
     uint32_t* sys_part_dev = nullptr;   // [nsys + 1] first slot of each system
+    uint32_t* cell_base_dev = nullptr;  // [nsys + 1] first global cell id of each system
     uint32_t* keys = nullptr;           // [n] final sorted keys
     uint32_t* perm = nullptr;           // [n] final permutation
     uint32_t* keys_alt = nullptr;       // [n] radix ping-pong buffers

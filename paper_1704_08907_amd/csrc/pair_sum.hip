@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <type_traits>
 
 #include "common.hpp"
 
@@ -76,6 +77,79 @@ struct PairOp {
             const T g = fma_t(q.p0 * (ai + aj), rinv, -q.p0);
 #pragma unroll
             for (int k = 0; k < D; ++k) acc[k] = fma_t(-g, dx[k], acc[k]);
+        }
+    }
+
+    // Branchless forms: every lane evaluates the summand and keeps it only if
+    // ok (a select, never a multiply, so the inf/NaN a rejected or sentinel
+    // candidate produces cannot leak into the sums).
+    __device__ __forceinline__ static void fwd_masked(const OpArgs<T>& q, T r, const T* dx, T d2, T ai, T aj, bool ok,
+                                                      T* acc) {
+        if constexpr (OP == ABORIA_OP_COUNT) {
+            acc[0] += ok ? T(1) : T(0);
+        } else if constexpr (OP == ABORIA_OP_SOFT_SPHERE) {
+            const T s = d2 * rsqrt_t(d2);
+            const T v = fma_t(-s, T(1) / r, T(1));
+            const T term = T(0.5) * v * v;
+            acc[0] += ok ? term : T(0);
+        } else {
+            const T rinv = rsqrt_t(d2);
+            T g;
+            if constexpr (OP == ABORIA_OP_SPRING) {
+                g = fma_t(q.p0 * r, rinv, -q.p0);
+            } else if constexpr (OP == ABORIA_OP_EXP_FORCE) {
+                g = q.p0 * exp_neg_t(d2 * rinv) * rinv;
+            } else {
+                g = fma_t(q.p0 * (ai + aj), rinv, -q.p0);
+            }
+            g = ok ? g : T(0);
+#pragma unroll
+            for (int k = 0; k < D; ++k) acc[k] = fma_t(-g, dx[k], acc[k]);
+        }
+    }
+
+    __device__ __forceinline__ static void bwd_masked(const OpArgs<T>& q, T r, const T* dx, T d2, T ai, T aj,
+                                                      const T* gyi, const T* gyj, bool ok, T* gx, T* ga) {
+        if constexpr (OP == ABORIA_OP_COUNT) {
+            return;
+        } else if constexpr (OP == ABORIA_OP_SOFT_SPHERE) {
+            const T rinv = rsqrt_t(d2);
+            const T s = d2 * rinv;
+            const T inv_r = T(1) / r;
+            T coef = (gyi[0] + gyj[0]) * inv_r * fma_t(-s, inv_r, T(1)) * rinv;
+            coef = ok ? coef : T(0);
+#pragma unroll
+            for (int k = 0; k < D; ++k) gx[k] = fma_t(coef, dx[k], gx[k]);
+        } else {
+            const T rinv = rsqrt_t(d2);
+            const T rinv3 = rinv * rinv * rinv;
+            T w[D];
+            T dw = T(0);
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                w[k] = gyi[k] - gyj[k];
+                dw = fma_t(dx[k], w[k], dw);
+            }
+            T g, gps;
+            if constexpr (OP == ABORIA_OP_SPRING) {
+                g = fma_t(q.p0 * r, rinv, -q.p0);
+                gps = -q.p0 * r * rinv3;
+            } else if constexpr (OP == ABORIA_OP_EXP_FORCE) {
+                const T s = d2 * rinv;
+                const T ce = q.p0 * exp_neg_t(s);
+                g = ce * rinv;
+                gps = -ce * (s + T(1)) * rinv3;
+            } else {
+                const T A = ai + aj;
+                g = fma_t(q.p0 * A, rinv, -q.p0);
+                gps = -q.p0 * A * rinv3;
+                const T ta = -q.p0 * dw * rinv;
+                ga[0] += ok ? ta : T(0);
+            }
+            g = ok ? g : T(0);
+            const T h = ok ? gps * dw : T(0);
+#pragma unroll
+            for (int k = 0; k < D; ++k) gx[k] = fma_t(g, w[k], fma_t(h, dx[k], gx[k]));
         }
     }
 
@@ -336,6 +410,281 @@ __global__ __launch_bounds__(256) void k_gather_rows(const T* __restrict__ src, 
 }
 
 // ---------------------------------------------------------------------------
+// cell-group work mapping
+//
+// A group of 16 lanes owns one home cell.  The candidates of the cell (its
+// 3^d neighbour cells, as up to 3^(d-1) x-rows of at most three pieces each)
+// form one flattened list; lane l of the group takes entries l, l+16, l+32, ...
+// walking a cursor over the group's piece table in LDS.  Each candidate is
+// loaded once into registers and tested against every home particle of the
+// current pass (up to IMAX, held in registers in all 16 lanes), so one load
+// feeds IMAX pair tests.  Home slots beyond the cell's particles, and list
+// entries beyond its candidates, hold far-away sentinel points whose squared
+// distance overflows to +inf and is rejected by the predicate, so the
+// unrolled i-loop needs no per-lane guard; the loop bounds are wave-uniform
+// maxima over the wave's four groups.  At the end each home particle's sums
+// are reduced across the 16 lanes with a xor butterfly and written to its
+// original index.
+// ---------------------------------------------------------------------------
+
+constexpr int kGroup = 16;
+
+template <typename T>
+struct Far;
+template <>
+struct Far<float> {
+    __device__ static constexpr float home() { return 1e30f; }
+    __device__ static constexpr float cand() { return -1e30f; }
+};
+template <>
+struct Far<double> {
+    __device__ static constexpr double home() { return 1e300; }
+    __device__ static constexpr double cand() { return -1e300; }
+};
+
+__device__ __forceinline__ uint32_t wave_max_of_groups(uint32_t v) {
+    // v is uniform within each 16-lane group; lanes 0, 16, 32, 48 lead the groups
+    uint32_t a = __builtin_amdgcn_readlane(v, 0), b = __builtin_amdgcn_readlane(v, 16);
+    uint32_t c = __builtin_amdgcn_readlane(v, 32), d = __builtin_amdgcn_readlane(v, 48);
+    return max(max(a, b), max(c, d));
+}
+
+__device__ __forceinline__ int find_system_cell(const uint32_t* __restrict__ cell_base, int nsys, uint32_t c) {
+    int lo = 0, hi = nsys - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (cell_base[mid] <= c) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+    for (int m = 8; m >= 1; m >>= 1) v += __shfl_xor(v, m, kGroup);
+    return v;
+}
+
+// Shift of one dimension from its 2-bit code: 0 -> -L, 1 -> 0, 2 -> +L.
+template <typename T>
+__device__ __forceinline__ T shift_of(uint32_t code, int k, T L) {
+    const uint32_t m = (code >> (2 * k)) & 3u;
+    return m == 0u ? -L : (m == 2u ? L : T(0));
+}
+
+template <typename T, int D, int OP, bool BATCH, bool BWD, int IMAX, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_pair_cells(
+    const T* __restrict__ xs, const uint32_t* __restrict__ off, const uint32_t* __restrict__ perm, uint32_t n,
+    uint32_t nwork, const SysParams<T>* __restrict__ sp, const uint32_t* __restrict__ cell_base, int nsys,
+    const T* __restrict__ a_s, const T* __restrict__ gy_s, OpArgs<T> q, T* __restrict__ out,
+    T* __restrict__ out_a) {
+    constexpr int PITCH = Pitch<D>::value;
+    constexpr int NY = OpShape<OP, D>::NY;
+    constexpr bool HAS_A = OpShape<OP, D>::NA > 0;
+    constexpr int NROWS = D == 1 ? 1 : (D == 2 ? 3 : 9);
+    constexpr int NPIECE = 3 * NROWS;
+    constexpr int GPB = BLOCK / kGroup;
+    constexpr uint32_t kCenter = D == 1 ? 1u : (D == 2 ? 5u : 21u);  // every dimension unshifted
+    using Op = PairOp<T, D, OP>;
+
+    __shared__ uint32_t s_start[GPB][NPIECE];
+    __shared__ uint32_t s_cum[GPB][NPIECE + 1];
+    __shared__ uint32_t s_code[GPB][NPIECE];
+
+    const int g = threadIdx.x / kGroup;
+    const int l = threadIdx.x % kGroup;
+    const uint32_t gid = xcd_tile(blockIdx.x, gridDim.x) * GPB + g;
+    const bool has_cell = gid < nwork;
+    const uint32_t cell = has_cell ? gid : 0u;
+    const int b = (BATCH && has_cell) ? find_system_cell(cell_base, nsys, cell) : 0;
+    const SysParams<T> P = sp[b];
+    const uint32_t local = cell - P.cell_base;
+    int32_t c[3] = {0, 0, 0};
+    {
+        uint32_t rest = local;
+        c[0] = (int32_t)(rest % (uint32_t)P.n[0]);
+        rest /= (uint32_t)P.n[0];
+        if (D >= 2) { c[1] = (int32_t)(rest % (uint32_t)P.n[1]); rest /= (uint32_t)P.n[1]; }
+        if (D >= 3) c[2] = (int32_t)rest;
+    }
+    const uint32_t hbeg = has_cell ? off[cell] : 0u;
+    const uint32_t nhome = has_cell ? off[cell + 1] - hbeg : 0u;
+
+    // piece table: lane l < NROWS fills the three x-pieces of row l
+    if (l < NROWS) {
+        int32_t row = 0;
+        uint32_t ycode = 0;
+        bool skip = !has_cell;
+        if (D >= 2) {
+            int32_t v = c[1] + (l % 3) - 1, m = 1;
+            if (v < 0) { if (!P.periodic[1]) skip = true; v += P.n[1]; m = 0; }
+            else if (v >= P.n[1]) { if (!P.periodic[1]) skip = true; v -= P.n[1]; m = 2; }
+            row = v;
+            ycode |= (uint32_t)m << 2;
+        }
+        if (D >= 3) {
+            int32_t v = c[2] + (l / 3) - 1, m = 1;
+            if (v < 0) { if (!P.periodic[2]) skip = true; v += P.n[2]; m = 0; }
+            else if (v >= P.n[2]) { if (!P.periodic[2]) skip = true; v -= P.n[2]; m = 2; }
+            row += P.n[1] * v;
+            ycode |= (uint32_t)m << 4;
+        }
+        const int32_t nx = P.n[0];
+        const uint32_t rowbase = P.cell_base + (uint32_t)nx * (uint32_t)row;
+        int32_t lo_[3] = {0, 0, 0}, hi_[3] = {-1, -1, -1};
+        uint32_t xm[3] = {1, 1, 1};
+        if (!skip) {
+            if (nx >= 3) {
+                lo_[0] = c[0] > 0 ? c[0] - 1 : 0;
+                hi_[0] = c[0] < nx - 1 ? c[0] + 1 : nx - 1;
+                if (P.periodic[0] && c[0] == 0) { lo_[1] = hi_[1] = nx - 1; xm[1] = 0; }
+                if (P.periodic[0] && c[0] == nx - 1) { lo_[2] = hi_[2] = 0; xm[2] = 2; }
+            } else {
+                for (int o = -1; o <= 1; ++o) {
+                    int32_t v = c[0] + o;
+                    uint32_t m = 1;
+                    if (v < 0) { if (!P.periodic[0]) continue; v += nx; m = 0; }
+                    else if (v >= nx) { if (!P.periodic[0]) continue; v -= nx; m = 2; }
+                    lo_[o + 1] = hi_[o + 1] = v;
+                    xm[o + 1] = m;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int p = 3 * l + k;
+            uint32_t st = 0, len = 0;
+            if (hi_[k] >= lo_[k]) {
+                st = off[rowbase + lo_[k]];
+                len = min(off[rowbase + hi_[k] + 1], n) - st;
+            }
+            s_start[g][p] = st;
+            s_cum[g][p + 1] = len;
+            s_code[g][p] = ycode | xm[k];
+        }
+    }
+    __syncthreads();
+    if (l == 0) {
+        uint32_t acc = 0;
+        s_cum[g][0] = 0;
+        for (int p = 0; p < NPIECE; ++p) {
+            acc += s_cum[g][p + 1];
+            s_cum[g][p + 1] = acc;
+        }
+    }
+    __syncthreads();
+
+    const uint32_t M = s_cum[g][NPIECE];
+    bool shifted = false;
+    for (int p = 0; p < NPIECE; ++p) shifted |= (s_code[g][p] != kCenter) && (s_cum[g][p + 1] > s_cum[g][p]);
+    const bool wave_shift = __ballot(shifted) != 0ull;
+    const uint32_t Mw = wave_max_of_groups(M);
+    const uint32_t passes_w = wave_max_of_groups((nhome + IMAX - 1) / IMAX);
+    const T r = P.r;
+    const T r2 = P.r2;
+
+    for (uint32_t pass = 0; pass < passes_w; ++pass) {
+        const uint32_t first = pass * IMAX;
+        const uint32_t nq = nhome > first ? min(nhome - first, (uint32_t)IMAX) : 0u;
+        const uint32_t nq_w = wave_max_of_groups(nq);
+        T xi[IMAX][D];
+        T gyi[IMAX][NY];
+        T ai[IMAX];
+        T acc[IMAX][BWD ? D : NY];
+        T acc_a[IMAX];
+#pragma unroll
+        for (int qq = 0; qq < IMAX; ++qq) {
+            const bool live = (uint32_t)qq < nq;
+            const uint32_t s = hbeg + first + qq;
+            if (live) {
+                const VecN<T, PITCH> v = reinterpret_cast<const VecN<T, PITCH>*>(xs)[s];
+#pragma unroll
+                for (int k = 0; k < D; ++k) xi[qq][k] = v.v[k];
+            } else {
+#pragma unroll
+                for (int k = 0; k < D; ++k) xi[qq][k] = Far<T>::home();
+            }
+#pragma unroll
+            for (int k = 0; k < NY; ++k) gyi[qq][k] = (BWD && live) ? gy_s[(size_t)s * NY + k] : T(0);
+            ai[qq] = (HAS_A && live) ? a_s[s] : T(0);
+#pragma unroll
+            for (int k = 0; k < (BWD ? D : NY); ++k) acc[qq][k] = T(0);
+            acc_a[qq] = T(0);
+        }
+
+        auto body = [&](auto shift_tag) {
+            constexpr bool SHIFT = decltype(shift_tag)::value;
+            int p = 0;
+            for (uint32_t t0 = 0; t0 < Mw; t0 += kGroup) {
+                const uint32_t t = t0 + (uint32_t)l;
+                T xj[D], sh[D], aj = T(0), gyj[NY];
+#pragma unroll
+                for (int k = 0; k < NY; ++k) gyj[k] = T(0);
+                if (t < M) {
+                    while (t >= s_cum[g][p + 1]) ++p;
+                    const uint32_t slot = s_start[g][p] + (t - s_cum[g][p]);
+                    const VecN<T, PITCH> v = reinterpret_cast<const VecN<T, PITCH>*>(xs)[slot];
+#pragma unroll
+                    for (int k = 0; k < D; ++k) xj[k] = v.v[k];
+                    if (SHIFT) {
+                        const uint32_t code = s_code[g][p];
+#pragma unroll
+                        for (int k = 0; k < D; ++k) sh[k] = shift_of<T>(code, k, P.L[k]);
+                    }
+                    if (HAS_A) aj = a_s[slot];
+                    if (BWD) {
+#pragma unroll
+                        for (int k = 0; k < NY; ++k) gyj[k] = gy_s[(size_t)slot * NY + k];
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < D; ++k) { xj[k] = Far<T>::cand(); sh[k] = T(0); }
+                }
+#pragma unroll
+                for (int qq = 0; qq < IMAX; ++qq) {
+                    if ((uint32_t)qq < nq_w) {
+                        T dx[D];
+#pragma unroll
+                        for (int k = 0; k < D; ++k) {
+                            dx[k] = xj[k] - xi[qq][k];
+                            if (SHIFT) dx[k] = dx[k] + sh[k];
+                        }
+                        T d2 = dx[0] * dx[0];
+                        if constexpr (D >= 2) d2 = fma_t(dx[1], dx[1], d2);
+                        if constexpr (D >= 3) d2 = fma_t(dx[2], dx[2], d2);
+                        const bool ok = d2 > T(0) && d2 < r2;
+                        if constexpr (BWD) {
+                            Op::bwd_masked(q, r, dx, d2, ai[qq], aj, gyi[qq], gyj, ok, acc[qq], &acc_a[qq]);
+                        } else {
+                            Op::fwd_masked(q, r, dx, d2, ai[qq], aj, ok, acc[qq]);
+                        }
+                    }
+                }
+            }
+        };
+        if (wave_shift) body(std::true_type{});
+        else body(std::false_type{});
+
+        // reduce over the group and write the pass's home particles
+#pragma unroll
+        for (int qq = 0; qq < IMAX; ++qq) {
+            if ((uint32_t)qq < nq_w) {
+#pragma unroll
+                for (int k = 0; k < (BWD ? D : NY); ++k) acc[qq][k] = group_sum(acc[qq][k]);
+                if (BWD && HAS_A) acc_a[qq] = group_sum(acc_a[qq]);
+                if ((uint32_t)l == (uint32_t)qq && (uint32_t)qq < nq) {
+                    const uint32_t o = perm[hbeg + first + qq];
+                    constexpr int W = BWD ? D : NY;
+#pragma unroll
+                    for (int k = 0; k < W; ++k) out[(size_t)o * W + k] = acc[qq][k];
+                    if (BWD && HAS_A && out_a) out_a[o] = acc_a[qq];
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // host dispatch
 // ---------------------------------------------------------------------------
 
@@ -351,61 +700,98 @@ aboria_status gather(aboria_ctx* ctx, const aboria_cells* c, const void* src, in
     return ABORIA_OK;
 }
 
-template <typename T, int D, int OP>
-aboria_status launch_fwd(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, T* y, int block) {
+// Work-mapping variants of the neighbour sums.
+struct Variant {
+    int kind;   // 0 = cell group, 1 = lane per particle
+    int imax;   // home particles per pass (cell group)
+    int block;  // threads per workgroup
+    const char* name;
+};
+
+const Variant kVariants[] = {
+    {0, 8, 128, "cell group of 16 lanes, 8 home particles per pass, 128-thread workgroups"},
+    {0, 16, 128, "cell group of 16 lanes, 16 home particles per pass, 128-thread workgroups"},
+    {0, 8, 256, "cell group of 16 lanes, 8 home particles per pass, 256-thread workgroups"},
+    {1, 0, 256, "lane per particle, x-row runs, 256-thread workgroups"},
+    {1, 0, 128, "lane per particle, x-row runs, 128-thread workgroups"},
+};
+constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+template <typename T, int D, int OP, bool BATCH, bool BWD, int IMAX, int BLOCK>
+void launch_cells(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, const T* gy_s, T* out,
+                  T* out_a) {
+    constexpr int GPB = BLOCK / kGroup;
+    const uint32_t nwork = (uint32_t)c->ncells;
+    const dim3 grid((nwork + GPB - 1) / GPB);
+    hipLaunchKernelGGL((k_pair_cells<T, D, OP, BATCH, BWD, IMAX, BLOCK>), grid, dim3(BLOCK), 0, ctx->stream,
+                       (const T*)c->xs, c->off, c->perm, (uint32_t)c->n, nwork,
+                       reinterpret_cast<const SysParams<T>*>(c->params_dev), c->cell_base_dev, c->nsys, a_s, gy_s, q,
+                       out, out_a);
+}
+
+template <typename T, int D, int OP, bool BATCH, bool BWD>
+void launch_variant(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, const T* gy_s, T* out,
+                    T* out_a, int variant) {
+    const Variant& v = kVariants[(variant < 0 || variant >= kNumVariants) ? 0 : variant];
     const uint32_t n = (uint32_t)c->n;
-    if (n == 0) return ABORIA_OK;
-    const dim3 grid((n + block - 1) / block);
     const SysParams<T>* sp = reinterpret_cast<const SysParams<T>*>(c->params_dev);
-    if (c->nsys == 1)
-        hipLaunchKernelGGL((k_pair_fwd<T, D, OP, false>), grid, dim3(block), 0, ctx->stream, (const T*)c->xs, c->off,
-                           c->perm, n, sp, c->sys_part_dev, c->nsys, a_s, q, y);
+    if (v.kind == 0) {
+        if (v.imax == 16) launch_cells<T, D, OP, BATCH, BWD, 16, 128>(ctx, c, q, a_s, gy_s, out, out_a);
+        else if (v.block == 256) launch_cells<T, D, OP, BATCH, BWD, 8, 256>(ctx, c, q, a_s, gy_s, out, out_a);
+        else launch_cells<T, D, OP, BATCH, BWD, 8, 128>(ctx, c, q, a_s, gy_s, out, out_a);
+        return;
+    }
+    const dim3 grid((n + v.block - 1) / v.block);
+    if constexpr (BWD)
+        hipLaunchKernelGGL((k_pair_bwd<T, D, OP, BATCH>), grid, dim3(v.block), 0, ctx->stream, (const T*)c->xs,
+                           c->off, c->perm, n, sp, c->sys_part_dev, c->nsys, a_s, gy_s, q, out, out_a);
     else
-        hipLaunchKernelGGL((k_pair_fwd<T, D, OP, true>), grid, dim3(block), 0, ctx->stream, (const T*)c->xs, c->off,
-                           c->perm, n, sp, c->sys_part_dev, c->nsys, a_s, q, y);
+        hipLaunchKernelGGL((k_pair_fwd<T, D, OP, BATCH>), grid, dim3(v.block), 0, ctx->stream, (const T*)c->xs,
+                           c->off, c->perm, n, sp, c->sys_part_dev, c->nsys, a_s, q, out);
+}
+
+template <typename T, int D, int OP>
+aboria_status launch_fwd(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, T* y, int variant) {
+    if (c->n == 0) return ABORIA_OK;
+    if (c->nsys == 1) launch_variant<T, D, OP, false, false>(ctx, c, q, a_s, nullptr, y, nullptr, variant);
+    else launch_variant<T, D, OP, true, false>(ctx, c, q, a_s, nullptr, y, nullptr, variant);
     ABORIA_HIP(ctx, hipGetLastError());
     return ABORIA_OK;
 }
 
 template <typename T, int D, int OP>
 aboria_status launch_bwd(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, const T* gy_s,
-                         T* gx, T* ga, int block) {
-    const uint32_t n = (uint32_t)c->n;
-    if (n == 0) return ABORIA_OK;
-    const dim3 grid((n + block - 1) / block);
-    const SysParams<T>* sp = reinterpret_cast<const SysParams<T>*>(c->params_dev);
-    if (c->nsys == 1)
-        hipLaunchKernelGGL((k_pair_bwd<T, D, OP, false>), grid, dim3(block), 0, ctx->stream, (const T*)c->xs, c->off,
-                           c->perm, n, sp, c->sys_part_dev, c->nsys, a_s, gy_s, q, gx, ga);
-    else
-        hipLaunchKernelGGL((k_pair_bwd<T, D, OP, true>), grid, dim3(block), 0, ctx->stream, (const T*)c->xs, c->off,
-                           c->perm, n, sp, c->sys_part_dev, c->nsys, a_s, gy_s, q, gx, ga);
+                         T* gx, T* ga, int variant) {
+    if (c->n == 0) return ABORIA_OK;
+    if (c->nsys == 1) launch_variant<T, D, OP, false, true>(ctx, c, q, a_s, gy_s, gx, ga, variant);
+    else launch_variant<T, D, OP, true, true>(ctx, c, q, a_s, gy_s, gx, ga, variant);
     ABORIA_HIP(ctx, hipGetLastError());
     return ABORIA_OK;
 }
 
 template <typename T, int D>
 aboria_status fwd_op(aboria_ctx* ctx, const aboria_cells* c, int op, const OpArgs<T>& q, const T* a_s, T* y,
-                     int block) {
+                     int variant) {
     switch (op) {
-        case ABORIA_OP_COUNT: return launch_fwd<T, D, ABORIA_OP_COUNT>(ctx, c, q, a_s, y, block);
-        case ABORIA_OP_SPRING: return launch_fwd<T, D, ABORIA_OP_SPRING>(ctx, c, q, a_s, y, block);
-        case ABORIA_OP_SOFT_SPHERE: return launch_fwd<T, D, ABORIA_OP_SOFT_SPHERE>(ctx, c, q, a_s, y, block);
-        case ABORIA_OP_EXP_FORCE: return launch_fwd<T, D, ABORIA_OP_EXP_FORCE>(ctx, c, q, a_s, y, block);
-        default: return launch_fwd<T, D, ABORIA_OP_DEM_SPRING>(ctx, c, q, a_s, y, block);
+        case ABORIA_OP_COUNT: return launch_fwd<T, D, ABORIA_OP_COUNT>(ctx, c, q, a_s, y, variant);
+        case ABORIA_OP_SPRING: return launch_fwd<T, D, ABORIA_OP_SPRING>(ctx, c, q, a_s, y, variant);
+        case ABORIA_OP_SOFT_SPHERE: return launch_fwd<T, D, ABORIA_OP_SOFT_SPHERE>(ctx, c, q, a_s, y, variant);
+        case ABORIA_OP_EXP_FORCE: return launch_fwd<T, D, ABORIA_OP_EXP_FORCE>(ctx, c, q, a_s, y, variant);
+        default: return launch_fwd<T, D, ABORIA_OP_DEM_SPRING>(ctx, c, q, a_s, y, variant);
     }
 }
 
 template <typename T, int D>
 aboria_status bwd_op(aboria_ctx* ctx, const aboria_cells* c, int op, const OpArgs<T>& q, const T* a_s,
-                     const T* gy_s, T* gx, T* ga, int block) {
+                     const T* gy_s, T* gx, T* ga, int variant) {
     switch (op) {
-        case ABORIA_OP_COUNT: return launch_bwd<T, D, ABORIA_OP_COUNT>(ctx, c, q, a_s, gy_s, gx, ga, block);
-        case ABORIA_OP_SPRING: return launch_bwd<T, D, ABORIA_OP_SPRING>(ctx, c, q, a_s, gy_s, gx, ga, block);
+        case ABORIA_OP_COUNT: return launch_bwd<T, D, ABORIA_OP_COUNT>(ctx, c, q, a_s, gy_s, gx, ga, variant);
+        case ABORIA_OP_SPRING: return launch_bwd<T, D, ABORIA_OP_SPRING>(ctx, c, q, a_s, gy_s, gx, ga, variant);
         case ABORIA_OP_SOFT_SPHERE:
-            return launch_bwd<T, D, ABORIA_OP_SOFT_SPHERE>(ctx, c, q, a_s, gy_s, gx, ga, block);
-        case ABORIA_OP_EXP_FORCE: return launch_bwd<T, D, ABORIA_OP_EXP_FORCE>(ctx, c, q, a_s, gy_s, gx, ga, block);
-        default: return launch_bwd<T, D, ABORIA_OP_DEM_SPRING>(ctx, c, q, a_s, gy_s, gx, ga, block);
+            return launch_bwd<T, D, ABORIA_OP_SOFT_SPHERE>(ctx, c, q, a_s, gy_s, gx, ga, variant);
+        case ABORIA_OP_EXP_FORCE:
+            return launch_bwd<T, D, ABORIA_OP_EXP_FORCE>(ctx, c, q, a_s, gy_s, gx, ga, variant);
+        default: return launch_bwd<T, D, ABORIA_OP_DEM_SPRING>(ctx, c, q, a_s, gy_s, gx, ga, variant);
     }
 }
 
@@ -422,23 +808,11 @@ aboria_status validate(aboria_ctx* ctx, const aboria_cells* c, int op, const dou
     return ABORIA_OK;
 }
 
-int block_of_variant(int32_t v) {
-    static const int blocks[] = {256, 128, 64};
-    return blocks[v < 0 || v > 2 ? 0 : v];
-}
-
 }  // namespace
 
-int32_t variant_count() { return 3; }
+int32_t variant_count() { return kNumVariants; }
 
-const char* variant_name(int32_t v) {
-    switch (v) {
-        case 0: return "lane-per-particle, x-row runs, 256-thread workgroups";
-        case 1: return "lane-per-particle, x-row runs, 128-thread workgroups";
-        case 2: return "lane-per-particle, x-row runs, 64-thread workgroups";
-        default: return "";
-    }
-}
+const char* variant_name(int32_t v) { return (v >= 0 && v < kNumVariants) ? kVariants[v].name : ""; }
 
 aboria_status pair_sum_impl(aboria_ctx* ctx, const aboria_cells* c, int32_t op, const double* params,
                             int32_t nparams, const void* a, int32_t na, void* y, int32_t ny, int32_t variant) {
@@ -448,7 +822,6 @@ aboria_status pair_sum_impl(aboria_ctx* ctx, const aboria_cells* c, int32_t op, 
     const size_t tsz = c->dtype == ABORIA_F32 ? 4 : 8;
     if (overlaps(y, tsz * ny * c->n, a, tsz * na * c->n))
         return fail(ctx, ABORIA_ERR_INVALID_ARG, "y overlaps a");
-    const int block = block_of_variant(variant);
     if (c->dtype == ABORIA_F32) {
         OpArgs<float> q{nparams > 0 ? (float)params[0] : 0.f};
         const float* a_s = nullptr;
@@ -457,9 +830,9 @@ aboria_status pair_sum_impl(aboria_ctx* ctx, const aboria_cells* c, int32_t op, 
             a_s = (const float*)c->work;
         }
         switch (c->d) {
-            case 1: return fwd_op<float, 1>(ctx, c, op, q, a_s, (float*)y, block);
-            case 2: return fwd_op<float, 2>(ctx, c, op, q, a_s, (float*)y, block);
-            default: return fwd_op<float, 3>(ctx, c, op, q, a_s, (float*)y, block);
+            case 1: return fwd_op<float, 1>(ctx, c, op, q, a_s, (float*)y, variant);
+            case 2: return fwd_op<float, 2>(ctx, c, op, q, a_s, (float*)y, variant);
+            default: return fwd_op<float, 3>(ctx, c, op, q, a_s, (float*)y, variant);
         }
     } else {
         OpArgs<double> q{nparams > 0 ? params[0] : 0.0};
@@ -469,9 +842,9 @@ aboria_status pair_sum_impl(aboria_ctx* ctx, const aboria_cells* c, int32_t op, 
             a_s = (const double*)c->work;
         }
         switch (c->d) {
-            case 1: return fwd_op<double, 1>(ctx, c, op, q, a_s, (double*)y, block);
-            case 2: return fwd_op<double, 2>(ctx, c, op, q, a_s, (double*)y, block);
-            default: return fwd_op<double, 3>(ctx, c, op, q, a_s, (double*)y, block);
+            case 1: return fwd_op<double, 1>(ctx, c, op, q, a_s, (double*)y, variant);
+            case 2: return fwd_op<double, 2>(ctx, c, op, q, a_s, (double*)y, variant);
+            default: return fwd_op<double, 3>(ctx, c, op, q, a_s, (double*)y, variant);
         }
     }
 }
@@ -490,7 +863,6 @@ aboria_status pair_bwd_impl(aboria_ctx* ctx, const aboria_cells* c, int32_t op, 
         overlaps(ga, tsz * na * nb, gy, tsz * ny * nb) || overlaps(ga, tsz * na * nb, a, tsz * na * nb) ||
         overlaps(ga, tsz * na * nb, gx, tsz * c->d * nb))
         return fail(ctx, ABORIA_ERR_INVALID_ARG, "outputs overlap inputs");
-    const int block = block_of_variant(variant);
     if (c->dtype == ABORIA_F32) {
         OpArgs<float> q{nparams > 0 ? (float)params[0] : 0.f};
         const float* a_s = nullptr;
@@ -501,9 +873,9 @@ aboria_status pair_bwd_impl(aboria_ctx* ctx, const aboria_cells* c, int32_t op, 
         if ((st = gather<float>(ctx, c, gy, ny, c->work2)) != ABORIA_OK) return st;
         const float* g_s = (const float*)c->work2;
         switch (c->d) {
-            case 1: return bwd_op<float, 1>(ctx, c, op, q, a_s, g_s, (float*)gx, (float*)ga, block);
-            case 2: return bwd_op<float, 2>(ctx, c, op, q, a_s, g_s, (float*)gx, (float*)ga, block);
-            default: return bwd_op<float, 3>(ctx, c, op, q, a_s, g_s, (float*)gx, (float*)ga, block);
+            case 1: return bwd_op<float, 1>(ctx, c, op, q, a_s, g_s, (float*)gx, (float*)ga, variant);
+            case 2: return bwd_op<float, 2>(ctx, c, op, q, a_s, g_s, (float*)gx, (float*)ga, variant);
+            default: return bwd_op<float, 3>(ctx, c, op, q, a_s, g_s, (float*)gx, (float*)ga, variant);
         }
     } else {
         OpArgs<double> q{nparams > 0 ? params[0] : 0.0};
@@ -515,9 +887,9 @@ aboria_status pair_bwd_impl(aboria_ctx* ctx, const aboria_cells* c, int32_t op, 
         if ((st = gather<double>(ctx, c, gy, ny, c->work2)) != ABORIA_OK) return st;
         const double* g_s = (const double*)c->work2;
         switch (c->d) {
-            case 1: return bwd_op<double, 1>(ctx, c, op, q, a_s, g_s, (double*)gx, (double*)ga, block);
-            case 2: return bwd_op<double, 2>(ctx, c, op, q, a_s, g_s, (double*)gx, (double*)ga, block);
-            default: return bwd_op<double, 3>(ctx, c, op, q, a_s, g_s, (double*)gx, (double*)ga, block);
+            case 1: return bwd_op<double, 1>(ctx, c, op, q, a_s, g_s, (double*)gx, (double*)ga, variant);
+            case 2: return bwd_op<double, 2>(ctx, c, op, q, a_s, g_s, (double*)gx, (double*)ga, variant);
+            default: return bwd_op<double, 3>(ctx, c, op, q, a_s, g_s, (double*)gx, (double*)ga, variant);
         }
     }
 }

@@ -375,21 +375,37 @@ def test_rebuild_in_place_matches_fresh_build(ctx):
         np.testing.assert_array_equal(a, b)
 
 
-def test_deterministic_and_variants_agree(ctx):
+@pytest.mark.parametrize("op,params", [("spring", (1.0,)), ("soft_sphere", ()), ("dem_spring", (1.5,))])
+def test_every_variant_matches_oracle_and_is_deterministic(ctx, op, params):
     w = syn.spring_cube(60000)
     s = w.systems[0]
+    g = oracle.grid_of(s)
+    rng = syn.SplitMix64(321)
+    a = (0.2 + 0.3 * rng.uniform(s.n)).astype(np.float32).reshape(-1, 1) if op == "dem_spring" else None
+    ny = A.op_ny(op, 3)
+    gy = rng.normal(s.n * ny).astype(np.float32).reshape(s.n, ny)
     cells = A.build_cells(ctx, to_dev(s.x), [box_of(s)])
-    ref = A.pair_sum(ctx, cells, "spring", (1.0,)).clone()
-    again = A.pair_sum(ctx, cells, "spring", (1.0,))
-    assert torch.equal(ref, again)
+    a_d = to_dev(a) if a is not None else None
+    gy_d = to_dev(gy)
+    yo, so = oracle.pair_sum(g, op, params, s.x, a=a)
+    gxo, gao, sxo, sao = oracle.pair_sum_backward(g, op, params, s.x, gy, a=a)
     for v in range(A.variant_count()):
         ctx.set_variant(v)
-        yv = A.pair_sum(ctx, cells, "spring", (1.0,))
-        assert torch.equal(yv, ref), A.variant_name(v)
+        y1 = A.pair_sum(ctx, cells, op, params, a_d)
+        y2 = A.pair_sum(ctx, cells, op, params, a_d)
+        gx1, ga1 = A.pair_sum_backward(ctx, cells, op, params, gy_d, a_d)
+        gx2, ga2 = A.pair_sum_backward(ctx, cells, op, params, gy_d, a_d)
+        name = A.variant_name(v)
+        assert torch.equal(y1, y2) and torch.equal(gx1, gx2), name
+        check_close(y1.cpu().numpy(), yo, so, TOL_F32, "forward %s [%s]" % (op, name))
+        check_close(gx1.cpu().numpy(), gxo, sxo, TOL_F32, "adjoint %s [%s]" % (op, name))
+        if ga1 is not None:
+            assert torch.equal(ga1, ga2)
+            check_close(ga1.cpu().numpy(), gao.reshape(-1, 1), sao, TOL_F32, "adjoint a [%s]" % name)
     ctx.set_variant(-1)
-    choice = A.autotune(ctx, cells, "spring", (1.0,))
+    choice = A.autotune(ctx, cells, op, params, a_d)
     assert 0 <= choice < A.variant_count()
-    assert torch.equal(A.pair_sum(ctx, cells, "spring", (1.0,)), ref)
+    ctx.sync()
 
 
 def test_graph_replay_matches_eager():
