@@ -118,6 +118,12 @@ def main():
     cand = candidate_count(cells)
     log("spring cube: n=%d pairs=%d candidates=%d (%.1f/particle)" % (n, pairs, cand, cand / n))
 
+    # autotuner: pick the fastest work mapping for each direction on this cell list
+    variant_fwd = A.autotune(ctx, cells, "spring", (1.0,))
+    variant_bwd = A.autotune(ctx, cells, "spring", (1.0,), gy=gy)
+    log("autotuned variants: forward %d (%s), adjoint %d (%s)" % (
+        variant_fwd, A.variant_name(variant_fwd), variant_bwd, A.variant_name(variant_bwd)))
+
     def step():
         A.build_cells(ctx, x, [box], cells=cells)
         A.pair_sum(ctx, cells, "spring", (1.0,), y=y)
@@ -164,7 +170,15 @@ def main():
     t_build = timed(lambda: A.build_cells(ctx, x, [box], cells=cells))
     t_fwd = timed(lambda: A.pair_sum(ctx, cells, "spring", (1.0,), y=y))
     t_bwd = timed(lambda: A.pair_sum_backward(ctx, cells, "spring", (1.0,), gy, gx=gx))
+    per_variant = {}
+    for v in range(A.variant_count()):
+        ctx.set_variant(v)
+        per_variant[A.variant_name(v)] = {
+            "fwd_ms": timed(lambda: A.pair_sum(ctx, cells, "spring", (1.0,), y=y), reps=5),
+            "bwd_ms": timed(lambda: A.pair_sum_backward(ctx, cells, "spring", (1.0,), gy, gx=gx), reps=5)}
+    ctx.set_variant(-1)
     ctx.sync()
+    log("variants", json.dumps(per_variant))
     ops_fwd = cand * OPS_PER_CANDIDATE + pairs * OPS_PER_PAIR["fwd"]
     ops_bwd = cand * OPS_PER_CANDIDATE + pairs * OPS_PER_PAIR["bwd"]
     # the adjoint call also gathers gy into cell order (a small copy kernel)
@@ -183,7 +197,9 @@ def main():
                  "fwd_only_pairs_per_s": pairs / (t_fwd * 1e-3),
                  "fwd_valu_frac": ops_fwd / (t_fwd * 1e-3) / 1e12 / VALU_PEAK_TOPS,
                  "bwd_valu_frac": ops_bwd / (t_bwd * 1e-3) / 1e12 / VALU_PEAK_TOPS,
-                 "candidates_per_step": cand}
+                 "candidates_per_step": cand,
+                 "variant_fwd": A.variant_name(variant_fwd), "variant_bwd": A.variant_name(variant_bwd),
+                 "per_variant": per_variant}
     log("breakdown", json.dumps(breakdown))
 
     # ---------------- other workloads ----------------
@@ -230,6 +246,7 @@ def main():
         gx5 = torch.empty((x5.shape[0], 3), device=dev)
         p5 = int(A.pair_sum(ctx, c5, "count", ()).sum().item())
         A.autotune(ctx, c5, "spring", (1.0,))
+        A.autotune(ctx, c5, "soft_sphere", (), gy=g5)
 
         def step5():
             A.build_cells(ctx, x5, boxes5, off5, cells=c5)

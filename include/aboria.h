@@ -134,8 +134,8 @@ aboria_status aboria_sync(aboria_ctx* ctx);
  *
  * Builds the cell list of nsys independent systems whose particles are
  * concatenated in x: system b owns rows [offsets_host[b], offsets_host[b+1]) of
- * x[n][d] (n = offsets_host[nsys]; offsets_host = NULL with nsys = 1 means all
- * rows; total rows < 2^31).  boxes_host[b] is system b's box; all boxes share
+ * x[n][d] (n = offsets_host[nsys]; offsets_host is required, {0, n} for a single
+ * system; total rows < 2^31).  boxes_host[b] is system b's box; all boxes share
  * d.  The steps: a cell id per particle, a stable LSD radix sort of
  * (cell id, index) pairs in LDS-ranked passes, a gather of the positions into
  * cell order, and the cell offsets (first slot of every cell).  Within a cell
@@ -220,16 +220,18 @@ aboria_status aboria_graph_launch(aboria_ctx* ctx, const aboria_graph* graph);
 aboria_status aboria_graph_destroy(aboria_graph* graph);
 
 /* ---- autotuning ---------------------------------------------------------------
- * Times the neighbour-sum kernel variants (launch shape and work mapping) for
- * this cell list and operator with HIP events on the context's stream, keeps the
- * fastest in the context's cache (keyed by d, dtype, op, size and density
- * buckets) and makes later sums on matching cell lists use it.  y_scratch is a
- * device buffer of n * ny elements the trials may overwrite.  *choice_host
- * receives the chosen variant's index (may be NULL).  Synchronises the stream;
- * not capturable.  Errors as for aboria_pair_sum. */
+ * Times the neighbour-sum kernel variants (work mapping and launch shape) for
+ * this cell list and operator with HIP events on the context's stream, keeps
+ * the fastest in the context's cache (keyed by d, dtype, operator, direction,
+ * size and density buckets) and makes later sums on matching cell lists use
+ * it.  gy == NULL tunes the forward sum, which writes out_scratch[n][ny];
+ * otherwise it tunes the adjoint for that upstream gradient gy[n][ny], which
+ * writes out_scratch[n][d] (ga is not computed).  a as for aboria_pair_sum.
+ * *choice_host receives the chosen variant (may be NULL).  Synchronises the
+ * stream; not capturable.  Errors as for aboria_pair_sum. */
 aboria_status aboria_autotune(aboria_ctx* ctx, const aboria_cells* cells, aboria_op op,
                               const double* params_host, int32_t nparams, const void* a, int32_t na,
-                              void* y_scratch, int32_t ny, int32_t* choice_host);
+                              const void* gy, int32_t ny, void* out_scratch, int32_t* choice_host);
 
 /* Number of neighbour-sum variants, and a static description of one. */
 int32_t aboria_variant_count(void);

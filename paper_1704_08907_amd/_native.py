@@ -80,7 +80,7 @@ def lib():
             "aboria_graph_capture_end": ([P, C.POINTER(P)], I32),
             "aboria_graph_launch": ([P, P], I32),
             "aboria_graph_destroy": ([P], I32),
-            "aboria_autotune": ([P, P, I32, C.POINTER(C.c_double), I32, P, I32, P, I32, C.POINTER(I32)], I32),
+            "aboria_autotune": ([P, P, I32, C.POINTER(C.c_double), I32, P, I32, P, I32, P, C.POINTER(I32)], I32),
             "aboria_variant_count": ([], I32),
             "aboria_variant_name": ([I32], C.c_char_p),
             "aboria_set_variant": ([P, I32], I32),
@@ -144,6 +144,7 @@ class Context:
         self.stream = stream
 
     def set_variant(self, v: int):
+        """Force a neighbour-sum variant for later calls (-1 = tuned / default)."""
         self.check(lib().aboria_set_variant(self.handle, v), "set_variant")
 
     def close(self):
@@ -338,12 +339,17 @@ def graph_launch(ctx: Context, g: Graph):
     ctx.check(lib().aboria_graph_launch(ctx.handle, g.handle), "graph_launch")
 
 
-def autotune(ctx: Context, cells: Cells, op: str, params=(), a: Optional[torch.Tensor] = None) -> int:
+def autotune(ctx: Context, cells: Cells, op: str, params=(), a: Optional[torch.Tensor] = None,
+             gy: Optional[torch.Tensor] = None) -> int:
+    """aboria_autotune: tunes the forward sum (gy None) or the adjoint for gy; returns the variant."""
     ny, na = op_ny(op, cells.d), op_na(op)
-    y = torch.empty((cells.n, ny), dtype=cells.dtype, device="cuda:%d" % ctx.device)
+    width = ny if gy is None else cells.d
+    out = torch.empty((cells.n, width), dtype=cells.dtype, device="cuda:%d" % ctx.device)
+    if gy is not None:
+        _check_dev(gy, "gy", cells.dtype)
     arr, npar = _params(params)
     choice = C.c_int32(-1)
-    st = lib().aboria_autotune(ctx.handle, cells.handle, OPS[op], arr, npar, _ptr(a), na, _ptr(y), ny,
+    st = lib().aboria_autotune(ctx.handle, cells.handle, OPS[op], arr, npar, _ptr(a), na, _ptr(gy), ny, _ptr(out),
                                C.byref(choice))
     ctx.check(st, "autotune")
     return int(choice.value)

@@ -11,7 +11,7 @@
 
 namespace aboria {
 
-uint64_t tune_key(const aboria_cells* c, int32_t op) {
+uint64_t tune_key(const aboria_cells* c, int32_t op, bool backward) {
     const int64_t n = std::max<int64_t>(c->n, 1);
     const int size_bucket = (int)std::floor(std::log2((double)n));
     const double per_cell = (double)c->n / (double)std::max<int64_t>(c->ncells, 1);
@@ -22,12 +22,13 @@ uint64_t tune_key(const aboria_cells* c, int32_t op) {
     k = k * 64 + (uint64_t)size_bucket;
     k = k * 64 + (uint64_t)std::min(dens_bucket, 63);
     k = k * 2 + (uint64_t)(c->nsys > 1);
+    k = k * 2 + (uint64_t)backward;
     return k;
 }
 
-int32_t pick_variant(aboria_ctx* ctx, const aboria_cells* c, int32_t op) {
+int32_t pick_variant(aboria_ctx* ctx, const aboria_cells* c, int32_t op, bool backward) {
     if (ctx->variant_forced >= 0) return ctx->variant_forced;
-    const uint64_t key = tune_key(c, op);
+    const uint64_t key = tune_key(c, op, backward);
     for (const auto& kv : ctx->tune_cache)
         if (kv.first == key) return kv.second;
     return 0;
@@ -50,7 +51,7 @@ extern "C" aboria_status aboria_set_variant(aboria_ctx* ctx, int32_t v) {
 
 extern "C" aboria_status aboria_autotune(aboria_ctx* ctx, const aboria_cells* cells, aboria_op op,
                                          const double* params_host, int32_t nparams, const void* a, int32_t na,
-                                         void* y_scratch, int32_t ny, int32_t* choice_host) {
+                                         const void* gy, int32_t ny, void* out_scratch, int32_t* choice_host) {
     if (!ctx) return ABORIA_ERR_INVALID_ARG;
     if (!cells) return fail(ctx, ABORIA_ERR_INVALID_ARG, "cells is NULL");
     if (ctx->capturing) return fail(ctx, ABORIA_ERR_UNSUPPORTED, "autotune cannot be captured");
@@ -66,13 +67,19 @@ extern "C" aboria_status aboria_autotune(aboria_ctx* ctx, const aboria_cells* ce
         int32_t best = 0;
         float best_ms = INFINITY;
         aboria_status st = ABORIA_OK;
+        const bool backward = gy != nullptr;
+        auto run = [&](int32_t v) {
+            return backward ? pair_bwd_impl(ctx, cells, op, params_host, nparams, a, na, gy, ny, out_scratch,
+                                            nullptr, v)
+                            : pair_sum_impl(ctx, cells, op, params_host, nparams, a, na, out_scratch, ny, v);
+        };
         for (int32_t v = 0; v < variant_count() && st == ABORIA_OK; ++v) {
-            st = pair_sum_impl(ctx, cells, op, params_host, nparams, a, na, y_scratch, ny, v);  // warm-up
+            st = run(v);  // warm-up
             if (st != ABORIA_OK) break;
             std::vector<float> times;
             for (int r = 0; r < reps && st == ABORIA_OK; ++r) {
                 if (hipEventRecord(e0, ctx->stream) != hipSuccess) { st = ABORIA_ERR_DEVICE; break; }
-                st = pair_sum_impl(ctx, cells, op, params_host, nparams, a, na, y_scratch, ny, v);
+                st = run(v);
                 if (st != ABORIA_OK) break;
                 if (hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
                     st = ABORIA_ERR_DEVICE;
@@ -96,7 +103,7 @@ extern "C" aboria_status aboria_autotune(aboria_ctx* ctx, const aboria_cells* ce
             if (ctx->last_error.empty()) ctx->last_error = "autotune: a trial failed";
             return st;
         }
-        const uint64_t key = tune_key(cells, op);
+        const uint64_t key = tune_key(cells, op, backward);
         bool found = false;
         for (auto& kv : ctx->tune_cache)
             if (kv.first == key) { kv.second = best; found = true; }

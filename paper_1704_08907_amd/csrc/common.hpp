@@ -155,10 +155,13 @@ int32_t op_nparams(int32_t op);
 // Neighbour-sum variants (work mappings) selectable by the autotuner.
 int32_t variant_count();
 const char* variant_name(int32_t v);
-int32_t pick_variant(aboria_ctx* ctx, const aboria_cells* cells, int32_t op);
-uint64_t tune_key(const aboria_cells* cells, int32_t op);
+int32_t pick_variant(aboria_ctx* ctx, const aboria_cells* cells, int32_t op, bool backward);
+uint64_t tune_key(const aboria_cells* cells, int32_t op, bool backward);
 
 aboria_status pair_sum_impl(aboria_ctx* ctx, const aboria_cells* cells, int32_t op, const double* params,
                             int32_t nparams, const void* a, int32_t na, void* y, int32_t ny, int32_t variant);
+aboria_status pair_bwd_impl(aboria_ctx* ctx, const aboria_cells* cells, int32_t op, const double* params,
+                            int32_t nparams, const void* a, int32_t na, const void* gy, int32_t ny, void* gx,
+                            void* ga, int32_t variant);
 
 }  // namespace aboria

@@ -472,7 +472,7 @@ __device__ __forceinline__ T shift_of(uint32_t code, int k, T L) {
     return m == 0u ? -L : (m == 2u ? L : T(0));
 }
 
-template <typename T, int D, int OP, bool BATCH, bool BWD, int IMAX, int BLOCK>
+template <typename T, int D, int OP, bool BATCH, bool BWD, int IMAX, int BLOCK, int ROUNDS>
 __global__ __launch_bounds__(BLOCK) void k_pair_cells(
     const T* __restrict__ xs, const uint32_t* __restrict__ off, const uint32_t* __restrict__ perm, uint32_t n,
     uint32_t nwork, const SysParams<T>* __restrict__ sp, const uint32_t* __restrict__ cell_base, int nsys,
@@ -484,203 +484,247 @@ __global__ __launch_bounds__(BLOCK) void k_pair_cells(
     constexpr int NROWS = D == 1 ? 1 : (D == 2 ? 3 : 9);
     constexpr int NPIECE = 3 * NROWS;
     constexpr int GPB = BLOCK / kGroup;
+    constexpr int TILE = GPB * ROUNDS;  // cells per workgroup
+    static_assert(TILE <= BLOCK, "one thread ranks one cell of the tile");
     constexpr uint32_t kCenter = D == 1 ? 1u : (D == 2 ? 5u : 21u);  // every dimension unshifted
     using Op = PairOp<T, D, OP>;
 
     __shared__ uint32_t s_start[GPB][NPIECE];
     __shared__ uint32_t s_cum[GPB][NPIECE + 1];
     __shared__ uint32_t s_code[GPB][NPIECE];
+    __shared__ uint32_t s_key[TILE];
+    __shared__ uint32_t s_order[TILE];
 
     const int g = threadIdx.x / kGroup;
     const int l = threadIdx.x % kGroup;
-    const uint32_t gid = xcd_tile(blockIdx.x, gridDim.x) * GPB + g;
-    const bool has_cell = gid < nwork;
-    const uint32_t cell = has_cell ? gid : 0u;
-    const int b = (BATCH && has_cell) ? find_system_cell(cell_base, nsys, cell) : 0;
-    const SysParams<T> P = sp[b];
-    const uint32_t local = cell - P.cell_base;
-    int32_t c[3] = {0, 0, 0};
-    {
-        uint32_t rest = local;
-        c[0] = (int32_t)(rest % (uint32_t)P.n[0]);
-        rest /= (uint32_t)P.n[0];
-        if (D >= 2) { c[1] = (int32_t)(rest % (uint32_t)P.n[1]); rest /= (uint32_t)P.n[1]; }
-        if (D >= 3) c[2] = (int32_t)rest;
-    }
-    const uint32_t hbeg = has_cell ? off[cell] : 0u;
-    const uint32_t nhome = has_cell ? off[cell + 1] - hbeg : 0u;
+    const uint32_t tile_base = xcd_tile(blockIdx.x, gridDim.x) * TILE;
 
-    // piece table: lane l < NROWS fills the three x-pieces of row l
-    if (l < NROWS) {
-        int32_t row = 0;
-        uint32_t ycode = 0;
-        bool skip = !has_cell;
-        if (D >= 2) {
-            int32_t v = c[1] + (l % 3) - 1, m = 1;
-            if (v < 0) { if (!P.periodic[1]) skip = true; v += P.n[1]; m = 0; }
-            else if (v >= P.n[1]) { if (!P.periodic[1]) skip = true; v -= P.n[1]; m = 2; }
-            row = v;
-            ycode |= (uint32_t)m << 2;
+    // Rank the tile's cells by (stencil wraps, occupancy) so that the four
+    // groups of a wave get cells of equal occupancy and equal wrap status.
+    if (ROUNDS > 1) {
+        if (threadIdx.x < TILE) {
+            const uint32_t cell = tile_base + threadIdx.x;
+            uint32_t key = 0xFFFFFFFFu;
+            if (cell < nwork) {
+                const int bb = BATCH ? find_system_cell(cell_base, nsys, cell) : 0;
+                const SysParams<T>& Pb = sp[bb];
+                uint32_t rest = cell - Pb.cell_base;
+                bool wraps = false;
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    const uint32_t ck = rest % (uint32_t)Pb.n[k];
+                    rest /= (uint32_t)Pb.n[k];
+                    wraps |= Pb.periodic[k] && (ck == 0u || ck + 1u >= (uint32_t)Pb.n[k]);
+                }
+                key = ((uint32_t)wraps << 16) | min(off[cell + 1] - off[cell], 0xFFFFu);
+            }
+            s_key[threadIdx.x] = key;
         }
-        if (D >= 3) {
-            int32_t v = c[2] + (l / 3) - 1, m = 1;
-            if (v < 0) { if (!P.periodic[2]) skip = true; v += P.n[2]; m = 0; }
-            else if (v >= P.n[2]) { if (!P.periodic[2]) skip = true; v -= P.n[2]; m = 2; }
-            row += P.n[1] * v;
-            ycode |= (uint32_t)m << 4;
+        __syncthreads();
+        if (threadIdx.x < TILE) {
+            const uint32_t me = s_key[threadIdx.x];
+            uint32_t rank = 0;
+            for (int u = 0; u < TILE; ++u) {
+                const uint32_t ku = s_key[u];
+                rank += (ku < me || (ku == me && u < (int)threadIdx.x)) ? 1u : 0u;
+            }
+            s_order[rank] = threadIdx.x;
         }
-        const int32_t nx = P.n[0];
-        const uint32_t rowbase = P.cell_base + (uint32_t)nx * (uint32_t)row;
-        int32_t lo_[3] = {0, 0, 0}, hi_[3] = {-1, -1, -1};
-        uint32_t xm[3] = {1, 1, 1};
-        if (!skip) {
-            if (nx >= 3) {
-                lo_[0] = c[0] > 0 ? c[0] - 1 : 0;
-                hi_[0] = c[0] < nx - 1 ? c[0] + 1 : nx - 1;
-                if (P.periodic[0] && c[0] == 0) { lo_[1] = hi_[1] = nx - 1; xm[1] = 0; }
-                if (P.periodic[0] && c[0] == nx - 1) { lo_[2] = hi_[2] = 0; xm[2] = 2; }
-            } else {
-                for (int o = -1; o <= 1; ++o) {
-                    int32_t v = c[0] + o;
-                    uint32_t m = 1;
-                    if (v < 0) { if (!P.periodic[0]) continue; v += nx; m = 0; }
-                    else if (v >= nx) { if (!P.periodic[0]) continue; v -= nx; m = 2; }
-                    lo_[o + 1] = hi_[o + 1] = v;
-                    xm[o + 1] = m;
+        __syncthreads();
+    }
+
+    for (int round = 0; round < ROUNDS; ++round) {
+        const uint32_t slot_in_tile = (uint32_t)(round * GPB + g);
+        const uint32_t gid = tile_base + (ROUNDS > 1 ? s_order[slot_in_tile] : slot_in_tile);
+        const bool has_cell = gid < nwork;
+        const uint32_t cell = has_cell ? gid : 0u;
+        const int b = (BATCH && has_cell) ? find_system_cell(cell_base, nsys, cell) : 0;
+        const SysParams<T> P = sp[b];
+        const uint32_t local = cell - P.cell_base;
+        int32_t c[3] = {0, 0, 0};
+        {
+            uint32_t rest = local;
+            c[0] = (int32_t)(rest % (uint32_t)P.n[0]);
+            rest /= (uint32_t)P.n[0];
+            if (D >= 2) { c[1] = (int32_t)(rest % (uint32_t)P.n[1]); rest /= (uint32_t)P.n[1]; }
+            if (D >= 3) c[2] = (int32_t)rest;
+        }
+        const uint32_t hbeg = has_cell ? off[cell] : 0u;
+        const uint32_t nhome = has_cell ? off[cell + 1] - hbeg : 0u;
+
+        // piece table: lane l < NROWS fills the three x-pieces of row l
+        if (l < NROWS) {
+            int32_t row = 0;
+            uint32_t ycode = 0;
+            bool skip = !has_cell;
+            if (D >= 2) {
+                int32_t v = c[1] + (l % 3) - 1, m = 1;
+                if (v < 0) { if (!P.periodic[1]) skip = true; v += P.n[1]; m = 0; }
+                else if (v >= P.n[1]) { if (!P.periodic[1]) skip = true; v -= P.n[1]; m = 2; }
+                row = v;
+                ycode |= (uint32_t)m << 2;
+            }
+            if (D >= 3) {
+                int32_t v = c[2] + (l / 3) - 1, m = 1;
+                if (v < 0) { if (!P.periodic[2]) skip = true; v += P.n[2]; m = 0; }
+                else if (v >= P.n[2]) { if (!P.periodic[2]) skip = true; v -= P.n[2]; m = 2; }
+                row += P.n[1] * v;
+                ycode |= (uint32_t)m << 4;
+            }
+            const int32_t nx = P.n[0];
+            const uint32_t rowbase = P.cell_base + (uint32_t)nx * (uint32_t)row;
+            int32_t lo_[3] = {0, 0, 0}, hi_[3] = {-1, -1, -1};
+            uint32_t xm[3] = {1, 1, 1};
+            if (!skip) {
+                if (nx >= 3) {
+                    lo_[0] = c[0] > 0 ? c[0] - 1 : 0;
+                    hi_[0] = c[0] < nx - 1 ? c[0] + 1 : nx - 1;
+                    if (P.periodic[0] && c[0] == 0) { lo_[1] = hi_[1] = nx - 1; xm[1] = 0; }
+                    if (P.periodic[0] && c[0] == nx - 1) { lo_[2] = hi_[2] = 0; xm[2] = 2; }
+                } else {
+                    for (int o = -1; o <= 1; ++o) {
+                        int32_t v = c[0] + o;
+                        uint32_t m = 1;
+                        if (v < 0) { if (!P.periodic[0]) continue; v += nx; m = 0; }
+                        else if (v >= nx) { if (!P.periodic[0]) continue; v -= nx; m = 2; }
+                        lo_[o + 1] = hi_[o + 1] = v;
+                        xm[o + 1] = m;
+                    }
                 }
             }
-        }
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const int p = 3 * l + k;
-            uint32_t st = 0, len = 0;
-            if (hi_[k] >= lo_[k]) {
-                st = off[rowbase + lo_[k]];
-                len = min(off[rowbase + hi_[k] + 1], n) - st;
+            for (int k = 0; k < 3; ++k) {
+                const int p = 3 * l + k;
+                uint32_t st = 0, len = 0;
+                if (hi_[k] >= lo_[k]) {
+                    st = off[rowbase + lo_[k]];
+                    len = min(off[rowbase + hi_[k] + 1], n) - st;
+                }
+                s_start[g][p] = st;
+                s_cum[g][p + 1] = len;
+                s_code[g][p] = ycode | xm[k];
             }
-            s_start[g][p] = st;
-            s_cum[g][p + 1] = len;
-            s_code[g][p] = ycode | xm[k];
         }
-    }
-    __syncthreads();
-    if (l == 0) {
-        uint32_t acc = 0;
-        s_cum[g][0] = 0;
-        for (int p = 0; p < NPIECE; ++p) {
-            acc += s_cum[g][p + 1];
-            s_cum[g][p + 1] = acc;
-        }
-    }
-    __syncthreads();
-
-    const uint32_t M = s_cum[g][NPIECE];
-    bool shifted = false;
-    for (int p = 0; p < NPIECE; ++p) shifted |= (s_code[g][p] != kCenter) && (s_cum[g][p + 1] > s_cum[g][p]);
-    const bool wave_shift = __ballot(shifted) != 0ull;
-    const uint32_t Mw = wave_max_of_groups(M);
-    const uint32_t passes_w = wave_max_of_groups((nhome + IMAX - 1) / IMAX);
-    const T r = P.r;
-    const T r2 = P.r2;
-
-    for (uint32_t pass = 0; pass < passes_w; ++pass) {
-        const uint32_t first = pass * IMAX;
-        const uint32_t nq = nhome > first ? min(nhome - first, (uint32_t)IMAX) : 0u;
-        const uint32_t nq_w = wave_max_of_groups(nq);
-        T xi[IMAX][D];
-        T gyi[IMAX][NY];
-        T ai[IMAX];
-        T acc[IMAX][BWD ? D : NY];
-        T acc_a[IMAX];
-#pragma unroll
-        for (int qq = 0; qq < IMAX; ++qq) {
-            const bool live = (uint32_t)qq < nq;
-            const uint32_t s = hbeg + first + qq;
-            if (live) {
-                const VecN<T, PITCH> v = reinterpret_cast<const VecN<T, PITCH>*>(xs)[s];
-#pragma unroll
-                for (int k = 0; k < D; ++k) xi[qq][k] = v.v[k];
-            } else {
-#pragma unroll
-                for (int k = 0; k < D; ++k) xi[qq][k] = Far<T>::home();
+        __syncthreads();
+        if (l == 0) {
+            uint32_t acc = 0;
+            s_cum[g][0] = 0;
+            for (int p = 0; p < NPIECE; ++p) {
+                acc += s_cum[g][p + 1];
+                s_cum[g][p + 1] = acc;
             }
-#pragma unroll
-            for (int k = 0; k < NY; ++k) gyi[qq][k] = (BWD && live) ? gy_s[(size_t)s * NY + k] : T(0);
-            ai[qq] = (HAS_A && live) ? a_s[s] : T(0);
-#pragma unroll
-            for (int k = 0; k < (BWD ? D : NY); ++k) acc[qq][k] = T(0);
-            acc_a[qq] = T(0);
         }
+        __syncthreads();
 
-        auto body = [&](auto shift_tag) {
-            constexpr bool SHIFT = decltype(shift_tag)::value;
-            int p = 0;
-            for (uint32_t t0 = 0; t0 < Mw; t0 += kGroup) {
-                const uint32_t t = t0 + (uint32_t)l;
-                T xj[D], sh[D], aj = T(0), gyj[NY];
+        const uint32_t M = s_cum[g][NPIECE];
+        bool shifted = false;
+        for (int p = 0; p < NPIECE; ++p) shifted |= (s_code[g][p] != kCenter) && (s_cum[g][p + 1] > s_cum[g][p]);
+        const bool wave_shift = __ballot(shifted) != 0ull;
+        const uint32_t Mw = wave_max_of_groups(M);
+        const uint32_t passes_w = wave_max_of_groups((nhome + IMAX - 1) / IMAX);
+        const T r = P.r;
+        const T r2 = P.r2;
+
+        for (uint32_t pass = 0; pass < passes_w; ++pass) {
+            const uint32_t first = pass * IMAX;
+            const uint32_t nq = nhome > first ? min(nhome - first, (uint32_t)IMAX) : 0u;
+            const uint32_t nq_w = wave_max_of_groups(nq);
+            T xi[IMAX][D];
+            T gyi[IMAX][NY];
+            T ai[IMAX];
+            T acc[IMAX][BWD ? D : NY];
+            T acc_a[IMAX];
 #pragma unroll
-                for (int k = 0; k < NY; ++k) gyj[k] = T(0);
-                if (t < M) {
-                    while (t >= s_cum[g][p + 1]) ++p;
-                    const uint32_t slot = s_start[g][p] + (t - s_cum[g][p]);
-                    const VecN<T, PITCH> v = reinterpret_cast<const VecN<T, PITCH>*>(xs)[slot];
+            for (int qq = 0; qq < IMAX; ++qq) {
+                const bool live = (uint32_t)qq < nq;
+                const uint32_t s = hbeg + first + qq;
+                if (live) {
+                    const VecN<T, PITCH> v = reinterpret_cast<const VecN<T, PITCH>*>(xs)[s];
 #pragma unroll
-                    for (int k = 0; k < D; ++k) xj[k] = v.v[k];
-                    if (SHIFT) {
-                        const uint32_t code = s_code[g][p];
-#pragma unroll
-                        for (int k = 0; k < D; ++k) sh[k] = shift_of<T>(code, k, P.L[k]);
-                    }
-                    if (HAS_A) aj = a_s[slot];
-                    if (BWD) {
-#pragma unroll
-                        for (int k = 0; k < NY; ++k) gyj[k] = gy_s[(size_t)slot * NY + k];
-                    }
+                    for (int k = 0; k < D; ++k) xi[qq][k] = v.v[k];
                 } else {
 #pragma unroll
-                    for (int k = 0; k < D; ++k) { xj[k] = Far<T>::cand(); sh[k] = T(0); }
+                    for (int k = 0; k < D; ++k) xi[qq][k] = Far<T>::home();
                 }
 #pragma unroll
-                for (int qq = 0; qq < IMAX; ++qq) {
-                    if ((uint32_t)qq < nq_w) {
-                        T dx[D];
+                for (int k = 0; k < NY; ++k) gyi[qq][k] = (BWD && live) ? gy_s[(size_t)s * NY + k] : T(0);
+                ai[qq] = (HAS_A && live) ? a_s[s] : T(0);
 #pragma unroll
-                        for (int k = 0; k < D; ++k) {
-                            dx[k] = xj[k] - xi[qq][k];
-                            if (SHIFT) dx[k] = dx[k] + sh[k];
+                for (int k = 0; k < (BWD ? D : NY); ++k) acc[qq][k] = T(0);
+                acc_a[qq] = T(0);
+            }
+
+            auto body = [&](auto shift_tag) {
+                constexpr bool SHIFT = decltype(shift_tag)::value;
+                int p = 0;
+                for (uint32_t t0 = 0; t0 < Mw; t0 += kGroup) {
+                    const uint32_t t = t0 + (uint32_t)l;
+                    T xj[D], sh[D], aj = T(0), gyj[NY];
+#pragma unroll
+                    for (int k = 0; k < NY; ++k) gyj[k] = T(0);
+                    if (t < M) {
+                        while (t >= s_cum[g][p + 1]) ++p;
+                        const uint32_t slot = s_start[g][p] + (t - s_cum[g][p]);
+                        const VecN<T, PITCH> v = reinterpret_cast<const VecN<T, PITCH>*>(xs)[slot];
+#pragma unroll
+                        for (int k = 0; k < D; ++k) xj[k] = v.v[k];
+                        if (SHIFT) {
+                            const uint32_t code = s_code[g][p];
+#pragma unroll
+                            for (int k = 0; k < D; ++k) sh[k] = shift_of<T>(code, k, P.L[k]);
                         }
-                        T d2 = dx[0] * dx[0];
-                        if constexpr (D >= 2) d2 = fma_t(dx[1], dx[1], d2);
-                        if constexpr (D >= 3) d2 = fma_t(dx[2], dx[2], d2);
-                        const bool ok = d2 > T(0) && d2 < r2;
-                        if constexpr (BWD) {
-                            Op::bwd_masked(q, r, dx, d2, ai[qq], aj, gyi[qq], gyj, ok, acc[qq], &acc_a[qq]);
-                        } else {
-                            Op::fwd_masked(q, r, dx, d2, ai[qq], aj, ok, acc[qq]);
+                        if (HAS_A) aj = a_s[slot];
+                        if (BWD) {
+#pragma unroll
+                            for (int k = 0; k < NY; ++k) gyj[k] = gy_s[(size_t)slot * NY + k];
+                        }
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < D; ++k) { xj[k] = Far<T>::cand(); sh[k] = T(0); }
+                    }
+#pragma unroll
+                    for (int qq = 0; qq < IMAX; ++qq) {
+                        if ((uint32_t)qq < nq_w) {
+                            T dx[D];
+#pragma unroll
+                            for (int k = 0; k < D; ++k) {
+                                dx[k] = xj[k] - xi[qq][k];
+                                if (SHIFT) dx[k] = dx[k] + sh[k];
+                            }
+                            T d2 = dx[0] * dx[0];
+                            if constexpr (D >= 2) d2 = fma_t(dx[1], dx[1], d2);
+                            if constexpr (D >= 3) d2 = fma_t(dx[2], dx[2], d2);
+                            const bool ok = d2 > T(0) && d2 < r2;
+                            if constexpr (BWD) {
+                                Op::bwd_masked(q, r, dx, d2, ai[qq], aj, gyi[qq], gyj, ok, acc[qq], &acc_a[qq]);
+                            } else {
+                                Op::fwd_masked(q, r, dx, d2, ai[qq], aj, ok, acc[qq]);
+                            }
                         }
                     }
                 }
-            }
-        };
-        if (wave_shift) body(std::true_type{});
-        else body(std::false_type{});
+            };
+            if (wave_shift) body(std::true_type{});
+            else body(std::false_type{});
 
-        // reduce over the group and write the pass's home particles
+            // reduce over the group and write the pass's home particles
 #pragma unroll
-        for (int qq = 0; qq < IMAX; ++qq) {
-            if ((uint32_t)qq < nq_w) {
+            for (int qq = 0; qq < IMAX; ++qq) {
+                if ((uint32_t)qq < nq_w) {
 #pragma unroll
-                for (int k = 0; k < (BWD ? D : NY); ++k) acc[qq][k] = group_sum(acc[qq][k]);
-                if (BWD && HAS_A) acc_a[qq] = group_sum(acc_a[qq]);
-                if ((uint32_t)l == (uint32_t)qq && (uint32_t)qq < nq) {
-                    const uint32_t o = perm[hbeg + first + qq];
-                    constexpr int W = BWD ? D : NY;
+                    for (int k = 0; k < (BWD ? D : NY); ++k) acc[qq][k] = group_sum(acc[qq][k]);
+                    if (BWD && HAS_A) acc_a[qq] = group_sum(acc_a[qq]);
+                    if ((uint32_t)l == (uint32_t)qq && (uint32_t)qq < nq) {
+                        const uint32_t o = perm[hbeg + first + qq];
+                        constexpr int W = BWD ? D : NY;
 #pragma unroll
-                    for (int k = 0; k < W; ++k) out[(size_t)o * W + k] = acc[qq][k];
-                    if (BWD && HAS_A && out_a) out_a[o] = acc_a[qq];
+                        for (int k = 0; k < W; ++k) out[(size_t)o * W + k] = acc[qq][k];
+                        if (BWD && HAS_A && out_a) out_a[o] = acc_a[qq];
+                    }
                 }
             }
         }
+        __syncthreads();  // the piece tables are rewritten by the next round
     }
 }
 
@@ -702,28 +746,29 @@ aboria_status gather(aboria_ctx* ctx, const aboria_cells* c, const void* src, in
 
 // Work-mapping variants of the neighbour sums.
 struct Variant {
-    int kind;   // 0 = cell group, 1 = lane per particle
-    int imax;   // home particles per pass (cell group)
-    int block;  // threads per workgroup
+    int kind;    // 0 = cell group, 1 = lane per particle
+    int imax;    // home particles per pass (cell group)
+    int block;   // threads per workgroup
+    int rounds;  // cell-group rounds per workgroup (tile = block/16 * rounds cells)
     const char* name;
 };
 
 const Variant kVariants[] = {
-    {0, 8, 128, "cell group of 16 lanes, 8 home particles per pass, 128-thread workgroups"},
-    {0, 16, 128, "cell group of 16 lanes, 16 home particles per pass, 128-thread workgroups"},
-    {0, 8, 256, "cell group of 16 lanes, 8 home particles per pass, 256-thread workgroups"},
-    {1, 0, 256, "lane per particle, x-row runs, 256-thread workgroups"},
-    {1, 0, 128, "lane per particle, x-row runs, 128-thread workgroups"},
+    {0, 8, 128, 8, "cell group of 16 lanes, 8 home particles per pass, 64-cell tiles ranked by occupancy"},
+    {0, 16, 128, 8, "cell group of 16 lanes, 16 home particles per pass, 64-cell tiles ranked by occupancy"},
+    {0, 8, 128, 1, "cell group of 16 lanes, 8 home particles per pass, cells in natural order"},
+    {1, 0, 256, 0, "lane per particle, x-row runs, 256-thread workgroups"},
+    {1, 0, 128, 0, "lane per particle, x-row runs, 128-thread workgroups"},
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
-template <typename T, int D, int OP, bool BATCH, bool BWD, int IMAX, int BLOCK>
+template <typename T, int D, int OP, bool BATCH, bool BWD, int IMAX, int BLOCK, int ROUNDS>
 void launch_cells(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, const T* gy_s, T* out,
                   T* out_a) {
-    constexpr int GPB = BLOCK / kGroup;
+    constexpr int TILE = BLOCK / kGroup * ROUNDS;
     const uint32_t nwork = (uint32_t)c->ncells;
-    const dim3 grid((nwork + GPB - 1) / GPB);
-    hipLaunchKernelGGL((k_pair_cells<T, D, OP, BATCH, BWD, IMAX, BLOCK>), grid, dim3(BLOCK), 0, ctx->stream,
+    const dim3 grid((nwork + TILE - 1) / TILE);
+    hipLaunchKernelGGL((k_pair_cells<T, D, OP, BATCH, BWD, IMAX, BLOCK, ROUNDS>), grid, dim3(BLOCK), 0, ctx->stream,
                        (const T*)c->xs, c->off, c->perm, (uint32_t)c->n, nwork,
                        reinterpret_cast<const SysParams<T>*>(c->params_dev), c->cell_base_dev, c->nsys, a_s, gy_s, q,
                        out, out_a);
@@ -736,9 +781,9 @@ void launch_variant(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, 
     const uint32_t n = (uint32_t)c->n;
     const SysParams<T>* sp = reinterpret_cast<const SysParams<T>*>(c->params_dev);
     if (v.kind == 0) {
-        if (v.imax == 16) launch_cells<T, D, OP, BATCH, BWD, 16, 128>(ctx, c, q, a_s, gy_s, out, out_a);
-        else if (v.block == 256) launch_cells<T, D, OP, BATCH, BWD, 8, 256>(ctx, c, q, a_s, gy_s, out, out_a);
-        else launch_cells<T, D, OP, BATCH, BWD, 8, 128>(ctx, c, q, a_s, gy_s, out, out_a);
+        if (v.imax == 16) launch_cells<T, D, OP, BATCH, BWD, 16, 128, 8>(ctx, c, q, a_s, gy_s, out, out_a);
+        else if (v.rounds == 1) launch_cells<T, D, OP, BATCH, BWD, 8, 128, 1>(ctx, c, q, a_s, gy_s, out, out_a);
+        else launch_cells<T, D, OP, BATCH, BWD, 8, 128, 8>(ctx, c, q, a_s, gy_s, out, out_a);
         return;
     }
     const dim3 grid((n + v.block - 1) / v.block);
@@ -849,8 +894,6 @@ aboria_status pair_sum_impl(aboria_ctx* ctx, const aboria_cells* c, int32_t op, 
     }
 }
 
-namespace {
-
 aboria_status pair_bwd_impl(aboria_ctx* ctx, const aboria_cells* c, int32_t op, const double* params,
                             int32_t nparams, const void* a, int32_t na, const void* gy, int32_t ny, void* gx,
                             void* ga, int32_t variant) {
@@ -893,6 +936,8 @@ aboria_status pair_bwd_impl(aboria_ctx* ctx, const aboria_cells* c, int32_t op, 
         }
     }
 }
+
+namespace {
 
 template <typename T, int D>
 aboria_status list_pairs(aboria_ctx* ctx, const aboria_cells* c, int64_t cap, uint32_t* pi, uint32_t* pj,
@@ -960,7 +1005,7 @@ extern "C" aboria_status aboria_pair_sum(aboria_ctx* ctx, const aboria_cells* ce
                                          void* y, int32_t ny) {
     if (!ctx) return ABORIA_ERR_INVALID_ARG;
     try {
-        const int32_t v = cells ? pick_variant(ctx, cells, op) : 0;
+        const int32_t v = cells ? pick_variant(ctx, cells, op, false) : 0;
         return pair_sum_impl(ctx, cells, op, params_host, nparams, a, na, y, ny, v);
     } catch (...) {
         return fail(ctx, ABORIA_ERR_OUT_OF_MEMORY, "host exception in pair_sum");
@@ -972,7 +1017,7 @@ extern "C" aboria_status aboria_pair_sum_backward(aboria_ctx* ctx, const aboria_
                                                   int32_t na, const void* gy, int32_t ny, void* gx, void* ga) {
     if (!ctx) return ABORIA_ERR_INVALID_ARG;
     try {
-        const int32_t v = cells ? pick_variant(ctx, cells, op) : 0;
+        const int32_t v = cells ? pick_variant(ctx, cells, op, true) : 0;
         return pair_bwd_impl(ctx, cells, op, params_host, nparams, a, na, gy, ny, gx, ga, v);
     } catch (...) {
         return fail(ctx, ABORIA_ERR_OUT_OF_MEMORY, "host exception in pair_sum_backward");

@@ -405,6 +405,10 @@ def test_every_variant_matches_oracle_and_is_deterministic(ctx, op, params):
     ctx.set_variant(-1)
     choice = A.autotune(ctx, cells, op, params, a_d)
     assert 0 <= choice < A.variant_count()
+    choice_b = A.autotune(ctx, cells, op, params, a_d, gy=gy_d)
+    assert 0 <= choice_b < A.variant_count()
+    gx_t, _ = A.pair_sum_backward(ctx, cells, op, params, gy_d, a_d)
+    check_close(gx_t.cpu().numpy(), gxo, sxo, TOL_F32, "adjoint %s [tuned]" % op)
     ctx.sync()
 
 
