@@ -1,0 +1,424 @@
+// Shared device code of the neighbour-sum kernels: precision primitives, the
+// operator functors (forward summand and adjoint contribution of one ordered
+// pair) and the per-particle box-search loop.  Internal to the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "common.hpp"
+
+namespace aboria {
+
+// ---------------------------------------------------------------------------
+// precision-specific primitives
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsqrt_t(double x) { return ::rsqrt(x); }
+__device__ __forceinline__ float exp_neg_t(float s) { return __builtin_amdgcn_exp2f(-s * 1.4426950408889634f); }
+__device__ __forceinline__ double exp_neg_t(double s) { return ::exp(-s); }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// ---------------------------------------------------------------------------
+// operators: forward summand and the adjoint contribution of one ordered pair
+// (i = the lane's particle, j = its neighbour; dx = x_j + shift - x_i = -u)
+// ---------------------------------------------------------------------------
+
+template <typename T>
+struct OpArgs {
+    T p0;  // k (spring, DEM spring) or c (exp force)
+};
+
+template <int OP, int D>
+struct OpShape {
+    static constexpr int NY = (OP == ABORIA_OP_COUNT || OP == ABORIA_OP_SOFT_SPHERE) ? 1 : D;
+    static constexpr int NA = OP == ABORIA_OP_DEM_SPRING ? 1 : 0;
+};
+
+template <typename T, int D, int OP>
+struct PairOp {
+    static constexpr int NY = OpShape<OP, D>::NY;
+
+    // acc += f(x_i, x_j, a_i, a_j)
+    __device__ __forceinline__ static void fwd(const OpArgs<T>& q, T r, const T* dx, T d2, T ai, T aj, T* acc) {
+        if constexpr (OP == ABORIA_OP_COUNT) {
+            acc[0] += T(1);
+        } else if constexpr (OP == ABORIA_OP_SPRING) {
+            // k (r - s) u / s = (k r / s - k) u,  u = -dx
+            const T rinv = rsqrt_t(d2);
+            const T g = fma_t(q.p0 * r, rinv, -q.p0);
+#pragma unroll
+            for (int k = 0; k < D; ++k) acc[k] = fma_t(-g, dx[k], acc[k]);
+        } else if constexpr (OP == ABORIA_OP_SOFT_SPHERE) {
+            const T s = d2 * rsqrt_t(d2);
+            const T v = fma_t(-s, T(1) / r, T(1));
+            acc[0] = fma_t(T(0.5) * v, v, acc[0]);
+        } else if constexpr (OP == ABORIA_OP_EXP_FORCE) {
+            // eq. (1): -c exp(-|dx|) dx / |dx|
+            const T rinv = rsqrt_t(d2);
+            const T s = d2 * rinv;
+            const T g = q.p0 * exp_neg_t(s) * rinv;
+#pragma unroll
+            for (int k = 0; k < D; ++k) acc[k] = fma_t(-g, dx[k], acc[k]);
+        } else {  // DEM spring: k (a_i + a_j - s) u / s
+            const T rinv = rsqrt_t(d2);
+            const T g = fma_t(q.p0 * (ai + aj), rinv, -q.p0);
+#pragma unroll
+            for (int k = 0; k < D; ++k) acc[k] = fma_t(-g, dx[k], acc[k]);
+        }
+    }
+
+    // Branchless forms: every lane evaluates the summand and keeps it only if
+    // ok (a select, never a multiply, so the inf/NaN a rejected or sentinel
+    // candidate produces cannot leak into the sums).
+    __device__ __forceinline__ static void fwd_masked(const OpArgs<T>& q, T r, const T* dx, T d2, T ai, T aj, bool ok,
+                                                      T* acc) {
+        if constexpr (OP == ABORIA_OP_COUNT) {
+            acc[0] += ok ? T(1) : T(0);
+        } else if constexpr (OP == ABORIA_OP_SOFT_SPHERE) {
+            const T s = d2 * rsqrt_t(d2);
+            const T v = fma_t(-s, T(1) / r, T(1));
+            const T term = T(0.5) * v * v;
+            acc[0] += ok ? term : T(0);
+        } else {
+            const T rinv = rsqrt_t(d2);
+            T g;
+            if constexpr (OP == ABORIA_OP_SPRING) {
+                g = fma_t(q.p0 * r, rinv, -q.p0);
+            } else if constexpr (OP == ABORIA_OP_EXP_FORCE) {
+                g = q.p0 * exp_neg_t(d2 * rinv) * rinv;
+            } else {
+                g = fma_t(q.p0 * (ai + aj), rinv, -q.p0);
+            }
+            g = ok ? g : T(0);
+#pragma unroll
+            for (int k = 0; k < D; ++k) acc[k] = fma_t(-g, dx[k], acc[k]);
+        }
+    }
+
+    __device__ __forceinline__ static void bwd_masked(const OpArgs<T>& q, T r, const T* dx, T d2, T ai, T aj,
+                                                      const T* gyi, const T* gyj, bool ok, T* gx, T* ga) {
+        if constexpr (OP == ABORIA_OP_COUNT) {
+            return;
+        } else if constexpr (OP == ABORIA_OP_SOFT_SPHERE) {
+            const T rinv = rsqrt_t(d2);
+            const T s = d2 * rinv;
+            const T inv_r = T(1) / r;
+            T coef = (gyi[0] + gyj[0]) * inv_r * fma_t(-s, inv_r, T(1)) * rinv;
+            coef = ok ? coef : T(0);
+#pragma unroll
+            for (int k = 0; k < D; ++k) gx[k] = fma_t(coef, dx[k], gx[k]);
+        } else {
+            const T rinv = rsqrt_t(d2);
+            const T rinv3 = rinv * rinv * rinv;
+            T w[D];
+            T dw = T(0);
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                w[k] = gyi[k] - gyj[k];
+                dw = fma_t(dx[k], w[k], dw);
+            }
+            T g, gps;
+            if constexpr (OP == ABORIA_OP_SPRING) {
+                g = fma_t(q.p0 * r, rinv, -q.p0);
+                gps = -q.p0 * r * rinv3;
+            } else if constexpr (OP == ABORIA_OP_EXP_FORCE) {
+                const T s = d2 * rinv;
+                const T ce = q.p0 * exp_neg_t(s);
+                g = ce * rinv;
+                gps = -ce * (s + T(1)) * rinv3;
+            } else {
+                const T A = ai + aj;
+                g = fma_t(q.p0 * A, rinv, -q.p0);
+                gps = -q.p0 * A * rinv3;
+                const T ta = -q.p0 * dw * rinv;
+                ga[0] += ok ? ta : T(0);
+            }
+            g = ok ? g : T(0);
+            const T h = ok ? gps * dw : T(0);
+#pragma unroll
+            for (int k = 0; k < D; ++k) gx[k] = fma_t(g, w[k], fma_t(h, dx[k], gx[k]));
+        }
+    }
+
+    // gx += J1(i,j)^T gy_i + J2(j,i)^T gy_j ; ga += d/da_i of the same.
+    // For f = g(s) u:  gx += g w + (g'/s)(u.w) u with w = gy_i - gy_j, and
+    // (u.w) u = (dx.w) dx.  For the soft sphere: gx += 1/2 (gy_i + gy_j)
+    // phi'(s) u/s with phi'(s) = -(2/r)(1 - s/r).
+    __device__ __forceinline__ static void bwd(const OpArgs<T>& q, T r, const T* dx, T d2, T ai, T aj,
+                                               const T* gyi, const T* gyj, T* gx, T* ga) {
+        if constexpr (OP == ABORIA_OP_COUNT) {
+            return;
+        } else if constexpr (OP == ABORIA_OP_SOFT_SPHERE) {
+            const T rinv = rsqrt_t(d2);
+            const T s = d2 * rinv;
+            const T inv_r = T(1) / r;
+            const T coef = (gyi[0] + gyj[0]) * inv_r * fma_t(-s, inv_r, T(1)) * rinv;
+#pragma unroll
+            for (int k = 0; k < D; ++k) gx[k] = fma_t(coef, dx[k], gx[k]);
+        } else {
+            const T rinv = rsqrt_t(d2);
+            const T rinv3 = rinv * rinv * rinv;
+            T w[D];
+            T dw = T(0);
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                w[k] = gyi[k] - gyj[k];
+                dw = fma_t(dx[k], w[k], dw);
+            }
+            T g, gps;  // g(s) and g'(s)/s
+            if constexpr (OP == ABORIA_OP_SPRING) {
+                g = fma_t(q.p0 * r, rinv, -q.p0);
+                gps = -q.p0 * r * rinv3;
+            } else if constexpr (OP == ABORIA_OP_EXP_FORCE) {
+                const T s = d2 * rinv;
+                const T ce = q.p0 * exp_neg_t(s);
+                g = ce * rinv;
+                gps = -ce * (s + T(1)) * rinv3;
+            } else {
+                const T A = ai + aj;
+                g = fma_t(q.p0 * A, rinv, -q.p0);
+                gps = -q.p0 * A * rinv3;
+                // d/da_i: k (gy_i - gy_j).u / s = -k (w.dx) / s
+                ga[0] = fma_t(-q.p0 * dw, rinv, ga[0]);
+            }
+            const T h = gps * dw;
+#pragma unroll
+            for (int k = 0; k < D; ++k) gx[k] = fma_t(g, w[k], fma_t(h, dx[k], gx[k]));
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// the per-particle box search
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int find_system_slot(const uint32_t* __restrict__ first, int nsys, uint32_t i) {
+    int lo = 0, hi = nsys - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (first[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void load_point(const T* __restrict__ xs, uint32_t s, T* xi) {
+    constexpr int PITCH = Pitch<D>::value;
+    const VecN<T, PITCH> v = reinterpret_cast<const VecN<T, PITCH>*>(xs)[s];
+#pragma unroll
+    for (int k = 0; k < D; ++k) xi[k] = v.v[k];
+}
+
+// Pair test of one candidate: dx_k = fl(fl(x_jk - x_ik) + s_k) (the shift add
+// only when SHIFT), d2 by the fixed fma chain; returns 0 < d2 < r2.
+template <typename T, int D, bool SHIFT>
+__device__ __forceinline__ bool pair_test(const T* xj, const T* xi, const T* sh, T r2, T* dx, T* d2out) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        dx[k] = xj[k] - xi[k];
+        if (SHIFT) dx[k] = dx[k] + sh[k];
+    }
+    T d2 = dx[0] * dx[0];
+    if constexpr (D >= 2) d2 = fma_t(dx[1], dx[1], d2);
+    if constexpr (D >= 3) d2 = fma_t(dx[2], dx[2], d2);
+    *d2out = d2;
+    return d2 > T(0) && d2 < r2;
+}
+
+// One contiguous slot range [j0, j1) of candidates with one image shift:
+// visit(j, dx, d2, shifted) for the accepted ones.  Two candidates are loaded
+// per iteration so their loads overlap.
+template <typename T, int D, bool SHIFT, typename Visit>
+__device__ __forceinline__ void scan_range(const T* __restrict__ xs, uint32_t j0, uint32_t j1, const T* xi,
+                                           const T* sh, T r2, Visit& visit) {
+    constexpr int PITCH = Pitch<D>::value;
+    const VecN<T, PITCH>* __restrict__ xv = reinterpret_cast<const VecN<T, PITCH>*>(xs);
+    uint32_t j = j0;
+    for (; j + 1 < j1; j += 2) {
+        const VecN<T, PITCH> a = xv[j];
+        const VecN<T, PITCH> b = xv[j + 1];
+        T dx[D], d2;
+        if (pair_test<T, D, SHIFT>(a.v, xi, sh, r2, dx, &d2)) visit(j, dx, d2, SHIFT);
+        if (pair_test<T, D, SHIFT>(b.v, xi, sh, r2, dx, &d2)) visit(j + 1, dx, d2, SHIFT);
+    }
+    if (j < j1) {
+        const VecN<T, PITCH> a = xv[j];
+        T dx[D], d2;
+        if (pair_test<T, D, SHIFT>(a.v, xi, sh, r2, dx, &d2)) visit(j, dx, d2, SHIFT);
+    }
+}
+
+// Box search of the point xi (a particle of the cell list, Section 2.2.2): its
+// cell and the adjacent cells, walked as 3^(d-1) x-rows of up to three cells,
+// each row split into contiguous pieces where a periodic wrap changes the
+// image shift.  A piece whose shift is zero on every active lane of the wave
+// runs the loop without the shift additions (adding zero is exact, so both
+// loops give the canonical dx).
+template <typename T, int D, typename Visit>
+__device__ __forceinline__ void neighbour_loop(const SysParams<T>& P, const T* __restrict__ xs,
+                                               const uint32_t* __restrict__ off, uint32_t n, const T* xi,
+                                               Visit&& visit) {
+    int32_t c[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const T t = xi[k] - P.lo[k];
+        const T q = t * P.inv_w[k];
+        const T f = floor(q);
+        c[k] = !(f >= T(0)) ? 0 : (f > T(P.n[k] - 1) ? P.n[k] - 1 : (int32_t)f);
+    }
+    const int32_t nx = P.n[0];
+    int np = 0;
+    int32_t plo[3], phi[3];
+    T psh[3];
+    if (nx >= 3) {
+        plo[0] = c[0] > 0 ? c[0] - 1 : 0;
+        phi[0] = c[0] < nx - 1 ? c[0] + 1 : nx - 1;
+        psh[0] = T(0);
+        np = 1;
+        if (P.periodic[0]) {
+            if (c[0] == 0) { plo[np] = phi[np] = nx - 1; psh[np] = -P.L[0]; ++np; }
+            if (c[0] == nx - 1) { plo[np] = phi[np] = 0; psh[np] = P.L[0]; ++np; }
+        }
+    } else {
+        for (int o = -1; o <= 1; ++o) {
+            int32_t v = c[0] + o;
+            T s = T(0);
+            if (v < 0) { if (!P.periodic[0]) continue; v += nx; s = -P.L[0]; }
+            else if (v >= nx) { if (!P.periodic[0]) continue; v -= nx; s = P.L[0]; }
+            plo[np] = phi[np] = v;
+            psh[np] = s;
+            ++np;
+        }
+    }
+    constexpr int NROWS = D == 1 ? 1 : (D == 2 ? 3 : 9);
+    const T r2 = P.r2;
+    for (int rr = 0; rr < NROWS; ++rr) {
+        T sh[3] = {T(0), T(0), T(0)};
+        uint32_t row = 0;
+        bool skip = false;
+        if constexpr (D >= 2) {
+            int32_t v = c[1] + (rr % 3) - 1;
+            if (v < 0) { if (!P.periodic[1]) skip = true; v += P.n[1]; sh[1] = -P.L[1]; }
+            else if (v >= P.n[1]) { if (!P.periodic[1]) skip = true; v -= P.n[1]; sh[1] = P.L[1]; }
+            row = (uint32_t)v;
+        }
+        if constexpr (D >= 3) {
+            int32_t v = c[2] + (rr / 3) - 1;
+            if (v < 0) { if (!P.periodic[2]) skip = true; v += P.n[2]; sh[2] = -P.L[2]; }
+            else if (v >= P.n[2]) { if (!P.periodic[2]) skip = true; v -= P.n[2]; sh[2] = P.L[2]; }
+            row += (uint32_t)P.n[1] * (uint32_t)v;
+        }
+        if (skip) continue;
+        const uint32_t rowbase = P.cell_base + (uint32_t)nx * row;
+        for (int p = 0; p < np; ++p) {
+            const uint32_t j0 = off[rowbase + plo[p]];
+            const uint32_t j1 = min(off[rowbase + phi[p] + 1], n);
+            sh[0] = psh[p];
+            bool lane_shift = false;
+#pragma unroll
+            for (int k = 0; k < D; ++k) lane_shift |= sh[k] != T(0);
+            if (__ballot(lane_shift) != 0ull) scan_range<T, D, true>(xs, j0, j1, xi, sh, r2, visit);
+            else scan_range<T, D, false>(xs, j0, j1, xi, sh, r2, visit);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// helpers of the cell-group mapping
+// ---------------------------------------------------------------------------
+
+constexpr int kGroup = 16;
+
+template <typename T>
+struct Far;
+template <>
+struct Far<float> {
+    __device__ static constexpr float home() { return 1e30f; }
+    __device__ static constexpr float cand() { return -1e30f; }
+};
+template <>
+struct Far<double> {
+    __device__ static constexpr double home() { return 1e300; }
+    __device__ static constexpr double cand() { return -1e300; }
+};
+
+__device__ __forceinline__ uint32_t wave_max_of_groups(uint32_t v) {
+    // v is uniform within each 16-lane group; lanes 0, 16, 32, 48 lead the groups
+    uint32_t a = __builtin_amdgcn_readlane(v, 0), b = __builtin_amdgcn_readlane(v, 16);
+    uint32_t c = __builtin_amdgcn_readlane(v, 32), d = __builtin_amdgcn_readlane(v, 48);
+    return max(max(a, b), max(c, d));
+}
+
+__device__ __forceinline__ int find_system_cell(const uint32_t* __restrict__ cell_base, int nsys, uint32_t c) {
+    int lo = 0, hi = nsys - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (cell_base[mid] <= c) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+    for (int m = 8; m >= 1; m >>= 1) v += __shfl_xor(v, m, kGroup);
+    return v;
+}
+
+// Shift of one dimension from its 2-bit code: 0 -> -L, 1 -> 0, 2 -> +L.
+template <typename T>
+__device__ __forceinline__ T shift_of(uint32_t code, int k, T L) {
+    const uint32_t m = (code >> (2 * k)) & 3u;
+    return m == 0u ? -L : (m == 2u ? L : T(0));
+}
+
+
+// ---------------------------------------------------------------------------
+// launchers (one translation unit each, explicitly instantiated)
+// ---------------------------------------------------------------------------
+
+// Lane-per-particle forward.
+template <typename T, int D, int OP, bool BATCH>
+void launch_lane_fwd(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, T* y, int block);
+
+// Lane-per-particle adjoint.  compact = true first lists each lane's accepted
+// neighbours in LDS and evaluates the adjoint summand on the list only.
+template <typename T, int D, int OP, bool BATCH>
+void launch_lane_bwd(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, const T* gy_s, T* gx,
+                     T* ga, int block, bool compact);
+
+// Cell-group forward / adjoint; rounds = 1 keeps natural cell order, 8 ranks
+// 64-cell tiles by (wrap, occupancy).
+template <typename T, int D, int OP, bool BATCH>
+void launch_cells_fwd(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, T* y, int rounds);
+template <typename T, int D, int OP, bool BATCH>
+void launch_cells_bwd(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, const T* gy_s, T* gx,
+                      T* ga, int rounds);
+
+#define ABORIA_FOR_EACH_PAIR_INSTANCE(X)                                                            \
+    X(float, 1, 0, false) X(float, 1, 1, false) X(float, 1, 2, false)                     \
+    X(float, 1, 3, false) X(float, 1, 4, false) X(float, 2, 0, false)                     \
+    X(float, 2, 1, false) X(float, 2, 2, false) X(float, 2, 3, false)                     \
+    X(float, 2, 4, false) X(float, 3, 0, false) X(float, 3, 1, false)                     \
+    X(float, 3, 2, false) X(float, 3, 3, false) X(float, 3, 4, false)                     \
+    X(float, 1, 0, true) X(float, 1, 1, true) X(float, 1, 2, true)                        \
+    X(float, 1, 3, true) X(float, 1, 4, true) X(float, 2, 0, true)                        \
+    X(float, 2, 1, true) X(float, 2, 2, true) X(float, 2, 3, true)                        \
+    X(float, 2, 4, true) X(float, 3, 0, true) X(float, 3, 1, true)                        \
+    X(float, 3, 2, true) X(float, 3, 3, true) X(float, 3, 4, true)                        \
+    X(double, 1, 0, false) X(double, 1, 1, false) X(double, 1, 2, false)                  \
+    X(double, 1, 3, false) X(double, 1, 4, false) X(double, 2, 0, false)                  \
+    X(double, 2, 1, false) X(double, 2, 2, false) X(double, 2, 3, false)                  \
+    X(double, 2, 4, false) X(double, 3, 0, false) X(double, 3, 1, false)                  \
+    X(double, 3, 2, false) X(double, 3, 3, false) X(double, 3, 4, false)                  \
+    X(double, 1, 0, true) X(double, 1, 1, true) X(double, 1, 2, true)                     \
+    X(double, 1, 3, true) X(double, 1, 4, true) X(double, 2, 0, true)                     \
+    X(double, 2, 1, true) X(double, 2, 2, true) X(double, 2, 3, true)                     \
+    X(double, 2, 4, true) X(double, 3, 0, true) X(double, 3, 1, true)                     \
+    X(double, 3, 2, true) X(double, 3, 3, true) X(double, 3, 4, true)
+
+}  // namespace aboria
