@@ -81,6 +81,7 @@ struct Variant {
 };
 
 const Variant kVariants[] = {
+    {0, 512, true, 0, "lane per particle, 256-thread workgroups, adjoint through a per-wave queue of accepted pairs"},
     {0, 256, true, 0, "lane per particle, 256-thread workgroups, adjoint on a 48-entry LDS list of accepted pairs"},
     {0, 128, true, 0, "lane per particle, 128-thread workgroups, adjoint on a 64-entry LDS list of accepted pairs"},
     {0, 256, false, 0, "lane per particle, 256-thread workgroups, adjoint evaluated on every candidate"},
@@ -93,7 +94,7 @@ template <typename T, int D, int OP, bool BATCH>
 void launch_fwd_variant(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, T* y,
                         const Variant& v) {
     if (v.kind == 1) launch_cells_fwd<T, D, OP, BATCH>(ctx, c, q, a_s, y, v.rounds);
-    else launch_lane_fwd<T, D, OP, BATCH>(ctx, c, q, a_s, y, v.block);
+    else launch_lane_fwd<T, D, OP, BATCH>(ctx, c, q, a_s, y, v.block > 256 ? 256 : v.block);
 }
 
 template <typename T, int D, int OP, bool BATCH>
