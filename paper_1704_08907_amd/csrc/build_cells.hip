@@ -6,8 +6,11 @@
 //   k_scan_local,    device-wide exclusive scan of the digit-major
 //   k_scan_top       (digit, tile) counts
 //   k_radix_scatter  stable in-tile ranks from wave ballots, then scatter
-//   k_finalize       cell offsets by boundary detection and the gather of the
-//                    positions into cell order
+//                    (these three run once per radix pass over the high key
+//                    bits, stably grouping particles by bucket of cells)
+//   k_bucket_finalize  the last radix pass, one workgroup per bucket: low-digit
+//                    histogram in LDS -> the bucket's cell offsets, stable
+//                    placement, and the gather of the positions into cell order
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -45,9 +48,18 @@ __global__ __launch_bounds__(kBlock) void k_cell_ids(const T* __restrict__ x, ui
                                                      const SysParams<T>* __restrict__ sp,
                                                      const uint32_t* __restrict__ sys_part, int nsys,
                                                      uint32_t* __restrict__ keys, uint32_t* __restrict__ flag) {
-    uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    int b = 0;
+    if (BATCH) {
+        // the workgroup's rows are contiguous: one binary search for its first
+        // row, then each lane steps forward over the (few) systems it spans
+        __shared__ int s_first;
+        if (threadIdx.x == 0) s_first = find_system(sys_part, nsys, blockIdx.x * kBlock);
+        __syncthreads();
+        b = s_first;
+        while (b + 1 < nsys && sys_part[b + 1] <= i) ++b;
+    }
     if (i >= n) return;
-    int b = BATCH ? find_system(sys_part, nsys, i) : 0;
     const SysParams<T>& P = sp[b];
     uint32_t id = 0, mul = 1;
     bool bad = false;
@@ -282,32 +294,127 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __rest
 }
 
 // ---------------------------------------------------------------------------
-// a3 + a4: cell offsets and the gather into cell order
+// last radix pass fused with a3 + a4: per bucket of 2^lb consecutive cells
 // ---------------------------------------------------------------------------
 
-// Thread t < n writes off[c] = t for the cells c in (keys[t-1], keys[t]] (all
-// cells up to keys[0] for t = 0) and copies the position of particle perm[t]
-// to slot t.  Threads t <= ncells past the last key write off[t] = n.
+// The input is sorted (stably) by key >> lb, so bucket b -- the cells
+// [b << lb, (b + 1) << lb) -- is one contiguous range of it, in original index
+// order.  One workgroup per bucket: it histograms the low digit of its keys in
+// LDS, writes the offsets of its cells (bucket start + exclusive scan), and
+// places its elements stably, chunk by chunk, with the same wave-ballot ranks
+// as k_radix_scatter, writing the sorted key, the permutation and the position
+// gathered from the original array.  Buckets cover cells 0..ncells inclusive,
+// so off[ncells] = n is written too.
 template <typename T, int D>
-__global__ __launch_bounds__(kBlock) void k_finalize(const uint32_t* __restrict__ keys,
-                                                     const uint32_t* __restrict__ perm, uint32_t n,
-                                                     const T* __restrict__ x, T* __restrict__ xs,
-                                                     uint32_t* __restrict__ off, uint32_t ncells) {
+__global__ __launch_bounds__(kBlock) void k_bucket_finalize(const uint32_t* __restrict__ keys_in,
+                                                            const uint32_t* __restrict__ vals_in, uint32_t n,
+                                                            int lb, uint32_t ncells, const T* __restrict__ x,
+                                                            T* __restrict__ xs, uint32_t* __restrict__ keys_out,
+                                                            uint32_t* __restrict__ perm_out,
+                                                            uint32_t* __restrict__ off) {
     constexpr int PITCH = Pitch<D>::value;
-    const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
-    if (t < n) {
-        const uint32_t key = min(keys[t], ncells - 1u);
-        const uint32_t first = t == 0 ? 0u : keys[t - 1] + 1u;
-        for (uint32_t c = first; c <= key; ++c) off[c] = t;
-        const uint32_t p = min(perm[t], n - 1u);
-        VecN<T, PITCH> v;
-#pragma unroll
-        for (int k = 0; k < PITCH; ++k) v.v[k] = k < D ? x[(size_t)p * D + k] : T(0);
-        reinterpret_cast<VecN<T, PITCH>*>(xs)[t] = v;
+    extern __shared__ uint32_t lds[];
+    const uint32_t R = 1u << lb, mask = R - 1u;
+    uint32_t* hist = lds;              // [R]
+    uint32_t* base = lds + R;          // [R] running destination base per digit
+    uint32_t* cnt = lds + 2 * R;       // [4][R] per-wave counts of the current chunk
+    __shared__ uint32_t s_range[2];
+    __shared__ uint32_t s_wsum[4];
+    const uint32_t bucket = blockIdx.x;
+    const uint32_t cell0 = bucket << lb;
+    if (threadIdx.x < 2) {
+        // first index whose high part is >= bucket + threadIdx.x
+        const uint32_t target = bucket + threadIdx.x;
+        uint32_t lo = 0, hi = n;
+        while (lo < hi) {
+            const uint32_t mid = lo + ((hi - lo) >> 1);
+            if ((keys_in[mid] >> lb) < target) lo = mid + 1; else hi = mid;
+        }
+        s_range[threadIdx.x] = lo;
     }
-    if (t <= ncells) {
-        if (n == 0) off[t] = 0;
-        else if (t > keys[n - 1]) off[t] = n;
+    for (uint32_t d = threadIdx.x; d < R; d += kBlock) hist[d] = 0;
+    __syncthreads();
+    const uint32_t b0 = s_range[0], b1 = s_range[1];
+    for (uint32_t i = b0 + threadIdx.x; i < b1; i += kBlock) atomicAdd(&hist[keys_in[i] & mask], 1u);
+    __syncthreads();
+    {   // exclusive scan of hist into base: each thread owns a run of R/256 digits (R >= 256) or one
+        const uint32_t per = R >= (uint32_t)kBlock ? R / kBlock : 1u;
+        const uint32_t d0 = threadIdx.x * per;
+        uint32_t tot = 0;
+        if (d0 < R)
+            for (uint32_t k = 0; k < per; ++k) tot += hist[d0 + k];
+        uint32_t total;
+        uint32_t ex = block_exclusive_scan(tot, s_wsum, &total);
+        if (d0 < R) {
+            for (uint32_t k = 0; k < per; ++k) {
+                const uint32_t c = cell0 + d0 + k;
+                base[d0 + k] = ex;
+                if (c <= ncells) off[c] = b0 + ex;
+                ex += hist[d0 + k];
+            }
+        }
+    }
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t* wc = cnt + w * R;
+    const uint64_t lt = lanemask_lt();
+    for (uint32_t chunk = b0; chunk < b1; chunk += kSortTile) {
+        for (uint32_t d = threadIdx.x; d < R; d += kBlock) {
+            cnt[d] = 0;
+            cnt[R + d] = 0;
+            cnt[2 * R + d] = 0;
+            cnt[3 * R + d] = 0;
+        }
+        __syncthreads();
+        const uint32_t wbase = chunk + w * (kWave * kSortIpt);
+        uint32_t key[kSortIpt], val[kSortIpt], loc[kSortIpt];
+#pragma unroll
+        for (int st = 0; st < kSortIpt; ++st) {
+            const uint32_t idx = wbase + st * kWave + lane;
+            const bool valid = idx < b1;
+            const uint32_t k = valid ? keys_in[idx] : 0u;
+            const uint32_t v = valid ? (vals_in ? vals_in[idx] : idx) : 0u;
+            const uint32_t dg = k & mask;
+            uint64_t peers = __ballot(valid);
+            for (int bb = 0; bb < lb; ++bb) {
+                const bool bit = (dg >> bb) & 1u;
+                const uint64_t m = __ballot(bit);
+                peers &= bit ? m : ~m;
+            }
+            const uint32_t below = (uint32_t)__popcll(peers & lt);
+            const uint32_t c = valid ? wc[dg] : 0u;
+            if (valid && below == 0) wc[dg] = c + (uint32_t)__popcll(peers);
+            key[st] = k;
+            val[st] = v;
+            loc[st] = c + below;
+        }
+        __syncthreads();
+        for (uint32_t d = threadIdx.x; d < R; d += kBlock) {
+            const uint32_t a0 = cnt[d], a1 = cnt[R + d], a2 = cnt[2 * R + d], a3 = cnt[3 * R + d];
+            cnt[d] = base[d];
+            cnt[R + d] = base[d] + a0;
+            cnt[2 * R + d] = base[d] + a0 + a1;
+            cnt[3 * R + d] = base[d] + a0 + a1 + a2;
+            base[d] += a0 + a1 + a2 + a3;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int st = 0; st < kSortIpt; ++st) {
+            const uint32_t idx = wbase + st * kWave + lane;
+            if (idx < b1) {
+                const uint32_t dest = b0 + wc[key[st] & mask] + loc[st];
+                if (dest < n) {  // always true for a consistent histogram; keeps a bad one in bounds
+                    keys_out[dest] = key[st];
+                    const uint32_t p = min(val[st], n - 1u);
+                    perm_out[dest] = p;
+                    VecN<T, PITCH> v;
+#pragma unroll
+                    for (int k = 0; k < PITCH; ++k) v.v[k] = k < D ? x[(size_t)p * D + k] : T(0);
+                    reinterpret_cast<VecN<T, PITCH>*>(xs)[dest] = v;
+                }
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -411,8 +518,11 @@ aboria_status launch_build(aboria_ctx* ctx, aboria_cells* c, const void* x) {
     const uint32_t n = (uint32_t)c->n;
     const SysParams<T>* sp = reinterpret_cast<const SysParams<T>*>(c->params_dev);
     hipStream_t st = ctx->stream;
-    uint32_t* k0 = (c->passes % 2 == 1) ? c->keys_alt : c->keys;
-    uint32_t* v0 = (c->passes % 2 == 1) ? c->perm_alt : c->perm;
+    // passes over the high bits [lb, key_bits) end in the *_alt buffers; the
+    // bucket pass then writes keys / perm
+    uint32_t* k0 = (c->passes % 2 == 1) ? c->keys : c->keys_alt;
+    uint32_t* kin = k0;
+    uint32_t* vin = nullptr;
     if (n > 0) {
         const dim3 grid((n + kBlock - 1) / kBlock);
         if (c->nsys == 1)
@@ -423,10 +533,10 @@ aboria_status launch_build(aboria_ctx* ctx, aboria_cells* c, const void* x) {
                                c->sys_part_dev, c->nsys, k0, ctx->d_flag);
         const uint32_t ntiles = (uint32_t)c->ntiles;
         const uint32_t radix = 1u << c->digit_bits;
-        uint32_t *kin = k0, *vin = nullptr, *kout = (k0 == c->keys) ? c->keys_alt : c->keys;
+        uint32_t* kout = (k0 == c->keys) ? c->keys_alt : c->keys;
         uint32_t* vout = (k0 == c->keys) ? c->perm_alt : c->perm;
         for (int p = 0; p < c->passes; ++p) {
-            const int shift = p * c->digit_bits;
+            const int shift = c->low_bits + p * c->digit_bits;
             hipLaunchKernelGGL(k_radix_hist, dim3(ntiles), dim3(kBlock), radix * sizeof(uint32_t), st, kin, n, shift,
                                c->digit_bits, c->hist, ntiles);
             aboria_status s = scan_exclusive_u32(ctx, c->hist, c->hist, (int64_t)radix * ntiles, c->block_sums,
@@ -438,11 +548,11 @@ aboria_status launch_build(aboria_ctx* ctx, aboria_cells* c, const void* x) {
             vin = vout;
             vout = (vout == c->perm) ? c->perm_alt : c->perm;
         }
-        (void)v0;
     }
-    const uint32_t threads = std::max<uint32_t>(n, (uint32_t)c->ncells + 1);
-    hipLaunchKernelGGL((k_finalize<T, D>), dim3((threads + kBlock - 1) / kBlock), dim3(kBlock), 0, st, c->keys,
-                       c->perm, n, (const T*)x, (T*)c->xs, c->off, (uint32_t)c->ncells);
+    const uint32_t R = 1u << c->low_bits;
+    const uint32_t nbuckets = (uint32_t)(((uint64_t)c->ncells + 1 + R - 1) / R);
+    hipLaunchKernelGGL((k_bucket_finalize<T, D>), dim3(nbuckets), dim3(kBlock), 6 * R * sizeof(uint32_t), st, kin,
+                       vin, n, c->low_bits, (uint32_t)c->ncells, (const T*)x, (T*)c->xs, c->keys, c->perm, c->off);
     ABORIA_HIP(ctx, hipGetLastError());
     return ABORIA_OK;
 }
@@ -522,8 +632,12 @@ extern "C" aboria_status aboria_build_cells(aboria_ctx* ctx, aboria_dtype dtype,
             int32_t bits = 1;
             while (bits < 32 && ((int64_t)1 << bits) < total_cells) ++bits;
             c->key_bits = bits;
-            c->passes = (bits + kMaxDigitBits - 1) / kMaxDigitBits;
-            c->digit_bits = (bits + c->passes - 1) / c->passes;
+            // the bucket pass sorts the low bits (8 to 10 of them); LDS-ranked
+            // radix passes of at most 10 bits sort the rest first
+            c->low_bits = std::min(bits, std::max(8, std::min(bits - kMaxDigitBits, kMaxDigitBits)));
+            const int high = bits - c->low_bits;
+            c->passes = (high + kMaxDigitBits - 1) / kMaxDigitBits;
+            c->digit_bits = c->passes > 0 ? (high + c->passes - 1) / c->passes : 1;
             c->ntiles = (n + kSortTile - 1) / kSortTile;
             c->hist_len = ((int64_t)1 << c->digit_bits) * std::max<int64_t>(c->ntiles, 1);
             c->nblock_sums = std::max<int64_t>(scan_block_count(c->hist_len), 1);

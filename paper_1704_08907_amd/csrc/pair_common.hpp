@@ -205,6 +205,21 @@ __device__ __forceinline__ int find_system_slot(const uint32_t* __restrict__ fir
     return lo;
 }
 
+// System of row i for a workgroup whose rows start at block_first and are
+// contiguous: one binary search per workgroup, then a short forward step per
+// lane.  Every thread of the workgroup must call it (it synchronises).
+template <bool BATCH>
+__device__ __forceinline__ int system_of_row(const uint32_t* __restrict__ sys_part, int nsys, uint32_t block_first,
+                                             uint32_t i) {
+    if (!BATCH) return 0;
+    __shared__ int s_first;
+    if (threadIdx.x == 0) s_first = find_system_slot(sys_part, nsys, block_first);
+    __syncthreads();
+    int b = s_first;
+    while (b + 1 < nsys && sys_part[b + 1] <= i) ++b;
+    return b;
+}
+
 template <typename T, int D>
 __device__ __forceinline__ void load_point(const T* __restrict__ xs, uint32_t s, T* xi) {
     constexpr int PITCH = Pitch<D>::value;

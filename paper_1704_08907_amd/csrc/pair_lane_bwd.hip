@@ -25,9 +25,10 @@ __global__ __launch_bounds__(256) void k_lane_bwd(const T* __restrict__ xs, cons
                                                   OpArgs<T> q, T* __restrict__ gx, T* __restrict__ ga) {
     using Op = PairOp<T, D, OP>;
     constexpr int NY = Op::NY;
-    const uint32_t s = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const uint32_t first = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x;
+    const uint32_t s = first + threadIdx.x;
+    const int b = system_of_row<BATCH>(sys_part, nsys, first, s);
     if (s >= n) return;
-    const int b = BATCH ? find_system_slot(sys_part, nsys, s) : 0;
     const SysParams<T> P = sp[b];
     T xi[D];
     load_point<T, D>(xs, s, xi);
@@ -64,9 +65,10 @@ __global__ __launch_bounds__(BLOCK) void k_lane_bwd_compact(
     constexpr uint32_t kShiftBit = 0x80000000u;
     __shared__ uint32_t list[CAP * BLOCK];
     const uint32_t tid = threadIdx.x;
-    const uint32_t s = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + tid;
+    const uint32_t first = xcd_tile(blockIdx.x, gridDim.x) * BLOCK;
+    const uint32_t s = first + tid;
+    const int b = system_of_row<BATCH>(sys_part, nsys, first, s);
     if (s >= n) return;
-    const int b = BATCH ? find_system_slot(sys_part, nsys, s) : 0;
     const SysParams<T> P = sp[b];
     T xi[D];
     load_point<T, D>(xs, s, xi);
@@ -151,7 +153,7 @@ __global__ __launch_bounds__(256) void k_lane_bwd_queue(
     const uint32_t s = xcd_tile(blockIdx.x, gridDim.x) * 256u + threadIdx.x;
     const bool live = s < n;
     const uint32_t sc = live ? s : 0u;
-    const int b = BATCH ? find_system_slot(sys_part, nsys, sc) : 0;
+    const int b = system_of_row<BATCH>(sys_part, nsys, s - threadIdx.x, sc);
     const SysParams<T> P = sp[b];
     T xi[D];
     load_point<T, D>(xs, sc, xi);

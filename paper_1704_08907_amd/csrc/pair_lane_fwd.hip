@@ -13,9 +13,10 @@ __global__ __launch_bounds__(256) void k_lane_fwd(const T* __restrict__ xs, cons
                                                   const T* __restrict__ a_s, OpArgs<T> q, T* __restrict__ y) {
     using Op = PairOp<T, D, OP>;
     constexpr int NY = Op::NY;
-    const uint32_t s = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const uint32_t first = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x;
+    const uint32_t s = first + threadIdx.x;
+    const int b = system_of_row<BATCH>(sys_part, nsys, first, s);
     if (s >= n) return;
-    const int b = BATCH ? find_system_slot(sys_part, nsys, s) : 0;
     const SysParams<T> P = sp[b];
     T xi[D];
     load_point<T, D>(xs, s, xi);

@@ -45,14 +45,18 @@ __global__ __launch_bounds__(kPairBlock) void k_pair_list(const T* __restrict__ 
     if (!FILL) counts[s] = cnt;
 }
 
-// dst[s][w] = src[perm[s]][w]
-template <typename T>
+// dst[s][:] = src[perm[s]][:] for rows of W elements (W <= 4): one thread per row.
+template <typename T, int W>
 __global__ __launch_bounds__(256) void k_gather_rows(const T* __restrict__ src, const uint32_t* __restrict__ perm,
-                                                     uint32_t n, int w, T* __restrict__ dst) {
-    const uint32_t t = blockIdx.x * 256 + threadIdx.x;
-    if (t >= n * (uint32_t)w) return;
-    const uint32_t s = t / w, k = t - s * w;
-    dst[t] = src[(size_t)perm[s] * w + k];
+                                                     uint32_t n, T* __restrict__ dst) {
+    const uint32_t s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= n) return;
+    const uint32_t p = perm[s];
+    T v[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) v[k] = src[(size_t)p * W + k];
+#pragma unroll
+    for (int k = 0; k < W; ++k) dst[(size_t)s * W + k] = v[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -63,10 +67,15 @@ namespace {
 
 template <typename T>
 aboria_status gather(aboria_ctx* ctx, const aboria_cells* c, const void* src, int w, void* dst) {
-    const uint64_t total = (uint64_t)c->n * (uint64_t)w;
-    if (total == 0) return ABORIA_OK;
-    hipLaunchKernelGGL(k_gather_rows<T>, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0, ctx->stream,
-                       (const T*)src, c->perm, (uint32_t)c->n, w, (T*)dst);
+    const uint32_t n = (uint32_t)c->n;
+    if (n == 0 || w == 0) return ABORIA_OK;
+    const dim3 grid((n + 255) / 256);
+    switch (w) {
+        case 1: hipLaunchKernelGGL((k_gather_rows<T, 1>), grid, dim3(256), 0, ctx->stream, (const T*)src, c->perm, n, (T*)dst); break;
+        case 2: hipLaunchKernelGGL((k_gather_rows<T, 2>), grid, dim3(256), 0, ctx->stream, (const T*)src, c->perm, n, (T*)dst); break;
+        case 3: hipLaunchKernelGGL((k_gather_rows<T, 3>), grid, dim3(256), 0, ctx->stream, (const T*)src, c->perm, n, (T*)dst); break;
+        default: hipLaunchKernelGGL((k_gather_rows<T, 4>), grid, dim3(256), 0, ctx->stream, (const T*)src, c->perm, n, (T*)dst); break;
+    }
     ABORIA_HIP(ctx, hipGetLastError());
     return ABORIA_OK;
 }
@@ -81,10 +90,10 @@ struct Variant {
 };
 
 const Variant kVariants[] = {
-    {0, 512, true, 0, "lane per particle, 256-thread workgroups, adjoint through a per-wave queue of accepted pairs"},
+    {0, 256, false, 0, "lane per particle, 256-thread workgroups, adjoint evaluated on every candidate"},
     {0, 256, true, 0, "lane per particle, 256-thread workgroups, adjoint on a 48-entry LDS list of accepted pairs"},
     {0, 128, true, 0, "lane per particle, 128-thread workgroups, adjoint on a 64-entry LDS list of accepted pairs"},
-    {0, 256, false, 0, "lane per particle, 256-thread workgroups, adjoint evaluated on every candidate"},
+    {0, 512, true, 0, "lane per particle, 256-thread workgroups, adjoint through a per-wave queue of accepted pairs"},
     {1, 128, false, 1, "cell group of 16 lanes per home cell, cells in natural order"},
     {1, 128, false, 8, "cell group of 16 lanes per home cell, 64-cell tiles ranked by occupancy"},
 };
