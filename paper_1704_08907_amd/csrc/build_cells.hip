@@ -305,13 +305,20 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __rest
 // as k_radix_scatter, writing the sorted key, the permutation and the position
 // gathered from the original array.  Buckets cover cells 0..ncells inclusive,
 // so off[ncells] = n is written too.
+// When exactly one radix pass sorted the high bits, its scanned digit-major
+// histogram (hist_scan + block_sums, ntiles tiles) gives each bucket's start
+// directly; otherwise (hist_scan == nullptr) the bounds are found by binary
+// search of the high parts.
 template <typename T, int D>
 __global__ __launch_bounds__(kBlock) void k_bucket_finalize(const uint32_t* __restrict__ keys_in,
                                                             const uint32_t* __restrict__ vals_in, uint32_t n,
                                                             int lb, uint32_t ncells, const T* __restrict__ x,
                                                             T* __restrict__ xs, uint32_t* __restrict__ keys_out,
                                                             uint32_t* __restrict__ perm_out,
-                                                            uint32_t* __restrict__ off) {
+                                                            uint32_t* __restrict__ off,
+                                                            const uint32_t* __restrict__ hist_scan,
+                                                            const uint32_t* __restrict__ block_sums, uint32_t ntiles,
+                                                            uint32_t ndigits) {
     constexpr int PITCH = Pitch<D>::value;
     extern __shared__ uint32_t lds[];
     const uint32_t R = 1u << lb, mask = R - 1u;
@@ -325,10 +332,21 @@ __global__ __launch_bounds__(kBlock) void k_bucket_finalize(const uint32_t* __re
     if (threadIdx.x < 2) {
         // first index whose high part is >= bucket + threadIdx.x
         const uint32_t target = bucket + threadIdx.x;
-        uint32_t lo = 0, hi = n;
-        while (lo < hi) {
-            const uint32_t mid = lo + ((hi - lo) >> 1);
-            if ((keys_in[mid] >> lb) < target) lo = mid + 1; else hi = mid;
+        uint32_t lo;
+        if (hist_scan) {
+            if (target >= ndigits) {
+                lo = n;
+            } else {
+                const size_t p = (size_t)target * ntiles;
+                lo = hist_scan[p] + block_sums[p / kScanTile];
+            }
+        } else {
+            lo = 0;
+            uint32_t hi = n;
+            while (lo < hi) {
+                const uint32_t mid = lo + ((hi - lo) >> 1);
+                if ((keys_in[mid] >> lb) < target) lo = mid + 1; else hi = mid;
+            }
         }
         s_range[threadIdx.x] = lo;
     }
@@ -551,8 +569,10 @@ aboria_status launch_build(aboria_ctx* ctx, aboria_cells* c, const void* x) {
     }
     const uint32_t R = 1u << c->low_bits;
     const uint32_t nbuckets = (uint32_t)(((uint64_t)c->ncells + 1 + R - 1) / R);
+    const bool direct = c->passes == 1 && n > 0;
     hipLaunchKernelGGL((k_bucket_finalize<T, D>), dim3(nbuckets), dim3(kBlock), 6 * R * sizeof(uint32_t), st, kin,
-                       vin, n, c->low_bits, (uint32_t)c->ncells, (const T*)x, (T*)c->xs, c->keys, c->perm, c->off);
+                       vin, n, c->low_bits, (uint32_t)c->ncells, (const T*)x, (T*)c->xs, c->keys, c->perm, c->off,
+                       direct ? c->hist : nullptr, c->block_sums, (uint32_t)c->ntiles, 1u << c->digit_bits);
     ABORIA_HIP(ctx, hipGetLastError());
     return ABORIA_OK;
 }
