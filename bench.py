@@ -168,6 +168,10 @@ def main():
         return e0.elapsed_time(e1) / reps
 
     t_build = timed(lambda: A.build_cells(ctx, x, [box], cells=cells))
+    ctx.set_build_strategy("radix")
+    t_build_radix = timed(lambda: A.build_cells(ctx, x, [box], cells=cells))
+    ctx.set_build_strategy("counting")
+    A.build_cells(ctx, x, [box], cells=cells)
     t_fwd = timed(lambda: A.pair_sum(ctx, cells, "spring", (1.0,), y=y))
     t_bwd = timed(lambda: A.pair_sum_backward(ctx, cells, "spring", (1.0,), gy, gx=gx))
     per_variant = {}
@@ -191,7 +195,7 @@ def main():
                 "algorithmic_ops_per_launch": ops_dom, "avg_launch_ms": t_dom}
     # build bytes: x in (12 B), keys+perm through 2 radix passes, offsets, sorted x out (16 B)
     build_bytes = n * (12 + 4 + 2 * (4 + 4 + 8 + 8) + 4 + 16) + 4 * (int(cells.view().ncells) + 1)
-    breakdown = {"build_ms": t_build, "fwd_ms": t_fwd, "bwd_ms": t_bwd,
+    breakdown = {"build_ms": t_build, "build_radix_ms": t_build_radix, "fwd_ms": t_fwd, "bwd_ms": t_bwd,
                  "build_hbm_frac": build_bytes / (t_build * 1e-3) / 1e9 / HBM_PEAK_GBS,
                  "fwd_pairs_per_s": pairs / ((t_build + t_fwd) * 1e-3),
                  "fwd_only_pairs_per_s": pairs / (t_fwd * 1e-3),

@@ -163,6 +163,18 @@ aboria_status aboria_build_cells(aboria_ctx* ctx, aboria_dtype dtype, int32_t ns
                                  const aboria_box* boxes_host, const int64_t* offsets_host,
                                  const void* x, aboria_cells** cells);
 aboria_status aboria_cells_view_get(const aboria_cells* cells, aboria_cells_view* out);
+
+/* How aboria_build_cells sorts particles into cell order (both give the same
+ * cell list, bit for bit: stable by cell, original index order inside a cell):
+ *   RADIX     LDS-ranked stable LSD radix passes over the high key bits, then
+ *             one pass per bucket of cells that also writes the offsets and
+ *             gathers the positions;
+ *   COUNTING  a per-cell count with each particle's arrival rank (atomic), a
+ *             scan of the counts (the cell offsets), placement, and a per-slot
+ *             fix-up that restores original index order inside each cell.
+ * The setting applies to later builds on ctx; the default is COUNTING. */
+typedef enum aboria_build_strategy { ABORIA_BUILD_RADIX = 0, ABORIA_BUILD_COUNTING = 1 } aboria_build_strategy;
+aboria_status aboria_set_build_strategy(aboria_ctx* ctx, aboria_build_strategy strategy);
 aboria_status aboria_cells_destroy(aboria_cells* cells);
 
 /* ---- neighbour sums (Section 3: eq. (1) and the velocity-update listing) ----

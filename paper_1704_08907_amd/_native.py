@@ -51,7 +51,7 @@ EXPORTS = ["aboria_create", "aboria_destroy", "aboria_set_stream", "aboria_last_
            "aboria_pair_sum_backward", "aboria_pair_list", "aboria_dense_sum",
            "aboria_graph_capture_begin", "aboria_graph_capture_end", "aboria_graph_launch",
            "aboria_graph_destroy", "aboria_autotune", "aboria_variant_count", "aboria_variant_name",
-           "aboria_set_variant", "aboria_op_ny", "aboria_op_na"]
+           "aboria_set_variant", "aboria_op_ny", "aboria_op_na", "aboria_set_build_strategy"]
 
 
 def lib():
@@ -86,6 +86,7 @@ def lib():
             "aboria_set_variant": ([P, I32], I32),
             "aboria_op_ny": ([I32, I32], I32),
             "aboria_op_na": ([I32], I32),
+            "aboria_set_build_strategy": ([P, I32], I32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -142,6 +143,11 @@ class Context:
     def set_stream(self, stream: torch.cuda.Stream):
         self.check(lib().aboria_set_stream(self.handle, C.c_void_p(stream.cuda_stream)), "set_stream")
         self.stream = stream
+
+    def set_build_strategy(self, strategy: str):
+        """Sort used by later builds: "radix" or "counting" (the same cell list either way)."""
+        code = {"radix": 0, "counting": 1}[strategy]
+        self.check(lib().aboria_set_build_strategy(self.handle, code), "set_build_strategy")
 
     def set_variant(self, v: int):
         """Force a neighbour-sum variant for later calls (-1 = tuned / default)."""

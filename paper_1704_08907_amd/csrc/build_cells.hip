@@ -43,11 +43,15 @@ __device__ __forceinline__ int find_system(const uint32_t* __restrict__ first, i
     return lo;
 }
 
+// With counts != nullptr it also takes the particle's arrival rank in its cell
+// (an atomic increment of the cell's count; the order of arrival is not
+// deterministic, the counting build restores the index order afterwards).
 template <typename T, int D, bool BATCH>
 __global__ __launch_bounds__(kBlock) void k_cell_ids(const T* __restrict__ x, uint32_t n,
                                                      const SysParams<T>* __restrict__ sp,
                                                      const uint32_t* __restrict__ sys_part, int nsys,
-                                                     uint32_t* __restrict__ keys, uint32_t* __restrict__ flag) {
+                                                     uint32_t* __restrict__ keys, uint32_t* __restrict__ flag,
+                                                     uint32_t* __restrict__ counts, uint32_t* __restrict__ ranks) {
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     int b = 0;
     if (BATCH) {
@@ -78,7 +82,68 @@ __global__ __launch_bounds__(kBlock) void k_cell_ids(const T* __restrict__ x, ui
         mul *= (uint32_t)P.n[k];
     }
     if (bad) atomicOr(flag, 1u);
-    keys[i] = P.cell_base + id;
+    const uint32_t key = P.cell_base + id;
+    keys[i] = key;
+    if (counts) ranks[i] = atomicAdd(&counts[key], 1u);
+}
+
+// ---------------------------------------------------------------------------
+// counting build: place by (cell offset + arrival rank), then restore the
+// original index order inside each cell
+// ---------------------------------------------------------------------------
+
+// perm_tmp[off[key] + rank] = i and key_tmp of that slot = key; off is the
+// local scan of the counts plus its block prefix.
+__global__ __launch_bounds__(kBlock) void k_count_place(const uint32_t* __restrict__ keys,
+                                                        const uint32_t* __restrict__ ranks, uint32_t n,
+                                                        const uint32_t* __restrict__ off_local,
+                                                        const uint32_t* __restrict__ block_sums,
+                                                        uint32_t* __restrict__ perm_tmp,
+                                                        uint32_t* __restrict__ key_tmp) {
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t k = keys[i];
+    const uint32_t slot = off_local[k] + block_sums[k / kScanTile] + ranks[i];
+    if (slot < n) {  // always true for consistent counts; keeps bad ones in bounds
+        perm_tmp[slot] = i;
+        key_tmp[slot] = k;
+    }
+}
+
+// Completes the cell offsets: off[c] += block prefix, and off[ncells] = n.
+__global__ __launch_bounds__(kBlock) void k_count_offsets(uint32_t* __restrict__ off, uint32_t ncells, uint32_t n,
+                                                          const uint32_t* __restrict__ block_sums) {
+    const uint32_t c = blockIdx.x * kBlock + threadIdx.x;
+    if (c < ncells) off[c] += block_sums[c / kScanTile];
+    else if (c == ncells) off[c] = n;
+}
+
+// Slot s of cell c holds element i = perm_tmp[s]; its final slot is
+// off[c] + #{t in cell c : perm_tmp[t] < i}, i.e. the cell's elements in
+// original index order.  Writes the final key, permutation and position.
+template <typename T, int D>
+__global__ __launch_bounds__(kBlock) void k_count_finalize(const uint32_t* __restrict__ perm_tmp,
+                                                           const uint32_t* __restrict__ key_tmp, uint32_t n,
+                                                           const uint32_t* __restrict__ off, uint32_t ncells,
+                                                           const T* __restrict__ x, T* __restrict__ xs,
+                                                           uint32_t* __restrict__ keys_out,
+                                                           uint32_t* __restrict__ perm_out) {
+    constexpr int PITCH = Pitch<D>::value;
+    const uint32_t s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= n) return;
+    const uint32_t c = min(key_tmp[s], ncells - 1u);
+    const uint32_t i = perm_tmp[s];
+    const uint32_t b0 = off[c], b1 = min(off[c + 1], n);
+    uint32_t rank = 0;
+    for (uint32_t t = b0; t < b1; ++t) rank += perm_tmp[t] < i ? 1u : 0u;
+    const uint32_t dest = min(b0 + rank, n - 1u);
+    const uint32_t p = min(i, n - 1u);
+    keys_out[dest] = c;
+    perm_out[dest] = p;
+    VecN<T, PITCH> v;
+#pragma unroll
+    for (int k = 0; k < PITCH; ++k) v.v[k] = k < D ? x[(size_t)p * D + k] : T(0);
+    reinterpret_cast<VecN<T, PITCH>*>(xs)[dest] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -532,7 +597,47 @@ void free_cells_buffers(aboria_cells* c) {
 }
 
 template <typename T, int D>
-aboria_status launch_build(aboria_ctx* ctx, aboria_cells* c, const void* x) {
+aboria_status launch_build_counting(aboria_ctx* ctx, aboria_cells* c, const void* x) {
+    const uint32_t n = (uint32_t)c->n;
+    const uint32_t nc = (uint32_t)c->ncells;
+    const SysParams<T>* sp = reinterpret_cast<const SysParams<T>*>(c->params_dev);
+    hipStream_t st = ctx->stream;
+    // keys_alt = keys in original order, perm_alt = arrival ranks, the work
+    // buffers hold the placed (index, key); counts are made and scanned in off
+    uint32_t* counts = c->off;
+    uint32_t* perm_tmp = reinterpret_cast<uint32_t*>(c->work);
+    uint32_t* key_tmp = reinterpret_cast<uint32_t*>(c->work2);
+    aboria_status s = fill_u32(ctx, counts, 0u, (int64_t)nc + 1);
+    if (s != ABORIA_OK) return s;
+    if (n > 0) {
+        const dim3 grid((n + kBlock - 1) / kBlock);
+        if (c->nsys == 1)
+            hipLaunchKernelGGL((k_cell_ids<T, D, false>), grid, dim3(kBlock), 0, st, (const T*)x, n, sp,
+                               c->sys_part_dev, c->nsys, c->keys_alt, ctx->d_flag, counts, c->perm_alt);
+        else
+            hipLaunchKernelGGL((k_cell_ids<T, D, true>), grid, dim3(kBlock), 0, st, (const T*)x, n, sp,
+                               c->sys_part_dev, c->nsys, c->keys_alt, ctx->d_flag, counts, c->perm_alt);
+    }
+    s = scan_exclusive_u32(ctx, counts, counts, nc, c->block_sums, c->nblock_sums);
+    if (s != ABORIA_OK) return s;
+    if (n > 0) {
+        const dim3 grid((n + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL(k_count_place, grid, dim3(kBlock), 0, st, c->keys_alt, c->perm_alt, n, counts,
+                           c->block_sums, perm_tmp, key_tmp);
+    }
+    hipLaunchKernelGGL(k_count_offsets, dim3((nc + 1 + kBlock - 1) / kBlock), dim3(kBlock), 0, st, c->off, nc, n,
+                       c->block_sums);
+    if (n > 0) {
+        const dim3 grid((n + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL((k_count_finalize<T, D>), grid, dim3(kBlock), 0, st, perm_tmp, key_tmp, n, c->off, nc,
+                           (const T*)x, (T*)c->xs, c->keys, c->perm);
+    }
+    ABORIA_HIP(ctx, hipGetLastError());
+    return ABORIA_OK;
+}
+
+template <typename T, int D>
+aboria_status launch_build_radix(aboria_ctx* ctx, aboria_cells* c, const void* x) {
     const uint32_t n = (uint32_t)c->n;
     const SysParams<T>* sp = reinterpret_cast<const SysParams<T>*>(c->params_dev);
     hipStream_t st = ctx->stream;
@@ -545,10 +650,10 @@ aboria_status launch_build(aboria_ctx* ctx, aboria_cells* c, const void* x) {
         const dim3 grid((n + kBlock - 1) / kBlock);
         if (c->nsys == 1)
             hipLaunchKernelGGL((k_cell_ids<T, D, false>), grid, dim3(kBlock), 0, st, (const T*)x, n, sp,
-                               c->sys_part_dev, c->nsys, k0, ctx->d_flag);
+                               c->sys_part_dev, c->nsys, k0, ctx->d_flag, nullptr, nullptr);
         else
             hipLaunchKernelGGL((k_cell_ids<T, D, true>), grid, dim3(kBlock), 0, st, (const T*)x, n, sp,
-                               c->sys_part_dev, c->nsys, k0, ctx->d_flag);
+                               c->sys_part_dev, c->nsys, k0, ctx->d_flag, nullptr, nullptr);
         const uint32_t ntiles = (uint32_t)c->ntiles;
         const uint32_t radix = 1u << c->digit_bits;
         uint32_t* kout = (k0 == c->keys) ? c->keys_alt : c->keys;
@@ -575,6 +680,12 @@ aboria_status launch_build(aboria_ctx* ctx, aboria_cells* c, const void* x) {
                        direct ? c->hist : nullptr, c->block_sums, (uint32_t)c->ntiles, 1u << c->digit_bits);
     ABORIA_HIP(ctx, hipGetLastError());
     return ABORIA_OK;
+}
+
+template <typename T, int D>
+aboria_status launch_build(aboria_ctx* ctx, aboria_cells* c, const void* x) {
+    return ctx->build_strategy == ABORIA_BUILD_RADIX ? launch_build_radix<T, D>(ctx, c, x)
+                                                     : launch_build_counting<T, D>(ctx, c, x);
 }
 
 template <typename T>
@@ -660,7 +771,8 @@ extern "C" aboria_status aboria_build_cells(aboria_ctx* ctx, aboria_dtype dtype,
             c->digit_bits = c->passes > 0 ? (high + c->passes - 1) / c->passes : 1;
             c->ntiles = (n + kSortTile - 1) / kSortTile;
             c->hist_len = ((int64_t)1 << c->digit_bits) * std::max<int64_t>(c->ntiles, 1);
-            c->nblock_sums = std::max<int64_t>(scan_block_count(c->hist_len), 1);
+            c->nblock_sums = std::max<int64_t>(std::max(scan_block_count(c->hist_len),
+                                                        scan_block_count(total_cells + 1)), 1);
             const size_t tsz = dtype == ABORIA_F32 ? 4 : 8;
             const size_t nn = (size_t)std::max<int64_t>(n, 1);
             struct Alloc { void** p; size_t bytes; } allocs[] = {

@@ -176,6 +176,14 @@ extern "C" aboria_status aboria_graph_destroy(aboria_graph* graph) {
     return ABORIA_OK;
 }
 
+extern "C" aboria_status aboria_set_build_strategy(aboria_ctx* ctx, aboria_build_strategy strategy) {
+    if (!ctx) return ABORIA_ERR_INVALID_ARG;
+    if (strategy != ABORIA_BUILD_RADIX && strategy != ABORIA_BUILD_COUNTING)
+        return fail(ctx, ABORIA_ERR_INVALID_ARG, "unknown build strategy");
+    ctx->build_strategy = strategy;
+    return ABORIA_OK;
+}
+
 extern "C" int32_t aboria_op_ny(aboria_op op, int32_t d) {
     if (d < 1 || d > 3) return -1;
     return op_ny(op, d);

@@ -78,11 +78,16 @@ def make_case(case):
     return g, x, box, prec
 
 
+@pytest.mark.parametrize("strategy", ["counting", "radix"])
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
-def test_cells_and_pairs_bit_exact(ctx, case):
+def test_cells_and_pairs_bit_exact(ctx, case, strategy):
     g, x, box, prec = make_case(case)
-    print("case", case[0], flush=True)
-    cells = A.build_cells(ctx, to_dev(x), [box])
+    print("case", case[0], strategy, flush=True)
+    ctx.set_build_strategy(strategy)
+    try:
+        cells = A.build_cells(ctx, to_dev(x), [box])
+    finally:
+        ctx.set_build_strategy("counting")
     ctx.sync()
     keys, perm, off, xs = cells_state(cells)
     ids, st = oracle.cell_ids(g, x)
@@ -166,12 +171,15 @@ def test_md_square_f64_vs_brute_force(ctx):
     assert abs(y.sum(0)).max().item() < 1e-12 * so.sum()
 
 
-def test_spring_cube_full_size(ctx):
+@pytest.mark.parametrize("strategy", ["counting", "radix"])
+def test_spring_cube_full_size(ctx, strategy):
     w = syn.spring_cube()
     s = w.systems[0]
     g = oracle.grid_of(s)
     x_d = to_dev(s.x)
+    ctx.set_build_strategy(strategy)
     cells = A.build_cells(ctx, x_d, [box_of(s)])
+    ctx.set_build_strategy("counting")
     y = A.pair_sum(ctx, cells, "spring", (1.0,))
     gx, _ = A.pair_sum_backward(ctx, cells, "spring", (1.0,), to_dev(w.extra["gy"]))
     cnt = A.pair_sum(ctx, cells, "count", ())
@@ -239,7 +247,9 @@ def test_dense_small_all_rows(ctx, d, prec):
     assert np.all(np.abs(y.cpu().numpy() - yo) <= tol * so)
 
 
-def test_batch_uneven_systems(ctx):
+@pytest.mark.parametrize("strategy", ["counting", "radix"])
+def test_batch_uneven_systems(ctx, strategy):
+    ctx.set_build_strategy(strategy)
     w = syn.batch_cubes()
     xs_all = np.concatenate([s.x for s in w.systems])
     offsets = np.concatenate([[0], np.cumsum([s.n for s in w.systems])]).tolist()
@@ -271,6 +281,7 @@ def test_batch_uneven_systems(ctx):
             np.testing.assert_array_equal(c_h[lo:hi], co[:, 0])
             go, _, sgo, _ = oracle.pair_sum_backward(g, "soft_sphere", (), s.x, np.ones((s.n, 1)))
             check_close(gx_h[lo:hi], go, sgo, TOL_F32, "batch soft sphere adjoint system %d" % b)
+    ctx.set_build_strategy("counting")
 
 
 # ---------------------------------------------------------------------------
