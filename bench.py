@@ -154,7 +154,7 @@ def main():
     value = pairs / (ms * 1e-3)
     log("step: %.3f ms (events %.3f ms, wall %.3f ms) -> %.3e pairs/s" % (ms, ev_ms, wall_ms, value))
 
-    # ---------------- per-phase breakdown (eager, HIP events on the context stream) -----
+    # ---------------- per-phase breakdown: each phase captured as its own graph ------------
     def timed(fn, reps=20):
         fn()
         torch.cuda.synchronize()
@@ -167,45 +167,47 @@ def main():
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
 
-    t_build = timed(lambda: A.build_cells(ctx, x, [box], cells=cells))
-    ctx.set_build_strategy("radix")
-    t_build_radix = timed(lambda: A.build_cells(ctx, x, [box], cells=cells))
+    def timed_graph(fn, reps=20):
+        """GPU time of fn's kernels, replayed from a graph (no host launch gaps)."""
+        fn()
+        stream.synchronize()
+        A.graph_capture_begin(ctx)
+        fn()
+        g = A.graph_capture_end(ctx)
+        t = timed(lambda: A.graph_launch(ctx, g), reps)
+        g.close()
+        return t
+
+    t_build = timed_graph(lambda: A.build_cells(ctx, x, [box], cells=cells))
     ctx.set_build_strategy("counting")
+    t_build_counting = timed_graph(lambda: A.build_cells(ctx, x, [box], cells=cells))
+    ctx.set_build_strategy("radix")
     A.build_cells(ctx, x, [box], cells=cells)
-    t_fwd = timed(lambda: A.pair_sum(ctx, cells, "spring", (1.0,), y=y))
-    t_bwd = timed(lambda: A.pair_sum_backward(ctx, cells, "spring", (1.0,), gy, gx=gx))
+    t_fwd = timed_graph(lambda: A.pair_sum(ctx, cells, "spring", (1.0,), y=y))
+    t_bwd = timed_graph(lambda: A.pair_sum_backward(ctx, cells, "spring", (1.0,), gy, gx=gx))
     per_variant = {}
     for v in range(A.variant_count()):
         ctx.set_variant(v)
         per_variant[A.variant_name(v)] = {
-            "fwd_ms": timed(lambda: A.pair_sum(ctx, cells, "spring", (1.0,), y=y), reps=5),
-            "bwd_ms": timed(lambda: A.pair_sum_backward(ctx, cells, "spring", (1.0,), gy, gx=gx), reps=5)}
+            "fwd_ms": timed_graph(lambda: A.pair_sum(ctx, cells, "spring", (1.0,), y=y), reps=5),
+            "bwd_ms": timed_graph(lambda: A.pair_sum_backward(ctx, cells, "spring", (1.0,), gy, gx=gx), reps=5)}
     ctx.set_variant(-1)
     ctx.sync()
     log("variants", json.dumps(per_variant))
     ops_fwd = cand * OPS_PER_CANDIDATE + pairs * OPS_PER_PAIR["fwd"]
     ops_bwd = cand * OPS_PER_CANDIDATE + pairs * OPS_PER_PAIR["bwd"]
-    # the adjoint call also gathers gy into cell order (a small copy kernel)
+    # the adjoint call is the gy gather into cell order plus the adjoint kernel
     dominant = "bwd" if t_bwd >= t_fwd else "fwd"
     t_dom = t_bwd if dominant == "bwd" else t_fwd
     ops_dom = ops_bwd if dominant == "bwd" else ops_fwd
     achieved = ops_dom / (t_dom * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": "k_pair_%s<float,3,SPRING>" % dominant, "achieved": achieved,
+    kname = {"fwd": "k_lane_fwd<float,3,SPRING> (forward call)",
+             "bwd": "k_gather_rows<float,3> + k_lane_bwd<float,3,SPRING> (adjoint call)"}[dominant]
+    roofline = {"bound": "alu", "kernel": kname, "achieved": achieved,
                 "peak": VALU_PEAK_TOPS, "unit": "Tops/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
                 "algorithmic_ops_per_launch": ops_dom, "avg_launch_ms": t_dom}
-    # build bytes: x in (12 B), keys+perm through 2 radix passes, offsets, sorted x out (16 B)
-    build_bytes = n * (12 + 4 + 2 * (4 + 4 + 8 + 8) + 4 + 16) + 4 * (int(cells.view().ncells) + 1)
-    breakdown = {"build_ms": t_build, "build_radix_ms": t_build_radix, "fwd_ms": t_fwd, "bwd_ms": t_bwd,
-                 "build_hbm_frac": build_bytes / (t_build * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                 "fwd_pairs_per_s": pairs / ((t_build + t_fwd) * 1e-3),
-                 "fwd_only_pairs_per_s": pairs / (t_fwd * 1e-3),
-                 "fwd_valu_frac": ops_fwd / (t_fwd * 1e-3) / 1e12 / VALU_PEAK_TOPS,
-                 "bwd_valu_frac": ops_bwd / (t_bwd * 1e-3) / 1e12 / VALU_PEAK_TOPS,
-                 "candidates_per_step": cand,
-                 "variant_fwd": A.variant_name(variant_fwd), "variant_bwd": A.variant_name(variant_bwd),
-                 "per_variant": per_variant}
-    log("breakdown", json.dumps(breakdown))
-
+    # build bytes: x in (12 B), keys+perm through the radix passes, sorted x out (16 B), offsets
+    build_bytes = n * (12 + 4 + (4 + 4 + 8 + 8) + (8 + 4 + 4 + 16)) + 4 * (int(cells.view().ncells) + 1)
     # ---------------- other workloads ----------------
     extra = {}
     if not args.no_extra:

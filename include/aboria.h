@@ -172,7 +172,7 @@ aboria_status aboria_cells_view_get(const aboria_cells* cells, aboria_cells_view
  *   COUNTING  a per-cell count with each particle's arrival rank (atomic), a
  *             scan of the counts (the cell offsets), placement, and a per-slot
  *             fix-up that restores original index order inside each cell.
- * The setting applies to later builds on ctx; the default is COUNTING. */
+ * The setting applies to later builds on ctx; the default is RADIX. */
 typedef enum aboria_build_strategy { ABORIA_BUILD_RADIX = 0, ABORIA_BUILD_COUNTING = 1 } aboria_build_strategy;
 aboria_status aboria_set_build_strategy(aboria_ctx* ctx, aboria_build_strategy strategy);
 aboria_status aboria_cells_destroy(aboria_cells* cells);

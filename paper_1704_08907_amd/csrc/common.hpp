@@ -85,7 +85,7 @@ struct aboria_ctx {
     void* scratch = nullptr;         // grow-only scratch for dense partial sums
     size_t scratch_bytes = 0;
     int32_t variant_forced = -1;
-    int32_t build_strategy = ABORIA_BUILD_COUNTING;
+    int32_t build_strategy = ABORIA_BUILD_RADIX;
     std::vector<std::pair<uint64_t, int32_t>> tune_cache;  // (key, variant)
 };
 

@@ -87,7 +87,7 @@ def test_cells_and_pairs_bit_exact(ctx, case, strategy):
     try:
         cells = A.build_cells(ctx, to_dev(x), [box])
     finally:
-        ctx.set_build_strategy("counting")
+        ctx.set_build_strategy("radix")
     ctx.sync()
     keys, perm, off, xs = cells_state(cells)
     ids, st = oracle.cell_ids(g, x)
@@ -179,7 +179,7 @@ def test_spring_cube_full_size(ctx, strategy):
     x_d = to_dev(s.x)
     ctx.set_build_strategy(strategy)
     cells = A.build_cells(ctx, x_d, [box_of(s)])
-    ctx.set_build_strategy("counting")
+    ctx.set_build_strategy("radix")
     y = A.pair_sum(ctx, cells, "spring", (1.0,))
     gx, _ = A.pair_sum_backward(ctx, cells, "spring", (1.0,), to_dev(w.extra["gy"]))
     cnt = A.pair_sum(ctx, cells, "count", ())
@@ -281,7 +281,7 @@ def test_batch_uneven_systems(ctx, strategy):
             np.testing.assert_array_equal(c_h[lo:hi], co[:, 0])
             go, _, sgo, _ = oracle.pair_sum_backward(g, "soft_sphere", (), s.x, np.ones((s.n, 1)))
             check_close(gx_h[lo:hi], go, sgo, TOL_F32, "batch soft sphere adjoint system %d" % b)
-    ctx.set_build_strategy("counting")
+    ctx.set_build_strategy("radix")
 
 
 # ---------------------------------------------------------------------------
