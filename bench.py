@@ -207,7 +207,20 @@ def main():
                 "peak": VALU_PEAK_TOPS, "unit": "Tops/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
                 "algorithmic_ops_per_launch": ops_dom, "avg_launch_ms": t_dom}
     # build bytes: x in (12 B), keys+perm through the radix passes, sorted x out (16 B), offsets
-    build_bytes = n * (12 + 4 + (4 + 4 + 8 + 8) + (8 + 4 + 4 + 16)) + 4 * (int(cells.view().ncells) + 1)
+    # build algorithmic bytes per particle (cell ids 16, one 16-byte pass over the
+    # high key bits, the bucket pass 16 + the gather 28, offsets 4 per cell)
+    build_bytes = n * (16 + 16 + 16 + 28) + 4 * (int(cells.view().ncells) + 1)
+    breakdown = {"build_ms": t_build, "build_counting_ms": t_build_counting, "fwd_ms": t_fwd, "bwd_ms": t_bwd,
+                 "build_hbm_frac": build_bytes / (t_build * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                 "fwd_pairs_per_s": pairs / ((t_build + t_fwd) * 1e-3),
+                 "fwd_only_pairs_per_s": pairs / (t_fwd * 1e-3),
+                 "fwd_valu_frac": ops_fwd / (t_fwd * 1e-3) / 1e12 / VALU_PEAK_TOPS,
+                 "bwd_valu_frac": ops_bwd / (t_bwd * 1e-3) / 1e12 / VALU_PEAK_TOPS,
+                 "candidates_per_step": cand,
+                 "variant_fwd": A.variant_name(variant_fwd), "variant_bwd": A.variant_name(variant_bwd),
+                 "per_variant": per_variant}
+    log("breakdown", json.dumps(breakdown))
+
     # ---------------- other workloads ----------------
     extra = {}
     if not args.no_extra:
