@@ -193,7 +193,7 @@ aboria_status aboria_pair_sum(aboria_ctx* ctx, const aboria_cells* cells, aboria
 /* Adjoint of aboria_pair_sum: given gy[n][ny] = dL/dy, writes gx[n][d] = dL/dx
  * and, for operators with per-particle variables, ga[n][na] = dL/da (ga may be
  * NULL to skip it), all in original order and overwritten.  It gathers over the
- * same cell list (no stored pair list, no atomics):
+ * same cell list, or over its recorded neighbour list (no atomics):
  *   gx_k = sum_{i in P(k)} [ J1(k,i)^T gy_k + J2(i,k)^T gy_i ],
  * J1, J2 the Jacobians of the summand in its first and second position.  The
  * pair set is held fixed (the summands are differentiated where they are
@@ -201,6 +201,30 @@ aboria_status aboria_pair_sum(aboria_ctx* ctx, const aboria_cells* cells, aboria
 aboria_status aboria_pair_sum_backward(aboria_ctx* ctx, const aboria_cells* cells, aboria_op op,
                                        const double* params_host, int32_t nparams, const void* a,
                                        int32_t na, const void* gy, int32_t ny, void* gx, void* ga);
+
+/* ---- recorded neighbour lists ---------------------------------------------------
+ *
+ * Records, for every particle of the cell list, its neighbour set P(i) (the
+ * box search of Section 2.2.2 under the canonical predicate above) in
+ * box-search order, in device memory owned by the cell list: up to `capacity`
+ * entries per particle (0 = chosen from the densest system's density: its mean
+ * neighbour count plus six standard deviations of a Poisson count, plus 8) and
+ * each particle's full count.  Later aboria_pair_sum and
+ * aboria_pair_sum_backward calls on these cells then evaluate recorded
+ * (accepted) pairs only, adding the summands in the same order as the box
+ * search, so their results equal the box-search results bit for bit.  A
+ * particle with more neighbours than the capacity, and every particle after a
+ * rebuild of the cells that was not followed by a new recording (a build
+ * generation kept on the device decides, so graph replays stay consistent),
+ * is summed by the box search instead.  The first call allocates
+ * capacity * n * 4 + n * 4 bytes and cannot be captured; later calls reuse
+ * that memory and can be captured (an explicit capacity above the allocated
+ * one is INVALID_ARG, an automatic one is clamped to it).  Memory is released
+ * with the cells.  Errors: INVALID_ARG for NULL cells, cells of another device
+ * or capacity outside 0..4096; OUT_OF_MEMORY. */
+aboria_status aboria_build_neighbours(aboria_ctx* ctx, aboria_cells* cells, int32_t capacity);
+/* Entries per particle of the latest recorded list (0 if none). */
+int32_t aboria_neighbour_capacity(const aboria_cells* cells);
 
 /* Lists the ordered neighbour pairs (original indices) of the cell list:
  * pair p is (pi[p], pj[p]) for p < min(total, cap), in an unspecified order;
@@ -223,8 +247,9 @@ aboria_status aboria_dense_sum(aboria_ctx* ctx, aboria_dtype dtype, aboria_kerne
 
 /* ---- graphs ------------------------------------------------------------------
  * Captures the calls made on ctx between begin and end into one executable
- * HIP graph (rebuilds with an existing cell list, sums, adjoints and dense sums
- * allocate nothing and can be captured; a first build, aboria_pair_list and
+ * HIP graph (rebuilds with an existing cell list, neighbour-list recordings
+ * after the first, sums, adjoints and dense sums allocate nothing and can be
+ * captured; a first build, a first neighbour list, aboria_pair_list and
  * aboria_sync cannot).  Launch replays it on the context's stream. */
 aboria_status aboria_graph_capture_begin(aboria_ctx* ctx);
 aboria_status aboria_graph_capture_end(aboria_ctx* ctx, aboria_graph** out);

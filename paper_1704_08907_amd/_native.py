@@ -51,7 +51,8 @@ EXPORTS = ["aboria_create", "aboria_destroy", "aboria_set_stream", "aboria_last_
            "aboria_pair_sum_backward", "aboria_pair_list", "aboria_dense_sum",
            "aboria_graph_capture_begin", "aboria_graph_capture_end", "aboria_graph_launch",
            "aboria_graph_destroy", "aboria_autotune", "aboria_variant_count", "aboria_variant_name",
-           "aboria_set_variant", "aboria_op_ny", "aboria_op_na", "aboria_set_build_strategy"]
+           "aboria_set_variant", "aboria_op_ny", "aboria_op_na", "aboria_set_build_strategy",
+           "aboria_build_neighbours", "aboria_neighbour_capacity"]
 
 
 def lib():
@@ -87,6 +88,8 @@ def lib():
             "aboria_op_ny": ([I32, I32], I32),
             "aboria_op_na": ([I32], I32),
             "aboria_set_build_strategy": ([P, I32], I32),
+            "aboria_build_neighbours": ([P, P, I32], I32),
+            "aboria_neighbour_capacity": ([P], I32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -282,6 +285,14 @@ def pair_sum_backward(ctx: Context, cells: Cells, op: str, params, gy: torch.Ten
                                         _ptr(gx), _ptr(ga))
     ctx.check(st, "pair_sum_backward")
     return gx, ga
+
+
+def build_neighbours(ctx: Context, cells: Cells, capacity: int = 0) -> int:
+    """aboria_build_neighbours: records each particle's neighbour set on the
+    cell list (later sums and adjoints on it replay the list); returns the
+    entries kept per particle."""
+    ctx.check(lib().aboria_build_neighbours(ctx.handle, cells.handle, int(capacity)), "build_neighbours")
+    return int(lib().aboria_neighbour_capacity(cells.handle))
 
 
 def pair_list(ctx: Context, cells: Cells):

@@ -1,6 +1,7 @@
 // Autotuner for the neighbour-sum launch: times every work-mapping variant on
 // the caller's cell list with HIP events on the context's stream and caches the
-// fastest per (d, dtype, operator, size bucket, density bucket).
+// fastest per (d, dtype, operator, direction, size bucket, density bucket,
+// batch, neighbour list recorded).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,6 +24,7 @@ uint64_t tune_key(const aboria_cells* c, int32_t op, bool backward) {
     k = k * 64 + (uint64_t)std::min(dens_bucket, 63);
     k = k * 2 + (uint64_t)(c->nsys > 1);
     k = k * 2 + (uint64_t)backward;
+    k = k * 2 + (uint64_t)c->nbr_recorded;
     return k;
 }
 
@@ -31,7 +33,8 @@ int32_t pick_variant(aboria_ctx* ctx, const aboria_cells* c, int32_t op, bool ba
     const uint64_t key = tune_key(c, op, backward);
     for (const auto& kv : ctx->tune_cache)
         if (kv.first == key) return kv.second;
-    return 0;
+    // untuned: replay the recorded neighbour list when there is one
+    return c->nbr_recorded ? list_variant() : 0;
 }
 
 }  // namespace aboria
@@ -74,6 +77,7 @@ extern "C" aboria_status aboria_autotune(aboria_ctx* ctx, const aboria_cells* ce
                             : pair_sum_impl(ctx, cells, op, params_host, nparams, a, na, out_scratch, ny, v);
         };
         for (int32_t v = 0; v < variant_count() && st == ABORIA_OK; ++v) {
+            if (variant_needs_list(v) && !cells->nbr_recorded) continue;
             st = run(v);  // warm-up
             if (st != ABORIA_OK) break;
             std::vector<float> times;

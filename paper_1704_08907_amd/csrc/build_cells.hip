@@ -51,8 +51,11 @@ __global__ __launch_bounds__(kBlock) void k_cell_ids(const T* __restrict__ x, ui
                                                      const SysParams<T>* __restrict__ sp,
                                                      const uint32_t* __restrict__ sys_part, int nsys,
                                                      uint32_t* __restrict__ keys, uint32_t* __restrict__ flag,
-                                                     uint32_t* __restrict__ counts, uint32_t* __restrict__ ranks) {
+                                                     uint32_t* __restrict__ counts, uint32_t* __restrict__ ranks,
+                                                     uint32_t* __restrict__ gen) {
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    // a new build generation: a neighbour list recorded for an older one is stale
+    if (i == 0) gen[0] = gen[0] + 1u;
     int b = 0;
     if (BATCH) {
         // the workgroup's rows are contiguous: one binary search for its first
@@ -587,13 +590,17 @@ void fill_params(const std::vector<GridPlan>& plans, const std::vector<aboria_bo
 
 void free_cells_buffers(aboria_cells* c) {
     void* ptrs[] = {c->params_dev, c->sys_part_dev, c->cell_base_dev, c->keys, c->perm, c->keys_alt,
-                    c->perm_alt, c->off, c->xs, c->work, c->work2, c->hist, c->block_sums};
+                    c->perm_alt, c->off, c->xs, c->work, c->work2, c->hist, c->block_sums,
+                    c->nbr, c->nbr_count, c->gen};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     c->params_dev = nullptr;
     c->sys_part_dev = c->cell_base_dev = c->keys = c->perm = c->keys_alt = c->perm_alt = c->off = nullptr;
     c->hist = c->block_sums = nullptr;
     c->xs = c->work = c->work2 = nullptr;
+    c->nbr = c->nbr_count = c->gen = nullptr;
+    c->nbr_alloc = 0;
+    c->nbr_recorded = false;
 }
 
 template <typename T, int D>
@@ -613,10 +620,10 @@ aboria_status launch_build_counting(aboria_ctx* ctx, aboria_cells* c, const void
         const dim3 grid((n + kBlock - 1) / kBlock);
         if (c->nsys == 1)
             hipLaunchKernelGGL((k_cell_ids<T, D, false>), grid, dim3(kBlock), 0, st, (const T*)x, n, sp,
-                               c->sys_part_dev, c->nsys, c->keys_alt, ctx->d_flag, counts, c->perm_alt);
+                               c->sys_part_dev, c->nsys, c->keys_alt, ctx->d_flag, counts, c->perm_alt, c->gen);
         else
             hipLaunchKernelGGL((k_cell_ids<T, D, true>), grid, dim3(kBlock), 0, st, (const T*)x, n, sp,
-                               c->sys_part_dev, c->nsys, c->keys_alt, ctx->d_flag, counts, c->perm_alt);
+                               c->sys_part_dev, c->nsys, c->keys_alt, ctx->d_flag, counts, c->perm_alt, c->gen);
     }
     s = scan_exclusive_u32(ctx, counts, counts, nc, c->block_sums, c->nblock_sums);
     if (s != ABORIA_OK) return s;
@@ -650,10 +657,10 @@ aboria_status launch_build_radix(aboria_ctx* ctx, aboria_cells* c, const void* x
         const dim3 grid((n + kBlock - 1) / kBlock);
         if (c->nsys == 1)
             hipLaunchKernelGGL((k_cell_ids<T, D, false>), grid, dim3(kBlock), 0, st, (const T*)x, n, sp,
-                               c->sys_part_dev, c->nsys, k0, ctx->d_flag, nullptr, nullptr);
+                               c->sys_part_dev, c->nsys, k0, ctx->d_flag, nullptr, nullptr, c->gen);
         else
             hipLaunchKernelGGL((k_cell_ids<T, D, true>), grid, dim3(kBlock), 0, st, (const T*)x, n, sp,
-                               c->sys_part_dev, c->nsys, k0, ctx->d_flag, nullptr, nullptr);
+                               c->sys_part_dev, c->nsys, k0, ctx->d_flag, nullptr, nullptr, c->gen);
         const uint32_t ntiles = (uint32_t)c->ntiles;
         const uint32_t radix = 1u << c->digit_bits;
         uint32_t* kout = (k0 == c->keys) ? c->keys_alt : c->keys;
@@ -789,6 +796,7 @@ extern "C" aboria_status aboria_build_cells(aboria_ctx* ctx, aboria_dtype dtype,
                 {&c->work2, tsz * 4 * nn},
                 {(void**)&c->hist, sizeof(uint32_t) * (size_t)c->hist_len},
                 {(void**)&c->block_sums, sizeof(uint32_t) * (size_t)c->nblock_sums},
+                {(void**)&c->gen, sizeof(uint32_t) * 2},
             };
             for (auto& a : allocs) {
                 if (hipMalloc(a.p, a.bytes) != hipSuccess) {
@@ -800,8 +808,11 @@ extern "C" aboria_status aboria_build_cells(aboria_ctx* ctx, aboria_dtype dtype,
             }
             std::vector<uint32_t> part((size_t)nsys + 1);
             for (int32_t b = 0; b <= nsys; ++b) part[b] = (uint32_t)off[b];
+            const uint32_t gen0[2] = {0u, 0xFFFFFFFFu};  // build generation, generation of the recorded list
             hipError_t e = hipMemcpyAsync(c->sys_part_dev, part.data(), part.size() * sizeof(uint32_t),
                                           hipMemcpyHostToDevice, ctx->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(c->gen, gen0, sizeof(gen0), hipMemcpyHostToDevice, ctx->stream);
             if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
             if (e != hipSuccess) {
                 free_cells_buffers(c);

@@ -122,6 +122,15 @@ struct aboria_cells {
     int64_t ntiles = 0;
     int64_t hist_len = 0;
     int64_t nblock_sums = 0;
+    // device [2]: generation of the latest build, generation the recorded
+    // neighbour list belongs to (the list is used only while they agree)
+    uint32_t* gen = nullptr;
+    // recorded neighbour list (aboria_build_neighbours)
+    uint32_t* nbr = nullptr;        // [nbr_cap][n] slot of each accepted neighbour, box-search order
+    uint32_t* nbr_count = nullptr;  // [n] neighbours of each slot (may exceed nbr_cap)
+    int64_t nbr_alloc = 0;          // entries per slot allocated in nbr (fixed once allocated)
+    uint32_t nbr_cap = 0;           // entries per slot of the latest recording
+    bool nbr_recorded = false;      // a list has been recorded on these cells
 };
 
 namespace aboria {
@@ -157,6 +166,8 @@ int32_t op_nparams(int32_t op);
 // Neighbour-sum variants (work mappings) selectable by the autotuner.
 int32_t variant_count();
 const char* variant_name(int32_t v);
+bool variant_needs_list(int32_t v);  // replays a recorded neighbour list
+int32_t list_variant();              // the variant that replays the list
 int32_t pick_variant(aboria_ctx* ctx, const aboria_cells* cells, int32_t op, bool backward);
 uint64_t tune_key(const aboria_cells* cells, int32_t op, bool backward);
 

@@ -245,11 +245,12 @@ __device__ __forceinline__ bool pair_test(const T* xj, const T* xi, const T* sh,
 }
 
 // One contiguous slot range [j0, j1) of candidates with one image shift:
-// visit(j, dx, d2, shifted) for the accepted ones.  Two candidates are loaded
-// per iteration so their loads overlap.
+// visit(j, dx, d2, shifted) for the accepted ones, shifted = the lane's shift
+// is nonzero in some dimension.  Two candidates are loaded per iteration so
+// their loads overlap.
 template <typename T, int D, bool SHIFT, typename Visit>
 __device__ __forceinline__ void scan_range(const T* __restrict__ xs, uint32_t j0, uint32_t j1, const T* xi,
-                                           const T* sh, T r2, Visit& visit) {
+                                           const T* sh, T r2, bool shifted, Visit& visit) {
     constexpr int PITCH = Pitch<D>::value;
     const VecN<T, PITCH>* __restrict__ xv = reinterpret_cast<const VecN<T, PITCH>*>(xs);
     uint32_t j = j0;
@@ -257,13 +258,13 @@ __device__ __forceinline__ void scan_range(const T* __restrict__ xs, uint32_t j0
         const VecN<T, PITCH> a = xv[j];
         const VecN<T, PITCH> b = xv[j + 1];
         T dx[D], d2;
-        if (pair_test<T, D, SHIFT>(a.v, xi, sh, r2, dx, &d2)) visit(j, dx, d2, SHIFT);
-        if (pair_test<T, D, SHIFT>(b.v, xi, sh, r2, dx, &d2)) visit(j + 1, dx, d2, SHIFT);
+        if (pair_test<T, D, SHIFT>(a.v, xi, sh, r2, dx, &d2)) visit(j, dx, d2, shifted);
+        if (pair_test<T, D, SHIFT>(b.v, xi, sh, r2, dx, &d2)) visit(j + 1, dx, d2, shifted);
     }
     if (j < j1) {
         const VecN<T, PITCH> a = xv[j];
         T dx[D], d2;
-        if (pair_test<T, D, SHIFT>(a.v, xi, sh, r2, dx, &d2)) visit(j, dx, d2, SHIFT);
+        if (pair_test<T, D, SHIFT>(a.v, xi, sh, r2, dx, &d2)) visit(j, dx, d2, shifted);
     }
 }
 
@@ -336,9 +337,77 @@ __device__ __forceinline__ void neighbour_loop(const SysParams<T>& P, const T* _
             bool lane_shift = false;
 #pragma unroll
             for (int k = 0; k < D; ++k) lane_shift |= sh[k] != T(0);
-            if (__ballot(lane_shift) != 0ull) scan_range<T, D, true>(xs, j0, j1, xi, sh, r2, visit);
-            else scan_range<T, D, false>(xs, j0, j1, xi, sh, r2, visit);
+            if (__ballot(lane_shift) != 0ull) scan_range<T, D, true>(xs, j0, j1, xi, sh, r2, lane_shift, visit);
+            else scan_range<T, D, false>(xs, j0, j1, xi, sh, r2, false, visit);
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// recorded neighbour lists
+// ---------------------------------------------------------------------------
+
+// An entry of a recorded list: the neighbour's slot, with the top bit set when
+// the box search reached it through a nonzero image shift.
+constexpr uint32_t kNbrShift = 0x80000000u;
+constexpr uint32_t kNbrSlot = 0x7FFFFFFFu;
+
+// Displacement and squared distance of a recorded pair, bit for bit those of
+// the box search: dx_k = fl(t_k + s_k) with t_k = fl(x_jk - x_ik).  For a
+// flagged entry s_k is recovered as the minimum image of t_k in each periodic
+// dimension: an accepted pair has |dx_k| < r, and the periodic side is at
+// least twice the guarded cutoff, so exactly one of -L, 0, +L brings t_k
+// within L/2, and it is the shift the search used.
+template <typename T, int D>
+__device__ __forceinline__ T replay_pair(const SysParams<T>& P, const T* xj, const T* xi, bool shifted, T* dx) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) dx[k] = xj[k] - xi[k];
+    if (shifted) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const T L = P.L[k];
+            const T h = T(0.5) * L;
+            const T sk = !P.periodic[k] ? T(0) : (dx[k] > h ? -L : (dx[k] < -h ? L : T(0)));
+            dx[k] = dx[k] + sk;
+        }
+    }
+    T d2 = dx[0] * dx[0];
+    if constexpr (D >= 2) d2 = fma_t(dx[1], dx[1], d2);
+    if constexpr (D >= 3) d2 = fma_t(dx[2], dx[2], d2);
+    return d2;
+}
+
+// Calls visit(j, dx, d2) for the recorded neighbours of slot s in recorded
+// order.  Entry k of slot s is at nbr[k * n + s], so the lanes of a wave read
+// consecutive words.  Two entries per iteration keep two position loads in
+// flight.
+template <typename T, int D, typename Visit>
+__device__ __forceinline__ void replay_list(const SysParams<T>& P, const T* __restrict__ xs,
+                                            const uint32_t* __restrict__ nbr, uint32_t n, uint32_t s, uint32_t cnt,
+                                            const T* xi, Visit& visit) {
+    constexpr int PITCH = Pitch<D>::value;
+    const VecN<T, PITCH>* __restrict__ xv = reinterpret_cast<const VecN<T, PITCH>*>(xs);
+    const uint32_t* p = nbr + s;
+    const size_t stride = (size_t)n;
+    uint32_t k = 0;
+    for (; k + 1 < cnt; k += 2) {
+        const uint32_t e0 = p[0];
+        const uint32_t e1 = p[stride];
+        p += 2 * stride;
+        const VecN<T, PITCH> a = xv[e0 & kNbrSlot];
+        const VecN<T, PITCH> b = xv[e1 & kNbrSlot];
+        T dx[D];
+        T d2 = replay_pair<T, D>(P, a.v, xi, (e0 & kNbrShift) != 0u, dx);
+        visit(e0 & kNbrSlot, dx, d2);
+        d2 = replay_pair<T, D>(P, b.v, xi, (e1 & kNbrShift) != 0u, dx);
+        visit(e1 & kNbrSlot, dx, d2);
+    }
+    if (k < cnt) {
+        const uint32_t e0 = p[0];
+        const VecN<T, PITCH> a = xv[e0 & kNbrSlot];
+        T dx[D];
+        const T d2 = replay_pair<T, D>(P, a.v, xi, (e0 & kNbrShift) != 0u, dx);
+        visit(e0 & kNbrSlot, dx, d2);
     }
 }
 
@@ -405,6 +474,14 @@ void launch_lane_fwd(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q,
 template <typename T, int D, int OP, bool BATCH>
 void launch_lane_bwd(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, const T* gy_s, T* gx,
                      T* ga, int block, bool compact);
+
+// Forward / adjoint over the cell list's recorded neighbour list (a particle
+// with more neighbours than the list holds is summed by the box search).
+template <typename T, int D, int OP, bool BATCH>
+void launch_nbr_fwd(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, T* y);
+template <typename T, int D, int OP, bool BATCH>
+void launch_nbr_bwd(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, const T* gy_s, T* gx,
+                    T* ga);
 
 // Cell-group forward / adjoint; rounds = 1 keeps natural cell order, 8 ranks
 // 64-cell tiles by (wrap, occupancy).

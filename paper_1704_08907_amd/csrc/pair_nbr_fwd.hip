@@ -1,0 +1,66 @@
+// Neighbour-sum forward over a recorded neighbour list: one lane per particle
+// in cell order walks its recorded neighbours and evaluates the summand of
+// each (accepted pairs only).  The summands are added in box-search order, so
+// the result equals the box-search forward bit for bit.  A particle whose list
+// overflowed, or every particle when the list belongs to an older build, is
+// summed by the box search.
+#include "pair_common.hpp"
+
+namespace aboria {
+
+template <typename T, int D, int OP, bool BATCH>
+__global__ __launch_bounds__(256) void k_nbr_fwd(const T* __restrict__ xs, const uint32_t* __restrict__ off,
+                                                 const uint32_t* __restrict__ perm, uint32_t n,
+                                                 const SysParams<T>* __restrict__ sp,
+                                                 const uint32_t* __restrict__ sys_part, int nsys,
+                                                 const uint32_t* __restrict__ nbr,
+                                                 const uint32_t* __restrict__ nbr_count, uint32_t cap,
+                                                 const uint32_t* __restrict__ gen, const T* __restrict__ a_s,
+                                                 OpArgs<T> q, T* __restrict__ y) {
+    using Op = PairOp<T, D, OP>;
+    constexpr int NY = Op::NY;
+    const uint32_t first = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x;
+    const uint32_t s = first + threadIdx.x;
+    const int b = system_of_row<BATCH>(sys_part, nsys, first, s);
+    if (s >= n) return;
+    const SysParams<T> P = sp[b];
+    T xi[D];
+    load_point<T, D>(xs, s, xi);
+    const T ai = OpShape<OP, D>::NA ? a_s[s] : T(0);
+    T acc[NY];
+#pragma unroll
+    for (int k = 0; k < NY; ++k) acc[k] = T(0);
+    const T r = P.r;
+    const uint32_t cnt = nbr_count[s];
+    if (gen[0] == gen[1] && cnt <= cap) {
+        auto visit = [&](uint32_t j, const T* dx, T d2) {
+            const T aj = OpShape<OP, D>::NA ? a_s[j] : T(0);
+            Op::fwd(q, r, dx, d2, ai, aj, acc);
+        };
+        replay_list<T, D>(P, xs, nbr, n, s, cnt, xi, visit);
+    } else {
+        auto visit = [&](uint32_t j, const T* dx, T d2, bool) {
+            const T aj = OpShape<OP, D>::NA ? a_s[j] : T(0);
+            Op::fwd(q, r, dx, d2, ai, aj, acc);
+        };
+        neighbour_loop<T, D>(P, xs, off, n, xi, visit);
+    }
+    const uint32_t o = perm[s];
+#pragma unroll
+    for (int k = 0; k < NY; ++k) y[(size_t)o * NY + k] = acc[k];
+}
+
+template <typename T, int D, int OP, bool BATCH>
+void launch_nbr_fwd(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, T* y) {
+    const uint32_t n = (uint32_t)c->n;
+    hipLaunchKernelGGL((k_nbr_fwd<T, D, OP, BATCH>), dim3((n + 255) / 256), dim3(256), 0, ctx->stream,
+                       (const T*)c->xs, c->off, c->perm, n, reinterpret_cast<const SysParams<T>*>(c->params_dev),
+                       c->sys_part_dev, c->nsys, c->nbr, c->nbr_count, c->nbr_cap, c->gen, a_s, q, y);
+}
+
+#define ABORIA_INST(T, D, OP, BATCH) \
+    template void launch_nbr_fwd<T, D, OP, BATCH>(aboria_ctx*, const aboria_cells*, const OpArgs<T>&, const T*, T*);
+ABORIA_FOR_EACH_PAIR_INSTANCE(ABORIA_INST)
+#undef ABORIA_INST
+
+}  // namespace aboria

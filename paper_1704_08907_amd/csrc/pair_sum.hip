@@ -82,7 +82,7 @@ aboria_status gather(aboria_ctx* ctx, const aboria_cells* c, const void* src, in
 
 // Work-mapping variants of the neighbour sums.
 struct Variant {
-    int kind;      // 0 = lane per particle, 1 = cell group
+    int kind;      // 0 = lane per particle, 1 = cell group, 2 = recorded neighbour list
     int block;     // threads per workgroup (lane mapping)
     bool compact;  // adjoint lists accepted pairs before evaluating them (lane mapping)
     int rounds;    // cell group: 1 = natural cell order, 8 = 64-cell tiles ranked by occupancy
@@ -96,20 +96,23 @@ const Variant kVariants[] = {
     {0, 512, true, 0, "lane per particle, 256-thread workgroups, adjoint through a per-wave queue of accepted pairs"},
     {1, 128, false, 1, "cell group of 16 lanes per home cell, cells in natural order"},
     {1, 128, false, 8, "cell group of 16 lanes per home cell, 64-cell tiles ranked by occupancy"},
+    {2, 256, false, 0, "lane per particle over the recorded neighbour list (accepted pairs only)"},
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 template <typename T, int D, int OP, bool BATCH>
 void launch_fwd_variant(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, T* y,
                         const Variant& v) {
-    if (v.kind == 1) launch_cells_fwd<T, D, OP, BATCH>(ctx, c, q, a_s, y, v.rounds);
+    if (v.kind == 2) launch_nbr_fwd<T, D, OP, BATCH>(ctx, c, q, a_s, y);
+    else if (v.kind == 1) launch_cells_fwd<T, D, OP, BATCH>(ctx, c, q, a_s, y, v.rounds);
     else launch_lane_fwd<T, D, OP, BATCH>(ctx, c, q, a_s, y, v.block > 256 ? 256 : v.block);
 }
 
 template <typename T, int D, int OP, bool BATCH>
 void launch_bwd_variant(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, const T* gy_s,
                         T* gx, T* ga, const Variant& v) {
-    if (v.kind == 1) launch_cells_bwd<T, D, OP, BATCH>(ctx, c, q, a_s, gy_s, gx, ga, v.rounds);
+    if (v.kind == 2) launch_nbr_bwd<T, D, OP, BATCH>(ctx, c, q, a_s, gy_s, gx, ga);
+    else if (v.kind == 1) launch_cells_bwd<T, D, OP, BATCH>(ctx, c, q, a_s, gy_s, gx, ga, v.rounds);
     else launch_lane_bwd<T, D, OP, BATCH>(ctx, c, q, a_s, gy_s, gx, ga, v.block, v.compact);
 }
 
@@ -173,16 +176,31 @@ aboria_status validate(aboria_ctx* ctx, const aboria_cells* c, int op, const dou
     return ABORIA_OK;
 }
 
+aboria_status check_variant(aboria_ctx* ctx, const aboria_cells* c, int variant) {
+    if (variant_needs_list(variant) && !c->nbr_recorded)
+        return fail(ctx, ABORIA_ERR_INVALID_ARG, "the variant needs a neighbour list recorded on these cells");
+    return ABORIA_OK;
+}
+
 }  // namespace
 
 int32_t variant_count() { return kNumVariants; }
 
 const char* variant_name(int32_t v) { return (v >= 0 && v < kNumVariants) ? kVariants[v].name : ""; }
 
+bool variant_needs_list(int32_t v) { return v >= 0 && v < kNumVariants && kVariants[v].kind == 2; }
+
+int32_t list_variant() {
+    for (int32_t v = 0; v < kNumVariants; ++v)
+        if (kVariants[v].kind == 2) return v;
+    return 0;
+}
+
 aboria_status pair_sum_impl(aboria_ctx* ctx, const aboria_cells* c, int32_t op, const double* params,
                             int32_t nparams, const void* a, int32_t na, void* y, int32_t ny, int32_t variant) {
     aboria_status st = validate(ctx, c, op, params, nparams, a, na, ny);
     if (st != ABORIA_OK) return st;
+    if ((st = check_variant(ctx, c, variant)) != ABORIA_OK) return st;
     if (c->n > 0 && !y) return fail(ctx, ABORIA_ERR_INVALID_ARG, "y is NULL");
     const size_t tsz = c->dtype == ABORIA_F32 ? 4 : 8;
     if (overlaps(y, tsz * ny * c->n, a, tsz * na * c->n))
@@ -219,6 +237,7 @@ aboria_status pair_bwd_impl(aboria_ctx* ctx, const aboria_cells* c, int32_t op, 
                             void* ga, int32_t variant) {
     aboria_status st = validate(ctx, c, op, params, nparams, a, na, ny);
     if (st != ABORIA_OK) return st;
+    if ((st = check_variant(ctx, c, variant)) != ABORIA_OK) return st;
     if (c->n > 0 && (!gy || !gx)) return fail(ctx, ABORIA_ERR_INVALID_ARG, "gy and gx are required");
     const size_t tsz = c->dtype == ABORIA_F32 ? 4 : 8;
     const size_t nb = (size_t)c->n;

@@ -396,6 +396,7 @@ def test_every_variant_matches_oracle_and_is_deterministic(ctx, op, params):
     ny = A.op_ny(op, 3)
     gy = rng.normal(s.n * ny).astype(np.float32).reshape(s.n, ny)
     cells = A.build_cells(ctx, to_dev(s.x), [box_of(s)])
+    A.build_neighbours(ctx, cells)  # the list-replay variant needs it
     a_d = to_dev(a) if a is not None else None
     gy_d = to_dev(gy)
     yo, so = oracle.pair_sum(g, op, params, s.x, a=a)
