@@ -74,6 +74,7 @@ def lib():
                                  C.c_double, P]
         L.or_dense_gauss.argtypes = [C.c_int32, C.c_int64, P, C.c_int64, P, P, C.c_double,
                                      C.c_int64, P, P, P]
+        L.or_md_step.argtypes = [C.POINTER(Grid), C.c_int32, C.c_double, C.c_double, C.c_int64, P, P, P]
         L.or_tie_band.argtypes = [C.POINTER(Grid), C.c_int64, P]
         L.or_tie_band.restype = C.c_int64
         L.or_op_ny.argtypes = [C.c_int32, C.c_int32]
@@ -168,6 +169,21 @@ def pair_sum(g: Grid, op: str, params, x, a=None, rows=None, route=ROUTE_CELLS):
     if st != OK:
         raise OracleError(st, "pair_sum")
     return y, sc
+
+
+def md_step(g: Grid, c: float, dt: float, x, v, route=ROUTE_CELLS):
+    """One time step of the Section 3 example in float64: returns (x_new, v_new, scale_v).
+
+    v_new = v + dt (c S), S_i = sum_j -exp(-|dx|) dx/|dx| over the neighbours;
+    x_new = x + dt v_new wrapped into the box in periodic dimensions."""
+    x = np.array(_f64(x), dtype=np.float64, copy=True, order="C")
+    v = np.array(_f64(v), dtype=np.float64, copy=True, order="C")
+    n = x.shape[0]
+    sc = np.zeros(max(n, 1))
+    st = lib().or_md_step(C.byref(g), route, float(c), float(dt), n, _ptr(x), _ptr(v), _ptr(sc))
+    if st != OK:
+        raise OracleError(st, "md_step")
+    return x, v, sc[:n]
 
 
 def pair_sum_backward(g: Grid, op: str, params, x, gy, a=None, rows=None, route=ROUTE_CELLS):

@@ -26,6 +26,10 @@
  *     of the listing excludes j = i and coincident points.
  *   - The dense global kernel sum of the RBF / Gaussian-process methods
  *     (Section 1 and Section 1.1): y_i = sum_j K(x_i, x_j) w_j over all j.
+ *   - One time step of the Section 3 molecular-dynamics example: the
+ *     velocity-update listing v_i += c sum_j (-exp(-|dx|) dx/|dx|) (eq. (1) in
+ *     eq. (2)), then the position-update listing x_i += v_i (eq. (3)), with the
+ *     step dt = 1 of the paper kept as a parameter.
  *
  * Readings the paper leaves open (each listed in the design notes):
  *   R1 cell count per dimension: n = floor(L/r), then decreased while n > 1 and
@@ -52,6 +56,11 @@
  *      cancels near the cutoff (k (r - s) as s -> r) cannot be evaluated in
  *      float32 more accurately than its distance is rounded, so its own
  *      magnitude alone is not a usable scale.
+ *   R7 the periodic domain of the time step: after x += dt v, a coordinate at
+ *      or above hi moves down by L, one below lo moves up by L (one image: a
+ *      step moves a particle less than a box side), and a result that rounds
+ *      onto hi becomes lo, so positions stay in the half-open box [lo, hi).
+ *      Non-periodic coordinates are not wrapped.
  */
 #include <math.h>
 #include <stdint.h>
@@ -832,4 +841,42 @@ int64_t or_tie_band(const or_grid* g, int64_t n, const double* x) {
     }
     free_linked(&lc);
     return diff;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One step of the Section 3 example (eqs. (1)-(3) and the two update        */
+/* listings), in the paper's order: S_i = sum_j -exp(-|dx_ij|) dx_ij/|dx_ij| */
+/* over the box search (the force of eq. (1) without its constant), then     */
+/* v_i += dt (c S_i), then x_i += dt v_i with the new velocity, then the     */
+/* periodic wrap of reading R7.  x and v are [n][d], overwritten; x must hold */
+/* P-rounded positions inside the box.  scale_v[i] (may be NULL) is the       */
+/* row's error scale of c S_i (reading R6 applied to the force).             */
+/* ------------------------------------------------------------------------ */
+
+int or_md_step(const or_grid* g, int32_t route, double c, double dt, int64_t n, double* x, double* v,
+               double* scale_v) {
+    int d = g->d;
+    double one[4] = {1.0, 0.0, 0.0, 0.0};
+    double* S = (double*)calloc((size_t)(n > 0 ? n : 1) * (size_t)d, sizeof(double));
+    double* sc = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    if (!S || !sc) { free(S); free(sc); return OR_ERR_NOMEM; }
+    int st = or_pair_sum(g, route, OR_OP_EXP_FORCE, one, n, x, NULL, 0, NULL, S, sc);
+    if (st != OR_OK) { free(S); free(sc); return st; }
+    for (int64_t i = 0; i < n; ++i) {
+        for (int k = 0; k < d; ++k) {
+            double vk = v[i * d + k] + dt * (c * S[i * d + k]);
+            double xk = x[i * d + k] + dt * vk;
+            if (g->periodic[k]) {
+                if (xk >= g->hi[k]) xk -= g->L[k];
+                else if (xk < g->lo[k]) xk += g->L[k];
+                if (xk >= g->hi[k]) xk = g->lo[k];
+            }
+            v[i * d + k] = vk;
+            x[i * d + k] = xk;
+        }
+        if (scale_v) scale_v[i] = fabs(c) * sc[i];
+    }
+    free(S);
+    free(sc);
+    return OR_OK;
 }

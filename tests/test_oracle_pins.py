@@ -388,3 +388,62 @@ def test_rows_subset_matches_full_and_tie_band_is_small():
     np.testing.assert_allclose(yb, y[rows], rtol=0, atol=1e-12)
     np.testing.assert_allclose(scb, sc[rows], rtol=1e-12)
     assert 0 <= oracle.tie_band(g, s.x) < 20
+
+
+# --------------------------------------------------------------------------
+# the Section 3 time step (eqs. (1)-(3), velocity and position updates)
+# --------------------------------------------------------------------------
+
+def unit_square(r, prec="f64"):
+    return oracle.grid(2, [0.0, 0.0], [1.0, 1.0], [1, 1], r, prec)
+
+
+@pytest.mark.parametrize("dt", [1.0, 0.5])
+def test_md_step_two_particles_closed_form(dt):
+    # dx_12 = r_2 - r_1 = (d, 0): f_12 = -c e^{-d} (1, 0) pushes particle 1 towards -x;
+    # the new velocity (not the old one) moves the position
+    c, d, r = 0.3, 0.04, 0.1
+    x = np.array([[0.30, 0.50], [0.30 + d, 0.50]])
+    v = np.array([[0.01, -0.02], [0.0, 0.03]])
+    xn, vn, _ = oracle.md_step(unit_square(r), c, dt, x, v)
+    f = c * math.exp(-d)
+    v_ref = v + dt * np.array([[-f, 0.0], [f, 0.0]])
+    np.testing.assert_allclose(vn, v_ref, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(xn, x + dt * v_ref, rtol=0, atol=1e-15)
+
+
+def test_md_step_pair_across_the_periodic_boundary():
+    # the shortest vector from 1 to 2 crosses x = 0: dx = (-0.02, 0), so 1 is pushed to +x
+    c = 0.5
+    x = np.array([[0.01, 0.40], [0.99, 0.40], [0.50, 0.90]])
+    v = np.zeros((3, 2))
+    xn, vn, _ = oracle.md_step(unit_square(0.1), c, 1.0, x, v)
+    f = c * math.exp(-0.02)
+    np.testing.assert_allclose(vn, [[f, 0.0], [-f, 0.0], [0.0, 0.0]], rtol=1e-12, atol=1e-15)
+    # particle 2 moves to 0.99 - f = 0.68...: inside the box, no wrap
+    np.testing.assert_allclose(xn[1], [0.99 - f, 0.40], rtol=0, atol=1e-15)
+
+
+def test_md_step_free_flight_wraps_into_the_box():
+    x = np.array([[0.999, 0.2], [0.5, 0.0], [0.25, 0.75]])
+    v = np.array([[0.002, -0.3], [-0.5, -0.25], [0.0, 0.25]])
+    xn, vn, _ = oracle.md_step(unit_square(0.05), 0.0, 1.0, x, v)
+    np.testing.assert_array_equal(vn, v)
+    np.testing.assert_allclose(xn, [[0.001, 0.9], [0.0, 0.75], [0.25, 0.0]], rtol=0, atol=1e-15)
+    assert np.all(xn >= 0.0) and np.all(xn < 1.0)
+
+
+def test_md_step_conserves_momentum_and_routes_agree():
+    # f_ij = -f_ji: the forces of a step sum to zero, so sum_i v_i is unchanged
+    n = 3000
+    rng = syn.SplitMix64(404)
+    x = syn.uniform_positions(rng, n, [0.0, 0.0], [1.0, 1.0], "f64")
+    v = 1e-3 * rng.normal(2 * n).reshape(n, 2)
+    g = unit_square(math.sqrt(3.0 / 300))  # ~30 neighbours so the forces are not sparse
+    xb, vb, _ = oracle.md_step(g, 1e-2, 1.0, x, v, route=oracle.ROUTE_BRUTE)
+    xc, vc, sc = oracle.md_step(g, 1e-2, 1.0, x, v, route=oracle.ROUTE_CELLS)
+    np.testing.assert_allclose(vc, vb, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(xc, xb, rtol=0, atol=1e-15)
+    dv = (vc - v).sum(axis=0)
+    assert np.all(np.abs(dv) < 1e-12 * sc.sum())
+    assert np.abs(vc - v).max() > 1e-4  # the forces are not all zero
