@@ -380,6 +380,29 @@ def main():
         extra["batch_512_systems"] = {"ms": m5, "particles": int(x5.shape[0]), "pairs": p5,
                                       "pairs_per_s": p5 / (m5 * 1e-3),
                                       "ratio_to_single_cube": (p5 / m5) / (pairs / ms), "step_forms_ms": t5}
+        # the Section 3 example: N = 2^20 in the periodic unit square, r = sqrt(3/N), c = 1e-3, dt = 1,
+        # float64; a step is a cell rebuild, the exp-force sum and the Euler update; 10 steps per graph
+        w6 = syn.md_paper()
+        s6 = w6.systems[0]
+        box6 = A.BoxSpec(2, s6.lo, s6.hi, s6.periodic, s6.cutoff)
+        x6 = torch.from_numpy(s6.x).to(dev)
+        v6 = torch.from_numpy(w6.extra["v"]).to(dev)
+        f6 = torch.empty_like(x6)
+        c6 = A.build_cells(ctx, x6, [box6])
+        p6 = int(A.pair_sum(ctx, c6, "count", ()).sum().item())
+        A.autotune(ctx, c6, "exp_force", w6.params)
+
+        def md_steps(k=10):
+            for _ in range(k):
+                A.build_cells(ctx, x6, [box6], cells=c6)
+                A.pair_sum(ctx, c6, "exp_force", w6.params, y=f6)
+                A.integrate(ctx, c6, w6.extra["dt"], f6, x6, v6)
+
+        t6 = timed_graph(md_steps, reps=5) / 10
+        ctx.sync()
+        extra["md_paper_n1048576_d2_f64"] = {"ms_per_step": t6, "steps_per_s": 1e3 / t6, "pairs": p6,
+                                             "pairs_per_s": p6 / (t6 * 1e-3),
+                                             "particle_updates_per_s": s6.n / (t6 * 1e-3)}
         log("extra", json.dumps(extra))
 
     # ---------------- CPU baseline: the oracle on the host ----------------

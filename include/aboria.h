@@ -202,6 +202,23 @@ aboria_status aboria_pair_sum_backward(aboria_ctx* ctx, const aboria_cells* cell
                                        const double* params_host, int32_t nparams, const void* a,
                                        int32_t na, const void* gy, int32_t ny, void* gx, void* ga);
 
+/* ---- time step (Section 3: eqs. (2)-(3), the velocity and position updates) ----
+ *
+ * Semi-implicit Euler step on the caller's arrays in original order, all
+ * [n][d] in the cell list's dtype and overwritten in place (x, v):
+ *   v_i <- v_i + dt f_i,  then  x_i <- x_i + dt v_i (with the new v_i),
+ * where f is typically aboria_pair_sum of the exp-force operator (eq. (1), c
+ * as its parameter) on cells built from the same x.  In periodic dimensions a
+ * coordinate at or above hi moves down by the side L and one below lo moves up
+ * by L (one image: a step must move a particle less than a side), and a result
+ * that rounds onto hi becomes lo; non-periodic coordinates are not wrapped (a
+ * particle that leaves the box is reported by the next build's domain check).
+ * The cell list supplies n, d, dtype and each system's box; it is not changed
+ * (rebuild it from the new x before the next force sum).  Errors: INVALID_ARG
+ * for NULL or overlapping arrays, a non-finite dt or cells of another device. */
+aboria_status aboria_integrate(aboria_ctx* ctx, const aboria_cells* cells, double dt, const void* f, void* x,
+                               void* v);
+
 /* ---- recorded neighbour lists ---------------------------------------------------
  *
  * Records, for every particle of the cell list, its neighbour set P(i) (the

@@ -2,14 +2,15 @@
 
 The hot path of the particle-based methods of Robinson & Bruna (arXiv
 1704.08907): a uniform cell list (Section 2.2.1), radius-limited neighbour sums
-by box search over it (Section 2.2.2, Section 3 eq. (1)), their adjoint, and the
-dense kernel sum of the RBF / Gaussian-process methods (Section 1).  The work is
+by box search over it (Section 2.2.2, Section 3 eq. (1)), their adjoint, the
+time step of the Section 3 example (eqs. (2)-(3)), and the dense kernel sum of
+the RBF / Gaussian-process methods (Section 1).  The work is
 done by the HIP library ``libaboria_mi355x.so``; this package binds it.
 """
 from ._native import (AboriaError, BoxSpec, Cells, Context, Graph, autotune, build_cells, build_neighbours,
-                      dense_sum, graph_capture_begin, graph_capture_end, graph_launch, lib, op_na, op_ny,
-                      pair_list, pair_sum, pair_sum_backward, variant_count, variant_name)
+                      dense_sum, graph_capture_begin, graph_capture_end, graph_launch, integrate, lib, op_na,
+                      op_ny, pair_list, pair_sum, pair_sum_backward, variant_count, variant_name)
 
 __all__ = ["AboriaError", "BoxSpec", "Cells", "Context", "Graph", "autotune", "build_cells", "build_neighbours",
-           "dense_sum", "graph_capture_begin", "graph_capture_end", "graph_launch", "lib", "op_na", "op_ny",
-           "pair_list", "pair_sum", "pair_sum_backward", "variant_count", "variant_name"]
+           "dense_sum", "graph_capture_begin", "graph_capture_end", "graph_launch", "integrate", "lib", "op_na",
+           "op_ny", "pair_list", "pair_sum", "pair_sum_backward", "variant_count", "variant_name"]

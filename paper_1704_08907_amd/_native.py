@@ -52,7 +52,7 @@ EXPORTS = ["aboria_create", "aboria_destroy", "aboria_set_stream", "aboria_last_
            "aboria_graph_capture_begin", "aboria_graph_capture_end", "aboria_graph_launch",
            "aboria_graph_destroy", "aboria_autotune", "aboria_variant_count", "aboria_variant_name",
            "aboria_set_variant", "aboria_op_ny", "aboria_op_na", "aboria_set_build_strategy",
-           "aboria_build_neighbours", "aboria_neighbour_capacity"]
+           "aboria_build_neighbours", "aboria_neighbour_capacity", "aboria_integrate"]
 
 
 def lib():
@@ -90,6 +90,7 @@ def lib():
             "aboria_set_build_strategy": ([P, I32], I32),
             "aboria_build_neighbours": ([P, P, I32], I32),
             "aboria_neighbour_capacity": ([P], I32),
+            "aboria_integrate": ([P, P, C.c_double, P, P, P], I32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -293,6 +294,16 @@ def build_neighbours(ctx: Context, cells: Cells, capacity: int = 0) -> int:
     entries kept per particle."""
     ctx.check(lib().aboria_build_neighbours(ctx.handle, cells.handle, int(capacity)), "build_neighbours")
     return int(lib().aboria_neighbour_capacity(cells.handle))
+
+
+def integrate(ctx: Context, cells: Cells, dt: float, f: torch.Tensor, x: torch.Tensor, v: torch.Tensor):
+    """aboria_integrate: v += dt f, then x += dt v, wrapped into the periodic box (in place)."""
+    for t, name in ((f, "f"), (x, "x"), (v, "v")):
+        _check_dev(t, name, cells.dtype)
+        if tuple(t.shape) != (cells.n, cells.d):
+            raise ValueError("%s must be [n][d]" % name)
+    ctx.check(lib().aboria_integrate(ctx.handle, cells.handle, float(dt), _ptr(f), _ptr(x), _ptr(v)), "integrate")
+    return x, v
 
 
 def pair_list(ctx: Context, cells: Cells):

@@ -194,3 +194,16 @@ def batch_cubes(nsys: int = 512, seed_offset: int = 5, nmin: int = 256,
     ntot = w.n
     w.extra["gy"] = np.ones((ntot, 1), dtype=np.float32)
     return w
+
+
+def md_paper(n: int = 1 << 20, seed_offset: int = 6, precision: str = "f64") -> Workload:
+    """The Section 3 example: n points uniform in the periodic unit square,
+    cutoff sqrt(3/n) (about 3 pi ~ 9.4 neighbours for any n), exp force with
+    c = 1e-3, step dt = 1, velocities starting at zero, float64."""
+    rng = SplitMix64(SEED_BASE + seed_offset)
+    x = uniform_positions(rng, n, [0.0, 0.0], [1.0, 1.0], precision)
+    sys = System(2, [0.0, 0.0], [1.0, 1.0], [1, 1], math.sqrt(3.0 / n), x, precision)
+    w = Workload("md_paper_n%d_d2_%s" % (n, precision), precision, [sys], "exp_force", (1e-3,))
+    w.extra["v"] = np.zeros((n, 2), dtype=np_dtype(precision))
+    w.extra["dt"] = 1.0
+    return w

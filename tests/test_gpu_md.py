@@ -1,0 +1,177 @@
+"""GPU parity of the Section 3 time step: the exp-force sum (eq. (1)) and the
+semi-implicit Euler update with periodic wrap (eqs. (2)-(3)), through the C-ABI,
+against the oracle's step.  Positions are compared as periodic differences (a
+coordinate that rounds across the box edge on one side is the same point)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1704_08907_amd as A
+from paper_1704_08907_amd import synthetic as syn
+from _parity import TOL_F32, TOL_F64, box_of, dev, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = A.Context(0)
+    yield c
+    c.close()
+
+
+def gpu_step(ctx, cells, boxes, x, v, c, dt, offsets=None, f=None):
+    A.build_cells(ctx, x, boxes, offsets, cells=cells)
+    f = A.pair_sum(ctx, cells, "exp_force", (c,), y=f)
+    A.integrate(ctx, cells, dt, f, x, v)
+    return f
+
+
+def periodic_diff(a, b, L=1.0):
+    d = np.asarray(a, dtype=np.float64) - np.asarray(b, dtype=np.float64)
+    return d - L * np.round(d / L)
+
+
+def check_state(x, v, xo, vo, v0, dt, scale_v, tol, what):
+    vv = v.cpu().numpy().astype(np.float64)
+    bound_v = tol * (np.abs(v0).max(axis=1) + dt * scale_v + 1e-300)
+    err_v = np.abs(vv - vo).max(axis=1)
+    assert np.all(err_v <= bound_v), "%s: v off by %g at row %d" % (what, err_v.max(), int(np.argmax(err_v - bound_v)))
+    err_x = np.abs(periodic_diff(x.cpu().numpy(), xo)).max(axis=1)
+    bound_x = tol * (1.0 + dt * np.abs(vo).max(axis=1)) + dt * bound_v
+    assert np.all(err_x <= bound_x), "%s: x off by %g" % (what, err_x.max())
+
+
+@pytest.mark.parametrize("n,prec,vel", [(1000, "f64", "zero"), (1000, "f64", "random"),
+                                        (50000, "f64", "random"), (50000, "f32", "random")])
+def test_one_step_matches_oracle(ctx, n, prec, vel):
+    w = syn.md_paper(n, precision=prec)
+    s = w.systems[0]
+    c = w.params[0]
+    print("md step", n, prec, vel, flush=True)
+    rng = syn.SplitMix64(77)
+    v0 = np.zeros((n, 2)) if vel == "zero" else 2e-3 * rng.normal(2 * n).reshape(n, 2)
+    v0 = v0.astype(s.x.dtype)
+    x, v = to_dev(s.x), to_dev(v0)
+    cells = A.build_cells(ctx, x, [box_of(s)])
+    gpu_step(ctx, cells, [box_of(s)], x, v, c, 1.0)
+    ctx.sync()
+    g = oracle.grid_of(s)
+    xo, vo, sv = oracle.md_step(g, c, 1.0, s.x, v0)
+    check_state(x, v, xo, vo, v0.astype(np.float64), 1.0, sv, TOL_F64 if prec == "f64" else TOL_F32,
+                "step %s n=%d" % (prec, n))
+    assert np.all(x.cpu().numpy() >= 0.0) and np.all(x.cpu().numpy() < 1.0)
+
+
+def test_trajectory_with_the_paper_parameters_matches_oracle(ctx):
+    # N = 1000, r = sqrt(3/N), c = 1e-3, dt = 1: a kick per step is small next to
+    # the cutoff, so rounding differences do not grow and the whole trajectory
+    # is compared; the forces are pairwise opposite, so the momentum stays zero
+    n, steps = 1000, 20
+    w = syn.md_paper(n)
+    s = w.systems[0]
+    c = w.params[0]
+    x, v = to_dev(s.x), to_dev(w.extra["v"])
+    cells = A.build_cells(ctx, x, [box_of(s)])
+    xo, vo = s.x.copy(), w.extra["v"].copy()
+    g = oracle.grid_of(s)
+    for _ in range(steps):
+        gpu_step(ctx, cells, [box_of(s)], x, v, c, 1.0)
+        xo, vo, _ = oracle.md_step(g, c, 1.0, xo, vo)
+    ctx.sync()
+    vg = v.cpu().numpy()
+    assert np.abs(periodic_diff(x.cpu().numpy(), xo)).max() < 1e-12
+    assert np.abs(vg - vo).max() < 1e-10 * np.abs(vo).max()
+    assert np.abs(vg).max() > 1e-4  # the particles did move
+    assert np.abs(vg.sum(axis=0)).max() < 1e-12 * np.abs(vg).sum()
+
+
+def test_every_step_of_a_trajectory_matches_oracle(ctx):
+    # a livelier system (c = 5e-3): each GPU step is compared with one oracle step
+    # taken from the GPU's own previous state
+    n, steps, c = 4096, 10, 5e-3
+    w = syn.md_paper(n)
+    s = w.systems[0]
+    x, v = to_dev(s.x), to_dev(w.extra["v"])
+    cells = A.build_cells(ctx, x, [box_of(s)])
+    g = oracle.grid_of(s)
+    for k in range(steps):
+        x_prev, v_prev = x.cpu().numpy(), v.cpu().numpy()
+        gpu_step(ctx, cells, [box_of(s)], x, v, c, 1.0)
+        ctx.sync()
+        xo, vo, sv = oracle.md_step(g, c, 1.0, x_prev, v_prev)
+        check_state(x, v, xo, vo, v_prev, 1.0, sv, TOL_F64, "step %d" % k)
+    assert np.abs(v.cpu().numpy()).max() > 1e-3
+
+
+def test_batched_systems_step_each_in_its_own_box(ctx):
+    ws = [syn.md_paper(n, seed_offset=60 + i) for i, n in enumerate((700, 3000, 12000))]
+    xs = np.concatenate([w.systems[0].x for w in ws])
+    offsets = np.concatenate([[0], np.cumsum([w.systems[0].n for w in ws])]).tolist()
+    boxes = [box_of(w.systems[0]) for w in ws]
+    rng = syn.SplitMix64(5)
+    v0 = 1e-3 * rng.normal(2 * xs.shape[0]).reshape(-1, 2)
+    x, v = to_dev(xs), to_dev(v0)
+    cells = A.build_cells(ctx, x, boxes, offsets)
+    gpu_step(ctx, cells, boxes, x, v, 0.01, 0.5, offsets)
+    ctx.sync()
+    for b, w in enumerate(ws):
+        lo, hi = offsets[b], offsets[b + 1]
+        xo, vo, sv = oracle.md_step(oracle.grid_of(w.systems[0]), 0.01, 0.5, w.systems[0].x, v0[lo:hi])
+        check_state(x[lo:hi], v[lo:hi], xo, vo, v0[lo:hi], 0.5, sv, TOL_F64, "system %d" % b)
+
+
+def test_graph_of_steps_matches_eager_steps():
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        gctx = A.Context(0, stream)
+        w = syn.md_paper(20000)
+        s = w.systems[0]
+        boxes = [box_of(s)]
+        x0, v0 = to_dev(s.x), to_dev(1e-3 * np.ones((s.n, 2)))
+        x, v = x0.clone(), v0.clone()
+        cells = A.build_cells(gctx, x, boxes)
+        f = torch.empty((s.n, 2), dtype=torch.float64, device=dev())
+        for _ in range(5):
+            gpu_step(gctx, cells, boxes, x, v, 0.02, 1.0, f=f)
+        stream.synchronize()
+        x_ref, v_ref = x.clone(), v.clone()
+        x.copy_(x0)
+        v.copy_(v0)
+        stream.synchronize()
+        A.graph_capture_begin(gctx)
+        for _ in range(5):
+            gpu_step(gctx, cells, boxes, x, v, 0.02, 1.0, f=f)
+        graph = A.graph_capture_end(gctx)
+        for rep in range(2):
+            x.copy_(x0)
+            v.copy_(v0)
+            stream.synchronize()
+            A.graph_launch(gctx, graph)
+            stream.synchronize()
+            assert torch.equal(x, x_ref) and torch.equal(v, v_ref), rep
+        graph.close()
+        gctx.sync()
+        gctx.close()
+
+
+def test_integrate_argument_errors(ctx):
+    w = syn.md_paper(500)
+    s = w.systems[0]
+    x = to_dev(s.x)
+    v = torch.zeros_like(x)
+    f = torch.zeros_like(x)
+    cells = A.build_cells(ctx, x, [box_of(s)])
+    with pytest.raises(A.AboriaError) as e:
+        A.integrate(ctx, cells, float("nan"), f, x, v)
+    assert e.value.status == "INVALID_ARG"
+    with pytest.raises(A.AboriaError) as e:
+        A.integrate(ctx, cells, 1.0, f, x, x)  # x and v alias
+    assert e.value.status == "INVALID_ARG"
+    A.integrate(ctx, cells, 1.0, f, x, v)  # zero force, zero velocity: nothing moves
+    ctx.sync()
+    assert torch.equal(x, to_dev(s.x))
+    assert math.isfinite(float(x.sum().item()))
