@@ -75,6 +75,9 @@ def lib():
         L.or_dense_gauss.argtypes = [C.c_int32, C.c_int64, P, C.c_int64, P, P, C.c_double,
                                      C.c_int64, P, P, P]
         L.or_md_step.argtypes = [C.POINTER(Grid), C.c_int32, C.c_double, C.c_double, C.c_int64, P, P, P]
+        L.or_dense_sum.argtypes = [C.c_int32, C.c_double, C.c_int32, C.c_int64, P, C.c_int64, P, P, P, P]
+        L.or_dense_backward.argtypes = [C.c_int32, C.c_double, C.c_int32, C.c_int64, P, C.c_int64, P, P, P,
+                                        P, P, P, P, P, P]
         L.or_tie_band.argtypes = [C.POINTER(Grid), C.c_int64, P]
         L.or_tie_band.restype = C.c_int64
         L.or_op_ny.argtypes = [C.c_int32, C.c_int32]
@@ -169,6 +172,38 @@ def pair_sum(g: Grid, op: str, params, x, a=None, rows=None, route=ROUTE_CELLS):
     if st != OK:
         raise OracleError(st, "pair_sum")
     return y, sc
+
+
+KERNELS = {"gaussian": 0, "multiquadric": 1}
+
+
+def dense_sum(kernel: str, prm: float, xt, xs, w):
+    """(y, scale): y_i = sum_j K(xt_i, xs_j) w_j in float64 (Gaussian: prm = sigma;
+    multiquadric sqrt(q + c^2): prm = c)."""
+    xt, xs, w = _f64(xt), _f64(xs), _f64(w).reshape(-1)
+    d = xt.shape[1]
+    y = np.zeros(xt.shape[0])
+    sc = np.zeros(xt.shape[0])
+    st = lib().or_dense_sum(KERNELS[kernel], float(prm), d, xt.shape[0], _ptr(xt), xs.shape[0], _ptr(xs), _ptr(w),
+                            _ptr(y), _ptr(sc))
+    if st != OK:
+        raise OracleError(st, "dense_sum")
+    return y, sc
+
+
+def dense_backward(kernel: str, prm: float, xt, xs, w, gy):
+    """Adjoint of dense_sum for L = sum_i gy_i y_i, float64:
+    (gxt, gxs, gw, scale_xt, scale_xs, scale_w)."""
+    xt, xs, w, gy = _f64(xt), _f64(xs), _f64(w).reshape(-1), _f64(gy).reshape(-1)
+    d = xt.shape[1]
+    nt, ns = xt.shape[0], xs.shape[0]
+    gxt, gxs, gw = np.zeros((nt, d)), np.zeros((ns, d)), np.zeros(ns)
+    sxt, sxs, sgw = np.zeros(nt), np.zeros(ns), np.zeros(ns)
+    st = lib().or_dense_backward(KERNELS[kernel], float(prm), d, nt, _ptr(xt), ns, _ptr(xs), _ptr(w), _ptr(gy),
+                                 _ptr(gxt), _ptr(gxs), _ptr(gw), _ptr(sxt), _ptr(sxs), _ptr(sgw))
+    if st != OK:
+        raise OracleError(st, "dense_backward")
+    return gxt, gxs, gw, sxt, sxs, sgw
 
 
 def md_step(g: Grid, c: float, dt: float, x, v, route=ROUTE_CELLS):

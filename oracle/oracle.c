@@ -56,6 +56,8 @@
  *      cancels near the cutoff (k (r - s) as s -> r) cannot be evaluated in
  *      float32 more accurately than its distance is rounded, so its own
  *      magnitude alone is not a usable scale.
+ *   R8 the multiquadric basis of the Section 1.1 RBF example, whose formula the
+ *      paper does not print: Hardy's K(x, x') = sqrt(|x - x'|^2 + c^2), c > 0.
  *   R7 the periodic domain of the time step: after x += dt v, a coordinate at
  *      or above hi moves down by L, one below lo moves up by L (one image: a
  *      step moves a particle less than a box side), and a result that rounds
@@ -878,5 +880,111 @@ int or_md_step(const or_grid* g, int32_t route, double c, double dt, int64_t n, 
     }
     free(S);
     free(sc);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Dense kernel sums with a choice of radial kernel (Section 1.1: Gaussian   */
+/* basis of the Kansa example, multiquadric basis of the RBF example, read   */
+/* as R8), and their adjoint.  K(a, b) = phi(|a - b|^2):                      */
+/*   Gaussian      phi(q) = exp(-q / (2 s^2)),   prm = s (sigma)              */
+/*   multiquadric  phi(q) = sqrt(q + c^2),       prm = c                      */
+/* y_i = sum_j K(xt_i, xs_j) w_j over every source (j = i included).  For     */
+/* L = sum_i gy_i y_i:                                                         */
+/*   dL/dw_j   = sum_i K(xt_i, xs_j) gy_i                                      */
+/*   dL/dxt_i  = gy_i sum_j w_j 2 phi'(q_ij) (xt_i - xs_j)                     */
+/*   dL/dxs_j  = w_j sum_i gy_i 2 phi'(q_ij) (xs_j - xt_i)                     */
+/* (the gradient of phi(|a - b|^2) in a is 2 phi'(q)(a - b), and in b its     */
+/* negative).  All in float64 from the given inputs; the scales are the sums */
+/* of the summands' magnitudes.                                               */
+/* ------------------------------------------------------------------------ */
+
+#define OR_K_GAUSSIAN 0
+#define OR_K_MULTIQUADRIC 1
+
+static double kern_phi(int kind, double prm, double q) {
+    return kind == OR_K_GAUSSIAN ? exp(-q / (2.0 * prm * prm)) : sqrt(q + prm * prm);
+}
+
+/* 2 phi'(q) */
+static double kern_2dphi(int kind, double prm, double q) {
+    return kind == OR_K_GAUSSIAN ? -exp(-q / (2.0 * prm * prm)) / (prm * prm) : 1.0 / sqrt(q + prm * prm);
+}
+
+static int kern_ok(int kind, double prm) {
+    return (kind == OR_K_GAUSSIAN || kind == OR_K_MULTIQUADRIC) && prm > 0.0 && isfinite(prm);
+}
+
+static double sqdist(int d, const double* a, const double* b) {
+    double q = 0.0;
+    for (int k = 0; k < d; ++k) {
+        double t = a[k] - b[k];
+        q += t * t;
+    }
+    return q;
+}
+
+int or_dense_sum(int32_t kind, double prm, int32_t d, int64_t nt, const double* xt, int64_t ns, const double* xs,
+                 const double* w, double* y, double* scale) {
+    if (d < 1 || d > 3 || !kern_ok(kind, prm)) return OR_ERR_INVALID;
+    for (int64_t i = 0; i < nt; ++i) {
+        double acc = 0.0, sc = 0.0;
+        for (int64_t j = 0; j < ns; ++j) {
+            double term = kern_phi(kind, prm, sqdist(d, xt + i * d, xs + j * d)) * w[j];
+            acc += term;
+            sc += fabs(term);
+        }
+        y[i] = acc;
+        if (scale) scale[i] = sc;
+    }
+    return OR_OK;
+}
+
+/* gxt[nt][d], gxs[ns][d], gw[ns] (each may be NULL); sxt[nt], sxs[ns], sgw[ns]
+ * their error scales (may be NULL). */
+int or_dense_backward(int32_t kind, double prm, int32_t d, int64_t nt, const double* xt, int64_t ns,
+                      const double* xs, const double* w, const double* gy, double* gxt, double* gxs, double* gw,
+                      double* sxt, double* sxs, double* sgw) {
+    if (d < 1 || d > 3 || !kern_ok(kind, prm)) return OR_ERR_INVALID;
+    if (gxt) {
+        for (int64_t i = 0; i < nt; ++i) {
+            double acc[3] = {0, 0, 0}, sc = 0.0;
+            for (int64_t j = 0; j < ns; ++j) {
+                double h = kern_2dphi(kind, prm, sqdist(d, xt + i * d, xs + j * d)) * w[j];
+                double mx = 0.0;
+                for (int k = 0; k < d; ++k) {
+                    double dk = xt[i * d + k] - xs[j * d + k];
+                    acc[k] += h * dk;
+                    if (fabs(h * dk) > mx) mx = fabs(h * dk);
+                }
+                sc += mx;
+            }
+            for (int k = 0; k < d; ++k) gxt[i * d + k] = gy[i] * acc[k];
+            if (sxt) sxt[i] = fabs(gy[i]) * sc;
+        }
+    }
+    if (gxs || gw) {
+        for (int64_t j = 0; j < ns; ++j) {
+            double acc[3] = {0, 0, 0}, sc = 0.0, aw = 0.0, sw = 0.0;
+            for (int64_t i = 0; i < nt; ++i) {
+                double q = sqdist(d, xt + i * d, xs + j * d);
+                double h = kern_2dphi(kind, prm, q) * gy[i];
+                double mx = 0.0;
+                for (int k = 0; k < d; ++k) {
+                    double dk = xs[j * d + k] - xt[i * d + k];
+                    acc[k] += h * dk;
+                    if (fabs(h * dk) > mx) mx = fabs(h * dk);
+                }
+                sc += mx;
+                double kt = kern_phi(kind, prm, q) * gy[i];
+                aw += kt;
+                sw += fabs(kt);
+            }
+            if (gxs) for (int k = 0; k < d; ++k) gxs[j * d + k] = w[j] * acc[k];
+            if (sxs) sxs[j] = fabs(w[j]) * sc;
+            if (gw) gw[j] = aw;
+            if (sgw) sgw[j] = sw;
+        }
+    }
     return OR_OK;
 }

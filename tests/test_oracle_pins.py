@@ -447,3 +447,66 @@ def test_md_step_conserves_momentum_and_routes_agree():
     dv = (vc - v).sum(axis=0)
     assert np.all(np.abs(dv) < 1e-12 * sc.sum())
     assert np.abs(vc - v).max() > 1e-4  # the forces are not all zero
+
+
+# --------------------------------------------------------------------------
+# dense kernel sums with a choice of kernel, and their adjoint
+# --------------------------------------------------------------------------
+
+def test_dense_multiquadric_closed_forms():
+    c = 0.3
+    xt = np.array([[0.0, 0.0], [1.0, 2.0]])
+    xs = np.array([[0.0, 0.0], [3.0, 4.0], [1.0, 2.0]])
+    w = np.array([2.0, -1.0, 0.5])
+    y, sc = oracle.dense_sum("multiquadric", c, xt, xs, w)
+    # |d| = 0, 5, sqrt(5) from the first target; sqrt(5), sqrt(8), 0 from the second
+    y0 = 2.0 * c - math.sqrt(25 + c * c) + 0.5 * math.sqrt(5 + c * c)
+    y1 = 2.0 * math.sqrt(5 + c * c) - math.sqrt(8 + c * c) + 0.5 * c
+    np.testing.assert_allclose(y, [y0, y1], rtol=1e-15)
+    assert sc[0] == pytest.approx(2.0 * c + math.sqrt(25 + c * c) + 0.5 * math.sqrt(5 + c * c), rel=1e-15)
+    # the Gaussian route agrees with the older Gaussian-only entry
+    yg, _ = oracle.dense_sum("gaussian", 0.7, xt, xs, w)
+    yg2, _ = oracle.dense_gauss(xt, xs, w, 0.7)
+    np.testing.assert_allclose(yg, yg2, rtol=1e-15)
+
+
+@pytest.mark.parametrize("kernel,prm", [("gaussian", 0.35), ("multiquadric", 0.2)])
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_dense_adjoint_matches_finite_differences(kernel, prm, d):
+    rng = syn.SplitMix64(900 + d)
+    nt, ns = 7, 9
+    xt = rng.uniform(nt * d).reshape(nt, d)
+    xs = rng.uniform(ns * d).reshape(ns, d)
+    w = rng.normal(ns)
+    gy = rng.normal(nt)
+
+    def loss(xt_, xs_, w_):
+        y, _ = oracle.dense_sum(kernel, prm, xt_, xs_, w_)
+        return float(gy @ y)
+
+    gxt, gxs, gw, _, _, _ = oracle.dense_backward(kernel, prm, xt, xs, w, gy)
+    h = 1e-6
+    for arr, grad in ((xt, gxt), (xs, gxs), (w, gw)):
+        fd = np.zeros_like(arr)
+        flat, fdf = arr.reshape(-1), fd.reshape(-1)
+        for k in range(flat.size):
+            keep = flat[k]
+            flat[k] = keep + h
+            up = loss(xt, xs, w)
+            flat[k] = keep - h
+            dn = loss(xt, xs, w)
+            flat[k] = keep
+            fdf[k] = (up - dn) / (2 * h)
+        np.testing.assert_allclose(grad, fd, rtol=1e-6, atol=1e-8)
+
+
+def test_dense_adjoint_of_weights_is_the_transposed_sum():
+    # dL/dw = K^T gy: the forward sum with targets and sources exchanged and gy as weights
+    rng = syn.SplitMix64(31)
+    xt = rng.uniform(40).reshape(20, 2)
+    xs = rng.uniform(30).reshape(15, 2)
+    w, gy = rng.normal(15), rng.normal(20)
+    for kernel, prm in (("gaussian", 0.2), ("multiquadric", 0.5)):
+        _, _, gw, _, _, _ = oracle.dense_backward(kernel, prm, xt, xs, w, gy)
+        yt, _ = oracle.dense_sum(kernel, prm, xs, xt, gy)
+        np.testing.assert_allclose(gw, yt, rtol=1e-13)
