@@ -73,7 +73,10 @@ typedef enum aboria_op {
 } aboria_op;
 
 typedef enum aboria_kernel {
-    ABORIA_K_GAUSSIAN = 0 /* K(x, x') = exp(-|x - x'|^2 / (2 sigma^2)), params {sigma} */
+    ABORIA_K_GAUSSIAN = 0,    /* K(x, x') = exp(-|x - x'|^2 / (2 sigma^2)), params {sigma}; the
+                                 Gaussian basis of the Kansa example (Section 1.1) */
+    ABORIA_K_MULTIQUADRIC = 1 /* K(x, x') = sqrt(|x - x'|^2 + c^2), params {c}; the multiquadric
+                                 basis of the RBF example (Section 1.1), in Hardy's form */
 } aboria_kernel;
 
 /* A hypercube domain [lo, hi) and cutoff (Section 1, property 1; the
@@ -257,10 +260,25 @@ aboria_status aboria_pair_list(aboria_ctx* ctx, const aboria_cells* cells, int64
  * source (j = i included when the sets coincide).  xt[n_target][d],
  * xs[n_source][d], w[n_source], y[n_target] in dtype; d in 1..3.  Float32 inputs
  * accumulate in float32 with per-tile partial sums.  Errors: INVALID_ARG for an
- * unknown kernel, sigma <= 0, d outside 1..3, NULL or overlapping arrays. */
+ * unknown kernel, a kernel parameter (sigma or c) that is not positive, d
+ * outside 1..3, NULL or overlapping arrays. */
 aboria_status aboria_dense_sum(aboria_ctx* ctx, aboria_dtype dtype, aboria_kernel kernel,
                                const double* params_host, int32_t nparams, int32_t d, int64_t n_target,
                                const void* xt, int64_t n_source, const void* xs, const void* w, void* y);
+
+/* Adjoint of aboria_dense_sum for L = sum_i gy_i y_i (gy[n_target]):
+ *   gw[j]     = sum_i K(xt_i, xs_j) gy_i                       (K^T gy)
+ *   gxt[i][:] = gy_i sum_j w_j 2 phi'(q_ij) (xt_i - xs_j)
+ *   gxs[j][:] = w_j sum_i gy_i 2 phi'(q_ij) (xs_j - xt_i)
+ * for K = phi(q), q = |xt_i - xs_j|^2.  When targets and sources are the same
+ * points, dL/dx = gxt + gxs.  Each output may be NULL (not computed); all are
+ * overwritten, in dtype, and must not overlap the inputs or each other.  Uses
+ * the same grow-only scratch as the forward (a first call of a size must not
+ * be captured).  Errors as for aboria_dense_sum. */
+aboria_status aboria_dense_sum_backward(aboria_ctx* ctx, aboria_dtype dtype, aboria_kernel kernel,
+                                        const double* params_host, int32_t nparams, int32_t d, int64_t n_target,
+                                        const void* xt, int64_t n_source, const void* xs, const void* w,
+                                        const void* gy, void* gxt, void* gxs, void* gw);
 
 /* ---- graphs ------------------------------------------------------------------
  * Captures the calls made on ctx between begin and end into one executable

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libaboria_mi355x.so")
 
 F32, F64 = 0, 1
 OPS = {"count": 0, "spring": 1, "soft_sphere": 2, "exp_force": 3, "dem_spring": 4}
-KERNELS = {"gaussian": 0}
+KERNELS = {"gaussian": 0, "multiquadric": 1}
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "DOMAIN", 3: "UNSUPPORTED", 4: "OUT_OF_MEMORY", 5: "DEVICE"}
 
 
@@ -52,7 +52,8 @@ EXPORTS = ["aboria_create", "aboria_destroy", "aboria_set_stream", "aboria_last_
            "aboria_graph_capture_begin", "aboria_graph_capture_end", "aboria_graph_launch",
            "aboria_graph_destroy", "aboria_autotune", "aboria_variant_count", "aboria_variant_name",
            "aboria_set_variant", "aboria_op_ny", "aboria_op_na", "aboria_set_build_strategy",
-           "aboria_build_neighbours", "aboria_neighbour_capacity", "aboria_integrate"]
+           "aboria_build_neighbours", "aboria_neighbour_capacity", "aboria_integrate",
+           "aboria_dense_sum_backward"]
 
 
 def lib():
@@ -91,6 +92,8 @@ def lib():
             "aboria_build_neighbours": ([P, P, I32], I32),
             "aboria_neighbour_capacity": ([P], I32),
             "aboria_integrate": ([P, P, C.c_double, P, P, P], I32),
+            "aboria_dense_sum_backward": ([P, I32, I32, C.POINTER(C.c_double), I32, I32, I64, P, I64, P, P, P,
+                                           P, P, P], I32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -322,7 +325,8 @@ def pair_list(ctx: Context, cells: Cells):
 
 def dense_sum(ctx: Context, xt: torch.Tensor, xs: torch.Tensor, w: torch.Tensor, sigma: float,
               y: Optional[torch.Tensor] = None, kernel: str = "gaussian") -> torch.Tensor:
-    """aboria_dense_sum: y[i] = sum_j K(xt_i, xs_j) w_j."""
+    """aboria_dense_sum: y[i] = sum_j K(xt_i, xs_j) w_j (sigma is the kernel's parameter:
+    the Gaussian's width or the multiquadric's c)."""
     _check_dev(xt, "xt")
     _check_dev(xs, "xs", xt.dtype)
     _check_dev(w, "w", xt.dtype)
@@ -335,6 +339,22 @@ def dense_sum(ctx: Context, xt: torch.Tensor, xs: torch.Tensor, w: torch.Tensor,
                                 _ptr(xt), int(xs.shape[0]), _ptr(xs), _ptr(w), _ptr(y))
     ctx.check(st, "dense_sum")
     return y
+
+
+def dense_sum_backward(ctx: Context, xt: torch.Tensor, xs: torch.Tensor, w: torch.Tensor, sigma: float,
+                       gy: torch.Tensor, kernel: str = "gaussian", want=("xt", "xs", "w")):
+    """aboria_dense_sum_backward: (gxt, gxs, gw) for L = sum_i gy_i y_i (None where not wanted)."""
+    for t, name in ((xt, "xt"), (xs, "xs"), (w, "w"), (gy, "gy")):
+        _check_dev(t, name, xt.dtype)
+    d, nt, ns = int(xt.shape[1]), int(xt.shape[0]), int(xs.shape[0])
+    gxt = torch.empty((nt, d), dtype=xt.dtype, device=xt.device) if "xt" in want else None
+    gxs = torch.empty((ns, d), dtype=xt.dtype, device=xt.device) if "xs" in want else None
+    gw = torch.empty(ns, dtype=xt.dtype, device=xt.device) if "w" in want else None
+    arr, npar = _params([sigma])
+    st = lib().aboria_dense_sum_backward(ctx.handle, _dtype_code(xt), KERNELS[kernel], arr, npar, d, nt, _ptr(xt),
+                                         ns, _ptr(xs), _ptr(w), _ptr(gy), _ptr(gxt), _ptr(gxs), _ptr(gw))
+    ctx.check(st, "dense_sum_backward")
+    return gxt, gxs, gw
 
 
 class Graph:

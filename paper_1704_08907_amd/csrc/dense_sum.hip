@@ -1,16 +1,20 @@
-// Dense kernel sum of the RBF / Gaussian-process methods (Section 1 and the
+// Dense kernel sums of the RBF / Gaussian-process methods (Section 1 and the
 // RBF and Kansa examples of Section 1.1): y_i = sum_j K(x_i, x_j) w_j over all
-// sources, here with the Gaussian kernel K = exp(-|x_i - x_j|^2 / (2 sigma^2)).
+// sources, for the radial kernels K = phi(|x_i - x_j|^2) of those examples:
+// the Gaussian exp(-q / (2 sigma^2)) and the multiquadric sqrt(q + c^2); and
+// the adjoint of the sum: dL/dw = K^T gy (the same sum with targets and
+// sources exchanged) and the position gradients sum_j w_j 2 phi'(q) (a - b).
 //
 // Each thread keeps TI targets in registers; the workgroup streams tiles of
 // 256 sources (position and weight, 16 or 32 bytes each) through LDS, and every
-// lane reads each source with one broadcast LDS load.  Coordinates are
+// lane reads each source with one broadcast LDS load.  Gaussian coordinates are
 // pre-scaled by sqrt(c) so that the squared scaled distance is directly the
 // argument of one exp2 (float) or exp (double).  The source range is split over
 // a second grid dimension so that the launch fills all compute units; the split
-// partial sums are added in a fixed order by a second kernel, and inside a
-// split every tile's sum is formed separately before it is added (pairwise
-// accumulation keeps the float32 error well below the tile length times u).
+// partial sums are added in a fixed order by a second kernel (which also
+// applies the gradient's per-row factor), and inside a split every tile's sum
+// is formed separately before it is added (pairwise accumulation keeps the
+// float32 error well below the tile length times u).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -27,24 +31,48 @@ __device__ __forceinline__ float kexp(float a) { return __builtin_amdgcn_exp2f(-
 __device__ __forceinline__ double kexp(double a) { return ::exp(-a); }
 __device__ __forceinline__ float kfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double kfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float ksqrt(float a) { return __builtin_amdgcn_sqrtf(a); }
+__device__ __forceinline__ double ksqrt(double a) { return ::sqrt(a); }
+__device__ __forceinline__ float krsqrt(float a) { return __builtin_amdgcn_rsqf(a); }
+__device__ __forceinline__ double krsqrt(double a) { return ::rsqrt(a); }
 
-template <typename T, int D, int TI>
-__global__ __launch_bounds__(kDenseBlock) void k_dense_gauss(const T* __restrict__ xt, uint32_t nt,
-                                                             const T* __restrict__ xs, const T* __restrict__ w,
-                                                             uint32_t ns, T sc, uint32_t jchunk,
-                                                             T* __restrict__ ypart) {
+// phi of the kernel on its working coordinates (value) and the factor of the
+// gradient summand w_j * slope * (a - b) (the constant 2 phi' / slope is
+// applied by the reduction): Gaussian value = slope = exp(-q') on coordinates
+// scaled by sqrt(c); multiquadric value = sqrt(q + c^2), slope = 1/value.
+template <typename T, int KERN>
+struct Radial {
+    __device__ __forceinline__ static T value(T q, T c2) {
+        if constexpr (KERN == ABORIA_K_GAUSSIAN) return kexp(q);
+        else return ksqrt(q + c2);
+    }
+    __device__ __forceinline__ static T slope(T q, T c2) {
+        if constexpr (KERN == ABORIA_K_GAUSSIAN) return kexp(q);
+        else return krsqrt(q + c2);
+    }
+};
+
+// GRAD = false: part[split][t] = sum over the split's sources of K w.
+// GRAD = true:  part[split][t][k] = sum of w * slope * (xt_t - xs_j)_k.
+template <typename T, int D, int TI, int KERN, bool GRAD>
+__global__ __launch_bounds__(kDenseBlock) void k_dense(const T* __restrict__ xt, uint32_t nt,
+                                                       const T* __restrict__ xs, const T* __restrict__ w,
+                                                       uint32_t ns, T sc, T c2, uint32_t jchunk,
+                                                       T* __restrict__ ypart) {
+    constexpr int OUT = GRAD ? D : 1;
     __shared__ VecN<T, 4> tile[kDenseTile];
     const uint32_t tb = xcd_tile(blockIdx.x, gridDim.x);
     const uint32_t split = blockIdx.y;
     T xi[TI][D];
-    T acc[TI];
+    T acc[TI][OUT];
 #pragma unroll
     for (int q = 0; q < TI; ++q) {
         const uint32_t t = tb * (kDenseBlock * TI) + q * kDenseBlock + threadIdx.x;
         const uint32_t tc = t < nt ? t : nt - 1;
 #pragma unroll
         for (int k = 0; k < D; ++k) xi[q][k] = xt[(size_t)tc * D + k] * sc;
-        acc[q] = T(0);
+#pragma unroll
+        for (int k = 0; k < OUT; ++k) acc[q][k] = T(0);
     }
     const uint32_t jbeg = split * jchunk;
     const uint32_t jend = min(ns, jbeg + jchunk);
@@ -62,54 +90,107 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense_gauss(const T* __restrict
             tile[threadIdx.x] = v;
         }
         __syncthreads();
-        T part[TI];
+        T part[TI][OUT];
 #pragma unroll
-        for (int q = 0; q < TI; ++q) part[q] = T(0);
+        for (int q = 0; q < TI; ++q)
+#pragma unroll
+            for (int k = 0; k < OUT; ++k) part[q][k] = T(0);
 #pragma unroll 4
         for (int jj = 0; jj < kDenseTile; ++jj) {
             const VecN<T, 4> p = tile[jj];
 #pragma unroll
             for (int q = 0; q < TI; ++q) {
-                const T d0 = xi[q][0] - p.v[0];
-                T d2 = d0 * d0;
-                if constexpr (D >= 2) {
-                    const T d1 = xi[q][1] - p.v[1];
-                    d2 = kfma(d1, d1, d2);
+                T dk[D];
+#pragma unroll
+                for (int k = 0; k < D; ++k) dk[k] = xi[q][k] - p.v[k];
+                T d2 = dk[0] * dk[0];
+                if constexpr (D >= 2) d2 = kfma(dk[1], dk[1], d2);
+                if constexpr (D >= 3) d2 = kfma(dk[2], dk[2], d2);
+                if constexpr (!GRAD) {
+                    part[q][0] = kfma(Radial<T, KERN>::value(d2, c2), p.v[3], part[q][0]);
+                } else {
+                    const T h = Radial<T, KERN>::slope(d2, c2) * p.v[3];
+#pragma unroll
+                    for (int k = 0; k < D; ++k) part[q][k] = kfma(h, dk[k], part[q][k]);
                 }
-                if constexpr (D >= 3) {
-                    const T dz = xi[q][2] - p.v[2];
-                    d2 = kfma(dz, dz, d2);
-                }
-                part[q] = kfma(kexp(d2), p.v[3], part[q]);
             }
         }
 #pragma unroll
-        for (int q = 0; q < TI; ++q) acc[q] += part[q];
+        for (int q = 0; q < TI; ++q)
+#pragma unroll
+            for (int k = 0; k < OUT; ++k) acc[q][k] += part[q][k];
     }
 #pragma unroll
     for (int q = 0; q < TI; ++q) {
         const uint32_t t = tb * (kDenseBlock * TI) + q * kDenseBlock + threadIdx.x;
-        if (t < nt) ypart[(size_t)split * nt + t] = acc[q];
+        if (t < nt)
+#pragma unroll
+            for (int k = 0; k < OUT; ++k) ypart[((size_t)split * nt + t) * OUT + k] = acc[q][k];
     }
 }
 
-template <typename T>
+// y[t][k] = sum over splits (in split order); with mult, y[t][k] = (mult[t] * C) * sum.
+template <typename T, int OUT>
 __global__ __launch_bounds__(256) void k_dense_reduce(const T* __restrict__ ypart, uint32_t nt, uint32_t nsplit,
-                                                      T* __restrict__ y) {
+                                                      const T* __restrict__ mult, T C, T* __restrict__ y) {
     const uint32_t t = blockIdx.x * 256 + threadIdx.x;
     if (t >= nt) return;
-    T s = T(0);
-    for (uint32_t k = 0; k < nsplit; ++k) s += ypart[(size_t)k * nt + t];
-    y[t] = s;
+#pragma unroll
+    for (int k = 0; k < OUT; ++k) {
+        T s = T(0);
+        for (uint32_t q = 0; q < nsplit; ++q) s += ypart[((size_t)q * nt + t) * OUT + k];
+        y[(size_t)t * OUT + k] = mult ? (mult[t] * C) * s : s;
+    }
 }
 
 namespace {
 
 constexpr int kTargetsPerThread = 4;
 
-template <typename T, int D>
+// Kernel constants: Gaussian prm = sigma, multiquadric prm = c.
+struct KernelPlan {
+    double sc;   // coordinate scale
+    double c2;   // multiquadric c^2
+    double C;    // gradient constant: 2 phi'(q) (a - b) = C * slope * (scaled a - scaled b)
+};
+
+template <typename T>
+KernelPlan plan_kernel(int kernel, double prm) {
+    KernelPlan k{1.0, 0.0, 1.0};
+    if (kernel == ABORIA_K_GAUSSIAN) {
+        // float: exp2(-c d^2) with c = log2(e) / (2 sigma^2); double: exp(-d^2 / (2 sigma^2))
+        const double c = (sizeof(T) == 4 ? 1.4426950408889634 : 1.0) / (2.0 * prm * prm);
+        k.sc = std::sqrt(c);
+        k.C = -1.0 / (prm * prm * (double)(T)k.sc);  // 2 phi' = -phi / sigma^2, and d = d' / sc
+    } else {
+        k.c2 = prm * prm;
+    }
+    return k;
+}
+
+aboria_status ensure_scratch(aboria_ctx* ctx, size_t need) {
+    if (ctx->scratch_bytes >= need) return ABORIA_OK;
+    if (ctx->capturing)
+        return fail(ctx, ABORIA_ERR_UNSUPPORTED, "dense scratch must be sized by an uncaptured call first");
+    if (ctx->scratch) {
+        ABORIA_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        (void)hipFree(ctx->scratch);
+        ctx->scratch = nullptr;
+        ctx->scratch_bytes = 0;
+    }
+    if (hipMalloc(&ctx->scratch, need) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, ABORIA_ERR_OUT_OF_MEMORY, "dense scratch allocation failed");
+    }
+    ctx->scratch_bytes = need;
+    return ABORIA_OK;
+}
+
+// out = sum_j K(xt_i, xs_j) w_j (GRAD = false) or mult_i * C * sum_j w_j slope (xt_i - xs_j) (GRAD = true).
+template <typename T, int D, int KERN, bool GRAD>
 aboria_status launch_dense(aboria_ctx* ctx, uint32_t nt, const void* xt, uint32_t ns, const void* xs, const void* w,
-                           double sigma, void* y) {
+                           const KernelPlan& kp, const void* mult, void* out) {
+    constexpr int OUT = GRAD ? D : 1;
     const uint32_t per_block = kDenseBlock * kTargetsPerThread;
     const uint32_t tblocks = (nt + per_block - 1) / per_block;
     const uint32_t ntiles = std::max<uint32_t>((ns + kDenseTile - 1) / kDenseTile, 1);
@@ -119,30 +200,55 @@ aboria_status launch_dense(aboria_ctx* ctx, uint32_t nt, const void* xt, uint32_
     const uint32_t tiles_per_split = (ntiles + nsplit - 1) / nsplit;
     nsplit = (ntiles + tiles_per_split - 1) / tiles_per_split;
     const uint32_t jchunk = tiles_per_split * kDenseTile;
-    const size_t need = sizeof(T) * (size_t)nsplit * nt;
-    if (ctx->scratch_bytes < need) {
-        if (ctx->capturing)
-            return fail(ctx, ABORIA_ERR_UNSUPPORTED, "dense scratch must be sized by an uncaptured call first");
-        if (ctx->scratch) {
-            ABORIA_HIP(ctx, hipStreamSynchronize(ctx->stream));
-            (void)hipFree(ctx->scratch);
-            ctx->scratch = nullptr;
-            ctx->scratch_bytes = 0;
-        }
-        if (hipMalloc(&ctx->scratch, need) != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(ctx, ABORIA_ERR_OUT_OF_MEMORY, "dense scratch allocation failed");
-        }
-        ctx->scratch_bytes = need;
-    }
-    // float: exp2(-c d^2) with c = log2(e) / (2 sigma^2); double: exp(-d^2 / (2 sigma^2))
-    const double c = (sizeof(T) == 4 ? 1.4426950408889634 : 1.0) / (2.0 * sigma * sigma);
-    const T sc = (T)std::sqrt(c);
-    hipLaunchKernelGGL((k_dense_gauss<T, D, kTargetsPerThread>), dim3(tblocks, nsplit), dim3(kDenseBlock), 0,
-                       ctx->stream, (const T*)xt, nt, (const T*)xs, (const T*)w, ns, sc, jchunk, (T*)ctx->scratch);
-    hipLaunchKernelGGL(k_dense_reduce<T>, dim3((nt + 255) / 256), dim3(256), 0, ctx->stream,
-                       (const T*)ctx->scratch, nt, nsplit, (T*)y);
+    aboria_status st = ensure_scratch(ctx, sizeof(T) * (size_t)nsplit * nt * OUT);
+    if (st != ABORIA_OK) return st;
+    hipLaunchKernelGGL((k_dense<T, D, kTargetsPerThread, KERN, GRAD>), dim3(tblocks, nsplit), dim3(kDenseBlock), 0,
+                       ctx->stream, (const T*)xt, nt, (const T*)xs, (const T*)w, ns, (T)kp.sc, (T)kp.c2, jchunk,
+                       (T*)ctx->scratch);
+    hipLaunchKernelGGL((k_dense_reduce<T, OUT>), dim3((nt + 255) / 256), dim3(256), 0, ctx->stream,
+                       (const T*)ctx->scratch, nt, nsplit, (const T*)mult, (T)kp.C, (T*)out);
     ABORIA_HIP(ctx, hipGetLastError());
+    return ABORIA_OK;
+}
+
+template <typename T, int D, bool GRAD>
+aboria_status launch_kernel(aboria_ctx* ctx, int kernel, uint32_t nt, const void* xt, uint32_t ns, const void* xs,
+                            const void* w, double prm, const void* mult, void* out) {
+    const KernelPlan kp = plan_kernel<T>(kernel, prm);
+    if (kernel == ABORIA_K_GAUSSIAN)
+        return launch_dense<T, D, ABORIA_K_GAUSSIAN, GRAD>(ctx, nt, xt, ns, xs, w, kp, mult, out);
+    return launch_dense<T, D, ABORIA_K_MULTIQUADRIC, GRAD>(ctx, nt, xt, ns, xs, w, kp, mult, out);
+}
+
+template <bool GRAD>
+aboria_status dispatch(aboria_ctx* ctx, int dtype, int d, int kernel, uint32_t nt, const void* xt, uint32_t ns,
+                       const void* xs, const void* w, double prm, const void* mult, void* out) {
+    if (dtype == ABORIA_F32) {
+        switch (d) {
+            case 1: return launch_kernel<float, 1, GRAD>(ctx, kernel, nt, xt, ns, xs, w, prm, mult, out);
+            case 2: return launch_kernel<float, 2, GRAD>(ctx, kernel, nt, xt, ns, xs, w, prm, mult, out);
+            default: return launch_kernel<float, 3, GRAD>(ctx, kernel, nt, xt, ns, xs, w, prm, mult, out);
+        }
+    }
+    switch (d) {
+        case 1: return launch_kernel<double, 1, GRAD>(ctx, kernel, nt, xt, ns, xs, w, prm, mult, out);
+        case 2: return launch_kernel<double, 2, GRAD>(ctx, kernel, nt, xt, ns, xs, w, prm, mult, out);
+        default: return launch_kernel<double, 3, GRAD>(ctx, kernel, nt, xt, ns, xs, w, prm, mult, out);
+    }
+}
+
+aboria_status check_common(aboria_ctx* ctx, aboria_dtype dtype, aboria_kernel kernel, const double* params_host,
+                           int32_t nparams, int32_t d, int64_t n_target, int64_t n_source) {
+    if (kernel != ABORIA_K_GAUSSIAN && kernel != ABORIA_K_MULTIQUADRIC)
+        return fail(ctx, ABORIA_ERR_INVALID_ARG, "unknown kernel");
+    if (dtype != ABORIA_F32 && dtype != ABORIA_F64) return fail(ctx, ABORIA_ERR_INVALID_ARG, "unknown dtype");
+    if (nparams != 1 || !params_host) return fail(ctx, ABORIA_ERR_INVALID_ARG, "the kernel takes one parameter");
+    const double prm = params_host[0];
+    if (!(prm > 0.0) || !std::isfinite(prm))
+        return fail(ctx, ABORIA_ERR_INVALID_ARG, "the kernel parameter (sigma or c) must be positive");
+    if (d < 1 || d > 3) return fail(ctx, ABORIA_ERR_INVALID_ARG, "d must be 1, 2 or 3");
+    if (n_target < 0 || n_source < 0 || n_target >= ((int64_t)1 << 31) || n_source >= ((int64_t)1 << 31))
+        return fail(ctx, ABORIA_ERR_INVALID_ARG, "sizes must lie in [0, 2^31)");
     return ABORIA_OK;
 }
 
@@ -157,14 +263,8 @@ extern "C" aboria_status aboria_dense_sum(aboria_ctx* ctx, aboria_dtype dtype, a
                                           const void* xt, int64_t n_source, const void* xs, const void* w, void* y) {
     if (!ctx) return ABORIA_ERR_INVALID_ARG;
     try {
-        if (kernel != ABORIA_K_GAUSSIAN) return fail(ctx, ABORIA_ERR_INVALID_ARG, "unknown kernel");
-        if (dtype != ABORIA_F32 && dtype != ABORIA_F64) return fail(ctx, ABORIA_ERR_INVALID_ARG, "unknown dtype");
-        if (nparams != 1 || !params_host) return fail(ctx, ABORIA_ERR_INVALID_ARG, "the Gaussian kernel takes {sigma}");
-        const double sigma = params_host[0];
-        if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(ctx, ABORIA_ERR_INVALID_ARG, "sigma must be positive");
-        if (d < 1 || d > 3) return fail(ctx, ABORIA_ERR_INVALID_ARG, "d must be 1, 2 or 3");
-        if (n_target < 0 || n_source < 0 || n_target >= ((int64_t)1 << 31) || n_source >= ((int64_t)1 << 31))
-            return fail(ctx, ABORIA_ERR_INVALID_ARG, "sizes must lie in [0, 2^31)");
+        aboria_status st = check_common(ctx, dtype, kernel, params_host, nparams, d, n_target, n_source);
+        if (st != ABORIA_OK) return st;
         if (n_target == 0) return ABORIA_OK;
         if (!xt || !y || (n_source > 0 && (!xs || !w))) return fail(ctx, ABORIA_ERR_INVALID_ARG, "NULL array");
         const size_t tsz = dtype == ABORIA_F32 ? 4 : 8;
@@ -172,21 +272,59 @@ extern "C" aboria_status aboria_dense_sum(aboria_ctx* ctx, aboria_dtype dtype, a
         if (overlaps(y, ny, xt, tsz * d * (size_t)n_target) || overlaps(y, ny, xs, tsz * d * (size_t)n_source) ||
             overlaps(y, ny, w, tsz * (size_t)n_source))
             return fail(ctx, ABORIA_ERR_INVALID_ARG, "y overlaps an input");
-        const uint32_t nt = (uint32_t)n_target, ns = (uint32_t)n_source;
-        if (dtype == ABORIA_F32) {
-            switch (d) {
-                case 1: return launch_dense<float, 1>(ctx, nt, xt, ns, xs, w, sigma, y);
-                case 2: return launch_dense<float, 2>(ctx, nt, xt, ns, xs, w, sigma, y);
-                default: return launch_dense<float, 3>(ctx, nt, xt, ns, xs, w, sigma, y);
-            }
-        } else {
-            switch (d) {
-                case 1: return launch_dense<double, 1>(ctx, nt, xt, ns, xs, w, sigma, y);
-                case 2: return launch_dense<double, 2>(ctx, nt, xt, ns, xs, w, sigma, y);
-                default: return launch_dense<double, 3>(ctx, nt, xt, ns, xs, w, sigma, y);
-            }
-        }
+        return dispatch<false>(ctx, dtype, d, kernel, (uint32_t)n_target, xt, (uint32_t)n_source, xs, w,
+                               params_host[0], nullptr, y);
     } catch (...) {
         return fail(ctx, ABORIA_ERR_OUT_OF_MEMORY, "host exception in dense_sum");
+    }
+}
+
+extern "C" aboria_status aboria_dense_sum_backward(aboria_ctx* ctx, aboria_dtype dtype, aboria_kernel kernel,
+                                                   const double* params_host, int32_t nparams, int32_t d,
+                                                   int64_t n_target, const void* xt, int64_t n_source,
+                                                   const void* xs, const void* w, const void* gy, void* gxt,
+                                                   void* gxs, void* gw) {
+    if (!ctx) return ABORIA_ERR_INVALID_ARG;
+    try {
+        aboria_status st = check_common(ctx, dtype, kernel, params_host, nparams, d, n_target, n_source);
+        if (st != ABORIA_OK) return st;
+        if (n_target == 0 || n_source == 0) {
+            // no pairs: every requested gradient is zero (a fill kernel, so the call stays capturable)
+            const int64_t words = dtype == ABORIA_F32 ? 1 : 2;
+            if (gxt && n_target > 0 && (st = fill_u32(ctx, (uint32_t*)gxt, 0u, words * d * n_target)) != ABORIA_OK)
+                return st;
+            if (gxs && n_source > 0 && (st = fill_u32(ctx, (uint32_t*)gxs, 0u, words * d * n_source)) != ABORIA_OK)
+                return st;
+            if (gw && n_source > 0 && (st = fill_u32(ctx, (uint32_t*)gw, 0u, words * n_source)) != ABORIA_OK)
+                return st;
+            return ABORIA_OK;
+        }
+        if (!xt || !xs || !w || !gy) return fail(ctx, ABORIA_ERR_INVALID_ARG, "NULL input array");
+        const size_t tsz = dtype == ABORIA_F32 ? 4 : 8;
+        const size_t nt = (size_t)n_target, ns = (size_t)n_source;
+        struct Span { const void* p; size_t bytes; };
+        const Span ins[] = {{xt, tsz * d * nt}, {xs, tsz * d * ns}, {w, tsz * ns}, {gy, tsz * nt}};
+        const Span outs[] = {{gxt, tsz * d * nt}, {gxs, tsz * d * ns}, {gw, tsz * ns}};
+        for (const Span& o : outs) {
+            if (!o.p) continue;
+            for (const Span& i : ins)
+                if (overlaps(o.p, o.bytes, i.p, i.bytes))
+                    return fail(ctx, ABORIA_ERR_INVALID_ARG, "an output overlaps an input");
+            for (const Span& o2 : outs)
+                if (&o2 != &o && o2.p && overlaps(o.p, o.bytes, o2.p, o2.bytes))
+                    return fail(ctx, ABORIA_ERR_INVALID_ARG, "outputs overlap");
+        }
+        const double prm = params_host[0];
+        const uint32_t t32 = (uint32_t)n_target, s32 = (uint32_t)n_source;
+        // dL/dw = K^T gy: the forward sum over the targets, seen from the sources
+        if (gw && (st = dispatch<false>(ctx, dtype, d, kernel, s32, xs, t32, xt, gy, prm, nullptr, gw)) != ABORIA_OK)
+            return st;
+        if (gxt && (st = dispatch<true>(ctx, dtype, d, kernel, t32, xt, s32, xs, w, prm, gy, gxt)) != ABORIA_OK)
+            return st;
+        if (gxs && (st = dispatch<true>(ctx, dtype, d, kernel, s32, xs, t32, xt, gy, prm, w, gxs)) != ABORIA_OK)
+            return st;
+        return ABORIA_OK;
+    } catch (...) {
+        return fail(ctx, ABORIA_ERR_OUT_OF_MEMORY, "host exception in dense_sum_backward");
     }
 }
