@@ -305,6 +305,12 @@ aboria_status aboria_autotune(aboria_ctx* ctx, const aboria_cells* cells, aboria
                               const double* params_host, int32_t nparams, const void* a, int32_t na,
                               const void* gy, int32_t ny, void* out_scratch, int32_t* choice_host);
 
+/* Without tuning or a forced variant, a sum on a cell list whose systems all
+ * have at most 2048 particles tests all pairs of each system at the minimum
+ * image (the small-N switch: no cell search; with an explicit cell count of 1
+ * per dimension the build is a single kernel as well); otherwise it replays
+ * the recorded neighbour list if there is one, else it searches cells. */
+
 /* Number of neighbour-sum variants, and a static description of one. */
 int32_t aboria_variant_count(void);
 const char* aboria_variant_name(int32_t variant);

@@ -33,8 +33,8 @@ int32_t pick_variant(aboria_ctx* ctx, const aboria_cells* c, int32_t op, bool ba
     const uint64_t key = tune_key(c, op, backward);
     for (const auto& kv : ctx->tune_cache)
         if (kv.first == key) return kv.second;
-    // untuned: replay the recorded neighbour list when there is one
-    return c->nbr_recorded ? list_variant() : 0;
+    // untuned: all pairs for small systems, else the recorded list when there is one
+    return default_variant(c);
 }
 
 }  // namespace aboria
@@ -77,7 +77,7 @@ extern "C" aboria_status aboria_autotune(aboria_ctx* ctx, const aboria_cells* ce
                             : pair_sum_impl(ctx, cells, op, params_host, nparams, a, na, out_scratch, ny, v);
         };
         for (int32_t v = 0; v < variant_count() && st == ABORIA_OK; ++v) {
-            if (variant_needs_list(v) && !cells->nbr_recorded) continue;
+            if (!variant_usable(v, cells)) continue;
             st = run(v);  // warm-up
             if (st != ABORIA_OK) break;
             std::vector<float> times;

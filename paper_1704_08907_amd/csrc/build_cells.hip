@@ -90,6 +90,49 @@ __global__ __launch_bounds__(kBlock) void k_cell_ids(const T* __restrict__ x, ui
     if (counts) ranks[i] = atomicAdd(&counts[key], 1u);
 }
 
+// One cell per system (an explicit cell count of 1 in every dimension, the
+// layout of the all-pairs sums of small systems): the stable cell order is the
+// input order, so one kernel writes the identity permutation, the systems'
+// cell ids, the positions and the offsets (the system offsets) in place of the
+// sort.  Threads up to nsys also write the offsets, so the grid covers
+// max(n, nsys + 1).
+template <typename T, int D, bool BATCH>
+__global__ __launch_bounds__(kBlock) void k_single_cells(const T* __restrict__ x, uint32_t n,
+                                                         const SysParams<T>* __restrict__ sp,
+                                                         const uint32_t* __restrict__ sys_part, int nsys,
+                                                         T* __restrict__ xs, uint32_t* __restrict__ keys,
+                                                         uint32_t* __restrict__ perm, uint32_t* __restrict__ off,
+                                                         uint32_t* __restrict__ flag, uint32_t* __restrict__ gen) {
+    constexpr int PITCH = Pitch<D>::value;
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i == 0) gen[0] = gen[0] + 1u;
+    if (i <= (uint32_t)nsys) off[i] = sys_part[i];
+    int b = 0;
+    if (BATCH) {
+        __shared__ int s_first;
+        if (threadIdx.x == 0) s_first = find_system(sys_part, nsys, min(blockIdx.x * kBlock, n > 0 ? n - 1 : 0u));
+        __syncthreads();
+        b = s_first;
+        while (b + 1 < nsys && sys_part[b + 1] <= i) ++b;
+    }
+    if (i >= n) return;
+    const SysParams<T>& P = sp[b];
+    VecN<T, PITCH> v;
+#pragma unroll
+    for (int k = 0; k < PITCH; ++k) v.v[k] = T(0);
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const T xk = x[(size_t)i * D + k];
+        bad |= !(xk >= P.lo[k]) || !(xk < P.hi[k]);
+        v.v[k] = xk;
+    }
+    if (bad) atomicOr(flag, 1u);
+    reinterpret_cast<VecN<T, PITCH>*>(xs)[i] = v;
+    keys[i] = P.cell_base;
+    perm[i] = i;
+}
+
 // ---------------------------------------------------------------------------
 // counting build: place by (cell offset + arrival rank), then restore the
 // original index order inside each cell
@@ -690,7 +733,24 @@ aboria_status launch_build_radix(aboria_ctx* ctx, aboria_cells* c, const void* x
 }
 
 template <typename T, int D>
+aboria_status launch_build_single(aboria_ctx* ctx, aboria_cells* c, const void* x) {
+    const uint32_t n = (uint32_t)c->n;
+    const uint32_t work = std::max<uint32_t>(n, (uint32_t)c->nsys + 1u);
+    const dim3 grid((work + kBlock - 1) / kBlock);
+    const SysParams<T>* sp = reinterpret_cast<const SysParams<T>*>(c->params_dev);
+    if (c->nsys == 1)
+        hipLaunchKernelGGL((k_single_cells<T, D, false>), grid, dim3(kBlock), 0, ctx->stream, (const T*)x, n, sp,
+                           c->sys_part_dev, c->nsys, (T*)c->xs, c->keys, c->perm, c->off, ctx->d_flag, c->gen);
+    else
+        hipLaunchKernelGGL((k_single_cells<T, D, true>), grid, dim3(kBlock), 0, ctx->stream, (const T*)x, n, sp,
+                           c->sys_part_dev, c->nsys, (T*)c->xs, c->keys, c->perm, c->off, ctx->d_flag, c->gen);
+    ABORIA_HIP(ctx, hipGetLastError());
+    return ABORIA_OK;
+}
+
+template <typename T, int D>
 aboria_status launch_build(aboria_ctx* ctx, aboria_cells* c, const void* x) {
+    if (c->ncells == c->nsys) return launch_build_single<T, D>(ctx, c, x);  // one cell per system: no sort
     return ctx->build_strategy == ABORIA_BUILD_RADIX ? launch_build_radix<T, D>(ctx, c, x)
                                                      : launch_build_counting<T, D>(ctx, c, x);
 }

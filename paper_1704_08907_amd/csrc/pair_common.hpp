@@ -344,6 +344,67 @@ __device__ __forceinline__ void neighbour_loop(const SysParams<T>& P, const T* _
 }
 
 // ---------------------------------------------------------------------------
+// all pairs of a small system (the brute-force fallback for small N)
+// ---------------------------------------------------------------------------
+
+// visit(j, dx, d2, shifted) for every slot j in [j0, j1) that is a neighbour of
+// xi, testing each particle once at its minimum image: in each periodic
+// dimension s_k = -L if t_k > L/2, +L if t_k < -L/2, else 0, with t_k =
+// fl(x_jk - x_ik).  For a neighbour this is the shift the box search uses (the
+// side is at least twice the guarded cutoff, so only one image can be within
+// r), so the pair set and each pair's dx are those of the box search; a
+// non-neighbour is rejected at every image because its nearest one is.
+// The slots visited are j0, j0 + step, j0 + 2 step, ... below j1 (a group of
+// lanes splits one particle's slots this way).
+template <typename T, int D, typename Visit>
+__device__ __forceinline__ void allpairs_loop(const SysParams<T>& P, const T* __restrict__ xs, uint32_t j0,
+                                              uint32_t j1, uint32_t step, const T* xi, Visit& visit) {
+    constexpr int PITCH = Pitch<D>::value;
+    const VecN<T, PITCH>* __restrict__ xv = reinterpret_cast<const VecN<T, PITCH>*>(xs);
+    T h[D], L[D];
+    bool per[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        L[k] = P.L[k];
+        h[k] = T(0.5) * L[k];
+        per[k] = P.periodic[k] != 0;
+    }
+    const T r2 = P.r2;
+    auto one = [&](uint32_t j, const VecN<T, PITCH>& a) {
+        T dx[D];
+        bool shifted = false;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const T t = a.v[k] - xi[k];
+            const T sk = !per[k] ? T(0) : (t > h[k] ? -L[k] : (t < -h[k] ? L[k] : T(0)));
+            shifted |= sk != T(0);
+            dx[k] = t + sk;
+        }
+        T d2 = dx[0] * dx[0];
+        if constexpr (D >= 2) d2 = fma_t(dx[1], dx[1], d2);
+        if constexpr (D >= 3) d2 = fma_t(dx[2], dx[2], d2);
+        if (d2 > T(0) && d2 < r2) visit(j, dx, d2, shifted);
+    };
+    uint32_t j = j0;
+    for (; j + step < j1; j += 2 * step) {
+        const VecN<T, PITCH> a = xv[j];
+        const VecN<T, PITCH> b = xv[j + step];
+        one(j, a);
+        one(j + step, b);
+    }
+    if (j < j1) one(j, xv[j]);
+}
+
+// Sum of v over the G lanes of a group (G a power of two dividing the wave) by a
+// fixed xor butterfly, so the result does not depend on timing.
+template <int G, typename T>
+__device__ __forceinline__ T group_reduce(T v) {
+#pragma unroll
+    for (int m = G / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, G);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
 // recorded neighbour lists
 // ---------------------------------------------------------------------------
 
@@ -481,6 +542,13 @@ template <typename T, int D, int OP, bool BATCH>
 void launch_nbr_fwd(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, T* y);
 template <typename T, int D, int OP, bool BATCH>
 void launch_nbr_bwd(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, const T* gy_s, T* gx,
+                    T* ga);
+
+// Forward / adjoint over every particle of the lane's system (minimum image).
+template <typename T, int D, int OP, bool BATCH>
+void launch_all_fwd(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, T* y);
+template <typename T, int D, int OP, bool BATCH>
+void launch_all_bwd(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, const T* gy_s, T* gx,
                     T* ga);
 
 // Cell-group forward / adjoint; rounds = 1 keeps natural cell order, 8 ranks

@@ -97,13 +97,24 @@ const Variant kVariants[] = {
     {1, 128, false, 1, "cell group of 16 lanes per home cell, cells in natural order"},
     {1, 128, false, 8, "cell group of 16 lanes per home cell, 64-cell tiles ranked by occupancy"},
     {2, 256, false, 0, "lane per particle over the recorded neighbour list (accepted pairs only)"},
+    {3, 256, false, 0, "lane per particle over all particles of its system (minimum image; small systems)"},
 };
+
+// Largest system the all-pairs variant accepts (its lanes test every particle of their system).
+constexpr int64_t kAllPairsMaxSystem = 16384;
+
+int64_t largest_system(const aboria_cells* c) {
+    int64_t m = 0;
+    for (int32_t b = 0; b < c->nsys; ++b) m = std::max<int64_t>(m, c->sys_off[(size_t)b + 1] - c->sys_off[(size_t)b]);
+    return m;
+}
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 template <typename T, int D, int OP, bool BATCH>
 void launch_fwd_variant(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, T* y,
                         const Variant& v) {
-    if (v.kind == 2) launch_nbr_fwd<T, D, OP, BATCH>(ctx, c, q, a_s, y);
+    if (v.kind == 3) launch_all_fwd<T, D, OP, BATCH>(ctx, c, q, a_s, y);
+    else if (v.kind == 2) launch_nbr_fwd<T, D, OP, BATCH>(ctx, c, q, a_s, y);
     else if (v.kind == 1) launch_cells_fwd<T, D, OP, BATCH>(ctx, c, q, a_s, y, v.rounds);
     else launch_lane_fwd<T, D, OP, BATCH>(ctx, c, q, a_s, y, v.block > 256 ? 256 : v.block);
 }
@@ -111,7 +122,8 @@ void launch_fwd_variant(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>&
 template <typename T, int D, int OP, bool BATCH>
 void launch_bwd_variant(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, const T* gy_s,
                         T* gx, T* ga, const Variant& v) {
-    if (v.kind == 2) launch_nbr_bwd<T, D, OP, BATCH>(ctx, c, q, a_s, gy_s, gx, ga);
+    if (v.kind == 3) launch_all_bwd<T, D, OP, BATCH>(ctx, c, q, a_s, gy_s, gx, ga);
+    else if (v.kind == 2) launch_nbr_bwd<T, D, OP, BATCH>(ctx, c, q, a_s, gy_s, gx, ga);
     else if (v.kind == 1) launch_cells_bwd<T, D, OP, BATCH>(ctx, c, q, a_s, gy_s, gx, ga, v.rounds);
     else launch_lane_bwd<T, D, OP, BATCH>(ctx, c, q, a_s, gy_s, gx, ga, v.block, v.compact);
 }
@@ -179,6 +191,8 @@ aboria_status validate(aboria_ctx* ctx, const aboria_cells* c, int op, const dou
 aboria_status check_variant(aboria_ctx* ctx, const aboria_cells* c, int variant) {
     if (variant_needs_list(variant) && !c->nbr_recorded)
         return fail(ctx, ABORIA_ERR_INVALID_ARG, "the variant needs a neighbour list recorded on these cells");
+    if (variant_of(variant).kind == 3 && largest_system(c) > kAllPairsMaxSystem)
+        return fail(ctx, ABORIA_ERR_INVALID_ARG, "the all-pairs variant takes systems of at most 16384 particles");
     return ABORIA_OK;
 }
 
@@ -190,10 +204,28 @@ const char* variant_name(int32_t v) { return (v >= 0 && v < kNumVariants) ? kVar
 
 bool variant_needs_list(int32_t v) { return v >= 0 && v < kNumVariants && kVariants[v].kind == 2; }
 
+bool variant_usable(int32_t v, const aboria_cells* c) {
+    if (v < 0 || v >= kNumVariants) return false;
+    if (kVariants[v].kind == 2) return c->nbr_recorded;
+    if (kVariants[v].kind == 3) return largest_system(c) <= kAllPairsMaxSystem;
+    return true;
+}
+
 int32_t list_variant() {
     for (int32_t v = 0; v < kNumVariants; ++v)
         if (kVariants[v].kind == 2) return v;
     return 0;
+}
+
+// Largest system for which an untuned sum tests all pairs instead of searching
+// cells (the small-N switch; the autotuner decides for tuned cell lists).
+constexpr int64_t kAllPairsDefaultMax = 2048;
+
+int32_t default_variant(const aboria_cells* c) {
+    if (largest_system(c) <= kAllPairsDefaultMax)
+        for (int32_t v = 0; v < kNumVariants; ++v)
+            if (kVariants[v].kind == 3) return v;
+    return c->nbr_recorded ? list_variant() : 0;
 }
 
 aboria_status pair_sum_impl(aboria_ctx* ctx, const aboria_cells* c, int32_t op, const double* params,
