@@ -61,6 +61,46 @@ def hip_download(ptr: int, count: int, dtype) -> np.ndarray:
     return out[:count]
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "spring_cube_n1048576_hbm_counters.txt")
+
+
+def counted_traffic(names):
+    """HBM bytes per launch of the named kernels (summed) from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary (calibrated by a plain device
+    copy); None when the summary is missing or does not list one of them."""
+    if not names or not os.path.exists(COUNTERS):
+        return None
+    mb = {}
+    with open(COUNTERS) as f:
+        for line in f:
+            parts = line.rsplit(None, 4)
+            if len(parts) == 5:
+                try:
+                    mb[parts[0].strip()] = float(parts[4])
+                except ValueError:
+                    pass
+    if not all(k in mb for k in names):
+        return None
+    return sum(mb[k] for k in names) * 1e6
+
+
+def profile_names(variant_name, direction):
+    """Kernel names as rocprofv3 reports them for the spring cube (float32, d = 3, no batch)."""
+    if "recorded" in variant_name:
+        k = ["k_nbr_fwd<float, 3, 1, false>"] if direction == "fwd" else ["k_nbr_bwd<float, 3, 1, false>"]
+    elif "cell group" in variant_name:
+        return None
+    elif direction == "fwd":
+        k = ["k_lane_fwd<float, 3, 1, false>"]
+    elif "queue" in variant_name:
+        k = ["k_lane_bwd_queue<float, 3, 1, false>"]
+    elif "LDS list" in variant_name:
+        return None
+    else:
+        k = ["k_lane_bwd<float, 3, 1, false>"]
+    return k if direction == "fwd" else ["k_gather_rows<float, 3>"] + k
+
+
 def candidate_count(cells) -> int:
     """Candidates the 3^3 box search tests: sum over cells of count(c) * count(3^3 around c)."""
     v = cells.view()
@@ -257,35 +297,40 @@ def main():
         t_fwd, t_bwd = t_fwd_search, t_bwd_search
         phases = {
             "fwd": (kernel_of(search_fwd, "fwd") + " (forward call, box search)", t_fwd,
-                    cand * OPS_PER_CANDIDATE + pairs * OPS_PER_PAIR["fwd"], n * (16 + 4 + 12) + 4 * (nc + 1)),
+                    cand * OPS_PER_CANDIDATE + pairs * OPS_PER_PAIR["fwd"], n * (16 + 4 + 12) + 4 * (nc + 1),
+                    profile_names(A.variant_name(search_fwd), "fwd")),
             "bwd": (kernel_of(search_bwd, "bwd") + " (adjoint call, box search)", t_bwd,
                     cand * OPS_PER_CANDIDATE + pairs * OPS_PER_PAIR["bwd"],
-                    n * (4 + 12 + 12) + n * (16 + 4 + 12 + 12) + 4 * (nc + 1)),
+                    n * (4 + 12 + 12) + n * (16 + 4 + 12 + 12) + 4 * (nc + 1),
+                    profile_names(A.variant_name(search_bwd), "bwd")),
         }
     else:
         t_fwd, t_bwd = t_fwd_list, t_bwd_list
         phases = {
             "neighbours": ("k_nbr_build<float,3> (neighbour-list recording)", t_nbr,
-                           cand * OPS_PER_CANDIDATE, n * (16 + 4) + 4 * (nc + 1) + 4 * pairs),
+                           cand * OPS_PER_CANDIDATE, n * (16 + 4) + 4 * (nc + 1) + 4 * pairs, None),
             "fwd": (kernel_of(variant_fwd, "fwd") + " (forward call, replay)", t_fwd,
-                    pairs * (OPS_PER_REPLAYED_PAIR + OPS_PER_PAIR["fwd"]), 4 * pairs + n * (16 + 4 + 4 + 12)),
+                    pairs * (OPS_PER_REPLAYED_PAIR + OPS_PER_PAIR["fwd"]), 4 * pairs + n * (16 + 4 + 4 + 12),
+                    profile_names(A.variant_name(variant_fwd), "fwd")),
             "bwd": (kernel_of(variant_bwd, "bwd") + " (adjoint call, replay)", t_bwd,
                     pairs * (OPS_PER_REPLAYED_PAIR + OPS_PER_PAIR["bwd"]),
-                    n * (4 + 12 + 12) + 4 * pairs + n * (16 + 4 + 4 + 12 + 12)),
+                    n * (4 + 12 + 12) + 4 * pairs + n * (16 + 4 + 4 + 12 + 12),
+                    profile_names(A.variant_name(variant_bwd), "bwd")),
         }
 
     def roof(key):
-        kname, t, ops, nbytes = phases[key]
+        kname, t, ops, nbytes, pnames = phases[key]
+        traffic = counted_traffic(pnames)
         alu_ms = ops / (VALU_PEAK_TOPS * 1e12) * 1e3
         hbm_ms = nbytes / (HBM_PEAK_GBS * 1e9) * 1e3
         if hbm_ms >= alu_ms:
             ach = nbytes / (t * 1e-3) / 1e9
             return {"bound": "hbm", "kernel": kname, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": ach / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes_per_launch": nbytes,
+                    "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "algorithmic_bytes_per_launch": nbytes,
                     "algorithmic_ops_per_launch": ops, "avg_launch_ms": t}
         ach = ops / (t * 1e-3) / 1e12
         return {"bound": "alu", "kernel": kname, "achieved": ach, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
-                "frac": ach / VALU_PEAK_TOPS, "traffic": None, "algorithmic_ops_per_launch": ops,
+                "frac": ach / VALU_PEAK_TOPS, "traffic": traffic, "algorithmic_ops_per_launch": ops,
                 "algorithmic_bytes_per_launch": nbytes, "avg_launch_ms": t}
 
     dominant = max(phases, key=lambda k: phases[k][1])

@@ -204,6 +204,15 @@ const char* variant_name(int32_t v) { return (v >= 0 && v < kNumVariants) ? kVar
 
 bool variant_needs_list(int32_t v) { return v >= 0 && v < kNumVariants && kVariants[v].kind == 2; }
 
+// The cell-group mapping gives one 16-lane group a whole home cell; with tens
+// of particles per cell (a coarse explicit grid, such as one cell per system)
+// a few groups do all the work, so the tuner does not time it there.
+bool variant_worth_timing(int32_t v, const aboria_cells* c) {
+    if (v < 0 || v >= kNumVariants) return false;
+    if (kVariants[v].kind == 1) return c->n <= 64 * c->ncells;
+    return true;
+}
+
 bool variant_usable(int32_t v, const aboria_cells* c) {
     if (v < 0 || v >= kNumVariants) return false;
     if (kVariants[v].kind == 2) return c->nbr_recorded;
