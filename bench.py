@@ -338,7 +338,13 @@ def main():
     # build algorithmic bytes per particle (cell ids 16, one 16-byte pass over the
     # high key bits, the bucket pass 16 + the gather 28, offsets 4 per cell)
     build_bytes = n * (16 + 16 + 16 + 28) + 4 * (nc + 1)
+    # the metric's two rates: forward (rebuild + forward) and forward + adjoint (the step), and the
+    # step's algorithmic HBM bytes (build + both calls) against the HBM peak
+    step_bytes = build_bytes + sum(v[3] for v in phases.values())
     breakdown = {"step_form": mode, "step_trials_ms": trial,
+                 "fwd_pairs_per_s": pairs / ((t_build + t_fwd) * 1e-3),
+                 "fwd_bwd_pairs_per_s": value,
+                 "step_hbm_frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                  "build_ms": t_build, "build_counting_ms": t_build_counting, "fwd_ms": t_fwd, "bwd_ms": t_bwd,
                  "box_search_fwd_ms": t_fwd_search, "box_search_bwd_ms": t_bwd_search,
                  "neighbour_list_record_ms": t_nbr, "replay_fwd_ms": t_fwd_list, "replay_bwd_ms": t_bwd_list,
@@ -410,6 +416,8 @@ def main():
         boxes5 = [A.BoxSpec(3, q.lo, q.hi, q.periodic, q.cutoff) for q in w5.systems]
         x5 = torch.from_numpy(xs5).to(dev)
         g5 = torch.from_numpy(w5.extra["gy"]).to(dev)
+        # cell size tuned for this batch (rebuild + spring forward)
+        boxes5, f5 = A.autotune_cells(ctx, x5, boxes5, off5, "spring", (1.0,))
         c5 = A.build_cells(ctx, x5, boxes5, off5)
         y5 = torch.empty((x5.shape[0], 3), device=dev)
         gx5 = torch.empty((x5.shape[0], 3), device=dev)
@@ -435,6 +443,7 @@ def main():
         ctx.sync()
         # the same systems' single-system rate reference: the headline cube's step rate
         extra["batch_512_systems"] = {"ms": m5, "particles": int(x5.shape[0]), "pairs": p5,
+                                      "cell_scale_factor": f5,
                                       "pairs_per_s": p5 / (m5 * 1e-3),
                                       "ratio_to_single_cube": (p5 / m5) / (pairs / ms), "step_forms_ms": t5}
         # the Section 3 example: N = 2^20 in the periodic unit square, r = sqrt(3/N), c = 1e-3, dt = 1,

@@ -305,6 +305,21 @@ aboria_status aboria_autotune(aboria_ctx* ctx, const aboria_cells* cells, aboria
                               const double* params_host, int32_t nparams, const void* a, int32_t na,
                               const void* gy, int32_t ny, void* out_scratch, int32_t* choice_host);
 
+/* Cell-size tuning: times a rebuild plus aboria_pair_sum (and, when gy is given,
+ * aboria_pair_sum_backward for that upstream gradient) of op on grids whose
+ * per-dimension cell counts are the automatic ones (or the boxes' explicit
+ * ones) scaled by 1, 0.85, 0.7 and 0.55 (rounded down, at least 1; coarser
+ * cells are always valid, finer ones are not), each with its work mapping
+ * tuned as by aboria_autotune (the tuned choices stay in ctx's cache).
+ * boxes_out[nsys] receives the input boxes with the fastest grid's explicit
+ * ncell; *factor_host (may be NULL) the chosen scale.  Arguments as for
+ * aboria_build_cells and aboria_autotune; allocates temporary cell lists and
+ * synchronises, so it cannot be captured. */
+aboria_status aboria_autotune_cells(aboria_ctx* ctx, aboria_dtype dtype, int32_t nsys, const aboria_box* boxes_host,
+                                    const int64_t* offsets_host, const void* x, aboria_op op,
+                                    const double* params_host, int32_t nparams, const void* a, int32_t na,
+                                    const void* gy, int32_t ny, aboria_box* boxes_out, double* factor_host);
+
 /* Without tuning or a forced variant, a sum on a cell list whose systems all
  * have at most 2048 particles tests all pairs of each system at the minimum
  * image (the small-N switch: no cell search; with an explicit cell count of 1

@@ -53,7 +53,7 @@ EXPORTS = ["aboria_create", "aboria_destroy", "aboria_set_stream", "aboria_last_
            "aboria_graph_destroy", "aboria_autotune", "aboria_variant_count", "aboria_variant_name",
            "aboria_set_variant", "aboria_op_ny", "aboria_op_na", "aboria_set_build_strategy",
            "aboria_build_neighbours", "aboria_neighbour_capacity", "aboria_integrate",
-           "aboria_dense_sum_backward"]
+           "aboria_dense_sum_backward", "aboria_autotune_cells"]
 
 
 def lib():
@@ -92,6 +92,8 @@ def lib():
             "aboria_build_neighbours": ([P, P, I32], I32),
             "aboria_neighbour_capacity": ([P], I32),
             "aboria_integrate": ([P, P, C.c_double, P, P, P], I32),
+            "aboria_autotune_cells": ([P, I32, I32, C.POINTER(Box), C.POINTER(I64), P, I32, C.POINTER(C.c_double),
+                                       I32, P, I32, P, I32, C.POINTER(Box), C.POINTER(C.c_double)], I32),
             "aboria_dense_sum_backward": ([P, I32, I32, C.POINTER(C.c_double), I32, I32, I64, P, I64, P, P, P,
                                            P, P, P], I32),
         }
@@ -401,6 +403,28 @@ def autotune(ctx: Context, cells: Cells, op: str, params=(), a: Optional[torch.T
                                C.byref(choice))
     ctx.check(st, "autotune")
     return int(choice.value)
+
+
+def autotune_cells(ctx: Context, x: torch.Tensor, boxes: Sequence[BoxSpec], offsets: Optional[Sequence[int]],
+                   op: str, params=(), a: Optional[torch.Tensor] = None, gy: Optional[torch.Tensor] = None):
+    """aboria_autotune_cells: (boxes with the fastest explicit cell counts, the chosen scale factor)."""
+    _check_dev(x, "x")
+    boxes = list(boxes)
+    nsys = len(boxes)
+    if offsets is None:
+        offsets = [0, int(x.shape[0])]
+    d = boxes[0].d
+    arr_b = (Box * nsys)(*[b.to_c() for b in boxes])
+    out_b = (Box * nsys)()
+    arr_o = (C.c_int64 * (nsys + 1))(*[int(o) for o in offsets])
+    arr, npar = _params(params)
+    factor = C.c_double(0.0)
+    st = lib().aboria_autotune_cells(ctx.handle, _dtype_code(x), nsys, arr_b, arr_o, _ptr(x), OPS[op], arr, npar,
+                                     _ptr(a), op_na(op), _ptr(gy), op_ny(op, d), out_b, C.byref(factor))
+    ctx.check(st, "autotune_cells")
+    tuned = [BoxSpec(b.d, b.lo, b.hi, b.periodic, b.cutoff, [int(out_b[i].ncell[k]) for k in range(d)])
+             for i, b in enumerate(boxes)]
+    return tuned, float(factor.value)
 
 
 def variant_count() -> int:

@@ -119,3 +119,90 @@ extern "C" aboria_status aboria_autotune(aboria_ctx* ctx, const aboria_cells* ce
         return fail(ctx, ABORIA_ERR_OUT_OF_MEMORY, "host exception in autotune");
     }
 }
+
+extern "C" aboria_status aboria_autotune_cells(aboria_ctx* ctx, aboria_dtype dtype, int32_t nsys,
+                                               const aboria_box* boxes_host, const int64_t* offsets_host,
+                                               const void* x, aboria_op op, const double* params_host,
+                                               int32_t nparams, const void* a, int32_t na, const void* gy,
+                                               int32_t ny, aboria_box* boxes_out, double* factor_host) {
+    if (!ctx) return ABORIA_ERR_INVALID_ARG;
+    if (ctx->capturing) return fail(ctx, ABORIA_ERR_UNSUPPORTED, "autotune cannot be captured");
+    if (nsys < 1 || !boxes_host || !offsets_host || !boxes_out)
+        return fail(ctx, ABORIA_ERR_INVALID_ARG, "need nsys >= 1, boxes, offsets and boxes_out");
+    if (dtype != ABORIA_F32 && dtype != ABORIA_F64) return fail(ctx, ABORIA_ERR_INVALID_ARG, "unknown dtype");
+    const int32_t d = boxes_host[0].d;
+    if (d < 1 || d > 3) return fail(ctx, ABORIA_ERR_INVALID_ARG, "d must be 1, 2 or 3");
+    if (op_ny(op, d) != ny) return fail(ctx, ABORIA_ERR_INVALID_ARG, "ny does not match the operator");
+    try {
+        // the grid every trial coarsens: the automatic (or given explicit) counts
+        std::vector<int32_t> base((size_t)nsys * 3, 1);
+        for (int32_t b = 0; b < nsys; ++b) {
+            aboria_status st = grid_counts(ctx, dtype, boxes_host[b], &base[(size_t)b * 3]);
+            if (st != ABORIA_OK) return st;
+        }
+        const int64_t n = offsets_host[nsys];
+        const size_t tsz = dtype == ABORIA_F32 ? 4 : 8;
+        ABORIA_HIP(ctx, hipSetDevice(ctx->device));
+        void* y = nullptr;
+        void* gx = nullptr;
+        const size_t nn = (size_t)std::max<int64_t>(n, 1);
+        if (hipMalloc(&y, tsz * nn * (size_t)std::max(ny, 1)) != hipSuccess ||
+            hipMalloc(&gx, tsz * nn * (size_t)d) != hipSuccess) {
+            (void)hipGetLastError();
+            if (y) (void)hipFree(y);
+            return fail(ctx, ABORIA_ERR_OUT_OF_MEMORY, "autotune scratch allocation failed");
+        }
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        aboria_status st = ABORIA_OK;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) st = ABORIA_ERR_DEVICE;
+        const double factors[] = {1.0, 0.85, 0.7, 0.55};
+        double best_ms = INFINITY, best_f = 1.0;
+        std::vector<aboria_box> trial(boxes_host, boxes_host + nsys), best_boxes(trial);
+        std::vector<int32_t> last;
+        for (double f : factors) {
+            if (st != ABORIA_OK) break;
+            std::vector<int32_t> counts(base.size());
+            for (size_t i = 0; i < base.size(); ++i) counts[i] = std::max<int32_t>(1, (int32_t)std::floor(f * base[i]));
+            if (counts == last) continue;  // the same grid as the previous factor
+            last = counts;
+            for (int32_t b = 0; b < nsys; ++b)
+                for (int k = 0; k < 3; ++k) trial[(size_t)b].ncell[k] = k < d ? counts[(size_t)b * 3 + k] : 0;
+            aboria_cells* cells = nullptr;
+            if ((st = aboria_build_cells(ctx, dtype, nsys, trial.data(), offsets_host, x, &cells)) != ABORIA_OK) break;
+            st = aboria_autotune(ctx, cells, op, params_host, nparams, a, na, nullptr, ny, y, nullptr);
+            if (st == ABORIA_OK && gy) st = aboria_autotune(ctx, cells, op, params_host, nparams, a, na, gy, ny, gx, nullptr);
+            const int reps = 3;
+            if (st == ABORIA_OK && hipEventRecord(e0, ctx->stream) != hipSuccess) st = ABORIA_ERR_DEVICE;
+            for (int r = 0; r < reps && st == ABORIA_OK; ++r) {
+                st = aboria_build_cells(ctx, dtype, nsys, trial.data(), offsets_host, x, &cells);
+                if (st == ABORIA_OK) st = aboria_pair_sum(ctx, cells, op, params_host, nparams, a, na, y, ny);
+                if (st == ABORIA_OK && gy)
+                    st = aboria_pair_sum_backward(ctx, cells, op, params_host, nparams, a, na, gy, ny, gx, nullptr);
+            }
+            float ms = 0.f;
+            if (st == ABORIA_OK && (hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                st = ABORIA_ERR_DEVICE;
+            (void)hipStreamSynchronize(ctx->stream);
+            (void)aboria_cells_destroy(cells);
+            if (st == ABORIA_OK && ms / reps < best_ms) {
+                best_ms = ms / reps;
+                best_f = f;
+                best_boxes = trial;
+            }
+        }
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        (void)hipFree(y);
+        (void)hipFree(gx);
+        if (st != ABORIA_OK) {
+            if (ctx->last_error.empty()) ctx->last_error = "autotune_cells: a trial failed";
+            return st;
+        }
+        for (int32_t b = 0; b < nsys; ++b) boxes_out[b] = best_boxes[(size_t)b];
+        if (factor_host) *factor_host = best_f;
+        return ABORIA_OK;
+    } catch (...) {
+        return fail(ctx, ABORIA_ERR_OUT_OF_MEMORY, "host exception in autotune_cells");
+    }
+}

@@ -766,6 +766,13 @@ aboria_status dispatch_build(aboria_ctx* ctx, aboria_cells* c, const void* x) {
 
 }  // namespace
 
+aboria_status grid_counts(aboria_ctx* ctx, int dtype, const aboria_box& b, int32_t n[3]) {
+    GridPlan g;
+    aboria_status s = plan_grid(ctx, dtype, b, &g);
+    for (int k = 0; k < 3; ++k) n[k] = g.n[k];
+    return s;
+}
+
 }  // namespace aboria
 
 using namespace aboria;

@@ -159,6 +159,10 @@ inline bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
     return a0 < b0 + nb && b0 < a0 + na;
 }
 
+// Cells per dimension of a box under the cell-count rule (or its explicit
+// counts); fails like aboria_build_cells on an invalid box.
+aboria_status grid_counts(aboria_ctx* ctx, int dtype, const aboria_box& b, int32_t n[3]);
+
 int32_t op_ny(int32_t op, int32_t d);
 int32_t op_na(int32_t op);
 int32_t op_nparams(int32_t op);

@@ -66,8 +66,7 @@ __global__ __launch_bounds__(256) void k_all_bwd(const T* __restrict__ xs, const
     load_point<T, D>(xs, sc, xi);
     const T ai = OpShape<OP, D>::NA ? a_s[sc] : T(0);
     T gyi[NY];
-#pragma unroll
-    for (int k = 0; k < NY; ++k) gyi[k] = gy_s[(size_t)sc * NY + k];
+    load_gy<T, NY>(gy_s, sc, gyi);
     T accx[D], acca[1] = {T(0)};
 #pragma unroll
     for (int k = 0; k < D; ++k) accx[k] = T(0);
@@ -75,8 +74,7 @@ __global__ __launch_bounds__(256) void k_all_bwd(const T* __restrict__ xs, const
     auto visit = [&](uint32_t j, const T* dx, T d2, bool) {
         const T aj = OpShape<OP, D>::NA ? a_s[j] : T(0);
         T gyj[NY];
-#pragma unroll
-        for (int k = 0; k < NY; ++k) gyj[k] = gy_s[(size_t)j * NY + k];
+        load_gy<T, NY>(gy_s, j, gyj);
         Op::bwd(q, r, dx, d2, ai, aj, gyi, gyj, accx, acca);
     };
     if (live) allpairs_loop<T, D>(P, xs, P.part_base + lane, P.part_end, G, xi, visit);

@@ -194,8 +194,9 @@ __global__ __launch_bounds__(BLOCK) void k_pair_cells(
 #pragma unroll
                     for (int k = 0; k < D; ++k) xi[qq][k] = Far<T>::home();
                 }
-#pragma unroll
-                for (int k = 0; k < NY; ++k) gyi[qq][k] = (BWD && live) ? gy_s[(size_t)s * NY + k] : T(0);
+                if (BWD && live) load_gy<T, NY>(gy_s, s, gyi[qq]);
+                else
+                    for (int k = 0; k < NY; ++k) gyi[qq][k] = T(0);
                 ai[qq] = (HAS_A && live) ? a_s[s] : T(0);
 #pragma unroll
                 for (int k = 0; k < (BWD ? D : NY); ++k) acc[qq][k] = T(0);
@@ -223,8 +224,7 @@ __global__ __launch_bounds__(BLOCK) void k_pair_cells(
                         }
                         if (HAS_A) aj = a_s[slot];
                         if (BWD) {
-#pragma unroll
-                            for (int k = 0; k < NY; ++k) gyj[k] = gy_s[(size_t)slot * NY + k];
+                            load_gy<T, NY>(gy_s, slot, gyj);
                         }
                     } else {
 #pragma unroll

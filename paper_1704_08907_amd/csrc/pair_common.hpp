@@ -220,6 +220,39 @@ __device__ __forceinline__ int system_of_row(const uint32_t* __restrict__ sys_pa
     return b;
 }
 
+// Rows of the upstream gradient in cell order: 3-wide rows are padded to 4 so
+// that one 16-byte (float) or 32-byte (double) load fetches a row.
+template <int NY>
+struct GyPitch {
+    static constexpr int value = NY == 3 ? 4 : NY;
+};
+
+// Element j of an array of N-element rows.  OFF32: the byte offset j * row size
+// fits in 32 bits (the launcher checks it), so the load takes a scalar base and
+// a 32-bit lane offset and its address costs one full-rate add.
+template <typename T, int N, bool OFF32>
+__device__ __forceinline__ VecN<T, N> load_row(const T* __restrict__ base, uint32_t j) {
+    if constexpr (OFF32)
+        return *reinterpret_cast<const VecN<T, N>*>(reinterpret_cast<const char*>(base) +
+                                                   (uint32_t)(j * (uint32_t)sizeof(VecN<T, N>)));
+    else
+        return reinterpret_cast<const VecN<T, N>*>(base)[j];
+}
+
+// True when every per-particle row the sums load (at most 4 elements of T)
+// lies below a 32-bit byte offset, so the kernels may use 32-bit offsets.
+template <typename T>
+inline bool off32_rows(uint64_t n) {
+    return n * 4 * sizeof(T) <= 0xFFFFFFFFull;
+}
+
+template <typename T, int NY, bool OFF32 = false>
+__device__ __forceinline__ void load_gy(const T* __restrict__ gy_s, uint32_t j, T* out) {
+    const VecN<T, GyPitch<NY>::value> v = load_row<T, GyPitch<NY>::value, OFF32>(gy_s, j);
+#pragma unroll
+    for (int k = 0; k < NY; ++k) out[k] = v.v[k];
+}
+
 template <typename T, int D>
 __device__ __forceinline__ void load_point(const T* __restrict__ xs, uint32_t s, T* xi) {
     constexpr int PITCH = Pitch<D>::value;
@@ -248,21 +281,20 @@ __device__ __forceinline__ bool pair_test(const T* xj, const T* xi, const T* sh,
 // visit(j, dx, d2, shifted) for the accepted ones, shifted = the lane's shift
 // is nonzero in some dimension.  Two candidates are loaded per iteration so
 // their loads overlap.
-template <typename T, int D, bool SHIFT, typename Visit>
+template <typename T, int D, bool SHIFT, bool OFF32, typename Visit>
 __device__ __forceinline__ void scan_range(const T* __restrict__ xs, uint32_t j0, uint32_t j1, const T* xi,
                                            const T* sh, T r2, bool shifted, Visit& visit) {
     constexpr int PITCH = Pitch<D>::value;
-    const VecN<T, PITCH>* __restrict__ xv = reinterpret_cast<const VecN<T, PITCH>*>(xs);
     uint32_t j = j0;
     for (; j + 1 < j1; j += 2) {
-        const VecN<T, PITCH> a = xv[j];
-        const VecN<T, PITCH> b = xv[j + 1];
+        const VecN<T, PITCH> a = load_row<T, PITCH, OFF32>(xs, j);
+        const VecN<T, PITCH> b = load_row<T, PITCH, OFF32>(xs, j + 1);
         T dx[D], d2;
         if (pair_test<T, D, SHIFT>(a.v, xi, sh, r2, dx, &d2)) visit(j, dx, d2, shifted);
         if (pair_test<T, D, SHIFT>(b.v, xi, sh, r2, dx, &d2)) visit(j + 1, dx, d2, shifted);
     }
     if (j < j1) {
-        const VecN<T, PITCH> a = xv[j];
+        const VecN<T, PITCH> a = load_row<T, PITCH, OFF32>(xs, j);
         T dx[D], d2;
         if (pair_test<T, D, SHIFT>(a.v, xi, sh, r2, dx, &d2)) visit(j, dx, d2, shifted);
     }
@@ -274,7 +306,7 @@ __device__ __forceinline__ void scan_range(const T* __restrict__ xs, uint32_t j0
 // image shift.  A piece whose shift is zero on every active lane of the wave
 // runs the loop without the shift additions (adding zero is exact, so both
 // loops give the canonical dx).
-template <typename T, int D, typename Visit>
+template <typename T, int D, bool OFF32 = false, typename Visit>
 __device__ __forceinline__ void neighbour_loop(const SysParams<T>& P, const T* __restrict__ xs,
                                                const uint32_t* __restrict__ off, uint32_t n, const T* xi,
                                                Visit&& visit) {
@@ -337,9 +369,155 @@ __device__ __forceinline__ void neighbour_loop(const SysParams<T>& P, const T* _
             bool lane_shift = false;
 #pragma unroll
             for (int k = 0; k < D; ++k) lane_shift |= sh[k] != T(0);
-            if (__ballot(lane_shift) != 0ull) scan_range<T, D, true>(xs, j0, j1, xi, sh, r2, lane_shift, visit);
-            else scan_range<T, D, false>(xs, j0, j1, xi, sh, r2, false, visit);
+            if (__ballot(lane_shift) != 0ull)
+                scan_range<T, D, true, OFF32>(xs, j0, j1, xi, sh, r2, lane_shift, visit);
+            else
+                scan_range<T, D, false, OFF32>(xs, j0, j1, xi, sh, r2, false, visit);
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// box search with the candidates of a stencil row staged in LDS per wave
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, m));
+    return v;
+}
+template <typename T>
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, m));
+    return v;
+}
+
+// The same box search as neighbour_loop (same candidates, same order, same
+// canonical dx), but for each stencil row the wave first copies the span of
+// slots its lanes will read -- [min over lanes of the row's first slot, max of
+// its last) -- into its own LDS region with coalesced loads, and the lanes then
+// read their candidates from LDS (lanes of one home cell read the same entries,
+// which the LDS broadcasts) instead of each issuing its own global load.  A
+// span longer than CAP (a wave across two rows of cells, or a wrap piece at the
+// far end of a long row) is read from global memory as before.  Every lane of
+// the wave must call it (live = false for lanes past the end), because the
+// span is a wave-wide reduction.
+template <typename T, int D, int CAP, typename Visit>
+__device__ __forceinline__ void neighbour_loop_staged(const SysParams<T>& P, const T* __restrict__ xs,
+                                                      const uint32_t* __restrict__ off, uint32_t n, const T* xi,
+                                                      bool live, VecN<T, Pitch<D>::value>* stage, Visit&& visit) {
+    constexpr int PITCH = Pitch<D>::value;
+    const uint32_t lane = __lane_id();
+    int32_t c[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const T t = xi[k] - P.lo[k];
+        const T q = t * P.inv_w[k];
+        const T f = floor(q);
+        c[k] = !(f >= T(0)) ? 0 : (f > T(P.n[k] - 1) ? P.n[k] - 1 : (int32_t)f);
+    }
+    const int32_t nx = P.n[0];
+    int np = 0;
+    int32_t plo[3], phi[3];
+    T psh[3];
+    if (nx >= 3) {
+        plo[0] = c[0] > 0 ? c[0] - 1 : 0;
+        phi[0] = c[0] < nx - 1 ? c[0] + 1 : nx - 1;
+        psh[0] = T(0);
+        np = 1;
+        if (P.periodic[0]) {
+            if (c[0] == 0) { plo[np] = phi[np] = nx - 1; psh[np] = -P.L[0]; ++np; }
+            if (c[0] == nx - 1) { plo[np] = phi[np] = 0; psh[np] = P.L[0]; ++np; }
+        }
+    } else {
+        for (int o = -1; o <= 1; ++o) {
+            int32_t v = c[0] + o;
+            T s = T(0);
+            if (v < 0) { if (!P.periodic[0]) continue; v += nx; s = -P.L[0]; }
+            else if (v >= nx) { if (!P.periodic[0]) continue; v -= nx; s = P.L[0]; }
+            plo[np] = phi[np] = v;
+            psh[np] = s;
+            ++np;
+        }
+    }
+    if (!live) np = 0;
+    constexpr int NROWS = D == 1 ? 1 : (D == 2 ? 3 : 9);
+    const T r2 = P.r2;
+    for (int rr = 0; rr < NROWS; ++rr) {
+        T sh[3] = {T(0), T(0), T(0)};
+        uint32_t row = 0;
+        bool skip = false;
+        if constexpr (D >= 2) {
+            int32_t v = c[1] + (rr % 3) - 1;
+            if (v < 0) { if (!P.periodic[1]) skip = true; v += P.n[1]; sh[1] = -P.L[1]; }
+            else if (v >= P.n[1]) { if (!P.periodic[1]) skip = true; v -= P.n[1]; sh[1] = P.L[1]; }
+            row = (uint32_t)v;
+        }
+        if constexpr (D >= 3) {
+            int32_t v = c[2] + (rr / 3) - 1;
+            if (v < 0) { if (!P.periodic[2]) skip = true; v += P.n[2]; sh[2] = -P.L[2]; }
+            else if (v >= P.n[2]) { if (!P.periodic[2]) skip = true; v -= P.n[2]; sh[2] = P.L[2]; }
+            row += (uint32_t)P.n[1] * (uint32_t)v;
+        }
+        const int npr = skip ? 0 : np;
+        const uint32_t rowbase = P.cell_base + (uint32_t)nx * row;
+        uint32_t j0[3], j1[3];
+        uint32_t lo = 0xFFFFFFFFu, hi = 0u;
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+            j0[p] = j1[p] = 0u;
+            if (p < npr) {
+                j0[p] = off[rowbase + plo[p]];
+                j1[p] = min(off[rowbase + phi[p] + 1], n);
+                if (j1[p] > j0[p]) {
+                    lo = min(lo, j0[p]);
+                    hi = max(hi, j1[p]);
+                }
+            }
+        }
+        lo = wave_min_u32<T>(lo);
+        hi = wave_max_u32<T>(hi);
+        const bool staged = hi > lo && hi - lo <= (uint32_t)CAP;
+        if (staged) {
+            __builtin_amdgcn_wave_barrier();
+            for (uint32_t t = lane; t < hi - lo; t += kWave) stage[t] = load_row<T, PITCH, true>(xs, lo + t);
+            __builtin_amdgcn_wave_barrier();
+        }
+        for (int p = 0; p < npr; ++p) {
+            sh[0] = psh[p];
+            bool lane_shift = false;
+#pragma unroll
+            for (int k = 0; k < D; ++k) lane_shift |= sh[k] != T(0);
+            const bool any_shift = __ballot(lane_shift) != 0ull;
+            if (staged) {
+                const VecN<T, PITCH>* src = stage - lo;
+                auto scan = [&](auto shift_tag) {
+                    constexpr bool SHIFT = decltype(shift_tag)::value;
+                    uint32_t j = j0[p];
+                    for (; j + 1 < j1[p]; j += 2) {
+                        const VecN<T, PITCH> a = src[j];
+                        const VecN<T, PITCH> b = src[j + 1];
+                        T dx[D], d2;
+                        if (pair_test<T, D, SHIFT>(a.v, xi, sh, r2, dx, &d2)) visit(j, dx, d2, lane_shift);
+                        if (pair_test<T, D, SHIFT>(b.v, xi, sh, r2, dx, &d2)) visit(j + 1, dx, d2, lane_shift);
+                    }
+                    if (j < j1[p]) {
+                        const VecN<T, PITCH> a = src[j];
+                        T dx[D], d2;
+                        if (pair_test<T, D, SHIFT>(a.v, xi, sh, r2, dx, &d2)) visit(j, dx, d2, lane_shift);
+                    }
+                };
+                if (any_shift) scan(std::integral_constant<bool, true>());
+                else scan(std::integral_constant<bool, false>());
+            } else if (any_shift) {
+                scan_range<T, D, true, true>(xs, j0[p], j1[p], xi, sh, r2, lane_shift, visit);
+            } else {
+                scan_range<T, D, false, true>(xs, j0[p], j1[p], xi, sh, r2, false, visit);
+            }
+        }
+        if (staged) __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -543,6 +721,14 @@ void launch_nbr_fwd(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, 
 template <typename T, int D, int OP, bool BATCH>
 void launch_nbr_bwd(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, const T* gy_s, T* gx,
                     T* ga);
+
+// Lane-per-particle forward / adjoint whose candidates are staged in LDS per
+// stencil row (needs 32-bit row offsets: off32_rows).
+template <typename T, int D, int OP, bool BATCH>
+void launch_stage_fwd(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, T* y);
+template <typename T, int D, int OP, bool BATCH>
+void launch_stage_bwd(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, const T* gy_s, T* gx,
+                      T* ga);
 
 // Forward / adjoint over every particle of the lane's system (minimum image).
 template <typename T, int D, int OP, bool BATCH>

@@ -16,7 +16,7 @@
 
 namespace aboria {
 
-template <typename T, int D, int OP, bool BATCH>
+template <typename T, int D, int OP, bool BATCH, bool OFF32>
 __global__ __launch_bounds__(256) void k_lane_bwd(const T* __restrict__ xs, const uint32_t* __restrict__ off,
                                                   const uint32_t* __restrict__ perm, uint32_t n,
                                                   const SysParams<T>* __restrict__ sp,
@@ -34,20 +34,18 @@ __global__ __launch_bounds__(256) void k_lane_bwd(const T* __restrict__ xs, cons
     load_point<T, D>(xs, s, xi);
     const T ai = OpShape<OP, D>::NA ? a_s[s] : T(0);
     T gyi[NY];
-#pragma unroll
-    for (int k = 0; k < NY; ++k) gyi[k] = gy_s[(size_t)s * NY + k];
+    load_gy<T, NY, OFF32>(gy_s, s, gyi);
     T accx[D], acca[1] = {T(0)};
 #pragma unroll
     for (int k = 0; k < D; ++k) accx[k] = T(0);
     const T r = P.r;
     auto visit = [&](uint32_t j, const T* dx, T d2, bool) {
-        const T aj = OpShape<OP, D>::NA ? a_s[j] : T(0);
+        const T aj = OpShape<OP, D>::NA ? load_row<T, 1, OFF32>(a_s, j).v[0] : T(0);
         T gyj[NY];
-#pragma unroll
-        for (int k = 0; k < NY; ++k) gyj[k] = gy_s[(size_t)j * NY + k];
+        load_gy<T, NY, OFF32>(gy_s, j, gyj);
         Op::bwd(q, r, dx, d2, ai, aj, gyi, gyj, accx, acca);
     };
-    neighbour_loop<T, D>(P, xs, off, n, xi, visit);
+    neighbour_loop<T, D, OFF32>(P, xs, off, n, xi, visit);
     const uint32_t o = perm[s];
 #pragma unroll
     for (int k = 0; k < D; ++k) gx[(size_t)o * D + k] = accx[k];
@@ -74,8 +72,7 @@ __global__ __launch_bounds__(BLOCK) void k_lane_bwd_compact(
     load_point<T, D>(xs, s, xi);
     const T ai = OpShape<OP, D>::NA ? a_s[s] : T(0);
     T gyi[NY];
-#pragma unroll
-    for (int k = 0; k < NY; ++k) gyi[k] = gy_s[(size_t)s * NY + k];
+    load_gy<T, NY>(gy_s, s, gyi);
     T accx[D], acca[1] = {T(0)};
 #pragma unroll
     for (int k = 0; k < D; ++k) accx[k] = T(0);
@@ -105,8 +102,7 @@ __global__ __launch_bounds__(BLOCK) void k_lane_bwd_compact(
             if constexpr (D >= 3) d2 = fma_t(dx[2], dx[2], d2);
             const T aj = OpShape<OP, D>::NA ? a_s[j] : T(0);
             T gyj[NY];
-#pragma unroll
-            for (int m = 0; m < NY; ++m) gyj[m] = gy_s[(size_t)j * NY + m];
+            load_gy<T, NY>(gy_s, j, gyj);
             Op::bwd(q, r, dx, d2, ai, aj, gyi, gyj, accx, acca);
         }
         cnt = 0;
@@ -157,8 +153,12 @@ __global__ __launch_bounds__(256) void k_lane_bwd_queue(
     const SysParams<T> P = sp[b];
     T xi[D];
     load_point<T, D>(xs, sc, xi);
+    {
+        T g[NY];
+        load_gy<T, NY>(gy_s, sc, g);
 #pragma unroll
-    for (int k = 0; k < NY; ++k) s_gyi[w][k][lane] = live ? gy_s[(size_t)sc * NY + k] : T(0);
+        for (int k = 0; k < NY; ++k) s_gyi[w][k][lane] = live ? g[k] : T(0);
+    }
     s_ai[w][lane] = (HAS_A && live) ? a_s[sc] : T(0);
 #pragma unroll
     for (int k = 0; k <= D; ++k) s_acc[w][k][lane] = T(0);
@@ -179,11 +179,9 @@ __global__ __launch_bounds__(256) void k_lane_bwd_queue(
             if constexpr (D >= 2) d2 = fma_t(dx[1], dx[1], d2);
             if constexpr (D >= 3) d2 = fma_t(dx[2], dx[2], d2);
             T gyi[NY], gyj[NY];
+            load_gy<T, NY>(gy_s, j, gyj);
 #pragma unroll
-            for (int k = 0; k < NY; ++k) {
-                gyi[k] = s_gyi[w][k][own];
-                gyj[k] = gy_s[(size_t)j * NY + k];
-            }
+            for (int k = 0; k < NY; ++k) gyi[k] = s_gyi[w][k][own];
             const T ai = s_ai[w][own];
             const T aj = HAS_A ? a_s[j] : T(0);
             T c[D], ca[1] = {T(0)};
@@ -305,9 +303,14 @@ void launch_lane_bwd(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q,
         hipLaunchKernelGGL((k_lane_bwd_compact<T, D, OP, BATCH, 256, 48>), dim3((n + 255) / 256), dim3(256), 0,
                            ctx->stream, (const T*)c->xs, c->off, c->perm, n, sp, c->sys_part_dev, c->nsys, a_s, gy_s,
                            q, gx, ga);
+    } else if (off32_rows<T>(n)) {
+        hipLaunchKernelGGL((k_lane_bwd<T, D, OP, BATCH, true>), dim3((n + block - 1) / block), dim3(block), 0,
+                           ctx->stream, (const T*)c->xs, c->off, c->perm, n, sp, c->sys_part_dev, c->nsys, a_s, gy_s,
+                           q, gx, ga);
     } else {
-        hipLaunchKernelGGL((k_lane_bwd<T, D, OP, BATCH>), dim3((n + block - 1) / block), dim3(block), 0, ctx->stream,
-                           (const T*)c->xs, c->off, c->perm, n, sp, c->sys_part_dev, c->nsys, a_s, gy_s, q, gx, ga);
+        hipLaunchKernelGGL((k_lane_bwd<T, D, OP, BATCH, false>), dim3((n + block - 1) / block), dim3(block), 0,
+                           ctx->stream, (const T*)c->xs, c->off, c->perm, n, sp, c->sys_part_dev, c->nsys, a_s, gy_s,
+                           q, gx, ga);
     }
 }
 

@@ -5,7 +5,7 @@
 
 namespace aboria {
 
-template <typename T, int D, int OP, bool BATCH>
+template <typename T, int D, int OP, bool BATCH, bool OFF32>
 __global__ __launch_bounds__(256) void k_lane_fwd(const T* __restrict__ xs, const uint32_t* __restrict__ off,
                                                   const uint32_t* __restrict__ perm, uint32_t n,
                                                   const SysParams<T>* __restrict__ sp,
@@ -26,10 +26,10 @@ __global__ __launch_bounds__(256) void k_lane_fwd(const T* __restrict__ xs, cons
     for (int k = 0; k < NY; ++k) acc[k] = T(0);
     const T r = P.r;
     auto visit = [&](uint32_t j, const T* dx, T d2, bool) {
-        const T aj = OpShape<OP, D>::NA ? a_s[j] : T(0);
+        const T aj = OpShape<OP, D>::NA ? load_row<T, 1, OFF32>(a_s, j).v[0] : T(0);
         Op::fwd(q, r, dx, d2, ai, aj, acc);
     };
-    neighbour_loop<T, D>(P, xs, off, n, xi, visit);
+    neighbour_loop<T, D, OFF32>(P, xs, off, n, xi, visit);
     const uint32_t o = perm[s];
 #pragma unroll
     for (int k = 0; k < NY; ++k) y[(size_t)o * NY + k] = acc[k];
@@ -39,9 +39,14 @@ template <typename T, int D, int OP, bool BATCH>
 void launch_lane_fwd(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, T* y, int block) {
     const uint32_t n = (uint32_t)c->n;
     const dim3 grid((n + block - 1) / block);
-    hipLaunchKernelGGL((k_lane_fwd<T, D, OP, BATCH>), grid, dim3(block), 0, ctx->stream, (const T*)c->xs, c->off,
-                       c->perm, n, reinterpret_cast<const SysParams<T>*>(c->params_dev), c->sys_part_dev, c->nsys,
-                       a_s, q, y);
+    if (off32_rows<T>(n))
+        hipLaunchKernelGGL((k_lane_fwd<T, D, OP, BATCH, true>), grid, dim3(block), 0, ctx->stream, (const T*)c->xs,
+                           c->off, c->perm, n, reinterpret_cast<const SysParams<T>*>(c->params_dev), c->sys_part_dev,
+                           c->nsys, a_s, q, y);
+    else
+        hipLaunchKernelGGL((k_lane_fwd<T, D, OP, BATCH, false>), grid, dim3(block), 0, ctx->stream, (const T*)c->xs,
+                           c->off, c->perm, n, reinterpret_cast<const SysParams<T>*>(c->params_dev), c->sys_part_dev,
+                           c->nsys, a_s, q, y);
 }
 
 #define ABORIA_INST(T, D, OP, BATCH)                                                                   \

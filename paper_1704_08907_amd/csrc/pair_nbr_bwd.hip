@@ -29,8 +29,7 @@ __global__ __launch_bounds__(256) void k_nbr_bwd(const T* __restrict__ xs, const
     load_point<T, D>(xs, s, xi);
     const T ai = OpShape<OP, D>::NA ? a_s[s] : T(0);
     T gyi[NY];
-#pragma unroll
-    for (int k = 0; k < NY; ++k) gyi[k] = gy_s[(size_t)s * NY + k];
+    load_gy<T, NY>(gy_s, s, gyi);
     T accx[D], acca[1] = {T(0)};
 #pragma unroll
     for (int k = 0; k < D; ++k) accx[k] = T(0);
@@ -38,8 +37,7 @@ __global__ __launch_bounds__(256) void k_nbr_bwd(const T* __restrict__ xs, const
     auto pair = [&](uint32_t j, const T* dx, T d2) {
         const T aj = OpShape<OP, D>::NA ? a_s[j] : T(0);
         T gyj[NY];
-#pragma unroll
-        for (int k = 0; k < NY; ++k) gyj[k] = gy_s[(size_t)j * NY + k];
+        load_gy<T, NY>(gy_s, j, gyj);
         Op::bwd(q, r, dx, d2, ai, aj, gyi, gyj, accx, acca);
     };
     const uint32_t cnt = nbr_count[s];

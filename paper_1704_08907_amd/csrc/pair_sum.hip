@@ -45,18 +45,19 @@ __global__ __launch_bounds__(kPairBlock) void k_pair_list(const T* __restrict__ 
     if (!FILL) counts[s] = cnt;
 }
 
-// dst[s][:] = src[perm[s]][:] for rows of W elements (W <= 4): one thread per row.
-template <typename T, int W>
+// dst[s][:] = src[perm[s]][:] for rows of W elements (W <= 4), written with a
+// row pitch of WP elements (3-wide rows are padded to 4, zero-filled, so that
+// the sums load a row with one vector load): one thread per row.
+template <typename T, int W, int WP>
 __global__ __launch_bounds__(256) void k_gather_rows(const T* __restrict__ src, const uint32_t* __restrict__ perm,
                                                      uint32_t n, T* __restrict__ dst) {
     const uint32_t s = blockIdx.x * 256 + threadIdx.x;
     if (s >= n) return;
     const uint32_t p = perm[s];
-    T v[W];
+    VecN<T, WP> v;
 #pragma unroll
-    for (int k = 0; k < W; ++k) v[k] = src[(size_t)p * W + k];
-#pragma unroll
-    for (int k = 0; k < W; ++k) dst[(size_t)s * W + k] = v[k];
+    for (int k = 0; k < WP; ++k) v.v[k] = k < W ? src[(size_t)p * W + k] : T(0);
+    reinterpret_cast<VecN<T, WP>*>(dst)[s] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -70,11 +71,13 @@ aboria_status gather(aboria_ctx* ctx, const aboria_cells* c, const void* src, in
     const uint32_t n = (uint32_t)c->n;
     if (n == 0 || w == 0) return ABORIA_OK;
     const dim3 grid((n + 255) / 256);
+    const T* s = (const T*)src;
+    T* d = (T*)dst;
     switch (w) {
-        case 1: hipLaunchKernelGGL((k_gather_rows<T, 1>), grid, dim3(256), 0, ctx->stream, (const T*)src, c->perm, n, (T*)dst); break;
-        case 2: hipLaunchKernelGGL((k_gather_rows<T, 2>), grid, dim3(256), 0, ctx->stream, (const T*)src, c->perm, n, (T*)dst); break;
-        case 3: hipLaunchKernelGGL((k_gather_rows<T, 3>), grid, dim3(256), 0, ctx->stream, (const T*)src, c->perm, n, (T*)dst); break;
-        default: hipLaunchKernelGGL((k_gather_rows<T, 4>), grid, dim3(256), 0, ctx->stream, (const T*)src, c->perm, n, (T*)dst); break;
+        case 1: hipLaunchKernelGGL((k_gather_rows<T, 1, 1>), grid, dim3(256), 0, ctx->stream, s, c->perm, n, d); break;
+        case 2: hipLaunchKernelGGL((k_gather_rows<T, 2, 2>), grid, dim3(256), 0, ctx->stream, s, c->perm, n, d); break;
+        case 3: hipLaunchKernelGGL((k_gather_rows<T, 3, 4>), grid, dim3(256), 0, ctx->stream, s, c->perm, n, d); break;
+        default: hipLaunchKernelGGL((k_gather_rows<T, 4, 4>), grid, dim3(256), 0, ctx->stream, s, c->perm, n, d); break;
     }
     ABORIA_HIP(ctx, hipGetLastError());
     return ABORIA_OK;
@@ -98,10 +101,15 @@ const Variant kVariants[] = {
     {1, 128, false, 8, "cell group of 16 lanes per home cell, 64-cell tiles ranked by occupancy"},
     {2, 256, false, 0, "lane per particle over the recorded neighbour list (accepted pairs only)"},
     {3, 256, false, 0, "lane per particle over all particles of its system (minimum image; small systems)"},
+    {4, 256, false, 0, "lane per particle, candidates staged in LDS per stencil row and wave"},
 };
 
 // Largest system the all-pairs variant accepts (its lanes test every particle of their system).
 constexpr int64_t kAllPairsMaxSystem = 16384;
+
+bool off32_ok(const aboria_cells* c) {
+    return c->dtype == ABORIA_F32 ? off32_rows<float>((uint64_t)c->n) : off32_rows<double>((uint64_t)c->n);
+}
 
 int64_t largest_system(const aboria_cells* c) {
     int64_t m = 0;
@@ -113,7 +121,8 @@ constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 template <typename T, int D, int OP, bool BATCH>
 void launch_fwd_variant(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, T* y,
                         const Variant& v) {
-    if (v.kind == 3) launch_all_fwd<T, D, OP, BATCH>(ctx, c, q, a_s, y);
+    if (v.kind == 4) launch_stage_fwd<T, D, OP, BATCH>(ctx, c, q, a_s, y);
+    else if (v.kind == 3) launch_all_fwd<T, D, OP, BATCH>(ctx, c, q, a_s, y);
     else if (v.kind == 2) launch_nbr_fwd<T, D, OP, BATCH>(ctx, c, q, a_s, y);
     else if (v.kind == 1) launch_cells_fwd<T, D, OP, BATCH>(ctx, c, q, a_s, y, v.rounds);
     else launch_lane_fwd<T, D, OP, BATCH>(ctx, c, q, a_s, y, v.block > 256 ? 256 : v.block);
@@ -122,7 +131,8 @@ void launch_fwd_variant(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>&
 template <typename T, int D, int OP, bool BATCH>
 void launch_bwd_variant(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, const T* gy_s,
                         T* gx, T* ga, const Variant& v) {
-    if (v.kind == 3) launch_all_bwd<T, D, OP, BATCH>(ctx, c, q, a_s, gy_s, gx, ga);
+    if (v.kind == 4) launch_stage_bwd<T, D, OP, BATCH>(ctx, c, q, a_s, gy_s, gx, ga);
+    else if (v.kind == 3) launch_all_bwd<T, D, OP, BATCH>(ctx, c, q, a_s, gy_s, gx, ga);
     else if (v.kind == 2) launch_nbr_bwd<T, D, OP, BATCH>(ctx, c, q, a_s, gy_s, gx, ga);
     else if (v.kind == 1) launch_cells_bwd<T, D, OP, BATCH>(ctx, c, q, a_s, gy_s, gx, ga, v.rounds);
     else launch_lane_bwd<T, D, OP, BATCH>(ctx, c, q, a_s, gy_s, gx, ga, v.block, v.compact);
@@ -193,6 +203,8 @@ aboria_status check_variant(aboria_ctx* ctx, const aboria_cells* c, int variant)
         return fail(ctx, ABORIA_ERR_INVALID_ARG, "the variant needs a neighbour list recorded on these cells");
     if (variant_of(variant).kind == 3 && largest_system(c) > kAllPairsMaxSystem)
         return fail(ctx, ABORIA_ERR_INVALID_ARG, "the all-pairs variant takes systems of at most 16384 particles");
+    if (variant_of(variant).kind == 4 && !off32_ok(c))
+        return fail(ctx, ABORIA_ERR_INVALID_ARG, "the staged variant needs rows below a 32-bit byte offset");
     return ABORIA_OK;
 }
 
@@ -217,6 +229,7 @@ bool variant_usable(int32_t v, const aboria_cells* c) {
     if (v < 0 || v >= kNumVariants) return false;
     if (kVariants[v].kind == 2) return c->nbr_recorded;
     if (kVariants[v].kind == 3) return largest_system(c) <= kAllPairsMaxSystem;
+    if (kVariants[v].kind == 4) return off32_ok(c);
     return true;
 }
 

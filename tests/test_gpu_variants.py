@@ -1,0 +1,102 @@
+"""Variants that keep the box search's candidate order and arithmetic give the
+plain lane kernel's results bit for bit: the LDS-staged lane kernels on every
+parity case (1-3 d, periodic and open, float32 and float64) and on a batch."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1704_08907_amd as A
+from paper_1704_08907_amd import synthetic as syn
+from _parity import box_of, to_dev
+from test_gpu_parity import CASES, OPS, make_case
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = A.Context(0)
+    yield c
+    c.set_variant(-1)
+    c.close()
+
+
+def variant(word):
+    return next(v for v in range(A.variant_count()) if word in A.variant_name(v))
+
+
+def both(ctx, cells, op, params, a_d, gy_d, v):
+    ctx.set_variant(v)
+    try:
+        y = A.pair_sum(ctx, cells, op, params, a_d)
+        gx, ga = A.pair_sum_backward(ctx, cells, op, params, gy_d, a_d)
+    finally:
+        ctx.set_variant(-1)
+    return y, gx, ga
+
+
+def same(u, v):
+    return (u is None and v is None) or torch.equal(u, v)
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_staged_equals_plain_lane_kernel(ctx, case):
+    g, x, box, prec = make_case(case)
+    n, d = x.shape
+    print("case", case[0], flush=True)
+    cells = A.build_cells(ctx, to_dev(x), [box])
+    rng = syn.SplitMix64(5150)
+    a_d = to_dev((0.2 + 0.3 * rng.uniform(n)).astype(x.dtype).reshape(n, 1))
+    for op, params in OPS:
+        gy_d = to_dev(rng.normal(n * A.op_ny(op, d)).astype(x.dtype).reshape(n, -1))
+        aa = a_d if op == "dem_spring" else None
+        ref = both(ctx, cells, op, params, aa, gy_d, 0)
+        got = both(ctx, cells, op, params, aa, gy_d, variant("staged"))
+        ctx.sync()
+        for u, v in zip(got, ref):
+            assert same(u, v), (case[0], op)
+
+
+def test_staged_equals_plain_on_a_batch(ctx):
+    w = syn.batch_cubes(nsys=48, nmax=16384)
+    xs_all = np.concatenate([s.x for s in w.systems])
+    offsets = np.concatenate([[0], np.cumsum([s.n for s in w.systems])]).tolist()
+    cells = A.build_cells(ctx, to_dev(xs_all), [box_of(s) for s in w.systems], offsets)
+    n = xs_all.shape[0]
+    gy_d = to_dev(syn.SplitMix64(9).normal(3 * n).astype(np.float32).reshape(n, 3))
+    ref = both(ctx, cells, "spring", (1.0,), None, gy_d, 0)
+    got = both(ctx, cells, "spring", (1.0,), None, gy_d, variant("staged"))
+    ctx.sync()
+    assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1])
+
+
+def test_autotuned_cell_size_gives_valid_coarser_grids(ctx):
+    import math
+
+    import oracle
+    from _parity import TOL_F32, check_close
+    w = syn.batch_cubes(nsys=16, nmax=8192)
+    xs_all = np.concatenate([s.x for s in w.systems])
+    offsets = np.concatenate([[0], np.cumsum([s.n for s in w.systems])]).tolist()
+    boxes = [box_of(s) for s in w.systems]
+    x_d = to_dev(xs_all)
+    n = xs_all.shape[0]
+    for op, params, gy in (("spring", (1.0,), None),
+                           ("soft_sphere", (), to_dev(np.ones((n, 1), dtype=np.float32)))):
+        tuned, f = A.autotune_cells(ctx, x_d, boxes, offsets, op, params, gy=gy)
+        assert f in (1.0, 0.85, 0.7, 0.55)
+        for s, t in zip(w.systems, tuned):
+            auto = oracle.grid_of(s).ncell
+            assert list(t.ncell) == [max(1, math.floor(f * a)) for a in auto]
+        cells = A.build_cells(ctx, x_d, tuned, offsets)
+        y = A.pair_sum(ctx, cells, "spring", (1.0,))
+        cnt = A.pair_sum(ctx, cells, "count", ())
+        ctx.sync()
+        for b in (0, 7, 15):
+            s, t = w.systems[b], tuned[b]
+            g = oracle.grid(3, s.lo, s.hi, s.periodic, s.cutoff, "f32", list(t.ncell))
+            lo, hi = offsets[b], offsets[b + 1]
+            yo, so = oracle.pair_sum(g, "spring", (1.0,), s.x)
+            check_close(y.cpu().numpy()[lo:hi], yo, so, TOL_F32, "tuned grid system %d" % b)
+            co, _ = oracle.pair_sum(g, "count", (), s.x)
+            np.testing.assert_array_equal(cnt.cpu().numpy()[lo:hi, 0], co[:, 0])
