@@ -222,6 +222,16 @@ aboria_status aboria_pair_sum_backward(aboria_ctx* ctx, const aboria_cells* cell
 aboria_status aboria_integrate(aboria_ctx* ctx, const aboria_cells* cells, double dt, const void* f, void* x,
                                void* v);
 
+/* Forward sum and adjoint in one box search, for an upstream gradient gy known
+ * before the forward (gy = 1 gives an energy E = sum_i e_i and its gradient, the
+ * pattern of force fields): y as aboria_pair_sum, gx (and ga, may be NULL) as
+ * aboria_pair_sum_backward for gy.  Each accepted pair is tested once.  Always
+ * the lane-per-particle box search (no variant choice).  Errors as for the two
+ * calls; no output may overlap an input or another output. */
+aboria_status aboria_pair_sum_and_backward(aboria_ctx* ctx, const aboria_cells* cells, aboria_op op,
+                                           const double* params_host, int32_t nparams, const void* a, int32_t na,
+                                           const void* gy, int32_t ny, void* y, void* gx, void* ga);
+
 /* ---- recorded neighbour lists ---------------------------------------------------
  *
  * Records, for every particle of the cell list, its neighbour set P(i) (the

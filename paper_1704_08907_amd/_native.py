@@ -53,7 +53,7 @@ EXPORTS = ["aboria_create", "aboria_destroy", "aboria_set_stream", "aboria_last_
            "aboria_graph_destroy", "aboria_autotune", "aboria_variant_count", "aboria_variant_name",
            "aboria_set_variant", "aboria_op_ny", "aboria_op_na", "aboria_set_build_strategy",
            "aboria_build_neighbours", "aboria_neighbour_capacity", "aboria_integrate",
-           "aboria_dense_sum_backward", "aboria_autotune_cells"]
+           "aboria_dense_sum_backward", "aboria_autotune_cells", "aboria_pair_sum_and_backward"]
 
 
 def lib():
@@ -92,6 +92,8 @@ def lib():
             "aboria_build_neighbours": ([P, P, I32], I32),
             "aboria_neighbour_capacity": ([P], I32),
             "aboria_integrate": ([P, P, C.c_double, P, P, P], I32),
+            "aboria_pair_sum_and_backward": ([P, P, I32, C.POINTER(C.c_double), I32, P, I32, P, I32, P, P, P],
+                                             I32),
             "aboria_autotune_cells": ([P, I32, I32, C.POINTER(Box), C.POINTER(I64), P, I32, C.POINTER(C.c_double),
                                        I32, P, I32, P, I32, C.POINTER(Box), C.POINTER(C.c_double)], I32),
             "aboria_dense_sum_backward": ([P, I32, I32, C.POINTER(C.c_double), I32, I32, I64, P, I64, P, P, P,
@@ -291,6 +293,25 @@ def pair_sum_backward(ctx: Context, cells: Cells, op: str, params, gy: torch.Ten
                                         _ptr(gx), _ptr(ga))
     ctx.check(st, "pair_sum_backward")
     return gx, ga
+
+
+def pair_sum_and_backward(ctx: Context, cells: Cells, op: str, params, gy: torch.Tensor,
+                          a: Optional[torch.Tensor] = None, y: Optional[torch.Tensor] = None,
+                          gx: Optional[torch.Tensor] = None, want_ga: bool = True):
+    """aboria_pair_sum_and_backward: (y, gx, ga) from one box search, gy known in advance."""
+    ny, na = op_ny(op, cells.d), op_na(op)
+    dev = "cuda:%d" % ctx.device
+    _check_dev(gy, "gy", cells.dtype)
+    if y is None:
+        y = torch.empty((cells.n, ny), dtype=cells.dtype, device=dev)
+    if gx is None:
+        gx = torch.empty((cells.n, cells.d), dtype=cells.dtype, device=dev)
+    ga = torch.empty((cells.n, na), dtype=cells.dtype, device=dev) if (na > 0 and want_ga) else None
+    arr, npar = _params(params)
+    st = lib().aboria_pair_sum_and_backward(ctx.handle, cells.handle, OPS[op], arr, npar, _ptr(a), na, _ptr(gy), ny,
+                                            _ptr(y), _ptr(gx), _ptr(ga))
+    ctx.check(st, "pair_sum_and_backward")
+    return y, gx, ga
 
 
 def build_neighbours(ctx: Context, cells: Cells, capacity: int = 0) -> int:

@@ -722,6 +722,11 @@ template <typename T, int D, int OP, bool BATCH>
 void launch_nbr_bwd(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, const T* gy_s, T* gx,
                     T* ga);
 
+// Forward and adjoint (for an upstream gradient known in advance) in one box search.
+template <typename T, int D, int OP, bool BATCH>
+void launch_lane_fused(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, const T* gy_s,
+                       T* y, T* gx, T* ga);
+
 // Lane-per-particle forward / adjoint whose candidates are staged in LDS per
 // stencil row (needs 32-bit row offsets: off32_rows).
 template <typename T, int D, int OP, bool BATCH>

@@ -333,6 +333,45 @@ aboria_status pair_bwd_impl(aboria_ctx* ctx, const aboria_cells* c, int32_t op, 
 namespace {
 
 template <typename T, int D>
+aboria_status fused_op(aboria_ctx* ctx, const aboria_cells* c, int op, const OpArgs<T>& q, const T* a_s,
+                       const T* gy_s, T* y, T* gx, T* ga) {
+    if (c->n == 0) return ABORIA_OK;
+    const bool batch = c->nsys > 1;
+#define F(OPC)                                                                       \
+    if (batch) launch_lane_fused<T, D, OPC, true>(ctx, c, q, a_s, gy_s, y, gx, ga);  \
+    else launch_lane_fused<T, D, OPC, false>(ctx, c, q, a_s, gy_s, y, gx, ga);
+    switch (op) {
+        case ABORIA_OP_COUNT: F(ABORIA_OP_COUNT) break;
+        case ABORIA_OP_SPRING: F(ABORIA_OP_SPRING) break;
+        case ABORIA_OP_SOFT_SPHERE: F(ABORIA_OP_SOFT_SPHERE) break;
+        case ABORIA_OP_EXP_FORCE: F(ABORIA_OP_EXP_FORCE) break;
+        default: F(ABORIA_OP_DEM_SPRING) break;
+    }
+#undef F
+    ABORIA_HIP(ctx, hipGetLastError());
+    return ABORIA_OK;
+}
+
+template <typename T>
+aboria_status fused_impl(aboria_ctx* ctx, const aboria_cells* c, int32_t op, const double* params, int32_t nparams,
+                         const void* a, int32_t na, const void* gy, int32_t ny, void* y, void* gx, void* ga) {
+    OpArgs<T> q{nparams > 0 ? (T)params[0] : T(0)};
+    aboria_status st;
+    const T* a_s = nullptr;
+    if (na > 0) {
+        if ((st = gather<T>(ctx, c, a, na, c->work)) != ABORIA_OK) return st;
+        a_s = (const T*)c->work;
+    }
+    if ((st = gather<T>(ctx, c, gy, ny, c->work2)) != ABORIA_OK) return st;
+    const T* g_s = (const T*)c->work2;
+    switch (c->d) {
+        case 1: return fused_op<T, 1>(ctx, c, op, q, a_s, g_s, (T*)y, (T*)gx, (T*)ga);
+        case 2: return fused_op<T, 2>(ctx, c, op, q, a_s, g_s, (T*)y, (T*)gx, (T*)ga);
+        default: return fused_op<T, 3>(ctx, c, op, q, a_s, g_s, (T*)y, (T*)gx, (T*)ga);
+    }
+}
+
+template <typename T, int D>
 aboria_status list_pairs(aboria_ctx* ctx, const aboria_cells* c, int64_t cap, uint32_t* pi, uint32_t* pj,
                          int64_t* total) {
     const uint32_t n = (uint32_t)c->n;
@@ -414,6 +453,36 @@ extern "C" aboria_status aboria_pair_sum_backward(aboria_ctx* ctx, const aboria_
         return pair_bwd_impl(ctx, cells, op, params_host, nparams, a, na, gy, ny, gx, ga, v);
     } catch (...) {
         return fail(ctx, ABORIA_ERR_OUT_OF_MEMORY, "host exception in pair_sum_backward");
+    }
+}
+
+extern "C" aboria_status aboria_pair_sum_and_backward(aboria_ctx* ctx, const aboria_cells* c, aboria_op op,
+                                                      const double* params_host, int32_t nparams, const void* a,
+                                                      int32_t na, const void* gy, int32_t ny, void* y, void* gx,
+                                                      void* ga) {
+    if (!ctx) return ABORIA_ERR_INVALID_ARG;
+    try {
+        aboria_status st = validate(ctx, c, op, params_host, nparams, a, na, ny);
+        if (st != ABORIA_OK) return st;
+        if (c->n > 0 && (!gy || !y || !gx)) return fail(ctx, ABORIA_ERR_INVALID_ARG, "gy, y and gx are required");
+        const size_t tsz = c->dtype == ABORIA_F32 ? 4 : 8;
+        const size_t nb = (size_t)c->n;
+        struct Span { const void* p; size_t bytes; };
+        const Span ins[] = {{a, tsz * na * nb}, {gy, tsz * ny * nb}};
+        const Span outs[] = {{y, tsz * ny * nb}, {gx, tsz * c->d * nb}, {ga, tsz * na * nb}};
+        for (const Span& o : outs) {
+            if (!o.p) continue;
+            for (const Span& i : ins)
+                if (overlaps(o.p, o.bytes, i.p, i.bytes))
+                    return fail(ctx, ABORIA_ERR_INVALID_ARG, "outputs overlap inputs");
+            for (const Span& o2 : outs)
+                if (&o2 != &o && o2.p && overlaps(o.p, o.bytes, o2.p, o2.bytes))
+                    return fail(ctx, ABORIA_ERR_INVALID_ARG, "outputs overlap");
+        }
+        return c->dtype == ABORIA_F32 ? fused_impl<float>(ctx, c, op, params_host, nparams, a, na, gy, ny, y, gx, ga)
+                                      : fused_impl<double>(ctx, c, op, params_host, nparams, a, na, gy, ny, y, gx, ga);
+    } catch (...) {
+        return fail(ctx, ABORIA_ERR_OUT_OF_MEMORY, "host exception in pair_sum_and_backward");
     }
 }
 

@@ -100,3 +100,36 @@ def test_autotuned_cell_size_gives_valid_coarser_grids(ctx):
             check_close(y.cpu().numpy()[lo:hi], yo, so, TOL_F32, "tuned grid system %d" % b)
             co, _ = oracle.pair_sum(g, "count", (), s.x)
             np.testing.assert_array_equal(cnt.cpu().numpy()[lo:hi, 0], co[:, 0])
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_fused_forward_and_adjoint_equal_the_two_calls(ctx, case):
+    g, x, box, prec = make_case(case)
+    n, d = x.shape
+    cells = A.build_cells(ctx, to_dev(x), [box])
+    rng = syn.SplitMix64(6160)
+    a_d = to_dev((0.2 + 0.3 * rng.uniform(n)).astype(x.dtype).reshape(n, 1))
+    for op, params in OPS:
+        gy_d = to_dev(rng.normal(n * A.op_ny(op, d)).astype(x.dtype).reshape(n, -1))
+        aa = a_d if op == "dem_spring" else None
+        ref = both(ctx, cells, op, params, aa, gy_d, 0)
+        got = A.pair_sum_and_backward(ctx, cells, op, params, gy_d, aa)
+        ctx.sync()
+        for u, v in zip(got, ref):
+            assert same(u, v), (case[0], op)
+
+
+def test_fused_on_a_batch_and_errors(ctx):
+    w = syn.batch_cubes(nsys=24, nmax=8192)
+    xs_all = np.concatenate([s.x for s in w.systems])
+    offsets = np.concatenate([[0], np.cumsum([s.n for s in w.systems])]).tolist()
+    cells = A.build_cells(ctx, to_dev(xs_all), [box_of(s) for s in w.systems], offsets)
+    n = xs_all.shape[0]
+    gy_d = to_dev(np.ones((n, 1), dtype=np.float32))
+    ref = both(ctx, cells, "soft_sphere", (), None, gy_d, 0)
+    got = A.pair_sum_and_backward(ctx, cells, "soft_sphere", (), gy_d)
+    ctx.sync()
+    assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1])
+    with pytest.raises(A.AboriaError) as e:
+        A.pair_sum_and_backward(ctx, cells, "soft_sphere", (), gy_d, y=gy_d)  # y aliases gy
+    assert e.value.status == "INVALID_ARG"
