@@ -334,18 +334,31 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(const uint32_t* __restric
 // same digit find each other with one ballot per digit bit; a lane's rank is
 // the number of such lanes below it plus the wave's running count for the
 // digit (kept in LDS, updated by the lowest such lane).  After all waves are
-// done the per-wave counts become per-wave offsets, and each key goes to
-//   scan[digit, tile] + offset[wave, digit] + rank.
+// done the per-wave counts become per-wave offsets, and the tile is shuffled
+// into digit order in LDS, so that keys and indices leave in one contiguous
+// run per digit instead of one scattered 4-byte store per lane.  The position
+// rows ride along as a payload (FIRST: read from the caller's x in original
+// order; later passes: from the previous pass's payload), so that the bucket
+// pass reads them in order instead of gathering them by index.
+template <typename T, int D, bool FIRST, bool SHUFFLE, bool PAYLOAD>
 __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __restrict__ keys_in,
                                                           const uint32_t* __restrict__ vals_in,
+                                                          const T* __restrict__ x,
+                                                          const VecN<T, Pitch<D>::value>* __restrict__ pay_in,
                                                           uint32_t* __restrict__ keys_out,
-                                                          uint32_t* __restrict__ vals_out, uint32_t n, int shift,
-                                                          int bits, const uint32_t* __restrict__ hist_scan,
+                                                          uint32_t* __restrict__ vals_out,
+                                                          VecN<T, Pitch<D>::value>* __restrict__ pay_out, uint32_t n,
+                                                          int shift, int bits, const uint32_t* __restrict__ hist_scan,
                                                           const uint32_t* __restrict__ block_sums, uint32_t ntiles) {
+    constexpr int PITCH = Pitch<D>::value;
     extern __shared__ uint32_t lds[];
+    __shared__ uint32_t s_wsum[4];
     const uint32_t radix = 1u << bits, mask = radix - 1;
-    uint32_t* cnt = lds;                 // [4][radix]
-    uint32_t* gbase = lds + 4 * radix;   // [radix]
+    uint32_t* cnt = lds;                 // [4][radix] per-wave counts, then per-wave offsets
+    uint32_t* gbase = lds + 4 * radix;   // [radix] first global slot of the tile's keys of a digit
+    uint32_t* tstart = lds + 5 * radix;  // [radix] first tile slot of a digit
+    uint32_t* sk = lds + 6 * radix;      // [kSortTile] keys in digit order
+    uint32_t* sv = sk + kSortTile;       // [kSortTile] indices in digit order
     const uint32_t tile = blockIdx.x;
     for (uint32_t d = threadIdx.x; d < radix; d += kBlock) {
         cnt[d] = 0;
@@ -359,14 +372,15 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __rest
     const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     uint32_t* wc = cnt + w * radix;
     const uint64_t lt = lanemask_lt();
-    const uint32_t wbase = tile * kSortTile + w * (kWave * kSortIpt);
+    const uint32_t tbase = tile * kSortTile;
+    const uint32_t wbase = tbase + w * (kWave * kSortIpt);
     uint32_t key[kSortIpt], val[kSortIpt], loc[kSortIpt];
 #pragma unroll
     for (int s = 0; s < kSortIpt; ++s) {
         const uint32_t idx = wbase + s * kWave + lane;
         const bool valid = idx < n;
         const uint32_t k = valid ? keys_in[idx] : 0u;
-        const uint32_t v = valid ? (vals_in ? vals_in[idx] : idx) : 0u;
+        const uint32_t v = valid ? (FIRST ? idx : vals_in[idx]) : 0u;
         const uint32_t dg = (k >> shift) & mask;
         uint64_t peers = __ballot(valid);
         for (int b = 0; b < bits; ++b) {
@@ -382,12 +396,34 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __rest
         loc[s] = c + below;
     }
     __syncthreads();
-    for (uint32_t d = threadIdx.x; d < radix; d += kBlock) {
-        uint32_t a0 = cnt[d], a1 = cnt[radix + d], a2 = cnt[2 * radix + d];
-        cnt[d] = 0;
-        cnt[radix + d] = a0;
-        cnt[2 * radix + d] = a0 + a1;
-        cnt[3 * radix + d] = a0 + a1 + a2;
+    {   // per digit: offsets of the waves, and the tile's exclusive scan over digits
+        constexpr uint32_t kMaxPer = (1u << kMaxDigitBits) / kBlock;
+        const uint32_t per = radix >= (uint32_t)kBlock ? radix / kBlock : 1u;
+        const uint32_t d0 = threadIdx.x * per;
+        uint32_t tot[kMaxPer > 0 ? kMaxPer : 1];
+        uint32_t sum = 0;
+        for (uint32_t q = 0; q < per; ++q) {
+            tot[q] = 0;
+            const uint32_t d = d0 + q;
+            if (d < radix) {
+                const uint32_t a0 = cnt[d], a1 = cnt[radix + d], a2 = cnt[2 * radix + d], a3 = cnt[3 * radix + d];
+                cnt[d] = 0;
+                cnt[radix + d] = a0;
+                cnt[2 * radix + d] = a0 + a1;
+                cnt[3 * radix + d] = a0 + a1 + a2;
+                tot[q] = a0 + a1 + a2 + a3;
+                sum += tot[q];
+            }
+        }
+        uint32_t total;
+        uint32_t ex = block_exclusive_scan(sum, s_wsum, &total);
+        for (uint32_t q = 0; q < per; ++q) {
+            const uint32_t d = d0 + q;
+            if (d < radix) {
+                tstart[d] = ex;
+                ex += tot[q];
+            }
+        }
     }
     __syncthreads();
 #pragma unroll
@@ -395,11 +431,40 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __rest
         const uint32_t idx = wbase + s * kWave + lane;
         if (idx < n) {
             const uint32_t dg = (key[s] >> shift) & mask;
-            const uint32_t pos = gbase[dg] + wc[dg] + loc[s];
-            if (pos < n) {  // always true for a consistent histogram; keeps a bad one in bounds
-                keys_out[pos] = key[s];
-                vals_out[pos] = val[s];
+            const uint32_t off_d = wc[dg] + loc[s];
+            const uint32_t tl = tstart[dg] + off_d;
+            const uint32_t pos = gbase[dg] + off_d;
+            if (tl < (uint32_t)kSortTile && pos < n) {  // always true for a consistent histogram
+                if (SHUFFLE) {
+                    sk[tl] = key[s];
+                    sv[tl] = val[s];
+                } else {
+                    keys_out[pos] = key[s];
+                    vals_out[pos] = val[s];
+                }
+                if (PAYLOAD) {
+                    VecN<T, PITCH> row;
+                    if (FIRST) {
+#pragma unroll
+                        for (int k = 0; k < PITCH; ++k) row.v[k] = k < D ? x[(size_t)idx * D + k] : T(0);
+                    } else {
+                        row = pay_in[idx];
+                    }
+                    pay_out[pos] = row;
+                }
             }
+        }
+    }
+    if (!SHUFFLE) return;
+    __syncthreads();
+    const uint32_t count = min((uint32_t)kSortTile, n - tbase);
+    for (uint32_t i = threadIdx.x; i < count; i += kBlock) {
+        const uint32_t k = sk[i];
+        const uint32_t dg = (k >> shift) & mask;
+        const uint32_t pos = gbase[dg] + (i - tstart[dg]);
+        if (pos < n) {  // always true for a consistent histogram; keeps a bad one in bounds
+            keys_out[pos] = k;
+            vals_out[pos] = sv[i];
         }
     }
 }
@@ -429,7 +494,8 @@ __global__ __launch_bounds__(kBlock) void k_bucket_finalize(const uint32_t* __re
                                                             uint32_t* __restrict__ off,
                                                             const uint32_t* __restrict__ hist_scan,
                                                             const uint32_t* __restrict__ block_sums, uint32_t ntiles,
-                                                            uint32_t ndigits) {
+                                                            uint32_t ndigits,
+                                                            const VecN<T, Pitch<D>::value>* __restrict__ pay) {
     constexpr int PITCH = Pitch<D>::value;
     extern __shared__ uint32_t lds[];
     const uint32_t R = 1u << lb, mask = R - 1u;
@@ -537,8 +603,12 @@ __global__ __launch_bounds__(kBlock) void k_bucket_finalize(const uint32_t* __re
                     const uint32_t p = min(val[st], n - 1u);
                     perm_out[dest] = p;
                     VecN<T, PITCH> v;
+                    if (pay) {
+                        v = pay[idx];  // the row travelled with its key through the radix passes
+                    } else {
 #pragma unroll
-                    for (int k = 0; k < PITCH; ++k) v.v[k] = k < D ? x[(size_t)p * D + k] : T(0);
+                        for (int k = 0; k < PITCH; ++k) v.v[k] = k < D ? x[(size_t)p * D + k] : T(0);
+                    }
                     reinterpret_cast<VecN<T, PITCH>*>(xs)[dest] = v;
                 }
             }
@@ -696,6 +766,8 @@ aboria_status launch_build_radix(aboria_ctx* ctx, aboria_cells* c, const void* x
     uint32_t* k0 = (c->passes % 2 == 1) ? c->keys : c->keys_alt;
     uint32_t* kin = k0;
     uint32_t* vin = nullptr;
+    using Row = VecN<T, Pitch<D>::value>;
+    const Row* pay = nullptr;  // position rows in the order of kin (after a radix pass)
     if (n > 0) {
         const dim3 grid((n + kBlock - 1) / kBlock);
         if (c->nsys == 1)
@@ -708,6 +780,21 @@ aboria_status launch_build_radix(aboria_ctx* ctx, aboria_cells* c, const void* x
         const uint32_t radix = 1u << c->digit_bits;
         uint32_t* kout = (k0 == c->keys) ? c->keys_alt : c->keys;
         uint32_t* vout = (k0 == c->keys) ? c->perm_alt : c->perm;
+        // Two choices, from measurements on MI355X (2^20 particles in one cube vs 512 systems
+        // of up to 65536): shuffling a tile into digit order in LDS makes the key writes
+        // contiguous but needs 57 KB of LDS, which pays while the tiles do not outnumber the CUs
+        // much (it slowed 1411 tiles); carrying the position rows through the pass turns the
+        // bucket pass's random gather into a sequential read, which pays when a system's
+        // positions do not fit in L2 (a 12 MB cube: 58 -> 38 us), while the gather of a
+        // 0.8 MB system already hits L2 and the payload only adds traffic.
+        const bool shuffle = ntiles <= 512;
+        int64_t largest = 0;
+        for (int32_t b = 0; b < c->nsys; ++b)
+            largest = std::max<int64_t>(largest, c->sys_off[(size_t)b + 1] - c->sys_off[(size_t)b]);
+        const bool payload = (uint64_t)largest * D * sizeof(T) > (2u << 20);
+        // position rows follow the keys through the passes, ping-ponging between the work buffers
+        Row* pout = reinterpret_cast<Row*>(c->work);
+        const size_t lds_bytes = (6 * (size_t)radix + 2 * (size_t)kSortTile) * sizeof(uint32_t);
         for (int p = 0; p < c->passes; ++p) {
             const int shift = c->low_bits + p * c->digit_bits;
             hipLaunchKernelGGL(k_radix_hist, dim3(ntiles), dim3(kBlock), radix * sizeof(uint32_t), st, kin, n, shift,
@@ -715,11 +802,33 @@ aboria_status launch_build_radix(aboria_ctx* ctx, aboria_cells* c, const void* x
             aboria_status s = scan_exclusive_u32(ctx, c->hist, c->hist, (int64_t)radix * ntiles, c->block_sums,
                                                  c->nblock_sums);
             if (s != ABORIA_OK) return s;
-            hipLaunchKernelGGL(k_radix_scatter, dim3(ntiles), dim3(kBlock), 5 * radix * sizeof(uint32_t), st, kin,
-                               vin, kout, vout, n, shift, c->digit_bits, c->hist, c->block_sums, ntiles);
+            const int pm = (shuffle ? 1 : 0) | (payload ? 2 : 0);
+            const size_t lds_sel = shuffle ? lds_bytes : 6 * (size_t)radix * sizeof(uint32_t);
+#define LS(F, SH, PL)                                                                                          \
+    hipLaunchKernelGGL((k_radix_scatter<T, D, F, SH, PL>), dim3(ntiles), dim3(kBlock), lds_sel, st, kin, vin,  \
+                       (const T*)x, (const Row*)pay, kout, vout, pout, n, shift, c->digit_bits, c->hist,       \
+                       c->block_sums, ntiles)
+            if (p == 0) {
+                switch (pm) {
+                    case 0: LS(true, false, false); break;
+                    case 1: LS(true, true, false); break;
+                    case 2: LS(true, false, true); break;
+                    default: LS(true, true, true); break;
+                }
+            } else {
+                switch (pm) {
+                    case 0: LS(false, false, false); break;
+                    case 1: LS(false, true, false); break;
+                    case 2: LS(false, false, true); break;
+                    default: LS(false, true, true); break;
+                }
+            }
+#undef LS
             std::swap(kin, kout);
             vin = vout;
             vout = (vout == c->perm) ? c->perm_alt : c->perm;
+            pay = payload ? pout : nullptr;
+            pout = reinterpret_cast<Row*>(pout == reinterpret_cast<Row*>(c->work) ? c->work2 : c->work);
         }
     }
     const uint32_t R = 1u << c->low_bits;
@@ -727,7 +836,7 @@ aboria_status launch_build_radix(aboria_ctx* ctx, aboria_cells* c, const void* x
     const bool direct = c->passes == 1 && n > 0;
     hipLaunchKernelGGL((k_bucket_finalize<T, D>), dim3(nbuckets), dim3(kBlock), 6 * R * sizeof(uint32_t), st, kin,
                        vin, n, c->low_bits, (uint32_t)c->ncells, (const T*)x, (T*)c->xs, c->keys, c->perm, c->off,
-                       direct ? c->hist : nullptr, c->block_sums, (uint32_t)c->ntiles, 1u << c->digit_bits);
+                       direct ? c->hist : nullptr, c->block_sums, (uint32_t)c->ntiles, 1u << c->digit_bits, pay);
     ABORIA_HIP(ctx, hipGetLastError());
     return ABORIA_OK;
 }
