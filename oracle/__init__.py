@@ -44,7 +44,7 @@ class Grid(C.Structure):
     _fields_ = [("d", C.c_int32), ("dtype", C.c_int32), ("periodic", C.c_int32 * 3),
                 ("n", C.c_int32 * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
                 ("L", C.c_double * 3), ("inv_w", C.c_double * 3), ("r", C.c_double),
-                ("r2", C.c_double), ("ncells", C.c_int64)]
+                ("r2", C.c_double), ("ncells", C.c_int64), ("reach", C.c_int32), ("pad", C.c_int32)]
 
     @property
     def ncell(self):
@@ -61,7 +61,7 @@ def lib():
             build()
         L = C.CDLL(LIB)
         P = C.c_void_p
-        L.or_grid_init.argtypes = [C.POINTER(Grid), C.c_int32, C.c_int32, P, P, P, C.c_double, P]
+        L.or_grid_init.argtypes = [C.POINTER(Grid), C.c_int32, C.c_int32, P, P, P, C.c_double, P, C.c_int32]
         L.or_cell_ids.argtypes = [C.POINTER(Grid), C.c_int64, P, P]
         L.or_sort_cells.argtypes = [C.POINTER(Grid), C.c_int64, P, P, P]
         L.or_pairs.argtypes = [C.POINTER(Grid), C.c_int32, C.c_int64, P, C.c_int64, P, P]
@@ -94,8 +94,9 @@ def _f64(a):
     return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
 
 
-def grid(d, lo, hi, periodic, cutoff, precision="f64", ncell=None) -> Grid:
-    """The cell grid of a box (cell count rule, P-rounded box, 1/w)."""
+def grid(d, lo, hi, periodic, cutoff, precision="f64", ncell=None, reach=1) -> Grid:
+    """The cell grid of a box (cell count rule R1 for search reach m = reach,
+    P-rounded box, 1/w)."""
     g = Grid()
     lo_a = np.zeros(3); lo_a[:d] = lo
     hi_a = np.ones(3); hi_a[:d] = hi
@@ -104,15 +105,15 @@ def grid(d, lo, hi, periodic, cutoff, precision="f64", ncell=None) -> Grid:
     if ncell is not None:
         nreq[:d] = ncell
     st = lib().or_grid_init(C.byref(g), d, F32 if precision == "f32" else F64, _ptr(lo_a),
-                            _ptr(hi_a), _ptr(per), float(cutoff), _ptr(nreq))
+                            _ptr(hi_a), _ptr(per), float(cutoff), _ptr(nreq), int(reach))
     if st != OK:
         raise OracleError(st, "grid")
     return g
 
 
-def grid_of(system, ncell=None) -> Grid:
+def grid_of(system, ncell=None, reach=1) -> Grid:
     return grid(system.d, system.lo, system.hi, system.periodic, system.cutoff,
-                system.precision, ncell)
+                system.precision, ncell, reach)
 
 
 def cell_ids(g: Grid, x) -> tuple:

@@ -19,7 +19,10 @@
  *     original index order inside a cell), and as the serial-insertion
  *     head/next linked list that Section 2.2.1 mentions as the second design.
  *   - The box search (Section 2.2.2, "Aboria Level 2"): candidates of particle
- *     i are the particles in i's cell and the adjacent cells.
+ *     i are the particles in i's cell and the adjacent cells.  A grid may also
+ *     use cells narrower than the cutoff (reading R1 with reach m > 1); the
+ *     search then takes every cell up to m cells away in each dimension.  The
+ *     accepted pairs do not depend on the grid: the predicate R3 alone decides.
  *   - The radius-limited sum (Section 3, eq. (1) and the velocity-update
  *     listing): y_i = sum over j with 0 < |dx_ij| < r of f_ij, with dx_ij the
  *     shortest (minimum-image) vector r_j - r_i.  The norm(dx) > 0 condition
@@ -32,9 +35,12 @@
  *     step dt = 1 of the paper kept as a parameter.
  *
  * Readings the paper leaves open (each listed in the design notes):
- *   R1 cell count per dimension: n = floor(L/r), then decreased while n > 1 and
- *      L/n < r + 16 u (|lo| + L), u the unit roundoff of the input precision,
- *      so that rounding in the cell assignment can never hide a pair.
+ *   R1 cell count per dimension: n = floor(m L/r), then decreased while n > 1
+ *      and L/n < (r + 16 u (|lo| + L)) / m, u the unit roundoff of the input
+ *      precision, so that rounding in the cell assignment can never put the two
+ *      points of a pair more than m cells apart.  m >= 1 is the search reach;
+ *      m = 1 is the paper's lattice (cells at least one cutoff wide, searched
+ *      with the adjacent cells).  An explicit count may not exceed this n.
  *   R2 cell of a coordinate: clamp(floor(fl(fl(x - lo) * fl(n / L))), 0, n-1);
  *      linear id = c0 + n0 (c1 + n1 c2); x == hi, x < lo or NaN is a domain
  *      error.
@@ -99,6 +105,8 @@ typedef struct or_grid {
     double r;
     double r2;
     int64_t ncells;
+    int32_t reach; /* m of reading R1: cells searched on each side */
+    int32_t pad;
 } or_grid;
 
 /* Round a double to the working precision P. */
@@ -111,9 +119,12 @@ static double unit_roundoff(int dtype) { return dtype == OR_F32 ? ldexp(1.0, -24
 /* ------------------------------------------------------------------------ */
 
 int or_grid_init(or_grid* g, int32_t d, int32_t dtype, const double* lo, const double* hi,
-                 const int32_t* periodic, double r, const int32_t* ncell_req) {
+                 const int32_t* periodic, double r, const int32_t* ncell_req, int32_t reach) {
     memset(g, 0, sizeof(*g));
     if (d < 1 || d > 3 || (dtype != OR_F32 && dtype != OR_F64)) return OR_ERR_INVALID;
+    if (reach == 0) reach = 1;
+    if (reach < 1 || reach > 16) return OR_ERR_INVALID;
+    g->reach = reach;
     g->d = d;
     g->dtype = dtype;
     g->r = to_p(dtype, r);
@@ -140,9 +151,9 @@ int or_grid_init(or_grid* g, int32_t d, int32_t dtype, const double* lo, const d
         else
             g->L[k] = g->hi[k] - g->lo[k];
         double guard = g->r + 16.0 * u * (fabs(g->lo[k]) + g->L[k]);
-        double q = floor(g->L[k] / g->r);
+        double q = floor((double)reach * g->L[k] / g->r);
         int64_t nmax = q < 1.0 ? 1 : (q > 2147483647.0 ? 2147483647 : (int64_t)q);
-        while (nmax > 1 && g->L[k] / (double)nmax < guard) --nmax;
+        while (nmax > 1 && g->L[k] / (double)nmax < guard / (double)reach) --nmax;
         int64_t nk = nmax;
         if (ncell_req && ncell_req[k] > 0) {
             if (ncell_req[k] > nmax) return OR_ERR_INVALID; /* cells narrower than the guard */
@@ -296,23 +307,27 @@ static void free_linked(linked_cells* lc) {
     free(lc->next);
 }
 
-/* Box search for point i: its cell and the adjacent cells (3^d offsets).  A
+/* Box search for point i: its cell and every cell up to m = reach cells away
+ * in each dimension ((2m+1)^d offsets; m = 1 is the paper's 3^d stencil).  A
  * periodic dimension wraps, and the wrap becomes the image shift of the
- * neighbour cell; a non-periodic dimension drops offsets outside the grid. */
+ * neighbour cell; a non-periodic dimension drops offsets outside the grid.  An
+ * offset that would need a second wrap is dropped too: that image lies at
+ * least one period L >= 2r from the first, so it can hold no pair. */
 static void visit_cells(const or_grid* g, const linked_cells* lc, const double* x, int64_t i,
                         visit_fn fn, void* ctx) {
     int bad = 0;
     int32_t c[3] = {0, 0, 0};
     for (int k = 0; k < g->d; ++k) c[k] = cell_coord(g, k, x[i * g->d + k], &bad);
+    const int side = 2 * g->reach + 1;
     int nstencil = 1;
-    for (int k = 0; k < g->d; ++k) nstencil *= 3;
+    for (int k = 0; k < g->d; ++k) nstencil *= side;
     for (int m = 0; m < nstencil; ++m) {
         int32_t cn[3] = {0, 0, 0};
         double s[3] = {0.0, 0.0, 0.0};
         int rest = m, skip = 0;
         for (int k = 0; k < g->d; ++k) {
-            int o = rest % 3 - 1;
-            rest /= 3;
+            int o = rest % side - g->reach;
+            rest /= side;
             int32_t v = c[k] + o;
             if (v < 0) {
                 if (!g->periodic[k]) { skip = 1; break; }
@@ -323,6 +338,7 @@ static void visit_cells(const or_grid* g, const linked_cells* lc, const double* 
                 v -= g->n[k];
                 s[k] = g->L[k];
             }
+            if (v < 0 || v >= g->n[k]) { skip = 1; break; }
             cn[k] = v;
         }
         if (skip) continue;

@@ -74,6 +74,26 @@ def test_grid_rule_unit_square_r01():
     assert g.ncell == [3, 5]
 
 
+def test_grid_rule_reach():
+    # reach m: the largest n with L/n >= (r + guard margin)/m, i.e. cells at least r/m wide
+    for m, n in ((1, 9), (2, 19), (3, 29)):  # L/(10 m) equals r/m exactly, so the guard takes one fewer
+        assert oracle.grid(2, [0, 0], [1, 1], [1, 1], 0.1, "f64", reach=m).ncell == [n, n]
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.grid(2, [0, 0], [1, 1], [1, 1], 0.1, "f64", ncell=[20, 20], reach=2)
+    assert e.value.code == oracle.ERR_INVALID
+    assert oracle.grid(2, [0, 0], [1, 1], [1, 1], 0.1, "f64", ncell=[19, 12], reach=2).ncell == [19, 12]
+    L = syn.side_for_density(1 << 20, 3, 30.0)  # 52.705...: 2L = 105.4, 3L = 158.1
+    assert oracle.grid(3, [0] * 3, [L] * 3, [1] * 3, 1.0, "f32", reach=2).ncell == [105] * 3
+    assert oracle.grid(3, [0] * 3, [L] * 3, [1] * 3, 1.0, "f32", reach=3).ncell == [158] * 3
+    # reach does not relax the periodic limit: a side below 2r still holds two images within r
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.grid(2, [0, 0], [1.9, 3], [1, 1], 1.0, "f32", reach=2)
+    assert e.value.code == oracle.ERR_UNSUPPORTED
+    for bad in (-1, 17):
+        with pytest.raises(oracle.OracleError):
+            oracle.grid(2, [0, 0], [1, 1], [1, 1], 0.1, "f64", reach=bad)
+
+
 def test_grid_rule_cube_and_limits():
     L = syn.side_for_density(1 << 20, 3, 30.0)
     g = oracle.grid(3, [0] * 3, [L] * 3, [1] * 3, 1.0, "f32")
@@ -169,10 +189,19 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("case", CASES)
-def test_brute_force_equals_cell_list(case):
+NARROW = [
+    # grids with fewer than 2m+1 cells per side at reach m: offsets alias or would wrap twice
+    (2, [2.1, 2.6], [1, 1], 1.0, "f32", [3, 4]),
+    (2, [2.1, 2.6], [1, 1], 1.0, "f64", [2, 1]),
+    (3, [2.2, 2.3, 2.4], [1, 0, 1], 1.0, "f32", [4, 2, 3]),
+]
+
+
+@pytest.mark.parametrize("case,reach", [(c, m) for m in (1, 2, 3) for c in CASES]
+                         + [(c, m) for m in (2, 3) for c in NARROW])
+def test_brute_force_equals_cell_list(case, reach):
     d, hi, per, r, prec, ncell = case
-    g = oracle.grid(d, [0.0] * d, hi, per, r, prec, ncell)
+    g = oracle.grid(d, [0.0] * d, hi, per, r, prec, ncell, reach)
     rng = syn.SplitMix64(1234 + d)
     x = syn.uniform_positions(rng, 700, [0.0] * d, hi, prec).astype(np.float64)
     xb = _near_boundary_points(rng, g, 300)
@@ -188,7 +217,7 @@ def test_brute_force_equals_cell_list(case):
     # the sums over the two routes agree to float64 rounding
     yb, _ = oracle.pair_sum(g, "spring", (1.0,), x, route=oracle.ROUTE_BRUTE)
     yc, _ = oracle.pair_sum(g, "spring", (1.0,), x, route=oracle.ROUTE_CELLS)
-    np.testing.assert_allclose(yb, yc, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(yb, yc, rtol=1e-12, atol=1e-12)  # summation order only
 
 
 def test_relabelling_equivariance():
