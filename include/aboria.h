@@ -81,14 +81,24 @@ typedef enum aboria_kernel {
 
 /* A hypercube domain [lo, hi) and cutoff (Section 1, property 1; the
  * init_neighbour_search(lo, hi, width, periodic) call of Section 3).  Entries
- * beyond d are ignored.  ncell[k] = 0 picks the cell count automatically (the
- * largest count whose cells are wider than the cutoff by a rounding guard);
- * an explicit count must not exceed that and is honoured as given. */
+ * beyond d are ignored.
+ *
+ * reach m (1..3; 0 = 1) is how many cells the box search looks on each side of
+ * a particle's own cell.  m = 1 is the paper's lattice: cells at least one
+ * cutoff wide, searched with the adjacent cells (Section 2.2.2).  m = 2 or 3
+ * uses cells about r/m wide searched m cells deep, which tests fewer
+ * candidates; the pair set is the same, since the pair predicate alone
+ * decides it.  The cell-group, LDS-list, wave-queue and LDS-staged variants
+ * need m = 1.
+ *
+ * ncell[k] = 0 picks the cell count automatically: the largest count whose
+ * cells are at least (cutoff + a rounding guard) / m wide.  An explicit count
+ * must not exceed that and is honoured as given. */
 typedef struct aboria_box {
     int32_t d;           /* 1, 2 or 3                                  */
     int32_t periodic[3]; /* nonzero = periodic in that dimension       */
     int32_t ncell[3];    /* 0 = automatic                              */
-    int32_t reserved;
+    int32_t reach;       /* search reach m, 0 = 1                      */
     double lo[3];
     double hi[3];
     double cutoff;       /* r > 0                                      */
@@ -316,13 +326,15 @@ aboria_status aboria_autotune(aboria_ctx* ctx, const aboria_cells* cells, aboria
                               const void* gy, int32_t ny, void* out_scratch, int32_t* choice_host);
 
 /* Cell-size tuning: times a rebuild plus aboria_pair_sum (and, when gy is given,
- * aboria_pair_sum_backward for that upstream gradient) of op on grids whose
- * per-dimension cell counts are the automatic ones (or the boxes' explicit
- * ones) scaled by 1, 0.85, 0.7 and 0.55 (rounded down, at least 1; coarser
- * cells are always valid, finer ones are not), each with its work mapping
- * tuned as by aboria_autotune (the tuned choices stay in ctx's cache).
+ * aboria_pair_sum_backward for that upstream gradient) of op on grids of each
+ * search reach (the boxes' reach when boxes_host[0].reach is set, else 1, 2
+ * and 3, skipping a reach that the boxes' explicit counts do not allow) whose
+ * per-dimension cell counts are that reach's automatic ones (or the boxes'
+ * explicit ones) scaled by 1, 0.85, 0.7 and 0.55 (rounded down, at least 1;
+ * coarser cells are always valid, finer ones are not), each with its work
+ * mapping tuned as by aboria_autotune (the tuned choices stay in ctx's cache).
  * boxes_out[nsys] receives the input boxes with the fastest grid's explicit
- * ncell; *factor_host (may be NULL) the chosen scale.  Arguments as for
+ * ncell and reach; *factor_host (may be NULL) the chosen scale.  Arguments as for
  * aboria_build_cells and aboria_autotune; allocates temporary cell lists and
  * synchronises, so it cannot be captured. */
 aboria_status aboria_autotune_cells(aboria_ctx* ctx, aboria_dtype dtype, int32_t nsys, const aboria_box* boxes_host,

@@ -33,7 +33,7 @@ class AboriaError(RuntimeError):
 
 class Box(C.Structure):
     _fields_ = [("d", C.c_int32), ("periodic", C.c_int32 * 3), ("ncell", C.c_int32 * 3),
-                ("reserved", C.c_int32), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
+                ("reach", C.c_int32), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
                 ("cutoff", C.c_double)]
 
 
@@ -184,10 +184,12 @@ class BoxSpec:
     periodic: Sequence[int]
     cutoff: float
     ncell: Optional[Sequence[int]] = None
+    reach: int = 0  # cells searched on each side of a particle's cell (0 = 1)
 
     def to_c(self) -> Box:
         b = Box()
         b.d = self.d
+        b.reach = int(self.reach)
         for k in range(min(self.d, 3)):
             b.lo[k] = float(self.lo[k])
             b.hi[k] = float(self.hi[k])
@@ -443,8 +445,8 @@ def autotune_cells(ctx: Context, x: torch.Tensor, boxes: Sequence[BoxSpec], offs
     st = lib().aboria_autotune_cells(ctx.handle, _dtype_code(x), nsys, arr_b, arr_o, _ptr(x), OPS[op], arr, npar,
                                      _ptr(a), op_na(op), _ptr(gy), op_ny(op, d), out_b, C.byref(factor))
     ctx.check(st, "autotune_cells")
-    tuned = [BoxSpec(b.d, b.lo, b.hi, b.periodic, b.cutoff, [int(out_b[i].ncell[k]) for k in range(d)])
-             for i, b in enumerate(boxes)]
+    tuned = [BoxSpec(b.d, b.lo, b.hi, b.periodic, b.cutoff, [int(out_b[i].ncell[k]) for k in range(d)],
+                     int(out_b[i].reach)) for i, b in enumerate(boxes)]
     return tuned, float(factor.value)
 
 

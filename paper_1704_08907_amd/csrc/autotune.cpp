@@ -1,7 +1,7 @@
 // Autotuner for the neighbour-sum launch: times every work-mapping variant on
 // the caller's cell list with HIP events on the context's stream and caches the
 // fastest per (d, dtype, operator, direction, size bucket, density bucket,
-// batch, neighbour list recorded).
+// batch, neighbour list recorded, search reach).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -25,6 +25,9 @@ uint64_t tune_key(const aboria_cells* c, int32_t op, bool backward) {
     k = k * 2 + (uint64_t)(c->nsys > 1);
     k = k * 2 + (uint64_t)backward;
     k = k * 2 + (uint64_t)c->nbr_recorded;
+    int32_t reach = 1;
+    for (const aboria_box& b : c->boxes) reach = std::max<int32_t>(reach, b.reach == 0 ? 1 : b.reach);
+    k = k * 4 + (uint64_t)reach;
     return k;
 }
 
@@ -134,12 +137,10 @@ extern "C" aboria_status aboria_autotune_cells(aboria_ctx* ctx, aboria_dtype dty
     if (d < 1 || d > 3) return fail(ctx, ABORIA_ERR_INVALID_ARG, "d must be 1, 2 or 3");
     if (op_ny(op, d) != ny) return fail(ctx, ABORIA_ERR_INVALID_ARG, "ny does not match the operator");
     try {
-        // the grid every trial coarsens: the automatic (or given explicit) counts
-        std::vector<int32_t> base((size_t)nsys * 3, 1);
-        for (int32_t b = 0; b < nsys; ++b) {
-            aboria_status st = grid_counts(ctx, dtype, boxes_host[b], &base[(size_t)b * 3]);
-            if (st != ABORIA_OK) return st;
-        }
+        // reaches to try: the caller's, or every reach when the boxes leave it to the library
+        std::vector<int32_t> reaches;
+        if (boxes_host[0].reach != 0) reaches.push_back(boxes_host[0].reach);
+        else for (int32_t m = 1; m <= kMaxReach; ++m) reaches.push_back(m);
         const int64_t n = offsets_host[nsys];
         const size_t tsz = dtype == ABORIA_F32 ? 4 : 8;
         ABORIA_HIP(ctx, hipSetDevice(ctx->device));
@@ -158,37 +159,58 @@ extern "C" aboria_status aboria_autotune_cells(aboria_ctx* ctx, aboria_dtype dty
         const double factors[] = {1.0, 0.85, 0.7, 0.55};
         double best_ms = INFINITY, best_f = 1.0;
         std::vector<aboria_box> trial(boxes_host, boxes_host + nsys), best_boxes(trial);
-        std::vector<int32_t> last;
-        for (double f : factors) {
-            if (st != ABORIA_OK) break;
-            std::vector<int32_t> counts(base.size());
-            for (size_t i = 0; i < base.size(); ++i) counts[i] = std::max<int32_t>(1, (int32_t)std::floor(f * base[i]));
-            if (counts == last) continue;  // the same grid as the previous factor
-            last = counts;
-            for (int32_t b = 0; b < nsys; ++b)
-                for (int k = 0; k < 3; ++k) trial[(size_t)b].ncell[k] = k < d ? counts[(size_t)b * 3 + k] : 0;
-            aboria_cells* cells = nullptr;
-            if ((st = aboria_build_cells(ctx, dtype, nsys, trial.data(), offsets_host, x, &cells)) != ABORIA_OK) break;
-            st = aboria_autotune(ctx, cells, op, params_host, nparams, a, na, nullptr, ny, y, nullptr);
-            if (st == ABORIA_OK && gy) st = aboria_autotune(ctx, cells, op, params_host, nparams, a, na, gy, ny, gx, nullptr);
-            const int reps = 3;
-            if (st == ABORIA_OK && hipEventRecord(e0, ctx->stream) != hipSuccess) st = ABORIA_ERR_DEVICE;
-            for (int r = 0; r < reps && st == ABORIA_OK; ++r) {
-                st = aboria_build_cells(ctx, dtype, nsys, trial.data(), offsets_host, x, &cells);
-                if (st == ABORIA_OK) st = aboria_pair_sum(ctx, cells, op, params_host, nparams, a, na, y, ny);
-                if (st == ABORIA_OK && gy)
-                    st = aboria_pair_sum_backward(ctx, cells, op, params_host, nparams, a, na, gy, ny, gx, nullptr);
+        for (int32_t m : reaches) {
+            // the grid every trial of this reach coarsens: the automatic (or given explicit) counts
+            std::vector<int32_t> base((size_t)nsys * 3, 1);
+            for (int32_t b = 0; b < nsys && st == ABORIA_OK; ++b) {
+                aboria_box bx = boxes_host[b];
+                bx.reach = m;
+                st = grid_counts(ctx, dtype, bx, &base[(size_t)b * 3]);
             }
-            float ms = 0.f;
-            if (st == ABORIA_OK && (hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-                st = ABORIA_ERR_DEVICE;
-            (void)hipStreamSynchronize(ctx->stream);
-            (void)aboria_cells_destroy(cells);
-            if (st == ABORIA_OK && ms / reps < best_ms) {
-                best_ms = ms / reps;
-                best_f = f;
-                best_boxes = trial;
+            if (st != ABORIA_OK && reaches.size() > 1) {  // explicit counts too fine for this reach
+                st = ABORIA_OK;
+                ctx->last_error.clear();
+                continue;
+            }
+            std::vector<int32_t> last;
+            for (double f : factors) {
+                if (st != ABORIA_OK) break;
+                std::vector<int32_t> counts(base.size());
+                for (size_t i = 0; i < base.size(); ++i)
+                    counts[i] = std::max<int32_t>(1, (int32_t)std::floor(f * base[i]));
+                if (counts == last) continue;  // the same grid as the previous factor
+                last = counts;
+                for (int32_t b = 0; b < nsys; ++b) {
+                    trial[(size_t)b].reach = m;
+                    for (int k = 0; k < 3; ++k) trial[(size_t)b].ncell[k] = k < d ? counts[(size_t)b * 3 + k] : 0;
+                }
+                aboria_cells* cells = nullptr;
+                if ((st = aboria_build_cells(ctx, dtype, nsys, trial.data(), offsets_host, x, &cells)) != ABORIA_OK)
+                    break;
+                st = aboria_autotune(ctx, cells, op, params_host, nparams, a, na, nullptr, ny, y, nullptr);
+                if (st == ABORIA_OK && gy)
+                    st = aboria_autotune(ctx, cells, op, params_host, nparams, a, na, gy, ny, gx, nullptr);
+                const int reps = 3;
+                if (st == ABORIA_OK && hipEventRecord(e0, ctx->stream) != hipSuccess) st = ABORIA_ERR_DEVICE;
+                for (int r = 0; r < reps && st == ABORIA_OK; ++r) {
+                    st = aboria_build_cells(ctx, dtype, nsys, trial.data(), offsets_host, x, &cells);
+                    if (st == ABORIA_OK) st = aboria_pair_sum(ctx, cells, op, params_host, nparams, a, na, y, ny);
+                    if (st == ABORIA_OK && gy)
+                        st = aboria_pair_sum_backward(ctx, cells, op, params_host, nparams, a, na, gy, ny, gx,
+                                                      nullptr);
+                }
+                float ms = 0.f;
+                if (st == ABORIA_OK && (hipEventRecord(e1, ctx->stream) != hipSuccess ||
+                                        hipEventSynchronize(e1) != hipSuccess ||
+                                        hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                    st = ABORIA_ERR_DEVICE;
+                (void)hipStreamSynchronize(ctx->stream);
+                (void)aboria_cells_destroy(cells);
+                if (st == ABORIA_OK && ms / reps < best_ms) {
+                    best_ms = ms / reps;
+                    best_f = f;
+                    best_boxes = trial;
+                }
             }
         }
         if (e0) (void)hipEventDestroy(e0);

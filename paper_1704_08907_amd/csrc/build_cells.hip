@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <new>
 
 #include "common.hpp"
@@ -625,19 +626,29 @@ namespace {
 
 struct GridPlan {
     int32_t n[3] = {1, 1, 1};
+    int32_t reach = 1;
     double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0}, L[3] = {0, 0, 0}, inv_w[3] = {0, 0, 0};
-    double r = 0, r2 = 0;
+    double w_lo[3] = {0, 0, 0}, slack[3] = {0, 0, 0};
+    double r = 0, r2 = 0, prune_r2 = 0;
     int64_t ncells = 1;
 };
 
 double round_to(int dtype, double v) { return dtype == ABORIA_F32 ? (double)(float)v : v; }
 
-// Cell grid of one box: the largest per-dimension count whose cells are wider
-// than the cutoff by a guard of 16 unit roundoffs of the coordinate magnitude,
-// so that rounding in the cell assignment cannot separate a pair by more than
-// one cell.
+// Cell grid of one box: the largest per-dimension count whose cells are at
+// least (cutoff + a guard of 16 unit roundoffs of the coordinate magnitude) /
+// reach wide, so that rounding in the cell assignment cannot put the points of
+// a pair more than `reach` cells apart.  Also the pruning bound of the
+// flattened search (SysParams): the margins cover the rounding of both cell
+// assignments (2 u |q| each, |q| <= n + 1 cell units), of an image shift
+// (n u) and of the gap itself (u reach), with room to spare, and the pair
+// predicate accepting a distance slightly above r (its differences round by
+// u L, its sum of squares by a few u).
 aboria_status plan_grid(aboria_ctx* ctx, int dtype, const aboria_box& b, GridPlan* g) {
     const double u = dtype == ABORIA_F32 ? std::ldexp(1.0, -24) : std::ldexp(1.0, -53);
+    g->reach = b.reach == 0 ? 1 : b.reach;
+    if (g->reach < 1 || g->reach > kMaxReach) return fail(ctx, ABORIA_ERR_INVALID_ARG, "reach must be 0 to 3");
+    const double m = (double)g->reach;
     g->r = round_to(dtype, b.cutoff);
     if (!(g->r > 0.0) || std::isinf(g->r)) return fail(ctx, ABORIA_ERR_INVALID_ARG, "cutoff must be positive and finite");
     if (dtype == ABORIA_F32) {
@@ -647,6 +658,7 @@ aboria_status plan_grid(aboria_ctx* ctx, int dtype, const aboria_box& b, GridPla
         g->r2 = g->r * g->r;
     }
     int64_t total = 1;
+    double Lmax = 0.0;
     for (int k = 0; k < b.d; ++k) {
         g->lo[k] = round_to(dtype, b.lo[k]);
         g->hi[k] = round_to(dtype, b.hi[k]);
@@ -654,22 +666,27 @@ aboria_status plan_grid(aboria_ctx* ctx, int dtype, const aboria_box& b, GridPla
             return fail(ctx, ABORIA_ERR_INVALID_ARG, "box needs finite lo < hi in every dimension");
         g->L[k] = dtype == ABORIA_F32 ? (double)((float)g->hi[k] - (float)g->lo[k]) : g->hi[k] - g->lo[k];
         const double guard = g->r + 16.0 * u * (std::fabs(g->lo[k]) + g->L[k]);
-        const double q = std::floor(g->L[k] / g->r);
+        const double q = std::floor(m * g->L[k] / g->r);
         int64_t nmax = q < 1.0 ? 1 : (q > 2147483647.0 ? 2147483647 : (int64_t)q);
-        while (nmax > 1 && g->L[k] / (double)nmax < guard) --nmax;
+        while (nmax > 1 && g->L[k] / (double)nmax < guard / m) --nmax;
         int64_t nk = nmax;
         if (b.ncell[k] > 0) {
             if (b.ncell[k] > nmax)
-                return fail(ctx, ABORIA_ERR_INVALID_ARG, "explicit ncell gives cells narrower than the guarded cutoff");
+                return fail(ctx, ABORIA_ERR_INVALID_ARG, "explicit ncell gives cells narrower than the guarded cutoff / reach");
             nk = b.ncell[k];
         }
         if (b.periodic[k] && g->L[k] < 2.0 * guard)
             return fail(ctx, ABORIA_ERR_UNSUPPORTED, "periodic side shorter than twice the guarded cutoff");
         g->n[k] = (int32_t)nk;
         g->inv_w[k] = round_to(dtype, (double)nk / g->L[k]);
+        g->w_lo[k] = g->L[k] / (double)nk * (1.0 - 16.0 * u);
+        g->slack[k] = 16.0 * u * ((double)nk + m + 2.0);
+        Lmax = std::max(Lmax, g->L[k] + std::fabs(g->lo[k]));
         total *= nk;
         if (total > 2147483647LL) return fail(ctx, ABORIA_ERR_UNSUPPORTED, "more than 2^31 cells");
     }
+    const double rp = g->r * (1.0 + 16.0 * u) + 16.0 * u * (Lmax + 3.0 * g->r);
+    g->prune_r2 = rp * rp * (1.0 + 64.0 * u);
     g->ncells = total;
     return ABORIA_OK;
 }
@@ -694,6 +711,13 @@ void fill_params(const std::vector<GridPlan>& plans, const std::vector<aboria_bo
         }
         p.r = (T)plans[b].r;
         p.r2 = (T)plans[b].r2;
+        // rounded the safe way: the width down, the slack and the threshold up
+        for (int k = 0; k < 3; ++k) {
+            p.w_lo[k] = (T)(plans[b].w_lo[k] * (1.0 - 4.0 * std::numeric_limits<T>::epsilon()));
+            p.slack[k] = (T)(plans[b].slack[k] * (1.0 + 4.0 * std::numeric_limits<T>::epsilon()));
+        }
+        p.prune_r2 = (T)(plans[b].prune_r2 * (1.0 + 4.0 * std::numeric_limits<T>::epsilon()));
+        p.reach = plans[b].reach;
         p.cell_base = cell_base[b];
         p.part_base = (uint32_t)off[b];
         p.part_end = (uint32_t)off[b + 1];

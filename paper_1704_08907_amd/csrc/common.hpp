@@ -26,13 +26,22 @@ struct SysParams {
     T inv_w[3];
     T r;
     T r2;
+    // pruning bound of the flattened search: a cell whose gap from a point,
+    // (max(gap in cell units - slack, 0) * w_lo) summed in squares over the
+    // dimensions, reaches prune_r2 holds no pair of that point
+    T w_lo[3];     // cell width, rounded down
+    T slack[3];    // rounding margin of a gap, in cell units
+    T prune_r2;    // (r + rounding margin of the predicate)^2, rounded up
     int32_t n[3];
     int32_t periodic[3];
+    int32_t reach;       // cells searched on each side of a point's own cell
     uint32_t cell_base;  // first global cell id of the system
     uint32_t part_base;  // first sorted slot (= first row) of the system
     uint32_t part_end;   // one past its last slot
-    uint32_t pad;
 };
+
+// Largest search reach a grid may use (cells at least r / kMaxReach wide).
+constexpr int kMaxReach = 3;
 
 // Aligned small vector so that one global load fetches a whole point.
 template <typename T, int N>

@@ -300,12 +300,51 @@ __device__ __forceinline__ void scan_range(const T* __restrict__ xs, uint32_t j0
     }
 }
 
+// Cell coordinate of xi in dimension k by the arithmetic of the cell assignment
+// (so it is the cell the build put the particle in), and the position inside
+// that cell in cell units, fr = q - c (exact: c = floor(q)).
+template <typename T>
+__device__ __forceinline__ int32_t cell_coord(const SysParams<T>& P, int k, T xk, T* fr) {
+    const T t = xk - P.lo[k];
+    const T q = t * P.inv_w[k];
+    const T f = floor(q);
+    const int32_t c = !(f >= T(0)) ? 0 : (f > T(P.n[k] - 1) ? P.n[k] - 1 : (int32_t)f);
+    *fr = q - T(c);
+    return c;
+}
+
+// Cell v = c + o of a dimension of n cells, wrapped once when periodic (the
+// wrap becomes the image shift); false when the offset leaves a non-periodic
+// grid or would need a second wrap (an image one more period away lies at
+// least L >= 2r further, so it holds no pair).
+template <typename T>
+__device__ __forceinline__ bool wrap_cell(int32_t v, int32_t n, int32_t periodic, T L, int32_t* out, T* shift) {
+    T s = T(0);
+    if (v < 0) {
+        if (!periodic) return false;
+        v += n;
+        s = -L;
+    } else if (v >= n) {
+        if (!periodic) return false;
+        v -= n;
+        s = L;
+    }
+    if (v < 0 || v >= n) return false;
+    *out = v;
+    *shift = s;
+    return true;
+}
+
 // Box search of the point xi (a particle of the cell list, Section 2.2.2): its
-// cell and the adjacent cells, walked as 3^(d-1) x-rows of up to three cells,
-// each row split into contiguous pieces where a periodic wrap changes the
-// image shift.  A piece whose shift is zero on every active lane of the wave
-// runs the loop without the shift additions (adding zero is exact, so both
-// loops give the canonical dx).
+// cell and every cell up to m = P.reach cells away in each dimension (m = 1:
+// the adjacent cells), walked as (2m+1)^(d-1) x-rows in (z, y) order.  On a
+// grid at least 2m+1 cells wide a row is one contiguous run of up to 2m+1
+// cells clipped to the grid, then, when periodic, the wrapped remainder with
+// its image shift (only one side can wrap); on a narrower grid each offset is
+// its own piece, in offset order.  A piece whose shift is zero on every active
+// lane of the wave runs the loop without the shift additions (adding zero is
+// exact, so both loops give the canonical dx).  flat_loop visits the accepted
+// neighbours in this same order.
 template <typename T, int D, bool OFF32 = false, typename Visit>
 __device__ __forceinline__ void neighbour_loop(const SysParams<T>& P, const T* __restrict__ xs,
                                                const uint32_t* __restrict__ off, uint32_t n, const T* xi,
@@ -313,67 +352,257 @@ __device__ __forceinline__ void neighbour_loop(const SysParams<T>& P, const T* _
     int32_t c[3] = {0, 0, 0};
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        const T t = xi[k] - P.lo[k];
-        const T q = t * P.inv_w[k];
-        const T f = floor(q);
-        c[k] = !(f >= T(0)) ? 0 : (f > T(P.n[k] - 1) ? P.n[k] - 1 : (int32_t)f);
+        T fr;
+        c[k] = cell_coord(P, k, xi[k], &fr);
     }
+    const int32_t M = P.reach;
     const int32_t nx = P.n[0];
-    int np = 0;
-    int32_t plo[3], phi[3];
-    T psh[3];
-    if (nx >= 3) {
-        plo[0] = c[0] > 0 ? c[0] - 1 : 0;
-        phi[0] = c[0] < nx - 1 ? c[0] + 1 : nx - 1;
-        psh[0] = T(0);
-        np = 1;
-        if (P.periodic[0]) {
-            if (c[0] == 0) { plo[np] = phi[np] = nx - 1; psh[np] = -P.L[0]; ++np; }
-            if (c[0] == nx - 1) { plo[np] = phi[np] = 0; psh[np] = P.L[0]; ++np; }
-        }
-    } else {
-        for (int o = -1; o <= 1; ++o) {
-            int32_t v = c[0] + o;
-            T s = T(0);
-            if (v < 0) { if (!P.periodic[0]) continue; v += nx; s = -P.L[0]; }
-            else if (v >= nx) { if (!P.periodic[0]) continue; v -= nx; s = P.L[0]; }
-            plo[np] = phi[np] = v;
-            psh[np] = s;
-            ++np;
+    const bool wide = nx >= 2 * M + 1;
+    const int32_t a0 = max(c[0] - M, 0), b0 = min(c[0] + M, nx - 1);
+    int32_t a1 = 0, b1 = -1;
+    T s1 = T(0);
+    if (P.periodic[0]) {
+        if (c[0] - M < 0) { a1 = c[0] - M + nx; b1 = nx - 1; s1 = -P.L[0]; }
+        else if (c[0] + M >= nx) { a1 = 0; b1 = c[0] + M - nx; s1 = P.L[0]; }
+    }
+    const T r2 = P.r2;
+    auto piece = [&](uint32_t ca, uint32_t cb, const T* sh) {
+        const uint32_t j0 = off[ca];
+        const uint32_t j1 = min(off[cb + 1], n);
+        bool lane_shift = false;
+#pragma unroll
+        for (int k = 0; k < D; ++k) lane_shift |= sh[k] != T(0);
+        if (__ballot(lane_shift) != 0ull)
+            scan_range<T, D, true, OFF32>(xs, j0, j1, xi, sh, r2, lane_shift, visit);
+        else
+            scan_range<T, D, false, OFF32>(xs, j0, j1, xi, sh, r2, false, visit);
+    };
+    const int32_t zr = D >= 3 ? M : 0, yr = D >= 2 ? M : 0;
+    for (int32_t dz = -zr; dz <= zr; ++dz) {
+        int32_t cz = 0;
+        T sz = T(0);
+        if (D >= 3 && !wrap_cell(c[2] + dz, P.n[2], P.periodic[2], P.L[2], &cz, &sz)) continue;
+        for (int32_t dy = -yr; dy <= yr; ++dy) {
+            int32_t cy = 0;
+            T sy = T(0);
+            if (D >= 2 && !wrap_cell(c[1] + dy, P.n[1], P.periodic[1], P.L[1], &cy, &sy)) continue;
+            const uint32_t rowbase = P.cell_base + (uint32_t)nx * ((uint32_t)cy + (uint32_t)P.n[1] * (uint32_t)cz);
+            T sh[3] = {T(0), sy, sz};
+            if (wide) {
+                piece(rowbase + a0, rowbase + b0, sh);
+                if (b1 >= a1) {
+                    sh[0] = s1;
+                    piece(rowbase + a1, rowbase + b1, sh);
+                }
+            } else {
+                for (int32_t o = -M; o <= M; ++o) {
+                    int32_t cx;
+                    if (!wrap_cell(c[0] + o, nx, P.periodic[0], P.L[0], &cx, &sh[0])) continue;
+                    piece(rowbase + cx, rowbase + cx, sh);
+                }
+            }
         }
     }
-    constexpr int NROWS = D == 1 ? 1 : (D == 2 ? 3 : 9);
-    const T r2 = P.r2;
-    for (int rr = 0; rr < NROWS; ++rr) {
-        T sh[3] = {T(0), T(0), T(0)};
-        uint32_t row = 0;
-        bool skip = false;
-        if constexpr (D >= 2) {
-            int32_t v = c[1] + (rr % 3) - 1;
-            if (v < 0) { if (!P.periodic[1]) skip = true; v += P.n[1]; sh[1] = -P.L[1]; }
-            else if (v >= P.n[1]) { if (!P.periodic[1]) skip = true; v -= P.n[1]; sh[1] = P.L[1]; }
-            row = (uint32_t)v;
-        }
-        if constexpr (D >= 3) {
-            int32_t v = c[2] + (rr / 3) - 1;
-            if (v < 0) { if (!P.periodic[2]) skip = true; v += P.n[2]; sh[2] = -P.L[2]; }
-            else if (v >= P.n[2]) { if (!P.periodic[2]) skip = true; v -= P.n[2]; sh[2] = P.L[2]; }
-            row += (uint32_t)P.n[1] * (uint32_t)v;
-        }
-        if (skip) continue;
-        const uint32_t rowbase = P.cell_base + (uint32_t)nx * row;
-        for (int p = 0; p < np; ++p) {
-            const uint32_t j0 = off[rowbase + plo[p]];
-            const uint32_t j1 = min(off[rowbase + phi[p] + 1], n);
-            sh[0] = psh[p];
-            bool lane_shift = false;
+}
+
+// ---------------------------------------------------------------------------
+// flattened box search with per-lane pruning
+// ---------------------------------------------------------------------------
+
+// Per-lane slot ranges of the flattened search, in LDS: entry k of lane t at
+// [k][t] (consecutive lanes in consecutive banks).  code packs the image shift
+// of the range, two bits per dimension (0: none, 1: -L, 2: +L).
+template <int CAP, int BLOCK>
+struct FlatRanges {
+    uint2 range[CAP][BLOCK];
+    uint8_t code[CAP][BLOCK];
+};
+
+template <typename T, int D>
+__device__ __forceinline__ void decode_shift(const SysParams<T>& P, uint32_t code, T* sh) {
 #pragma unroll
-            for (int k = 0; k < D; ++k) lane_shift |= sh[k] != T(0);
-            if (__ballot(lane_shift) != 0ull)
-                scan_range<T, D, true, OFF32>(xs, j0, j1, xi, sh, r2, lane_shift, visit);
-            else
-                scan_range<T, D, false, OFF32>(xs, j0, j1, xi, sh, r2, false, visit);
+    for (int k = 0; k < D; ++k) {
+        const uint32_t b = (code >> (2 * k)) & 3u;
+        sh[k] = b == 1u ? -P.L[k] : (b == 2u ? P.L[k] : T(0));
+    }
+}
+
+// Lower bound of the length between the point and any point of the cell `o`
+// cells away in one dimension, squared.  g = o - fr (o > 0) or fr - o - 1
+// (o < 0) is the gap in cell units; the slack and the rounded-down cell width
+// cover the rounding of the cell assignment of both points and of the image
+// shift, so a cell this bound prunes can hold no pair the predicate accepts.
+template <typename T>
+__device__ __forceinline__ T gap2(const SysParams<T>& P, int k, int32_t o, T fr) {
+    const T g = o > 0 ? T(o) - fr : (o < 0 ? fr - T(o) - T(1) : T(0));
+    const T gl = max(g - P.slack[k], T(0)) * P.w_lo[k];
+    return gl * gl;
+}
+
+// The box search of neighbour_loop, flattened per lane.  Each lane first lists
+// the slot ranges of its (row, piece) sequence in LDS, dropping every row and
+// every cell at the ends of a row that the pruning bound (gap2, threshold
+// P.prune_r2) shows to be out of reach, and empty ranges; then it walks the
+// listed ranges as one sequence, one candidate per iteration, so the wave
+// runs as many iterations as its busiest lane has candidates instead of the
+// sum over rows of the longest row.  A lane lists at most CAP ranges per
+// round; rounds repeat while a lane of the wave has rows left.  The accepted
+// neighbours and their order are those of neighbour_loop (pruning removes only
+// candidates the predicate rejects).  A lane uses its own LDS column only, so
+// no barrier is needed and lanes past the end may simply not call it.  t_self
+// is the lane's own slot (< n), the target of loads issued past its last
+// candidate.
+template <typename T, int D, int CAP, int BLOCK, bool OFF32, typename Visit>
+__device__ __forceinline__ void flat_loop(const SysParams<T>& P, const T* __restrict__ xs,
+                                          const uint32_t* __restrict__ off, uint32_t n, const T* xi,
+                                          uint32_t t_self, FlatRanges<CAP, BLOCK>& fr_lds, Visit&& visit) {
+    constexpr int PITCH = Pitch<D>::value;
+    const uint32_t t = threadIdx.x;
+    int32_t c[3] = {0, 0, 0};
+    T fr[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int k = 0; k < D; ++k) c[k] = cell_coord(P, k, xi[k], &fr[k]);
+    const int32_t M = P.reach;
+    const int32_t nx = P.n[0];
+    const bool wide = nx >= 2 * M + 1;
+    const T pr2 = P.prune_r2;
+    // squared x gaps of the offsets -t and +t, t = 1..3 (+inf past the reach)
+    T gxn[kMaxReach], gxp[kMaxReach];
+#pragma unroll
+    for (int q = 0; q < kMaxReach; ++q) {
+        const bool in = q < M;
+        gxn[q] = in ? gap2(P, 0, -(q + 1), fr[0]) : T(INFINITY);
+        gxp[q] = in ? gap2(P, 0, q + 1, fr[0]) : T(INFINITY);
+    }
+    // ranges a row can add: one run and one wrapped run, or one per offset
+    const int pmax = wide ? (P.periodic[0] ? 2 : 1) : 2 * M + 1;
+    const int32_t zr = D >= 3 ? M : 0, yr = D >= 2 ? M : 0;
+    int32_t dy = -yr, dz = -zr;
+    bool rows_left = true;
+    const T r2 = P.r2;
+    while (__ballot(rows_left) != 0ull) {
+        // ---- list up to CAP ranges ----
+        int kd = 0;
+        bool any_shift = false;
+        auto put = [&](uint32_t ca, uint32_t cb, uint32_t code) {
+            const uint32_t j0 = off[ca];
+            const uint32_t j1 = min(off[cb + 1], n);
+            if (j1 > j0) {
+                fr_lds.range[kd][t] = make_uint2(j0, j1);
+                fr_lds.code[kd][t] = (uint8_t)code;
+                any_shift |= code != 0u;
+                ++kd;
+            }
+        };
+        while (rows_left && kd + pmax <= CAP) {
+            const int32_t ry = dy, rz = dz;
+            if (++dy > yr) {
+                dy = -yr;
+                if (++dz > zr) rows_left = false;
+            }
+            const T g2 = (D >= 2 ? gap2(P, 1, ry, fr[1]) : T(0)) + (D >= 3 ? gap2(P, 2, rz, fr[2]) : T(0));
+            if (!(g2 < pr2)) continue;
+            int32_t cz = 0, cy = 0;
+            T sz = T(0), sy = T(0);
+            if (D >= 3 && !wrap_cell(c[2] + rz, P.n[2], P.periodic[2], P.L[2], &cz, &sz)) continue;
+            if (D >= 2 && !wrap_cell(c[1] + ry, P.n[1], P.periodic[1], P.L[1], &cy, &sy)) continue;
+            const uint32_t yz = (sy < T(0) ? 1u : (sy > T(0) ? 2u : 0u)) << 2 |
+                                (sz < T(0) ? 1u : (sz > T(0) ? 2u : 0u)) << 4;
+            // offsets lo..hi of the row that the bound keeps (the bound grows with |o|)
+            int32_t lo = 0, hi = 0;
+#pragma unroll
+            for (int q = 0; q < kMaxReach; ++q) {
+                lo -= (gxn[q] + g2 < pr2) ? 1 : 0;
+                hi += (gxp[q] + g2 < pr2) ? 1 : 0;
+            }
+            const uint32_t rowbase = P.cell_base + (uint32_t)nx * ((uint32_t)cy + (uint32_t)P.n[1] * (uint32_t)cz);
+            if (wide) {
+                put(rowbase + max(c[0] + lo, 0), rowbase + min(c[0] + hi, nx - 1), yz);
+                if (P.periodic[0]) {
+                    if (c[0] + lo < 0) put(rowbase + (c[0] + lo + nx), rowbase + (nx - 1), yz | 1u);
+                    else if (c[0] + hi >= nx) put(rowbase, rowbase + (c[0] + hi - nx), yz | 2u);
+                }
+            } else {
+                for (int32_t o = lo; o <= hi; ++o) {
+                    int32_t cx;
+                    T sx;
+                    if (!wrap_cell(c[0] + o, nx, P.periodic[0], P.L[0], &cx, &sx)) continue;
+                    put(rowbase + cx, rowbase + cx, yz | (sx < T(0) ? 1u : (sx > T(0) ? 2u : 0u)));
+                }
+            }
         }
+        // ---- walk the listed ranges as one sequence ----
+        // Two candidate registers, A and B, alternate: one is tested while the
+        // other's load is in flight.  Every step reads the range the cursor
+        // takes next from LDS, so a range change uses a value read one step
+        // earlier, and issues its load unconditionally (a lane past its last
+        // candidate reloads its own row); the loop leaves only when no lane of
+        // the wave has candidates left.
+        auto walk = [&](auto shift_tag) {
+            constexpr bool SHIFT = decltype(shift_tag)::value;
+            uint32_t kr = 0u;  // index of the next range to take
+            uint2 ndp = fr_lds.range[0][t];
+            uint32_t ndc = SHIFT ? (uint32_t)fr_lds.code[0][t] : 0u;
+            uint32_t j = 0u, e = 0u;
+            bool alive = true;
+            T cs[3] = {T(0), T(0), T(0)};  // shift of the cursor's range
+            // the slot of the lane's next candidate (its own slot once it has none)
+            auto step = [&]() -> uint32_t {
+                ++j;
+                if (j >= e) {
+                    if (kr < (uint32_t)kd) {
+                        j = ndp.x;
+                        e = ndp.y;
+                        if (SHIFT) decode_shift<T, D>(P, ndc, cs);
+                        ++kr;
+                    } else {
+                        alive = false;
+                    }
+                }
+                const uint32_t kn = min(kr, (uint32_t)(CAP - 1));
+                ndp = fr_lds.range[kn][t];
+                if (SHIFT) ndc = fr_lds.code[kn][t];
+                return alive ? j : t_self;
+            };
+            // evaluated on every lane (an idle lane tests its own row, which the
+            // predicate rejects) so that the wait for the row is never skipped
+            auto test = [&](const VecN<T, PITCH>& xj, uint32_t jj, const T* sh, bool valid) {
+                T dx[D], d2;
+                const bool acc = pair_test<T, D, SHIFT>(xj.v, xi, sh, r2, dx, &d2);
+                if (acc & valid) {
+                    bool shifted = false;
+                    if (SHIFT) {
+#pragma unroll
+                        for (int k = 0; k < D; ++k) shifted |= sh[k] != T(0);
+                    }
+                    visit(jj, dx, d2, shifted);
+                }
+            };
+            T sa[3], sb[3];
+            uint32_t ja = step();
+            bool va = alive;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) sa[k] = cs[k];
+            VecN<T, PITCH> A = load_row<T, PITCH, OFF32>(xs, ja);
+            for (;;) {
+                const uint32_t jb = step();
+                const bool vb = alive;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) sb[k] = cs[k];
+                const VecN<T, PITCH> B = load_row<T, PITCH, OFF32>(xs, jb);
+                test(A, ja, sa, va);
+                if (__ballot(vb) == 0ull) break;
+                ja = step();
+                va = alive;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) sa[k] = cs[k];
+                A = load_row<T, PITCH, OFF32>(xs, ja);
+                test(B, jb, sb, vb);
+                if (__ballot(va) == 0ull) break;
+            }
+        };
+        if (__ballot(any_shift) != 0ull) walk(std::integral_constant<bool, true>());
+        else walk(std::integral_constant<bool, false>());
     }
 }
 
@@ -726,6 +955,9 @@ void launch_nbr_bwd(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, 
 template <typename T, int D, int OP, bool BATCH>
 void launch_lane_fused(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, const T* gy_s,
                        T* y, T* gx, T* ga);
+template <typename T, int D, int OP, bool BATCH, int MODE>
+void launch_flat(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, const T* gy_s, T* y,
+                 T* gx, T* ga);
 
 // Lane-per-particle forward / adjoint whose candidates are staged in LDS per
 // stencil row (needs 32-bit row offsets: off32_rows).

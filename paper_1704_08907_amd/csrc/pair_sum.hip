@@ -85,7 +85,8 @@ aboria_status gather(aboria_ctx* ctx, const aboria_cells* c, const void* src, in
 
 // Work-mapping variants of the neighbour sums.
 struct Variant {
-    int kind;      // 0 = lane per particle, 1 = cell group, 2 = recorded neighbour list
+    int kind;      // 0 = lane per particle, 1 = cell group, 2 = recorded neighbour list,
+                   // 3 = all pairs, 4 = LDS-staged rows, 5 = flattened pruned search
     int block;     // threads per workgroup (lane mapping)
     bool compact;  // adjoint lists accepted pairs before evaluating them (lane mapping)
     int rounds;    // cell group: 1 = natural cell order, 8 = 64-cell tiles ranked by occupancy
@@ -102,7 +103,11 @@ const Variant kVariants[] = {
     {2, 256, false, 0, "lane per particle over the recorded neighbour list (accepted pairs only)"},
     {3, 256, false, 0, "lane per particle over all particles of its system (minimum image; small systems)"},
     {4, 256, false, 0, "lane per particle, candidates staged in LDS per stencil row and wave"},
+    {5, 256, false, 0, "lane per particle, flattened box search over pruned slot ranges listed in LDS"},
 };
+
+// Modes of the flattened kernel (pair_flat.hpp).
+constexpr int kFlatModeFwd = 0, kFlatModeBwd = 1, kFlatModeFused = 2;
 
 // Largest system the all-pairs variant accepts (its lanes test every particle of their system).
 constexpr int64_t kAllPairsMaxSystem = 16384;
@@ -110,6 +115,16 @@ constexpr int64_t kAllPairsMaxSystem = 16384;
 bool off32_ok(const aboria_cells* c) {
     return c->dtype == ABORIA_F32 ? off32_rows<float>((uint64_t)c->n) : off32_rows<double>((uint64_t)c->n);
 }
+
+// Largest search reach over the systems of a cell list.
+int32_t max_reach(const aboria_cells* c) {
+    int32_t m = 1;
+    for (const aboria_box& b : c->boxes) m = std::max<int32_t>(m, b.reach == 0 ? 1 : b.reach);
+    return m;
+}
+
+// Variants with their own box-search loops, written for the 3^d stencil.
+bool needs_reach1(const Variant& v) { return v.kind == 1 || v.kind == 4 || (v.kind == 0 && v.compact); }
 
 int64_t largest_system(const aboria_cells* c) {
     int64_t m = 0;
@@ -121,7 +136,8 @@ constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 template <typename T, int D, int OP, bool BATCH>
 void launch_fwd_variant(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, T* y,
                         const Variant& v) {
-    if (v.kind == 4) launch_stage_fwd<T, D, OP, BATCH>(ctx, c, q, a_s, y);
+    if (v.kind == 5) launch_flat<T, D, OP, BATCH, kFlatModeFwd>(ctx, c, q, a_s, nullptr, y, nullptr, nullptr);
+    else if (v.kind == 4) launch_stage_fwd<T, D, OP, BATCH>(ctx, c, q, a_s, y);
     else if (v.kind == 3) launch_all_fwd<T, D, OP, BATCH>(ctx, c, q, a_s, y);
     else if (v.kind == 2) launch_nbr_fwd<T, D, OP, BATCH>(ctx, c, q, a_s, y);
     else if (v.kind == 1) launch_cells_fwd<T, D, OP, BATCH>(ctx, c, q, a_s, y, v.rounds);
@@ -131,7 +147,8 @@ void launch_fwd_variant(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>&
 template <typename T, int D, int OP, bool BATCH>
 void launch_bwd_variant(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, const T* gy_s,
                         T* gx, T* ga, const Variant& v) {
-    if (v.kind == 4) launch_stage_bwd<T, D, OP, BATCH>(ctx, c, q, a_s, gy_s, gx, ga);
+    if (v.kind == 5) launch_flat<T, D, OP, BATCH, kFlatModeBwd>(ctx, c, q, a_s, gy_s, nullptr, gx, ga);
+    else if (v.kind == 4) launch_stage_bwd<T, D, OP, BATCH>(ctx, c, q, a_s, gy_s, gx, ga);
     else if (v.kind == 3) launch_all_bwd<T, D, OP, BATCH>(ctx, c, q, a_s, gy_s, gx, ga);
     else if (v.kind == 2) launch_nbr_bwd<T, D, OP, BATCH>(ctx, c, q, a_s, gy_s, gx, ga);
     else if (v.kind == 1) launch_cells_bwd<T, D, OP, BATCH>(ctx, c, q, a_s, gy_s, gx, ga, v.rounds);
@@ -205,6 +222,8 @@ aboria_status check_variant(aboria_ctx* ctx, const aboria_cells* c, int variant)
         return fail(ctx, ABORIA_ERR_INVALID_ARG, "the all-pairs variant takes systems of at most 16384 particles");
     if (variant_of(variant).kind == 4 && !off32_ok(c))
         return fail(ctx, ABORIA_ERR_INVALID_ARG, "the staged variant needs rows below a 32-bit byte offset");
+    if (needs_reach1(variant_of(variant)) && max_reach(c) > 1)
+        return fail(ctx, ABORIA_ERR_INVALID_ARG, "the variant searches the 3^d stencil only (reach 1)");
     return ABORIA_OK;
 }
 
@@ -227,6 +246,7 @@ bool variant_worth_timing(int32_t v, const aboria_cells* c) {
 
 bool variant_usable(int32_t v, const aboria_cells* c) {
     if (v < 0 || v >= kNumVariants) return false;
+    if (needs_reach1(kVariants[v]) && max_reach(c) > 1) return false;
     if (kVariants[v].kind == 2) return c->nbr_recorded;
     if (kVariants[v].kind == 3) return largest_system(c) <= kAllPairsMaxSystem;
     if (kVariants[v].kind == 4) return off32_ok(c);
@@ -243,11 +263,18 @@ int32_t list_variant() {
 // cells (the small-N switch; the autotuner decides for tuned cell lists).
 constexpr int64_t kAllPairsDefaultMax = 2048;
 
+int32_t flat_variant() {
+    for (int32_t v = 0; v < kNumVariants; ++v)
+        if (kVariants[v].kind == 5) return v;
+    return 0;
+}
+
 int32_t default_variant(const aboria_cells* c) {
     if (largest_system(c) <= kAllPairsDefaultMax)
         for (int32_t v = 0; v < kNumVariants; ++v)
             if (kVariants[v].kind == 3) return v;
-    return c->nbr_recorded ? list_variant() : 0;
+    if (c->nbr_recorded) return list_variant();
+    return max_reach(c) > 1 ? flat_variant() : 0;
 }
 
 aboria_status pair_sum_impl(aboria_ctx* ctx, const aboria_cells* c, int32_t op, const double* params,
@@ -334,11 +361,13 @@ namespace {
 
 template <typename T, int D>
 aboria_status fused_op(aboria_ctx* ctx, const aboria_cells* c, int op, const OpArgs<T>& q, const T* a_s,
-                       const T* gy_s, T* y, T* gx, T* ga) {
+                       const T* gy_s, T* y, T* gx, T* ga, bool flat) {
     if (c->n == 0) return ABORIA_OK;
     const bool batch = c->nsys > 1;
-#define F(OPC)                                                                       \
-    if (batch) launch_lane_fused<T, D, OPC, true>(ctx, c, q, a_s, gy_s, y, gx, ga);  \
+#define F(OPC)                                                                                      \
+    if (flat && batch) launch_flat<T, D, OPC, true, kFlatModeFused>(ctx, c, q, a_s, gy_s, y, gx, ga);   \
+    else if (flat) launch_flat<T, D, OPC, false, kFlatModeFused>(ctx, c, q, a_s, gy_s, y, gx, ga);      \
+    else if (batch) launch_lane_fused<T, D, OPC, true>(ctx, c, q, a_s, gy_s, y, gx, ga);                \
     else launch_lane_fused<T, D, OPC, false>(ctx, c, q, a_s, gy_s, y, gx, ga);
     switch (op) {
         case ABORIA_OP_COUNT: F(ABORIA_OP_COUNT) break;
@@ -354,7 +383,8 @@ aboria_status fused_op(aboria_ctx* ctx, const aboria_cells* c, int op, const OpA
 
 template <typename T>
 aboria_status fused_impl(aboria_ctx* ctx, const aboria_cells* c, int32_t op, const double* params, int32_t nparams,
-                         const void* a, int32_t na, const void* gy, int32_t ny, void* y, void* gx, void* ga) {
+                         const void* a, int32_t na, const void* gy, int32_t ny, void* y, void* gx, void* ga,
+                         bool flat) {
     OpArgs<T> q{nparams > 0 ? (T)params[0] : T(0)};
     aboria_status st;
     const T* a_s = nullptr;
@@ -365,9 +395,9 @@ aboria_status fused_impl(aboria_ctx* ctx, const aboria_cells* c, int32_t op, con
     if ((st = gather<T>(ctx, c, gy, ny, c->work2)) != ABORIA_OK) return st;
     const T* g_s = (const T*)c->work2;
     switch (c->d) {
-        case 1: return fused_op<T, 1>(ctx, c, op, q, a_s, g_s, (T*)y, (T*)gx, (T*)ga);
-        case 2: return fused_op<T, 2>(ctx, c, op, q, a_s, g_s, (T*)y, (T*)gx, (T*)ga);
-        default: return fused_op<T, 3>(ctx, c, op, q, a_s, g_s, (T*)y, (T*)gx, (T*)ga);
+        case 1: return fused_op<T, 1>(ctx, c, op, q, a_s, g_s, (T*)y, (T*)gx, (T*)ga, flat);
+        case 2: return fused_op<T, 2>(ctx, c, op, q, a_s, g_s, (T*)y, (T*)gx, (T*)ga, flat);
+        default: return fused_op<T, 3>(ctx, c, op, q, a_s, g_s, (T*)y, (T*)gx, (T*)ga, flat);
     }
 }
 
@@ -479,8 +509,11 @@ extern "C" aboria_status aboria_pair_sum_and_backward(aboria_ctx* ctx, const abo
                 if (&o2 != &o && o2.p && overlaps(o.p, o.bytes, o2.p, o2.bytes))
                     return fail(ctx, ABORIA_ERR_INVALID_ARG, "outputs overlap");
         }
-        return c->dtype == ABORIA_F32 ? fused_impl<float>(ctx, c, op, params_host, nparams, a, na, gy, ny, y, gx, ga)
-                                      : fused_impl<double>(ctx, c, op, params_host, nparams, a, na, gy, ny, y, gx, ga);
+        // one box search for both: the flattened one when the forward would use it
+        const bool flat = variant_of(pick_variant(ctx, c, op, false)).kind == 5;
+        return c->dtype == ABORIA_F32
+                   ? fused_impl<float>(ctx, c, op, params_host, nparams, a, na, gy, ny, y, gx, ga, flat)
+                   : fused_impl<double>(ctx, c, op, params_host, nparams, a, na, gy, ny, y, gx, ga, flat);
     } catch (...) {
         return fail(ctx, ABORIA_ERR_OUT_OF_MEMORY, "host exception in pair_sum_and_backward");
     }

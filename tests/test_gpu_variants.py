@@ -86,7 +86,7 @@ def test_autotuned_cell_size_gives_valid_coarser_grids(ctx):
         tuned, f = A.autotune_cells(ctx, x_d, boxes, offsets, op, params, gy=gy)
         assert f in (1.0, 0.85, 0.7, 0.55)
         for s, t in zip(w.systems, tuned):
-            auto = oracle.grid_of(s).ncell
+            auto = oracle.grid_of(s, None, t.reach).ncell
             assert list(t.ncell) == [max(1, math.floor(f * a)) for a in auto]
         cells = A.build_cells(ctx, x_d, tuned, offsets)
         y = A.pair_sum(ctx, cells, "spring", (1.0,))
@@ -94,7 +94,7 @@ def test_autotuned_cell_size_gives_valid_coarser_grids(ctx):
         ctx.sync()
         for b in (0, 7, 15):
             s, t = w.systems[b], tuned[b]
-            g = oracle.grid(3, s.lo, s.hi, s.periodic, s.cutoff, "f32", list(t.ncell))
+            g = oracle.grid(3, s.lo, s.hi, s.periodic, s.cutoff, "f32", list(t.ncell), t.reach)
             lo, hi = offsets[b], offsets[b + 1]
             yo, so = oracle.pair_sum(g, "spring", (1.0,), s.x)
             check_close(y.cpu().numpy()[lo:hi], yo, so, TOL_F32, "tuned grid system %d" % b)
