@@ -85,20 +85,21 @@ def counted_traffic(names):
 
 
 def profile_names(variant_name, direction):
-    """Kernel names as rocprofv3 reports them for the spring cube (float32, d = 3, no batch)."""
+    """Kernel names as rocprofv3 reports them for the spring cube (float32, d = 3, no batch,
+    32-bit row offsets)."""
     if "recorded" in variant_name:
         k = ["k_nbr_fwd<float, 3, 1, false>"] if direction == "fwd" else ["k_nbr_bwd<float, 3, 1, false>"]
-    elif "cell group" in variant_name:
+    elif "cell group" in variant_name or "LDS list" in variant_name or "staged" in variant_name:
         return None
+    elif "flattened" in variant_name:
+        k = ["k_flat<float, 3, 1, false, true, %d>" % (0 if direction == "fwd" else 1)]
     elif direction == "fwd":
-        k = ["k_lane_fwd<float, 3, 1, false>"]
+        k = ["k_lane_fwd<float, 3, 1, false, true>"]
     elif "queue" in variant_name:
         k = ["k_lane_bwd_queue<float, 3, 1, false>"]
-    elif "LDS list" in variant_name:
-        return None
     else:
-        k = ["k_lane_bwd<float, 3, 1, false>"]
-    return k if direction == "fwd" else ["k_gather_rows<float, 3>"] + k
+        k = ["k_lane_bwd<float, 3, 1, false, true>"]
+    return k if direction == "fwd" else ["k_gather_rows<float, 3, 4>"] + k
 
 
 def candidate_count(cells) -> int:
@@ -282,17 +283,9 @@ def main():
     nc = int(cells.view().ncells)
 
     def kernel_of(v, direction):
-        name = A.variant_name(v)
-        if "recorded" in name:
-            k = "k_nbr_fwd<float,3,SPRING>" if direction == "fwd" else "k_nbr_bwd<float,3,SPRING>"
-        elif "cell group" in name:
-            k = "k_pair_cells<float,3,SPRING>"
-        elif direction == "fwd":
-            k = "k_lane_fwd<float,3,SPRING>"
-        else:
-            k = {"queue": "k_lane_bwd_queue", "LDS list": "k_lane_bwd_compact"}.get(
-                next((t for t in ("queue", "LDS list") if t in name), ""), "k_lane_bwd") + "<float,3,SPRING>"
-        return k if direction == "fwd" else "k_gather_rows<float,3> + " + k
+        """The call's kernels as rocprofv3 names them (a readable label where no profile row exists)."""
+        names = profile_names(A.variant_name(v), direction)
+        return " + ".join(names) if names else A.variant_name(v)
 
     # algorithmic work of each call of the step: (kernel, time, VALU lane-ops, HBM bytes)
     # box-search sums: every candidate is tested; each call reads xs (16 B), the offsets, perm (4) and
@@ -313,7 +306,7 @@ def main():
     else:
         t_fwd, t_bwd = t_fwd_list, t_bwd_list
         phases = {
-            "neighbours": ("k_nbr_build<float,3> (neighbour-list recording)", t_nbr,
+            "neighbours": ("k_nbr_build<float, 3, false> (neighbour-list recording)", t_nbr,
                            cand * OPS_PER_CANDIDATE, n * (16 + 4) + 4 * (nc + 1) + 4 * pairs, None),
             "fwd": (kernel_of(variant_fwd, "fwd") + " (forward call, replay)", t_fwd,
                     pairs * (OPS_PER_REPLAYED_PAIR + OPS_PER_PAIR["fwd"]), 4 * pairs + n * (16 + 4 + 4 + 12),
@@ -368,6 +361,23 @@ def main():
     # ---------------- other workloads ----------------
     extra = {}
     if not args.no_extra:
+        # candidate reduction: the same cube on cells about r/2 wide searched two cells deep,
+        # by the row search and by the flattened, pruned search
+        box_r2 = A.BoxSpec(3, s.lo, s.hi, s.periodic, s.cutoff, None, 2)
+        c_r2 = A.build_cells(ctx, x, [box_r2])
+        r2 = {"ncell": [int(c_r2.view().ncell_host[k]) for k in range(3)],
+              "build_ms": timed_graph(lambda: A.build_cells(ctx, x, [box_r2], cells=c_r2), reps=10)}
+        for label, word in (("row_search", "adjoint evaluated on every candidate"), ("flattened", "flattened")):
+            ctx.set_variant(next(v for v in range(A.variant_count()) if word in A.variant_name(v)))
+            r2[label + "_fwd_ms"] = timed_graph(lambda: A.pair_sum(ctx, c_r2, "spring", (1.0,), y=y), reps=10)
+            r2[label + "_bwd_ms"] = timed_graph(
+                lambda: A.pair_sum_backward(ctx, c_r2, "spring", (1.0,), gy, gx=gx), reps=10)
+        ctx.set_variant(-1)
+        r2["step_ms_best"] = r2["build_ms"] + min(r2["row_search_fwd_ms"], r2["flattened_fwd_ms"]) + min(
+            r2["row_search_bwd_ms"], r2["flattened_bwd_ms"])
+        extra["spring_cube_reach2"] = r2
+        c_r2.close()
+
         # dense Gaussian sum, N = 65536, d = 2
         xd, wd, sigma = syn.gaussian_square()
         xd_t = torch.from_numpy(xd).to(dev)

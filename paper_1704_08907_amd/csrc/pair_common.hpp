@@ -280,23 +280,97 @@ __device__ __forceinline__ bool pair_test(const T* xj, const T* xi, const T* sh,
 // One contiguous slot range [j0, j1) of candidates with one image shift:
 // visit(j, dx, d2, shifted) for the accepted ones, shifted = the lane's shift
 // is nonzero in some dimension.  Two candidates are loaded per iteration so
-// their loads overlap.
-template <typename T, int D, bool SHIFT, bool OFF32, typename Visit>
+// their loads overlap.  With NAUX > 0 the candidates' rows of aux (NAUX
+// elements, padded as gradient rows) are loaded with their positions and
+// passed as a fifth argument, so an accepted pair never waits for them.
+template <typename T, int D, bool SHIFT, bool OFF32, int NAUX = 0, typename Visit>
 __device__ __forceinline__ void scan_range(const T* __restrict__ xs, uint32_t j0, uint32_t j1, const T* xi,
-                                           const T* sh, T r2, bool shifted, Visit& visit) {
+                                           const T* sh, T r2, bool shifted, Visit& visit,
+                                           const T* __restrict__ aux = nullptr) {
     constexpr int PITCH = Pitch<D>::value;
+    constexpr int AP = NAUX > 0 ? GyPitch<NAUX>::value : 1;
+    auto call = [&](uint32_t jj, const T* dx, T d2, const VecN<T, AP>& av) {
+        if constexpr (NAUX > 0) visit(jj, dx, d2, shifted, av.v);
+        else visit(jj, dx, d2, shifted);
+    };
     uint32_t j = j0;
     for (; j + 1 < j1; j += 2) {
         const VecN<T, PITCH> a = load_row<T, PITCH, OFF32>(xs, j);
         const VecN<T, PITCH> b = load_row<T, PITCH, OFF32>(xs, j + 1);
+        VecN<T, AP> aa{}, ab{};
+        if constexpr (NAUX > 0) {
+            aa = load_row<T, AP, OFF32>(aux, j);
+            ab = load_row<T, AP, OFF32>(aux, j + 1);
+        }
         T dx[D], d2;
-        if (pair_test<T, D, SHIFT>(a.v, xi, sh, r2, dx, &d2)) visit(j, dx, d2, shifted);
-        if (pair_test<T, D, SHIFT>(b.v, xi, sh, r2, dx, &d2)) visit(j + 1, dx, d2, shifted);
+        if (pair_test<T, D, SHIFT>(a.v, xi, sh, r2, dx, &d2)) call(j, dx, d2, aa);
+        if (pair_test<T, D, SHIFT>(b.v, xi, sh, r2, dx, &d2)) call(j + 1, dx, d2, ab);
     }
     if (j < j1) {
         const VecN<T, PITCH> a = load_row<T, PITCH, OFF32>(xs, j);
+        VecN<T, AP> aa{};
+        if constexpr (NAUX > 0) aa = load_row<T, AP, OFF32>(aux, j);
         T dx[D], d2;
-        if (pair_test<T, D, SHIFT>(a.v, xi, sh, r2, dx, &d2)) visit(j, dx, d2, shifted);
+        if (pair_test<T, D, SHIFT>(a.v, xi, sh, r2, dx, &d2)) call(j, dx, d2, aa);
+    }
+}
+
+// Operators whose adjoint summand (a d-vector update with a reciprocal square
+// root and a dozen multiply-adds) costs several pair tests: their adjoint runs
+// the deferred scan.  The soft sphere's scalar summand and the count do not.
+template <int OP>
+constexpr bool kDeferAdjoint = OP == ABORIA_OP_SPRING || OP == ABORIA_OP_EXP_FORCE || OP == ABORIA_OP_DEM_SPRING;
+
+// scan_range in two passes per chunk of up to 32 candidates, for summands that
+// cost much more than the pair test (the adjoint): the first pass tests every
+// candidate and keeps a bit per accepted one; the second pops the bits in
+// increasing order, reloads that candidate's position and aux row (the
+// neighbour's gradient row), recomputes its dx and d2 exactly as the test did
+// and calls visit(j, dx, d2, shifted, aux_j).  In SIMD the summand then runs
+// as many times per chunk as the busiest lane has accepted pairs, instead of
+// once per candidate that any lane of the wave accepts.  The pairs and their
+// order are those of scan_range, so the sums are bit for bit the same.
+template <typename T, int D, bool SHIFT, bool OFF32, int NAUX, typename Visit>
+__device__ __forceinline__ void scan_range_deferred(const T* __restrict__ xs, const T* __restrict__ aux,
+                                                    uint32_t j0, uint32_t j1, const T* xi, const T* sh, T r2,
+                                                    bool shifted, Visit& visit) {
+    constexpr int PITCH = Pitch<D>::value;
+    constexpr int AP = GyPitch<NAUX>::value;
+    for (uint32_t c0 = j0; c0 < j1; c0 += 32u) {
+        const uint32_t c1 = min(c0 + 32u, j1);
+        uint32_t mask = 0u;
+        uint32_t j = c0;
+        for (; j + 1 < c1; j += 2) {
+            const VecN<T, PITCH> a = load_row<T, PITCH, OFF32>(xs, j);
+            const VecN<T, PITCH> b = load_row<T, PITCH, OFF32>(xs, j + 1);
+            T dx[D], d2;
+            mask |= (pair_test<T, D, SHIFT>(a.v, xi, sh, r2, dx, &d2) ? 1u : 0u) << (j - c0);
+            mask |= (pair_test<T, D, SHIFT>(b.v, xi, sh, r2, dx, &d2) ? 1u : 0u) << (j + 1 - c0);
+        }
+        if (j < c1) {
+            const VecN<T, PITCH> a = load_row<T, PITCH, OFF32>(xs, j);
+            T dx[D], d2;
+            mask |= (pair_test<T, D, SHIFT>(a.v, xi, sh, r2, dx, &d2) ? 1u : 0u) << (j - c0);
+        }
+        // two accepted pairs per iteration, so their four loads overlap
+        while (mask != 0u) {
+            const uint32_t ja = c0 + (uint32_t)__builtin_ctz(mask);
+            mask &= mask - 1u;
+            const bool vb = mask != 0u;
+            const uint32_t jb = vb ? c0 + (uint32_t)__builtin_ctz(mask) : ja;
+            mask &= mask - 1u;
+            const VecN<T, PITCH> a = load_row<T, PITCH, OFF32>(xs, ja);
+            const VecN<T, AP> ava = load_row<T, AP, OFF32>(aux, ja);
+            const VecN<T, PITCH> b = load_row<T, PITCH, OFF32>(xs, jb);
+            const VecN<T, AP> avb = load_row<T, AP, OFF32>(aux, jb);
+            T dx[D], d2;
+            (void)pair_test<T, D, SHIFT>(a.v, xi, sh, r2, dx, &d2);
+            visit(ja, dx, d2, shifted, ava.v);
+            if (vb) {
+                (void)pair_test<T, D, SHIFT>(b.v, xi, sh, r2, dx, &d2);
+                visit(jb, dx, d2, shifted, avb.v);
+            }
+        }
     }
 }
 
@@ -345,10 +419,10 @@ __device__ __forceinline__ bool wrap_cell(int32_t v, int32_t n, int32_t periodic
 // lane of the wave runs the loop without the shift additions (adding zero is
 // exact, so both loops give the canonical dx).  flat_loop visits the accepted
 // neighbours in this same order.
-template <typename T, int D, bool OFF32 = false, typename Visit>
-__device__ __forceinline__ void neighbour_loop(const SysParams<T>& P, const T* __restrict__ xs,
-                                               const uint32_t* __restrict__ off, uint32_t n, const T* xi,
-                                               Visit&& visit) {
+template <typename T, int D, bool OFF32, int NAUX, typename Visit>
+__device__ __forceinline__ void neighbour_loop_aux(const SysParams<T>& P, const T* __restrict__ xs,
+                                                   const T* __restrict__ aux, const uint32_t* __restrict__ off,
+                                                   uint32_t n, const T* xi, Visit&& visit) {
     int32_t c[3] = {0, 0, 0};
 #pragma unroll
     for (int k = 0; k < D; ++k) {
@@ -372,10 +446,17 @@ __device__ __forceinline__ void neighbour_loop(const SysParams<T>& P, const T* _
         bool lane_shift = false;
 #pragma unroll
         for (int k = 0; k < D; ++k) lane_shift |= sh[k] != T(0);
-        if (__ballot(lane_shift) != 0ull)
-            scan_range<T, D, true, OFF32>(xs, j0, j1, xi, sh, r2, lane_shift, visit);
-        else
-            scan_range<T, D, false, OFF32>(xs, j0, j1, xi, sh, r2, false, visit);
+        if constexpr (NAUX > 0) {
+            if (__ballot(lane_shift) != 0ull)
+                scan_range_deferred<T, D, true, OFF32, NAUX>(xs, aux, j0, j1, xi, sh, r2, lane_shift, visit);
+            else
+                scan_range_deferred<T, D, false, OFF32, NAUX>(xs, aux, j0, j1, xi, sh, r2, false, visit);
+        } else {
+            if (__ballot(lane_shift) != 0ull)
+                scan_range<T, D, true, OFF32>(xs, j0, j1, xi, sh, r2, lane_shift, visit);
+            else
+                scan_range<T, D, false, OFF32>(xs, j0, j1, xi, sh, r2, false, visit);
+        }
     };
     const int32_t zr = D >= 3 ? M : 0, yr = D >= 2 ? M : 0;
     for (int32_t dz = -zr; dz <= zr; ++dz) {
@@ -403,6 +484,14 @@ __device__ __forceinline__ void neighbour_loop(const SysParams<T>& P, const T* _
             }
         }
     }
+}
+
+// The box search without prefetched per-candidate rows: visit(j, dx, d2, shifted).
+template <typename T, int D, bool OFF32 = false, typename Visit>
+__device__ __forceinline__ void neighbour_loop(const SysParams<T>& P, const T* __restrict__ xs,
+                                               const uint32_t* __restrict__ off, uint32_t n, const T* xi,
+                                               Visit&& visit) {
+    neighbour_loop_aux<T, D, OFF32, 0>(P, xs, nullptr, off, n, xi, visit);
 }
 
 // ---------------------------------------------------------------------------

@@ -39,13 +39,22 @@ __global__ __launch_bounds__(256) void k_lane_bwd(const T* __restrict__ xs, cons
 #pragma unroll
     for (int k = 0; k < D; ++k) accx[k] = T(0);
     const T r = P.r;
-    auto visit = [&](uint32_t j, const T* dx, T d2, bool) {
-        const T aj = OpShape<OP, D>::NA ? load_row<T, 1, OFF32>(a_s, j).v[0] : T(0);
-        T gyj[NY];
-        load_gy<T, NY, OFF32>(gy_s, j, gyj);
-        Op::bwd(q, r, dx, d2, ai, aj, gyi, gyj, accx, acca);
-    };
-    neighbour_loop<T, D, OFF32>(P, xs, off, n, xi, visit);
+    if constexpr (kDeferAdjoint<OP>) {
+        // accepted pairs first, then their summands (the neighbour's gradient row is
+        // loaded with its position)
+        auto visit = [&](uint32_t j, const T* dx, T d2, bool, const T* gyj) {
+            const T aj = OpShape<OP, D>::NA ? load_row<T, 1, OFF32>(a_s, j).v[0] : T(0);
+            Op::bwd(q, r, dx, d2, ai, aj, gyi, gyj, accx, acca);
+        };
+        neighbour_loop_aux<T, D, OFF32, NY>(P, xs, gy_s, off, n, xi, visit);
+    } else {
+        auto visit = [&](uint32_t j, const T* dx, T d2, bool) {
+            T gyj[NY];
+            load_gy<T, NY, OFF32>(gy_s, j, gyj);
+            Op::bwd(q, r, dx, d2, ai, T(0), gyi, gyj, accx, acca);
+        };
+        neighbour_loop<T, D, OFF32>(P, xs, off, n, xi, visit);
+    }
     const uint32_t o = perm[s];
 #pragma unroll
     for (int k = 0; k < D; ++k) gx[(size_t)o * D + k] = accx[k];
@@ -81,14 +90,22 @@ __global__ __launch_bounds__(256) void k_lane_fused(const T* __restrict__ xs, co
 #pragma unroll
     for (int k = 0; k < D; ++k) accx[k] = T(0);
     const T r = P.r;
-    auto visit = [&](uint32_t j, const T* dx, T d2, bool) {
-        const T aj = OpShape<OP, D>::NA ? load_row<T, 1, OFF32>(a_s, j).v[0] : T(0);
-        T gyj[NY];
-        load_gy<T, NY, OFF32>(gy_s, j, gyj);
-        Op::fwd(q, r, dx, d2, ai, aj, acc);
-        Op::bwd(q, r, dx, d2, ai, aj, gyi, gyj, accx, acca);
-    };
-    neighbour_loop<T, D, OFF32>(P, xs, off, n, xi, visit);
+    if constexpr (kDeferAdjoint<OP>) {
+        auto visit = [&](uint32_t j, const T* dx, T d2, bool, const T* gyj) {
+            const T aj = OpShape<OP, D>::NA ? load_row<T, 1, OFF32>(a_s, j).v[0] : T(0);
+            Op::fwd(q, r, dx, d2, ai, aj, acc);
+            Op::bwd(q, r, dx, d2, ai, aj, gyi, gyj, accx, acca);
+        };
+        neighbour_loop_aux<T, D, OFF32, NY>(P, xs, gy_s, off, n, xi, visit);
+    } else {
+        auto visit = [&](uint32_t j, const T* dx, T d2, bool) {
+            T gyj[NY];
+            load_gy<T, NY, OFF32>(gy_s, j, gyj);
+            Op::fwd(q, r, dx, d2, ai, T(0), acc);
+            Op::bwd(q, r, dx, d2, ai, T(0), gyi, gyj, accx, acca);
+        };
+        neighbour_loop<T, D, OFF32>(P, xs, off, n, xi, visit);
+    }
     const uint32_t o = perm[s];
 #pragma unroll
     for (int k = 0; k < NY; ++k) y[(size_t)o * NY + k] = acc[k];
