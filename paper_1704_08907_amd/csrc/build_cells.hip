@@ -24,8 +24,8 @@
 namespace aboria {
 
 constexpr int kBlock = 256;
-constexpr int kSortIpt = 16;                  // keys per thread per tile
-constexpr int kSortTile = kBlock * kSortIpt;  // 4096 keys per tile
+// A sort tile is kBlock * IPT keys, IPT = 16, 8 or 4 chosen per cell list by
+// sort_ipt_for.
 constexpr int kScanIpt = 16;
 constexpr int kScanTile = kBlock * kScanIpt;  // 4096 values per scan block
 constexpr int kMaxDigitBits = 10;
@@ -313,6 +313,7 @@ aboria_status fill_u32(aboria_ctx* ctx, uint32_t* p, uint32_t v, int64_t len) {
 // ---------------------------------------------------------------------------
 
 // hist[digit * ntiles + tile] = number of keys of the tile with that digit.
+template <int IPT>
 __global__ __launch_bounds__(kBlock) void k_radix_hist(const uint32_t* __restrict__ keys, uint32_t n, int shift,
                                                        int bits, uint32_t* __restrict__ hist, uint32_t ntiles) {
     extern __shared__ uint32_t lds[];
@@ -320,9 +321,9 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(const uint32_t* __restric
     for (uint32_t d = threadIdx.x; d < radix; d += kBlock) lds[d] = 0;
     __syncthreads();
     const uint32_t tile = blockIdx.x;
-    const uint32_t base = tile * kSortTile;
+    const uint32_t base = tile * (kBlock * IPT);
 #pragma unroll 4
-    for (int k = 0; k < kSortIpt; ++k) {
+    for (int k = 0; k < IPT; ++k) {
         uint32_t idx = base + k * kBlock + threadIdx.x;
         if (idx < n) atomicAdd(&lds[(keys[idx] >> shift) & mask], 1u);
     }
@@ -330,8 +331,9 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(const uint32_t* __restric
     for (uint32_t d = threadIdx.x; d < radix; d += kBlock) hist[(size_t)d * ntiles + tile] = lds[d];
 }
 
-// Stable scatter of one tile.  Wave w owns keys [w*1024, (w+1)*1024) of the
-// tile and walks them in 16 steps of 64 consecutive keys.  Lanes holding the
+// Stable scatter of one tile of kBlock * IPT keys.  Wave w owns keys
+// [w * 64 IPT, (w + 1) * 64 IPT) of the tile and walks them in IPT steps of 64
+// consecutive keys.  Lanes holding the
 // same digit find each other with one ballot per digit bit; a lane's rank is
 // the number of such lanes below it plus the wave's running count for the
 // digit (kept in LDS, updated by the lowest such lane).  After all waves are
@@ -341,7 +343,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(const uint32_t* __restric
 // rows ride along as a payload (FIRST: read from the caller's x in original
 // order; later passes: from the previous pass's payload), so that the bucket
 // pass reads them in order instead of gathering them by index.
-template <typename T, int D, bool FIRST, bool SHUFFLE, bool PAYLOAD>
+template <typename T, int D, bool FIRST, bool SHUFFLE, bool PAYLOAD, int IPT>
 __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __restrict__ keys_in,
                                                           const uint32_t* __restrict__ vals_in,
                                                           const T* __restrict__ x,
@@ -352,6 +354,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __rest
                                                           int shift, int bits, const uint32_t* __restrict__ hist_scan,
                                                           const uint32_t* __restrict__ block_sums, uint32_t ntiles) {
     constexpr int PITCH = Pitch<D>::value;
+    constexpr int kSortTile = kBlock * IPT;
     extern __shared__ uint32_t lds[];
     __shared__ uint32_t s_wsum[4];
     const uint32_t radix = 1u << bits, mask = radix - 1;
@@ -374,10 +377,10 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __rest
     uint32_t* wc = cnt + w * radix;
     const uint64_t lt = lanemask_lt();
     const uint32_t tbase = tile * kSortTile;
-    const uint32_t wbase = tbase + w * (kWave * kSortIpt);
-    uint32_t key[kSortIpt], val[kSortIpt], loc[kSortIpt];
+    const uint32_t wbase = tbase + w * (kWave * IPT);
+    uint32_t key[IPT], val[IPT], loc[IPT];
 #pragma unroll
-    for (int s = 0; s < kSortIpt; ++s) {
+    for (int s = 0; s < IPT; ++s) {
         const uint32_t idx = wbase + s * kWave + lane;
         const bool valid = idx < n;
         const uint32_t k = valid ? keys_in[idx] : 0u;
@@ -428,7 +431,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __rest
     }
     __syncthreads();
 #pragma unroll
-    for (int s = 0; s < kSortIpt; ++s) {
+    for (int s = 0; s < IPT; ++s) {
         const uint32_t idx = wbase + s * kWave + lane;
         if (idx < n) {
             const uint32_t dg = (key[s] >> shift) & mask;
@@ -486,7 +489,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __rest
 // histogram (hist_scan + block_sums, ntiles tiles) gives each bucket's start
 // directly; otherwise (hist_scan == nullptr) the bounds are found by binary
 // search of the high parts.
-template <typename T, int D>
+template <typename T, int D, int IPT>
 __global__ __launch_bounds__(kBlock) void k_bucket_finalize(const uint32_t* __restrict__ keys_in,
                                                             const uint32_t* __restrict__ vals_in, uint32_t n,
                                                             int lb, uint32_t ncells, const T* __restrict__ x,
@@ -498,6 +501,7 @@ __global__ __launch_bounds__(kBlock) void k_bucket_finalize(const uint32_t* __re
                                                             uint32_t ndigits,
                                                             const VecN<T, Pitch<D>::value>* __restrict__ pay) {
     constexpr int PITCH = Pitch<D>::value;
+    constexpr int kSortTile = kBlock * IPT;
     extern __shared__ uint32_t lds[];
     const uint32_t R = 1u << lb, mask = R - 1u;
     uint32_t* hist = lds;              // [R]
@@ -562,10 +566,10 @@ __global__ __launch_bounds__(kBlock) void k_bucket_finalize(const uint32_t* __re
             cnt[3 * R + d] = 0;
         }
         __syncthreads();
-        const uint32_t wbase = chunk + w * (kWave * kSortIpt);
-        uint32_t key[kSortIpt], val[kSortIpt], loc[kSortIpt];
+        const uint32_t wbase = chunk + w * (kWave * IPT);
+        uint32_t key[IPT], val[IPT], loc[IPT];
 #pragma unroll
-        for (int st = 0; st < kSortIpt; ++st) {
+        for (int st = 0; st < IPT; ++st) {
             const uint32_t idx = wbase + st * kWave + lane;
             const bool valid = idx < b1;
             const uint32_t k = valid ? keys_in[idx] : 0u;
@@ -595,7 +599,7 @@ __global__ __launch_bounds__(kBlock) void k_bucket_finalize(const uint32_t* __re
         }
         __syncthreads();
 #pragma unroll
-        for (int st = 0; st < kSortIpt; ++st) {
+        for (int st = 0; st < IPT; ++st) {
             const uint32_t idx = wbase + st * kWave + lane;
             if (idx < b1) {
                 const uint32_t dest = b0 + wc[key[st] & mask] + loc[st];
@@ -780,8 +784,21 @@ aboria_status launch_build_counting(aboria_ctx* ctx, aboria_cells* c, const void
     return ABORIA_OK;
 }
 
-template <typename T, int D>
-aboria_status launch_build_radix(aboria_ctx* ctx, aboria_cells* c, const void* x) {
+// Keys per thread of a sort tile for n keys: the largest of 16, 8, 4 that
+// still gives at least 512 tiles (2 per CU; the scatter and bucket passes are
+// latency-bound with fewer), else 4.  Measured on MI355X: a 2^20 cube builds
+// in the same time with 4096- or 2048-key tiles but 25 % faster with 2048 on
+// cells of half the width; 2^18 particles build 22 % faster with 1024-key
+// tiles; 5.8 M particles in 512 systems are fastest with 4096.
+int sort_ipt_for(int64_t n) {
+    if (n >= (int64_t)512 * kBlock * 16) return 16;
+    if (n >= (int64_t)512 * kBlock * 8) return 8;
+    return 4;
+}
+
+template <typename T, int D, int IPT>
+aboria_status launch_build_radix_ipt(aboria_ctx* ctx, aboria_cells* c, const void* x) {
+    constexpr int kSortTile = kBlock * IPT;
     const uint32_t n = (uint32_t)c->n;
     const SysParams<T>* sp = reinterpret_cast<const SysParams<T>*>(c->params_dev);
     hipStream_t st = ctx->stream;
@@ -821,15 +838,15 @@ aboria_status launch_build_radix(aboria_ctx* ctx, aboria_cells* c, const void* x
         const size_t lds_bytes = (6 * (size_t)radix + 2 * (size_t)kSortTile) * sizeof(uint32_t);
         for (int p = 0; p < c->passes; ++p) {
             const int shift = c->low_bits + p * c->digit_bits;
-            hipLaunchKernelGGL(k_radix_hist, dim3(ntiles), dim3(kBlock), radix * sizeof(uint32_t), st, kin, n, shift,
-                               c->digit_bits, c->hist, ntiles);
+            hipLaunchKernelGGL(k_radix_hist<IPT>, dim3(ntiles), dim3(kBlock), radix * sizeof(uint32_t), st, kin, n,
+                               shift, c->digit_bits, c->hist, ntiles);
             aboria_status s = scan_exclusive_u32(ctx, c->hist, c->hist, (int64_t)radix * ntiles, c->block_sums,
                                                  c->nblock_sums);
             if (s != ABORIA_OK) return s;
             const int pm = (shuffle ? 1 : 0) | (payload ? 2 : 0);
             const size_t lds_sel = shuffle ? lds_bytes : 6 * (size_t)radix * sizeof(uint32_t);
 #define LS(F, SH, PL)                                                                                          \
-    hipLaunchKernelGGL((k_radix_scatter<T, D, F, SH, PL>), dim3(ntiles), dim3(kBlock), lds_sel, st, kin, vin,  \
+    hipLaunchKernelGGL((k_radix_scatter<T, D, F, SH, PL, IPT>), dim3(ntiles), dim3(kBlock), lds_sel, st, kin, vin, \
                        (const T*)x, (const Row*)pay, kout, vout, pout, n, shift, c->digit_bits, c->hist,       \
                        c->block_sums, ntiles)
             if (p == 0) {
@@ -858,11 +875,20 @@ aboria_status launch_build_radix(aboria_ctx* ctx, aboria_cells* c, const void* x
     const uint32_t R = 1u << c->low_bits;
     const uint32_t nbuckets = (uint32_t)(((uint64_t)c->ncells + 1 + R - 1) / R);
     const bool direct = c->passes == 1 && n > 0;
-    hipLaunchKernelGGL((k_bucket_finalize<T, D>), dim3(nbuckets), dim3(kBlock), 6 * R * sizeof(uint32_t), st, kin,
+    hipLaunchKernelGGL((k_bucket_finalize<T, D, IPT>), dim3(nbuckets), dim3(kBlock), 6 * R * sizeof(uint32_t), st, kin,
                        vin, n, c->low_bits, (uint32_t)c->ncells, (const T*)x, (T*)c->xs, c->keys, c->perm, c->off,
                        direct ? c->hist : nullptr, c->block_sums, (uint32_t)c->ntiles, 1u << c->digit_bits, pay);
     ABORIA_HIP(ctx, hipGetLastError());
     return ABORIA_OK;
+}
+
+template <typename T, int D>
+aboria_status launch_build_radix(aboria_ctx* ctx, aboria_cells* c, const void* x) {
+    switch (c->sort_ipt) {
+        case 16: return launch_build_radix_ipt<T, D, 16>(ctx, c, x);
+        case 8: return launch_build_radix_ipt<T, D, 8>(ctx, c, x);
+        default: return launch_build_radix_ipt<T, D, 4>(ctx, c, x);
+    }
 }
 
 template <typename T, int D>
@@ -976,7 +1002,8 @@ extern "C" aboria_status aboria_build_cells(aboria_ctx* ctx, aboria_dtype dtype,
             const int high = bits - c->low_bits;
             c->passes = (high + kMaxDigitBits - 1) / kMaxDigitBits;
             c->digit_bits = c->passes > 0 ? (high + c->passes - 1) / c->passes : 1;
-            c->ntiles = (n + kSortTile - 1) / kSortTile;
+            c->sort_ipt = sort_ipt_for(n);
+            c->ntiles = (n + (int64_t)kBlock * c->sort_ipt - 1) / ((int64_t)kBlock * c->sort_ipt);
             c->hist_len = ((int64_t)1 << c->digit_bits) * std::max<int64_t>(c->ntiles, 1);
             c->nblock_sums = std::max<int64_t>(std::max(scan_block_count(c->hist_len),
                                                         scan_block_count(total_cells + 1)), 1);

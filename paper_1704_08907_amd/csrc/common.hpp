@@ -128,6 +128,7 @@ struct aboria_cells {
     int32_t passes = 0;
     int32_t digit_bits = 0;
     int32_t low_bits = 0;      // bits sorted by the per-bucket pass
+    int32_t sort_ipt = 16;     // keys per thread of a sort tile (tile = 256 * sort_ipt keys)
     int64_t ntiles = 0;
     int64_t hist_len = 0;
     int64_t nblock_sums = 0;
