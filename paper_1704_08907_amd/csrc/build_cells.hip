@@ -2,7 +2,9 @@
 // parallel-insertion form (the particles are reordered into cell order).
 //
 //   k_cell_ids       per particle: global cell id under the canonical rounding
-//   k_radix_hist     per tile of 4096 keys: digit histogram in LDS
+//                    (k_cell_ids_hist: per sort tile, with the first radix
+//                    pass's digit histogram)
+//   k_radix_hist     per sort tile: digit histogram in LDS (later passes)
 //   k_scan_local,    device-wide exclusive scan of the digit-major
 //   k_scan_top       (digit, tile) counts
 //   k_radix_scatter  stable in-tile ranks from wave ballots, then scatter
@@ -44,6 +46,29 @@ __device__ __forceinline__ int find_system(const uint32_t* __restrict__ first, i
     return lo;
 }
 
+// Global cell id of particle i under the canonical rounding (reading R2);
+// *bad is set for a coordinate outside [lo, hi) or NaN (clamped into the grid).
+template <typename T, int D>
+__device__ __forceinline__ uint32_t cell_key(const SysParams<T>& P, const T* __restrict__ x, uint32_t i,
+                                             bool* bad) {
+    uint32_t id = 0, mul = 1;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        T xk = x[(size_t)i * D + k];
+        *bad |= !(xk >= P.lo[k]) || !(xk < P.hi[k]);
+        T t = xk - P.lo[k];  // contraction is off: two separately rounded operations
+        T q = t * P.inv_w[k];
+        T f = floor(q);
+        int32_t c;
+        if (!(f >= T(0))) c = 0;  // negative or NaN
+        else if (f > T(P.n[k] - 1)) c = P.n[k] - 1;
+        else c = (int32_t)f;
+        id += mul * (uint32_t)c;
+        mul *= (uint32_t)P.n[k];
+    }
+    return P.cell_base + id;
+}
+
 // With counts != nullptr it also takes the particle's arrival rank in its cell
 // (an atomic increment of the cell's count; the order of arrival is not
 // deterministic, the counting build restores the index order afterwards).
@@ -68,27 +93,58 @@ __global__ __launch_bounds__(kBlock) void k_cell_ids(const T* __restrict__ x, ui
         while (b + 1 < nsys && sys_part[b + 1] <= i) ++b;
     }
     if (i >= n) return;
-    const SysParams<T>& P = sp[b];
-    uint32_t id = 0, mul = 1;
     bool bad = false;
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-        T xk = x[(size_t)i * D + k];
-        bad |= !(xk >= P.lo[k]) || !(xk < P.hi[k]);
-        T t = xk - P.lo[k];  // contraction is off: two separately rounded operations
-        T q = t * P.inv_w[k];
-        T f = floor(q);
-        int32_t c;
-        if (!(f >= T(0))) c = 0;  // negative or NaN
-        else if (f > T(P.n[k] - 1)) c = P.n[k] - 1;
-        else c = (int32_t)f;
-        id += mul * (uint32_t)c;
-        mul *= (uint32_t)P.n[k];
-    }
+    const uint32_t key = cell_key<T, D>(sp[b], x, i, &bad);
     if (bad) atomicOr(flag, 1u);
-    const uint32_t key = P.cell_base + id;
     keys[i] = key;
     if (counts) ranks[i] = atomicAdd(&counts[key], 1u);
+}
+
+// k_cell_ids fused with the digit histogram of the first radix pass: one
+// workgroup per sort tile of kBlock * IPT particles (the tiles of
+// k_radix_scatter) writes the tile's keys and hist[digit * ntiles + tile] for
+// the digit (key >> shift) & (2^bits - 1), as k_radix_hist would from them.
+template <typename T, int D, bool BATCH, int IPT>
+__global__ __launch_bounds__(kBlock) void k_cell_ids_hist(const T* __restrict__ x, uint32_t n,
+                                                          const SysParams<T>* __restrict__ sp,
+                                                          const uint32_t* __restrict__ sys_part, int nsys,
+                                                          uint32_t* __restrict__ keys, uint32_t* __restrict__ flag,
+                                                          uint32_t* __restrict__ gen, int shift, int bits,
+                                                          uint32_t* __restrict__ hist, uint32_t ntiles) {
+    extern __shared__ uint32_t lds[];
+    const uint32_t radix = 1u << bits, mask = radix - 1u;
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);  // neighbouring tiles share an XCD's L2
+    const uint32_t base = tile * (kBlock * IPT);
+    if (tile == 0 && threadIdx.x == 0) gen[0] = gen[0] + 1u;
+    for (uint32_t d = threadIdx.x; d < radix; d += kBlock) lds[d] = 0;
+    int b = 0;
+    if (BATCH) {
+        __shared__ int s_first;
+        if (threadIdx.x == 0) s_first = find_system(sys_part, nsys, base);
+        __syncthreads();
+        b = s_first;
+    }
+    __syncthreads();
+    bool bad = false;
+    uint32_t key[IPT];
+    // all keys first (their position loads in flight together), then the histogram
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+        const uint32_t i = base + k * kBlock + threadIdx.x;
+        key[k] = 0u;
+        if (i < n) {
+            if (BATCH)
+                while (b + 1 < nsys && sys_part[b + 1] <= i) ++b;
+            key[k] = cell_key<T, D>(sp[b], x, i, &bad);
+            keys[i] = key[k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < IPT; ++k)
+        if (base + k * kBlock + threadIdx.x < n) atomicAdd(&lds[(key[k] >> shift) & mask], 1u);
+    if (bad) atomicOr(flag, 1u);
+    __syncthreads();
+    for (uint32_t d = threadIdx.x; d < radix; d += kBlock) hist[(size_t)d * ntiles + tile] = lds[d];
 }
 
 // One cell per system (an explicit cell count of 1 in every dimension, the
@@ -320,7 +376,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(const uint32_t* __restric
     const uint32_t radix = 1u << bits, mask = radix - 1;
     for (uint32_t d = threadIdx.x; d < radix; d += kBlock) lds[d] = 0;
     __syncthreads();
-    const uint32_t tile = blockIdx.x;
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);  // neighbouring tiles share an XCD's L2
     const uint32_t base = tile * (kBlock * IPT);
 #pragma unroll 4
     for (int k = 0; k < IPT; ++k) {
@@ -363,7 +419,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __rest
     uint32_t* tstart = lds + 5 * radix;  // [radix] first tile slot of a digit
     uint32_t* sk = lds + 6 * radix;      // [kSortTile] keys in digit order
     uint32_t* sv = sk + kSortTile;       // [kSortTile] indices in digit order
-    const uint32_t tile = blockIdx.x;
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);  // neighbouring tiles share an XCD's L2
     for (uint32_t d = threadIdx.x; d < radix; d += kBlock) {
         cnt[d] = 0;
         cnt[radix + d] = 0;
@@ -810,15 +866,27 @@ aboria_status launch_build_radix_ipt(aboria_ctx* ctx, aboria_cells* c, const voi
     using Row = VecN<T, Pitch<D>::value>;
     const Row* pay = nullptr;  // position rows in the order of kin (after a radix pass)
     if (n > 0) {
-        const dim3 grid((n + kBlock - 1) / kBlock);
-        if (c->nsys == 1)
-            hipLaunchKernelGGL((k_cell_ids<T, D, false>), grid, dim3(kBlock), 0, st, (const T*)x, n, sp,
-                               c->sys_part_dev, c->nsys, k0, ctx->d_flag, nullptr, nullptr, c->gen);
-        else
-            hipLaunchKernelGGL((k_cell_ids<T, D, true>), grid, dim3(kBlock), 0, st, (const T*)x, n, sp,
-                               c->sys_part_dev, c->nsys, k0, ctx->d_flag, nullptr, nullptr, c->gen);
         const uint32_t ntiles = (uint32_t)c->ntiles;
         const uint32_t radix = 1u << c->digit_bits;
+        if (c->passes > 0) {  // cell ids with the first pass's digit histogram
+            const int shift0 = c->low_bits;
+            if (c->nsys == 1)
+                hipLaunchKernelGGL((k_cell_ids_hist<T, D, false, IPT>), dim3(ntiles), dim3(kBlock),
+                                   radix * sizeof(uint32_t), st, (const T*)x, n, sp, c->sys_part_dev, c->nsys, k0,
+                                   ctx->d_flag, c->gen, shift0, c->digit_bits, c->hist, ntiles);
+            else
+                hipLaunchKernelGGL((k_cell_ids_hist<T, D, true, IPT>), dim3(ntiles), dim3(kBlock),
+                                   radix * sizeof(uint32_t), st, (const T*)x, n, sp, c->sys_part_dev, c->nsys, k0,
+                                   ctx->d_flag, c->gen, shift0, c->digit_bits, c->hist, ntiles);
+        } else {
+            const dim3 grid((n + kBlock - 1) / kBlock);
+            if (c->nsys == 1)
+                hipLaunchKernelGGL((k_cell_ids<T, D, false>), grid, dim3(kBlock), 0, st, (const T*)x, n, sp,
+                                   c->sys_part_dev, c->nsys, k0, ctx->d_flag, nullptr, nullptr, c->gen);
+            else
+                hipLaunchKernelGGL((k_cell_ids<T, D, true>), grid, dim3(kBlock), 0, st, (const T*)x, n, sp,
+                                   c->sys_part_dev, c->nsys, k0, ctx->d_flag, nullptr, nullptr, c->gen);
+        }
         uint32_t* kout = (k0 == c->keys) ? c->keys_alt : c->keys;
         uint32_t* vout = (k0 == c->keys) ? c->perm_alt : c->perm;
         // Two choices, from measurements on MI355X (2^20 particles in one cube vs 512 systems
@@ -838,8 +906,9 @@ aboria_status launch_build_radix_ipt(aboria_ctx* ctx, aboria_cells* c, const voi
         const size_t lds_bytes = (6 * (size_t)radix + 2 * (size_t)kSortTile) * sizeof(uint32_t);
         for (int p = 0; p < c->passes; ++p) {
             const int shift = c->low_bits + p * c->digit_bits;
-            hipLaunchKernelGGL(k_radix_hist<IPT>, dim3(ntiles), dim3(kBlock), radix * sizeof(uint32_t), st, kin, n,
-                               shift, c->digit_bits, c->hist, ntiles);
+            if (p > 0)  // the first pass's histogram came with the cell ids
+                hipLaunchKernelGGL(k_radix_hist<IPT>, dim3(ntiles), dim3(kBlock), radix * sizeof(uint32_t), st, kin,
+                                   n, shift, c->digit_bits, c->hist, ntiles);
             aboria_status s = scan_exclusive_u32(ctx, c->hist, c->hist, (int64_t)radix * ntiles, c->block_sums,
                                                  c->nblock_sums);
             if (s != ABORIA_OK) return s;
