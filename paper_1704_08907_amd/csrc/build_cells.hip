@@ -435,12 +435,19 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __rest
     const uint32_t tbase = tile * kSortTile;
     const uint32_t wbase = tbase + w * (kWave * IPT);
     uint32_t key[IPT], val[IPT], loc[IPT];
+    // the tile's key and index loads first, so they are in flight together
 #pragma unroll
     for (int s = 0; s < IPT; ++s) {
         const uint32_t idx = wbase + s * kWave + lane;
         const bool valid = idx < n;
-        const uint32_t k = valid ? keys_in[idx] : 0u;
-        const uint32_t v = valid ? (FIRST ? idx : vals_in[idx]) : 0u;
+        key[s] = valid ? keys_in[idx] : 0u;
+        val[s] = valid ? (FIRST ? idx : vals_in[idx]) : 0u;
+    }
+#pragma unroll
+    for (int s = 0; s < IPT; ++s) {
+        const uint32_t idx = wbase + s * kWave + lane;
+        const bool valid = idx < n;
+        const uint32_t k = key[s];
         const uint32_t dg = (k >> shift) & mask;
         uint64_t peers = __ballot(valid);
         for (int b = 0; b < bits; ++b) {
@@ -451,8 +458,6 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __rest
         const uint32_t below = (uint32_t)__popcll(peers & lt);
         const uint32_t c = valid ? wc[dg] : 0u;
         if (valid && below == 0) wc[dg] = c + (uint32_t)__popcll(peers);
-        key[s] = k;
-        val[s] = v;
         loc[s] = c + below;
     }
     __syncthreads();
@@ -588,12 +593,11 @@ __global__ __launch_bounds__(kBlock) void k_bucket_finalize(const uint32_t* __re
         }
         s_range[threadIdx.x] = lo;
     }
-    for (uint32_t d = threadIdx.x; d < R; d += kBlock) hist[d] = 0;
     __syncthreads();
     const uint32_t b0 = s_range[0], b1 = s_range[1];
-    for (uint32_t i = b0 + threadIdx.x; i < b1; i += kBlock) atomicAdd(&hist[keys_in[i] & mask], 1u);
-    __syncthreads();
-    {   // exclusive scan of hist into base: each thread owns a run of R/256 digits (R >= 256) or one
+    // exclusive scan of hist into base and the offsets of the bucket's cells: each
+    // thread owns a run of R/256 digits (R >= 256) or one
+    auto scan_hist = [&]() {
         const uint32_t per = R >= (uint32_t)kBlock ? R / kBlock : 1u;
         const uint32_t d0 = threadIdx.x * per;
         uint32_t tot = 0;
@@ -609,8 +613,18 @@ __global__ __launch_bounds__(kBlock) void k_bucket_finalize(const uint32_t* __re
                 ex += hist[d0 + k];
             }
         }
+    };
+    // A nonempty bucket that fits one chunk takes its histogram from the chunk's
+    // per-wave rank counts below; a larger (or empty) one counts its keys first.
+    const bool single = b1 > b0 && b1 - b0 <= (uint32_t)kSortTile;
+    if (!single) {
+        for (uint32_t d = threadIdx.x; d < R; d += kBlock) hist[d] = 0;
+        __syncthreads();
+        for (uint32_t i = b0 + threadIdx.x; i < b1; i += kBlock) atomicAdd(&hist[keys_in[i] & mask], 1u);
+        __syncthreads();
+        scan_hist();
+        __syncthreads();
     }
-    __syncthreads();
     const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     uint32_t* wc = cnt + w * R;
     const uint64_t lt = lanemask_lt();
@@ -624,12 +638,21 @@ __global__ __launch_bounds__(kBlock) void k_bucket_finalize(const uint32_t* __re
         __syncthreads();
         const uint32_t wbase = chunk + w * (kWave * IPT);
         uint32_t key[IPT], val[IPT], loc[IPT];
+        VecN<T, PITCH> row[IPT];
+        // every load of the chunk first, so they are in flight together
 #pragma unroll
         for (int st = 0; st < IPT; ++st) {
             const uint32_t idx = wbase + st * kWave + lane;
             const bool valid = idx < b1;
-            const uint32_t k = valid ? keys_in[idx] : 0u;
-            const uint32_t v = valid ? (vals_in ? vals_in[idx] : idx) : 0u;
+            key[st] = valid ? keys_in[idx] : 0u;
+            val[st] = valid ? (vals_in ? vals_in[idx] : idx) : 0u;
+            if (pay && valid) row[st] = pay[idx];  // the row travelled with its key through the radix passes
+        }
+#pragma unroll
+        for (int st = 0; st < IPT; ++st) {
+            const uint32_t idx = wbase + st * kWave + lane;
+            const bool valid = idx < b1;
+            const uint32_t k = key[st];
             const uint32_t dg = k & mask;
             uint64_t peers = __ballot(valid);
             for (int bb = 0; bb < lb; ++bb) {
@@ -640,11 +663,16 @@ __global__ __launch_bounds__(kBlock) void k_bucket_finalize(const uint32_t* __re
             const uint32_t below = (uint32_t)__popcll(peers & lt);
             const uint32_t c = valid ? wc[dg] : 0u;
             if (valid && below == 0) wc[dg] = c + (uint32_t)__popcll(peers);
-            key[st] = k;
-            val[st] = v;
             loc[st] = c + below;
         }
         __syncthreads();
+        if (single) {
+            for (uint32_t d = threadIdx.x; d < R; d += kBlock)
+                hist[d] = cnt[d] + cnt[R + d] + cnt[2 * R + d] + cnt[3 * R + d];
+            __syncthreads();
+            scan_hist();
+            __syncthreads();
+        }
         for (uint32_t d = threadIdx.x; d < R; d += kBlock) {
             const uint32_t a0 = cnt[d], a1 = cnt[R + d], a2 = cnt[2 * R + d], a3 = cnt[3 * R + d];
             cnt[d] = base[d];
@@ -665,7 +693,7 @@ __global__ __launch_bounds__(kBlock) void k_bucket_finalize(const uint32_t* __re
                     perm_out[dest] = p;
                     VecN<T, PITCH> v;
                     if (pay) {
-                        v = pay[idx];  // the row travelled with its key through the radix passes
+                        v = row[st];
                     } else {
 #pragma unroll
                         for (int k = 0; k < PITCH; ++k) v.v[k] = k < D ? x[(size_t)p * D + k] : T(0);
