@@ -550,7 +550,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __rest
 // histogram (hist_scan + block_sums, ntiles tiles) gives each bucket's start
 // directly; otherwise (hist_scan == nullptr) the bounds are found by binary
 // search of the high parts.
-template <typename T, int D, int IPT>
+template <typename T, int D, int IPT, bool STAGE>
 __global__ __launch_bounds__(kBlock) void k_bucket_finalize(const uint32_t* __restrict__ keys_in,
                                                             const uint32_t* __restrict__ vals_in, uint32_t n,
                                                             int lb, uint32_t ncells, const T* __restrict__ x,
@@ -682,6 +682,36 @@ __global__ __launch_bounds__(kBlock) void k_bucket_finalize(const uint32_t* __re
             base[d] += a0 + a1 + a2 + a3;
         }
         __syncthreads();
+        if (STAGE && single) {
+            // sorted order assembled in LDS, then written as contiguous runs (scattered
+            // stores into the bucket's range left partly written lines behind)
+            uint32_t* sk = lds + 6 * R;
+            uint32_t* sv = sk + kSortTile;
+            VecN<T, PITCH>* srow = reinterpret_cast<VecN<T, PITCH>*>(sv + kSortTile);
+#pragma unroll
+            for (int st = 0; st < IPT; ++st) {
+                const uint32_t idx = wbase + st * kWave + lane;
+                if (idx < b1) {
+                    const uint32_t rel = wc[key[st] & mask] + loc[st];
+                    if (rel < (uint32_t)kSortTile) {  // always true for a consistent histogram
+                        sk[rel] = key[st];
+                        sv[rel] = min(val[st], n - 1u);
+                        srow[rel] = row[st];
+                    }
+                }
+            }
+            __syncthreads();
+            const uint32_t count = b1 - b0;
+            for (uint32_t i = threadIdx.x; i < count; i += kBlock) {
+                if (b0 + i < n) {
+                    keys_out[b0 + i] = sk[i];
+                    perm_out[b0 + i] = sv[i];
+                    reinterpret_cast<VecN<T, PITCH>*>(xs)[b0 + i] = srow[i];
+                }
+            }
+            __syncthreads();
+            continue;
+        }
 #pragma unroll
         for (int st = 0; st < IPT; ++st) {
             const uint32_t idx = wbase + st * kWave + lane;
@@ -972,9 +1002,21 @@ aboria_status launch_build_radix_ipt(aboria_ctx* ctx, aboria_cells* c, const voi
     const uint32_t R = 1u << c->low_bits;
     const uint32_t nbuckets = (uint32_t)(((uint64_t)c->ncells + 1 + R - 1) / R);
     const bool direct = c->passes == 1 && n > 0;
-    hipLaunchKernelGGL((k_bucket_finalize<T, D, IPT>), dim3(nbuckets), dim3(kBlock), 6 * R * sizeof(uint32_t), st, kin,
-                       vin, n, c->low_bits, (uint32_t)c->ncells, (const T*)x, (T*)c->xs, c->keys, c->perm, c->off,
-                       direct ? c->hist : nullptr, c->block_sums, (uint32_t)c->ntiles, 1u << c->digit_bits, pay);
+    // Single-chunk buckets assemble their output in LDS when the rows travelled with the
+    // keys and the staging area stays small (float rows, tiles of at most 2048 keys).
+    constexpr bool kStageable = IPT <= 8 && sizeof(VecN<T, Pitch<D>::value>) <= 16;
+    const bool stage = kStageable && pay != nullptr;
+    const size_t stage_bytes = (size_t)kSortTile * (2 * sizeof(uint32_t) + sizeof(VecN<T, Pitch<D>::value>));
+    if (stage)
+        hipLaunchKernelGGL((k_bucket_finalize<T, D, IPT, kStageable>), dim3(nbuckets), dim3(kBlock),
+                           6 * R * sizeof(uint32_t) + stage_bytes, st, kin, vin, n, c->low_bits, (uint32_t)c->ncells,
+                           (const T*)x, (T*)c->xs, c->keys, c->perm, c->off, direct ? c->hist : nullptr,
+                           c->block_sums, (uint32_t)c->ntiles, 1u << c->digit_bits, pay);
+    else
+        hipLaunchKernelGGL((k_bucket_finalize<T, D, IPT, false>), dim3(nbuckets), dim3(kBlock), 6 * R * sizeof(uint32_t),
+                           st, kin, vin, n, c->low_bits, (uint32_t)c->ncells, (const T*)x, (T*)c->xs, c->keys,
+                           c->perm, c->off, direct ? c->hist : nullptr, c->block_sums, (uint32_t)c->ntiles,
+                           1u << c->digit_bits, pay);
     ABORIA_HIP(ctx, hipGetLastError());
     return ABORIA_OK;
 }
