@@ -419,6 +419,8 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __rest
     uint32_t* tstart = lds + 5 * radix;  // [radix] first tile slot of a digit
     uint32_t* sk = lds + 6 * radix;      // [kSortTile] keys in digit order
     uint32_t* sv = sk + kSortTile;       // [kSortTile] indices in digit order
+    // [kSortTile] position rows in digit order (SHUFFLE and PAYLOAD)
+    VecN<T, PITCH>* srow = reinterpret_cast<VecN<T, PITCH>*>(sv + kSortTile);
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);  // neighbouring tiles share an XCD's L2
     for (uint32_t d = threadIdx.x; d < radix; d += kBlock) {
         cnt[d] = 0;
@@ -515,7 +517,8 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __rest
                     } else {
                         row = pay_in[idx];
                     }
-                    pay_out[pos] = row;
+                    if (SHUFFLE) srow[tl] = row;  // leaves with its key, in digit order
+                    else pay_out[pos] = row;
                 }
             }
         }
@@ -530,6 +533,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __rest
         if (pos < n) {  // always true for a consistent histogram; keeps a bad one in bounds
             keys_out[pos] = k;
             vals_out[pos] = sv[i];
+            if (PAYLOAD) pay_out[pos] = srow[i];
         }
     }
 }
@@ -948,20 +952,28 @@ aboria_status launch_build_radix_ipt(aboria_ctx* ctx, aboria_cells* c, const voi
         uint32_t* kout = (k0 == c->keys) ? c->keys_alt : c->keys;
         uint32_t* vout = (k0 == c->keys) ? c->perm_alt : c->perm;
         // Two choices, from measurements on MI355X (2^20 particles in one cube vs 512 systems
-        // of up to 65536): shuffling a tile into digit order in LDS makes the key writes
-        // contiguous but needs 57 KB of LDS, which pays while the tiles do not outnumber the CUs
-        // much (it slowed 1411 tiles); carrying the position rows through the pass turns the
+        // of up to 65536): shuffling a tile into digit order in LDS (keys, indices and carried
+        // rows) makes its writes contiguous but needs tens of KB of LDS (72 KB for 2048 float
+        // rows), which pays while the tiles do not outnumber the CUs much (it slowed 1411
+        // tiles), and must fit the device's LDS per workgroup; carrying the position rows through the pass turns the
         // bucket pass's random gather into a sequential read, which pays when a system's
         // positions do not fit in L2 (a 12 MB cube: 58 -> 38 us), while the gather of a
         // 0.8 MB system already hits L2 and the payload only adds traffic.
-        const bool shuffle = ntiles <= 512;
+        if (ctx->lds_per_block == 0) {
+            int v = 0;
+            if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device) != hipSuccess)
+                v = 65536;
+            ctx->lds_per_block = v;
+        }
         int64_t largest = 0;
         for (int32_t b = 0; b < c->nsys; ++b)
             largest = std::max<int64_t>(largest, c->sys_off[(size_t)b + 1] - c->sys_off[(size_t)b]);
         const bool payload = (uint64_t)largest * D * sizeof(T) > (2u << 20);
         // position rows follow the keys through the passes, ping-ponging between the work buffers
         Row* pout = reinterpret_cast<Row*>(c->work);
-        const size_t lds_bytes = (6 * (size_t)radix + 2 * (size_t)kSortTile) * sizeof(uint32_t);
+        const size_t lds_bytes = (6 * (size_t)radix + 2 * (size_t)kSortTile) * sizeof(uint32_t) +
+                                 (payload ? (size_t)kSortTile * sizeof(Row) : 0);
+        const bool shuffle = ntiles <= 512 && lds_bytes <= (size_t)ctx->lds_per_block;
         for (int p = 0; p < c->passes; ++p) {
             const int shift = c->low_bits + p * c->digit_bits;
             if (p > 0)  // the first pass's histogram came with the cell ids

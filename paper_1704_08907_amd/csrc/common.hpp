@@ -95,6 +95,7 @@ struct aboria_ctx {
     size_t scratch_bytes = 0;
     int32_t variant_forced = -1;
     int32_t build_strategy = ABORIA_BUILD_RADIX;
+    int32_t lds_per_block = 0;       // device limit on LDS per workgroup (queried on first use)
     std::vector<std::pair<uint64_t, int32_t>> tune_cache;  // (key, variant)
 };
 
