@@ -391,12 +391,14 @@ def main():
         # its adjoint with targets = sources: K^T gy plus the target and source position gradients
         gyd = torch.from_numpy(syn.SplitMix64(12).normal(xd.shape[0]).astype(np.float32)).to(dev)
         t_dense_b = timed(lambda: A.dense_sum_backward(ctx, xd_t, xd_t, wd_t, sigma, gyd), reps=5)
-        extra["dense_gaussian_n65536_adjoint"] = {"ms": t_dense_b, "pair_passes": 3,
-                                                  "pairs_per_s": 3 * npair / (t_dense_b * 1e-3)}
-        # the multiquadric basis of the RBF example, c = 0.1 (per pair: 2 sub, fma with c^2, fma, sqrt, fma)
+        # passes over the N^2 pairs: K^T gy with the source gradient, then the target gradient
+        extra["dense_gaussian_n65536_adjoint"] = {"ms": t_dense_b, "pair_passes": 2,
+                                                  "pairs_per_s": 2 * npair / (t_dense_b * 1e-3)}
+        # the multiquadric basis of the RBF example, c = 0.1 (per pair: 2 sub, mul, fma, add of c^2,
+        # rsqrt, mul, fma)
         t_mq = timed(lambda: A.dense_sum(ctx, xd_t, xd_t, wd_t, 0.1, y=yd, kernel="multiquadric"), reps=10)
         extra["dense_multiquadric_n65536"] = {"ms": t_mq, "pairs_per_s": npair / (t_mq * 1e-3),
-                                              "valu_frac": npair * 6 / (t_mq * 1e-3) / 1e12 / VALU_PEAK_TOPS}
+                                              "valu_frac": npair * 8 / (t_mq * 1e-3) / 1e12 / VALU_PEAK_TOPS}
         del xd_t, wd_t, yd, gyd
         # soft sphere N = 2^18 forward + adjoint (energy gradient)
         w4 = syn.soft_sphere_cube()

@@ -31,20 +31,20 @@ __device__ __forceinline__ float kexp(float a) { return __builtin_amdgcn_exp2f(-
 __device__ __forceinline__ double kexp(double a) { return ::exp(-a); }
 __device__ __forceinline__ float kfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double kfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
-__device__ __forceinline__ float ksqrt(float a) { return __builtin_amdgcn_sqrtf(a); }
-__device__ __forceinline__ double ksqrt(double a) { return ::sqrt(a); }
 __device__ __forceinline__ float krsqrt(float a) { return __builtin_amdgcn_rsqf(a); }
 __device__ __forceinline__ double krsqrt(double a) { return ::rsqrt(a); }
 
 // phi of the kernel on its working coordinates (value) and the factor of the
 // gradient summand w_j * slope * (a - b) (the constant 2 phi' / slope is
 // applied by the reduction): Gaussian value = slope = exp(-q') on coordinates
-// scaled by sqrt(c); multiquadric value = sqrt(q + c^2), slope = 1/value.
+// scaled by sqrt(c); multiquadric slope = 1/sqrt(q + c^2) and value = (q + c^2)
+// * slope, so that a pass needing both takes one reciprocal square root and its
+// value is bit for bit the forward's.
 template <typename T, int KERN>
 struct Radial {
     __device__ __forceinline__ static T value(T q, T c2) {
         if constexpr (KERN == ABORIA_K_GAUSSIAN) return kexp(q);
-        else return ksqrt(q + c2);
+        else return (q + c2) * krsqrt(q + c2);
     }
     __device__ __forceinline__ static T slope(T q, T c2) {
         if constexpr (KERN == ABORIA_K_GAUSSIAN) return kexp(q);
@@ -52,14 +52,23 @@ struct Radial {
     }
 };
 
-// GRAD = false: part[split][t] = sum over the split's sources of K w.
-// GRAD = true:  part[split][t][k] = sum of w * slope * (xt_t - xs_j)_k.
-template <typename T, int D, int TI, int KERN, bool GRAD>
+// What a pass sums per target t over the split's sources j:
+//   kSum:     part[split][t]      = sum of K w
+//   kGrad:    part[split][t][k]   = sum of w * slope * (xt_t - xs_j)_k
+//   kSumGrad: part[split][t][0]   = sum of K w and part[split][t][1 + k] the kGrad sum
+//             (one pass for two sums with the same targets, sources and weights:
+//             the adjoint's K^T gy and source-position gradient)
+enum DenseMode { kSum = 0, kGrad = 1, kSumGrad = 2 };
+
+template <int MODE, int D>
+constexpr int dense_out() { return MODE == kSum ? 1 : (MODE == kGrad ? D : D + 1); }
+
+template <typename T, int D, int TI, int KERN, int MODE>
 __global__ __launch_bounds__(kDenseBlock) void k_dense(const T* __restrict__ xt, uint32_t nt,
                                                        const T* __restrict__ xs, const T* __restrict__ w,
                                                        uint32_t ns, T sc, T c2, uint32_t jchunk,
                                                        T* __restrict__ ypart) {
-    constexpr int OUT = GRAD ? D : 1;
+    constexpr int OUT = dense_out<MODE, D>();
     __shared__ VecN<T, 4> tile[kDenseTile];
     const uint32_t tb = xcd_tile(blockIdx.x, gridDim.x);
     const uint32_t split = blockIdx.y;
@@ -106,12 +115,24 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(const T* __restrict__ xt,
                 T d2 = dk[0] * dk[0];
                 if constexpr (D >= 2) d2 = kfma(dk[1], dk[1], d2);
                 if constexpr (D >= 3) d2 = kfma(dk[2], dk[2], d2);
-                if constexpr (!GRAD) {
+                if constexpr (MODE == kSum) {
                     part[q][0] = kfma(Radial<T, KERN>::value(d2, c2), p.v[3], part[q][0]);
                 } else {
-                    const T h = Radial<T, KERN>::slope(d2, c2) * p.v[3];
+                    constexpr int G = MODE == kSumGrad ? 1 : 0;  // first gradient component
+                    T slope;
+                    if constexpr (MODE == kSumGrad && KERN == ABORIA_K_MULTIQUADRIC) {
+                        // value and slope from one reciprocal square root: sqrt(a) = a / sqrt(a)
+                        const T a = d2 + c2;
+                        slope = krsqrt(a);
+                        part[q][0] = kfma(a * slope, p.v[3], part[q][0]);
+                    } else {
+                        slope = Radial<T, KERN>::slope(d2, c2);
+                        if constexpr (MODE == kSumGrad)  // the Gaussian's value is its slope
+                            part[q][0] = kfma(Radial<T, KERN>::value(d2, c2), p.v[3], part[q][0]);
+                    }
+                    const T h = slope * p.v[3];
 #pragma unroll
-                    for (int k = 0; k < D; ++k) part[q][k] = kfma(h, dk[k], part[q][k]);
+                    for (int k = 0; k < D; ++k) part[q][G + k] = kfma(h, dk[k], part[q][G + k]);
                 }
             }
         }
@@ -140,6 +161,23 @@ __global__ __launch_bounds__(256) void k_dense_reduce(const T* __restrict__ ypar
         T s = T(0);
         for (uint32_t q = 0; q < nsplit; ++q) s += ypart[((size_t)q * nt + t) * OUT + k];
         y[(size_t)t * OUT + k] = mult ? (mult[t] * C) * s : s;
+    }
+}
+
+// The kSumGrad partials: y[t] = sum of component 0, g[t][k] = (mult[t] * C) * sum of
+// component 1 + k, each over the splits in split order.
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_dense_reduce2(const T* __restrict__ ypart, uint32_t nt, uint32_t nsplit,
+                                                       const T* __restrict__ mult, T C, T* __restrict__ y,
+                                                       T* __restrict__ g) {
+    const uint32_t t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= nt) return;
+#pragma unroll
+    for (int k = 0; k <= D; ++k) {
+        T s = T(0);
+        for (uint32_t q = 0; q < nsplit; ++q) s += ypart[((size_t)q * nt + t) * (D + 1) + k];
+        if (k == 0) y[t] = s;
+        else g[(size_t)t * D + k - 1] = (mult[t] * C) * s;
     }
 }
 
@@ -186,11 +224,12 @@ aboria_status ensure_scratch(aboria_ctx* ctx, size_t need) {
     return ABORIA_OK;
 }
 
-// out = sum_j K(xt_i, xs_j) w_j (GRAD = false) or mult_i * C * sum_j w_j slope (xt_i - xs_j) (GRAD = true).
-template <typename T, int D, int KERN, bool GRAD>
+// kSum: out = sum_j K(xt_i, xs_j) w_j; kGrad: out = mult_i * C * sum_j w_j slope (xt_i - xs_j);
+// kSumGrad: out = the kSum sum and out2 = the kGrad sum, from one pass.
+template <typename T, int D, int KERN, int MODE>
 aboria_status launch_dense(aboria_ctx* ctx, uint32_t nt, const void* xt, uint32_t ns, const void* xs, const void* w,
-                           const KernelPlan& kp, const void* mult, void* out) {
-    constexpr int OUT = GRAD ? D : 1;
+                           const KernelPlan& kp, const void* mult, void* out, void* out2 = nullptr) {
+    constexpr int OUT = dense_out<MODE, D>();
     const uint32_t per_block = kDenseBlock * kTargetsPerThread;
     const uint32_t tblocks = (nt + per_block - 1) / per_block;
     const uint32_t ntiles = std::max<uint32_t>((ns + kDenseTile - 1) / kDenseTile, 1);
@@ -202,38 +241,43 @@ aboria_status launch_dense(aboria_ctx* ctx, uint32_t nt, const void* xt, uint32_
     const uint32_t jchunk = tiles_per_split * kDenseTile;
     aboria_status st = ensure_scratch(ctx, sizeof(T) * (size_t)nsplit * nt * OUT);
     if (st != ABORIA_OK) return st;
-    hipLaunchKernelGGL((k_dense<T, D, kTargetsPerThread, KERN, GRAD>), dim3(tblocks, nsplit), dim3(kDenseBlock), 0,
+    hipLaunchKernelGGL((k_dense<T, D, kTargetsPerThread, KERN, MODE>), dim3(tblocks, nsplit), dim3(kDenseBlock), 0,
                        ctx->stream, (const T*)xt, nt, (const T*)xs, (const T*)w, ns, (T)kp.sc, (T)kp.c2, jchunk,
                        (T*)ctx->scratch);
-    hipLaunchKernelGGL((k_dense_reduce<T, OUT>), dim3((nt + 255) / 256), dim3(256), 0, ctx->stream,
-                       (const T*)ctx->scratch, nt, nsplit, (const T*)mult, (T)kp.C, (T*)out);
+    if constexpr (MODE == kSumGrad)
+        hipLaunchKernelGGL((k_dense_reduce2<T, D>), dim3((nt + 255) / 256), dim3(256), 0, ctx->stream,
+                           (const T*)ctx->scratch, nt, nsplit, (const T*)mult, (T)kp.C, (T*)out, (T*)out2);
+    else
+        hipLaunchKernelGGL((k_dense_reduce<T, OUT>), dim3((nt + 255) / 256), dim3(256), 0, ctx->stream,
+                           (const T*)ctx->scratch, nt, nsplit, (const T*)mult, (T)kp.C, (T*)out);
     ABORIA_HIP(ctx, hipGetLastError());
     return ABORIA_OK;
 }
 
-template <typename T, int D, bool GRAD>
+template <typename T, int D, int MODE>
 aboria_status launch_kernel(aboria_ctx* ctx, int kernel, uint32_t nt, const void* xt, uint32_t ns, const void* xs,
-                            const void* w, double prm, const void* mult, void* out) {
+                            const void* w, double prm, const void* mult, void* out, void* out2) {
     const KernelPlan kp = plan_kernel<T>(kernel, prm);
     if (kernel == ABORIA_K_GAUSSIAN)
-        return launch_dense<T, D, ABORIA_K_GAUSSIAN, GRAD>(ctx, nt, xt, ns, xs, w, kp, mult, out);
-    return launch_dense<T, D, ABORIA_K_MULTIQUADRIC, GRAD>(ctx, nt, xt, ns, xs, w, kp, mult, out);
+        return launch_dense<T, D, ABORIA_K_GAUSSIAN, MODE>(ctx, nt, xt, ns, xs, w, kp, mult, out, out2);
+    return launch_dense<T, D, ABORIA_K_MULTIQUADRIC, MODE>(ctx, nt, xt, ns, xs, w, kp, mult, out, out2);
 }
 
-template <bool GRAD>
+template <int MODE>
 aboria_status dispatch(aboria_ctx* ctx, int dtype, int d, int kernel, uint32_t nt, const void* xt, uint32_t ns,
-                       const void* xs, const void* w, double prm, const void* mult, void* out) {
+                       const void* xs, const void* w, double prm, const void* mult, void* out,
+                       void* out2 = nullptr) {
     if (dtype == ABORIA_F32) {
         switch (d) {
-            case 1: return launch_kernel<float, 1, GRAD>(ctx, kernel, nt, xt, ns, xs, w, prm, mult, out);
-            case 2: return launch_kernel<float, 2, GRAD>(ctx, kernel, nt, xt, ns, xs, w, prm, mult, out);
-            default: return launch_kernel<float, 3, GRAD>(ctx, kernel, nt, xt, ns, xs, w, prm, mult, out);
+            case 1: return launch_kernel<float, 1, MODE>(ctx, kernel, nt, xt, ns, xs, w, prm, mult, out, out2);
+            case 2: return launch_kernel<float, 2, MODE>(ctx, kernel, nt, xt, ns, xs, w, prm, mult, out, out2);
+            default: return launch_kernel<float, 3, MODE>(ctx, kernel, nt, xt, ns, xs, w, prm, mult, out, out2);
         }
     }
     switch (d) {
-        case 1: return launch_kernel<double, 1, GRAD>(ctx, kernel, nt, xt, ns, xs, w, prm, mult, out);
-        case 2: return launch_kernel<double, 2, GRAD>(ctx, kernel, nt, xt, ns, xs, w, prm, mult, out);
-        default: return launch_kernel<double, 3, GRAD>(ctx, kernel, nt, xt, ns, xs, w, prm, mult, out);
+        case 1: return launch_kernel<double, 1, MODE>(ctx, kernel, nt, xt, ns, xs, w, prm, mult, out, out2);
+        case 2: return launch_kernel<double, 2, MODE>(ctx, kernel, nt, xt, ns, xs, w, prm, mult, out, out2);
+        default: return launch_kernel<double, 3, MODE>(ctx, kernel, nt, xt, ns, xs, w, prm, mult, out, out2);
     }
 }
 
@@ -272,8 +316,8 @@ extern "C" aboria_status aboria_dense_sum(aboria_ctx* ctx, aboria_dtype dtype, a
         if (overlaps(y, ny, xt, tsz * d * (size_t)n_target) || overlaps(y, ny, xs, tsz * d * (size_t)n_source) ||
             overlaps(y, ny, w, tsz * (size_t)n_source))
             return fail(ctx, ABORIA_ERR_INVALID_ARG, "y overlaps an input");
-        return dispatch<false>(ctx, dtype, d, kernel, (uint32_t)n_target, xt, (uint32_t)n_source, xs, w,
-                               params_host[0], nullptr, y);
+        return dispatch<kSum>(ctx, dtype, d, kernel, (uint32_t)n_target, xt, (uint32_t)n_source, xs, w,
+                              params_host[0], nullptr, y);
     } catch (...) {
         return fail(ctx, ABORIA_ERR_OUT_OF_MEMORY, "host exception in dense_sum");
     }
@@ -316,12 +360,20 @@ extern "C" aboria_status aboria_dense_sum_backward(aboria_ctx* ctx, aboria_dtype
         }
         const double prm = params_host[0];
         const uint32_t t32 = (uint32_t)n_target, s32 = (uint32_t)n_source;
-        // dL/dw = K^T gy: the forward sum over the targets, seen from the sources
-        if (gw && (st = dispatch<false>(ctx, dtype, d, kernel, s32, xs, t32, xt, gy, prm, nullptr, gw)) != ABORIA_OK)
-            return st;
-        if (gxt && (st = dispatch<true>(ctx, dtype, d, kernel, t32, xt, s32, xs, w, prm, gy, gxt)) != ABORIA_OK)
-            return st;
-        if (gxs && (st = dispatch<true>(ctx, dtype, d, kernel, s32, xs, t32, xt, gy, prm, w, gxs)) != ABORIA_OK)
+        // dL/dw = K^T gy (the forward sum over the targets, seen from the sources) and the
+        // source-position gradient sum over the same pairs with the same weights gy: one
+        // pass when both are requested
+        if (gw && gxs) {
+            if ((st = dispatch<kSumGrad>(ctx, dtype, d, kernel, s32, xs, t32, xt, gy, prm, w, gw, gxs)) != ABORIA_OK)
+                return st;
+        } else if (gw) {
+            if ((st = dispatch<kSum>(ctx, dtype, d, kernel, s32, xs, t32, xt, gy, prm, nullptr, gw)) != ABORIA_OK)
+                return st;
+        } else if (gxs) {
+            if ((st = dispatch<kGrad>(ctx, dtype, d, kernel, s32, xs, t32, xt, gy, prm, w, gxs)) != ABORIA_OK)
+                return st;
+        }
+        if (gxt && (st = dispatch<kGrad>(ctx, dtype, d, kernel, t32, xt, s32, xs, w, prm, gy, gxt)) != ABORIA_OK)
             return st;
         return ABORIA_OK;
     } catch (...) {
