@@ -292,7 +292,8 @@ aboria_status aboria_dense_sum(aboria_ctx* ctx, aboria_dtype dtype, aboria_kerne
  *   gxs[j][:] = w_j sum_i gy_i 2 phi'(q_ij) (xs_j - xt_i)
  * for K = phi(q), q = |xt_i - xs_j|^2.  When targets and sources are the same
  * points, dL/dx = gxt + gxs.  Each output may be NULL (not computed); all are
- * overwritten, in dtype, and must not overlap the inputs or each other.  Uses
+ * overwritten, in dtype, and must not overlap the inputs or each other.  gw and
+ * gxs come from one pass over the pairs, gxt from a second.  Uses
  * the same grow-only scratch as the forward (a first call of a size must not
  * be captured).  Errors as for aboria_dense_sum. */
 aboria_status aboria_dense_sum_backward(aboria_ctx* ctx, aboria_dtype dtype, aboria_kernel kernel,
