@@ -91,6 +91,8 @@ def profile_names(variant_name, direction):
         k = ["k_nbr_fwd<float, 3, 1, false>"] if direction == "fwd" else ["k_nbr_bwd<float, 3, 1, false>"]
     elif "cell group" in variant_name or "LDS list" in variant_name or "staged" in variant_name:
         return None
+    elif "accepted-pair bit masks" in variant_name:
+        k = ["k_lane_mask<float, 3, 1, false, true, %d>" % (0 if direction == "fwd" else 1)]
     elif "flattened" in variant_name:
         k = ["k_flat<float, 3, 1, false, true, %d>" % (0 if direction == "fwd" else 1)]
     elif direction == "fwd":
@@ -214,17 +216,30 @@ def main():
         A.build_cells(ctx, x, [box], cells=cells)
         A.pair_sum_and_backward(ctx, cells, "spring", (1.0,), gy, y=y, gx=gx)
 
+    # box search whose forward records each stencil row's accepted candidates, which the
+    # adjoint replays instead of testing every candidate again
+    mask_variant = next(v for v in range(A.variant_count()) if "accepted-pair bit masks" in A.variant_name(v))
+
+    def step_masks():
+        A.build_cells(ctx, x, [box], cells=cells)
+        ctx.set_variant(mask_variant)
+        A.pair_sum(ctx, cells, "spring", (1.0,), y=y)
+        A.pair_sum_backward(ctx, cells, "spring", (1.0,), gy, gx=gx)
+        ctx.set_variant(-1)
+
     # both forms of the step are timed briefly; the faster one is the headline.  The fused
     # form (forward and adjoint from one box search) needs gy before the forward, which a
     # training step does not have, so it is reported beside the headline, not as it.
     trial = {}
-    for name, fn in (("neighbour_list", step), ("box_search", step_search), ("fused_gy_known", step_fused)):
+    forms = {"neighbour_list": step, "box_search": step_search, "recorded_masks": step_masks,
+             "fused_gy_known": step_fused}
+    for name, fn in forms.items():
         g = capture(fn)
         trial[name] = max(run_graph(g, 2, max(5, args.steps // 5)))
         g.close()
-    mode = min(("neighbour_list", "box_search"), key=trial.get)
+    mode = min(("neighbour_list", "box_search", "recorded_masks"), key=trial.get)
     log("step trials (ms): %s -> headline uses %s" % (json.dumps(trial), mode))
-    graph = capture(step if mode == "neighbour_list" else step_search)
+    graph = capture(forms[mode])
     wall_ms, ev_ms = run_graph(graph, args.warmup, args.steps)
     ms = max(wall_ms, ev_ms)
     value = pairs / (ms * 1e-3)
@@ -267,6 +282,9 @@ def main():
     t_fwd_search = timed_graph(lambda: A.pair_sum(ctx, cells, "spring", (1.0,), y=y))
     ctx.set_variant(search_bwd)
     t_bwd_search = timed_graph(lambda: A.pair_sum_backward(ctx, cells, "spring", (1.0,), gy, gx=gx))
+    ctx.set_variant(mask_variant)  # each forward records the masks the adjoints then replay
+    t_fwd_mask = timed_graph(lambda: A.pair_sum(ctx, cells, "spring", (1.0,), y=y))
+    t_bwd_mask = timed_graph(lambda: A.pair_sum_backward(ctx, cells, "spring", (1.0,), gy, gx=gx))
     ctx.set_variant(-1)
     per_variant = {}
     for v in range(A.variant_count()):
@@ -292,7 +310,20 @@ def main():
     # writes y or gx (12); the adjoint call also gathers gy (perm 4 + 12 in + 12 out) and reads it (12)
     # recording: xs (16 B), the offsets, one list word per pair and a count per particle
     # replayed sums: list (4 B/pair), xs (16), perm (4), y or gx (12); adjoint as above for gy
-    if mode == "box_search":
+    # masks: the box-search forward plus its record (two words per stencil row and a status word
+    # per particle, 76 B); the adjoint reads them and visits the accepted pairs only
+    if mode == "recorded_masks":
+        t_fwd, t_bwd = t_fwd_mask, t_bwd_mask
+        phases = {
+            "fwd": (kernel_of(mask_variant, "fwd") + " (forward call, box search + record)", t_fwd,
+                    cand * OPS_PER_CANDIDATE + pairs * OPS_PER_PAIR["fwd"],
+                    n * (16 + 4 + 12 + 76) + 4 * (nc + 1), profile_names(A.variant_name(mask_variant), "fwd")),
+            "bwd": (kernel_of(mask_variant, "bwd") + " (adjoint call, replayed masks)", t_bwd,
+                    pairs * (OPS_PER_REPLAYED_PAIR + OPS_PER_PAIR["bwd"]),
+                    n * (4 + 12 + 12) + n * (16 + 4 + 12 + 12 + 76) + 4 * (nc + 1),
+                    profile_names(A.variant_name(mask_variant), "bwd")),
+        }
+    elif mode == "box_search":
         t_fwd, t_bwd = t_fwd_search, t_bwd_search
         phases = {
             "fwd": (kernel_of(search_fwd, "fwd") + " (forward call, box search)", t_fwd,
@@ -347,6 +378,7 @@ def main():
                  "step_hbm_frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                  "build_ms": t_build, "build_counting_ms": t_build_counting, "fwd_ms": t_fwd, "bwd_ms": t_bwd,
                  "box_search_fwd_ms": t_fwd_search, "box_search_bwd_ms": t_bwd_search,
+                 "recorded_masks_fwd_ms": t_fwd_mask, "recorded_masks_bwd_ms": t_bwd_mask,
                  "neighbour_list_record_ms": t_nbr, "replay_fwd_ms": t_fwd_list, "replay_bwd_ms": t_bwd_list,
                  "build_hbm_frac": build_bytes / (t_build * 1e-3) / 1e9 / HBM_PEAK_GBS,
                  "roofline_per_call": {k: {q: v for q, v in roof(k).items() if q in ("bound", "frac", "avg_launch_ms")}
@@ -551,9 +583,13 @@ def main():
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": w.name, "n": n, "box_side": float(s.hi[0]), "cutoff": 1.0,
                       "pairs_per_step": pairs,
-                      "step": ("cell rebuild + neighbour-list recording + spring forward + adjoint (replayed), "
-                               "one hipGraph") if mode == "neighbour_list" else
-                              "cell rebuild + spring forward + adjoint (box search), one hipGraph",
+                      "step": {"neighbour_list": "cell rebuild + neighbour-list recording + spring forward + "
+                                                 "adjoint (replayed), one hipGraph",
+                               "recorded_masks": "cell rebuild + spring forward (box search, recording each "
+                                                 "row's accepted candidates) + adjoint (replaying them), "
+                                                 "one hipGraph",
+                               "box_search": "cell rebuild + spring forward + adjoint (box search), "
+                                             "one hipGraph"}[mode],
                       "parallelism": "single GPU"},
            "roofline": roofline, "cpu_baseline": cpu, "breakdown": breakdown, "other_workloads": extra}
     print(json.dumps(out), flush=True)

@@ -850,7 +850,7 @@ void fill_params(const std::vector<GridPlan>& plans, const std::vector<aboria_bo
 void free_cells_buffers(aboria_cells* c) {
     void* ptrs[] = {c->params_dev, c->sys_part_dev, c->cell_base_dev, c->keys, c->perm, c->keys_alt,
                     c->perm_alt, c->off, c->xs, c->work, c->work2, c->hist, c->block_sums,
-                    c->nbr, c->nbr_count, c->gen};
+                    c->nbr, c->nbr_count, c->gen, c->masks, c->mask_status};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     c->params_dev = nullptr;
@@ -858,6 +858,7 @@ void free_cells_buffers(aboria_cells* c) {
     c->hist = c->block_sums = nullptr;
     c->xs = c->work = c->work2 = nullptr;
     c->nbr = c->nbr_count = c->gen = nullptr;
+    c->masks = c->mask_status = nullptr;
     c->nbr_alloc = 0;
     c->nbr_recorded = false;
 }

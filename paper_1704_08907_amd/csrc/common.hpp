@@ -142,6 +142,9 @@ struct aboria_cells {
     int64_t nbr_alloc = 0;          // entries per slot allocated in nbr (fixed once allocated)
     uint32_t nbr_cap = 0;           // entries per slot of the latest recording
     bool nbr_recorded = false;      // a list has been recorded on these cells
+    // accepted-pair bit masks of the recording forward (pair_mask.hip), allocated on first use
+    uint32_t* masks = nullptr;        // [2 * rows][n] two words per stencil row of each slot
+    uint32_t* mask_status = nullptr;  // [n] generation the slot's masks belong to (0: none)
 };
 
 namespace aboria {

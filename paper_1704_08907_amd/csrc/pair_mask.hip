@@ -1,0 +1,273 @@
+// Lane-per-particle neighbour sums whose forward records, for every stencil
+// row of a particle, one bit per candidate it accepted, and whose adjoint
+// replays those bits instead of testing every candidate again.
+//
+// The row search of the 3^d stencil (reach 1) visits 3^(d-1) rows, each the
+// run of up to three neighbouring cells in x plus, at a periodic wrap, the
+// wrapped remainder.  The candidates of row r, concatenated in visiting order,
+// number at most kMaskBits; bit k of the row's mask word pair (masks[(2r) n +
+// s], masks[(2r + 1) n + s] for slot s) is set when the k-th is a neighbour.
+// The rows advance in lockstep across a wave, so each word is stored as one
+// contiguous 256-byte run.  status[s] = the build generation the masks were
+// recorded for, or 0 when a row of the particle held more than kMaskBits
+// candidates; the adjoint replays a particle only when its status matches the
+// current generation, and otherwise tests its candidates again (the deferred
+// box search), so a stale or overflowing record only costs time.
+//
+// Replayed pairs are visited in box-search order with dx and d2 recomputed by
+// the same pair test, so forward and adjoint equal the plain lane kernels' bit
+// for bit.
+#include "pair_common.hpp"
+
+namespace aboria {
+
+constexpr int kMaskBits = 64;  // candidates per stencil row a record covers
+
+// The pieces of one stencil row of the reach-1 box search (the visiting order
+// of neighbour_loop): at most three runs, each with its x image shift.
+template <typename T>
+struct RowPieces {
+    int np;
+    uint32_t j0[3], j1[3];
+    T sx[3];
+    T sy, sz;
+};
+
+// Calls fn(row, pieces) for every stencil row of xi that exists (rows are
+// numbered (dz + 1) * 3^(d-2) ... in visiting order, so skipped rows keep their
+// numbers).  Reach 1 only.
+template <typename T, int D, typename Fn>
+__device__ __forceinline__ void for_each_row(const SysParams<T>& P, const uint32_t* __restrict__ off, uint32_t n,
+                                             const T* xi, Fn&& fn) {
+    int32_t c[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        T fr;
+        c[k] = cell_coord(P, k, xi[k], &fr);
+    }
+    const int32_t nx = P.n[0];
+    const bool wide = nx >= 3;
+    const int32_t a0 = max(c[0] - 1, 0), b0 = min(c[0] + 1, nx - 1);
+    int32_t a1 = 0, b1 = -1;
+    T s1 = T(0);
+    if (P.periodic[0]) {
+        if (c[0] - 1 < 0) { a1 = nx - 1; b1 = nx - 1; s1 = -P.L[0]; }
+        else if (c[0] + 1 >= nx) { a1 = 0; b1 = 0; s1 = P.L[0]; }
+    }
+    const int32_t zr = D >= 3 ? 1 : 0, yr = D >= 2 ? 1 : 0;
+    for (int32_t dz = -zr; dz <= zr; ++dz) {
+        int32_t cz = 0;
+        T sz = T(0);
+        if (D >= 3 && !wrap_cell(c[2] + dz, P.n[2], P.periodic[2], P.L[2], &cz, &sz)) continue;
+        for (int32_t dy = -yr; dy <= yr; ++dy) {
+            int32_t cy = 0;
+            T sy = T(0);
+            if (D >= 2 && !wrap_cell(c[1] + dy, P.n[1], P.periodic[1], P.L[1], &cy, &sy)) continue;
+            const int row = (dz + zr) * (2 * yr + 1) + (dy + yr);
+            const uint32_t rowbase = P.cell_base + (uint32_t)nx * ((uint32_t)cy + (uint32_t)P.n[1] * (uint32_t)cz);
+            RowPieces<T> rp;
+            rp.np = 0;
+            rp.sy = sy;
+            rp.sz = sz;
+            auto add = [&](uint32_t ca, uint32_t cb, T sx) {
+                rp.j0[rp.np] = off[ca];
+                rp.j1[rp.np] = min(off[cb + 1], n);
+                rp.sx[rp.np] = sx;
+                ++rp.np;
+            };
+            if (wide) {
+                add(rowbase + a0, rowbase + b0, T(0));
+                if (b1 >= a1) add(rowbase + a1, rowbase + b1, s1);
+            } else {
+                for (int32_t o = -1; o <= 1; ++o) {
+                    int32_t cx;
+                    T sx;
+                    if (!wrap_cell(c[0] + o, nx, P.periodic[0], P.L[0], &cx, &sx)) continue;
+                    add(rowbase + cx, rowbase + cx, sx);
+                }
+            }
+            fn(row, rp);
+        }
+    }
+}
+
+// MODE 0: forward sum + record.  MODE 1: adjoint from the record (gy_s gathered
+// into cell order, rows padded as gradient rows).
+template <typename T, int D, int OP, bool BATCH, bool OFF32, int MODE>
+__global__ __launch_bounds__(256) void k_lane_mask(const T* __restrict__ xs, const uint32_t* __restrict__ off,
+                                                   const uint32_t* __restrict__ perm, uint32_t n,
+                                                   const SysParams<T>* __restrict__ sp,
+                                                   const uint32_t* __restrict__ sys_part, int nsys,
+                                                   const T* __restrict__ a_s, const T* __restrict__ gy_s,
+                                                   OpArgs<T> q, T* __restrict__ y, T* __restrict__ gx,
+                                                   T* __restrict__ ga, uint32_t* __restrict__ masks,
+                                                   uint32_t* __restrict__ status, const uint32_t* __restrict__ gen) {
+    using Op = PairOp<T, D, OP>;
+    constexpr int NY = Op::NY;
+    constexpr int PITCH = Pitch<D>::value;
+    constexpr int GP = GyPitch<NY>::value;
+    const uint32_t first = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x;
+    const uint32_t s = first + threadIdx.x;
+    const int b = system_of_row<BATCH>(sys_part, nsys, first, s);
+    if (s >= n) return;
+    const SysParams<T> P = sp[b];
+    T xi[D];
+    load_point<T, D>(xs, s, xi);
+    const T ai = OpShape<OP, D>::NA ? a_s[s] : T(0);
+    const T r = P.r, r2 = P.r2;
+    if constexpr (MODE == 0) {
+        T acc[NY];
+#pragma unroll
+        for (int k = 0; k < NY; ++k) acc[k] = T(0);
+        bool overflow = false;
+        auto visit = [&](uint32_t j, const T* dx, T d2) {
+            const T aj = OpShape<OP, D>::NA ? load_row<T, 1, OFF32>(a_s, j).v[0] : T(0);
+            Op::fwd(q, r, dx, d2, ai, aj, acc);
+        };
+        // candidates [ja, jb) at row positions k0, k0 + 1, ...: the summand of each
+        // accepted one, and its bit (k mod 32) in word; two candidates per iteration
+        auto scan_part = [&](auto shift_tag, uint32_t ja, uint32_t jb, uint32_t k0, const T* sh, uint32_t& word) {
+            constexpr bool SHIFT = decltype(shift_tag)::value;
+            uint32_t j = ja, k = k0;
+            for (; j + 1 < jb; j += 2, k += 2) {
+                const VecN<T, PITCH> xa = load_row<T, PITCH, OFF32>(xs, j);
+                const VecN<T, PITCH> xb = load_row<T, PITCH, OFF32>(xs, j + 1);
+                T dx[D], d2;
+                const bool oa = pair_test<T, D, SHIFT>(xa.v, xi, sh, r2, dx, &d2);
+                if (oa) visit(j, dx, d2);
+                word |= (oa ? 1u : 0u) << (k & 31u);
+                const bool ob = pair_test<T, D, SHIFT>(xb.v, xi, sh, r2, dx, &d2);
+                if (ob) visit(j + 1, dx, d2);
+                word |= (ob ? 1u : 0u) << ((k + 1u) & 31u);
+            }
+            if (j < jb) {
+                const VecN<T, PITCH> xa = load_row<T, PITCH, OFF32>(xs, j);
+                T dx[D], d2;
+                const bool oa = pair_test<T, D, SHIFT>(xa.v, xi, sh, r2, dx, &d2);
+                if (oa) visit(j, dx, d2);
+                word |= (oa ? 1u : 0u) << (k & 31u);
+            }
+        };
+        for_each_row<T, D>(P, off, n, xi, [&](int row, const RowPieces<T>& rp) {
+            uint32_t mlo = 0, mhi = 0, spill = 0;
+            uint32_t pos = 0;  // row position of the piece's first candidate
+            for (int p = 0; p < rp.np; ++p) {
+                const T sh[3] = {rp.sx[p], rp.sy, rp.sz};
+                bool lane_shift = false;
+#pragma unroll
+                for (int k = 0; k < D; ++k) lane_shift |= sh[k] != T(0);
+                const uint32_t j0 = rp.j0[p], j1 = max(rp.j1[p], rp.j0[p]);
+                // the piece split where its row positions reach 32 and 64
+                const uint32_t s32 = pos >= 32u ? j0 : min(j1, j0 + (32u - pos));
+                const uint32_t s64 = pos >= 64u ? j0 : min(j1, j0 + (64u - pos));
+                auto parts = [&](auto tag) {
+                    scan_part(tag, j0, s32, pos, sh, mlo);
+                    scan_part(tag, s32, s64, pos + (s32 - j0), sh, mhi);
+                    scan_part(tag, s64, j1, 0u, sh, spill);
+                };
+                if (__ballot(lane_shift) != 0ull) parts(std::integral_constant<bool, true>());
+                else parts(std::integral_constant<bool, false>());
+                pos += j1 - j0;
+            }
+            overflow |= pos > (uint32_t)kMaskBits;
+            masks[(size_t)(2 * row) * n + s] = mlo;
+            masks[(size_t)(2 * row + 1) * n + s] = mhi;
+        });
+        status[s] = overflow ? 0u : gen[0];
+        const uint32_t o = perm[s];
+#pragma unroll
+        for (int k = 0; k < NY; ++k) y[(size_t)o * NY + k] = acc[k];
+    } else {
+        T gyi[NY];
+        load_gy<T, NY, OFF32>(gy_s, s, gyi);
+        T accx[D], acca[1] = {T(0)};
+#pragma unroll
+        for (int k = 0; k < D; ++k) accx[k] = T(0);
+        auto pair = [&](uint32_t j, const T* dx, T d2, const T* gyj) {
+            const T aj = OpShape<OP, D>::NA ? load_row<T, 1, OFF32>(a_s, j).v[0] : T(0);
+            Op::bwd(q, r, dx, d2, ai, aj, gyi, gyj, accx, acca);
+        };
+        if (status[s] == gen[0]) {
+            for_each_row<T, D>(P, off, n, xi, [&](int row, const RowPieces<T>& rp) {
+                const uint64_t m = (uint64_t)masks[(size_t)(2 * row) * n + s] |
+                                   ((uint64_t)masks[(size_t)(2 * row + 1) * n + s] << 32);
+                uint32_t pos = 0;
+                for (int p = 0; p < rp.np; ++p) {
+                    const T sh[3] = {rp.sx[p], rp.sy, rp.sz};
+                    const uint32_t j0 = rp.j0[p];
+                    const uint32_t len = rp.j1[p] > j0 ? rp.j1[p] - j0 : 0u;
+                    uint64_t bits = pos < 64u ? m >> pos : 0ull;
+                    if (len < 64u) bits &= (1ull << len) - 1ull;
+                    pos += len;
+                    // two accepted pairs per iteration, so their loads overlap
+                    while (bits != 0ull) {
+                        const uint32_t ja = j0 + (uint32_t)__builtin_ctzll(bits);
+                        bits &= bits - 1ull;
+                        const bool vb = bits != 0ull;
+                        const uint32_t jb = vb ? j0 + (uint32_t)__builtin_ctzll(bits) : ja;
+                        bits &= bits - 1ull;
+                        const VecN<T, PITCH> xa = load_row<T, PITCH, OFF32>(xs, ja);
+                        const VecN<T, GP> ga_ = load_row<T, GP, OFF32>(gy_s, ja);
+                        const VecN<T, PITCH> xb = load_row<T, PITCH, OFF32>(xs, jb);
+                        const VecN<T, GP> gb_ = load_row<T, GP, OFF32>(gy_s, jb);
+                        T dx[D], d2;
+                        (void)pair_test<T, D, true>(xa.v, xi, sh, r2, dx, &d2);
+                        pair(ja, dx, d2, ga_.v);
+                        if (vb) {
+                            (void)pair_test<T, D, true>(xb.v, xi, sh, r2, dx, &d2);
+                            pair(jb, dx, d2, gb_.v);
+                        }
+                    }
+                }
+            });
+        } else {
+            auto visit = [&](uint32_t j, const T* dx, T d2, bool, const T* gyj) { pair(j, dx, d2, gyj); };
+            neighbour_loop_aux<T, D, OFF32, NY>(P, xs, gy_s, off, n, xi, visit);
+        }
+        const uint32_t o = perm[s];
+#pragma unroll
+        for (int k = 0; k < D; ++k) gx[(size_t)o * D + k] = accx[k];
+        if (OpShape<OP, D>::NA && ga) ga[o] = acca[0];
+    }
+}
+
+template <typename T, int D, int OP, bool BATCH>
+void launch_mask_fwd(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, T* y) {
+    const uint32_t n = (uint32_t)c->n;
+    const SysParams<T>* sp = reinterpret_cast<const SysParams<T>*>(c->params_dev);
+    const dim3 grid((n + 255) / 256);
+    if (off32_rows<T>(n))
+        hipLaunchKernelGGL((k_lane_mask<T, D, OP, BATCH, true, 0>), grid, dim3(256), 0, ctx->stream, (const T*)c->xs,
+                           c->off, c->perm, n, sp, c->sys_part_dev, c->nsys, a_s, nullptr, q, y, nullptr, nullptr,
+                           c->masks, c->mask_status, c->gen);
+    else
+        hipLaunchKernelGGL((k_lane_mask<T, D, OP, BATCH, false, 0>), grid, dim3(256), 0, ctx->stream, (const T*)c->xs,
+                           c->off, c->perm, n, sp, c->sys_part_dev, c->nsys, a_s, nullptr, q, y, nullptr, nullptr,
+                           c->masks, c->mask_status, c->gen);
+}
+
+template <typename T, int D, int OP, bool BATCH>
+void launch_mask_bwd(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, const T* gy_s, T* gx,
+                     T* ga) {
+    const uint32_t n = (uint32_t)c->n;
+    const SysParams<T>* sp = reinterpret_cast<const SysParams<T>*>(c->params_dev);
+    const dim3 grid((n + 255) / 256);
+    if (off32_rows<T>(n))
+        hipLaunchKernelGGL((k_lane_mask<T, D, OP, BATCH, true, 1>), grid, dim3(256), 0, ctx->stream, (const T*)c->xs,
+                           c->off, c->perm, n, sp, c->sys_part_dev, c->nsys, a_s, gy_s, q, nullptr, gx, ga,
+                           c->masks, c->mask_status, c->gen);
+    else
+        hipLaunchKernelGGL((k_lane_mask<T, D, OP, BATCH, false, 1>), grid, dim3(256), 0, ctx->stream, (const T*)c->xs,
+                           c->off, c->perm, n, sp, c->sys_part_dev, c->nsys, a_s, gy_s, q, nullptr, gx, ga,
+                           c->masks, c->mask_status, c->gen);
+}
+
+#define ABORIA_INST(T, D, OP, BATCH)                                                                          \
+    template void launch_mask_fwd<T, D, OP, BATCH>(aboria_ctx*, const aboria_cells*, const OpArgs<T>&,        \
+                                                   const T*, T*);                                             \
+    template void launch_mask_bwd<T, D, OP, BATCH>(aboria_ctx*, const aboria_cells*, const OpArgs<T>&,        \
+                                                   const T*, const T*, T*, T*);
+ABORIA_FOR_EACH_PAIR_INSTANCE(ABORIA_INST)
+#undef ABORIA_INST
+
+}  // namespace aboria

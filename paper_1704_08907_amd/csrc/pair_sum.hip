@@ -86,7 +86,8 @@ aboria_status gather(aboria_ctx* ctx, const aboria_cells* c, const void* src, in
 // Work-mapping variants of the neighbour sums.
 struct Variant {
     int kind;      // 0 = lane per particle, 1 = cell group, 2 = recorded neighbour list,
-                   // 3 = all pairs, 4 = LDS-staged rows, 5 = flattened pruned search
+                   // 3 = all pairs, 4 = LDS-staged rows, 5 = flattened pruned search,
+                   // 6 = lane per particle with recorded accepted-pair masks
     int block;     // threads per workgroup (lane mapping)
     bool compact;  // adjoint lists accepted pairs before evaluating them (lane mapping)
     int rounds;    // cell group: 1 = natural cell order, 8 = 64-cell tiles ranked by occupancy
@@ -104,6 +105,7 @@ const Variant kVariants[] = {
     {3, 256, false, 0, "lane per particle over all particles of its system (minimum image; small systems)"},
     {4, 256, false, 0, "lane per particle, candidates staged in LDS per stencil row and wave"},
     {5, 256, false, 0, "lane per particle, flattened box search over pruned slot ranges listed in LDS"},
+    {6, 256, false, 0, "lane per particle, forward records accepted-pair bit masks per stencil row, adjoint replays them"},
 };
 
 // Modes of the flattened kernel (pair_flat.hpp).
@@ -124,7 +126,7 @@ int32_t max_reach(const aboria_cells* c) {
 }
 
 // Variants with their own box-search loops, written for the 3^d stencil.
-bool needs_reach1(const Variant& v) { return v.kind == 1 || v.kind == 4 || (v.kind == 0 && v.compact); }
+bool needs_reach1(const Variant& v) { return v.kind == 1 || v.kind == 4 || v.kind == 6 || (v.kind == 0 && v.compact); }
 
 int64_t largest_system(const aboria_cells* c) {
     int64_t m = 0;
@@ -136,7 +138,8 @@ constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 template <typename T, int D, int OP, bool BATCH>
 void launch_fwd_variant(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, T* y,
                         const Variant& v) {
-    if (v.kind == 5) launch_flat<T, D, OP, BATCH, kFlatModeFwd>(ctx, c, q, a_s, nullptr, y, nullptr, nullptr);
+    if (v.kind == 6) launch_mask_fwd<T, D, OP, BATCH>(ctx, c, q, a_s, y);
+    else if (v.kind == 5) launch_flat<T, D, OP, BATCH, kFlatModeFwd>(ctx, c, q, a_s, nullptr, y, nullptr, nullptr);
     else if (v.kind == 4) launch_stage_fwd<T, D, OP, BATCH>(ctx, c, q, a_s, y);
     else if (v.kind == 3) launch_all_fwd<T, D, OP, BATCH>(ctx, c, q, a_s, y);
     else if (v.kind == 2) launch_nbr_fwd<T, D, OP, BATCH>(ctx, c, q, a_s, y);
@@ -147,7 +150,8 @@ void launch_fwd_variant(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>&
 template <typename T, int D, int OP, bool BATCH>
 void launch_bwd_variant(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, const T* gy_s,
                         T* gx, T* ga, const Variant& v) {
-    if (v.kind == 5) launch_flat<T, D, OP, BATCH, kFlatModeBwd>(ctx, c, q, a_s, gy_s, nullptr, gx, ga);
+    if (v.kind == 6) launch_mask_bwd<T, D, OP, BATCH>(ctx, c, q, a_s, gy_s, gx, ga);
+    else if (v.kind == 5) launch_flat<T, D, OP, BATCH, kFlatModeBwd>(ctx, c, q, a_s, gy_s, nullptr, gx, ga);
     else if (v.kind == 4) launch_stage_bwd<T, D, OP, BATCH>(ctx, c, q, a_s, gy_s, gx, ga);
     else if (v.kind == 3) launch_all_bwd<T, D, OP, BATCH>(ctx, c, q, a_s, gy_s, gx, ga);
     else if (v.kind == 2) launch_nbr_bwd<T, D, OP, BATCH>(ctx, c, q, a_s, gy_s, gx, ga);
@@ -215,6 +219,26 @@ aboria_status validate(aboria_ctx* ctx, const aboria_cells* c, int op, const dou
     return ABORIA_OK;
 }
 
+// Allocates the accepted-pair masks of a cell list on first use (status zeroed,
+// so nothing counts as recorded until a recording forward runs).
+aboria_status ensure_masks(aboria_ctx* ctx, const aboria_cells* cc) {
+    aboria_cells* c = const_cast<aboria_cells*>(cc);
+    if (c->masks || c->n == 0) return ABORIA_OK;
+    if (ctx->capturing)
+        return fail(ctx, ABORIA_ERR_UNSUPPORTED, "the mask variant allocates on first use and cannot be captured then");
+    const size_t rows = c->d == 1 ? 1 : (c->d == 2 ? 3 : 9);
+    const size_t nn = (size_t)c->n;
+    if (hipMalloc((void**)&c->masks, sizeof(uint32_t) * 2 * rows * nn) != hipSuccess ||
+        hipMalloc((void**)&c->mask_status, sizeof(uint32_t) * nn) != hipSuccess) {
+        (void)hipGetLastError();
+        if (c->masks) (void)hipFree(c->masks);
+        if (c->mask_status) (void)hipFree(c->mask_status);
+        c->masks = c->mask_status = nullptr;
+        return fail(ctx, ABORIA_ERR_OUT_OF_MEMORY, "device allocation for the pair masks failed");
+    }
+    return fill_u32(ctx, c->mask_status, 0u, (int64_t)nn);
+}
+
 aboria_status check_variant(aboria_ctx* ctx, const aboria_cells* c, int variant) {
     if (variant_needs_list(variant) && !c->nbr_recorded)
         return fail(ctx, ABORIA_ERR_INVALID_ARG, "the variant needs a neighbour list recorded on these cells");
@@ -224,6 +248,7 @@ aboria_status check_variant(aboria_ctx* ctx, const aboria_cells* c, int variant)
         return fail(ctx, ABORIA_ERR_INVALID_ARG, "the staged variant needs rows below a 32-bit byte offset");
     if (needs_reach1(variant_of(variant)) && max_reach(c) > 1)
         return fail(ctx, ABORIA_ERR_INVALID_ARG, "the variant searches the 3^d stencil only (reach 1)");
+    if (variant_of(variant).kind == 6) return ensure_masks(ctx, c);
     return ABORIA_OK;
 }
 
@@ -240,6 +265,9 @@ bool variant_needs_list(int32_t v) { return v >= 0 && v < kNumVariants && kVaria
 // a few groups do all the work, so the tuner does not time it there.
 bool variant_worth_timing(int32_t v, const aboria_cells* c) {
     if (v < 0 || v >= kNumVariants) return false;
+    // the mask-recording pair pays only across a forward and its adjoint, which the
+    // tuner times separately: callers select it for both calls
+    if (kVariants[v].kind == 6) return false;
     if (kVariants[v].kind == 1) return c->n <= 64 * c->ncells;
     return true;
 }

@@ -1,0 +1,163 @@
+"""The mask-recording variant: its forward records, per stencil row, the
+candidates it accepted; its adjoint replays them.  Both must equal the plain
+lane kernels bit for bit -- after a recording, without one (every particle
+falls back to testing its candidates), after a rebuild made the record stale,
+when rows overflow the record, on a batch and in a graph."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1704_08907_amd as A
+from paper_1704_08907_amd import synthetic as syn
+from _parity import box_of, to_dev
+from test_gpu_parity import CASES, OPS, make_case
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = A.Context(0)
+    yield c
+    c.set_variant(-1)
+    c.close()
+
+
+def variant(word):
+    return next(v for v in range(A.variant_count()) if word in A.variant_name(v))
+
+
+MASK = "records accepted-pair bit masks"
+PLAIN = "adjoint evaluated on every candidate"
+
+
+def fwd(ctx, cells, op, params, a_d, v):
+    ctx.set_variant(v)
+    try:
+        return A.pair_sum(ctx, cells, op, params, a_d)
+    finally:
+        ctx.set_variant(-1)
+
+
+def bwd(ctx, cells, op, params, gy_d, a_d, v):
+    ctx.set_variant(v)
+    try:
+        return A.pair_sum_backward(ctx, cells, op, params, gy_d, a_d)
+    finally:
+        ctx.set_variant(-1)
+
+
+def same(u, v):
+    return (u is None and v is None) or torch.equal(u, v)
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_recorded_masks_equal_the_plain_kernels(ctx, case):
+    g, x, box, prec = make_case(case)
+    n, d = x.shape
+    print("case", case[0], flush=True)
+    cells = A.build_cells(ctx, to_dev(x), [box])
+    rng = syn.SplitMix64(8080)
+    a_d = to_dev((0.2 + 0.3 * rng.uniform(n)).astype(x.dtype).reshape(n, 1))
+    for op, params in OPS:
+        gy_d = to_dev(rng.normal(n * A.op_ny(op, d)).astype(x.dtype).reshape(n, -1))
+        aa = a_d if op == "dem_spring" else None
+        y_ref = fwd(ctx, cells, op, params, aa, variant(PLAIN))
+        g_ref = bwd(ctx, cells, op, params, gy_d, aa, variant(PLAIN))
+        y = fwd(ctx, cells, op, params, aa, variant(MASK))   # records
+        g = bwd(ctx, cells, op, params, gy_d, aa, variant(MASK))  # replays
+        ctx.sync()
+        assert torch.equal(y, y_ref), (case[0], op)
+        for u, v in zip(g, g_ref):
+            assert same(u, v), (case[0], op)
+
+
+def test_without_and_after_a_stale_record(ctx):
+    w = syn.spring_cube(n=50000)
+    s = w.systems[0]
+    box = box_of(s)
+    x = s.x.copy()
+    cells = A.build_cells(ctx, to_dev(x), [box])
+    n = x.shape[0]
+    gy_d = to_dev(syn.SplitMix64(4).normal(3 * n).astype(np.float32).reshape(n, 3))
+    # no record yet: every particle tests its candidates again
+    g0 = bwd(ctx, cells, "spring", (1.0,), gy_d, None, variant(MASK))
+    r0 = bwd(ctx, cells, "spring", (1.0,), gy_d, None, variant(PLAIN))
+    assert torch.equal(g0[0], r0[0])
+    fwd(ctx, cells, "spring", (1.0,), None, variant(MASK))
+    # move the points and rebuild: the record belongs to the previous build
+    rng = syn.SplitMix64(5)
+    x2 = (x + 0.3 * (rng.uniform(x.size).reshape(x.shape) - 0.5)).astype(np.float32)
+    x2 = np.mod(x2 - np.float32(s.lo[0]), np.float32(s.hi[0] - s.lo[0])).astype(np.float32) + np.float32(s.lo[0])
+    x2 = np.minimum(x2, np.nextafter(np.float32(s.hi[0]), np.float32(-np.inf)))
+    A.build_cells(ctx, to_dev(x2), [box], cells=cells)
+    g1 = bwd(ctx, cells, "spring", (1.0,), gy_d, None, variant(MASK))
+    r1 = bwd(ctx, cells, "spring", (1.0,), gy_d, None, variant(PLAIN))
+    ctx.sync()
+    assert torch.equal(g1[0], r1[0])
+
+
+def test_overflowing_rows_fall_back(ctx):
+    # a coarse explicit grid packs ~50 candidates per cell, so rows of three cells hold
+    # more than 64 candidates and those particles keep no record
+    w = syn.spring_cube(n=40000)
+    s = w.systems[0]
+    box = A.BoxSpec(3, s.lo, s.hi, s.periodic, s.cutoff, [6, 6, 6])
+    cells = A.build_cells(ctx, to_dev(s.x), [box])
+    n = s.n
+    gy_d = to_dev(syn.SplitMix64(6).normal(3 * n).astype(np.float32).reshape(n, 3))
+    y = fwd(ctx, cells, "spring", (1.0,), None, variant(MASK))
+    g = bwd(ctx, cells, "spring", (1.0,), gy_d, None, variant(MASK))
+    y_ref = fwd(ctx, cells, "spring", (1.0,), None, variant(PLAIN))
+    g_ref = bwd(ctx, cells, "spring", (1.0,), gy_d, None, variant(PLAIN))
+    ctx.sync()
+    assert torch.equal(y, y_ref) and torch.equal(g[0], g_ref[0])
+
+
+def test_batch_and_graph():
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    ctx = A.Context(0, stream)
+    w = syn.batch_cubes(nsys=24, nmax=16384)
+    xs_all = np.concatenate([q.x for q in w.systems])
+    offsets = np.concatenate([[0], np.cumsum([q.n for q in w.systems])]).tolist()
+    boxes = [box_of(q) for q in w.systems]
+    x_d = to_dev(xs_all)
+    n = xs_all.shape[0]
+    gy_d = to_dev(syn.SplitMix64(9).normal(3 * n).astype(np.float32).reshape(n, 3))
+    cells = A.build_cells(ctx, x_d, boxes, offsets)
+    y_ref = fwd(ctx, cells, "spring", (1.0,), None, variant(PLAIN))
+    g_ref = bwd(ctx, cells, "spring", (1.0,), gy_d, None, variant(PLAIN))
+    y = torch.empty_like(y_ref)
+    gx = torch.empty_like(g_ref[0])
+
+    def step():
+        A.build_cells(ctx, x_d, boxes, offsets, cells=cells)
+        ctx.set_variant(variant(MASK))
+        A.pair_sum(ctx, cells, "spring", (1.0,), y=y)
+        A.pair_sum_backward(ctx, cells, "spring", (1.0,), gy_d, gx=gx)
+        ctx.set_variant(-1)
+
+    step()
+    ctx.sync()
+    assert torch.equal(y, y_ref) and torch.equal(gx, g_ref[0])
+    A.graph_capture_begin(ctx)
+    step()
+    graph = A.graph_capture_end(ctx)
+    for _ in range(3):
+        y.zero_()  # on the same stream as the graph
+        gx.zero_()
+        A.graph_launch(ctx, graph)
+        ctx.sync()
+        assert torch.equal(y, y_ref) and torch.equal(gx, g_ref[0])
+    graph.close()
+    ctx.close()
+    torch.cuda.set_stream(torch.cuda.default_stream())
+
+
+def test_needs_reach_1(ctx):
+    s = syn.spring_cube(n=20000).systems[0]
+    cells = A.build_cells(ctx, to_dev(s.x), [A.BoxSpec(3, s.lo, s.hi, s.periodic, s.cutoff, None, 2)])
+    with pytest.raises(A.AboriaError) as e:
+        fwd(ctx, cells, "spring", (1.0,), None, variant(MASK))
+    assert e.value.status == "INVALID_ARG"
