@@ -88,8 +88,8 @@ typedef enum aboria_kernel {
  * cutoff wide, searched with the adjacent cells (Section 2.2.2).  m = 2 or 3
  * uses cells about r/m wide searched m cells deep, which tests fewer
  * candidates; the pair set is the same, since the pair predicate alone
- * decides it.  The cell-group, LDS-list, wave-queue and LDS-staged variants
- * need m = 1.
+ * decides it.  The cell-group, LDS-list, wave-queue, LDS-staged and
+ * recorded-mask variants need m = 1.
  *
  * ncell[k] = 0 picks the cell count automatically: the largest count whose
  * cells are at least (cutoff + a rounding guard) / m wide.  An explicit count
@@ -352,7 +352,14 @@ aboria_status aboria_autotune_cells(aboria_ctx* ctx, aboria_dtype dtype, int32_t
 /* Number of neighbour-sum variants, and a static description of one. */
 int32_t aboria_variant_count(void);
 const char* aboria_variant_name(int32_t variant);
-/* Forces a variant for later sums on ctx (-1 = use the tuned / default one). */
+/* Forces a variant for later sums on ctx (-1 = use the tuned / default one).
+ * The recorded-mask variant's forward also stores, per particle and stencil
+ * row, which candidates it accepted; its adjoint on the same cells (until they
+ * are rebuilt) visits only those, and otherwise repeats the search.  The first
+ * sum with it on a cell list allocates 2 * 3^(d-1) + 1 words per particle,
+ * owned and freed with the cell list (so that first call cannot be captured);
+ * INVALID_ARG if the list has m > 1.  Sums that overlap on one cell list with
+ * this variant race on its record. */
 aboria_status aboria_set_variant(aboria_ctx* ctx, int32_t variant);
 
 /* Summand widths of an operator: ny for dimension d, and na. -1 if unknown. */
