@@ -239,6 +239,16 @@ __device__ __forceinline__ VecN<T, N> load_row(const T* __restrict__ base, uint3
         return reinterpret_cast<const VecN<T, N>*>(base)[j];
 }
 
+// Marks the first N elements of a loaded row as used at this point (an empty
+// asm statement, no instruction).  A load whose only other use sits inside a
+// branch would otherwise be sunk into that branch and issued only there; held
+// here, it is issued where it is written and overlaps the work before it.
+template <int N, typename T>
+__device__ __forceinline__ void keep_issued(const T* v) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) asm volatile("" ::"v"(v[k]));
+}
+
 // True when every per-particle row the sums load (at most 4 elements of T)
 // lies below a 32-bit byte offset, so the kernels may use 32-bit offsets.
 template <typename T>
@@ -338,20 +348,23 @@ __device__ __forceinline__ void scan_range_deferred(const T* __restrict__ xs, co
     constexpr int AP = GyPitch<NAUX>::value;
     for (uint32_t c0 = j0; c0 < j1; c0 += 32u) {
         const uint32_t c1 = min(c0 + 32u, j1);
+        // each test's bit is shifted in from the bottom (the first candidate ends
+        // highest), then one bit reversal puts candidate c0 + k at bit k
         uint32_t mask = 0u;
         uint32_t j = c0;
         for (; j + 1 < c1; j += 2) {
             const VecN<T, PITCH> a = load_row<T, PITCH, OFF32>(xs, j);
             const VecN<T, PITCH> b = load_row<T, PITCH, OFF32>(xs, j + 1);
             T dx[D], d2;
-            mask |= (pair_test<T, D, SHIFT>(a.v, xi, sh, r2, dx, &d2) ? 1u : 0u) << (j - c0);
-            mask |= (pair_test<T, D, SHIFT>(b.v, xi, sh, r2, dx, &d2) ? 1u : 0u) << (j + 1 - c0);
+            mask = (mask << 1) | (pair_test<T, D, SHIFT>(a.v, xi, sh, r2, dx, &d2) ? 1u : 0u);
+            mask = (mask << 1) | (pair_test<T, D, SHIFT>(b.v, xi, sh, r2, dx, &d2) ? 1u : 0u);
         }
         if (j < c1) {
             const VecN<T, PITCH> a = load_row<T, PITCH, OFF32>(xs, j);
             T dx[D], d2;
-            mask |= (pair_test<T, D, SHIFT>(a.v, xi, sh, r2, dx, &d2) ? 1u : 0u) << (j - c0);
+            mask = (mask << 1) | (pair_test<T, D, SHIFT>(a.v, xi, sh, r2, dx, &d2) ? 1u : 0u);
         }
+        mask = __builtin_bitreverse32(mask) >> (32u - (c1 - c0));
         // two accepted pairs per iteration, so their four loads overlap
         while (mask != 0u) {
             const uint32_t ja = c0 + (uint32_t)__builtin_ctz(mask);
@@ -366,6 +379,8 @@ __device__ __forceinline__ void scan_range_deferred(const T* __restrict__ xs, co
             T dx[D], d2;
             (void)pair_test<T, D, SHIFT>(a.v, xi, sh, r2, dx, &d2);
             visit(ja, dx, d2, shifted, ava.v);
+            keep_issued<D>(b.v);
+            keep_issued<NAUX>(avb.v);
             if (vb) {
                 (void)pair_test<T, D, SHIFT>(b.v, xi, sh, r2, dx, &d2);
                 visit(jb, dx, d2, shifted, avb.v);

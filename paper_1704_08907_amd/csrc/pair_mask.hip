@@ -23,22 +23,15 @@ namespace aboria {
 
 constexpr int kMaskBits = 64;  // candidates per stencil row a record covers
 
-// The pieces of one stencil row of the reach-1 box search (the visiting order
-// of neighbour_loop): at most three runs, each with its x image shift.
-template <typename T>
-struct RowPieces {
-    int np;
-    uint32_t j0[3], j1[3];
-    T sx[3];
-    T sy, sz;
-};
-
-// Calls fn(row, pieces) for every stencil row of xi that exists (rows are
-// numbered (dz + 1) * 3^(d-2) ... in visiting order, so skipped rows keep their
-// numbers).  Reach 1 only.
-template <typename T, int D, typename Fn>
-__device__ __forceinline__ void for_each_row(const SysParams<T>& P, const uint32_t* __restrict__ off, uint32_t n,
-                                             const T* xi, Fn&& fn) {
+// Walks the stencil rows of xi that exist, in the visiting order of the
+// reach-1 box search: begin(row), then piece(j0, j1, sh) for each run of slots
+// [j0, j1) of the row with its image shift sh (up to three runs: the x
+// neighbours, plus the wrapped remainder at a periodic boundary), then
+// end(row).  Rows are numbered (dz + 1) * 3^(d-2) + (dy + 1) in visiting order,
+// so skipped rows keep their numbers.
+template <typename T, int D, typename Begin, typename Piece, typename End>
+__device__ __forceinline__ void for_each_piece(const SysParams<T>& P, const uint32_t* __restrict__ off, uint32_t n,
+                                               const T* xi, Begin&& begin, Piece&& piece, End&& end) {
     int32_t c[3] = {0, 0, 0};
 #pragma unroll
     for (int k = 0; k < D; ++k) {
@@ -65,28 +58,23 @@ __device__ __forceinline__ void for_each_row(const SysParams<T>& P, const uint32
             if (D >= 2 && !wrap_cell(c[1] + dy, P.n[1], P.periodic[1], P.L[1], &cy, &sy)) continue;
             const int row = (dz + zr) * (2 * yr + 1) + (dy + yr);
             const uint32_t rowbase = P.cell_base + (uint32_t)nx * ((uint32_t)cy + (uint32_t)P.n[1] * (uint32_t)cz);
-            RowPieces<T> rp;
-            rp.np = 0;
-            rp.sy = sy;
-            rp.sz = sz;
-            auto add = [&](uint32_t ca, uint32_t cb, T sx) {
-                rp.j0[rp.np] = off[ca];
-                rp.j1[rp.np] = min(off[cb + 1], n);
-                rp.sx[rp.np] = sx;
-                ++rp.np;
-            };
+            T sh[3] = {T(0), sy, sz};
+            begin(row);
+            auto run = [&](uint32_t ca, uint32_t cb) { piece(off[ca], min(off[cb + 1], n), sh); };
             if (wide) {
-                add(rowbase + a0, rowbase + b0, T(0));
-                if (b1 >= a1) add(rowbase + a1, rowbase + b1, s1);
+                run(rowbase + a0, rowbase + b0);
+                if (b1 >= a1) {
+                    sh[0] = s1;
+                    run(rowbase + a1, rowbase + b1);
+                }
             } else {
                 for (int32_t o = -1; o <= 1; ++o) {
                     int32_t cx;
-                    T sx;
-                    if (!wrap_cell(c[0] + o, nx, P.periodic[0], P.L[0], &cx, &sx)) continue;
-                    add(rowbase + cx, rowbase + cx, sx);
+                    if (!wrap_cell(c[0] + o, nx, P.periodic[0], P.L[0], &cx, &sh[0])) continue;
+                    run(rowbase + cx, rowbase + cx);
                 }
             }
-            fn(row, rp);
+            end(row);
         }
     }
 }
@@ -124,55 +112,58 @@ __global__ __launch_bounds__(256) void k_lane_mask(const T* __restrict__ xs, con
             const T aj = OpShape<OP, D>::NA ? load_row<T, 1, OFF32>(a_s, j).v[0] : T(0);
             Op::fwd(q, r, dx, d2, ai, aj, acc);
         };
-        // candidates [ja, jb) at row positions k0, k0 + 1, ...: the summand of each
-        // accepted one, and its bit (k mod 32) in word; two candidates per iteration
-        auto scan_part = [&](auto shift_tag, uint32_t ja, uint32_t jb, uint32_t k0, const T* sh, uint32_t& word) {
+        // candidates [ja, jb): the summand of each accepted one, and its bit shifted
+        // into rec from the bottom (the row's first candidate ends highest; the
+        // record is bit-reversed when the row is done); two candidates per iteration
+        auto scan = [&](auto shift_tag, uint32_t ja, uint32_t jb, const T* sh, uint64_t& rec) {
             constexpr bool SHIFT = decltype(shift_tag)::value;
-            uint32_t j = ja, k = k0;
-            for (; j + 1 < jb; j += 2, k += 2) {
+            uint32_t j = ja;
+            for (; j + 1 < jb; j += 2) {
                 const VecN<T, PITCH> xa = load_row<T, PITCH, OFF32>(xs, j);
                 const VecN<T, PITCH> xb = load_row<T, PITCH, OFF32>(xs, j + 1);
                 T dx[D], d2;
                 const bool oa = pair_test<T, D, SHIFT>(xa.v, xi, sh, r2, dx, &d2);
                 if (oa) visit(j, dx, d2);
-                word |= (oa ? 1u : 0u) << (k & 31u);
                 const bool ob = pair_test<T, D, SHIFT>(xb.v, xi, sh, r2, dx, &d2);
                 if (ob) visit(j + 1, dx, d2);
-                word |= (ob ? 1u : 0u) << ((k + 1u) & 31u);
+                rec = (rec << 2) | (oa ? 2u : 0u) | (ob ? 1u : 0u);
             }
             if (j < jb) {
                 const VecN<T, PITCH> xa = load_row<T, PITCH, OFF32>(xs, j);
                 T dx[D], d2;
                 const bool oa = pair_test<T, D, SHIFT>(xa.v, xi, sh, r2, dx, &d2);
                 if (oa) visit(j, dx, d2);
-                word |= (oa ? 1u : 0u) << (k & 31u);
+                rec = (rec << 1) | (oa ? 1u : 0u);
             }
         };
-        for_each_row<T, D>(P, off, n, xi, [&](int row, const RowPieces<T>& rp) {
-            uint32_t mlo = 0, mhi = 0, spill = 0;
-            uint32_t pos = 0;  // row position of the piece's first candidate
-            for (int p = 0; p < rp.np; ++p) {
-                const T sh[3] = {rp.sx[p], rp.sy, rp.sz};
+        uint64_t rec = 0;  // the current row's bits, most recent lowest
+        uint32_t pos = 0;  // candidates of the current row so far
+        for_each_piece<T, D>(
+            P, off, n, xi,
+            [&](int) {
+                rec = 0;
+                pos = 0;
+            },
+            [&](uint32_t j0, uint32_t j1, const T* sh) {
                 bool lane_shift = false;
 #pragma unroll
                 for (int k = 0; k < D; ++k) lane_shift |= sh[k] != T(0);
-                const uint32_t j0 = rp.j0[p], j1 = max(rp.j1[p], rp.j0[p]);
-                // the piece split where its row positions reach 32 and 64
-                const uint32_t s32 = pos >= 32u ? j0 : min(j1, j0 + (32u - pos));
-                const uint32_t s64 = pos >= 64u ? j0 : min(j1, j0 + (64u - pos));
-                auto parts = [&](auto tag) {
-                    scan_part(tag, j0, s32, pos, sh, mlo);
-                    scan_part(tag, s32, s64, pos + (s32 - j0), sh, mhi);
-                    scan_part(tag, s64, j1, 0u, sh, spill);
-                };
-                if (__ballot(lane_shift) != 0ull) parts(std::integral_constant<bool, true>());
-                else parts(std::integral_constant<bool, false>());
+                j1 = max(j1, j0);
+                if (__ballot(lane_shift) != 0ull) scan(std::integral_constant<bool, true>(), j0, j1, sh, rec);
+                else scan(std::integral_constant<bool, false>(), j0, j1, sh, rec);
                 pos += j1 - j0;
-            }
-            overflow |= pos > (uint32_t)kMaskBits;
-            masks[(size_t)(2 * row) * n + s] = mlo;
-            masks[(size_t)(2 * row + 1) * n + s] = mhi;
-        });
+            },
+            [&](int row) {
+                overflow |= pos > (uint32_t)kMaskBits;
+                // c <= 64 bits shifted in put row position k at bit c - 1 - k;
+                // reversed and shifted down by 64 - c it lands at bit k
+                const uint32_t c = min(pos, (uint32_t)kMaskBits);
+                const uint64_t rev = ((uint64_t)__builtin_bitreverse32((uint32_t)rec) << 32) |
+                                     __builtin_bitreverse32((uint32_t)(rec >> 32));
+                const uint64_t m = c == 0u ? 0ull : rev >> (64u - c);
+                masks[(size_t)(2 * row) * n + s] = (uint32_t)m;
+                masks[(size_t)(2 * row + 1) * n + s] = (uint32_t)(m >> 32);
+            });
         status[s] = overflow ? 0u : gen[0];
         const uint32_t o = perm[s];
 #pragma unroll
@@ -188,14 +179,17 @@ __global__ __launch_bounds__(256) void k_lane_mask(const T* __restrict__ xs, con
             Op::bwd(q, r, dx, d2, ai, aj, gyi, gyj, accx, acca);
         };
         if (status[s] == gen[0]) {
-            for_each_row<T, D>(P, off, n, xi, [&](int row, const RowPieces<T>& rp) {
-                const uint64_t m = (uint64_t)masks[(size_t)(2 * row) * n + s] |
-                                   ((uint64_t)masks[(size_t)(2 * row + 1) * n + s] << 32);
-                uint32_t pos = 0;
-                for (int p = 0; p < rp.np; ++p) {
-                    const T sh[3] = {rp.sx[p], rp.sy, rp.sz};
-                    const uint32_t j0 = rp.j0[p];
-                    const uint32_t len = rp.j1[p] > j0 ? rp.j1[p] - j0 : 0u;
+            uint64_t m = 0;    // the current row's record
+            uint32_t pos = 0;  // row position of the next piece's first candidate
+            for_each_piece<T, D>(
+                P, off, n, xi,
+                [&](int row) {
+                    m = (uint64_t)masks[(size_t)(2 * row) * n + s] |
+                        ((uint64_t)masks[(size_t)(2 * row + 1) * n + s] << 32);
+                    pos = 0;
+                },
+                [&](uint32_t j0, uint32_t j1, const T* sh) {
+                    const uint32_t len = j1 > j0 ? j1 - j0 : 0u;
                     uint64_t bits = pos < 64u ? m >> pos : 0ull;
                     if (len < 64u) bits &= (1ull << len) - 1ull;
                     pos += len;
@@ -213,13 +207,15 @@ __global__ __launch_bounds__(256) void k_lane_mask(const T* __restrict__ xs, con
                         T dx[D], d2;
                         (void)pair_test<T, D, true>(xa.v, xi, sh, r2, dx, &d2);
                         pair(ja, dx, d2, ga_.v);
+                        keep_issued<D>(xb.v);
+                        keep_issued<NY>(gb_.v);
                         if (vb) {
                             (void)pair_test<T, D, true>(xb.v, xi, sh, r2, dx, &d2);
                             pair(jb, dx, d2, gb_.v);
                         }
                     }
-                }
-            });
+                },
+                [&](int) {});
         } else {
             auto visit = [&](uint32_t j, const T* dx, T d2, bool, const T* gyj) { pair(j, dx, d2, gyj); };
             neighbour_loop_aux<T, D, OFF32, NY>(P, xs, gy_s, off, n, xi, visit);
