@@ -36,14 +36,17 @@ HBM_PEAK_GBS = 8000.0
 # lane per clock; packed fp32 is not used), in 10^12 lane-operations per second
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
-# algorithmic VALU lane-operations: per candidate of the 3^d box search
-# (3 sub, 1 mul, 2 fma, 1 compare), per replayed pair its displacement and
-# squared distance (3 sub, 1 mul, 2 fma), and per accepted pair the summand
-# (spring forward: rsqrt, 1 fma for g, 3 fma; spring adjoint: rsqrt, 3 sub,
-# 3 fma for w.dx, 2 mul for 1/s^3, 1 fma for g, 2 mul for g'/s and h, 6 fma)
+# algorithmic VALU lane-operations, transcendental instructions (exp2, sqrt,
+# rsqrt) not counted: they issue to their own unit alongside the plain VALU work
+# (the dense multiquadric ran at 102 % of the issue rate with its reciprocal
+# square root counted).  Per candidate of the 3^d box search (3 sub, 1 mul,
+# 2 fma, 1 compare), per replayed pair its displacement and squared distance
+# (3 sub, 1 mul, 2 fma), and per accepted pair the summand (spring forward:
+# 1 fma for g, 3 fma; spring adjoint: 3 sub, 3 fma for w.dx, 2 mul for 1/s^3,
+# 1 fma for g, 2 mul for g'/s and h, 6 fma)
 OPS_PER_CANDIDATE = 7
 OPS_PER_REPLAYED_PAIR = 6
-OPS_PER_PAIR = {"fwd": 5, "bwd": 18}
+OPS_PER_PAIR = {"fwd": 4, "bwd": 17}
 
 METRIC = "pair interactions/s (fwd and fwd+bwd) at stated tol; % HBM roofline"
 
@@ -417,9 +420,9 @@ def main():
         yd = torch.empty(xd.shape[0], device=dev)
         t_dense = timed(lambda: A.dense_sum(ctx, xd_t, xd_t, wd_t, sigma, y=yd), reps=10)
         npair = float(xd.shape[0]) ** 2
-        # per pair: 2 sub, 1 mul, 1 fma, 1 exp2, 1 fma
+        # per pair: 2 sub, 1 mul, 1 fma, 1 fma (and the exp2)
         extra["dense_gaussian_n65536"] = {"ms": t_dense, "pairs_per_s": npair / (t_dense * 1e-3),
-                                          "valu_frac": npair * 6 / (t_dense * 1e-3) / 1e12 / VALU_PEAK_TOPS}
+                                          "valu_frac": npair * 5 / (t_dense * 1e-3) / 1e12 / VALU_PEAK_TOPS}
         # its adjoint with targets = sources: K^T gy plus the target and source position gradients
         gyd = torch.from_numpy(syn.SplitMix64(12).normal(xd.shape[0]).astype(np.float32)).to(dev)
         t_dense_b = timed(lambda: A.dense_sum_backward(ctx, xd_t, xd_t, wd_t, sigma, gyd), reps=5)
@@ -427,10 +430,10 @@ def main():
         extra["dense_gaussian_n65536_adjoint"] = {"ms": t_dense_b, "pair_passes": 2,
                                                   "pairs_per_s": 2 * npair / (t_dense_b * 1e-3)}
         # the multiquadric basis of the RBF example, c = 0.1 (per pair: 2 sub, mul, fma, add of c^2,
-        # rsqrt, mul, fma)
+        # fma, and the sqrt)
         t_mq = timed(lambda: A.dense_sum(ctx, xd_t, xd_t, wd_t, 0.1, y=yd, kernel="multiquadric"), reps=10)
         extra["dense_multiquadric_n65536"] = {"ms": t_mq, "pairs_per_s": npair / (t_mq * 1e-3),
-                                              "valu_frac": npair * 8 / (t_mq * 1e-3) / 1e12 / VALU_PEAK_TOPS}
+                                              "valu_frac": npair * 6 / (t_mq * 1e-3) / 1e12 / VALU_PEAK_TOPS}
         del xd_t, wd_t, yd, gyd
         # soft sphere N = 2^18 forward + adjoint (energy gradient)
         w4 = syn.soft_sphere_cube()
@@ -459,9 +462,17 @@ def main():
             A.build_cells(ctx, x4, [box4], cells=c4)
             A.pair_sum_and_backward(ctx, c4, "soft_sphere", (), g4, y=e4, gx=gx4)
 
+        def step4_masks():
+            A.build_cells(ctx, x4, [box4], cells=c4)
+            ctx.set_variant(mask_variant)
+            A.pair_sum(ctx, c4, "soft_sphere", (), y=e4)
+            A.pair_sum_backward(ctx, c4, "soft_sphere", (), g4, gx=gx4)
+            ctx.set_variant(-1)
+
         # energy and its gradient: gy = 1 is known before the forward, so the fused form applies
         t4 = {"box_search": timed_graph(lambda: step4(False), reps=10),
               "neighbour_list": timed_graph(lambda: step4(True), reps=10),
+              "recorded_masks": timed_graph(step4_masks, reps=10),
               "fused_energy_and_gradient": timed_graph(step4_fused, reps=10)}
         m4 = min(t4.values())
         extra["soft_sphere_n262144_fwd_bwd"] = {"ms": m4, "pairs": p4, "pairs_per_s": p4 / (m4 * 1e-3),
@@ -494,8 +505,19 @@ def main():
             A.pair_sum_backward(ctx, c5, "soft_sphere", (), g5, gx=gx5)
             ctx.set_variant(-1)
 
+        def step5_masks():
+            # the spring forward records the pairs; the soft-sphere adjoint replays them
+            # (the pair set depends on positions and cutoffs only)
+            A.build_cells(ctx, x5, boxes5, off5, cells=c5)
+            ctx.set_variant(mask_variant)
+            A.pair_sum(ctx, c5, "spring", (1.0,), y=y5)
+            A.pair_sum_backward(ctx, c5, "soft_sphere", (), g5, gx=gx5)
+            ctx.set_variant(-1)
+
         t5 = {"box_search": timed_graph(lambda: step5(False), reps=10),
               "neighbour_list": timed_graph(lambda: step5(True), reps=10)}
+        if max(b.reach or 1 for b in boxes5) == 1:  # the mask record covers the reach-1 stencil
+            t5["recorded_masks"] = timed_graph(step5_masks, reps=10)
         m5 = min(t5.values())
         ctx.sync()
         # the same systems' single-system rate reference: the headline cube's step rate

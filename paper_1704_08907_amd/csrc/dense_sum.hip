@@ -31,20 +31,22 @@ __device__ __forceinline__ float kexp(float a) { return __builtin_amdgcn_exp2f(-
 __device__ __forceinline__ double kexp(double a) { return ::exp(-a); }
 __device__ __forceinline__ float kfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double kfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float ksqrt(float a) { return __builtin_amdgcn_sqrtf(a); }
+__device__ __forceinline__ double ksqrt(double a) { return ::sqrt(a); }
 __device__ __forceinline__ float krsqrt(float a) { return __builtin_amdgcn_rsqf(a); }
 __device__ __forceinline__ double krsqrt(double a) { return ::rsqrt(a); }
 
 // phi of the kernel on its working coordinates (value) and the factor of the
 // gradient summand w_j * slope * (a - b) (the constant 2 phi' / slope is
 // applied by the reduction): Gaussian value = slope = exp(-q') on coordinates
-// scaled by sqrt(c); multiquadric slope = 1/sqrt(q + c^2) and value = (q + c^2)
-// * slope, so that a pass needing both takes one reciprocal square root and its
-// value is bit for bit the forward's.
+// scaled by sqrt(c); multiquadric value = sqrt(q + c^2) and slope =
+// 1/sqrt(q + c^2), each one transcendental instruction, so a pass needing both
+// computes the value exactly as the forward does.
 template <typename T, int KERN>
 struct Radial {
     __device__ __forceinline__ static T value(T q, T c2) {
         if constexpr (KERN == ABORIA_K_GAUSSIAN) return kexp(q);
-        else return (q + c2) * krsqrt(q + c2);
+        else return ksqrt(q + c2);
     }
     __device__ __forceinline__ static T slope(T q, T c2) {
         if constexpr (KERN == ABORIA_K_GAUSSIAN) return kexp(q);
@@ -121,10 +123,9 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense(const T* __restrict__ xt,
                     constexpr int G = MODE == kSumGrad ? 1 : 0;  // first gradient component
                     T slope;
                     if constexpr (MODE == kSumGrad && KERN == ABORIA_K_MULTIQUADRIC) {
-                        // value and slope from one reciprocal square root: sqrt(a) = a / sqrt(a)
                         const T a = d2 + c2;
                         slope = krsqrt(a);
-                        part[q][0] = kfma(a * slope, p.v[3], part[q][0]);
+                        part[q][0] = kfma(ksqrt(a), p.v[3], part[q][0]);
                     } else {
                         slope = Radial<T, KERN>::slope(d2, c2);
                         if constexpr (MODE == kSumGrad)  // the Gaussian's value is its slope

@@ -97,6 +97,28 @@ def test_without_and_after_a_stale_record(ctx):
     assert torch.equal(g1[0], r1[0])
 
 
+def test_record_serves_another_operator(ctx):
+    # the pair set depends on positions and cutoff only, so one forward's record
+    # serves the adjoint of any operator on the same build
+    w = syn.spring_cube(n=60000)
+    s = w.systems[0]
+    cells = A.build_cells(ctx, to_dev(s.x), [box_of(s)])
+    n = s.n
+    rng = syn.SplitMix64(77)
+    a_d = to_dev((0.2 + 0.3 * rng.uniform(n)).astype(np.float32).reshape(n, 1))
+    fwd(ctx, cells, "spring", (1.0,), None, variant(MASK))  # records
+    for op, params in OPS:
+        if op == "spring":
+            continue
+        gy_d = to_dev(rng.normal(n * A.op_ny(op, 3)).astype(np.float32).reshape(n, -1))
+        aa = a_d if op == "dem_spring" else None
+        g = bwd(ctx, cells, op, params, gy_d, aa, variant(MASK))
+        g_ref = bwd(ctx, cells, op, params, gy_d, aa, variant(PLAIN))
+        ctx.sync()
+        for u, v in zip(g, g_ref):
+            assert same(u, v), op
+
+
 def test_overflowing_rows_fall_back(ctx):
     # a coarse explicit grid packs ~50 candidates per cell, so rows of three cells hold
     # more than 64 candidates and those particles keep no record
