@@ -48,10 +48,14 @@ __device__ __forceinline__ void for_each_piece(const SysParams<T>& P, const uint
         else if (c[0] + 1 >= nx) { a1 = 0; b1 = 0; s1 = P.L[0]; }
     }
     const int32_t zr = D >= 3 ? 1 : 0, yr = D >= 2 ? 1 : 0;
+    // the row and offset loops stay rolled: unrolled, the compiler hoists work
+    // across rows and the kernels hold 8 to 9 more registers per lane
+#pragma unroll 1
     for (int32_t dz = -zr; dz <= zr; ++dz) {
         int32_t cz = 0;
         T sz = T(0);
         if (D >= 3 && !wrap_cell(c[2] + dz, P.n[2], P.periodic[2], P.L[2], &cz, &sz)) continue;
+#pragma unroll 1
         for (int32_t dy = -yr; dy <= yr; ++dy) {
             int32_t cy = 0;
             T sy = T(0);
@@ -68,6 +72,7 @@ __device__ __forceinline__ void for_each_piece(const SysParams<T>& P, const uint
                     run(rowbase + a1, rowbase + b1);
                 }
             } else {
+#pragma unroll 1
                 for (int32_t o = -1; o <= 1; ++o) {
                     int32_t cx;
                     if (!wrap_cell(c[0] + o, nx, P.periodic[0], P.L[0], &cx, &sh[0])) continue;
