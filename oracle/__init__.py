@@ -44,7 +44,7 @@ class Grid(C.Structure):
     _fields_ = [("d", C.c_int32), ("dtype", C.c_int32), ("periodic", C.c_int32 * 3),
                 ("n", C.c_int32 * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
                 ("L", C.c_double * 3), ("inv_w", C.c_double * 3), ("r", C.c_double),
-                ("r2", C.c_double), ("ncells", C.c_int64), ("reach", C.c_int32), ("pad", C.c_int32)]
+                ("r2", C.c_double), ("ncells", C.c_int64), ("reach", C.c_int32 * 3), ("pad", C.c_int32)]
 
     @property
     def ncell(self):
@@ -61,7 +61,7 @@ def lib():
             build()
         L = C.CDLL(LIB)
         P = C.c_void_p
-        L.or_grid_init.argtypes = [C.POINTER(Grid), C.c_int32, C.c_int32, P, P, P, C.c_double, P, C.c_int32]
+        L.or_grid_init.argtypes = [C.POINTER(Grid), C.c_int32, C.c_int32, P, P, P, C.c_double, P, P]
         L.or_cell_ids.argtypes = [C.POINTER(Grid), C.c_int64, P, P]
         L.or_sort_cells.argtypes = [C.POINTER(Grid), C.c_int64, P, P, P]
         L.or_pairs.argtypes = [C.POINTER(Grid), C.c_int32, C.c_int64, P, C.c_int64, P, P]
@@ -96,7 +96,7 @@ def _f64(a):
 
 def grid(d, lo, hi, periodic, cutoff, precision="f64", ncell=None, reach=1) -> Grid:
     """The cell grid of a box (cell count rule R1 for search reach m = reach,
-    P-rounded box, 1/w)."""
+    one value for every dimension or one per dimension; P-rounded box, 1/w)."""
     g = Grid()
     lo_a = np.zeros(3); lo_a[:d] = lo
     hi_a = np.ones(3); hi_a[:d] = hi
@@ -104,8 +104,10 @@ def grid(d, lo, hi, periodic, cutoff, precision="f64", ncell=None, reach=1) -> G
     nreq = np.zeros(3, dtype=np.int32)
     if ncell is not None:
         nreq[:d] = ncell
+    m = np.ones(3, dtype=np.int32)
+    m[:d] = reach
     st = lib().or_grid_init(C.byref(g), d, F32 if precision == "f32" else F64, _ptr(lo_a),
-                            _ptr(hi_a), _ptr(per), float(cutoff), _ptr(nreq), int(reach))
+                            _ptr(hi_a), _ptr(per), float(cutoff), _ptr(nreq), _ptr(m))
     if st != OK:
         raise OracleError(st, "grid")
     return g

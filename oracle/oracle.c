@@ -38,9 +38,10 @@
  *   R1 cell count per dimension: n = floor(m L/r), then decreased while n > 1
  *      and L/n < (r + 16 u (|lo| + L)) / m, u the unit roundoff of the input
  *      precision, so that rounding in the cell assignment can never put the two
- *      points of a pair more than m cells apart.  m >= 1 is the search reach;
- *      m = 1 is the paper's lattice (cells at least one cutoff wide, searched
- *      with the adjacent cells).  An explicit count may not exceed this n.
+ *      points of a pair more than m cells apart.  m >= 1 is the search reach,
+ *      given per dimension; m = 1 is the paper's lattice (cells at least one
+ *      cutoff wide, searched with the adjacent cells).  An explicit count may
+ *      not exceed this n.
  *   R2 cell of a coordinate: clamp(floor(fl(fl(x - lo) * fl(n / L))), 0, n-1);
  *      linear id = c0 + n0 (c1 + n1 c2); x == hi, x < lo or NaN is a domain
  *      error.
@@ -105,7 +106,7 @@ typedef struct or_grid {
     double r;
     double r2;
     int64_t ncells;
-    int32_t reach; /* m of reading R1: cells searched on each side */
+    int32_t reach[3]; /* m of reading R1 per dimension: cells searched on each side */
     int32_t pad;
 } or_grid;
 
@@ -119,12 +120,15 @@ static double unit_roundoff(int dtype) { return dtype == OR_F32 ? ldexp(1.0, -24
 /* ------------------------------------------------------------------------ */
 
 int or_grid_init(or_grid* g, int32_t d, int32_t dtype, const double* lo, const double* hi,
-                 const int32_t* periodic, double r, const int32_t* ncell_req, int32_t reach) {
+                 const int32_t* periodic, double r, const int32_t* ncell_req, const int32_t* reach) {
     memset(g, 0, sizeof(*g));
     if (d < 1 || d > 3 || (dtype != OR_F32 && dtype != OR_F64)) return OR_ERR_INVALID;
-    if (reach == 0) reach = 1;
-    if (reach < 1 || reach > 16) return OR_ERR_INVALID;
-    g->reach = reach;
+    for (int k = 0; k < 3; ++k) {
+        int32_t m = (reach && k < d) ? reach[k] : 1;
+        if (m == 0) m = 1;
+        if (m < 1 || m > 16) return OR_ERR_INVALID;
+        g->reach[k] = m;
+    }
     g->d = d;
     g->dtype = dtype;
     g->r = to_p(dtype, r);
@@ -151,9 +155,9 @@ int or_grid_init(or_grid* g, int32_t d, int32_t dtype, const double* lo, const d
         else
             g->L[k] = g->hi[k] - g->lo[k];
         double guard = g->r + 16.0 * u * (fabs(g->lo[k]) + g->L[k]);
-        double q = floor((double)reach * g->L[k] / g->r);
+        double q = floor((double)g->reach[k] * g->L[k] / g->r);
         int64_t nmax = q < 1.0 ? 1 : (q > 2147483647.0 ? 2147483647 : (int64_t)q);
-        while (nmax > 1 && g->L[k] / (double)nmax < guard / (double)reach) --nmax;
+        while (nmax > 1 && g->L[k] / (double)nmax < guard / (double)g->reach[k]) --nmax;
         int64_t nk = nmax;
         if (ncell_req && ncell_req[k] > 0) {
             if (ncell_req[k] > nmax) return OR_ERR_INVALID; /* cells narrower than the guard */
@@ -307,8 +311,9 @@ static void free_linked(linked_cells* lc) {
     free(lc->next);
 }
 
-/* Box search for point i: its cell and every cell up to m = reach cells away
- * in each dimension ((2m+1)^d offsets; m = 1 is the paper's 3^d stencil).  A
+/* Box search for point i: its cell and every cell up to m_k = reach[k] cells
+ * away in dimension k (prod_k (2 m_k + 1) offsets; m = 1 in every dimension is
+ * the paper's 3^d stencil).  A
  * periodic dimension wraps, and the wrap becomes the image shift of the
  * neighbour cell; a non-periodic dimension drops offsets outside the grid.  An
  * offset that would need a second wrap is dropped too: that image lies at
@@ -318,15 +323,15 @@ static void visit_cells(const or_grid* g, const linked_cells* lc, const double* 
     int bad = 0;
     int32_t c[3] = {0, 0, 0};
     for (int k = 0; k < g->d; ++k) c[k] = cell_coord(g, k, x[i * g->d + k], &bad);
-    const int side = 2 * g->reach + 1;
     int nstencil = 1;
-    for (int k = 0; k < g->d; ++k) nstencil *= side;
+    for (int k = 0; k < g->d; ++k) nstencil *= 2 * g->reach[k] + 1;
     for (int m = 0; m < nstencil; ++m) {
         int32_t cn[3] = {0, 0, 0};
         double s[3] = {0.0, 0.0, 0.0};
         int rest = m, skip = 0;
         for (int k = 0; k < g->d; ++k) {
-            int o = rest % side - g->reach;
+            const int side = 2 * g->reach[k] + 1;
+            int o = rest % side - g->reach[k];
             rest /= side;
             int32_t v = c[k] + o;
             if (v < 0) {

@@ -92,6 +92,14 @@ def test_grid_rule_reach():
     for bad in (-1, 17):
         with pytest.raises(oracle.OracleError):
             oracle.grid(2, [0, 0], [1, 1], [1, 1], 0.1, "f64", reach=bad)
+    # a reach per dimension: the rule applies dimension by dimension
+    assert oracle.grid(2, [0, 0], [1, 1], [1, 1], 0.1, "f64", reach=[2, 1]).ncell == [19, 9]
+    assert oracle.grid(2, [0, 0], [1, 1], [1, 1], 0.1, "f64", reach=[0, 3]).ncell == [9, 29]
+    assert oracle.grid(3, [0] * 3, [L] * 3, [1] * 3, 1.0, "f32", reach=[2, 1, 1]).ncell == [105, 52, 52]
+    assert oracle.grid(3, [0] * 3, [L] * 3, [1] * 3, 1.0, "f32", reach=[3, 1, 1]).ncell == [158, 52, 52]
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.grid(2, [0, 0], [1, 1], [1, 1], 0.1, "f64", ncell=[19, 10], reach=[2, 1])
+    assert e.value.code == oracle.ERR_INVALID
 
 
 def test_grid_rule_cube_and_limits():
@@ -197,8 +205,20 @@ NARROW = [
 ]
 
 
+# a reach per dimension (truncated to the case's d): finer cells along some
+# dimensions only, the others searched one cell deep
+ANISO = [(2, 1, 1), (3, 1, 1), (1, 3, 2)]
+NARROW_ANISO = [
+    # fewer than 2m+1 cells along the deep dimension
+    ((2, [2.1, 2.6], [1, 1], 1.0, "f32", [3, 2]), [2, 1]),
+    ((3, [2.2, 2.3, 2.4], [1, 0, 1], 1.0, "f32", [4, 2, 2]), [2, 1, 1]),
+    ((3, [2.2, 2.3, 2.4], [1, 1, 1], 1.0, "f64", [6, 2, 2]), [3, 1, 1]),
+]
+
+
 @pytest.mark.parametrize("case,reach", [(c, m) for m in (1, 2, 3) for c in CASES]
-                         + [(c, m) for m in (2, 3) for c in NARROW])
+                         + [(c, m) for m in (2, 3) for c in NARROW]
+                         + [(c, list(m[:c[0]])) for m in ANISO for c in CASES if c[0] > 1] + NARROW_ANISO)
 def test_brute_force_equals_cell_list(case, reach):
     d, hi, per, r, prec, ncell = case
     g = oracle.grid(d, [0.0] * d, hi, per, r, prec, ncell, reach)
