@@ -107,16 +107,18 @@ def profile_names(variant_name, direction):
     return k if direction == "fwd" else ["k_gather_rows<float, 3, 4>"] + k
 
 
-def candidate_count(cells) -> int:
-    """Candidates the 3^3 box search tests: sum over cells of count(c) * count(3^3 around c)."""
+def candidate_count(cells, reach) -> int:
+    """Candidates the box search of a periodic 3-d grid tests: sum over cells of
+    count(c) * count(the cells up to reach[k] away in each dimension k around c)."""
     v = cells.view()
     off = hip_download(v.cell_offsets, int(v.ncells) + 1, np.uint32).astype(np.int64)
     n = [v.ncell_host[k] for k in range(3)]
     cnt = np.diff(off).reshape(n[2], n[1], n[0])
     s = np.zeros_like(cnt)
-    for dz in (-1, 0, 1):
-        for dy in (-1, 0, 1):
-            for dx in (-1, 0, 1):
+    mx, my, mz = reach
+    for dz in range(-mz, mz + 1):
+        for dy in range(-my, my + 1):
+            for dx in range(-mx, mx + 1):
                 s += np.roll(cnt, (dz, dy, dx), axis=(0, 1, 2))
     return int((cnt * s).sum())
 
@@ -128,6 +130,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary workloads")
+    ap.add_argument("--reach", default="3,1,1",
+                    help="search reach per dimension of the headline cell grid (x,y,z)")
+    ap.add_argument("--no-reach-trials", action="store_true",
+                    help="set up only the --reach grid (no trials at other reaches, no per-variant table)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 256 MiB device copy (known bytes) to calibrate HBM counters")
     args = ap.parse_args()
@@ -155,42 +161,14 @@ def main():
     # ---------------- headline workload: spring cube, build + fwd + bwd ----------------
     w = syn.spring_cube()
     s = w.systems[0]
-    box = A.BoxSpec(3, s.lo, s.hi, s.periodic, s.cutoff)
     x = torch.from_numpy(s.x).to(dev)
     gy = torch.from_numpy(w.extra["gy"]).to(dev)
     n = s.n
-    cells = A.build_cells(ctx, x, [box])
     y = torch.empty((n, 3), device=dev)
     gx = torch.empty((n, 3), device=dev)
-    cnt = A.pair_sum(ctx, cells, "count", ())
-    ctx.sync()
-    pairs = int(cnt.sum().item())
-    cand = candidate_count(cells)
-    log("spring cube: n=%d pairs=%d candidates=%d (%.1f/particle)" % (n, pairs, cand, cand / n))
-
-    # box-search baseline: the autotuner's fastest mapping without a neighbour list
-    search_fwd = A.autotune(ctx, cells, "spring", (1.0,))
-    search_bwd = A.autotune(ctx, cells, "spring", (1.0,), gy=gy)
-    # record the neighbour lists; the tuner then also times their replay
-    cap = A.build_neighbours(ctx, cells)
-    variant_fwd = A.autotune(ctx, cells, "spring", (1.0,))
-    variant_bwd = A.autotune(ctx, cells, "spring", (1.0,), gy=gy)
-    log("autotuned variants: forward %d (%s), adjoint %d (%s); list capacity %d" % (
-        variant_fwd, A.variant_name(variant_fwd), variant_bwd, A.variant_name(variant_bwd), cap))
-
-    def step():
-        A.build_cells(ctx, x, [box], cells=cells)
-        A.build_neighbours(ctx, cells)
-        A.pair_sum(ctx, cells, "spring", (1.0,), y=y)
-        A.pair_sum_backward(ctx, cells, "spring", (1.0,), gy, gx=gx)
-
-    def step_search():
-        A.build_cells(ctx, x, [box], cells=cells)
-        ctx.set_variant(search_fwd)
-        A.pair_sum(ctx, cells, "spring", (1.0,), y=y)
-        ctx.set_variant(search_bwd)
-        A.pair_sum_backward(ctx, cells, "spring", (1.0,), gy, gx=gx)
-        ctx.set_variant(-1)
+    # box search whose forward records each stencil row's accepted candidates, which the
+    # adjoint replays instead of testing every candidate again
+    mask_variant = next(v for v in range(A.variant_count()) if "accepted-pair bit masks" in A.variant_name(v))
 
     def capture(fn):
         fn()
@@ -215,34 +193,89 @@ def main():
         ctx.sync()
         return (t1 - t0) * 1e3 / steps, e0.elapsed_time(e1) / steps
 
-    def step_fused():
-        A.build_cells(ctx, x, [box], cells=cells)
-        A.pair_sum_and_backward(ctx, cells, "spring", (1.0,), gy, y=y, gx=gx)
+    def setup(reach):
+        """Cells of the cube at a search reach per dimension, the tuned variants and the step forms."""
+        st = {"reach": reach}
+        box = A.BoxSpec(3, s.lo, s.hi, s.periodic, s.cutoff, None, reach)
+        cells = A.build_cells(ctx, x, [box])
+        st["box"], st["cells"] = box, cells
+        # box-search baseline: the autotuner's fastest mapping without a neighbour list
+        st["search_fwd"] = A.autotune(ctx, cells, "spring", (1.0,))
+        st["search_bwd"] = A.autotune(ctx, cells, "spring", (1.0,), gy=gy)
+        # record the neighbour lists; the tuner then also times their replay
+        st["cap"] = A.build_neighbours(ctx, cells)
+        st["variant_fwd"] = A.autotune(ctx, cells, "spring", (1.0,))
+        st["variant_bwd"] = A.autotune(ctx, cells, "spring", (1.0,), gy=gy)
 
-    # box search whose forward records each stencil row's accepted candidates, which the
-    # adjoint replays instead of testing every candidate again
-    mask_variant = next(v for v in range(A.variant_count()) if "accepted-pair bit masks" in A.variant_name(v))
+        def step():
+            A.build_cells(ctx, x, [box], cells=cells)
+            A.build_neighbours(ctx, cells)
+            A.pair_sum(ctx, cells, "spring", (1.0,), y=y)
+            A.pair_sum_backward(ctx, cells, "spring", (1.0,), gy, gx=gx)
 
-    def step_masks():
-        A.build_cells(ctx, x, [box], cells=cells)
-        ctx.set_variant(mask_variant)
-        A.pair_sum(ctx, cells, "spring", (1.0,), y=y)
-        A.pair_sum_backward(ctx, cells, "spring", (1.0,), gy, gx=gx)
-        ctx.set_variant(-1)
+        def step_search():
+            A.build_cells(ctx, x, [box], cells=cells)
+            ctx.set_variant(st["search_fwd"])
+            A.pair_sum(ctx, cells, "spring", (1.0,), y=y)
+            ctx.set_variant(st["search_bwd"])
+            A.pair_sum_backward(ctx, cells, "spring", (1.0,), gy, gx=gx)
+            ctx.set_variant(-1)
 
-    # both forms of the step are timed briefly; the faster one is the headline.  The fused
+        def step_masks():
+            A.build_cells(ctx, x, [box], cells=cells)
+            ctx.set_variant(mask_variant)
+            A.pair_sum(ctx, cells, "spring", (1.0,), y=y)
+            A.pair_sum_backward(ctx, cells, "spring", (1.0,), gy, gx=gx)
+            ctx.set_variant(-1)
+
+        def step_fused():
+            A.build_cells(ctx, x, [box], cells=cells)
+            A.pair_sum_and_backward(ctx, cells, "spring", (1.0,), gy, y=y, gx=gx)
+
+        st["forms"] = {"neighbour_list": step, "box_search": step_search, "recorded_masks": step_masks,
+                       "fused_gy_known": step_fused}
+        return st
+
+    # The step forms are timed briefly on the paper's lattice (reach 1: cells about r wide,
+    # searched one cell deep) and on grids with cells r/2 and r/3 wide along x only (the same
+    # nine rows, each shorter).  The headline grid is --reach (cells r/3 wide along x, the
+    # fastest of the three when measured), its fastest form the headline step.  The fused
     # form (forward and adjoint from one box search) needs gy before the forward, which a
     # training step does not have, so it is reported beside the headline, not as it.
+    head_reach = [int(v) for v in args.reach.split(",")]
+    head_tag = "".join(map(str, head_reach))
+    reaches = [head_reach] if args.no_reach_trials else \
+        [m for m in ([1, 1, 1], [2, 1, 1], [3, 1, 1]) if m != head_reach] + [head_reach]
     trial = {}
-    forms = {"neighbour_list": step, "box_search": step_search, "recorded_masks": step_masks,
-             "fused_gy_known": step_fused}
-    for name, fn in forms.items():
-        g = capture(fn)
-        trial[name] = max(run_graph(g, 2, max(5, args.steps // 5)))
-        g.close()
-    mode = min(("neighbour_list", "box_search", "recorded_masks"), key=trial.get)
-    log("step trials (ms): %s -> headline uses %s" % (json.dumps(trial), mode))
-    graph = capture(forms[mode])
+    setups = {}
+    for reach in reaches:
+        st = setup(reach)
+        tag = "".join(map(str, reach))
+        setups[tag] = st
+        for name, fn in st["forms"].items():
+            g = capture(fn)
+            trial["%s@%s" % (name, tag)] = max(run_graph(g, 2, max(5, args.steps // 5)))
+            g.close()
+    best = min((k for k in trial if not k.startswith("fused") and k.endswith("@" + head_tag)), key=trial.get)
+    mode, tag = best.split("@")
+    log("step trials (ms): %s -> headline uses %s" % (json.dumps(trial), best))
+    chosen = setups[tag]
+    reach, box, cells = chosen["reach"], chosen["box"], chosen["cells"]
+    search_fwd, search_bwd = chosen["search_fwd"], chosen["search_bwd"]
+    variant_fwd, variant_bwd, cap = chosen["variant_fwd"], chosen["variant_bwd"], chosen["cap"]
+    for k, st in setups.items():
+        if k not in (tag, "111"):
+            st["cells"].close()
+    cells1 = setups["111"]["cells"] if "111" in setups else None  # the per-variant table's lattice
+    cnt = A.pair_sum(ctx, cells, "count", ())
+    ctx.sync()
+    pairs = int(cnt.sum().item())
+    cand = candidate_count(cells, reach)
+    log("spring cube: n=%d pairs=%d candidates=%d (%.1f/particle) at reach %s; variants: forward %d (%s), "
+        "adjoint %d (%s); list capacity %d" % (n, pairs, cand, cand / n, reach, variant_fwd,
+                                               A.variant_name(variant_fwd), variant_bwd,
+                                               A.variant_name(variant_bwd), cap))
+    graph = capture(chosen["forms"][mode])
     wall_ms, ev_ms = run_graph(graph, args.warmup, args.steps)
     ms = max(wall_ms, ev_ms)
     value = pairs / (ms * 1e-3)
@@ -289,13 +322,17 @@ def main():
     t_fwd_mask = timed_graph(lambda: A.pair_sum(ctx, cells, "spring", (1.0,), y=y))
     t_bwd_mask = timed_graph(lambda: A.pair_sum_backward(ctx, cells, "spring", (1.0,), gy, gx=gx))
     ctx.set_variant(-1)
-    per_variant = {}
-    for v in range(A.variant_count()):
+    per_variant = {}  # on the paper's lattice (reach 1), where every variant applies
+    if cells1 is not None:
+        A.build_cells(ctx, x, [setups["111"]["box"]], cells=cells1)
+        A.build_neighbours(ctx, cells1)  # for the replayed-list variant
+    for v in range(A.variant_count() if cells1 is not None else 0):
         ctx.set_variant(v)
         try:
             per_variant[A.variant_name(v)] = {
-                "fwd_ms": timed_graph(lambda: A.pair_sum(ctx, cells, "spring", (1.0,), y=y), reps=5),
-                "bwd_ms": timed_graph(lambda: A.pair_sum_backward(ctx, cells, "spring", (1.0,), gy, gx=gx), reps=5)}
+                "fwd_ms": timed_graph(lambda: A.pair_sum(ctx, cells1, "spring", (1.0,), y=y), reps=5),
+                "bwd_ms": timed_graph(lambda: A.pair_sum_backward(ctx, cells1, "spring", (1.0,), gy, gx=gx),
+                                      reps=5)}
         except A.AboriaError as e:  # a variant whose requirements these cells do not meet
             per_variant[A.variant_name(v)] = {"not_applicable": str(e)}
     ctx.set_variant(-1)
@@ -374,10 +411,12 @@ def main():
     # the metric's two rates: forward (rebuild + forward) and forward + adjoint (the step), and the
     # step's algorithmic HBM bytes (build + both calls) against the HBM peak
     step_bytes = build_bytes + sum(v[3] for v in phases.values())
-    breakdown = {"step_form": mode, "step_trials_ms": trial,
+    t_fused = trial["fused_gy_known@" + head_tag]
+    breakdown = {"step_form": mode, "search_reach": reach, "ncell": [int(cells.view().ncell_host[k]) for k in range(3)],
+                 "step_trials_ms": trial,
                  "fwd_pairs_per_s": pairs / ((t_build + t_fwd) * 1e-3),
                  "fwd_bwd_pairs_per_s": value,
-                 "fused_gy_known_pairs_per_s": pairs / (trial["fused_gy_known"] * 1e-3),
+                 "fused_gy_known_pairs_per_s": pairs / (t_fused * 1e-3),
                  "step_hbm_frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                  "build_ms": t_build, "build_counting_ms": t_build_counting, "fwd_ms": t_fwd, "bwd_ms": t_bwd,
                  "box_search_fwd_ms": t_fwd_search, "box_search_bwd_ms": t_bwd_search,
@@ -462,18 +501,29 @@ def main():
             A.build_cells(ctx, x4, [box4], cells=c4)
             A.pair_sum_and_backward(ctx, c4, "soft_sphere", (), g4, y=e4, gx=gx4)
 
-        def step4_masks():
-            A.build_cells(ctx, x4, [box4], cells=c4)
+        def step4_masks(bx, cc):
+            A.build_cells(ctx, x4, [bx], cells=cc)
             ctx.set_variant(mask_variant)
-            A.pair_sum(ctx, c4, "soft_sphere", (), y=e4)
-            A.pair_sum_backward(ctx, c4, "soft_sphere", (), g4, gx=gx4)
+            A.pair_sum(ctx, cc, "soft_sphere", (), y=e4)
+            A.pair_sum_backward(ctx, cc, "soft_sphere", (), g4, gx=gx4)
             ctx.set_variant(-1)
+
+        # the same on cells r/3 wide along x (nine shorter rows)
+        box4x = A.BoxSpec(3, s4.lo, s4.hi, s4.periodic, s4.cutoff, None, [3, 1, 1])
+        c4x = A.build_cells(ctx, x4, [box4x])
+
+        def step4_fused_x():
+            A.build_cells(ctx, x4, [box4x], cells=c4x)
+            A.pair_sum_and_backward(ctx, c4x, "soft_sphere", (), g4, y=e4, gx=gx4)
 
         # energy and its gradient: gy = 1 is known before the forward, so the fused form applies
         t4 = {"box_search": timed_graph(lambda: step4(False), reps=10),
               "neighbour_list": timed_graph(lambda: step4(True), reps=10),
-              "recorded_masks": timed_graph(step4_masks, reps=10),
-              "fused_energy_and_gradient": timed_graph(step4_fused, reps=10)}
+              "recorded_masks": timed_graph(lambda: step4_masks(box4, c4), reps=10),
+              "recorded_masks_reach_311": timed_graph(lambda: step4_masks(box4x, c4x), reps=10),
+              "fused_energy_and_gradient": timed_graph(step4_fused, reps=10),
+              "fused_energy_and_gradient_reach_311": timed_graph(step4_fused_x, reps=10)}
+        c4x.close()
         m4 = min(t4.values())
         extra["soft_sphere_n262144_fwd_bwd"] = {"ms": m4, "pairs": p4, "pairs_per_s": p4 / (m4 * 1e-3),
                                                 "step_forms_ms": t4}
@@ -516,7 +566,7 @@ def main():
 
         t5 = {"box_search": timed_graph(lambda: step5(False), reps=10),
               "neighbour_list": timed_graph(lambda: step5(True), reps=10)}
-        if max(b.reach or 1 for b in boxes5) == 1:  # the mask record covers the reach-1 stencil
+        if all(m <= 1 for b in boxes5 for m in b.reach_list()[1:]):  # the record covers 3^(d-1) rows
             t5["recorded_masks"] = timed_graph(step5_masks, reps=10)
         m5 = min(t5.values())
         ctx.sync()
@@ -605,6 +655,7 @@ def main():
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": w.name, "n": n, "box_side": float(s.hi[0]), "cutoff": 1.0,
                       "pairs_per_step": pairs,
+                      "search_reach": reach,
                       "step": {"neighbour_list": "cell rebuild + neighbour-list recording + spring forward + "
                                                  "adjoint (replayed), one hipGraph",
                                "recorded_masks": "cell rebuild + spring forward (box search, recording each "

@@ -83,13 +83,15 @@ typedef enum aboria_kernel {
  * init_neighbour_search(lo, hi, width, periodic) call of Section 3).  Entries
  * beyond d are ignored.
  *
- * reach m (1..3; 0 = 1) is how many cells the box search looks on each side of
- * a particle's own cell.  m = 1 is the paper's lattice: cells at least one
- * cutoff wide, searched with the adjacent cells (Section 2.2.2).  m = 2 or 3
- * uses cells about r/m wide searched m cells deep, which tests fewer
- * candidates; the pair set is the same, since the pair predicate alone
- * decides it.  The cell-group, LDS-list, wave-queue, LDS-staged and
- * recorded-mask variants need m = 1.
+ * reach[k] = m (1..3; 0 = 1) is how many cells the box search looks on each
+ * side of a particle's own cell in dimension k.  m = 1 is the paper's lattice:
+ * cells at least one cutoff wide, searched with the adjacent cells (Section
+ * 2.2.2).  m = 2 or 3 uses cells about r/m wide searched m cells deep, which
+ * tests fewer candidates; the pair set is the same, since the pair predicate
+ * alone decides it.  A deeper reach along x only (e.g. {2, 1, 1}) keeps the
+ * 3^(d-1) rows of the search and shortens each.  The cell-group, LDS-list,
+ * wave-queue and LDS-staged variants need m = 1 in every dimension; the
+ * recorded-mask variant needs it in every dimension but x.
  *
  * ncell[k] = 0 picks the cell count automatically: the largest count whose
  * cells are at least (cutoff + a rounding guard) / m wide.  An explicit count
@@ -98,7 +100,7 @@ typedef struct aboria_box {
     int32_t d;           /* 1, 2 or 3                                  */
     int32_t periodic[3]; /* nonzero = periodic in that dimension       */
     int32_t ncell[3];    /* 0 = automatic                              */
-    int32_t reach;       /* search reach m, 0 = 1                      */
+    int32_t reach[3];    /* search reach m per dimension, 0 = 1        */
     double lo[3];
     double hi[3];
     double cutoff;       /* r > 0                                      */
@@ -328,8 +330,9 @@ aboria_status aboria_autotune(aboria_ctx* ctx, const aboria_cells* cells, aboria
 
 /* Cell-size tuning: times a rebuild plus aboria_pair_sum (and, when gy is given,
  * aboria_pair_sum_backward for that upstream gradient) of op on grids of each
- * search reach (the boxes' reach when boxes_host[0].reach is set, else 1, 2
- * and 3, skipping a reach that the boxes' explicit counts do not allow) whose
+ * search reach (the boxes' reach when any entry of boxes_host[0].reach is set,
+ * else 1, 2 and 3 in every dimension and, for d >= 2, {2, 1, 1} and {3, 1, 1},
+ * skipping a reach that the boxes' explicit counts do not allow) whose
  * per-dimension cell counts are that reach's automatic ones (or the boxes'
  * explicit ones) scaled by 1, 0.85, 0.7 and 0.55 (rounded down, at least 1;
  * coarser cells are always valid, finer ones are not), each with its work

@@ -11,7 +11,7 @@ from __future__ import annotations
 import ctypes as C
 import os
 from dataclasses import dataclass, field
-from typing import Optional, Sequence
+from typing import Optional, Sequence, Union
 
 import torch
 
@@ -33,7 +33,7 @@ class AboriaError(RuntimeError):
 
 class Box(C.Structure):
     _fields_ = [("d", C.c_int32), ("periodic", C.c_int32 * 3), ("ncell", C.c_int32 * 3),
-                ("reach", C.c_int32), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
+                ("reach", C.c_int32 * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
                 ("cutoff", C.c_double)]
 
 
@@ -184,12 +184,21 @@ class BoxSpec:
     periodic: Sequence[int]
     cutoff: float
     ncell: Optional[Sequence[int]] = None
-    reach: int = 0  # cells searched on each side of a particle's cell (0 = 1)
+    # cells searched on each side of a particle's cell (0 = 1): one value for every
+    # dimension or one per dimension
+    reach: Union[int, Sequence[int]] = 0
+
+    def reach_list(self) -> list:
+        r = [int(v) for v in self.reach] if hasattr(self.reach, "__len__") else [int(self.reach)] * self.d
+        if len(r) != self.d:
+            raise ValueError("reach needs one value or d values")
+        return r
 
     def to_c(self) -> Box:
         b = Box()
         b.d = self.d
-        b.reach = int(self.reach)
+        for k, m in enumerate(self.reach_list()[:3]):  # the library rejects d > 3
+            b.reach[k] = m
         for k in range(min(self.d, 3)):
             b.lo[k] = float(self.lo[k])
             b.hi[k] = float(self.hi[k])
@@ -446,7 +455,7 @@ def autotune_cells(ctx: Context, x: torch.Tensor, boxes: Sequence[BoxSpec], offs
                                      _ptr(a), op_na(op), _ptr(gy), op_ny(op, d), out_b, C.byref(factor))
     ctx.check(st, "autotune_cells")
     tuned = [BoxSpec(b.d, b.lo, b.hi, b.periodic, b.cutoff, [int(out_b[i].ncell[k]) for k in range(d)],
-                     int(out_b[i].reach)) for i, b in enumerate(boxes)]
+                     [int(out_b[i].reach[k]) for k in range(d)]) for i, b in enumerate(boxes)]
     return tuned, float(factor.value)
 
 

@@ -25,9 +25,10 @@ uint64_t tune_key(const aboria_cells* c, int32_t op, bool backward) {
     k = k * 2 + (uint64_t)(c->nsys > 1);
     k = k * 2 + (uint64_t)backward;
     k = k * 2 + (uint64_t)c->nbr_recorded;
-    int32_t reach = 1;
-    for (const aboria_box& b : c->boxes) reach = std::max<int32_t>(reach, b.reach == 0 ? 1 : b.reach);
-    k = k * 4 + (uint64_t)reach;
+    int32_t reach[3] = {1, 1, 1};
+    for (const aboria_box& b : c->boxes)
+        for (int q = 0; q < b.d; ++q) reach[q] = std::max<int32_t>(reach[q], b.reach[q] == 0 ? 1 : b.reach[q]);
+    k = k * 32 + (uint64_t)((reach[0] - 1) + 3 * (reach[1] - 1) + 9 * (reach[2] - 1));
     return k;
 }
 
@@ -137,10 +138,20 @@ extern "C" aboria_status aboria_autotune_cells(aboria_ctx* ctx, aboria_dtype dty
     if (d < 1 || d > 3) return fail(ctx, ABORIA_ERR_INVALID_ARG, "d must be 1, 2 or 3");
     if (op_ny(op, d) != ny) return fail(ctx, ABORIA_ERR_INVALID_ARG, "ny does not match the operator");
     try {
-        // reaches to try: the caller's, or every reach when the boxes leave it to the library
-        std::vector<int32_t> reaches;
-        if (boxes_host[0].reach != 0) reaches.push_back(boxes_host[0].reach);
-        else for (int32_t m = 1; m <= kMaxReach; ++m) reaches.push_back(m);
+        // reaches to try: the caller's, or, when the boxes leave it to the library,
+        // 1, 2 and 3 in every dimension and (d >= 2) 2 and 3 along x only
+        struct Reach {
+            int32_t m[3];
+        };
+        std::vector<Reach> reaches;
+        const int32_t* r0 = boxes_host[0].reach;
+        if (r0[0] != 0 || r0[1] != 0 || r0[2] != 0) {
+            reaches.push_back({{r0[0], r0[1], r0[2]}});
+        } else {
+            for (int32_t m = 1; m <= kMaxReach; ++m) reaches.push_back({{m, m, m}});
+            if (d >= 2)
+                for (int32_t m = 2; m <= kMaxReach; ++m) reaches.push_back({{m, 1, 1}});
+        }
         const int64_t n = offsets_host[nsys];
         const size_t tsz = dtype == ABORIA_F32 ? 4 : 8;
         ABORIA_HIP(ctx, hipSetDevice(ctx->device));
@@ -159,12 +170,12 @@ extern "C" aboria_status aboria_autotune_cells(aboria_ctx* ctx, aboria_dtype dty
         const double factors[] = {1.0, 0.85, 0.7, 0.55};
         double best_ms = INFINITY, best_f = 1.0;
         std::vector<aboria_box> trial(boxes_host, boxes_host + nsys), best_boxes(trial);
-        for (int32_t m : reaches) {
+        for (const Reach& R : reaches) {
             // the grid every trial of this reach coarsens: the automatic (or given explicit) counts
             std::vector<int32_t> base((size_t)nsys * 3, 1);
             for (int32_t b = 0; b < nsys && st == ABORIA_OK; ++b) {
                 aboria_box bx = boxes_host[b];
-                bx.reach = m;
+                for (int k = 0; k < 3; ++k) bx.reach[k] = R.m[k];
                 st = grid_counts(ctx, dtype, bx, &base[(size_t)b * 3]);
             }
             if (st != ABORIA_OK && reaches.size() > 1) {  // explicit counts too fine for this reach
@@ -181,7 +192,7 @@ extern "C" aboria_status aboria_autotune_cells(aboria_ctx* ctx, aboria_dtype dty
                 if (counts == last) continue;  // the same grid as the previous factor
                 last = counts;
                 for (int32_t b = 0; b < nsys; ++b) {
-                    trial[(size_t)b].reach = m;
+                    for (int k = 0; k < 3; ++k) trial[(size_t)b].reach[k] = R.m[k];
                     for (int k = 0; k < 3; ++k) trial[(size_t)b].ncell[k] = k < d ? counts[(size_t)b * 3 + k] : 0;
                 }
                 aboria_cells* cells = nullptr;

@@ -748,7 +748,7 @@ namespace {
 
 struct GridPlan {
     int32_t n[3] = {1, 1, 1};
-    int32_t reach = 1;
+    int32_t reach[3] = {1, 1, 1};
     double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0}, L[3] = {0, 0, 0}, inv_w[3] = {0, 0, 0};
     double w_lo[3] = {0, 0, 0}, slack[3] = {0, 0, 0};
     double r = 0, r2 = 0, prune_r2 = 0;
@@ -759,8 +759,8 @@ double round_to(int dtype, double v) { return dtype == ABORIA_F32 ? (double)(flo
 
 // Cell grid of one box: the largest per-dimension count whose cells are at
 // least (cutoff + a guard of 16 unit roundoffs of the coordinate magnitude) /
-// reach wide, so that rounding in the cell assignment cannot put the points of
-// a pair more than `reach` cells apart.  Also the pruning bound of the
+// m wide, m the dimension's reach, so that rounding in the cell assignment
+// cannot put the points of a pair more than m cells apart.  Also the pruning bound of the
 // flattened search (SysParams): the margins cover the rounding of both cell
 // assignments (2 u |q| each, |q| <= n + 1 cell units), of an image shift
 // (n u) and of the gap itself (u reach), with room to spare, and the pair
@@ -768,9 +768,11 @@ double round_to(int dtype, double v) { return dtype == ABORIA_F32 ? (double)(flo
 // u L, its sum of squares by a few u).
 aboria_status plan_grid(aboria_ctx* ctx, int dtype, const aboria_box& b, GridPlan* g) {
     const double u = dtype == ABORIA_F32 ? std::ldexp(1.0, -24) : std::ldexp(1.0, -53);
-    g->reach = b.reach == 0 ? 1 : b.reach;
-    if (g->reach < 1 || g->reach > kMaxReach) return fail(ctx, ABORIA_ERR_INVALID_ARG, "reach must be 0 to 3");
-    const double m = (double)g->reach;
+    for (int k = 0; k < 3; ++k) {
+        g->reach[k] = k < b.d && b.reach[k] != 0 ? b.reach[k] : 1;
+        if (g->reach[k] < 1 || g->reach[k] > kMaxReach)
+            return fail(ctx, ABORIA_ERR_INVALID_ARG, "reach must be 0 to 3 in every dimension");
+    }
     g->r = round_to(dtype, b.cutoff);
     if (!(g->r > 0.0) || std::isinf(g->r)) return fail(ctx, ABORIA_ERR_INVALID_ARG, "cutoff must be positive and finite");
     if (dtype == ABORIA_F32) {
@@ -788,6 +790,7 @@ aboria_status plan_grid(aboria_ctx* ctx, int dtype, const aboria_box& b, GridPla
             return fail(ctx, ABORIA_ERR_INVALID_ARG, "box needs finite lo < hi in every dimension");
         g->L[k] = dtype == ABORIA_F32 ? (double)((float)g->hi[k] - (float)g->lo[k]) : g->hi[k] - g->lo[k];
         const double guard = g->r + 16.0 * u * (std::fabs(g->lo[k]) + g->L[k]);
+        const double m = (double)g->reach[k];
         const double q = std::floor(m * g->L[k] / g->r);
         int64_t nmax = q < 1.0 ? 1 : (q > 2147483647.0 ? 2147483647 : (int64_t)q);
         while (nmax > 1 && g->L[k] / (double)nmax < guard / m) --nmax;
@@ -839,7 +842,7 @@ void fill_params(const std::vector<GridPlan>& plans, const std::vector<aboria_bo
             p.slack[k] = (T)(plans[b].slack[k] * (1.0 + 4.0 * std::numeric_limits<T>::epsilon()));
         }
         p.prune_r2 = (T)(plans[b].prune_r2 * (1.0 + 4.0 * std::numeric_limits<T>::epsilon()));
-        p.reach = plans[b].reach;
+        for (int k = 0; k < 3; ++k) p.reach[k] = plans[b].reach[k];
         p.cell_base = cell_base[b];
         p.part_base = (uint32_t)off[b];
         p.part_end = (uint32_t)off[b + 1];

@@ -34,7 +34,7 @@ struct SysParams {
     T prune_r2;    // (r + rounding margin of the predicate)^2, rounded up
     int32_t n[3];
     int32_t periodic[3];
-    int32_t reach;       // cells searched on each side of a point's own cell
+    int32_t reach[3];    // cells searched on each side of a point's own cell, per dimension
     uint32_t cell_base;  // first global cell id of the system
     uint32_t part_base;  // first sorted slot (= first row) of the system
     uint32_t part_end;   // one past its last slot

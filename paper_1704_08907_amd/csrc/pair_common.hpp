@@ -425,12 +425,12 @@ __device__ __forceinline__ bool wrap_cell(int32_t v, int32_t n, int32_t periodic
 }
 
 // Box search of the point xi (a particle of the cell list, Section 2.2.2): its
-// cell and every cell up to m = P.reach cells away in each dimension (m = 1:
-// the adjacent cells), walked as (2m+1)^(d-1) x-rows in (z, y) order.  On a
-// grid at least 2m+1 cells wide a row is one contiguous run of up to 2m+1
-// cells clipped to the grid, then, when periodic, the wrapped remainder with
-// its image shift (only one side can wrap); on a narrower grid each offset is
-// its own piece, in offset order.  A piece whose shift is zero on every active
+// cell and every cell up to m_k = P.reach[k] cells away in dimension k (m = 1:
+// the adjacent cells), walked as (2 m_y + 1)(2 m_z + 1) x-rows in (z, y)
+// order.  On a grid at least 2 m_x + 1 cells wide a row is one contiguous run
+// of up to 2 m_x + 1 cells clipped to the grid, then, when periodic, the
+// wrapped remainder with its image shift (only one side can wrap); on a
+// narrower grid each offset is its own piece, in offset order.  A piece whose shift is zero on every active
 // lane of the wave runs the loop without the shift additions (adding zero is
 // exact, so both loops give the canonical dx).  flat_loop visits the accepted
 // neighbours in this same order.
@@ -444,7 +444,7 @@ __device__ __forceinline__ void neighbour_loop_aux(const SysParams<T>& P, const 
         T fr;
         c[k] = cell_coord(P, k, xi[k], &fr);
     }
-    const int32_t M = P.reach;
+    const int32_t M = P.reach[0];
     const int32_t nx = P.n[0];
     const bool wide = nx >= 2 * M + 1;
     const int32_t a0 = max(c[0] - M, 0), b0 = min(c[0] + M, nx - 1);
@@ -473,7 +473,7 @@ __device__ __forceinline__ void neighbour_loop_aux(const SysParams<T>& P, const 
                 scan_range<T, D, false, OFF32>(xs, j0, j1, xi, sh, r2, false, visit);
         }
     };
-    const int32_t zr = D >= 3 ? M : 0, yr = D >= 2 ? M : 0;
+    const int32_t zr = D >= 3 ? P.reach[2] : 0, yr = D >= 2 ? P.reach[1] : 0;
     for (int32_t dz = -zr; dz <= zr; ++dz) {
         int32_t cz = 0;
         T sz = T(0);
@@ -566,7 +566,7 @@ __device__ __forceinline__ void flat_loop(const SysParams<T>& P, const T* __rest
     T fr[3] = {T(0), T(0), T(0)};
 #pragma unroll
     for (int k = 0; k < D; ++k) c[k] = cell_coord(P, k, xi[k], &fr[k]);
-    const int32_t M = P.reach;
+    const int32_t M = P.reach[0];
     const int32_t nx = P.n[0];
     const bool wide = nx >= 2 * M + 1;
     const T pr2 = P.prune_r2;
@@ -580,7 +580,7 @@ __device__ __forceinline__ void flat_loop(const SysParams<T>& P, const T* __rest
     }
     // ranges a row can add: one run and one wrapped run, or one per offset
     const int pmax = wide ? (P.periodic[0] ? 2 : 1) : 2 * M + 1;
-    const int32_t zr = D >= 3 ? M : 0, yr = D >= 2 ? M : 0;
+    const int32_t zr = D >= 3 ? P.reach[2] : 0, yr = D >= 2 ? P.reach[1] : 0;
     int32_t dy = -yr, dz = -zr;
     bool rows_left = true;
     const T r2 = P.r2;

@@ -2,9 +2,9 @@
 // row of a particle, one bit per candidate it accepted, and whose adjoint
 // replays those bits instead of testing every candidate again.
 //
-// The row search of the 3^d stencil (reach 1) visits 3^(d-1) rows, each the
-// run of up to three neighbouring cells in x plus, at a periodic wrap, the
-// wrapped remainder.  The candidates of row r, concatenated in visiting order,
+// The row search with reach 1 in y and z visits the 3^(d-1) rows of the 3^d
+// stencil, each the run of up to 2 m + 1 neighbouring cells in x (m the x
+// reach) plus, at a periodic wrap, the wrapped remainder.  The candidates of row r, concatenated in visiting order,
 // number at most kMaskBits; bit k of the row's mask word pair (masks[(2r) n +
 // s], masks[(2r + 1) n + s] for slot s) is set when the k-th is a neighbour.
 // The rows advance in lockstep across a wave, so each word is stored as one
@@ -23,11 +23,11 @@ namespace aboria {
 
 constexpr int kMaskBits = 64;  // candidates per stencil row a record covers
 
-// Walks the stencil rows of xi that exist, in the visiting order of the
-// reach-1 box search: begin(row), then piece(j0, j1, sh) for each run of slots
-// [j0, j1) of the row with its image shift sh (up to three runs: the x
-// neighbours, plus the wrapped remainder at a periodic boundary), then
-// end(row).  Rows are numbered (dz + 1) * 3^(d-2) + (dy + 1) in visiting order,
+// Walks the stencil rows of xi that exist, in the visiting order of the box
+// search with reach 1 in y and z: begin(row), then piece(j0, j1, sh) for each
+// run of slots [j0, j1) of the row with its image shift sh (the cells up to m
+// away in x as one run plus the wrapped remainder at a periodic boundary, or,
+// on a grid narrower than 2 m + 1 cells, one run per offset), then end(row).  Rows are numbered (dz + 1) * 3^(d-2) + (dy + 1) in visiting order,
 // so skipped rows keep their numbers.
 template <typename T, int D, typename Begin, typename Piece, typename End>
 __device__ __forceinline__ void for_each_piece(const SysParams<T>& P, const uint32_t* __restrict__ off, uint32_t n,
@@ -38,14 +38,15 @@ __device__ __forceinline__ void for_each_piece(const SysParams<T>& P, const uint
         T fr;
         c[k] = cell_coord(P, k, xi[k], &fr);
     }
+    const int32_t M = P.reach[0];
     const int32_t nx = P.n[0];
-    const bool wide = nx >= 3;
-    const int32_t a0 = max(c[0] - 1, 0), b0 = min(c[0] + 1, nx - 1);
+    const bool wide = nx >= 2 * M + 1;
+    const int32_t a0 = max(c[0] - M, 0), b0 = min(c[0] + M, nx - 1);
     int32_t a1 = 0, b1 = -1;
     T s1 = T(0);
     if (P.periodic[0]) {
-        if (c[0] - 1 < 0) { a1 = nx - 1; b1 = nx - 1; s1 = -P.L[0]; }
-        else if (c[0] + 1 >= nx) { a1 = 0; b1 = 0; s1 = P.L[0]; }
+        if (c[0] - M < 0) { a1 = c[0] - M + nx; b1 = nx - 1; s1 = -P.L[0]; }
+        else if (c[0] + M >= nx) { a1 = 0; b1 = c[0] + M - nx; s1 = P.L[0]; }
     }
     const int32_t zr = D >= 3 ? 1 : 0, yr = D >= 2 ? 1 : 0;
     // the row and offset loops stay rolled: unrolled, the compiler hoists work
@@ -73,7 +74,7 @@ __device__ __forceinline__ void for_each_piece(const SysParams<T>& P, const uint
                 }
             } else {
 #pragma unroll 1
-                for (int32_t o = -1; o <= 1; ++o) {
+                for (int32_t o = -M; o <= M; ++o) {
                     int32_t cx;
                     if (!wrap_cell(c[0] + o, nx, P.periodic[0], P.L[0], &cx, &sh[0])) continue;
                     run(rowbase + cx, rowbase + cx);

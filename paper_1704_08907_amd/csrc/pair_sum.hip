@@ -118,15 +118,26 @@ bool off32_ok(const aboria_cells* c) {
     return c->dtype == ABORIA_F32 ? off32_rows<float>((uint64_t)c->n) : off32_rows<double>((uint64_t)c->n);
 }
 
-// Largest search reach over the systems of a cell list.
-int32_t max_reach(const aboria_cells* c) {
+// Largest search reach over the systems of a cell list in dimension k.
+int32_t max_reach(const aboria_cells* c, int k) {
     int32_t m = 1;
-    for (const aboria_box& b : c->boxes) m = std::max<int32_t>(m, b.reach == 0 ? 1 : b.reach);
+    for (const aboria_box& b : c->boxes)
+        if (k < b.d) m = std::max<int32_t>(m, b.reach[k] == 0 ? 1 : b.reach[k]);
     return m;
 }
 
-// Variants with their own box-search loops, written for the 3^d stencil.
-bool needs_reach1(const Variant& v) { return v.kind == 1 || v.kind == 4 || v.kind == 6 || (v.kind == 0 && v.compact); }
+// Reach 1 in every dimension but x: the search has the 3^(d-1) rows of the
+// paper's stencil (each row may span more, narrower cells along x).
+bool rows_reach1(const aboria_cells* c) { return max_reach(c, 1) == 1 && max_reach(c, 2) == 1; }
+bool all_reach1(const aboria_cells* c) { return rows_reach1(c) && max_reach(c, 0) == 1; }
+
+// Variants with their own box-search loops, written for the 3^d stencil: the
+// mask variant for its rows, the others for every cell of it.
+bool reach_ok(const Variant& v, const aboria_cells* c) {
+    if (v.kind == 6) return rows_reach1(c);
+    if (v.kind == 1 || v.kind == 4 || (v.kind == 0 && v.compact)) return all_reach1(c);
+    return true;
+}
 
 int64_t largest_system(const aboria_cells* c) {
     int64_t m = 0;
@@ -246,8 +257,10 @@ aboria_status check_variant(aboria_ctx* ctx, const aboria_cells* c, int variant)
         return fail(ctx, ABORIA_ERR_INVALID_ARG, "the all-pairs variant takes systems of at most 16384 particles");
     if (variant_of(variant).kind == 4 && !off32_ok(c))
         return fail(ctx, ABORIA_ERR_INVALID_ARG, "the staged variant needs rows below a 32-bit byte offset");
-    if (needs_reach1(variant_of(variant)) && max_reach(c) > 1)
-        return fail(ctx, ABORIA_ERR_INVALID_ARG, "the variant searches the 3^d stencil only (reach 1)");
+    if (!reach_ok(variant_of(variant), c))
+        return fail(ctx, ABORIA_ERR_INVALID_ARG,
+                    variant_of(variant).kind == 6 ? "the variant needs reach 1 in every dimension but x"
+                                                  : "the variant searches the 3^d stencil only (reach 1)");
     if (variant_of(variant).kind == 6) return ensure_masks(ctx, c);
     return ABORIA_OK;
 }
@@ -274,7 +287,7 @@ bool variant_worth_timing(int32_t v, const aboria_cells* c) {
 
 bool variant_usable(int32_t v, const aboria_cells* c) {
     if (v < 0 || v >= kNumVariants) return false;
-    if (needs_reach1(kVariants[v]) && max_reach(c) > 1) return false;
+    if (!reach_ok(kVariants[v], c)) return false;
     if (kVariants[v].kind == 2) return c->nbr_recorded;
     if (kVariants[v].kind == 3) return largest_system(c) <= kAllPairsMaxSystem;
     if (kVariants[v].kind == 4) return off32_ok(c);
@@ -302,7 +315,8 @@ int32_t default_variant(const aboria_cells* c) {
         for (int32_t v = 0; v < kNumVariants; ++v)
             if (kVariants[v].kind == 3) return v;
     if (c->nbr_recorded) return list_variant();
-    return max_reach(c) > 1 ? flat_variant() : 0;
+    // rows of the 3^d stencil (any x reach): the row search; deeper rows: the flattened search
+    return rows_reach1(c) ? 0 : flat_variant();
 }
 
 aboria_status pair_sum_impl(aboria_ctx* ctx, const aboria_cells* c, int32_t op, const double* params,

@@ -177,6 +177,49 @@ def test_batch_and_graph():
     torch.cuda.set_stream(torch.cuda.default_stream())
 
 
+@pytest.mark.parametrize("reach", [[2, 1, 1], [3, 1, 1]])
+def test_masks_with_reach_along_x(ctx, reach):
+    # narrower cells along x make each of the nine rows a longer run of cells
+    w = syn.spring_cube(n=60000)
+    s = w.systems[0]
+    cells = A.build_cells(ctx, to_dev(s.x), [A.BoxSpec(3, s.lo, s.hi, s.periodic, s.cutoff, None, reach)])
+    n = s.n
+    rng = syn.SplitMix64(99)
+    a_d = to_dev((0.2 + 0.3 * rng.uniform(n)).astype(np.float32).reshape(n, 1))
+    for op, params in OPS:
+        gy_d = to_dev(rng.normal(n * A.op_ny(op, 3)).astype(np.float32).reshape(n, -1))
+        aa = a_d if op == "dem_spring" else None
+        y_ref = fwd(ctx, cells, op, params, aa, variant(PLAIN))
+        g_ref = bwd(ctx, cells, op, params, gy_d, aa, variant(PLAIN))
+        y = fwd(ctx, cells, op, params, aa, variant(MASK))
+        g = bwd(ctx, cells, op, params, gy_d, aa, variant(MASK))
+        ctx.sync()
+        assert torch.equal(y, y_ref), (reach, op)
+        for u, v in zip(g, g_ref):
+            assert same(u, v), (reach, op)
+
+
+def test_masks_with_reach_along_x_on_narrow_grids(ctx):
+    # fewer than 2m + 1 cells along x: each offset is its own piece of the row
+    from test_gpu_reach import NARROW_ANISO, make_case
+    for case in NARROW_ANISO:
+        g, x, box, prec = make_case(case, [2, 1, 1])
+        n, d = x.shape
+        cells = A.build_cells(ctx, to_dev(x), [box])
+        rng = syn.SplitMix64(5150)
+        for op, params in OPS:
+            if op == "dem_spring":
+                continue
+            gy_d = to_dev(rng.normal(n * A.op_ny(op, d)).astype(x.dtype).reshape(n, -1))
+            y_ref = fwd(ctx, cells, op, params, None, variant(PLAIN))
+            g_ref = bwd(ctx, cells, op, params, gy_d, None, variant(PLAIN))
+            y = fwd(ctx, cells, op, params, None, variant(MASK))
+            gg = bwd(ctx, cells, op, params, gy_d, None, variant(MASK))
+            ctx.sync()
+            assert torch.equal(y, y_ref), (case[0], op)
+            assert torch.equal(gg[0], g_ref[0]), (case[0], op)
+
+
 def test_needs_reach_1(ctx):
     s = syn.spring_cube(n=20000).systems[0]
     cells = A.build_cells(ctx, to_dev(s.x), [A.BoxSpec(3, s.lo, s.hi, s.periodic, s.cutoff, None, 2)])

@@ -1,5 +1,6 @@
 """Cell grids with search reach 2 and 3 (cells about r/2 or r/3 wide, searched
-2 or 3 cells deep) and the flattened, pruned box search.
+2 or 3 cells deep), in every dimension or along x only, and the flattened,
+pruned box search.
 
 Bit-exact against the oracle: cell ids, permutation, offsets and pair sets on
 the reach's grid (points placed within a few ulps of the narrower cell
@@ -45,12 +46,25 @@ NARROW = [
     ("d3_narrow_mixed", 3, [2.2, 2.3, 2.4], [1, 0, 1], 1.0, "f64", [4, 2, 3], 600),
 ]
 REACH_CASES = [c for c in CASES if c[6] is None] + NARROW
+# reach along x only: the 3^(d-1) rows of the reach-1 search, each over narrower cells
+ANISO = [[2, 1, 1], [3, 1, 1]]
+NARROW_ANISO = [
+    ("d2_narrow_x", 2, [2.1, 2.6], [1, 1], 1.0, "f32", [3, 2], 700),
+    ("d3_narrow_x_mixed", 3, [2.2, 2.3, 2.4], [1, 0, 1], 1.0, "f64", [4, 2, 2], 600),
+]
+ANISO_CASES = [(c, m) for m in ANISO for c in REACH_CASES if c[6] is None and c[1] > 1] + \
+    [(c, m) for m in ANISO[:1] for c in NARROW_ANISO]
+ALL_REACH = [(c, m) for m in (2, 3) for c in REACH_CASES] + ANISO_CASES
+ALL_IDS = ["%s-%s" % (c[0], m if isinstance(m, int) else "".join(map(str, m))) for c, m in ALL_REACH]
 
 
 def make_case(case, reach):
     name, d, hi, per, r, prec, ncell, n = case
+    if not isinstance(reach, int):
+        reach = list(reach[:d])
     g = oracle.grid(d, [0.0] * d, hi, per, r, prec, ncell, reach)
-    rng = syn.SplitMix64(zlib.crc32(name.encode()) + reach)
+    tag = reach if isinstance(reach, int) else 100 + sum(m << (2 * k) for k, m in enumerate(reach))
+    rng = syn.SplitMix64(zlib.crc32(name.encode()) + tag)
     x = syn.uniform_positions(rng, n - n // 4, [0.0] * d, hi, prec)
     xb = near_boundary(rng, g, n // 4, prec)
     x = np.ascontiguousarray(np.concatenate([x, xb]))
@@ -72,8 +86,7 @@ def same(u, v):
     return (u is None and v is None) or torch.equal(u, v)
 
 
-@pytest.mark.parametrize("reach", [2, 3])
-@pytest.mark.parametrize("case", REACH_CASES, ids=[c[0] for c in REACH_CASES])
+@pytest.mark.parametrize("case,reach", ALL_REACH, ids=ALL_IDS)
 def test_reach_cells_and_pairs_bit_exact(ctx, case, reach):
     g, x, box, prec = make_case(case, reach)
     print("case", case[0], "reach", reach, flush=True)
@@ -91,8 +104,7 @@ def test_reach_cells_and_pairs_bit_exact(ctx, case, reach):
     np.testing.assert_array_equal(gpu_pairs_sorted(ctx, cells), oracle.pairs(g, x.astype(np.float64)))
 
 
-@pytest.mark.parametrize("reach", [2, 3])
-@pytest.mark.parametrize("case", REACH_CASES, ids=[c[0] for c in REACH_CASES])
+@pytest.mark.parametrize("case,reach", ALL_REACH, ids=ALL_IDS)
 def test_reach_sums_match_oracle_and_row_search(ctx, case, reach):
     g, x, box, prec = make_case(case, reach)
     n, d = x.shape
@@ -107,7 +119,8 @@ def test_reach_sums_match_oracle_and_row_search(ctx, case, reach):
         aa = a if op == "dem_spring" else None
         aa_d = to_dev(aa) if aa is not None else None
         gy_d = to_dev(gy)
-        # the untuned default at reach > 1 is the flattened search (above the small-N switch)
+        # the untuned default above the small-N switch: the flattened search at reach > 1 in y
+        # or z, the row search otherwise (the two are equal bit for bit)
         y = A.pair_sum(ctx, cells, op, params, aa_d)
         gx, ga = A.pair_sum_backward(ctx, cells, op, params, gy_d, aa_d)
         flat = run(ctx, cells, op, params, aa_d, gy_d, variant(FLAT))
@@ -173,7 +186,7 @@ def test_reach_fused_and_replayed_list_equal_the_flat_search(ctx):
 
 def test_batch_of_mixed_reaches(ctx):
     w = syn.batch_cubes(nsys=12, nmax=8192)
-    reaches = [1 + (b % 3) for b in range(len(w.systems))]
+    reaches = [[[1, 1, 1], [2, 2, 2], [3, 3, 3], [2, 1, 1], [3, 1, 1]][b % 5] for b in range(len(w.systems))]
     xs_all = np.concatenate([s.x for s in w.systems])
     offsets = np.concatenate([[0], np.cumsum([s.n for s in w.systems])]).tolist()
     boxes = [A.BoxSpec(s.d, s.lo, s.hi, s.periodic, s.cutoff, None, m) for s, m in zip(w.systems, reaches)]
@@ -211,8 +224,24 @@ def test_reach_1_only_variants_are_refused_and_skipped(ctx):
     # the tuner skips them and picks a variant that runs on these cells
     choice = A.autotune(ctx, cells, "spring", (1.0,))
     assert "cell group" not in A.variant_name(choice) and "staged" not in A.variant_name(choice)
+    # reach 2 along x only: the same variants are refused, the mask variant runs
+    cx = A.build_cells(ctx, to_dev(s.x), [A.BoxSpec(s.d, s.lo, s.hi, s.periodic, s.cutoff, None, [2, 1, 1])])
+    for word in ("cell group of 16 lanes per home cell, cells in natural order", "staged", "48-entry LDS list"):
+        ctx.set_variant(variant(word))
+        try:
+            with pytest.raises(A.AboriaError):
+                A.pair_sum(ctx, cx, "spring", (1.0,))
+        finally:
+            ctx.set_variant(-1)
+    ctx.set_variant(variant("records accepted-pair bit masks"))
+    try:
+        A.pair_sum(ctx, cx, "spring", (1.0,))
+    finally:
+        ctx.set_variant(-1)
     with pytest.raises(A.AboriaError):
         A.build_cells(ctx, to_dev(s.x), [A.BoxSpec(s.d, s.lo, s.hi, s.periodic, s.cutoff, None, 4)])
+    with pytest.raises(A.AboriaError):
+        A.build_cells(ctx, to_dev(s.x), [A.BoxSpec(s.d, s.lo, s.hi, s.periodic, s.cutoff, None, [1, 4, 1])])
     with pytest.raises(A.AboriaError):  # explicit counts finer than reach 1 allows
         A.build_cells(ctx, to_dev(s.x), [A.BoxSpec(s.d, s.lo, s.hi, s.periodic, s.cutoff, [40, 40, 40], 1)])
     ctx.sync()
@@ -226,7 +255,7 @@ def test_autotuned_reach_and_cell_size_are_valid(ctx):
     tuned, f = A.autotune_cells(ctx, x_d, [box_of(s) for s in w.systems], offsets, "spring", (1.0,))
     assert f in (1.0, 0.85, 0.7, 0.55)
     m = tuned[0].reach
-    assert m in (1, 2, 3) and all(t.reach == m for t in tuned)
+    assert m in ([1, 1, 1], [2, 2, 2], [3, 3, 3], [2, 1, 1], [3, 1, 1]) and all(t.reach == m for t in tuned)
     for s, t in zip(w.systems, tuned):
         auto = oracle.grid_of(s, None, m).ncell
         assert list(t.ncell) == [max(1, math.floor(f * a)) for a in auto]
