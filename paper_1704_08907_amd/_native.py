@@ -139,6 +139,7 @@ class Context:
         if st != 0:
             raise AboriaError(st, "create", "device %d" % device)
         self.handle = h
+        self.forced_variant = -1
 
     def check(self, st: int, what: str):
         if st != 0:
@@ -163,6 +164,7 @@ class Context:
     def set_variant(self, v: int):
         """Force a neighbour-sum variant for later calls (-1 = tuned / default)."""
         self.check(lib().aboria_set_variant(self.handle, v), "set_variant")
+        self.forced_variant = int(v)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -255,6 +257,7 @@ def build_cells(ctx: Context, x: torch.Tensor, boxes: Sequence[BoxSpec], offsets
     st = lib().aboria_build_cells(ctx.handle, _dtype_code(x), nsys, arr_b, arr_o, _ptr(x), C.byref(h))
     ctx.check(st, "build_cells")
     if cells is not None:
+        cells.boxes, cells.offsets = boxes, list(offsets)
         return cells
     return Cells(ctx, h, n, boxes[0].d, x.dtype, nsys, boxes, list(offsets))
 
