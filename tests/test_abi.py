@@ -42,3 +42,46 @@ def test_static_queries_without_gpu():
     assert N.op_ny("spring", 3) == 3 and N.op_ny("soft_sphere", 3) == 1 and N.op_na("dem_spring") == 1
     assert N.lib().aboria_op_ny(99, 3) == -1 and N.lib().aboria_op_ny(1, 4) == -1
     assert N.variant_count() >= 1 and N.variant_name(0)
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    # the binding's ctypes structures against the header, compiled by the host C compiler
+    import shutil
+    import subprocess
+    from paper_1704_08907_amd import _native as N
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = {"aboria_box": N.Box, "aboria_cells_view": N.CellsView}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "aboria.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in py._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line.strip():
+            a, b, c = line.split()
+            got[(a, b)] = int(c)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_box_reach_per_dimension_marshalling():
+    from paper_1704_08907_amd import _native as N
+    b = N.BoxSpec(3, [0] * 3, [1] * 3, [1] * 3, 0.1, None, 2).to_c()
+    assert list(b.reach) == [2, 2, 2]
+    b = N.BoxSpec(3, [0] * 3, [1] * 3, [1] * 3, 0.1, None, [3, 1, 1]).to_c()
+    assert list(b.reach) == [3, 1, 1]
+    b = N.BoxSpec(2, [0] * 2, [1] * 2, [1] * 2, 0.1).to_c()
+    assert list(b.reach) == [0, 0, 0]  # 0 = reach 1 in the library
+    with pytest.raises(ValueError):
+        N.BoxSpec(3, [0] * 3, [1] * 3, [1] * 3, 0.1, None, [2, 1]).to_c()
