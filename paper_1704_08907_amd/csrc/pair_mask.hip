@@ -4,9 +4,10 @@
 //
 // The row search with reach 1 in y and z visits the 3^(d-1) rows of the 3^d
 // stencil, each the run of up to 2 m + 1 neighbouring cells in x (m the x
-// reach) plus, at a periodic wrap, the wrapped remainder.  The candidates of row r, concatenated in visiting order,
-// number at most kMaskBits; bit k of the row's mask word pair (masks[(2r) n +
-// s], masks[(2r + 1) n + s] for slot s) is set when the k-th is a neighbour.
+// reach) plus, at a periodic wrap, the wrapped remainder.  The candidates of
+// row r, concatenated in visiting order, number at most kMaskBits; bit k of the
+// row's mask word pair (masks[(2r) n + s], masks[(2r + 1) n + s] for slot s) is
+// set when the k-th is a neighbour.
 // The rows advance in lockstep across a wave, so each word is stored as one
 // contiguous 256-byte run.  status[s] = the build generation the masks were
 // recorded for, or 0 when a row of the particle held more than kMaskBits
@@ -27,8 +28,9 @@ constexpr int kMaskBits = 64;  // candidates per stencil row a record covers
 // search with reach 1 in y and z: begin(row), then piece(j0, j1, sh) for each
 // run of slots [j0, j1) of the row with its image shift sh (the cells up to m
 // away in x as one run plus the wrapped remainder at a periodic boundary, or,
-// on a grid narrower than 2 m + 1 cells, one run per offset), then end(row).  Rows are numbered (dz + 1) * 3^(d-2) + (dy + 1) in visiting order,
-// so skipped rows keep their numbers.
+// on a grid narrower than 2 m + 1 cells, one run per offset), then end(row).
+// Rows are numbered (dz + 1) * 3^(d-2) + (dy + 1) in visiting order, so skipped
+// rows keep their numbers.
 template <typename T, int D, typename Begin, typename Piece, typename End>
 __device__ __forceinline__ void for_each_piece(const SysParams<T>& P, const uint32_t* __restrict__ off, uint32_t n,
                                                const T* xi, Begin&& begin, Piece&& piece, End&& end) {
