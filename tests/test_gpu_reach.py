@@ -125,7 +125,10 @@ def test_reach_sums_match_oracle_and_row_search(ctx, case, reach):
         gx, ga = A.pair_sum_backward(ctx, cells, op, params, gy_d, aa_d)
         flat = run(ctx, cells, op, params, aa_d, gy_d, variant(FLAT))
         rows = run(ctx, cells, op, params, aa_d, gy_d, variant(ROWS))
+        fused = A.pair_sum_and_backward(ctx, cells, op, params, gy_d, aa_d)  # one search for both
         ctx.sync()
+        for u, v in zip(fused, rows):
+            assert same(u, v), (case[0], op, "fused")
         if n > 2048:  # smaller systems default to the all-pairs sums
             for u, v in zip((y, gx, ga), flat):
                 assert same(u, v), (case[0], op, "default")
