@@ -220,6 +220,35 @@ def test_masks_with_reach_along_x_on_narrow_grids(ctx):
             assert torch.equal(gg[0], g_ref[0]), (case[0], op)
 
 
+def test_headline_configuration_full_size(ctx):
+    # the bench's step: spring cube N = 2^20 on cells r/3 wide along x, the forward
+    # recording masks and the adjoint replaying them; bit-equal to the row search on
+    # the same grid, and sampled rows against the oracle
+    import oracle
+    from _parity import TOL_F32, check_close
+    w = syn.spring_cube()
+    s = w.systems[0]
+    box = A.BoxSpec(3, s.lo, s.hi, s.periodic, s.cutoff, None, [3, 1, 1])
+    x_d = to_dev(s.x)
+    gy_d = to_dev(w.extra["gy"])
+    cells = A.build_cells(ctx, x_d, [box])
+    assert [int(cells.view().ncell_host[k]) for k in range(3)] == [158, 52, 52]
+    y = fwd(ctx, cells, "spring", (1.0,), None, variant(MASK))
+    gx = bwd(ctx, cells, "spring", (1.0,), gy_d, None, variant(MASK))[0]
+    y_ref = fwd(ctx, cells, "spring", (1.0,), None, variant(PLAIN))
+    gx_ref = bwd(ctx, cells, "spring", (1.0,), gy_d, None, variant(PLAIN))[0]
+    ctx.sync()
+    assert torch.equal(y, y_ref) and torch.equal(gx, gx_ref)
+    g = oracle.grid(3, s.lo, s.hi, s.periodic, s.cutoff, "f32", None, [3, 1, 1])
+    rows = np.floor(syn.SplitMix64(33).uniform(256) * s.n).astype(np.int64)
+    rows = np.concatenate([rows, [0, s.n - 1]])
+    x64 = s.x.astype(np.float64)
+    yo, so = oracle.pair_sum(g, "spring", (1.0,), x64, rows=rows)
+    check_close(y.cpu().numpy()[rows], yo, so, TOL_F32, "headline forward rows")
+    gxo, _, sxo, _ = oracle.pair_sum_backward(g, "spring", (1.0,), x64, w.extra["gy"].astype(np.float64), rows=rows)
+    check_close(gx.cpu().numpy()[rows], gxo, sxo, TOL_F32, "headline adjoint rows")
+
+
 def test_needs_reach_1(ctx):
     s = syn.spring_cube(n=20000).systems[0]
     cells = A.build_cells(ctx, to_dev(s.x), [A.BoxSpec(3, s.lo, s.hi, s.periodic, s.cutoff, None, 2)])
