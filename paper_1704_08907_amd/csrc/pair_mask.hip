@@ -12,8 +12,8 @@
 // contiguous 256-byte run.  status[s] = the build generation the masks were
 // recorded for, or 0 when a row of the particle held more than kMaskBits
 // candidates; the adjoint replays a particle only when its status matches the
-// current generation, and otherwise tests its candidates again (the deferred
-// box search), so a stale or overflowing record only costs time.
+// current generation, and otherwise tests its candidates again (the row
+// search, in the same order), so a stale or overflowing record only costs time.
 //
 // Replayed pairs are visited in box-search order with dx and d2 recomputed by
 // the same pair test, so forward and adjoint equal the plain lane kernels' bit
@@ -201,32 +201,48 @@ __global__ __launch_bounds__(256) void k_lane_mask(const T* __restrict__ xs, con
                     uint64_t bits = pos < 64u ? m >> pos : 0ull;
                     if (len < 64u) bits &= (1ull << len) - 1ull;
                     pos += len;
-                    // two accepted pairs per iteration, so their loads overlap
+                    // three accepted pairs per iteration, so their loads overlap
                     while (bits != 0ull) {
                         const uint32_t ja = j0 + (uint32_t)__builtin_ctzll(bits);
                         bits &= bits - 1ull;
                         const bool vb = bits != 0ull;
                         const uint32_t jb = vb ? j0 + (uint32_t)__builtin_ctzll(bits) : ja;
                         bits &= bits - 1ull;
+                        const bool vc = bits != 0ull;
+                        const uint32_t jc = vc ? j0 + (uint32_t)__builtin_ctzll(bits) : ja;
+                        bits &= bits - 1ull;
                         const VecN<T, PITCH> xa = load_row<T, PITCH, OFF32>(xs, ja);
                         const VecN<T, GP> ga_ = load_row<T, GP, OFF32>(gy_s, ja);
                         const VecN<T, PITCH> xb = load_row<T, PITCH, OFF32>(xs, jb);
                         const VecN<T, GP> gb_ = load_row<T, GP, OFF32>(gy_s, jb);
+                        const VecN<T, PITCH> xc = load_row<T, PITCH, OFF32>(xs, jc);
+                        const VecN<T, GP> gc_ = load_row<T, GP, OFF32>(gy_s, jc);
                         T dx[D], d2;
                         (void)pair_test<T, D, true>(xa.v, xi, sh, r2, dx, &d2);
                         pair(ja, dx, d2, ga_.v);
                         keep_issued<D>(xb.v);
                         keep_issued<NY>(gb_.v);
+                        keep_issued<D>(xc.v);
+                        keep_issued<NY>(gc_.v);
                         if (vb) {
                             (void)pair_test<T, D, true>(xb.v, xi, sh, r2, dx, &d2);
                             pair(jb, dx, d2, gb_.v);
+                        }
+                        if (vc) {
+                            (void)pair_test<T, D, true>(xc.v, xi, sh, r2, dx, &d2);
+                            pair(jc, dx, d2, gc_.v);
                         }
                     }
                 },
                 [&](int) {});
         } else {
-            auto visit = [&](uint32_t j, const T* dx, T d2, bool, const T* gyj) { pair(j, dx, d2, gyj); };
-            neighbour_loop_aux<T, D, OFF32, NY>(P, xs, gy_s, off, n, xi, visit);
+            // no record: the plain row search (not its deferred form, whose
+            // registers would lower the replay's occupancy)
+            auto visit = [&](uint32_t j, const T* dx, T d2, bool) {
+                const VecN<T, GP> gj = load_row<T, GP, OFF32>(gy_s, j);
+                pair(j, dx, d2, gj.v);
+            };
+            neighbour_loop<T, D, OFF32>(P, xs, off, n, xi, visit);
         }
         const uint32_t o = perm[s];
 #pragma unroll
