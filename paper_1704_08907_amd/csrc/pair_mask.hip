@@ -122,10 +122,28 @@ __global__ __launch_bounds__(256) void k_lane_mask(const T* __restrict__ xs, con
         };
         // candidates [ja, jb): the summand of each accepted one, and its bit shifted
         // into rec from the bottom (the row's first candidate ends highest; the
-        // record is bit-reversed when the row is done); two candidates per iteration
+        // record is bit-reversed when the row is done)
         auto scan = [&](auto shift_tag, uint32_t ja, uint32_t jb, const T* sh, uint64_t& rec) {
             constexpr bool SHIFT = decltype(shift_tag)::value;
             uint32_t j = ja;
+            // float: four candidates per iteration keep four loads in flight (the
+            // float64 kernel, with twice the registers per row, stays at two)
+            for (; sizeof(T) == 4 && j + 3 < jb; j += 4) {
+                const VecN<T, PITCH> xa = load_row<T, PITCH, OFF32>(xs, j);
+                const VecN<T, PITCH> xb = load_row<T, PITCH, OFF32>(xs, j + 1);
+                const VecN<T, PITCH> xc = load_row<T, PITCH, OFF32>(xs, j + 2);
+                const VecN<T, PITCH> xd = load_row<T, PITCH, OFF32>(xs, j + 3);
+                T dx[D], d2;
+                const bool oa = pair_test<T, D, SHIFT>(xa.v, xi, sh, r2, dx, &d2);
+                if (oa) visit(j, dx, d2);
+                const bool ob = pair_test<T, D, SHIFT>(xb.v, xi, sh, r2, dx, &d2);
+                if (ob) visit(j + 1, dx, d2);
+                const bool oc = pair_test<T, D, SHIFT>(xc.v, xi, sh, r2, dx, &d2);
+                if (oc) visit(j + 2, dx, d2);
+                const bool od = pair_test<T, D, SHIFT>(xd.v, xi, sh, r2, dx, &d2);
+                if (od) visit(j + 3, dx, d2);
+                rec = (rec << 4) | (oa ? 8u : 0u) | (ob ? 4u : 0u) | (oc ? 2u : 0u) | (od ? 1u : 0u);
+            }
             for (; j + 1 < jb; j += 2) {
                 const VecN<T, PITCH> xa = load_row<T, PITCH, OFF32>(xs, j);
                 const VecN<T, PITCH> xb = load_row<T, PITCH, OFF32>(xs, j + 1);
