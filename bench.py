@@ -2,19 +2,25 @@
 
 A step is one pass of the whole hot path over the 2^20-particle periodic cube
 (spring force, ~30 neighbours within r = 1, float32): rebuild the cell list
-from the original-order positions (cell ids, radix sort, offsets, gather),
-record every particle's neighbours by one box search, the neighbour-sum
-forward and its adjoint for a seeded upstream gradient (both replaying the
-recorded neighbours).  The step is captured once as a HIP graph and replayed.
-The headline value is ordered pair interactions per second of the step.  The
-same step with both sums doing their own box search is timed beside it.
+from the original-order positions (cell ids, radix sort, offsets, gather), the
+neighbour-sum forward and its adjoint for a seeded upstream gradient.  The step
+is captured once as a HIP graph and replayed; the headline value is ordered
+pair interactions per second of the step.  Three forms of the step are timed
+on three grids (cells about r wide, and r/2 or r/3 wide along x): both sums
+searching the box, a recorded neighbour list replayed by both, and a forward
+that records each row's accepted candidates for the adjoint to replay.  The
+headline takes the fastest form on the --reach grid.
 
-Besides the JSON line's roofline (dominant kernel, HIP-event timed) and the
-CPU baseline (the C oracle, single thread, bounded sample), the line carries
-the per-phase breakdown and the other workloads: the dense Gaussian sum, the
-soft-sphere forward+adjoint, and 512 uneven systems in one graph.
+Besides the JSON line's roofline (the longer call of the step, HIP-event
+timed; traffic from the committed rocprofv3 counter summary) and the CPU
+baseline (the C oracle, single thread, bounded sample), the line carries the
+per-phase breakdown, the per-variant table and the other workloads: candidate
+reduction at reach 2, the dense Gaussian and multiquadric sums and adjoint, the
+soft-sphere energy gradient, 512 uneven systems in one graph, the molecular
+dynamics example and the small-N workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                    [--no-extra] [--reach 3,1,1] [--no-reach-trials]
 """
 from __future__ import annotations
 
