@@ -97,3 +97,24 @@ def test_spring_gradient_through_autograd_equals_the_row_search(ctx):
     ctx.sync()
     assert torch.equal(y.detach(), y2) and torch.equal(gx, gx2)
     assert torch.equal(y3.detach(), y2) and torch.equal(gx3, gx2)
+
+
+def test_autograd_on_cells_narrower_along_x(ctx):
+    # reach {3, 1, 1}: the autograd pair records masks there too; equal to the row search
+    w = syn.spring_cube(n=30000)
+    s = w.systems[0]
+    box = A.BoxSpec(3, s.lo, s.hi, s.periodic, s.cutoff, None, [3, 1, 1])
+    gy = torch.from_numpy(w.extra["gy"][: s.n]).to("cuda:0")
+    x = torch.tensor(s.x, device="cuda:0", requires_grad=True)
+    y = diff_pair_sum(x, ctx, [box], "spring", (1.0,))
+    (gx,) = torch.autograd.grad(y, x, gy)
+    plain = next(v for v in range(A.variant_count()) if "adjoint evaluated on every candidate" in A.variant_name(v))
+    cells = A.build_cells(ctx, x.detach(), [box])
+    ctx.set_variant(plain)
+    try:
+        y2 = A.pair_sum(ctx, cells, "spring", (1.0,))
+        gx2, _ = A.pair_sum_backward(ctx, cells, "spring", (1.0,), gy)
+    finally:
+        ctx.set_variant(-1)
+    ctx.sync()
+    assert torch.equal(y.detach(), y2) and torch.equal(gx, gx2)
