@@ -98,16 +98,12 @@ def profile_names(variant_name, direction):
     32-bit row offsets)."""
     if "recorded" in variant_name:
         k = ["k_nbr_fwd<float, 3, 1, false>"] if direction == "fwd" else ["k_nbr_bwd<float, 3, 1, false>"]
-    elif "cell group" in variant_name or "LDS list" in variant_name or "staged" in variant_name:
-        return None
     elif "accepted-pair bit masks" in variant_name:
         k = ["k_lane_mask<float, 3, 1, false, true, %d>" % (0 if direction == "fwd" else 1)]
     elif "flattened" in variant_name:
         k = ["k_flat<float, 3, 1, false, true, %d>" % (0 if direction == "fwd" else 1)]
     elif direction == "fwd":
         k = ["k_lane_fwd<float, 3, 1, false, true>"]
-    elif "queue" in variant_name:
-        k = ["k_lane_bwd_queue<float, 3, 1, false>"]
     else:
         k = ["k_lane_bwd<float, 3, 1, false, true>"]
     return k if direction == "fwd" else ["k_gather_rows<float, 3, 4>"] + k

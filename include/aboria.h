@@ -89,9 +89,8 @@ typedef enum aboria_kernel {
  * 2.2.2).  m = 2 or 3 uses cells about r/m wide searched m cells deep, which
  * tests fewer candidates; the pair set is the same, since the pair predicate
  * alone decides it.  A deeper reach along x only (e.g. {2, 1, 1}) keeps the
- * 3^(d-1) rows of the search and shortens each.  The cell-group, LDS-list,
- * wave-queue and LDS-staged variants need m = 1 in every dimension; the
- * recorded-mask variant needs it in every dimension but x.
+ * 3^(d-1) rows of the search and shortens each.  The recorded-mask variant
+ * needs m = 1 in every dimension but x.
  *
  * ncell[k] = 0 picks the cell count automatically: the largest count whose
  * cells are at least (cutoff + a rounding guard) / m wide.  An explicit count

@@ -34,7 +34,7 @@ class OracleError(RuntimeError):
 def build() -> str:
     """Compile oracle.c.  Contraction is off so that every fma is the explicit one."""
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
-           "-fno-fast-math", "-Wall", "-o", LIB + ".tmp", SRC, "-lm"]
+           "-fno-fast-math", "-Wall", "-o", LIB + ".tmp", SRC, "-lm", "-lpthread"]
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
     return LIB
@@ -67,14 +67,14 @@ def lib():
         L.or_pairs.argtypes = [C.POINTER(Grid), C.c_int32, C.c_int64, P, C.c_int64, P, P]
         L.or_pairs.restype = C.c_int64
         L.or_pair_sum.argtypes = [C.POINTER(Grid), C.c_int32, C.c_int32, P, C.c_int64, P, P,
-                                  C.c_int64, P, P, P]
+                                  C.c_int64, P, P, P, P, C.c_int32]
         L.or_pair_sum_backward.argtypes = [C.POINTER(Grid), C.c_int32, C.c_int32, P, C.c_int64, P, P,
-                                           P, C.c_int64, P, P, P, P, P]
+                                           P, C.c_int64, P, P, P, P, P, P, P, C.c_int32]
         L.or_fd_grad.argtypes = [C.POINTER(Grid), C.c_int32, P, C.c_int64, P, P, P, C.c_int64, P,
                                  C.c_double, P]
         L.or_dense_gauss.argtypes = [C.c_int32, C.c_int64, P, C.c_int64, P, P, C.c_double,
                                      C.c_int64, P, P, P]
-        L.or_md_step.argtypes = [C.POINTER(Grid), C.c_int32, C.c_double, C.c_double, C.c_int64, P, P, P]
+        L.or_md_step.argtypes = [C.POINTER(Grid), C.c_int32, C.c_double, C.c_double, C.c_int64, P, P, P, P]
         L.or_dense_sum.argtypes = [C.c_int32, C.c_double, C.c_int32, C.c_int64, P, C.c_int64, P, P, P, P]
         L.or_dense_backward.argtypes = [C.c_int32, C.c_double, C.c_int32, C.c_int64, P, C.c_int64, P, P, P,
                                         P, P, P, P, P, P]
@@ -158,8 +158,51 @@ def op_ny(op: str, d: int) -> int:
     return lib().or_op_ny(OPS[op], d)
 
 
-def pair_sum(g: Grid, op: str, params, x, a=None, rows=None, route=ROUTE_CELLS):
-    """(y, scale) in float64: y[row][ny], scale[row] = sum of |summand|_inf."""
+# Allowance for the rounding of a summand's displacement and distance, in units
+# of the working precision's unit roundoff (reading R6 in oracle.c).
+COND_ULPS = 16.0
+
+
+class RowScale:
+    """The two per-row scales of reading R6 (oracle.c) for one output.
+
+    s[row]: sum over the row's summands of their max-norm (the absolute-sum
+    scale of a relative tolerance).  d[row]: sum over the row's summands of
+    their condition with respect to the pair displacement.  u: unit roundoff
+    of the working precision.  A result row passes at tolerance tol when
+    |got - ref|_inf <= tol * s + COND_ULPS * u * d."""
+
+    def __init__(self, s, d, u):
+        self.s = np.asarray(s, dtype=np.float64)
+        self.d = np.asarray(d, dtype=np.float64)
+        self.u = float(u)
+
+    def bound(self, tol):
+        return tol * self.s + COND_ULPS * self.u * self.d
+
+    def __getitem__(self, idx):
+        return RowScale(self.s[idx], self.d[idx], self.u)
+
+    def __len__(self):
+        return self.s.shape[0]
+
+
+def unit_roundoff(g: Grid) -> float:
+    return 2.0 ** -24 if g.dtype == F32 else 2.0 ** -53
+
+
+def _threads(nthreads):
+    if nthreads is None:
+        return 1
+    if nthreads == "all":
+        return len(os.sched_getaffinity(0))
+    return max(1, int(nthreads))
+
+
+def pair_sum(g: Grid, op: str, params, x, a=None, rows=None, route=ROUTE_CELLS, scales=True, nthreads=None):
+    """(y, RowScale) in float64, or y alone with scales=False (then nothing
+    beyond the plain sum is computed).  nthreads: threads over rows (an
+    integer, or "all" for every core this process may run on)."""
     x = _f64(x)
     n = x.shape[0]
     a = _f64(a)
@@ -168,13 +211,14 @@ def pair_sum(g: Grid, op: str, params, x, a=None, rows=None, route=ROUTE_CELLS):
     m = n if rows is None else rows_a.shape[0]
     ny = op_ny(op, g.d)
     y = np.zeros((m, ny))
-    sc = np.zeros(m)
+    sc = np.zeros(m) if scales else None
+    cd = np.zeros(m) if scales else None
     st = lib().or_pair_sum(C.byref(g), route, OPS[op], _ptr(prm), n, _ptr(x),
                            _ptr(a if a is None else a.reshape(-1)), m if rows is not None else 0,
-                           _ptr(rows_a), _ptr(y), _ptr(sc))
+                           _ptr(rows_a), _ptr(y), _ptr(sc), _ptr(cd), _threads(nthreads))
     if st != OK:
         raise OracleError(st, "pair_sum")
-    return y, sc
+    return (y, RowScale(sc, cd, unit_roundoff(g))) if scales else y
 
 
 KERNELS = {"gaussian": 0, "multiquadric": 1}
@@ -213,19 +257,23 @@ def md_step(g: Grid, c: float, dt: float, x, v, route=ROUTE_CELLS):
     """One time step of the Section 3 example in float64: returns (x_new, v_new, scale_v).
 
     v_new = v + dt (c S), S_i = sum_j -exp(-|dx|) dx/|dx| over the neighbours;
-    x_new = x + dt v_new wrapped into the box in periodic dimensions."""
+    x_new = x + dt v_new wrapped into the box in periodic dimensions; scale_v
+    is the RowScale of the velocity change dt c S."""
     x = np.array(_f64(x), dtype=np.float64, copy=True, order="C")
     v = np.array(_f64(v), dtype=np.float64, copy=True, order="C")
     n = x.shape[0]
     sc = np.zeros(max(n, 1))
-    st = lib().or_md_step(C.byref(g), route, float(c), float(dt), n, _ptr(x), _ptr(v), _ptr(sc))
+    cd = np.zeros(max(n, 1))
+    st = lib().or_md_step(C.byref(g), route, float(c), float(dt), n, _ptr(x), _ptr(v), _ptr(sc), _ptr(cd))
     if st != OK:
         raise OracleError(st, "md_step")
-    return x, v, sc[:n]
+    return x, v, RowScale(sc[:n], cd[:n], unit_roundoff(g))
 
 
-def pair_sum_backward(g: Grid, op: str, params, x, gy, a=None, rows=None, route=ROUTE_CELLS):
-    """(gx, ga, scale_x, scale_a) in float64 for L = sum_i gy_i . y_i."""
+def pair_sum_backward(g: Grid, op: str, params, x, gy, a=None, rows=None, route=ROUTE_CELLS, scales=True,
+                      nthreads=None):
+    """(gx, ga, RowScale of gx, RowScale of ga) in float64 for L = sum_i gy_i . y_i,
+    or (gx, ga) with scales=False.  nthreads as in pair_sum."""
     x = _f64(x)
     n = x.shape[0]
     a = _f64(a)
@@ -235,15 +283,17 @@ def pair_sum_backward(g: Grid, op: str, params, x, gy, a=None, rows=None, route=
     m = n if rows is None else rows_a.shape[0]
     gx = np.zeros((m, g.d))
     ga = np.zeros(m)
-    sx = np.zeros(m)
-    sa = np.zeros(m)
+    sx, cx, sa, ca = ((np.zeros(m), np.zeros(m), np.zeros(m), np.zeros(m)) if scales else (None,) * 4)
     st = lib().or_pair_sum_backward(C.byref(g), route, OPS[op], _ptr(prm), n, _ptr(x),
                                     _ptr(a if a is None else a.reshape(-1)), _ptr(gy),
                                     m if rows is not None else 0, _ptr(rows_a), _ptr(gx),
-                                    _ptr(ga), _ptr(sx), _ptr(sa))
+                                    _ptr(ga), _ptr(sx), _ptr(cx), _ptr(sa), _ptr(ca), _threads(nthreads))
     if st != OK:
         raise OracleError(st, "pair_sum_backward")
-    return gx, ga, sx, sa
+    if not scales:
+        return gx, ga
+    u = unit_roundoff(g)
+    return gx, ga, RowScale(sx, cx, u), RowScale(sa, ca, u)
 
 
 def fd_grad(g: Grid, op: str, params, x, gy, coords, h, a=None):

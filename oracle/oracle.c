@@ -54,15 +54,28 @@
  *      sphere e_i = 1/2 sum (1 - s/r)^2; the paper's eq. (1) force
  *      y_i = sum -c exp(-s) dx/s; a spring with per-particle resting lengths
  *      y_i = sum k (a_i + a_j - s) u/s (the DEM example of Section 1.1).
- *   R6 the error scale of a row (what "relative tolerance" is relative to): the
- *      sum over its summands of (a) the summand's formula evaluated with every
- *      input and intermediate replaced by its magnitude -- the componentwise
- *      forward-error scale of a floating-point evaluation -- plus (b) the
- *      summand's first-order change under a relative change of the pair
- *      displacement, which rounding of the pair distance causes.  A summand that
- *      cancels near the cutoff (k (r - s) as s -> r) cannot be evaluated in
- *      float32 more accurately than its distance is rounded, so its own
- *      magnitude alone is not a usable scale.
+ *   R6 what a result is compared against.  Each output row gets two scales:
+ *      S = the sum over the row's summands of their max-norm (the absolute-sum
+ *      scale of a relative tolerance), and D = the sum over the row's summands
+ *      of max_k sum_q |d f_k / d q| base_q, the summand's condition with respect
+ *      to the quantities an evaluation in precision P forms by rounding: each
+ *      displacement coordinate u_m (base |raw_m| + |u_m|, raw_m = x_jm - x_im
+ *      the difference reading R3 rounds before the periodic shift is added),
+ *      each coordinate of the upstream gradients a pair combines (gy_i - gy_j
+ *      or gy_i + gy_j, base |gy_im| + |gy_jm|) and the per-particle variables
+ *      (a_i + a_j, base |a_i| + |a_j|).  Each of these carries a rounding of
+ *      at most u_P base_q, and the distance and the functions of it a few u_P
+ *      relative (a perturbation of |u|), so a correct P evaluation differs
+ *      from the exact summand by a few u_P D plus a few u_P |f|.  A row i
+ *      passes at tolerance tol when |y_i - y*_i|_inf <= tol S_i + 16 u_P D_i;
+ *      16 u_P is the same allowance the cell-count guard of R1 gives the
+ *      rounding of a coordinate.  Near the cutoff k (r - s) -> 0 while its
+ *      rounding does not; across a periodic face the displacement inherits the
+ *      rounding of a coordinate up to L; and an adjoint summand g w_perp +
+ *      gpar w_par with g ~ k r/s at a close pair amplifies the rounding of w
+ *      by g: the D term carries exactly these, the S term everything else.
+ *      The partial derivatives are forward differences of the float64 summand
+ *      with the step 2^-20 base_q.
  *   R8 the multiquadric basis of the Section 1.1 RBF example, whose formula the
  *      paper does not print: Hardy's K(x, x') = sqrt(|x - x'|^2 + c^2), c > 0.
  *   R7 the periodic domain of the time step: after x += dt v, a coordinate at
@@ -72,6 +85,7 @@
  *      Non-periodic coordinates are not wrapped.
  */
 #include <math.h>
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -362,10 +376,43 @@ static void visit_brute(const or_grid* g, int64_t n, const double* x, int64_t i,
     }
 }
 
-/* Visit the accepted neighbours of each requested row by the chosen route. */
+/* Visit the accepted neighbours of each requested row by the chosen route.
+ * With nthreads > 1 the rows are split into nthreads contiguous blocks, one
+ * POSIX thread each; ctxs[t] is thread t's own context (row_begin and fn only
+ * ever see the context of the thread that runs the row), so the threads share
+ * nothing they write.  Every row is computed exactly as in one thread. */
+typedef struct {
+    const or_grid* g;
+    int route;
+    int64_t n;
+    const double* x;
+    const int64_t* rows;
+    const linked_cells* lc;
+    visit_fn fn;
+    void (*row_begin)(void*, int64_t, int64_t);
+    void* ctx;
+    int64_t r0, r1;
+} rows_job;
+
+static void* rows_worker(void* vjob) {
+    rows_job* J = (rows_job*)vjob;
+    for (int64_t r = J->r0; r < J->r1; ++r) {
+        int64_t i = J->rows ? J->rows[r] : r;
+        if (i < 0 || i >= J->n) continue;
+        if (J->row_begin) J->row_begin(J->ctx, r, i);
+        if (J->route == OR_ROUTE_CELLS)
+            visit_cells(J->g, J->lc, J->x, i, J->fn, J->ctx);
+        else
+            visit_brute(J->g, J->n, J->x, i, J->fn, J->ctx);
+    }
+    return NULL;
+}
+
+#define OR_MAX_THREADS 256
+
 static int for_rows(const or_grid* g, int route, int64_t n, const double* x, int64_t nrows,
-                    const int64_t* rows, visit_fn fn, void** ctxs, void (*row_begin)(void*, int64_t, int64_t),
-                    void* rctx) {
+                    const int64_t* rows, visit_fn fn, void (*row_begin)(void*, int64_t, int64_t), void** ctxs,
+                    int nthreads) {
     linked_cells lc = {0, 0};
     int st = OR_OK;
     if (route == OR_ROUTE_CELLS) {
@@ -373,14 +420,24 @@ static int for_rows(const or_grid* g, int route, int64_t n, const double* x, int
         if (st == OR_ERR_NOMEM) { free_linked(&lc); return st; }
     }
     int64_t m = rows ? nrows : n;
-    for (int64_t r = 0; r < m; ++r) {
-        int64_t i = rows ? rows[r] : r;
-        if (i < 0 || i >= n) continue;
-        if (row_begin) row_begin(rctx, r, i);
-        if (route == OR_ROUTE_CELLS)
-            visit_cells(g, &lc, x, i, fn, ctxs[0]);
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > OR_MAX_THREADS) nthreads = OR_MAX_THREADS;
+    if ((int64_t)nthreads > m) nthreads = m > 0 ? (int)m : 1;
+    rows_job jobs[OR_MAX_THREADS];
+    pthread_t tid[OR_MAX_THREADS];
+    int started[OR_MAX_THREADS];
+    for (int t = 0; t < nthreads; ++t) {
+        rows_job J = {g, route, n, x, rows, &lc, fn, row_begin, ctxs[t], m * t / nthreads, m * (t + 1) / nthreads};
+        jobs[t] = J;
+        started[t] = 0;
+    }
+    for (int t = 1; t < nthreads; ++t) started[t] = pthread_create(&tid[t], NULL, rows_worker, &jobs[t]) == 0;
+    rows_worker(&jobs[0]);
+    for (int t = 1; t < nthreads; ++t) {
+        if (started[t])
+            pthread_join(tid[t], NULL);
         else
-            visit_brute(g, n, x, i, fn, ctxs[0]);
+            rows_worker(&jobs[t]); /* no thread available: run the block here */
     }
     if (route == OR_ROUTE_CELLS) free_linked(&lc);
     return st;
@@ -412,7 +469,7 @@ int64_t or_pairs(const or_grid* g, int32_t route, int64_t n, const double* x, in
                  uint32_t* pj) {
     pair_list_ctx c = {0, cap, pi, pj};
     void* ctxs[1] = {&c};
-    int st = for_rows(g, route, n, x, 0, NULL, add_pair, ctxs, NULL, NULL);
+    int st = for_rows(g, route, n, x, 0, NULL, add_pair, NULL, ctxs, 1);
     if (st == OR_ERR_NOMEM) return -1;
     return c.count;
 }
@@ -472,54 +529,38 @@ static double radial_g(int op, const double* prm, double r, double s, double ai,
     }
 }
 
-/* |g(s)| evaluated with every operand of its subtractions taken by magnitude
- * (k (r + s)/s for k (r - s)/s): the size of the quantities a floating-point
- * evaluation of g combines. */
-static double radial_g_mag(int op, const double* prm, double r, double s, double ai, double aj) {
-    switch (op) {
-        case OR_OP_SPRING: return fabs(prm[0]) * (r + s) / s;
-        case OR_OP_EXP_FORCE: return fabs(prm[0]) * exp(-s) / s;
-        case OR_OP_DEM_SPRING: return fabs(prm[0]) * (fabs(ai) + fabs(aj) + s) / s;
-        default: return 0.0;
-    }
-}
-
-/* Forward summand of one ordered pair, u = x_i - (x_j + shift), in float64;
- * mag[k] is the same formula evaluated on magnitudes. */
+/* Forward summand of one ordered pair, u = x_i - (x_j + shift), in float64. */
 static void fwd_term(const or_grid* g, int op, const double* prm, const double* u, double ai, double aj,
-                     double* t, double* mag) {
+                     double* t) {
     double s2 = 0.0;
     for (int k = 0; k < g->d; ++k) s2 += u[k] * u[k];
     double dist = sqrt(s2);
     switch (op) {
         case OR_OP_COUNT:
-            t[0] = mag[0] = 1.0;
+            t[0] = 1.0;
             break;
         case OR_OP_SOFT_SPHERE: {
             double v = 1.0 - dist / g->r;
-            double va = 1.0 + dist / g->r;
             t[0] = 0.5 * v * v;
-            mag[0] = 0.5 * va * va;
             break;
         }
         default: {
             double dg;
             double gv = radial_g(op, prm, g->r, dist, ai, aj, &dg);
-            double gm = radial_g_mag(op, prm, g->r, dist, ai, aj);
-            for (int k = 0; k < g->d; ++k) {
-                t[k] = gv * u[k];
-                mag[k] = gm * fabs(u[k]);
-            }
+            for (int k = 0; k < g->d; ++k) t[k] = gv * u[k];
             break;
         }
     }
 }
 
-/* Relative step used to measure how strongly a summand reacts to a relative
- * change of its pair displacement (what rounding of the pair distance does to
- * a computed summand).  The tolerance scale of a row adds this first-order
- * sensitivity to the summands' magnitudes. */
-#define OR_SENS_EPS 1e-6
+/* Relative forward-difference step of the condition D of reading R6. */
+#define OR_COND_EPS 0x1p-20
+
+/* raw = x_j - x_i (the difference reading R3 rounds before the shift). */
+static void pair_raw(const or_grid* g, const double* xi, const double* xj, double* raw) {
+    for (int k = 0; k < 3; ++k) raw[k] = 0.0;
+    for (int k = 0; k < g->d; ++k) raw[k] = xj[k] - xi[k];
+}
 
 typedef struct {
     const or_grid* g;
@@ -528,56 +569,84 @@ typedef struct {
     const double* x;
     const double* a;
     int ny;
+    double* y;      /* [rows][ny] */
+    double* scale;  /* [rows] or NULL */
+    double* cond;   /* [rows] or NULL */
     double* yrow;
     double* srow;
+    double* crow;
 } sum_ctx;
 
 static void sum_begin(void* vctx, int64_t r, int64_t i) {
     (void)i;
-    sum_ctx* c = (sum_ctx*)((void**)vctx)[0];
-    double* y = (double*)((void**)vctx)[1];
-    double* sc = (double*)((void**)vctx)[2];
-    c->yrow = y + r * c->ny;
-    c->srow = sc ? sc + r : NULL;
+    sum_ctx* c = (sum_ctx*)vctx;
+    c->yrow = c->y + r * c->ny;
+    c->srow = c->scale ? c->scale + r : NULL;
+    c->crow = c->cond ? c->cond + r : NULL;
     for (int m = 0; m < c->ny; ++m) c->yrow[m] = 0.0;
     if (c->srow) *c->srow = 0.0;
+    if (c->crow) *c->crow = 0.0;
 }
 
 static void sum_pair(void* vctx, int64_t i, int64_t j, const double* s) {
     sum_ctx* c = (sum_ctx*)vctx;
     const or_grid* g = c->g;
-    double u[3], up[3], t[3] = {0, 0, 0}, tp[3] = {0, 0, 0}, mag[3] = {0, 0, 0}, magp[3];
+    double u[3], t[3] = {0, 0, 0};
     pair_u(g, c->x + i * g->d, c->x + j * g->d, s, u);
     double ai = c->a ? c->a[i] : 0.0, aj = c->a ? c->a[j] : 0.0;
-    fwd_term(g, c->op, c->prm, u, ai, aj, t, mag);
+    fwd_term(g, c->op, c->prm, u, ai, aj, t);
     for (int k = 0; k < c->ny; ++k) c->yrow[k] += t[k];
     if (c->srow) {
-        for (int k = 0; k < 3; ++k) up[k] = u[k] * (1.0 + OR_SENS_EPS);
-        fwd_term(g, c->op, c->prm, up, ai, aj, tp, magp);
-        double mx = 0.0, sens = 0.0;
-        for (int k = 0; k < c->ny; ++k) {
-            if (mag[k] > mx) mx = mag[k];
-            double dk = fabs(tp[k] - t[k]) / OR_SENS_EPS;
-            if (dk > sens) sens = dk;
+        double mx = 0.0;
+        for (int k = 0; k < c->ny; ++k)
+            if (fabs(t[k]) > mx) mx = fabs(t[k]);
+        *c->srow += mx;
+    }
+    if (c->crow) {
+        /* D: sum over the formed quantities q of |df/dq| base_q, max over outputs:
+         * the displacement coordinates (base |raw_m| + |u_m|) and the sum of the
+         * per-particle variables (base |a_i| + |a_j|) */
+        double raw[3], acc[3] = {0, 0, 0};
+        pair_raw(g, c->x + i * g->d, c->x + j * g->d, raw);
+        for (int m = 0; m < g->d; ++m) {
+            double base = fabs(raw[m]) + fabs(u[m]);
+            double up[3] = {u[0], u[1], u[2]}, tp[3] = {0, 0, 0};
+            up[m] += OR_COND_EPS * base;
+            fwd_term(g, c->op, c->prm, up, ai, aj, tp);
+            for (int k = 0; k < c->ny; ++k) acc[k] += fabs(tp[k] - t[k]) / OR_COND_EPS;
         }
-        *c->srow += mx + sens;
+        if (c->a) {
+            double tp[3] = {0, 0, 0};
+            fwd_term(g, c->op, c->prm, u, ai + OR_COND_EPS * (fabs(ai) + fabs(aj)), aj, tp);
+            for (int k = 0; k < c->ny; ++k) acc[k] += fabs(tp[k] - t[k]) / OR_COND_EPS;
+        }
+        double mx = 0.0;
+        for (int k = 0; k < c->ny; ++k)
+            if (acc[k] > mx) mx = acc[k];
+        *c->crow += mx;
     }
 }
 
 /* y[row][ny] = sum over the accepted neighbours of the requested rows (all rows
- * if rows == NULL).  scale[row] = sum over the row's summands of their max-norm
- * plus their first-order sensitivity to a relative change of the pair
- * displacement: the scale a float32 evaluation's error is measured against.
- * a is [n] or NULL. */
+ * if rows == NULL).  scale[row] = S and cond[row] = D of reading R6; either may
+ * be NULL, and with both NULL nothing beyond the plain sum is computed.  a is
+ * [n] or NULL.  nthreads >= 1 threads split the rows. */
 int or_pair_sum(const or_grid* g, int32_t route, int32_t op, const double* prm, int64_t n, const double* x,
-                const double* a, int64_t nrows, const int64_t* rows, double* y, double* scale) {
+                const double* a, int64_t nrows, const int64_t* rows, double* y, double* scale, double* cond,
+                int32_t nthreads) {
     int ny = or_op_ny(op, g->d);
     if (ny < 0) return OR_ERR_INVALID;
     if (or_op_na(op) && !a) return OR_ERR_INVALID;
-    sum_ctx c = {g, op, prm, x, a, ny, NULL, NULL};
-    void* begin_ctx[3] = {&c, y, scale};
-    void* ctxs[1] = {&c};
-    int st = for_rows(g, route, n, x, nrows, rows, sum_pair, ctxs, sum_begin, begin_ctx);
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > OR_MAX_THREADS) nthreads = OR_MAX_THREADS;
+    sum_ctx c[OR_MAX_THREADS];
+    void* ctxs[OR_MAX_THREADS];
+    for (int t = 0; t < nthreads; ++t) {
+        sum_ctx ct = {g, op, prm, x, a, ny, y, scale, cond, NULL, NULL, NULL};
+        c[t] = ct;
+        ctxs[t] = &c[t];
+    }
+    int st = for_rows(g, route, n, x, nrows, rows, sum_pair, sum_begin, ctxs, nthreads);
     return st == OR_ERR_NOMEM ? st : OR_OK;
 }
 
@@ -599,111 +668,133 @@ typedef struct {
     const double* a;
     const double* gy;
     int ny;
-    double* gxrow;
-    double* garow;
-    double* sxrow;
-    double* sarow;
+    double *gx, *ga, *sx, *cx, *sa, *ca;             /* outputs, [rows][d] / [rows] */
+    double *gxrow, *garow, *sxrow, *cxrow, *sarow, *carow;
 } bwd_ctx;
 
 static void bwd_begin(void* vctx, int64_t r, int64_t i) {
     (void)i;
-    void** v = (void**)vctx;
-    bwd_ctx* c = (bwd_ctx*)v[0];
-    double* gx = (double*)v[1];
-    double* ga = (double*)v[2];
-    double* sx = (double*)v[3];
-    double* sa = (double*)v[4];
-    c->gxrow = gx + r * c->g->d;
-    c->garow = ga ? ga + r : NULL;
-    c->sxrow = sx ? sx + r : NULL;
-    c->sarow = sa ? sa + r : NULL;
+    bwd_ctx* c = (bwd_ctx*)vctx;
+    c->gxrow = c->gx + r * c->g->d;
+    c->garow = c->ga ? c->ga + r : NULL;
+    c->sxrow = c->sx ? c->sx + r : NULL;
+    c->cxrow = c->cx ? c->cx + r : NULL;
+    c->sarow = c->sa ? c->sa + r : NULL;
+    c->carow = c->ca ? c->ca + r : NULL;
     for (int k = 0; k < c->g->d; ++k) c->gxrow[k] = 0.0;
     if (c->garow) *c->garow = 0.0;
     if (c->sxrow) *c->sxrow = 0.0;
+    if (c->cxrow) *c->cxrow = 0.0;
     if (c->sarow) *c->sarow = 0.0;
+    if (c->carow) *c->carow = 0.0;
 }
 
-/* Adjoint contribution of the ordered pair (k, i), u = x_k - (x_i + shift);
- * mag[m] receives the summed magnitudes of the products that make up gx[m]. */
+/* Adjoint contribution of the ordered pair (k, i), u = x_k - (x_i + shift). */
 static void bwd_term(const or_grid* g, int op, const double* prm, const double* u, double ak, double ai,
-                     const double* gyk, const double* gyi, double* gx, double* ga, double* mag,
-                     double* gamag) {
+                     const double* gyk, const double* gyi, double* gx, double* ga) {
     int d = g->d;
     double s2 = 0.0;
     for (int m = 0; m < d; ++m) s2 += u[m] * u[m];
     double dist = sqrt(s2);
-    for (int m = 0; m < 3; ++m) gx[m] = mag[m] = 0.0;
-    *ga = *gamag = 0.0;
+    for (int m = 0; m < 3; ++m) gx[m] = 0.0;
+    *ga = 0.0;
     if (op == OR_OP_COUNT) return;
     if (op == OR_OP_SOFT_SPHERE) {
         double dphi = -(2.0 / g->r) * (1.0 - dist / g->r);
         double coef = 0.5 * (gyk[0] + gyi[0]) * dphi / dist;
-        double cmag = 0.5 * (fabs(gyk[0]) + fabs(gyi[0])) * (2.0 / g->r) * (1.0 + dist / g->r) / dist;
-        for (int m = 0; m < d; ++m) {
-            gx[m] = coef * u[m];
-            mag[m] = cmag * fabs(u[m]);
-        }
+        for (int m = 0; m < d; ++m) gx[m] = coef * u[m];
         return;
     }
     double dg;
     double gv = radial_g(op, prm, g->r, dist, ak, ai, &dg);
-    double gm = radial_g_mag(op, prm, g->r, dist, ak, ai);
-    double w[3] = {0, 0, 0}, wm[3] = {0, 0, 0};
-    double uw = 0.0, uwm = 0.0;
+    double w[3] = {0, 0, 0};
+    double uw = 0.0;
     for (int m = 0; m < d; ++m) {
         w[m] = gyk[m] - gyi[m];
-        wm[m] = fabs(gyk[m]) + fabs(gyi[m]);
         uw += u[m] * w[m];
-        uwm += fabs(u[m]) * wm[m];
     }
-    for (int m = 0; m < d; ++m) {
-        gx[m] = gv * w[m] + (dg / dist) * uw * u[m];
-        mag[m] = gm * wm[m] + fabs(dg / dist) * uwm * fabs(u[m]);
-    }
-    if (op == OR_OP_DEM_SPRING) {
-        *ga = prm[0] * uw / dist;
-        *gamag = fabs(prm[0]) * uwm / dist;
-    }
+    for (int m = 0; m < d; ++m) gx[m] = gv * w[m] + (dg / dist) * uw * u[m];
+    if (op == OR_OP_DEM_SPRING) *ga = prm[0] * uw / dist;
 }
 
 static void bwd_pair(void* vctx, int64_t k, int64_t i, const double* s) {
     bwd_ctx* c = (bwd_ctx*)vctx;
     const or_grid* g = c->g;
     int d = g->d;
-    double u[3], up[3], t[3], tp[3], mag[3], magp[3], ta, tap, tam, tamp;
+    double u[3], t[3], ta;
     pair_u(g, c->x + k * d, c->x + i * d, s, u);
     const double* gyk = c->gy + k * c->ny;
     const double* gyi = c->gy + i * c->ny;
     double ak = c->a ? c->a[k] : 0.0, ai = c->a ? c->a[i] : 0.0;
-    bwd_term(g, c->op, c->prm, u, ak, ai, gyk, gyi, t, &ta, mag, &tam);
+    bwd_term(g, c->op, c->prm, u, ak, ai, gyk, gyi, t, &ta);
     for (int m = 0; m < d; ++m) c->gxrow[m] += t[m];
     if (c->garow) *c->garow += ta;
-    for (int m = 0; m < 3; ++m) up[m] = u[m] * (1.0 + OR_SENS_EPS);
-    bwd_term(g, c->op, c->prm, up, ak, ai, gyk, gyi, tp, &tap, magp, &tamp);
     if (c->sxrow) {
-        double mx = 0.0, sens = 0.0;
-        for (int m = 0; m < d; ++m) {
-            if (mag[m] > mx) mx = mag[m];
-            double dm = fabs(tp[m] - t[m]) / OR_SENS_EPS;
-            if (dm > sens) sens = dm;
-        }
-        *c->sxrow += mx + sens;
+        double mx = 0.0;
+        for (int m = 0; m < d; ++m)
+            if (fabs(t[m]) > mx) mx = fabs(t[m]);
+        *c->sxrow += mx;
     }
-    if (c->sarow) *c->sarow += tam + fabs(tap - ta) / OR_SENS_EPS;
+    if (c->sarow) *c->sarow += fabs(ta);
+    if (c->cxrow || c->carow) {
+        /* D over the displacement coordinates, the coordinates of the upstream
+         * gradients the pair combines (base |gy_k,m| + |gy_i,m|: gy_k - gy_i or
+         * gy_k + gy_i is formed in P) and the per-particle variables */
+        double raw[3], acc[3] = {0, 0, 0}, acca = 0.0;
+        double tp[3], tap;
+        pair_raw(g, c->x + k * d, c->x + i * d, raw);
+        for (int m = 0; m < d; ++m) {
+            double base = fabs(raw[m]) + fabs(u[m]);
+            double up[3] = {u[0], u[1], u[2]};
+            up[m] += OR_COND_EPS * base;
+            bwd_term(g, c->op, c->prm, up, ak, ai, gyk, gyi, tp, &tap);
+            for (int q = 0; q < d; ++q) acc[q] += fabs(tp[q] - t[q]) / OR_COND_EPS;
+            acca += fabs(tap - ta) / OR_COND_EPS;
+        }
+        for (int m = 0; m < c->ny; ++m) {
+            double gp[3] = {0, 0, 0};
+            for (int q = 0; q < c->ny; ++q) gp[q] = gyk[q];
+            gp[m] += OR_COND_EPS * (fabs(gyk[m]) + fabs(gyi[m]));
+            bwd_term(g, c->op, c->prm, u, ak, ai, gp, gyi, tp, &tap);
+            for (int q = 0; q < d; ++q) acc[q] += fabs(tp[q] - t[q]) / OR_COND_EPS;
+            acca += fabs(tap - ta) / OR_COND_EPS;
+        }
+        if (c->a) {
+            bwd_term(g, c->op, c->prm, u, ak + OR_COND_EPS * (fabs(ak) + fabs(ai)), ai, gyk, gyi, tp, &tap);
+            for (int q = 0; q < d; ++q) acc[q] += fabs(tp[q] - t[q]) / OR_COND_EPS;
+            acca += fabs(tap - ta) / OR_COND_EPS;
+        }
+        if (c->cxrow) {
+            double mx = 0.0;
+            for (int q = 0; q < d; ++q)
+                if (acc[q] > mx) mx = acc[q];
+            *c->cxrow += mx;
+        }
+        if (c->carow) *c->carow += acca;
+    }
 }
 
-/* gx[row][d], ga[row] (DEM spring only, else may be NULL); scale_x / scale_a as
- * in or_pair_sum.  gy is [n][ny] in original order. */
+/* gx[row][d], ga[row] (DEM spring only, else may be NULL); S and D of reading
+ * R6 for gx (scale_x, cond_x) and ga (scale_a, cond_a), each may be NULL.  gy
+ * is [n][ny] in original order.  nthreads >= 1 threads split the rows. */
 int or_pair_sum_backward(const or_grid* g, int32_t route, int32_t op, const double* prm, int64_t n,
                          const double* x, const double* a, const double* gy, int64_t nrows, const int64_t* rows,
-                         double* gx, double* ga, double* scale_x, double* scale_a) {
+                         double* gx, double* ga, double* scale_x, double* cond_x, double* scale_a, double* cond_a,
+                         int32_t nthreads) {
     int ny = or_op_ny(op, g->d);
     if (ny < 0) return OR_ERR_INVALID;
     if (or_op_na(op) && !a) return OR_ERR_INVALID;
-    bwd_ctx c = {g, op, prm, x, a, gy, ny, NULL, NULL, NULL, NULL};
-    void* begin_ctx[5] = {&c, gx, ga, scale_x, scale_a};
-    void* ctxs[1] = {&c};
-    int st = for_rows(g, route, n, x, nrows, rows, bwd_pair, ctxs, bwd_begin, begin_ctx);
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > OR_MAX_THREADS) nthreads = OR_MAX_THREADS;
+    bwd_ctx c[OR_MAX_THREADS];
+    void* ctxs[OR_MAX_THREADS];
+    for (int t = 0; t < nthreads; ++t) {
+        bwd_ctx ct = {g, op, prm, x, a, gy, ny, gx, ga, scale_x, cond_x, scale_a, cond_a,
+                      NULL, NULL, NULL, NULL, NULL, NULL};
+        c[t] = ct;
+        ctxs[t] = &c[t];
+    }
+    int st = for_rows(g, route, n, x, nrows, rows, bwd_pair, bwd_begin, ctxs, nthreads);
     return st == OR_ERR_NOMEM ? st : OR_OK;
 }
 
@@ -872,19 +963,21 @@ int64_t or_tie_band(const or_grid* g, int64_t n, const double* x) {
 /* over the box search (the force of eq. (1) without its constant), then     */
 /* v_i += dt (c S_i), then x_i += dt v_i with the new velocity, then the     */
 /* periodic wrap of reading R7.  x and v are [n][d], overwritten; x must hold */
-/* P-rounded positions inside the box.  scale_v[i] (may be NULL) is the       */
-/* row's error scale of c S_i (reading R6 applied to the force).             */
+/* P-rounded positions inside the box.  scale_v and cond_v (each may be NULL) */
+/* are S and D of reading R6 for the velocity change dt c S_i.               */
 /* ------------------------------------------------------------------------ */
 
 int or_md_step(const or_grid* g, int32_t route, double c, double dt, int64_t n, double* x, double* v,
-               double* scale_v) {
+               double* scale_v, double* cond_v) {
     int d = g->d;
     double one[4] = {1.0, 0.0, 0.0, 0.0};
-    double* S = (double*)calloc((size_t)(n > 0 ? n : 1) * (size_t)d, sizeof(double));
-    double* sc = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
-    if (!S || !sc) { free(S); free(sc); return OR_ERR_NOMEM; }
-    int st = or_pair_sum(g, route, OR_OP_EXP_FORCE, one, n, x, NULL, 0, NULL, S, sc);
-    if (st != OR_OK) { free(S); free(sc); return st; }
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    double* S = (double*)calloc(nn * (size_t)d, sizeof(double));
+    double* sc = (double*)calloc(nn, sizeof(double));
+    double* cd = (double*)calloc(nn, sizeof(double));
+    if (!S || !sc || !cd) { free(S); free(sc); free(cd); return OR_ERR_NOMEM; }
+    int st = or_pair_sum(g, route, OR_OP_EXP_FORCE, one, n, x, NULL, 0, NULL, S, sc, cd, 1);
+    if (st != OR_OK) { free(S); free(sc); free(cd); return st; }
     for (int64_t i = 0; i < n; ++i) {
         for (int k = 0; k < d; ++k) {
             double vk = v[i * d + k] + dt * (c * S[i * d + k]);
@@ -897,10 +990,12 @@ int or_md_step(const or_grid* g, int32_t route, double c, double dt, int64_t n, 
             v[i * d + k] = vk;
             x[i * d + k] = xk;
         }
-        if (scale_v) scale_v[i] = fabs(c) * sc[i];
+        if (scale_v) scale_v[i] = fabs(dt * c) * sc[i];
+        if (cond_v) cond_v[i] = fabs(dt * c) * cd[i];
     }
     free(S);
     free(sc);
+    free(cd);
     return OR_OK;
 }
 

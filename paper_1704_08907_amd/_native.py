@@ -220,6 +220,9 @@ class Cells:
     nsys: int
     boxes: list = field(default_factory=list)
     offsets: list = field(default_factory=list)
+    # host-side count of the builds into this cell list (1 after it is created):
+    # a caller that keeps results tied to one build (an autograd graph) checks it
+    builds: int = 1
 
     def view(self) -> CellsView:
         v = CellsView()
@@ -258,6 +261,7 @@ def build_cells(ctx: Context, x: torch.Tensor, boxes: Sequence[BoxSpec], offsets
     ctx.check(st, "build_cells")
     if cells is not None:
         cells.boxes, cells.offsets = boxes, list(offsets)
+        cells.builds += 1
         return cells
     return Cells(ctx, h, n, boxes[0].d, x.dtype, nsys, boxes, list(offsets))
 

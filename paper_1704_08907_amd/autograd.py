@@ -63,6 +63,7 @@ class PairSum(torch.autograd.Function):
         fctx.variant = _mask_variant() if grad and _use_masks(ctx, cells) else None
         y = _with_variant(ctx, fctx.variant, lambda: N.pair_sum(ctx, cells, op, params, ad))
         fctx.cells = cells
+        fctx.build = cells.builds
         fctx.nctx = ctx
         fctx.op = op
         fctx.params = params
@@ -72,6 +73,12 @@ class PairSum(torch.autograd.Function):
 
     @staticmethod
     def backward(fctx, gy: torch.Tensor):
+        if fctx.cells.builds != fctx.build:
+            # the adjoint reads the cell list's sorted positions and permutation: after a
+            # rebuild with other positions they no longer belong to this forward
+            raise RuntimeError("PairSum backward: the cell list passed to this forward was rebuilt (build %d, "
+                               "now %d) before the backward ran; give each forward whose gradient is still "
+                               "pending its own Cells" % (fctx.build, fctx.cells.builds))
         gx, ga = _with_variant(fctx.nctx, fctx.variant, lambda: N.pair_sum_backward(
             fctx.nctx, fctx.cells, fctx.op, fctx.params, gy.contiguous(), fctx.a, want_ga=fctx.want_ga))
         return gx, (ga if fctx.want_ga else None), None, None, None, None, None, None
@@ -79,5 +86,9 @@ class PairSum(torch.autograd.Function):
 
 def pair_sum(x: torch.Tensor, ctx: N.Context, boxes: Sequence[N.BoxSpec], op: str, params=(),
              a: Optional[torch.Tensor] = None, offsets=None, cells: Optional[N.Cells] = None) -> torch.Tensor:
-    """Differentiable y = sum over neighbours of op's summand (original order)."""
+    """Differentiable y = sum over neighbours of op's summand (original order).
+
+    A caller-supplied cells is rebuilt in place from x; its backward needs that
+    build, so a second forward on the same Cells before the first backward makes
+    the first backward raise (give such forwards separate Cells)."""
     return PairSum.apply(x, a, ctx, list(boxes), offsets, op, tuple(params), cells)

@@ -16,9 +16,9 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libaboria_mi355x.so")
 SOURCES = ["context.cpp", "build_cells.hip", "pair_sum.hip", "pair_lane_fwd.hip", "pair_lane_bwd.hip",
-           "pair_cells_fwd.hip", "pair_cells_bwd.hip", "pair_nbr.hip", "pair_nbr_fwd.hip", "pair_nbr_bwd.hip",
-           "pair_allpairs.hip", "pair_staged.hip", "pair_flat_fwd.hip", "pair_flat_bwd.hip", "pair_flat_fused.hip", "pair_mask.hip",
-           "dense_sum.hip", "integrate.hip", "autotune.cpp"]
+           "pair_nbr.hip", "pair_nbr_fwd.hip", "pair_nbr_bwd.hip", "pair_allpairs.hip", "pair_flat_fwd.hip",
+           "pair_flat_bwd.hip", "pair_flat_fused.hip", "pair_mask.hip", "dense_sum.hip", "integrate.hip",
+           "autotune.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

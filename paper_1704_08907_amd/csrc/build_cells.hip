@@ -81,7 +81,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_ids(const T* __restrict__ x, ui
                                                      uint32_t* __restrict__ gen) {
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     // a new build generation: a neighbour list recorded for an older one is stale
-    if (i == 0) gen[0] = gen[0] + 1u;
+    if (i == 0) gen[0] = next_generation(gen[0]);
     int b = 0;
     if (BATCH) {
         // the workgroup's rows are contiguous: one binary search for its first
@@ -115,7 +115,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_ids_hist(const T* __restrict__ 
     const uint32_t radix = 1u << bits, mask = radix - 1u;
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);  // neighbouring tiles share an XCD's L2
     const uint32_t base = tile * (kBlock * IPT);
-    if (tile == 0 && threadIdx.x == 0) gen[0] = gen[0] + 1u;
+    if (tile == 0 && threadIdx.x == 0) gen[0] = next_generation(gen[0]);
     for (uint32_t d = threadIdx.x; d < radix; d += kBlock) lds[d] = 0;
     int b = 0;
     if (BATCH) {
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(kBlock) void k_single_cells(const T* __restrict__ x
                                                          uint32_t* __restrict__ flag, uint32_t* __restrict__ gen) {
     constexpr int PITCH = Pitch<D>::value;
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-    if (i == 0) gen[0] = gen[0] + 1u;
+    if (i == 0) gen[0] = next_generation(gen[0]);
     if (i <= (uint32_t)nsys) off[i] = sys_part[i];
     int b = 0;
     if (BATCH) {
@@ -1190,7 +1190,7 @@ extern "C" aboria_status aboria_build_cells(aboria_ctx* ctx, aboria_dtype dtype,
             }
             std::vector<uint32_t> part((size_t)nsys + 1);
             for (int32_t b = 0; b <= nsys; ++b) part[b] = (uint32_t)off[b];
-            const uint32_t gen0[2] = {0u, 0xFFFFFFFFu};  // build generation, generation of the recorded list
+            const uint32_t gen0[2] = {kGenNone, kGenNeverListed};  // build generation, generation of the recorded list
             hipError_t e = hipMemcpyAsync(c->sys_part_dev, part.data(), part.size() * sizeof(uint32_t),
                                           hipMemcpyHostToDevice, ctx->stream);
             if (e == hipSuccess)

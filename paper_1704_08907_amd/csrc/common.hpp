@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/aboria.h"
+#include "generation.hpp"
 
 namespace aboria {
 

@@ -99,6 +99,25 @@ struct PairOp {
         }
     }
 
+    // The radial profile of the vector operators f = g(s) u at one pair, as the
+    // two factors of its Jacobian J = g I + (g'/s) u u^T: g across u and
+    // gpar = g + s g' along u.  Spring and DEM spring: gpar = -k; eq. (1)
+    // force: gpar = -c e^{-s}.  rinv = 1/s.
+    __device__ __forceinline__ static void radial_parts(const OpArgs<T>& q, T r, T d2, T rinv, T ai, T aj, T& g,
+                                                        T& gpar) {
+        if constexpr (OP == ABORIA_OP_SPRING) {
+            g = fma_t(q.p0 * r, rinv, -q.p0);
+            gpar = -q.p0;
+        } else if constexpr (OP == ABORIA_OP_EXP_FORCE) {
+            const T ce = q.p0 * exp_neg_t(d2 * rinv);
+            g = ce * rinv;
+            gpar = -ce;
+        } else {
+            g = fma_t(q.p0 * (ai + aj), rinv, -q.p0);
+            gpar = -q.p0;
+        }
+    }
+
     __device__ __forceinline__ static void bwd_masked(const OpArgs<T>& q, T r, const T* dx, T d2, T ai, T aj,
                                                       const T* gyi, const T* gyj, bool ok, T* gx, T* ga) {
         if constexpr (OP == ABORIA_OP_COUNT) {
@@ -112,8 +131,9 @@ struct PairOp {
 #pragma unroll
             for (int k = 0; k < D; ++k) gx[k] = fma_t(coef, dx[k], gx[k]);
         } else {
+            // as bwd(); every factor is zeroed on a rejected candidate, whose
+            // d2 may be 0 (rinv = inf), before it meets a finite w
             const T rinv = rsqrt_t(d2);
-            const T rinv3 = rinv * rinv * rinv;
             T w[D];
             T dw = T(0);
 #pragma unroll
@@ -121,33 +141,35 @@ struct PairOp {
                 w[k] = gyi[k] - gyj[k];
                 dw = fma_t(dx[k], w[k], dw);
             }
-            T g, gps;
-            if constexpr (OP == ABORIA_OP_SPRING) {
-                g = fma_t(q.p0 * r, rinv, -q.p0);
-                gps = -q.p0 * r * rinv3;
-            } else if constexpr (OP == ABORIA_OP_EXP_FORCE) {
-                const T s = d2 * rinv;
-                const T ce = q.p0 * exp_neg_t(s);
-                g = ce * rinv;
-                gps = -ce * (s + T(1)) * rinv3;
-            } else {
-                const T A = ai + aj;
-                g = fma_t(q.p0 * A, rinv, -q.p0);
-                gps = -q.p0 * A * rinv3;
+            T g, gpar;
+            radial_parts(q, r, d2, rinv, ai, aj, g, gpar);
+            if constexpr (OP == ABORIA_OP_DEM_SPRING) {
                 const T ta = -q.p0 * dw * rinv;
                 ga[0] += ok ? ta : T(0);
             }
-            g = ok ? g : T(0);
-            const T h = ok ? gps * dw : T(0);
+            if constexpr (D == 1) {
+                gx[0] = fma_t(ok ? gpar : T(0), w[0], gx[0]);
+            } else {
+                const T c = ok ? dw * (rinv * rinv) : T(0);
+                g = ok ? g : T(0);
+                const T pc = gpar * c;
 #pragma unroll
-            for (int k = 0; k < D; ++k) gx[k] = fma_t(g, w[k], fma_t(h, dx[k], gx[k]));
+                for (int k = 0; k < D; ++k) {
+                    const T wperp = fma_t(-c, dx[k], w[k]);
+                    gx[k] = fma_t(g, wperp, fma_t(pc, dx[k], gx[k]));
+                }
+            }
         }
     }
 
     // gx += J1(i,j)^T gy_i + J2(j,i)^T gy_j ; ga += d/da_i of the same.
-    // For f = g(s) u:  gx += g w + (g'/s)(u.w) u with w = gy_i - gy_j, and
-    // (u.w) u = (dx.w) dx.  For the soft sphere: gx += 1/2 (gy_i + gy_j)
-    // phi'(s) u/s with phi'(s) = -(2/r)(1 - s/r).
+    // For f = g(s) u the pair adds J w with w = gy_i - gy_j.  Splitting w into
+    // its parts along and across u, w_par = ((dx.w)/s^2) dx and w_perp = w -
+    // w_par, gives J w = g w_perp + gpar w_par: no two O(g) products cancel
+    // (written as g w + (g'/s)(u.w) u, the spring's two terms are each about
+    // k r/s along u and leave -k, so float32 rounding of them would grow as
+    // r/s).  For the soft sphere: gx += 1/2 (gy_i + gy_j) phi'(s) u/s with
+    // phi'(s) = -(2/r)(1 - s/r).
     __device__ __forceinline__ static void bwd(const OpArgs<T>& q, T r, const T* dx, T d2, T ai, T aj,
                                                const T* gyi, const T* gyj, T* gx, T* ga) {
         if constexpr (OP == ABORIA_OP_COUNT) {
@@ -161,7 +183,6 @@ struct PairOp {
             for (int k = 0; k < D; ++k) gx[k] = fma_t(coef, dx[k], gx[k]);
         } else {
             const T rinv = rsqrt_t(d2);
-            const T rinv3 = rinv * rinv * rinv;
             T w[D];
             T dw = T(0);
 #pragma unroll
@@ -169,25 +190,25 @@ struct PairOp {
                 w[k] = gyi[k] - gyj[k];
                 dw = fma_t(dx[k], w[k], dw);
             }
-            T g, gps;  // g(s) and g'(s)/s
-            if constexpr (OP == ABORIA_OP_SPRING) {
-                g = fma_t(q.p0 * r, rinv, -q.p0);
-                gps = -q.p0 * r * rinv3;
-            } else if constexpr (OP == ABORIA_OP_EXP_FORCE) {
-                const T s = d2 * rinv;
-                const T ce = q.p0 * exp_neg_t(s);
-                g = ce * rinv;
-                gps = -ce * (s + T(1)) * rinv3;
-            } else {
-                const T A = ai + aj;
-                g = fma_t(q.p0 * A, rinv, -q.p0);
-                gps = -q.p0 * A * rinv3;
+            T g, gpar;
+            radial_parts(q, r, d2, rinv, ai, aj, g, gpar);
+            if constexpr (OP == ABORIA_OP_DEM_SPRING) {
                 // d/da_i: k (gy_i - gy_j).u / s = -k (w.dx) / s
                 ga[0] = fma_t(-q.p0 * dw, rinv, ga[0]);
             }
-            const T h = gps * dw;
+            if constexpr (D == 1) {
+                // one dimension: w is all along u, exactly (no rounded projection
+                // whose residue g, large at small s, would multiply)
+                gx[0] = fma_t(gpar, w[0], gx[0]);
+            } else {
+                const T c = dw * (rinv * rinv);  // w_par = c dx
+                const T pc = gpar * c;
 #pragma unroll
-            for (int k = 0; k < D; ++k) gx[k] = fma_t(g, w[k], fma_t(h, dx[k], gx[k]));
+                for (int k = 0; k < D; ++k) {
+                    const T wperp = fma_t(-c, dx[k], w[k]);
+                    gx[k] = fma_t(g, wperp, fma_t(pc, dx[k], gx[k]));
+                }
+            }
         }
     }
 };
@@ -711,150 +732,6 @@ __device__ __forceinline__ void flat_loop(const SysParams<T>& P, const T* __rest
 }
 
 // ---------------------------------------------------------------------------
-// box search with the candidates of a stencil row staged in LDS per wave
-// ---------------------------------------------------------------------------
-
-template <typename T>
-__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, m));
-    return v;
-}
-template <typename T>
-__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, m));
-    return v;
-}
-
-// The same box search as neighbour_loop (same candidates, same order, same
-// canonical dx), but for each stencil row the wave first copies the span of
-// slots its lanes will read -- [min over lanes of the row's first slot, max of
-// its last) -- into its own LDS region with coalesced loads, and the lanes then
-// read their candidates from LDS (lanes of one home cell read the same entries,
-// which the LDS broadcasts) instead of each issuing its own global load.  A
-// span longer than CAP (a wave across two rows of cells, or a wrap piece at the
-// far end of a long row) is read from global memory as before.  Every lane of
-// the wave must call it (live = false for lanes past the end), because the
-// span is a wave-wide reduction.
-template <typename T, int D, int CAP, typename Visit>
-__device__ __forceinline__ void neighbour_loop_staged(const SysParams<T>& P, const T* __restrict__ xs,
-                                                      const uint32_t* __restrict__ off, uint32_t n, const T* xi,
-                                                      bool live, VecN<T, Pitch<D>::value>* stage, Visit&& visit) {
-    constexpr int PITCH = Pitch<D>::value;
-    const uint32_t lane = __lane_id();
-    int32_t c[3] = {0, 0, 0};
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-        const T t = xi[k] - P.lo[k];
-        const T q = t * P.inv_w[k];
-        const T f = floor(q);
-        c[k] = !(f >= T(0)) ? 0 : (f > T(P.n[k] - 1) ? P.n[k] - 1 : (int32_t)f);
-    }
-    const int32_t nx = P.n[0];
-    int np = 0;
-    int32_t plo[3], phi[3];
-    T psh[3];
-    if (nx >= 3) {
-        plo[0] = c[0] > 0 ? c[0] - 1 : 0;
-        phi[0] = c[0] < nx - 1 ? c[0] + 1 : nx - 1;
-        psh[0] = T(0);
-        np = 1;
-        if (P.periodic[0]) {
-            if (c[0] == 0) { plo[np] = phi[np] = nx - 1; psh[np] = -P.L[0]; ++np; }
-            if (c[0] == nx - 1) { plo[np] = phi[np] = 0; psh[np] = P.L[0]; ++np; }
-        }
-    } else {
-        for (int o = -1; o <= 1; ++o) {
-            int32_t v = c[0] + o;
-            T s = T(0);
-            if (v < 0) { if (!P.periodic[0]) continue; v += nx; s = -P.L[0]; }
-            else if (v >= nx) { if (!P.periodic[0]) continue; v -= nx; s = P.L[0]; }
-            plo[np] = phi[np] = v;
-            psh[np] = s;
-            ++np;
-        }
-    }
-    if (!live) np = 0;
-    constexpr int NROWS = D == 1 ? 1 : (D == 2 ? 3 : 9);
-    const T r2 = P.r2;
-    for (int rr = 0; rr < NROWS; ++rr) {
-        T sh[3] = {T(0), T(0), T(0)};
-        uint32_t row = 0;
-        bool skip = false;
-        if constexpr (D >= 2) {
-            int32_t v = c[1] + (rr % 3) - 1;
-            if (v < 0) { if (!P.periodic[1]) skip = true; v += P.n[1]; sh[1] = -P.L[1]; }
-            else if (v >= P.n[1]) { if (!P.periodic[1]) skip = true; v -= P.n[1]; sh[1] = P.L[1]; }
-            row = (uint32_t)v;
-        }
-        if constexpr (D >= 3) {
-            int32_t v = c[2] + (rr / 3) - 1;
-            if (v < 0) { if (!P.periodic[2]) skip = true; v += P.n[2]; sh[2] = -P.L[2]; }
-            else if (v >= P.n[2]) { if (!P.periodic[2]) skip = true; v -= P.n[2]; sh[2] = P.L[2]; }
-            row += (uint32_t)P.n[1] * (uint32_t)v;
-        }
-        const int npr = skip ? 0 : np;
-        const uint32_t rowbase = P.cell_base + (uint32_t)nx * row;
-        uint32_t j0[3], j1[3];
-        uint32_t lo = 0xFFFFFFFFu, hi = 0u;
-#pragma unroll
-        for (int p = 0; p < 3; ++p) {
-            j0[p] = j1[p] = 0u;
-            if (p < npr) {
-                j0[p] = off[rowbase + plo[p]];
-                j1[p] = min(off[rowbase + phi[p] + 1], n);
-                if (j1[p] > j0[p]) {
-                    lo = min(lo, j0[p]);
-                    hi = max(hi, j1[p]);
-                }
-            }
-        }
-        lo = wave_min_u32<T>(lo);
-        hi = wave_max_u32<T>(hi);
-        const bool staged = hi > lo && hi - lo <= (uint32_t)CAP;
-        if (staged) {
-            __builtin_amdgcn_wave_barrier();
-            for (uint32_t t = lane; t < hi - lo; t += kWave) stage[t] = load_row<T, PITCH, true>(xs, lo + t);
-            __builtin_amdgcn_wave_barrier();
-        }
-        for (int p = 0; p < npr; ++p) {
-            sh[0] = psh[p];
-            bool lane_shift = false;
-#pragma unroll
-            for (int k = 0; k < D; ++k) lane_shift |= sh[k] != T(0);
-            const bool any_shift = __ballot(lane_shift) != 0ull;
-            if (staged) {
-                const VecN<T, PITCH>* src = stage - lo;
-                auto scan = [&](auto shift_tag) {
-                    constexpr bool SHIFT = decltype(shift_tag)::value;
-                    uint32_t j = j0[p];
-                    for (; j + 1 < j1[p]; j += 2) {
-                        const VecN<T, PITCH> a = src[j];
-                        const VecN<T, PITCH> b = src[j + 1];
-                        T dx[D], d2;
-                        if (pair_test<T, D, SHIFT>(a.v, xi, sh, r2, dx, &d2)) visit(j, dx, d2, lane_shift);
-                        if (pair_test<T, D, SHIFT>(b.v, xi, sh, r2, dx, &d2)) visit(j + 1, dx, d2, lane_shift);
-                    }
-                    if (j < j1[p]) {
-                        const VecN<T, PITCH> a = src[j];
-                        T dx[D], d2;
-                        if (pair_test<T, D, SHIFT>(a.v, xi, sh, r2, dx, &d2)) visit(j, dx, d2, lane_shift);
-                    }
-                };
-                if (any_shift) scan(std::integral_constant<bool, true>());
-                else scan(std::integral_constant<bool, false>());
-            } else if (any_shift) {
-                scan_range<T, D, true, true>(xs, j0[p], j1[p], xi, sh, r2, lane_shift, visit);
-            } else {
-                scan_range<T, D, false, true>(xs, j0[p], j1[p], xi, sh, r2, false, visit);
-            }
-        }
-        if (staged) __builtin_amdgcn_wave_barrier();
-    }
-}
-
-// ---------------------------------------------------------------------------
 // all pairs of a small system (the brute-force fallback for small N)
 // ---------------------------------------------------------------------------
 
@@ -1041,11 +918,10 @@ __device__ __forceinline__ T shift_of(uint32_t code, int k, T L) {
 template <typename T, int D, int OP, bool BATCH>
 void launch_lane_fwd(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, T* y, int block);
 
-// Lane-per-particle adjoint.  compact = true first lists each lane's accepted
-// neighbours in LDS and evaluates the adjoint summand on the list only.
+// Lane-per-particle adjoint.
 template <typename T, int D, int OP, bool BATCH>
 void launch_lane_bwd(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, const T* gy_s, T* gx,
-                     T* ga, int block, bool compact);
+                     T* ga, int block);
 
 // Forward / adjoint over the cell list's recorded neighbour list (a particle
 // with more neighbours than the list holds is summed by the box search).
@@ -1068,28 +944,12 @@ template <typename T, int D, int OP, bool BATCH, int MODE>
 void launch_flat(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, const T* gy_s, T* y,
                  T* gx, T* ga);
 
-// Lane-per-particle forward / adjoint whose candidates are staged in LDS per
-// stencil row (needs 32-bit row offsets: off32_rows).
-template <typename T, int D, int OP, bool BATCH>
-void launch_stage_fwd(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, T* y);
-template <typename T, int D, int OP, bool BATCH>
-void launch_stage_bwd(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, const T* gy_s, T* gx,
-                      T* ga);
-
 // Forward / adjoint over every particle of the lane's system (minimum image).
 template <typename T, int D, int OP, bool BATCH>
 void launch_all_fwd(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, T* y);
 template <typename T, int D, int OP, bool BATCH>
 void launch_all_bwd(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, const T* gy_s, T* gx,
                     T* ga);
-
-// Cell-group forward / adjoint; rounds = 1 keeps natural cell order, 8 ranks
-// 64-cell tiles by (wrap, occupancy).
-template <typename T, int D, int OP, bool BATCH>
-void launch_cells_fwd(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, T* y, int rounds);
-template <typename T, int D, int OP, bool BATCH>
-void launch_cells_bwd(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, const T* gy_s, T* gx,
-                      T* ga, int rounds);
 
 #define ABORIA_FOR_EACH_PAIR_INSTANCE(X)                                                            \
     X(float, 1, 0, false) X(float, 1, 1, false) X(float, 1, 2, false)                     \

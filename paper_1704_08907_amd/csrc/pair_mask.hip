@@ -190,7 +190,7 @@ __global__ __launch_bounds__(256) void k_lane_mask(const T* __restrict__ xs, con
                 masks[(size_t)(2 * row) * n + s] = (uint32_t)m;
                 masks[(size_t)(2 * row + 1) * n + s] = (uint32_t)(m >> 32);
             });
-        status[s] = overflow ? 0u : gen[0];
+        status[s] = overflow ? kGenNone : gen[0];
         const uint32_t o = perm[s];
 #pragma unroll
         for (int k = 0; k < NY; ++k) y[(size_t)o * NY + k] = acc[k];

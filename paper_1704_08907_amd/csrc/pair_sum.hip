@@ -1,7 +1,8 @@
 // Radius-limited neighbour sums over the cell list: host dispatch, argument
 // validation and the C-ABI entry points of the forward, the adjoint and the
-// pair listing.  The kernels live in pair_lane_fwd.hip, pair_lane_bwd.hip and
-// pair_cells_{fwd,bwd}.hip (see pair_common.hpp for the shared device code).
+// pair listing.  The kernels live in pair_lane_*.hip, pair_mask.hip,
+// pair_flat_*.hip, pair_nbr*.hip and pair_allpairs.hip (see pair_common.hpp for
+// the shared device code).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -85,27 +86,19 @@ aboria_status gather(aboria_ctx* ctx, const aboria_cells* c, const void* src, in
 
 // Work-mapping variants of the neighbour sums.
 struct Variant {
-    int kind;      // 0 = lane per particle, 1 = cell group, 2 = recorded neighbour list,
-                   // 3 = all pairs, 4 = LDS-staged rows, 5 = flattened pruned search,
-                   // 6 = lane per particle with recorded accepted-pair masks
-    int block;     // threads per workgroup (lane mapping)
-    bool compact;  // adjoint lists accepted pairs before evaluating them (lane mapping)
-    int rounds;    // cell group: 1 = natural cell order, 8 = 64-cell tiles ranked by occupancy
+    int kind;   // 0 = lane per particle, 2 = recorded neighbour list, 3 = all pairs,
+                // 5 = flattened pruned search, 6 = lane per particle with recorded
+                // accepted-pair masks
+    int block;  // threads per workgroup
     const char* name;
 };
 
 const Variant kVariants[] = {
-    {0, 256, false, 0, "lane per particle, 256-thread workgroups, adjoint evaluated on every candidate"},
-    {0, 256, true, 0, "lane per particle, 256-thread workgroups, adjoint on a 48-entry LDS list of accepted pairs"},
-    {0, 128, true, 0, "lane per particle, 128-thread workgroups, adjoint on a 64-entry LDS list of accepted pairs"},
-    {0, 512, true, 0, "lane per particle, 256-thread workgroups, adjoint through a per-wave queue of accepted pairs"},
-    {1, 128, false, 1, "cell group of 16 lanes per home cell, cells in natural order"},
-    {1, 128, false, 8, "cell group of 16 lanes per home cell, 64-cell tiles ranked by occupancy"},
-    {2, 256, false, 0, "lane per particle over the recorded neighbour list (accepted pairs only)"},
-    {3, 256, false, 0, "lane per particle over all particles of its system (minimum image; small systems)"},
-    {4, 256, false, 0, "lane per particle, candidates staged in LDS per stencil row and wave"},
-    {5, 256, false, 0, "lane per particle, flattened box search over pruned slot ranges listed in LDS"},
-    {6, 256, false, 0, "lane per particle, forward records accepted-pair bit masks per stencil row, adjoint replays them"},
+    {0, 256, "lane per particle, 256-thread workgroups, adjoint evaluated on every candidate"},
+    {2, 256, "lane per particle over the recorded neighbour list (accepted pairs only)"},
+    {3, 256, "lane per particle over all particles of its system (minimum image; small systems)"},
+    {5, 256, "lane per particle, flattened box search over pruned slot ranges listed in LDS"},
+    {6, 256, "lane per particle, forward records accepted-pair bit masks per stencil row, adjoint replays them"},
 };
 
 // Modes of the flattened kernel (pair_flat.hpp).
@@ -113,10 +106,6 @@ constexpr int kFlatModeFwd = 0, kFlatModeBwd = 1, kFlatModeFused = 2;
 
 // Largest system the all-pairs variant accepts (its lanes test every particle of their system).
 constexpr int64_t kAllPairsMaxSystem = 16384;
-
-bool off32_ok(const aboria_cells* c) {
-    return c->dtype == ABORIA_F32 ? off32_rows<float>((uint64_t)c->n) : off32_rows<double>((uint64_t)c->n);
-}
 
 // Largest search reach over the systems of a cell list in dimension k.
 int32_t max_reach(const aboria_cells* c, int k) {
@@ -129,13 +118,11 @@ int32_t max_reach(const aboria_cells* c, int k) {
 // Reach 1 in every dimension but x: the search has the 3^(d-1) rows of the
 // paper's stencil (each row may span more, narrower cells along x).
 bool rows_reach1(const aboria_cells* c) { return max_reach(c, 1) == 1 && max_reach(c, 2) == 1; }
-bool all_reach1(const aboria_cells* c) { return rows_reach1(c) && max_reach(c, 0) == 1; }
 
 // Variants with their own box-search loops, written for the 3^d stencil: the
 // mask variant for its rows, the others for every cell of it.
 bool reach_ok(const Variant& v, const aboria_cells* c) {
     if (v.kind == 6) return rows_reach1(c);
-    if (v.kind == 1 || v.kind == 4 || (v.kind == 0 && v.compact)) return all_reach1(c);
     return true;
 }
 
@@ -151,11 +138,9 @@ void launch_fwd_variant(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>&
                         const Variant& v) {
     if (v.kind == 6) launch_mask_fwd<T, D, OP, BATCH>(ctx, c, q, a_s, y);
     else if (v.kind == 5) launch_flat<T, D, OP, BATCH, kFlatModeFwd>(ctx, c, q, a_s, nullptr, y, nullptr, nullptr);
-    else if (v.kind == 4) launch_stage_fwd<T, D, OP, BATCH>(ctx, c, q, a_s, y);
     else if (v.kind == 3) launch_all_fwd<T, D, OP, BATCH>(ctx, c, q, a_s, y);
     else if (v.kind == 2) launch_nbr_fwd<T, D, OP, BATCH>(ctx, c, q, a_s, y);
-    else if (v.kind == 1) launch_cells_fwd<T, D, OP, BATCH>(ctx, c, q, a_s, y, v.rounds);
-    else launch_lane_fwd<T, D, OP, BATCH>(ctx, c, q, a_s, y, v.block > 256 ? 256 : v.block);
+    else launch_lane_fwd<T, D, OP, BATCH>(ctx, c, q, a_s, y, v.block);
 }
 
 template <typename T, int D, int OP, bool BATCH>
@@ -163,11 +148,9 @@ void launch_bwd_variant(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>&
                         T* gx, T* ga, const Variant& v) {
     if (v.kind == 6) launch_mask_bwd<T, D, OP, BATCH>(ctx, c, q, a_s, gy_s, gx, ga);
     else if (v.kind == 5) launch_flat<T, D, OP, BATCH, kFlatModeBwd>(ctx, c, q, a_s, gy_s, nullptr, gx, ga);
-    else if (v.kind == 4) launch_stage_bwd<T, D, OP, BATCH>(ctx, c, q, a_s, gy_s, gx, ga);
     else if (v.kind == 3) launch_all_bwd<T, D, OP, BATCH>(ctx, c, q, a_s, gy_s, gx, ga);
     else if (v.kind == 2) launch_nbr_bwd<T, D, OP, BATCH>(ctx, c, q, a_s, gy_s, gx, ga);
-    else if (v.kind == 1) launch_cells_bwd<T, D, OP, BATCH>(ctx, c, q, a_s, gy_s, gx, ga, v.rounds);
-    else launch_lane_bwd<T, D, OP, BATCH>(ctx, c, q, a_s, gy_s, gx, ga, v.block, v.compact);
+    else launch_lane_bwd<T, D, OP, BATCH>(ctx, c, q, a_s, gy_s, gx, ga, v.block);
 }
 
 const Variant& variant_of(int variant) { return kVariants[(variant < 0 || variant >= kNumVariants) ? 0 : variant]; }
@@ -255,12 +238,8 @@ aboria_status check_variant(aboria_ctx* ctx, const aboria_cells* c, int variant)
         return fail(ctx, ABORIA_ERR_INVALID_ARG, "the variant needs a neighbour list recorded on these cells");
     if (variant_of(variant).kind == 3 && largest_system(c) > kAllPairsMaxSystem)
         return fail(ctx, ABORIA_ERR_INVALID_ARG, "the all-pairs variant takes systems of at most 16384 particles");
-    if (variant_of(variant).kind == 4 && !off32_ok(c))
-        return fail(ctx, ABORIA_ERR_INVALID_ARG, "the staged variant needs rows below a 32-bit byte offset");
     if (!reach_ok(variant_of(variant), c))
-        return fail(ctx, ABORIA_ERR_INVALID_ARG,
-                    variant_of(variant).kind == 6 ? "the variant needs reach 1 in every dimension but x"
-                                                  : "the variant searches the 3^d stencil only (reach 1)");
+        return fail(ctx, ABORIA_ERR_INVALID_ARG, "the variant needs reach 1 in every dimension but x");
     if (variant_of(variant).kind == 6) return ensure_masks(ctx, c);
     return ABORIA_OK;
 }
@@ -273,15 +252,12 @@ const char* variant_name(int32_t v) { return (v >= 0 && v < kNumVariants) ? kVar
 
 bool variant_needs_list(int32_t v) { return v >= 0 && v < kNumVariants && kVariants[v].kind == 2; }
 
-// The cell-group mapping gives one 16-lane group a whole home cell; with tens
-// of particles per cell (a coarse explicit grid, such as one cell per system)
-// a few groups do all the work, so the tuner does not time it there.
 bool variant_worth_timing(int32_t v, const aboria_cells* c) {
+    (void)c;
     if (v < 0 || v >= kNumVariants) return false;
     // the mask-recording pair pays only across a forward and its adjoint, which the
     // tuner times separately: callers select it for both calls
     if (kVariants[v].kind == 6) return false;
-    if (kVariants[v].kind == 1) return c->n <= 64 * c->ncells;
     return true;
 }
 
@@ -290,7 +266,6 @@ bool variant_usable(int32_t v, const aboria_cells* c) {
     if (!reach_ok(kVariants[v], c)) return false;
     if (kVariants[v].kind == 2) return c->nbr_recorded;
     if (kVariants[v].kind == 3) return largest_system(c) <= kAllPairsMaxSystem;
-    if (kVariants[v].kind == 4) return off32_ok(c);
     return true;
 }
 

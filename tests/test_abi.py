@@ -2,12 +2,14 @@
 import ctypes
 import os
 import re
+import subprocess
 
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "aboria.h")
 LIB = os.path.join(ROOT, "paper_1704_08907_amd", "libaboria_mi355x.so")
+CSRC = os.path.join(ROOT, "paper_1704_08907_amd", "csrc")
 
 
 def declared():
@@ -85,3 +87,23 @@ def test_box_reach_per_dimension_marshalling():
     assert list(b.reach) == [0, 0, 0]  # 0 = reach 1 in the library
     with pytest.raises(ValueError):
         N.BoxSpec(3, [0] * 3, [1] * 3, [1] * 3, 0.1, None, [2, 1]).to_c()
+
+
+def test_build_generation_never_takes_a_reserved_value(tmp_path):
+    # the device's build counter (csrc/generation.hpp) skips 0 (mask status "no
+    # record") and 0xFFFFFFFF (list "never recorded") when it wraps, so neither
+    # a missing record nor an unrecorded list can ever match a build
+    src = tmp_path / "gen.cpp"
+    src.write_text('#include "generation.hpp"\n#include <stdio.h>\nusing namespace aboria;\n'
+                   'int main() {\n'
+                   '  const uint32_t probe[] = {0u, 1u, 2u, 0x7FFFFFFFu, 0xFFFFFFFDu, 0xFFFFFFFEu, 0xFFFFFFFFu};\n'
+                   '  for (uint32_t g : probe) printf("%u %u\\n", g, next_generation(g));\n'
+                   '  uint32_t g = 0xFFFFFFF0u;\n'
+                   '  for (int k = 0; k < 64; ++k) { g = next_generation(g); if (g == kGenNone || g == kGenNeverListed) return 1; }\n'
+                   '  return 0;\n}\n')
+    exe = tmp_path / "gen"
+    subprocess.run(["g++", "-std=c++17", "-I", CSRC, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert out.returncode == 0
+    got = dict(tuple(int(v) for v in line.split()) for line in out.stdout.split("\n") if line)
+    assert got == {0: 1, 1: 2, 2: 3, 0x7FFFFFFF: 0x80000000, 0xFFFFFFFD: 0xFFFFFFFE, 0xFFFFFFFE: 1, 0xFFFFFFFF: 1}

@@ -118,3 +118,25 @@ def test_autograd_on_cells_narrower_along_x(ctx):
         ctx.set_variant(-1)
     ctx.sync()
     assert torch.equal(y.detach(), y2) and torch.equal(gx, gx2)
+
+
+def test_rebuilt_cells_make_a_pending_backward_raise(ctx):
+    # two forwards on one caller-supplied Cells: the second rebuilds it in place from
+    # other positions, so the first forward's backward would read the wrong sorted
+    # positions and permutation; it raises instead, and the second one is correct
+    w = syn.spring_cube(8192)
+    s = w.systems[0]
+    box = A.BoxSpec(3, s.lo, s.hi, s.periodic, s.cutoff)
+    x1 = torch.from_numpy(s.x).to("cuda:0").requires_grad_(True)
+    x2 = torch.from_numpy(s.x[::-1].copy()).to("cuda:0").requires_grad_(True)
+    cells = A.build_cells(ctx, x1.detach(), [box])
+    gy = torch.from_numpy(w.extra["gy"]).to("cuda:0")
+    y1 = diff_pair_sum(x1, ctx, [box], "spring", (1.0,), cells=cells)
+    y2 = diff_pair_sum(x2, ctx, [box], "spring", (1.0,), cells=cells)
+    with pytest.raises(RuntimeError, match="rebuilt"):
+        torch.autograd.grad(y1, x1, gy)
+    (g2,) = torch.autograd.grad(y2, x2, gy)
+    fresh = A.build_cells(ctx, x2.detach(), [box])
+    ref, _ = A.pair_sum_backward(ctx, fresh, "spring", (1.0,), gy)
+    ctx.sync()
+    assert torch.equal(g2, ref)

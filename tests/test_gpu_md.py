@@ -37,7 +37,8 @@ def periodic_diff(a, b, L=1.0):
 
 def check_state(x, v, xo, vo, v0, dt, scale_v, tol, what):
     vv = v.cpu().numpy().astype(np.float64)
-    bound_v = tol * (np.abs(v0).max(axis=1) + dt * scale_v + 1e-300)
+    # scale_v: the oracle's RowScale of the velocity change dt c S_i
+    bound_v = tol * (np.abs(v0).max(axis=1) + 1e-300) + scale_v.bound(tol)
     err_v = np.abs(vv - vo).max(axis=1)
     assert np.all(err_v <= bound_v), "%s: v off by %g at row %d" % (what, err_v.max(), int(np.argmax(err_v - bound_v)))
     err_x = np.abs(periodic_diff(x.cpu().numpy(), xo)).max(axis=1)

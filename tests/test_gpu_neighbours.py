@@ -78,10 +78,11 @@ def test_replay_matches_oracle_and_box_search(ctx, case, op, params):
         np.testing.assert_array_equal(y.cpu().numpy()[:, 0], yo[:, 0])
         assert torch.all(gx == 0)
         return
-    check_close(y.cpu().numpy(), yo, so, tol_of(prec), "forward " + op, normwise=False)
-    check_close(gx.cpu().numpy(), gxo, sxo, tol_of(prec), "adjoint " + op, normwise=False)
+    uni = slice(0, n - n // 5)  # the uniform rows of make_case
+    check_close(y.cpu().numpy(), yo, so, tol_of(prec), "forward " + op, normwise=uni)
+    check_close(gx.cpu().numpy(), gxo, sxo, tol_of(prec), "adjoint " + op, normwise=uni)
     if op == "dem_spring":
-        check_close(ga.cpu().numpy(), gao.reshape(-1, 1), sao, tol_of(prec), "adjoint a", normwise=False)
+        check_close(ga.cpu().numpy(), gao.reshape(-1, 1), sao, tol_of(prec), "adjoint a", normwise=uni)
 
 
 @pytest.mark.parametrize("capacity", [1, 4, 29])

@@ -119,18 +119,19 @@ def test_pair_sum_and_adjoint(ctx, case, op, params):
     gx, ga = A.pair_sum_backward(ctx, cells, op, params, to_dev(gy), a_d)
     ctx.sync()
     x64 = x.astype(np.float64)
+    uni = slice(0, n - n // 5)  # the uniform rows (the rest sit within ulps of cell faces)
     yo, so = oracle.pair_sum(g, op, params, x64, a=a)
     if op == "count":
         np.testing.assert_array_equal(y.cpu().numpy()[:, 0], yo[:, 0])
     else:
-        check_close(y.cpu().numpy(), yo, so, tol_of(prec), "forward " + op, normwise=False)
+        check_close(y.cpu().numpy(), yo, so, tol_of(prec), "forward " + op, normwise=uni)
     gxo, gao, sxo, sao = oracle.pair_sum_backward(g, op, params, x64, gy, a=a)
     if op == "count":
         assert torch.all(gx == 0)
     else:
-        check_close(gx.cpu().numpy(), gxo, sxo, tol_of(prec), "adjoint " + op, normwise=False)
+        check_close(gx.cpu().numpy(), gxo, sxo, tol_of(prec), "adjoint " + op, normwise=uni)
     if op == "dem_spring":
-        check_close(ga.cpu().numpy(), gao.reshape(-1, 1), sao, tol_of(prec), "adjoint a", normwise=False)
+        check_close(ga.cpu().numpy(), gao.reshape(-1, 1), sao, tol_of(prec), "adjoint a", normwise=uni)
     assert y.dtype == tdt
 
 
@@ -170,7 +171,7 @@ def test_md_square_f64_vs_brute_force(ctx):
     y = A.pair_sum(ctx, cells, "spring", (1.0,))
     yo, so = oracle.pair_sum(g, "spring", (1.0,), s.x, route=oracle.ROUTE_BRUTE)
     check_close(y.cpu().numpy(), yo, so, TOL_F64, "md square spring")
-    assert abs(y.sum(0)).max().item() < 1e-12 * so.sum()
+    assert abs(y.sum(0)).max().item() < 1e-12 * so.s.sum()
 
 
 @pytest.mark.parametrize("strategy", ["counting", "radix"])
@@ -220,7 +221,7 @@ def test_soft_sphere_cube_full_size(ctx):
     coords = np.floor(syn.SplitMix64(6).uniform(64) * s.n * 3).astype(np.int64)
     fd = oracle.fd_grad(g, "soft_sphere", (), s.x.astype(np.float64), np.ones((s.n, 1)), coords, 1e-6)
     got = gx.cpu().numpy().reshape(-1)[coords].astype(np.float64)
-    assert np.all(np.abs(got - fd) <= TOL_F32 * np.maximum(sxo[coords // 3], 1e-30) + 1e-6)
+    assert np.all(np.abs(got - fd) <= sxo[coords // 3].bound(TOL_F32) + 1e-6)
 
 
 def test_dense_gaussian_full_size(ctx):

@@ -139,10 +139,11 @@ def test_reach_sums_match_oracle_and_row_search(ctx, case, reach):
         if op == "count":
             np.testing.assert_array_equal(y.cpu().numpy()[:, 0], yo[:, 0])
             continue
-        check_close(y.cpu().numpy(), yo, so, tol, "forward " + op, normwise=False)
-        check_close(gx.cpu().numpy(), gxo, sxo, tol, "adjoint " + op, normwise=False)
+        uni = slice(0, n - n // 4)  # the uniform rows (the rest sit within ulps of cell faces)
+        check_close(y.cpu().numpy(), yo, so, tol, "forward " + op, normwise=uni)
+        check_close(gx.cpu().numpy(), gxo, sxo, tol, "adjoint " + op, normwise=uni)
         if op == "dem_spring":
-            check_close(ga.cpu().numpy(), gao.reshape(-1, 1), sao, tol, "adjoint a", normwise=False)
+            check_close(ga.cpu().numpy(), gao.reshape(-1, 1), sao, tol, "adjoint a", normwise=uni)
 
 
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
@@ -211,31 +212,23 @@ def test_batch_of_mixed_reaches(ctx):
         check_close(flat[1].cpu().numpy()[lo:hi], gxo, sxo, TOL_F32, "system %d adjoint" % b)
 
 
-def test_reach_1_only_variants_are_refused_and_skipped(ctx):
+def test_mask_variant_needs_reach_1_in_y_and_z(ctx):
+    # the mask record holds the 3^(d-1) rows of the paper's stencil: deeper
+    # searches in y or z are refused, and the tuner never picks it alone
     w = syn.spring_cube(n=20000)
     s = w.systems[0]
     cells = A.build_cells(ctx, to_dev(s.x), [A.BoxSpec(s.d, s.lo, s.hi, s.periodic, s.cutoff, None, 2)])
-    for word in ("cell group of 16 lanes per home cell, cells in natural order", "staged",
-                 "48-entry LDS list", "per-wave queue"):
-        ctx.set_variant(variant(word))
-        try:
-            with pytest.raises(A.AboriaError) as e:
-                A.pair_sum(ctx, cells, "spring", (1.0,))
-            assert e.value.status == "INVALID_ARG"
-        finally:
-            ctx.set_variant(-1)
-    # the tuner skips them and picks a variant that runs on these cells
+    ctx.set_variant(variant("records accepted-pair bit masks"))
+    try:
+        with pytest.raises(A.AboriaError) as e:
+            A.pair_sum(ctx, cells, "spring", (1.0,))
+        assert e.value.status == "INVALID_ARG"
+    finally:
+        ctx.set_variant(-1)
     choice = A.autotune(ctx, cells, "spring", (1.0,))
-    assert "cell group" not in A.variant_name(choice) and "staged" not in A.variant_name(choice)
-    # reach 2 along x only: the same variants are refused, the mask variant runs
+    assert "bit masks" not in A.variant_name(choice)
+    # reach 2 along x only: the mask variant runs
     cx = A.build_cells(ctx, to_dev(s.x), [A.BoxSpec(s.d, s.lo, s.hi, s.periodic, s.cutoff, None, [2, 1, 1])])
-    for word in ("cell group of 16 lanes per home cell, cells in natural order", "staged", "48-entry LDS list"):
-        ctx.set_variant(variant(word))
-        try:
-            with pytest.raises(A.AboriaError):
-                A.pair_sum(ctx, cx, "spring", (1.0,))
-        finally:
-            ctx.set_variant(-1)
     ctx.set_variant(variant("records accepted-pair bit masks"))
     try:
         A.pair_sum(ctx, cx, "spring", (1.0,))

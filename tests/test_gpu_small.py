@@ -78,10 +78,11 @@ def test_all_pairs_matches_oracle_and_box_search(ctx, case):
             np.testing.assert_array_equal(y.cpu().numpy()[:, 0], yo[:, 0])
             assert torch.equal(outs[0][0], y)
             continue
-        check_close(y.cpu().numpy(), yo, so, tol, "%s forward %s" % (name, op), normwise=False)
-        check_close(gx.cpu().numpy(), gxo, sxo, tol, "%s adjoint %s" % (name, op), normwise=False)
+        nw = n >= 1000  # uniform inputs; a handful of pairs has no meaningful norm
+        check_close(y.cpu().numpy(), yo, so, tol, "%s forward %s" % (name, op), normwise=nw)
+        check_close(gx.cpu().numpy(), gxo, sxo, tol, "%s adjoint %s" % (name, op), normwise=nw)
         if op == "dem_spring":
-            check_close(ga.cpu().numpy(), gao.reshape(-1, 1), sao, tol, "%s adjoint a" % name, normwise=False)
+            check_close(ga.cpu().numpy(), gao.reshape(-1, 1), sao, tol, "%s adjoint a" % name, normwise=nw)
 
 
 def test_batch_of_single_cell_systems(ctx):
@@ -108,7 +109,8 @@ def test_batch_of_single_cell_systems(ctx):
     for b, (L, xb) in enumerate(systems):
         g = oracle.grid(3, [0.0] * 3, [L] * 3, [1, 1, 1], r, "f32", [1, 1, 1])
         yo, so = oracle.pair_sum(g, "spring", (1.0,), xb.astype(np.float64))
-        check_close(y.cpu().numpy()[offsets[b]:offsets[b + 1]], yo, so, TOL_F32, "system %d" % b, normwise=False)
+        check_close(y.cpu().numpy()[offsets[b]:offsets[b + 1]], yo, so, TOL_F32, "system %d" % b,
+                    normwise=xb.shape[0] >= 1000)
 
 
 def test_single_cell_build_reports_domain_errors(ctx):

@@ -52,6 +52,51 @@ def test_hand_case_cells_pairs_and_sums(prec):
         np.testing.assert_array_equal(gx, np.array(t["soft_sphere_grad_gy1"]))
 
 
+@pytest.mark.parametrize("route", [oracle.ROUTE_BRUTE, oracle.ROUTE_CELLS])
+def test_hand_case_error_scales(route):
+    # reading R6: the per-row scale S (sum of the summands' max-norms) and the
+    # condition D (displacement sensitivity, with the rounding base |raw| + |u|)
+    # against values computed by hand; rows 0 and 5 hold the pair across the
+    # periodic face, whose base includes the coordinate difference before the shift
+    t = load("t1_hand_case.json")
+    x = np.array(t["x"], dtype=np.float64)
+    g = oracle.grid(t["d"], t["lo"], t["hi"], t["periodic"], t["cutoff"], "f64", t["ncell"])
+    _, sc = oracle.pair_sum(g, "spring", (1.0,), x, route=route)
+    np.testing.assert_allclose(sc.s, t["spring_k1_scale_S"], rtol=1e-14)
+    np.testing.assert_allclose(sc.d, t["spring_k1_cond_D"], rtol=1e-4)
+    _, _, sg, _ = oracle.pair_sum_backward(g, "soft_sphere", (), x, np.ones((6, 1)), route=route)
+    np.testing.assert_allclose(sg.s, t["soft_sphere_grad_gy1_scale_S"], rtol=1e-14)
+    np.testing.assert_allclose(sg.d, t["soft_sphere_grad_gy1_cond_D"], rtol=1e-4)
+    gx, _, sx, _ = oracle.pair_sum_backward(g, "spring", (1.0,), x, np.array(t["spring_k1_adjoint_gy"]), route=route)
+    np.testing.assert_allclose(gx, t["spring_k1_adjoint_gx"], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(sx.s, t["spring_k1_adjoint_scale_S"], rtol=1e-14, atol=0)
+    np.testing.assert_allclose(sx.d, t["spring_k1_adjoint_cond_D"], rtol=1e-4, atol=0)
+    # the bound the GPU comparison applies: tol S + 16 u_P D
+    np.testing.assert_allclose(sc.bound(1e-5), 1e-5 * np.array(t["spring_k1_scale_S"])
+                               + 16 * 2.0 ** -53 * np.array(t["spring_k1_cond_D"]), rtol=1e-4)
+
+
+def test_error_scale_is_tight_on_the_spring_cube():
+    # the per-row bound tol S + 16 u D must stay close to the plain scale tol S:
+    # on uniform rows of the spring cube a summand's condition D is about seven
+    # times its norm (|J| ~ k against k (r - s)), and 16 u_32 = 9.5e-7 is a
+    # tenth of tol = 1e-5, so the rounding allowance adds about two thirds of
+    # tol S, not orders of magnitude that would make the comparison vacuous
+    w = syn.spring_cube(1 << 14)
+    s = w.systems[0]
+    g = oracle.grid_of(s)
+    y, sc = oracle.pair_sum(g, "spring", (1.0,), s.x)
+    ratio = sc.bound(1e-5) / np.maximum(1e-5 * sc.s, 1e-300)
+    assert 1.3 < np.median(ratio) < 2.0 and np.percentile(ratio, 90) < 3.5, (np.median(ratio), np.percentile(ratio, 90))
+    # and S itself is the sum of the rows' summand norms: |y_i| <= S_i, with equality only without cancellation
+    assert np.all(np.abs(y).max(axis=1) <= sc.s * (1 + 1e-12))
+    gx, _, sx, _ = oracle.pair_sum_backward(g, "spring", (1.0,), s.x, w.extra["gy"])
+    ratio = sx.bound(1e-5) / np.maximum(1e-5 * sx.s, 1e-300)
+    assert np.median(ratio) < 2.0 and np.percentile(ratio, 90) < 3.5, (np.median(ratio), np.percentile(ratio, 90))
+    print("bound / (tol S): forward median %.2f, adjoint median %.2f" % (
+        np.median(sc.bound(1e-5) / (1e-5 * sc.s)), np.median(ratio)))
+
+
 def test_hand_case_auto_grid_same_pairs():
     t = load("t1_hand_case.json")
     x = np.array(t["x"])
@@ -339,8 +384,8 @@ def test_newtons_third_law(op, params, needs_a):
     x = syn.uniform_positions(rng, 5000, [0] * 3, [L] * 3, "f32")
     a = rng.uniform(5000) * 0.5 if needs_a else None
     y, sc = oracle.pair_sum(g, op, params, x, a=a)
-    assert np.abs(y.sum(axis=0)).max() < 1e-11 * sc.sum()
-    assert sc.sum() > 0
+    assert np.abs(y.sum(axis=0)).max() < 1e-11 * sc.s.sum()
+    assert sc.s.sum() > 0
 
 
 def test_mean_neighbour_count_matches_density():
@@ -372,12 +417,12 @@ def test_adjoint_matches_finite_differences(op, params, needs_a, d):
     coords = np.floor(rng.uniform(200) * n * d).astype(np.int64)
     fd = oracle.fd_grad(g, op, params, x, gy, coords, 1e-6, a=a)
     an = gx.reshape(-1)[coords]
-    scale = sx[coords // d]
+    scale = sx.s[coords // d]
     assert np.all(np.abs(fd - an) <= 1e-7 * np.maximum(scale, 1e-30) + 1e-9)
     if needs_a:
         ca = n * d + np.floor(rng.uniform(100) * n).astype(np.int64)
         fda = oracle.fd_grad(g, op, params, x, gy, ca, 1e-6, a=a)
-        assert np.all(np.abs(fda - ga[ca - n * d]) <= 1e-7 * np.maximum(sa[ca - n * d], 1e-30) + 1e-9)
+        assert np.all(np.abs(fda - ga[ca - n * d]) <= 1e-7 * np.maximum(sa.s[ca - n * d], 1e-30) + 1e-9)
 
 
 def test_energy_gradient_is_scaled_spring_force():
@@ -390,8 +435,8 @@ def test_energy_gradient_is_scaled_spring_force():
     k = 1.0
     gx, _, sx, _ = oracle.pair_sum_backward(g, "soft_sphere", (), x, np.ones((n, 1)))
     f, sf = oracle.pair_sum(g, "spring", (k,), x)
-    np.testing.assert_allclose(gx, -(2.0 / (k * g.r * g.r)) * f, rtol=0, atol=1e-12 * sx.max())
-    assert np.abs(gx.sum(axis=0)).max() < 1e-11 * sx.sum()  # translation invariance of E
+    np.testing.assert_allclose(gx, -(2.0 / (k * g.r * g.r)) * f, rtol=0, atol=1e-12 * sx.s.max())
+    assert np.abs(gx.sum(axis=0)).max() < 1e-11 * sx.s.sum()  # translation invariance of E
 
 
 # --------------------------------------------------------------------------
@@ -435,7 +480,8 @@ def test_rows_subset_matches_full_and_tie_band_is_small():
     rows = np.array([0, 5, 100, 16383])
     yb, scb = oracle.pair_sum(g, "spring", (1.0,), s.x, rows=rows, route=oracle.ROUTE_BRUTE)
     np.testing.assert_allclose(yb, y[rows], rtol=0, atol=1e-12)
-    np.testing.assert_allclose(scb, sc[rows], rtol=1e-12)
+    np.testing.assert_allclose(scb.s, sc.s[rows], rtol=1e-12)
+    np.testing.assert_allclose(scb.d, sc.d[rows], rtol=1e-12)
     assert 0 <= oracle.tie_band(g, s.x) < 20
 
 
@@ -494,7 +540,7 @@ def test_md_step_conserves_momentum_and_routes_agree():
     np.testing.assert_allclose(vc, vb, rtol=0, atol=1e-15)
     np.testing.assert_allclose(xc, xb, rtol=0, atol=1e-15)
     dv = (vc - v).sum(axis=0)
-    assert np.all(np.abs(dv) < 1e-12 * sc.sum())
+    assert np.all(np.abs(dv) < 1e-12 * sc.s.sum())
     assert np.abs(vc - v).max() > 1e-4  # the forces are not all zero
 
 
