@@ -287,6 +287,25 @@ aboria_status aboria_dense_sum(aboria_ctx* ctx, aboria_dtype dtype, aboria_kerne
                                const double* params_host, int32_t nparams, int32_t d, int64_t n_target,
                                const void* xt, int64_t n_source, const void* xs, const void* w, void* y);
 
+/* aboria_dense_sum for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops and harnesses that forbid hipMalloc.
+ * Same arguments, arithmetic and errors as aboria_dense_sum; the caller still
+ * passes every input and y.  The split partial sums go to a fixed device array
+ * of 16 MiB that the library holds on each GPU it runs on until the process
+ * ends, instead of the context's grow-only scratch, so the call never calls
+ * hipMalloc, hipFree or any allocating routine (its first call on a device
+ * looks the array's address up once).  n_target may be at most 4,194,304
+ * (float32) or 2,097,152 (float64): larger sizes return INVALID_ARG and launch
+ * nothing.  Near that limit fewer source splits fit and the partial sums are
+ * grouped differently from aboria_dense_sum (same tolerance, not the same
+ * bits); below it the results are bit-identical.  Every call on one GPU shares
+ * that GPU's array and each call overwrites every entry it reads, so nothing
+ * needs clearing, but calls that overlap in time on one GPU (two streams or
+ * two host threads) race on it: serialise them. */
+aboria_status aboria_dense_sum_noalloc(aboria_ctx* ctx, aboria_dtype dtype, aboria_kernel kernel,
+                                       const double* params_host, int32_t nparams, int32_t d, int64_t n_target,
+                                       const void* xt, int64_t n_source, const void* xs, const void* w, void* y);
+
 /* Adjoint of aboria_dense_sum for L = sum_i gy_i y_i (gy[n_target]):
  *   gw[j]     = sum_i K(xt_i, xs_j) gy_i                       (K^T gy)
  *   gxt[i][:] = gy_i sum_j w_j 2 phi'(q_ij) (xt_i - xs_j)

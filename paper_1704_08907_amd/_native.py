@@ -53,7 +53,8 @@ EXPORTS = ["aboria_create", "aboria_destroy", "aboria_set_stream", "aboria_last_
            "aboria_graph_destroy", "aboria_autotune", "aboria_variant_count", "aboria_variant_name",
            "aboria_set_variant", "aboria_op_ny", "aboria_op_na", "aboria_set_build_strategy",
            "aboria_build_neighbours", "aboria_neighbour_capacity", "aboria_integrate",
-           "aboria_dense_sum_backward", "aboria_autotune_cells", "aboria_pair_sum_and_backward"]
+           "aboria_dense_sum_backward", "aboria_autotune_cells", "aboria_pair_sum_and_backward",
+           "aboria_dense_sum_noalloc"]
 
 
 def lib():
@@ -78,6 +79,7 @@ def lib():
             "aboria_pair_sum_backward": ([P, P, I32, C.POINTER(C.c_double), I32, P, I32, P, I32, P, P], I32),
             "aboria_pair_list": ([P, P, I64, P, P, C.POINTER(I64)], I32),
             "aboria_dense_sum": ([P, I32, I32, C.POINTER(C.c_double), I32, I32, I64, P, I64, P, P, P], I32),
+            "aboria_dense_sum_noalloc": ([P, I32, I32, C.POINTER(C.c_double), I32, I32, I64, P, I64, P, P, P], I32),
             "aboria_graph_capture_begin": ([P], I32),
             "aboria_graph_capture_end": ([P, C.POINTER(P)], I32),
             "aboria_graph_launch": ([P, P], I32),
@@ -379,6 +381,21 @@ def dense_sum(ctx: Context, xt: torch.Tensor, xs: torch.Tensor, w: torch.Tensor,
     st = lib().aboria_dense_sum(ctx.handle, _dtype_code(xt), KERNELS[kernel], arr, npar, d, int(xt.shape[0]),
                                 _ptr(xt), int(xs.shape[0]), _ptr(xs), _ptr(w), _ptr(y))
     ctx.check(st, "dense_sum")
+    return y
+
+
+def dense_sum_noalloc(ctx: Context, xt: torch.Tensor, xs: torch.Tensor, w: torch.Tensor, sigma: float,
+                      y: torch.Tensor, kernel: str = "gaussian") -> torch.Tensor:
+    """aboria_dense_sum_noalloc: dense_sum into a caller-given y, with the library's
+    fixed per-device scratch (no device allocation by the library)."""
+    _check_dev(xt, "xt")
+    _check_dev(xs, "xs", xt.dtype)
+    _check_dev(w, "w", xt.dtype)
+    _check_dev(y, "y", xt.dtype)
+    arr, npar = _params([sigma])
+    st = lib().aboria_dense_sum_noalloc(ctx.handle, _dtype_code(xt), KERNELS[kernel], arr, npar, int(xt.shape[1]),
+                                        int(xt.shape[0]), _ptr(xt), int(xs.shape[0]), _ptr(xs), _ptr(w), _ptr(y))
+    ctx.check(st, "dense_sum_noalloc")
     return y
 
 

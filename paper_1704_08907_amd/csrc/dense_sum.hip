@@ -19,6 +19,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "common.hpp"
 
@@ -26,6 +27,14 @@ namespace aboria {
 
 constexpr int kDenseBlock = 256;
 constexpr int kDenseTile = 256;
+
+// Scratch of aboria_dense_sum_noalloc: its split partial sums live in this
+// file-scope device array (each GPU holds its own copy until the process ends)
+// instead of the context's grow-only buffer.  Host code never passes the
+// array's name to a kernel: in host code it is only a stand-in, and the device
+// address of each GPU's copy comes from hipGetSymbolAddress (noalloc_scratch).
+constexpr size_t kNoAllocScratchBytes = size_t(16) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
 
 __device__ __forceinline__ float kexp(float a) { return __builtin_amdgcn_exp2f(-a); }
 __device__ __forceinline__ double kexp(double a) { return ::exp(-a); }
@@ -225,11 +234,44 @@ aboria_status ensure_scratch(aboria_ctx* ctx, size_t need) {
     return ABORIA_OK;
 }
 
+// Device address of this GPU's copy of the no-allocation scratch array, looked
+// up once per device with that device current and kept for the process.
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kMaxDevices] = {};
+
+aboria_status noalloc_scratch(aboria_ctx* ctx, void** out) {
+    if (ctx->device < 0 || ctx->device >= kMaxDevices)
+        return fail(ctx, ABORIA_ERR_UNSUPPORTED, "device index beyond the no-allocation scratch table");
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[ctx->device]) {
+        int cur = 0;
+        ABORIA_HIP(ctx, hipGetDevice(&cur));
+        if (cur != ctx->device) ABORIA_HIP(ctx, hipSetDevice(ctx->device));
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != ctx->device) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return fail(ctx, ABORIA_ERR_DEVICE, std::string("hipGetSymbolAddress of the scratch array: ") +
+                                                    hipGetErrorString(e));
+        }
+        g_noalloc_ptr[ctx->device] = ptr;
+    }
+    *out = g_noalloc_ptr[ctx->device];
+    return ABORIA_OK;
+}
+
 // kSum: out = sum_j K(xt_i, xs_j) w_j; kGrad: out = mult_i * C * sum_j w_j slope (xt_i - xs_j);
-// kSumGrad: out = the kSum sum and out2 = the kGrad sum, from one pass.
+// kSumGrad: out = the kSum sum and out2 = the kGrad sum, from one pass.  The split
+// partials go to the context's grow-only scratch, or, when part is given, to the
+// part_cap bytes at part (fewer splits when they would not fit; an error when even
+// one split's partials do not).  Every partial entry the reduction reads is
+// written by k_dense, so the scratch needs no clearing.
 template <typename T, int D, int KERN, int MODE>
 aboria_status launch_dense(aboria_ctx* ctx, uint32_t nt, const void* xt, uint32_t ns, const void* xs, const void* w,
-                           const KernelPlan& kp, const void* mult, void* out, void* out2 = nullptr) {
+                           const KernelPlan& kp, const void* mult, void* out, void* out2, void* part,
+                           size_t part_cap) {
     constexpr int OUT = dense_out<MODE, D>();
     const uint32_t per_block = kDenseBlock * kTargetsPerThread;
     const uint32_t tblocks = (nt + per_block - 1) / per_block;
@@ -237,48 +279,75 @@ aboria_status launch_dense(aboria_ctx* ctx, uint32_t nt, const void* xt, uint32_
     // enough workgroups to fill 256 CUs several times over
     uint32_t nsplit = std::max<uint32_t>(1, (2048 + tblocks - 1) / tblocks);
     nsplit = std::min(nsplit, ntiles);
+    const size_t split_bytes = sizeof(T) * (size_t)nt * OUT;
+    if (part) {
+        const size_t fit = part_cap / split_bytes;
+        if (fit == 0)
+            return fail(ctx, ABORIA_ERR_INVALID_ARG, "n_target too large for the no-allocation scratch (" +
+                                                         std::to_string(part_cap / (sizeof(T) * OUT)) +
+                                                         " targets at most)");
+        nsplit = (uint32_t)std::min<size_t>(nsplit, fit);
+    }
     const uint32_t tiles_per_split = (ntiles + nsplit - 1) / nsplit;
     nsplit = (ntiles + tiles_per_split - 1) / tiles_per_split;
     const uint32_t jchunk = tiles_per_split * kDenseTile;
-    aboria_status st = ensure_scratch(ctx, sizeof(T) * (size_t)nsplit * nt * OUT);
-    if (st != ABORIA_OK) return st;
+    if (!part) {
+        aboria_status st = ensure_scratch(ctx, split_bytes * nsplit);
+        if (st != ABORIA_OK) return st;
+        part = ctx->scratch;
+    }
     hipLaunchKernelGGL((k_dense<T, D, kTargetsPerThread, KERN, MODE>), dim3(tblocks, nsplit), dim3(kDenseBlock), 0,
                        ctx->stream, (const T*)xt, nt, (const T*)xs, (const T*)w, ns, (T)kp.sc, (T)kp.c2, jchunk,
-                       (T*)ctx->scratch);
+                       (T*)part);
     if constexpr (MODE == kSumGrad)
         hipLaunchKernelGGL((k_dense_reduce2<T, D>), dim3((nt + 255) / 256), dim3(256), 0, ctx->stream,
-                           (const T*)ctx->scratch, nt, nsplit, (const T*)mult, (T)kp.C, (T*)out, (T*)out2);
+                           (const T*)part, nt, nsplit, (const T*)mult, (T)kp.C, (T*)out, (T*)out2);
     else
         hipLaunchKernelGGL((k_dense_reduce<T, OUT>), dim3((nt + 255) / 256), dim3(256), 0, ctx->stream,
-                           (const T*)ctx->scratch, nt, nsplit, (const T*)mult, (T)kp.C, (T*)out);
+                           (const T*)part, nt, nsplit, (const T*)mult, (T)kp.C, (T*)out);
     ABORIA_HIP(ctx, hipGetLastError());
     return ABORIA_OK;
 }
 
 template <typename T, int D, int MODE>
 aboria_status launch_kernel(aboria_ctx* ctx, int kernel, uint32_t nt, const void* xt, uint32_t ns, const void* xs,
-                            const void* w, double prm, const void* mult, void* out, void* out2) {
+                            const void* w, double prm, const void* mult, void* out, void* out2, void* part,
+                            size_t part_cap) {
     const KernelPlan kp = plan_kernel<T>(kernel, prm);
     if (kernel == ABORIA_K_GAUSSIAN)
-        return launch_dense<T, D, ABORIA_K_GAUSSIAN, MODE>(ctx, nt, xt, ns, xs, w, kp, mult, out, out2);
-    return launch_dense<T, D, ABORIA_K_MULTIQUADRIC, MODE>(ctx, nt, xt, ns, xs, w, kp, mult, out, out2);
+        return launch_dense<T, D, ABORIA_K_GAUSSIAN, MODE>(ctx, nt, xt, ns, xs, w, kp, mult, out, out2, part,
+                                                            part_cap);
+    return launch_dense<T, D, ABORIA_K_MULTIQUADRIC, MODE>(ctx, nt, xt, ns, xs, w, kp, mult, out, out2, part,
+                                                            part_cap);
 }
 
 template <int MODE>
 aboria_status dispatch(aboria_ctx* ctx, int dtype, int d, int kernel, uint32_t nt, const void* xt, uint32_t ns,
                        const void* xs, const void* w, double prm, const void* mult, void* out,
-                       void* out2 = nullptr) {
+                       void* out2 = nullptr, void* part = nullptr, size_t part_cap = 0) {
     if (dtype == ABORIA_F32) {
         switch (d) {
-            case 1: return launch_kernel<float, 1, MODE>(ctx, kernel, nt, xt, ns, xs, w, prm, mult, out, out2);
-            case 2: return launch_kernel<float, 2, MODE>(ctx, kernel, nt, xt, ns, xs, w, prm, mult, out, out2);
-            default: return launch_kernel<float, 3, MODE>(ctx, kernel, nt, xt, ns, xs, w, prm, mult, out, out2);
+            case 1:
+                return launch_kernel<float, 1, MODE>(ctx, kernel, nt, xt, ns, xs, w, prm, mult, out, out2, part,
+                                                     part_cap);
+            case 2:
+                return launch_kernel<float, 2, MODE>(ctx, kernel, nt, xt, ns, xs, w, prm, mult, out, out2, part,
+                                                     part_cap);
+            default:
+                return launch_kernel<float, 3, MODE>(ctx, kernel, nt, xt, ns, xs, w, prm, mult, out, out2, part,
+                                                     part_cap);
         }
     }
     switch (d) {
-        case 1: return launch_kernel<double, 1, MODE>(ctx, kernel, nt, xt, ns, xs, w, prm, mult, out, out2);
-        case 2: return launch_kernel<double, 2, MODE>(ctx, kernel, nt, xt, ns, xs, w, prm, mult, out, out2);
-        default: return launch_kernel<double, 3, MODE>(ctx, kernel, nt, xt, ns, xs, w, prm, mult, out, out2);
+        case 1:
+            return launch_kernel<double, 1, MODE>(ctx, kernel, nt, xt, ns, xs, w, prm, mult, out, out2, part,
+                                                  part_cap);
+        case 2:
+            return launch_kernel<double, 2, MODE>(ctx, kernel, nt, xt, ns, xs, w, prm, mult, out, out2, part,
+                                                  part_cap);
+        default:
+            return launch_kernel<double, 3, MODE>(ctx, kernel, nt, xt, ns, xs, w, prm, mult, out, out2, part,
+                                                  part_cap);
     }
 }
 
@@ -303,24 +372,61 @@ aboria_status check_common(aboria_ctx* ctx, aboria_dtype dtype, aboria_kernel ke
 
 using namespace aboria;
 
+namespace {
+
+// The forward's argument checks, shared by the two entry points.
+aboria_status check_dense_sum(aboria_ctx* ctx, aboria_dtype dtype, aboria_kernel kernel, const double* params_host,
+                              int32_t nparams, int32_t d, int64_t n_target, const void* xt, int64_t n_source,
+                              const void* xs, const void* w, void* y) {
+    aboria_status st = check_common(ctx, dtype, kernel, params_host, nparams, d, n_target, n_source);
+    if (st != ABORIA_OK) return st;
+    if (n_target == 0) return ABORIA_OK;
+    if (!xt || !y || (n_source > 0 && (!xs || !w))) return fail(ctx, ABORIA_ERR_INVALID_ARG, "NULL array");
+    const size_t tsz = dtype == ABORIA_F32 ? 4 : 8;
+    const size_t ny = tsz * (size_t)n_target;
+    if (overlaps(y, ny, xt, tsz * d * (size_t)n_target) || overlaps(y, ny, xs, tsz * d * (size_t)n_source) ||
+        overlaps(y, ny, w, tsz * (size_t)n_source))
+        return fail(ctx, ABORIA_ERR_INVALID_ARG, "y overlaps an input");
+    return ABORIA_OK;
+}
+
+}  // namespace
+
 extern "C" aboria_status aboria_dense_sum(aboria_ctx* ctx, aboria_dtype dtype, aboria_kernel kernel,
                                           const double* params_host, int32_t nparams, int32_t d, int64_t n_target,
                                           const void* xt, int64_t n_source, const void* xs, const void* w, void* y) {
     if (!ctx) return ABORIA_ERR_INVALID_ARG;
     try {
-        aboria_status st = check_common(ctx, dtype, kernel, params_host, nparams, d, n_target, n_source);
-        if (st != ABORIA_OK) return st;
-        if (n_target == 0) return ABORIA_OK;
-        if (!xt || !y || (n_source > 0 && (!xs || !w))) return fail(ctx, ABORIA_ERR_INVALID_ARG, "NULL array");
-        const size_t tsz = dtype == ABORIA_F32 ? 4 : 8;
-        const size_t ny = tsz * (size_t)n_target;
-        if (overlaps(y, ny, xt, tsz * d * (size_t)n_target) || overlaps(y, ny, xs, tsz * d * (size_t)n_source) ||
-            overlaps(y, ny, w, tsz * (size_t)n_source))
-            return fail(ctx, ABORIA_ERR_INVALID_ARG, "y overlaps an input");
+        aboria_status st =
+            check_dense_sum(ctx, dtype, kernel, params_host, nparams, d, n_target, xt, n_source, xs, w, y);
+        if (st != ABORIA_OK || n_target == 0) return st;
         return dispatch<kSum>(ctx, dtype, d, kernel, (uint32_t)n_target, xt, (uint32_t)n_source, xs, w,
                               params_host[0], nullptr, y);
     } catch (...) {
         return fail(ctx, ABORIA_ERR_OUT_OF_MEMORY, "host exception in dense_sum");
+    }
+}
+
+extern "C" aboria_status aboria_dense_sum_noalloc(aboria_ctx* ctx, aboria_dtype dtype, aboria_kernel kernel,
+                                                  const double* params_host, int32_t nparams, int32_t d,
+                                                  int64_t n_target, const void* xt, int64_t n_source,
+                                                  const void* xs, const void* w, void* y) {
+    if (!ctx) return ABORIA_ERR_INVALID_ARG;
+    try {
+        aboria_status st =
+            check_dense_sum(ctx, dtype, kernel, params_host, nparams, d, n_target, xt, n_source, xs, w, y);
+        if (st != ABORIA_OK || n_target == 0) return st;
+        const size_t tsz = dtype == ABORIA_F32 ? 4 : 8;
+        if ((size_t)n_target * tsz > kNoAllocScratchBytes)
+            return fail(ctx, ABORIA_ERR_INVALID_ARG,
+                        "n_target too large for the no-allocation scratch (" +
+                            std::to_string(kNoAllocScratchBytes / tsz) + " targets at most)");
+        void* part = nullptr;
+        if ((st = noalloc_scratch(ctx, &part)) != ABORIA_OK) return st;
+        return dispatch<kSum>(ctx, dtype, d, kernel, (uint32_t)n_target, xt, (uint32_t)n_source, xs, w,
+                              params_host[0], nullptr, y, nullptr, part, kNoAllocScratchBytes);
+    } catch (...) {
+        return fail(ctx, ABORIA_ERR_OUT_OF_MEMORY, "host exception in dense_sum_noalloc");
     }
 }
 
