@@ -204,6 +204,48 @@ __global__ __launch_bounds__(256) void k_lane_mask(const T* __restrict__ xs, con
             const T aj = OpShape<OP, D>::NA ? load_row<T, 1, OFF32>(a_s, j).v[0] : T(0);
             Op::bwd(q, r, dx, d2, ai, aj, gyi, gyj, accx, acca);
         };
+        // the accepted pairs of one piece, bits64 bit k = its k-th slot from j0: popped
+        // three per iteration (their loads overlap), each 32-bit half of the piece's
+        // record in turn (one-word bit operations)
+        auto replay = [&](auto shift_tag, uint32_t j0, uint64_t bits64, const T* sh) {
+            constexpr bool SHIFT = decltype(shift_tag)::value;
+#pragma unroll 1
+            for (uint32_t h = 0; h < 2u; ++h) {
+                uint32_t bits = h ? (uint32_t)(bits64 >> 32) : (uint32_t)bits64;
+                const uint32_t base = j0 + 32u * h;
+                while (bits != 0u) {
+                    const uint32_t ja = base + (uint32_t)__builtin_ctz(bits);
+                    bits &= bits - 1u;
+                    const bool vb = bits != 0u;
+                    const uint32_t jb = vb ? base + (uint32_t)__builtin_ctz(bits) : ja;
+                    bits &= bits - 1u;
+                    const bool vc = bits != 0u;
+                    const uint32_t jc = vc ? base + (uint32_t)__builtin_ctz(bits) : ja;
+                    bits &= bits - 1u;
+                    const VecN<T, PITCH> xa = load_row<T, PITCH, OFF32>(xs, ja);
+                    const VecN<T, GP> ga_ = load_row<T, GP, OFF32>(gy_s, ja);
+                    const VecN<T, PITCH> xb = load_row<T, PITCH, OFF32>(xs, jb);
+                    const VecN<T, GP> gb_ = load_row<T, GP, OFF32>(gy_s, jb);
+                    const VecN<T, PITCH> xc = load_row<T, PITCH, OFF32>(xs, jc);
+                    const VecN<T, GP> gc_ = load_row<T, GP, OFF32>(gy_s, jc);
+                    T dx[D], d2;
+                    (void)pair_test<T, D, SHIFT>(xa.v, xi, sh, r2, dx, &d2);
+                    pair(ja, dx, d2, ga_.v);
+                    keep_issued<D>(xb.v);
+                    keep_issued<NY>(gb_.v);
+                    keep_issued<D>(xc.v);
+                    keep_issued<NY>(gc_.v);
+                    if (vb) {
+                        (void)pair_test<T, D, SHIFT>(xb.v, xi, sh, r2, dx, &d2);
+                        pair(jb, dx, d2, gb_.v);
+                    }
+                    if (vc) {
+                        (void)pair_test<T, D, SHIFT>(xc.v, xi, sh, r2, dx, &d2);
+                        pair(jc, dx, d2, gc_.v);
+                    }
+                }
+            }
+        };
         if (status[s] == gen[0]) {
             uint64_t m = 0;    // the current row's record
             uint32_t pos = 0;  // row position of the next piece's first candidate
@@ -219,38 +261,12 @@ __global__ __launch_bounds__(256) void k_lane_mask(const T* __restrict__ xs, con
                     uint64_t bits = pos < 64u ? m >> pos : 0ull;
                     if (len < 64u) bits &= (1ull << len) - 1ull;
                     pos += len;
-                    // three accepted pairs per iteration, so their loads overlap
-                    while (bits != 0ull) {
-                        const uint32_t ja = j0 + (uint32_t)__builtin_ctzll(bits);
-                        bits &= bits - 1ull;
-                        const bool vb = bits != 0ull;
-                        const uint32_t jb = vb ? j0 + (uint32_t)__builtin_ctzll(bits) : ja;
-                        bits &= bits - 1ull;
-                        const bool vc = bits != 0ull;
-                        const uint32_t jc = vc ? j0 + (uint32_t)__builtin_ctzll(bits) : ja;
-                        bits &= bits - 1ull;
-                        const VecN<T, PITCH> xa = load_row<T, PITCH, OFF32>(xs, ja);
-                        const VecN<T, GP> ga_ = load_row<T, GP, OFF32>(gy_s, ja);
-                        const VecN<T, PITCH> xb = load_row<T, PITCH, OFF32>(xs, jb);
-                        const VecN<T, GP> gb_ = load_row<T, GP, OFF32>(gy_s, jb);
-                        const VecN<T, PITCH> xc = load_row<T, PITCH, OFF32>(xs, jc);
-                        const VecN<T, GP> gc_ = load_row<T, GP, OFF32>(gy_s, jc);
-                        T dx[D], d2;
-                        (void)pair_test<T, D, true>(xa.v, xi, sh, r2, dx, &d2);
-                        pair(ja, dx, d2, ga_.v);
-                        keep_issued<D>(xb.v);
-                        keep_issued<NY>(gb_.v);
-                        keep_issued<D>(xc.v);
-                        keep_issued<NY>(gc_.v);
-                        if (vb) {
-                            (void)pair_test<T, D, true>(xb.v, xi, sh, r2, dx, &d2);
-                            pair(jb, dx, d2, gb_.v);
-                        }
-                        if (vc) {
-                            (void)pair_test<T, D, true>(xc.v, xi, sh, r2, dx, &d2);
-                            pair(jc, dx, d2, gc_.v);
-                        }
-                    }
+                    bool lane_shift = false;
+#pragma unroll
+                    for (int k = 0; k < D; ++k) lane_shift |= sh[k] != T(0);
+                    // the image shift's adds only where some lane of the wave needs them
+                    if (__ballot(lane_shift) != 0ull) replay(std::integral_constant<bool, true>(), j0, bits, sh);
+                    else replay(std::integral_constant<bool, false>(), j0, bits, sh);
                 },
                 [&](int) {});
         } else {
