@@ -627,11 +627,42 @@ def main():
                 A.pair_sum(ctx, c6, "exp_force", w6.params, y=f6)
                 A.integrate(ctx, c6, w6.extra["dt"], f6, x6, v6)
 
-        t6 = timed_graph(md_steps, reps=5) / 10
+        def md_steps_fused(k=10):
+            for _ in range(k):
+                A.build_cells(ctx, x6, [box6], cells=c6)
+                A.md_step(ctx, c6, "exp_force", w6.params, w6.extra["dt"], x6, v6)
+
+        x6b, v6b = torch.empty_like(x6), torch.empty_like(v6)
+
+        def md_steps_cell_ordered(k=10):
+            # the reordering container: each step writes the new positions and velocities
+            # in the new cell order (ping-pong buffers; k is even, so they end where they began)
+            bufs = [(x6, v6), (x6b, v6b)]
+            for i in range(k):
+                (xa, va), (xb, vb) = bufs[i % 2], bufs[(i + 1) % 2]
+                A.build_cells(ctx, xa, [box6], cells=c6)
+                A.md_step(ctx, c6, "exp_force", w6.params, w6.extra["dt"], None, va, xb, vb)
+
+        x6_0, v6_0 = x6.clone(), v6.clone()
+        forms6 = {}
+        for name6, fn6 in (("force_sum_then_integrate", md_steps), ("fused_step", md_steps_fused),
+                           ("cell_ordered_fused_step", md_steps_cell_ordered)):
+            x6.copy_(x6_0)
+            v6.copy_(v6_0)
+            forms6[name6] = timed_graph(fn6, reps=5) / 10
+        x6.copy_(x6_0)
+        v6.copy_(v6_0)
+        t_build6 = timed_graph(lambda: A.build_cells(ctx, x6, [box6], cells=c6), reps=10)
+        A.cells_reorder(ctx, c6, x6, v6)  # the same positions in cell order
+        t_build6_sorted = timed_graph(lambda: A.build_cells(ctx, x6, [box6], cells=c6), reps=10)
+        t6 = min(forms6.values())
         ctx.sync()
         extra["md_paper_n1048576_d2_f64"] = {"ms_per_step": t6, "steps_per_s": 1e3 / t6, "pairs": p6,
                                              "pairs_per_s": p6 / (t6 * 1e-3),
-                                             "particle_updates_per_s": s6.n / (t6 * 1e-3)}
+                                             "particle_updates_per_s": s6.n / (t6 * 1e-3),
+                                             "step_forms_ms": forms6,
+                                             "build_ms_random_order": t_build6,
+                                             "build_ms_cell_order": t_build6_sorted}
         # the small correctness workload (N = 1000, d = 2, periodic unit square, r = 0.1, spring, float64):
         # build + forward + adjoint as a graph, with the tuned box search and with the single-cell
         # build and all-pairs sums (the small-N switch)

@@ -233,6 +233,46 @@ aboria_status aboria_pair_sum_backward(aboria_ctx* ctx, const aboria_cells* cell
 aboria_status aboria_integrate(aboria_ctx* ctx, const aboria_cells* cells, double dt, const void* f, void* x,
                                void* v);
 
+/* The whole time step of the Section 3 example in one kernel: the force of
+ * eq. (1) (op = ABORIA_OP_EXP_FORCE, params_host[0] = c) -- or the spring
+ * force (ABORIA_OP_SPRING, k) -- of every particle by the box search over the
+ * cells, followed at once by the update of aboria_integrate (velocity first,
+ * then position, the same periodic wrap).  The force never leaves registers.
+ * The cells must have been built from the positions the step starts from; the
+ * search reads the cell list's exact snapshot of them.
+ *   x_out = v_out = NULL: x and v ([n][d], the order the cells were built
+ *     from) are updated in place; the result equals aboria_pair_sum followed by
+ *     aboria_integrate bit for bit.
+ *   x_out, v_out given (both [n][d]): the reordering container of Section
+ *     2.2.1 -- the particle in cell-order slot s starts from the snapshot's
+ *     position and from v[perm[s]], and its new position and velocity are
+ *     written to x_out[s], v_out[s]: the outputs come out in cell order, equal to
+ *     the in-place results permuted, and the next build from x_out starts from
+ *     nearly sorted cell ids.  x is not read (may be NULL).  The cell list's
+ *     permutation is left as it is, so per-particle arrays that must follow
+ *     (ids, variables) are permuted with aboria_cells_reorder after this call.
+ * Rebuild before the next step.  Errors: UNSUPPORTED for another operator;
+ * INVALID_ARG for a parameter count other than one, a non-finite parameter or
+ * dt, a missing or overlapping array, only one of x_out and v_out, cells of
+ * another device. */
+aboria_status aboria_md_step(aboria_ctx* ctx, const aboria_cells* cells, aboria_op op, const double* params_host,
+                             int32_t nparams, double dt, void* x, void* v, void* x_out, void* v_out);
+
+/* Reordering container (Section 2.2.1, parallel insertion by reordering the
+ * particles): permutes nbuf caller arrays -- each [n] rows of row_bytes_host[b]
+ * bytes (a multiple of 4, at most 4 elements of the cell list's dtype), in the
+ * particle order the cell list was built from -- in place into the cell
+ * order, and makes that the cell list's particle order (its permutation
+ * becomes the identity).  From then on the caller's arrays are in cell order:
+ * every sum and step reads and writes them there, so outputs are written
+ * contiguously, and the next build from the reordered positions starts from
+ * nearly sorted cell ids.  Pass every per-particle array that must stay aligned
+ * with x (positions, velocities, per-particle variables, ids).  The cell
+ * list's own sorted copy and offsets are unchanged.  Errors: INVALID_ARG for
+ * NULL, overlapping or oversized buffers, cells of another device. */
+aboria_status aboria_cells_reorder(aboria_ctx* ctx, aboria_cells* cells, int32_t nbuf, void* const* bufs_host,
+                                   const int32_t* row_bytes_host);
+
 /* Forward sum and adjoint in one box search, for an upstream gradient gy known
  * before the forward (gy = 1 gives an energy E = sum_i e_i and its gradient, the
  * pattern of force fields): y as aboria_pair_sum, gx (and ga, may be NULL) as

@@ -54,7 +54,7 @@ EXPORTS = ["aboria_create", "aboria_destroy", "aboria_set_stream", "aboria_last_
            "aboria_set_variant", "aboria_op_ny", "aboria_op_na", "aboria_set_build_strategy",
            "aboria_build_neighbours", "aboria_neighbour_capacity", "aboria_integrate",
            "aboria_dense_sum_backward", "aboria_autotune_cells", "aboria_pair_sum_and_backward",
-           "aboria_dense_sum_noalloc"]
+           "aboria_dense_sum_noalloc", "aboria_md_step", "aboria_cells_reorder"]
 
 
 def lib():
@@ -79,6 +79,8 @@ def lib():
             "aboria_pair_sum_backward": ([P, P, I32, C.POINTER(C.c_double), I32, P, I32, P, I32, P, P], I32),
             "aboria_pair_list": ([P, P, I64, P, P, C.POINTER(I64)], I32),
             "aboria_dense_sum": ([P, I32, I32, C.POINTER(C.c_double), I32, I32, I64, P, I64, P, P, P], I32),
+            "aboria_md_step": ([P, P, I32, C.POINTER(C.c_double), I32, C.c_double, P, P, P, P], I32),
+            "aboria_cells_reorder": ([P, P, I32, C.POINTER(P), C.POINTER(I32)], I32),
             "aboria_dense_sum_noalloc": ([P, I32, I32, C.POINTER(C.c_double), I32, I32, I64, P, I64, P, P, P], I32),
             "aboria_graph_capture_begin": ([P], I32),
             "aboria_graph_capture_end": ([P, C.POINTER(P)], I32),
@@ -350,6 +352,36 @@ def integrate(ctx: Context, cells: Cells, dt: float, f: torch.Tensor, x: torch.T
             raise ValueError("%s must be [n][d]" % name)
     ctx.check(lib().aboria_integrate(ctx.handle, cells.handle, float(dt), _ptr(f), _ptr(x), _ptr(v)), "integrate")
     return x, v
+
+
+def md_step(ctx: Context, cells: Cells, op: str, params, dt: float, x: Optional[torch.Tensor], v: torch.Tensor,
+            x_out: Optional[torch.Tensor] = None, v_out: Optional[torch.Tensor] = None):
+    """aboria_md_step: the force of op (exp_force or spring) by the box search and the
+    Euler update in one kernel: in place on x and v, or, with x_out and v_out, written
+    in cell order to them (x is then not read and may be None)."""
+    for t, name in ((x, "x"), (v, "v"), (x_out, "x_out"), (v_out, "v_out")):
+        if t is None:
+            continue
+        _check_dev(t, name, cells.dtype)
+        if tuple(t.shape) != (cells.n, cells.d):
+            raise ValueError("%s must be [n][d]" % name)
+    arr, npar = _params(params)
+    st = lib().aboria_md_step(ctx.handle, cells.handle, OPS[op], arr, npar, float(dt), _ptr(x), _ptr(v),
+                              _ptr(x_out), _ptr(v_out))
+    ctx.check(st, "md_step")
+    return (x, v) if x_out is None else (x_out, v_out)
+
+
+def cells_reorder(ctx: Context, cells: Cells, *bufs: torch.Tensor):
+    """aboria_cells_reorder: permutes each [n][...] device tensor into the cell order in
+    place and makes that the cell list's particle order."""
+    for t in bufs:
+        if t.device.type != "cuda" or not t.is_contiguous() or int(t.shape[0]) != cells.n:
+            raise ValueError("reorder buffers must be contiguous [n][...] device tensors")
+    ptrs = (C.c_void_p * max(1, len(bufs)))(*[t.data_ptr() for t in bufs])
+    sizes = (C.c_int32 * max(1, len(bufs)))(*[t.element_size() * (t.numel() // max(1, cells.n)) for t in bufs])
+    ctx.check(lib().aboria_cells_reorder(ctx.handle, cells.handle, len(bufs), ptrs, sizes), "cells_reorder")
+    return bufs
 
 
 def pair_list(ctx: Context, cells: Cells):

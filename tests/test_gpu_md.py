@@ -176,3 +176,137 @@ def test_integrate_argument_errors(ctx):
     ctx.sync()
     assert torch.equal(x, to_dev(s.x))
     assert math.isfinite(float(x.sum().item()))
+
+
+# --------------------------------------------------------------------------
+# the fused step and the cell-ordered (reordering container) mode
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,prec", [(50000, "f64"), (50000, "f32"), (3000, "f64")])
+def test_fused_step_equals_force_sum_then_integrate(ctx, n, prec):
+    # aboria_md_step computes the eq. (1) force and the Euler update in one kernel:
+    # the same bits as aboria_pair_sum followed by aboria_integrate
+    w = syn.md_paper(n, precision=prec)
+    s = w.systems[0]
+    c = 5e-3
+    rng = syn.SplitMix64(91)
+    v0 = (1e-3 * rng.normal(2 * n).reshape(n, 2)).astype(s.x.dtype)
+    print("fused step", n, prec, flush=True)
+    x1, v1, x2, v2 = to_dev(s.x), to_dev(v0), to_dev(s.x), to_dev(v0)
+    cells = A.build_cells(ctx, x1, [box_of(s)])
+    for _ in range(3):
+        gpu_step(ctx, cells, [box_of(s)], x1, v1, c, 1.0)
+    for _ in range(3):
+        A.build_cells(ctx, x2, [box_of(s)], cells=cells)
+        A.md_step(ctx, cells, "exp_force", (c,), 1.0, x2, v2)
+    ctx.sync()
+    assert torch.equal(x1, x2) and torch.equal(v1, v2)
+
+
+def test_fused_spring_step_on_a_batch_of_cubes(ctx):
+    w = syn.batch_cubes(nsys=12, nmax=8192)
+    xs = np.concatenate([q.x for q in w.systems])
+    offsets = np.concatenate([[0], np.cumsum([q.n for q in w.systems])]).tolist()
+    boxes = [box_of(q) for q in w.systems]
+    v0 = (1e-2 * syn.SplitMix64(8).normal(3 * xs.shape[0]).reshape(-1, 3)).astype(np.float32)
+    x1, v1, x2, v2 = to_dev(xs), to_dev(v0), to_dev(xs), to_dev(v0)
+    cells = A.build_cells(ctx, x1, boxes, offsets)
+    f = A.pair_sum(ctx, cells, "spring", (0.5,))
+    A.integrate(ctx, cells, 0.1, f, x1, v1)
+    A.md_step(ctx, cells, "spring", (0.5,), 0.1, x2, v2)
+    ctx.sync()
+    assert torch.equal(x1, x2) and torch.equal(v1, v2)
+    with pytest.raises(A.AboriaError) as e:
+        A.md_step(ctx, cells, "soft_sphere", (1.0,), 0.1, x2, v2)
+    assert e.value.status == "UNSUPPORTED"
+    with pytest.raises(A.AboriaError) as e:
+        A.md_step(ctx, cells, "spring", (0.5,), 0.1, x2, x2)
+    assert e.value.status == "INVALID_ARG"
+
+
+def test_reorder_puts_the_callers_arrays_in_cell_order(ctx):
+    from _parity import cells_state
+    w = syn.md_paper(20000)
+    s = w.systems[0]
+    n = s.n
+    x = to_dev(s.x)
+    v = to_dev(1e-3 * syn.SplitMix64(4).normal(2 * n).reshape(n, 2))
+    ids = torch.arange(n, dtype=torch.int32, device=dev())
+    cells = A.build_cells(ctx, x, [box_of(s)])
+    keys0, perm0, off0, xs0 = cells_state(cells)
+    y0 = A.pair_sum(ctx, cells, "exp_force", (1e-3,)).clone()
+    x_old, v_old = x.clone(), v.clone()
+    A.cells_reorder(ctx, cells, x, v, ids)
+    ctx.sync()
+    p = torch.from_numpy(perm0.astype(np.int64)).to(dev())
+    assert torch.equal(x, x_old[p]) and torch.equal(v, v_old[p])
+    assert torch.equal(ids.long(), p)
+    keys1, perm1, off1, xs1 = cells_state(cells)
+    assert perm1.tolist() == list(range(n))
+    np.testing.assert_array_equal(keys1, keys0)
+    # the same search, outputs now in the caller's (cell) order
+    y1 = A.pair_sum(ctx, cells, "exp_force", (1e-3,))
+    ctx.sync()
+    assert torch.equal(y1, y0[p])
+    # a rebuild from the reordered positions finds them sorted: the same cells, identity order
+    A.build_cells(ctx, x, [box_of(s)], cells=cells)
+    ctx.sync()
+    keys2, perm2, off2, xs2 = cells_state(cells)
+    assert perm2.tolist() == list(range(n))
+    np.testing.assert_array_equal(keys2, keys0)
+    np.testing.assert_array_equal(off2, off0)
+    np.testing.assert_array_equal(xs2, xs0)
+    with pytest.raises(A.AboriaError) as e:
+        A.cells_reorder(ctx, cells, torch.zeros((n, 8), dtype=torch.float64, device=dev()))
+    assert e.value.status == "INVALID_ARG"  # 64-byte rows exceed the work buffer
+
+
+def test_sorted_output_step_equals_the_in_place_step_permuted(ctx):
+    from _parity import cells_state
+    for n, prec in ((30000, "f64"), (30000, "f32")):
+        w = syn.md_paper(n, precision=prec)
+        s = w.systems[0]
+        v0 = (1e-3 * syn.SplitMix64(12).normal(2 * n).reshape(n, 2)).astype(s.x.dtype)
+        x, v = to_dev(s.x), to_dev(v0)
+        cells = A.build_cells(ctx, x, [box_of(s)])
+        perm = torch.from_numpy(cells_state(cells)[1].astype(np.int64)).to(dev())
+        x_out, v_out = torch.empty_like(x), torch.empty_like(v)
+        A.md_step(ctx, cells, "exp_force", (5e-3,), 1.0, None, v, x_out, v_out)
+        A.md_step(ctx, cells, "exp_force", (5e-3,), 1.0, x, v)
+        ctx.sync()
+        assert torch.equal(x_out, x[perm]) and torch.equal(v_out, v[perm]), prec
+    with pytest.raises(A.AboriaError) as e:
+        A.md_step(ctx, cells, "exp_force", (5e-3,), 1.0, None, v, x_out, None)
+    assert e.value.status == "INVALID_ARG"
+    with pytest.raises(A.AboriaError) as e:
+        A.md_step(ctx, cells, "exp_force", (5e-3,), 1.0, None, v, x_out, v)
+    assert e.value.status == "INVALID_ARG"
+
+
+def test_cell_ordered_trajectory_matches_oracle_step_by_step(ctx):
+    # the reordering container: every step rebuilds from the cell-ordered positions, the
+    # fused step writes the new positions and velocities in the new cell order (ping-pong
+    # buffers) and the particle ids follow with aboria_cells_reorder; each step is compared
+    # with one oracle step from the GPU's previous state
+    from _parity import cells_state
+    n, steps, c = 4096, 8, 5e-3
+    w = syn.md_paper(n)
+    s = w.systems[0]
+    xa, va = to_dev(s.x), to_dev(w.extra["v"])
+    xb, vb = torch.empty_like(xa), torch.empty_like(va)
+    ids = torch.arange(n, dtype=torch.int32, device=dev())
+    cells = A.build_cells(ctx, xa, [box_of(s)])
+    g = oracle.grid_of(s)
+    for k in range(steps):
+        A.build_cells(ctx, xa, [box_of(s)], cells=cells)
+        perm = cells_state(cells)[1].astype(np.int64)
+        x_prev, v_prev = xa.cpu().numpy(), va.cpu().numpy()
+        A.md_step(ctx, cells, "exp_force", (c,), 1.0, None, va, xb, vb)
+        A.cells_reorder(ctx, cells, ids)
+        ctx.sync()
+        xo, vo, sv = oracle.md_step(g, c, 1.0, x_prev, v_prev)
+        check_state(xb, vb, xo[perm], vo[perm], v_prev[perm], 1.0, sv[perm], TOL_F64,
+                    "cell-ordered step %d" % k)
+        xa, xb, va, vb = xb, xa, vb, va
+    assert sorted(ids.cpu().tolist()) == list(range(n))
+    assert np.abs(va.cpu().numpy()).max() > 1e-3
