@@ -222,31 +222,79 @@ def test_masks_with_reach_along_x_on_narrow_grids(ctx):
 
 def test_headline_configuration_full_size(ctx):
     # the bench's step: spring cube N = 2^20 on cells r/3 wide along x, the forward
-    # recording masks and the adjoint replaying them; bit-equal to the row search on
-    # the same grid, and sampled rows against the oracle
+    # recording masks and the adjoint replaying them: the cell list bit-equal to the
+    # oracle's, the pair counts of every row bit-equal, the forward and the adjoint of
+    # every row against the oracle (threads over rows), and both bit-equal to the row
+    # search on the same grid
     import oracle
-    from _parity import TOL_F32, check_close
+    from _parity import TOL_F32, cells_state, check_close
     w = syn.spring_cube()
     s = w.systems[0]
     box = A.BoxSpec(3, s.lo, s.hi, s.periodic, s.cutoff, None, [3, 1, 1])
     x_d = to_dev(s.x)
     gy_d = to_dev(w.extra["gy"])
+    print("headline full size", flush=True)
     cells = A.build_cells(ctx, x_d, [box])
     assert [int(cells.view().ncell_host[k]) for k in range(3)] == [158, 52, 52]
     y = fwd(ctx, cells, "spring", (1.0,), None, variant(MASK))
     gx = bwd(ctx, cells, "spring", (1.0,), gy_d, None, variant(MASK))[0]
+    cnt = fwd(ctx, cells, "count", (), None, variant(PLAIN))
     y_ref = fwd(ctx, cells, "spring", (1.0,), None, variant(PLAIN))
     gx_ref = bwd(ctx, cells, "spring", (1.0,), gy_d, None, variant(PLAIN))[0]
     ctx.sync()
     assert torch.equal(y, y_ref) and torch.equal(gx, gx_ref)
     g = oracle.grid(3, s.lo, s.hi, s.periodic, s.cutoff, "f32", None, [3, 1, 1])
-    rows = np.floor(syn.SplitMix64(33).uniform(256) * s.n).astype(np.int64)
-    rows = np.concatenate([rows, [0, s.n - 1]])
     x64 = s.x.astype(np.float64)
-    yo, so = oracle.pair_sum(g, "spring", (1.0,), x64, rows=rows)
-    check_close(y.cpu().numpy()[rows], yo, so, TOL_F32, "headline forward rows")
-    gxo, _, sxo, _ = oracle.pair_sum_backward(g, "spring", (1.0,), x64, w.extra["gy"].astype(np.float64), rows=rows)
-    check_close(gx.cpu().numpy()[rows], gxo, sxo, TOL_F32, "headline adjoint rows")
+    keys, perm, off, xs = cells_state(cells)
+    ids, st = oracle.cell_ids(g, x64)
+    assert st == oracle.OK
+    operm, ooff = oracle.sort_cells(g, ids)
+    np.testing.assert_array_equal(perm, operm)
+    np.testing.assert_array_equal(off, ooff)
+    np.testing.assert_array_equal(xs[:, :3], s.x[operm])
+    co = oracle.pair_sum(g, "count", (), x64, scales=False, nthreads="all")
+    np.testing.assert_array_equal(cnt.cpu().numpy()[:, 0], co[:, 0])
+    yo, so = oracle.pair_sum(g, "spring", (1.0,), x64, nthreads="all")
+    r = check_close(y.cpu().numpy(), yo, so, TOL_F32, "headline forward, every row")
+    gxo, _, sxo, _ = oracle.pair_sum_backward(g, "spring", (1.0,), x64, w.extra["gy"].astype(np.float64),
+                                              nthreads="all")
+    rg = check_close(gx.cpu().numpy(), gxo, sxo, TOL_F32, "headline adjoint, every row")
+    print("worst row error / bound: forward %.3f, adjoint %.3f" % (r, rg))
+
+
+def test_benched_batch_step_full_size(ctx):
+    # the bench's batch step exactly: 512 uneven systems (5.8 M particles), the cell
+    # size tuned for the batch, the spring forward recording the pairs and the
+    # soft-sphere adjoint (gy = 1) replaying them; eight systems at full size against
+    # the oracle (the smallest, the largest and six drawn at random), the forward and
+    # the energy gradient of every row of each
+    import oracle
+    from _parity import TOL_F32, check_close
+    w = syn.batch_cubes()
+    xs_all = np.concatenate([q.x for q in w.systems])
+    offsets = np.concatenate([[0], np.cumsum([q.n for q in w.systems])]).tolist()
+    boxes = [A.BoxSpec(3, q.lo, q.hi, q.periodic, q.cutoff) for q in w.systems]
+    x_d = to_dev(xs_all)
+    g_d = to_dev(w.extra["gy"])
+    print("benched batch", xs_all.shape[0], flush=True)
+    boxes, _ = A.autotune_cells(ctx, x_d, boxes, offsets, "spring", (1.0,))
+    cells = A.build_cells(ctx, x_d, boxes, offsets)
+    y = fwd(ctx, cells, "spring", (1.0,), None, variant(MASK))
+    gx = bwd(ctx, cells, "soft_sphere", (), g_d, None, variant(MASK))[0]
+    ctx.sync()
+    sizes = [q.n for q in w.systems]
+    pick = {int(np.argmin(sizes)), int(np.argmax(sizes))}
+    pick |= set(np.floor(syn.SplitMix64(77).uniform(6) * len(sizes)).astype(int).tolist())
+    y_h, gx_h = y.cpu().numpy(), gx.cpu().numpy()
+    for b in sorted(pick):
+        q = w.systems[b]
+        lo, hi = offsets[b], offsets[b + 1]
+        g = oracle.grid_of(q)
+        x64 = q.x.astype(np.float64)
+        yo, so = oracle.pair_sum(g, "spring", (1.0,), x64, nthreads="all")
+        check_close(y_h[lo:hi], yo, so, TOL_F32, "batch system %d forward" % b)
+        go, _, sgo, _ = oracle.pair_sum_backward(g, "soft_sphere", (), x64, np.ones((q.n, 1)), nthreads="all")
+        check_close(gx_h[lo:hi], go, sgo, TOL_F32, "batch system %d soft-sphere gradient" % b)
 
 
 def test_needs_reach_1(ctx):
