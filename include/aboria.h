@@ -381,7 +381,15 @@ aboria_status aboria_graph_destroy(aboria_graph* graph);
  * otherwise it tunes the adjoint for that upstream gradient gy[n][ny], which
  * writes out_scratch[n][d] (ga is not computed).  a as for aboria_pair_sum.
  * *choice_host receives the chosen variant (may be NULL).  Synchronises the
- * stream; not capturable.  Errors as for aboria_pair_sum. */
+ * stream; not capturable.  Errors as for aboria_pair_sum.
+ *
+ * Persistence: when the environment variable ABORIA_TUNE_CACHE names a file
+ * at aboria_create, the context loads the choices stored there for this
+ * device architecture, and every aboria_autotune and aboria_autotune_cells
+ * rewrites the file with the context's choices (JSON, one entry per line,
+ * variants by name; written to a temporary file and renamed).  Contexts that
+ * tune concurrently with the same file keep the last writer's entries.
+ * ABORIA_LOG=1 prints errors and tuning decisions to stderr. */
 aboria_status aboria_autotune(aboria_ctx* ctx, const aboria_cells* cells, aboria_op op,
                               const double* params_host, int32_t nparams, const void* a, int32_t na,
                               const void* gy, int32_t ny, void* out_scratch, int32_t* choice_host);
@@ -422,6 +430,12 @@ const char* aboria_variant_name(int32_t variant);
  * INVALID_ARG if the list has m > 1.  Sums that overlap on one cell list with
  * this variant race on its record. */
 aboria_status aboria_set_variant(aboria_ctx* ctx, int32_t variant);
+
+/* The variant a sum on these cells with this operator would use now (forced,
+ * tuned -- from this context's tuning or its persistent cache -- or the
+ * untuned default), backward != 0 for the adjoint.  Launches nothing. */
+aboria_status aboria_selected_variant(aboria_ctx* ctx, const aboria_cells* cells, aboria_op op, int32_t backward,
+                                      int32_t* variant_host);
 
 /* Summand widths of an operator: ny for dimension d, and na. -1 if unknown. */
 int32_t aboria_op_ny(aboria_op op, int32_t d);

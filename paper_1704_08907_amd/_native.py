@@ -54,7 +54,7 @@ EXPORTS = ["aboria_create", "aboria_destroy", "aboria_set_stream", "aboria_last_
            "aboria_set_variant", "aboria_op_ny", "aboria_op_na", "aboria_set_build_strategy",
            "aboria_build_neighbours", "aboria_neighbour_capacity", "aboria_integrate",
            "aboria_dense_sum_backward", "aboria_autotune_cells", "aboria_pair_sum_and_backward",
-           "aboria_dense_sum_noalloc", "aboria_md_step", "aboria_cells_reorder"]
+           "aboria_dense_sum_noalloc", "aboria_md_step", "aboria_cells_reorder", "aboria_selected_variant"]
 
 
 def lib():
@@ -79,6 +79,7 @@ def lib():
             "aboria_pair_sum_backward": ([P, P, I32, C.POINTER(C.c_double), I32, P, I32, P, I32, P, P], I32),
             "aboria_pair_list": ([P, P, I64, P, P, C.POINTER(I64)], I32),
             "aboria_dense_sum": ([P, I32, I32, C.POINTER(C.c_double), I32, I32, I64, P, I64, P, P, P], I32),
+            "aboria_selected_variant": ([P, P, I32, I32, C.POINTER(I32)], I32),
             "aboria_md_step": ([P, P, I32, C.POINTER(C.c_double), I32, C.c_double, P, P, P, P], I32),
             "aboria_cells_reorder": ([P, P, I32, C.POINTER(P), C.POINTER(I32)], I32),
             "aboria_dense_sum_noalloc": ([P, I32, I32, C.POINTER(C.c_double), I32, I32, I64, P, I64, P, P, P], I32),
@@ -352,6 +353,14 @@ def integrate(ctx: Context, cells: Cells, dt: float, f: torch.Tensor, x: torch.T
             raise ValueError("%s must be [n][d]" % name)
     ctx.check(lib().aboria_integrate(ctx.handle, cells.handle, float(dt), _ptr(f), _ptr(x), _ptr(v)), "integrate")
     return x, v
+
+
+def selected_variant(ctx: Context, cells: Cells, op: str, backward: bool = False) -> int:
+    """aboria_selected_variant: the variant a sum (or adjoint) on cells would use now."""
+    out = C.c_int32()
+    ctx.check(lib().aboria_selected_variant(ctx.handle, cells.handle, OPS[op], int(bool(backward)), C.byref(out)),
+              "selected_variant")
+    return int(out.value)
 
 
 def md_step(ctx: Context, cells: Cells, op: str, params, dt: float, x: Optional[torch.Tensor], v: torch.Tensor,

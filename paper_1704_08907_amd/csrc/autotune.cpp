@@ -1,11 +1,21 @@
 // Autotuner for the neighbour-sum launch: times every work-mapping variant on
 // the caller's cell list with HIP events on the context's stream and caches the
 // fastest per (d, dtype, operator, direction, size bucket, density bucket,
-// batch, neighbour list recorded, search reach).
+// batch, neighbour list recorded, search reach); and the cell-size tuner, which
+// times rebuild + sums over search reaches and cell counts.  With the
+// environment variable ABORIA_TUNE_CACHE naming a file, both caches persist:
+// the file is read when a context is created and rewritten after every tuning
+// call.  It is JSON with one entry per line, variants stored by name (so a
+// library whose variant numbering differs skips what it does not know) and
+// the whole file tied to the device architecture it was measured on.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cinttypes>
 #include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
 #include <vector>
 
 #include "common.hpp"
@@ -30,6 +40,69 @@ uint64_t tune_key(const aboria_cells* c, int32_t op, bool backward) {
         for (int q = 0; q < b.d; ++q) reach[q] = std::max<int32_t>(reach[q], b.reach[q] == 0 ? 1 : b.reach[q]);
     k = k * 32 + (uint64_t)((reach[0] - 1) + 3 * (reach[1] - 1) + 9 * (reach[2] - 1));
     return k;
+}
+
+void tune_cache_load(aboria_ctx* ctx) {
+    if (ctx->cache_path.empty()) return;
+    FILE* f = std::fopen(ctx->cache_path.c_str(), "r");
+    if (!f) return;
+    char line[1024];
+    bool arch_ok = false;
+    int nv = 0, nc = 0;
+    while (std::fgets(line, sizeof line, f)) {
+        const char* a = std::strstr(line, "\"arch\": \"");
+        if (a) {
+            a += 9;
+            const char* e = std::strchr(a, '"');
+            arch_ok = e && std::string(a, e) == ctx->arch;
+            continue;
+        }
+        if (!arch_ok) continue;
+        unsigned long long key = 0;
+        char name[512];
+        int m0, m1, m2;
+        double factor;
+        if (std::sscanf(line, " {\"key\": %llu, \"variant\": \"%511[^\"]\"}", &key, name) == 2) {
+            for (int32_t v = 0; v < variant_count(); ++v)
+                if (std::strcmp(variant_name(v), name) == 0) {
+                    ctx->tune_cache.emplace_back((uint64_t)key, v);
+                    ++nv;
+                }
+        } else if (std::sscanf(line, " {\"key\": %llu, \"reach\": [%d, %d, %d], \"factor\": %lf}", &key, &m0, &m1,
+                               &m2, &factor) == 5) {
+            aboria_ctx::CellsChoice ch{{m0, m1, m2}, factor};
+            ctx->cells_cache.emplace_back((uint64_t)key, ch);
+            ++nc;
+        }
+    }
+    std::fclose(f);
+    log_msg("tune cache %s: %d variant and %d cell-size entries for %s", ctx->cache_path.c_str(), nv, nc,
+            ctx->arch.c_str());
+}
+
+void tune_cache_save(aboria_ctx* ctx) {
+    if (ctx->cache_path.empty()) return;
+    const std::string tmp = ctx->cache_path + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) {
+        log_msg("tune cache %s: cannot write", ctx->cache_path.c_str());
+        return;
+    }
+    std::fprintf(f, "{\"format\": 1,\n\"arch\": \"%s\",\n\"variants\": [\n", ctx->arch.c_str());
+    for (size_t i = 0; i < ctx->tune_cache.size(); ++i)
+        std::fprintf(f, "{\"key\": %" PRIu64 ", \"variant\": \"%s\"}%s\n", ctx->tune_cache[i].first,
+                     variant_name(ctx->tune_cache[i].second), i + 1 < ctx->tune_cache.size() ? "," : "");
+    std::fprintf(f, "],\n\"cells\": [\n");
+    for (size_t i = 0; i < ctx->cells_cache.size(); ++i) {
+        const aboria_ctx::CellsChoice& ch = ctx->cells_cache[i].second;
+        std::fprintf(f, "{\"key\": %" PRIu64 ", \"reach\": [%d, %d, %d], \"factor\": %.17g}%s\n",
+                     ctx->cells_cache[i].first, ch.reach[0], ch.reach[1], ch.reach[2], ch.factor,
+                     i + 1 < ctx->cells_cache.size() ? "," : "");
+    }
+    std::fprintf(f, "]}\n");
+    const bool ok = std::fclose(f) == 0;
+    if (!ok || std::rename(tmp.c_str(), ctx->cache_path.c_str()) != 0)
+        log_msg("tune cache %s: cannot replace", ctx->cache_path.c_str());
 }
 
 int32_t pick_variant(aboria_ctx* ctx, const aboria_cells* c, int32_t op, bool backward) {
@@ -117,6 +190,9 @@ extern "C" aboria_status aboria_autotune(aboria_ctx* ctx, const aboria_cells* ce
         for (auto& kv : ctx->tune_cache)
             if (kv.first == key) { kv.second = best; found = true; }
         if (!found) ctx->tune_cache.emplace_back(key, best);
+        log_msg("autotune %s (op %d, n %" PRId64 "): %s, %.4f ms", backward ? "adjoint" : "forward", (int)op,
+                cells->n, variant_name(best), (double)best_ms);
+        tune_cache_save(ctx);
         if (choice_host) *choice_host = best;
         return ABORIA_OK;
     } catch (...) {
@@ -138,6 +214,42 @@ extern "C" aboria_status aboria_autotune_cells(aboria_ctx* ctx, aboria_dtype dty
     if (d < 1 || d > 3) return fail(ctx, ABORIA_ERR_INVALID_ARG, "d must be 1, 2 or 3");
     if (op_ny(op, d) != ny) return fail(ctx, ABORIA_ERR_INVALID_ARG, "ny does not match the operator");
     try {
+        // cache key: (d, dtype, operator, adjoint timed, batch, caller's reach, size
+        // bucket of the total, density bucket of the mean particles per cutoff cube)
+        const int64_t ntot = offsets_host[nsys];
+        double dens = 0.0;
+        for (int32_t b = 0; b < nsys; ++b) {
+            double vol = 1.0;
+            for (int k = 0; k < d; ++k) vol *= (boxes_host[b].hi[k] - boxes_host[b].lo[k]) / boxes_host[b].cutoff;
+            dens += (double)(offsets_host[b + 1] - offsets_host[b]) / std::max(vol, 1e-300);
+        }
+        dens /= nsys;
+        uint64_t ckey = (uint64_t)d;
+        ckey = ckey * 4 + (uint64_t)dtype;
+        ckey = ckey * 16 + (uint64_t)op;
+        ckey = ckey * 2 + (uint64_t)(gy != nullptr);
+        ckey = ckey * 2 + (uint64_t)(nsys > 1);
+        for (int k = 0; k < 3; ++k) ckey = ckey * 8 + (uint64_t)std::min<int32_t>(7, std::max(0, boxes_host[0].reach[k]));
+        ckey = ckey * 64 + (uint64_t)std::floor(std::log2((double)std::max<int64_t>(ntot, 1)));
+        ckey = ckey * 64 + (uint64_t)std::min(63.0, std::max(0.0, std::floor(2.0 * std::log2(dens + 1.0))));
+        for (const auto& kv : ctx->cells_cache) {
+            if (kv.first != ckey) continue;
+            // a cached choice: the grid of that reach, coarsened by the factor
+            for (int32_t b = 0; b < nsys; ++b) {
+                aboria_box bx = boxes_host[b];
+                for (int k = 0; k < 3; ++k) bx.reach[k] = kv.second.reach[k];
+                int32_t base[3];
+                aboria_status st = grid_counts(ctx, dtype, bx, base);
+                if (st != ABORIA_OK) return st;
+                for (int k = 0; k < 3; ++k)
+                    bx.ncell[k] = k < d ? std::max<int32_t>(1, (int32_t)std::floor(kv.second.factor * base[k])) : 0;
+                boxes_out[b] = bx;
+            }
+            if (factor_host) *factor_host = kv.second.factor;
+            log_msg("autotune_cells: cached reach {%d, %d, %d}, factor %.2f", kv.second.reach[0], kv.second.reach[1],
+                    kv.second.reach[2], kv.second.factor);
+            return ABORIA_OK;
+        }
         // reaches to try: the caller's, or, when the boxes leave it to the library,
         // 1, 2 and 3 in every dimension and (d >= 2) 2 and 3 along x only
         struct Reach {
@@ -234,8 +346,25 @@ extern "C" aboria_status aboria_autotune_cells(aboria_ctx* ctx, aboria_dtype dty
         }
         for (int32_t b = 0; b < nsys; ++b) boxes_out[b] = best_boxes[(size_t)b];
         if (factor_host) *factor_host = best_f;
+        aboria_ctx::CellsChoice ch{{best_boxes[0].reach[0], best_boxes[0].reach[1], best_boxes[0].reach[2]}, best_f};
+        bool found = false;
+        for (auto& kv : ctx->cells_cache)
+            if (kv.first == ckey) { kv.second = ch; found = true; }
+        if (!found) ctx->cells_cache.emplace_back(ckey, ch);
+        log_msg("autotune_cells: reach {%d, %d, %d}, factor %.2f, %.4f ms", ch.reach[0], ch.reach[1], ch.reach[2],
+                best_f, best_ms);
+        tune_cache_save(ctx);
         return ABORIA_OK;
     } catch (...) {
         return fail(ctx, ABORIA_ERR_OUT_OF_MEMORY, "host exception in autotune_cells");
     }
+}
+
+extern "C" aboria_status aboria_selected_variant(aboria_ctx* ctx, const aboria_cells* cells, aboria_op op,
+                                                 int32_t backward, int32_t* variant_host) {
+    if (!ctx) return ABORIA_ERR_INVALID_ARG;
+    if (!cells || !variant_host) return fail(ctx, ABORIA_ERR_INVALID_ARG, "cells and variant_host are required");
+    if (op_ny(op, cells->d) < 0) return fail(ctx, ABORIA_ERR_INVALID_ARG, "unknown operator");
+    *variant_host = pick_variant(ctx, cells, op, backward != 0);
+    return ABORIA_OK;
 }

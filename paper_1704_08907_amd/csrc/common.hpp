@@ -98,6 +98,14 @@ struct aboria_ctx {
     int32_t build_strategy = ABORIA_BUILD_RADIX;
     int32_t lds_per_block = 0;       // device limit on LDS per workgroup (queried on first use)
     std::vector<std::pair<uint64_t, int32_t>> tune_cache;  // (key, variant)
+    // cell-size tuner results: key -> search reach per dimension and cell-count factor
+    struct CellsChoice {
+        int32_t reach[3];
+        double factor;
+    };
+    std::vector<std::pair<uint64_t, CellsChoice>> cells_cache;
+    std::string arch;        // the device's architecture name (keys the persistent cache)
+    std::string cache_path;  // ABORIA_TUNE_CACHE at creation ("" = no persistent cache)
 };
 
 struct aboria_cells {
@@ -149,6 +157,16 @@ struct aboria_cells {
 };
 
 namespace aboria {
+
+// Diagnostics on stderr, enabled by the environment variable ABORIA_LOG (an
+// integer; 0 or unset: silent, 1: errors and tuning decisions).
+int log_level();
+void log_msg(const char* fmt, ...);
+
+// The persistent tuning cache (ABORIA_TUNE_CACHE): loaded when a context is
+// created, written after every tuning call.
+void tune_cache_load(aboria_ctx* ctx);
+void tune_cache_save(aboria_ctx* ctx);
 
 // Error helpers used by the host code (sets ctx->last_error).
 aboria_status fail(aboria_ctx* ctx, aboria_status code, const std::string& msg);

@@ -2,6 +2,9 @@
 // the C-ABI.
 #include <hip/hip_runtime.h>
 
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -10,14 +13,34 @@
 
 namespace aboria {
 
+int log_level() {
+    static const int level = [] {
+        const char* v = std::getenv("ABORIA_LOG");
+        return v ? std::atoi(v) : 0;
+    }();
+    return level;
+}
+
+void log_msg(const char* fmt, ...) {
+    if (log_level() < 1) return;
+    va_list ap;
+    va_start(ap, fmt);
+    std::fputs("aboria: ", stderr);
+    std::vfprintf(stderr, fmt, ap);
+    std::fputc('\n', stderr);
+    va_end(ap);
+}
+
 aboria_status fail(aboria_ctx* ctx, aboria_status code, const std::string& msg) {
     if (ctx) ctx->last_error = msg;
+    log_msg("error %d: %s", (int)code, msg.c_str());
     return code;
 }
 
 aboria_status hip_fail(aboria_ctx* ctx, hipError_t e, const char* what) {
     std::string m = std::string(what) + ": " + hipGetErrorString(e);
     if (ctx) ctx->last_error = m;
+    log_msg("HIP error: %s", m.c_str());
     return e == hipErrorOutOfMemory ? ABORIA_ERR_OUT_OF_MEMORY : ABORIA_ERR_DEVICE;
 }
 
@@ -86,6 +109,17 @@ extern "C" aboria_status aboria_create(int32_t device, void* hip_stream, aboria_
         (void)hipHostFree(ctx->h_flag);
         delete ctx;
         return ABORIA_ERR_DEVICE;
+    }
+    try {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->arch = prop.gcnArchName;
+        const char* path = std::getenv("ABORIA_TUNE_CACHE");
+        if (path && *path) {
+            ctx->cache_path = path;
+            tune_cache_load(ctx);
+        }
+    } catch (...) {
+        // a context works without its persistent cache
     }
     *out = ctx;
     return ABORIA_OK;

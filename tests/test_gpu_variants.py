@@ -101,3 +101,47 @@ def test_fused_on_a_batch_and_errors(ctx):
     with pytest.raises(A.AboriaError) as e:
         A.pair_sum_and_backward(ctx, cells, "soft_sphere", (), gy_d, y=gy_d)  # y aliases gy
     assert e.value.status == "INVALID_ARG"
+
+
+def test_tuning_persists_across_contexts(tmp_path):
+    # ABORIA_TUNE_CACHE: a context stores its tuning choices in the file, and a new
+    # context loads them (the same variant selected without tuning again; the cell-size
+    # tuner answers from the cache)
+    import json
+    import os
+    path = str(tmp_path / "tune.json")
+    old = os.environ.get("ABORIA_TUNE_CACHE")
+    os.environ["ABORIA_TUNE_CACHE"] = path
+    try:
+        w = syn.spring_cube(n=60000)
+        s = w.systems[0]
+        x_d = to_dev(s.x)
+        c1 = A.Context(0)
+        boxes, f = A.autotune_cells(c1, x_d, [box_of(s)], [0, s.n], "spring", (1.0,))
+        cells = A.build_cells(c1, x_d, boxes)
+        v_f = A.autotune(c1, cells, "spring", (1.0,))
+        c1.sync()
+        doc = json.load(open(path))
+        assert doc["format"] == 1 and doc["arch"]
+        assert A.variant_name(v_f) in [e["variant"] for e in doc["variants"]]
+        assert len(doc["cells"]) == 1
+        c2 = A.Context(0)
+        cells2 = A.build_cells(c2, x_d, boxes)
+        assert A.selected_variant(c2, cells2, "spring") == v_f
+        boxes2, f2 = A.autotune_cells(c2, x_d, [box_of(s)], [0, s.n], "spring", (1.0,))
+        assert f2 == f and [b.reach_list() for b in boxes2] == [b.reach_list() for b in boxes]
+        assert [list(b.ncell) for b in boxes2] == [list(b.ncell) for b in boxes]
+        c2.sync()
+        # a forced variant wins over the cache
+        other = next(v for v in range(A.variant_count()) if v != v_f and "bit masks" not in A.variant_name(v)
+                     and "recorded neighbour list" not in A.variant_name(v) and "all particles" not in A.variant_name(v))
+        c2.set_variant(other)
+        assert A.selected_variant(c2, cells2, "spring") == other
+        c2.set_variant(-1)
+        for c in (c1, c2):
+            c.close()
+    finally:
+        if old is None:
+            os.environ.pop("ABORIA_TUNE_CACHE", None)
+        else:
+            os.environ["ABORIA_TUNE_CACHE"] = old
