@@ -260,6 +260,19 @@ __device__ __forceinline__ VecN<T, N> load_row(const T* __restrict__ base, uint3
         return reinterpret_cast<const VecN<T, N>*>(base)[j];
 }
 
+// Row j + k with k a small constant: with 32-bit offsets the address is the
+// row-j address plus k rows, which the load takes as an immediate offset
+// (row j + k lies below the same 32-bit bound, so the two addresses agree).
+template <typename T, int N, bool OFF32>
+__device__ __forceinline__ VecN<T, N> load_row_at(const T* __restrict__ base, uint32_t j, uint32_t k) {
+    if constexpr (OFF32)
+        return *reinterpret_cast<const VecN<T, N>*>(reinterpret_cast<const char*>(base) +
+                                                   (size_t)(uint32_t)(j * (uint32_t)sizeof(VecN<T, N>)) +
+                                                   (size_t)k * sizeof(VecN<T, N>));
+    else
+        return reinterpret_cast<const VecN<T, N>*>(base)[j + k];
+}
+
 // Marks the first N elements of a loaded row as used at this point (an empty
 // asm statement, no instruction).  A load whose only other use sits inside a
 // branch would otherwise be sunk into that branch and issued only there; held
@@ -327,11 +340,11 @@ __device__ __forceinline__ void scan_range(const T* __restrict__ xs, uint32_t j0
     uint32_t j = j0;
     for (; j + 1 < j1; j += 2) {
         const VecN<T, PITCH> a = load_row<T, PITCH, OFF32>(xs, j);
-        const VecN<T, PITCH> b = load_row<T, PITCH, OFF32>(xs, j + 1);
+        const VecN<T, PITCH> b = load_row_at<T, PITCH, OFF32>(xs, j, 1);
         VecN<T, AP> aa{}, ab{};
         if constexpr (NAUX > 0) {
             aa = load_row<T, AP, OFF32>(aux, j);
-            ab = load_row<T, AP, OFF32>(aux, j + 1);
+            ab = load_row_at<T, AP, OFF32>(aux, j, 1);
         }
         T dx[D], d2;
         if (pair_test<T, D, SHIFT>(a.v, xi, sh, r2, dx, &d2)) call(j, dx, d2, aa);
@@ -375,7 +388,7 @@ __device__ __forceinline__ void scan_range_deferred(const T* __restrict__ xs, co
         uint32_t j = c0;
         for (; j + 1 < c1; j += 2) {
             const VecN<T, PITCH> a = load_row<T, PITCH, OFF32>(xs, j);
-            const VecN<T, PITCH> b = load_row<T, PITCH, OFF32>(xs, j + 1);
+            const VecN<T, PITCH> b = load_row_at<T, PITCH, OFF32>(xs, j, 1);
             T dx[D], d2;
             mask = (mask << 1) | (pair_test<T, D, SHIFT>(a.v, xi, sh, r2, dx, &d2) ? 1u : 0u);
             mask = (mask << 1) | (pair_test<T, D, SHIFT>(b.v, xi, sh, r2, dx, &d2) ? 1u : 0u);

@@ -127,8 +127,40 @@ __global__ __launch_bounds__(256) void k_lane_mask(const T* __restrict__ xs, con
             constexpr bool SHIFT = decltype(shift_tag)::value;
             uint32_t j = ja;
             // float: four candidates per iteration keep four loads in flight (the
-            // float64 kernel, with twice the registers per row, stays at two)
-            for (; sizeof(T) == 4 && j + 3 < jb; j += 4) {
+            // float64 kernel, with twice the registers per row, stays at two).
+            // With 32-bit row offsets the loop runs on the first candidate's byte
+            // offset, the other three loads take immediate offsets from the same
+            // address, and the four bits enter the record as two 32-bit halves.
+            if constexpr (sizeof(T) == 4 && OFF32) {
+                constexpr uint32_t RB = (uint32_t)sizeof(VecN<T, PITCH>);
+                const char* const xrow = reinterpret_cast<const char*>(xs);
+                const uint32_t oend = jb * RB;
+                const uint32_t olast = oend >= 3u * RB ? oend - 3u * RB : 0u;
+                uint32_t o = ja * RB;
+                uint32_t lo = (uint32_t)rec, hi = (uint32_t)(rec >> 32);
+                for (; o < olast; o += 4u * RB) {
+                    const char* const pj = xrow + (size_t)o;
+                    const VecN<T, PITCH> xa = *reinterpret_cast<const VecN<T, PITCH>*>(pj);
+                    const VecN<T, PITCH> xb = *reinterpret_cast<const VecN<T, PITCH>*>(pj + RB);
+                    const VecN<T, PITCH> xc = *reinterpret_cast<const VecN<T, PITCH>*>(pj + 2u * RB);
+                    const VecN<T, PITCH> xd = *reinterpret_cast<const VecN<T, PITCH>*>(pj + 3u * RB);
+                    const uint32_t jj = o / RB;
+                    T dx[D], d2;
+                    const bool oa = pair_test<T, D, SHIFT>(xa.v, xi, sh, r2, dx, &d2);
+                    if (oa) visit(jj, dx, d2);
+                    const bool ob = pair_test<T, D, SHIFT>(xb.v, xi, sh, r2, dx, &d2);
+                    if (ob) visit(jj + 1, dx, d2);
+                    const bool oc = pair_test<T, D, SHIFT>(xc.v, xi, sh, r2, dx, &d2);
+                    if (oc) visit(jj + 2, dx, d2);
+                    const bool od = pair_test<T, D, SHIFT>(xd.v, xi, sh, r2, dx, &d2);
+                    if (od) visit(jj + 3, dx, d2);
+                    hi = (hi << 4) | (lo >> 28);
+                    lo = (lo << 4) | (oa ? 8u : 0u) | (ob ? 4u : 0u) | (oc ? 2u : 0u) | (od ? 1u : 0u);
+                }
+                rec = ((uint64_t)hi << 32) | lo;
+                j = o / RB;
+            }
+            for (; sizeof(T) == 4 && !OFF32 && j + 3 < jb; j += 4) {
                 const VecN<T, PITCH> xa = load_row<T, PITCH, OFF32>(xs, j);
                 const VecN<T, PITCH> xb = load_row<T, PITCH, OFF32>(xs, j + 1);
                 const VecN<T, PITCH> xc = load_row<T, PITCH, OFF32>(xs, j + 2);
@@ -146,7 +178,7 @@ __global__ __launch_bounds__(256) void k_lane_mask(const T* __restrict__ xs, con
             }
             for (; j + 1 < jb; j += 2) {
                 const VecN<T, PITCH> xa = load_row<T, PITCH, OFF32>(xs, j);
-                const VecN<T, PITCH> xb = load_row<T, PITCH, OFF32>(xs, j + 1);
+                const VecN<T, PITCH> xb = load_row_at<T, PITCH, OFF32>(xs, j, 1);
                 T dx[D], d2;
                 const bool oa = pair_test<T, D, SHIFT>(xa.v, xi, sh, r2, dx, &d2);
                 if (oa) visit(j, dx, d2);
@@ -207,8 +239,9 @@ __global__ __launch_bounds__(256) void k_lane_mask(const T* __restrict__ xs, con
         // the accepted pairs of one piece, bits64 bit k = its k-th slot from j0: popped
         // three per iteration (their loads overlap), each 32-bit half of the piece's
         // record in turn (one-word bit operations)
-        auto replay = [&](auto shift_tag, uint32_t j0, uint64_t bits64, const T* sh) {
-            constexpr bool SHIFT = decltype(shift_tag)::value;
+        // (one form for shifted and unshifted pieces: a specialised no-shift form
+        // took three more registers, seven waves per SIMD, for no gain)
+        auto replay = [&](uint32_t j0, uint64_t bits64, const T* sh) {
 #pragma unroll 1
             for (uint32_t h = 0; h < 2u; ++h) {
                 uint32_t bits = h ? (uint32_t)(bits64 >> 32) : (uint32_t)bits64;
@@ -229,18 +262,18 @@ __global__ __launch_bounds__(256) void k_lane_mask(const T* __restrict__ xs, con
                     const VecN<T, PITCH> xc = load_row<T, PITCH, OFF32>(xs, jc);
                     const VecN<T, GP> gc_ = load_row<T, GP, OFF32>(gy_s, jc);
                     T dx[D], d2;
-                    (void)pair_test<T, D, SHIFT>(xa.v, xi, sh, r2, dx, &d2);
+                    (void)pair_test<T, D, true>(xa.v, xi, sh, r2, dx, &d2);
                     pair(ja, dx, d2, ga_.v);
                     keep_issued<D>(xb.v);
                     keep_issued<NY>(gb_.v);
                     keep_issued<D>(xc.v);
                     keep_issued<NY>(gc_.v);
                     if (vb) {
-                        (void)pair_test<T, D, SHIFT>(xb.v, xi, sh, r2, dx, &d2);
+                        (void)pair_test<T, D, true>(xb.v, xi, sh, r2, dx, &d2);
                         pair(jb, dx, d2, gb_.v);
                     }
                     if (vc) {
-                        (void)pair_test<T, D, SHIFT>(xc.v, xi, sh, r2, dx, &d2);
+                        (void)pair_test<T, D, true>(xc.v, xi, sh, r2, dx, &d2);
                         pair(jc, dx, d2, gc_.v);
                     }
                 }
@@ -261,12 +294,7 @@ __global__ __launch_bounds__(256) void k_lane_mask(const T* __restrict__ xs, con
                     uint64_t bits = pos < 64u ? m >> pos : 0ull;
                     if (len < 64u) bits &= (1ull << len) - 1ull;
                     pos += len;
-                    bool lane_shift = false;
-#pragma unroll
-                    for (int k = 0; k < D; ++k) lane_shift |= sh[k] != T(0);
-                    // the image shift's adds only where some lane of the wave needs them
-                    (void)lane_shift;
-                    replay(std::integral_constant<bool, true>(), j0, bits, sh);
+                    replay(j0, bits, sh);
                 },
                 [&](int) {});
         } else {
