@@ -133,7 +133,11 @@ typedef struct aboria_cells_view {
 /* Creates a context on HIP device `device` that enqueues on `hip_stream` (a
  * hipStream_t; NULL = the legacy default stream).  *out receives the handle. */
 aboria_status aboria_create(int32_t device, void* hip_stream, aboria_ctx** out);
-/* Releases the context and its scratch memory (waits for its stream first). */
+/* Releases the context and its scratch memory (waits for its stream first).
+ * Called on a thread while that thread captures a graph (on any context), the
+ * release waits until the thread's last capture ends: a free or a wait would
+ * invalidate the capture.  The same holds for aboria_cells_destroy and
+ * aboria_graph_destroy. */
 aboria_status aboria_destroy(aboria_ctx* ctx);
 /* Changes the stream subsequent calls enqueue on. */
 aboria_status aboria_set_stream(aboria_ctx* ctx, void* hip_stream);
@@ -189,6 +193,8 @@ aboria_status aboria_cells_view_get(const aboria_cells* cells, aboria_cells_view
  * The setting applies to later builds on ctx; the default is RADIX. */
 typedef enum aboria_build_strategy { ABORIA_BUILD_RADIX = 0, ABORIA_BUILD_COUNTING = 1 } aboria_build_strategy;
 aboria_status aboria_set_build_strategy(aboria_ctx* ctx, aboria_build_strategy strategy);
+/* Releases a cell list (after the device has finished with it; deferred while
+ * the calling thread captures a graph, see aboria_destroy). */
 aboria_status aboria_cells_destroy(aboria_cells* cells);
 
 /* ---- neighbour sums (Section 3: eq. (1) and the velocity-update listing) ----

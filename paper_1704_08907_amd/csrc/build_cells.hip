@@ -31,6 +31,10 @@ constexpr int kBlock = 256;
 constexpr int kScanIpt = 16;
 constexpr int kScanTile = kBlock * kScanIpt;  // 4096 values per scan block
 constexpr int kMaxDigitBits = 10;
+// Scan blocks whose totals a radix pass's consumers prefix-sum themselves in LDS
+// (one value per block of kScanTile histogram entries); a longer histogram keeps
+// the separate top-level scan.
+constexpr int kTopInline = 4 * 256;
 
 // ---------------------------------------------------------------------------
 // a1: cell ids
@@ -104,19 +108,29 @@ __global__ __launch_bounds__(kBlock) void k_cell_ids(const T* __restrict__ x, ui
 // workgroup per sort tile of kBlock * IPT particles (the tiles of
 // k_radix_scatter) writes the tile's keys and hist[digit * ntiles + tile] for
 // the digit (key >> shift) & (2^bits - 1), as k_radix_hist would from them.
+// Threads of a k_cell_ids_hist workgroup for sort tiles of kBlock * IPT keys:
+// two keys per thread (at most 1024 threads), so a CU holds four times the
+// waves a sort pass would and the position loads' latency is hidden.
+template <int IPT>
+struct IdsThreads {
+    static constexpr int value = kBlock * IPT / 2 > 1024 ? 1024 : kBlock * IPT / 2;
+};
+
 template <typename T, int D, bool BATCH, int IPT>
-__global__ __launch_bounds__(kBlock) void k_cell_ids_hist(const T* __restrict__ x, uint32_t n,
+__global__ __launch_bounds__(IdsThreads<IPT>::value) void k_cell_ids_hist(const T* __restrict__ x, uint32_t n,
                                                           const SysParams<T>* __restrict__ sp,
                                                           const uint32_t* __restrict__ sys_part, int nsys,
                                                           uint32_t* __restrict__ keys, uint32_t* __restrict__ flag,
                                                           uint32_t* __restrict__ gen, int shift, int bits,
                                                           uint32_t* __restrict__ hist, uint32_t ntiles) {
+    constexpr int NT = IdsThreads<IPT>::value;
+    constexpr int KPT = kBlock * IPT / NT;
     extern __shared__ uint32_t lds[];
     const uint32_t radix = 1u << bits, mask = radix - 1u;
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);  // neighbouring tiles share an XCD's L2
     const uint32_t base = tile * (kBlock * IPT);
     if (tile == 0 && threadIdx.x == 0) gen[0] = next_generation(gen[0]);
-    for (uint32_t d = threadIdx.x; d < radix; d += kBlock) lds[d] = 0;
+    for (uint32_t d = threadIdx.x; d < radix; d += NT) lds[d] = 0;
     int b = 0;
     if (BATCH) {
         __shared__ int s_first;
@@ -126,11 +140,11 @@ __global__ __launch_bounds__(kBlock) void k_cell_ids_hist(const T* __restrict__ 
     }
     __syncthreads();
     bool bad = false;
-    uint32_t key[IPT];
+    uint32_t key[KPT];
     // all keys first (their position loads in flight together), then the histogram
 #pragma unroll
-    for (int k = 0; k < IPT; ++k) {
-        const uint32_t i = base + k * kBlock + threadIdx.x;
+    for (int k = 0; k < KPT; ++k) {
+        const uint32_t i = base + k * NT + threadIdx.x;
         key[k] = 0u;
         if (i < n) {
             if (BATCH)
@@ -140,11 +154,11 @@ __global__ __launch_bounds__(kBlock) void k_cell_ids_hist(const T* __restrict__ 
         }
     }
 #pragma unroll
-    for (int k = 0; k < IPT; ++k)
-        if (base + k * kBlock + threadIdx.x < n) atomicAdd(&lds[(key[k] >> shift) & mask], 1u);
+    for (int k = 0; k < KPT; ++k)
+        if (base + k * NT + threadIdx.x < n) atomicAdd(&lds[(key[k] >> shift) & mask], 1u);
     if (bad) atomicOr(flag, 1u);
     __syncthreads();
-    for (uint32_t d = threadIdx.x; d < radix; d += kBlock) hist[(size_t)d * ntiles + tile] = lds[d];
+    for (uint32_t d = threadIdx.x; d < radix; d += NT) hist[(size_t)d * ntiles + tile] = lds[d];
 }
 
 // One cell per system (an explicit cell count of 1 in every dimension, the
@@ -348,6 +362,19 @@ aboria_status scan_exclusive_u32(aboria_ctx* ctx, const uint32_t* in, uint32_t* 
     return ABORIA_OK;
 }
 
+// The first level of scan_exclusive_u32 only: out holds each 4096-block's
+// exclusive scan and block_sums the blocks' raw totals.
+aboria_status scan_local_u32(aboria_ctx* ctx, const uint32_t* in, uint32_t* out, int64_t len, uint32_t* block_sums,
+                             int64_t nblock_sums) {
+    if (len <= 0) return ABORIA_OK;
+    int64_t nb = scan_block_count(len);
+    if (nb > nblock_sums) return fail(ctx, ABORIA_ERR_INVALID_ARG, "scan: block-sum buffer too small");
+    hipLaunchKernelGGL(k_scan_local, dim3((uint32_t)nb), dim3(kBlock), 0, ctx->stream, in, out, (uint32_t)len,
+                       block_sums);
+    ABORIA_HIP(ctx, hipGetLastError());
+    return ABORIA_OK;
+}
+
 aboria_status scan_finish_u32(aboria_ctx* ctx, uint32_t* out, int64_t len, const uint32_t* block_sums) {
     if (len <= 0) return ABORIA_OK;
     hipLaunchKernelGGL(k_scan_add, dim3((uint32_t)((len + kBlock - 1) / kBlock)), dim3(kBlock), 0, ctx->stream, out,
@@ -408,11 +435,13 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __rest
                                                           uint32_t* __restrict__ vals_out,
                                                           VecN<T, Pitch<D>::value>* __restrict__ pay_out, uint32_t n,
                                                           int shift, int bits, const uint32_t* __restrict__ hist_scan,
-                                                          const uint32_t* __restrict__ block_sums, uint32_t ntiles) {
+                                                          const uint32_t* __restrict__ block_sums, uint32_t ntiles,
+                                                          int top_done, uint32_t* __restrict__ top_out) {
     constexpr int PITCH = Pitch<D>::value;
     constexpr int kSortTile = kBlock * IPT;
     extern __shared__ uint32_t lds[];
     __shared__ uint32_t s_wsum[4];
+    __shared__ uint32_t s_top[kTopInline];  // exclusive prefix of the scan blocks' totals
     const uint32_t radix = 1u << bits, mask = radix - 1;
     uint32_t* cnt = lds;                 // [4][radix] per-wave counts, then per-wave offsets
     uint32_t* gbase = lds + 4 * radix;   // [radix] first global slot of the tile's keys of a digit
@@ -422,22 +451,12 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __rest
     // [kSortTile] position rows in digit order (SHUFFLE and PAYLOAD)
     VecN<T, PITCH>* srow = reinterpret_cast<VecN<T, PITCH>*>(sv + kSortTile);
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);  // neighbouring tiles share an XCD's L2
-    for (uint32_t d = threadIdx.x; d < radix; d += kBlock) {
-        cnt[d] = 0;
-        cnt[radix + d] = 0;
-        cnt[2 * radix + d] = 0;
-        cnt[3 * radix + d] = 0;
-        size_t p = (size_t)d * ntiles + tile;
-        gbase[d] = hist_scan[p] + block_sums[p / kScanTile];
-    }
-    __syncthreads();
     const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    uint32_t* wc = cnt + w * radix;
-    const uint64_t lt = lanemask_lt();
     const uint32_t tbase = tile * kSortTile;
     const uint32_t wbase = tbase + w * (kWave * IPT);
     uint32_t key[IPT], val[IPT], loc[IPT];
-    // the tile's key and index loads first, so they are in flight together
+    // the tile's key and index loads first, so they are in flight together and
+    // with the histogram reads below
 #pragma unroll
     for (int s = 0; s < IPT; ++s) {
         const uint32_t idx = wbase + s * kWave + lane;
@@ -445,6 +464,41 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __rest
         key[s] = valid ? keys_in[idx] : 0u;
         val[s] = valid ? (FIRST ? idx : vals_in[idx]) : 0u;
     }
+    if (!top_done) {
+        // the top level of the histogram scan: every tile prefix-sums the scan
+        // blocks' totals itself (tile 0 also stores them for the bucket pass)
+        const uint32_t nb = (radix * ntiles + kScanTile - 1) / kScanTile;
+        uint32_t v[kTopInline / kBlock], tot = 0;
+#pragma unroll
+        for (int q = 0; q < kTopInline / kBlock; ++q) {
+            const uint32_t b = threadIdx.x * (kTopInline / kBlock) + q;
+            v[q] = b < nb ? block_sums[b] : 0u;
+            tot += v[q];
+        }
+        uint32_t total;
+        uint32_t ex = block_exclusive_scan(tot, s_wsum, &total);
+#pragma unroll
+        for (int q = 0; q < kTopInline / kBlock; ++q) {
+            const uint32_t b = threadIdx.x * (kTopInline / kBlock) + q;
+            if (b < nb) {
+                s_top[b] = ex;
+                if (tile == 0) top_out[b] = ex;
+            }
+            ex += v[q];
+        }
+        __syncthreads();
+    }
+    for (uint32_t d = threadIdx.x; d < radix; d += kBlock) {
+        cnt[d] = 0;
+        cnt[radix + d] = 0;
+        cnt[2 * radix + d] = 0;
+        cnt[3 * radix + d] = 0;
+        size_t p = (size_t)d * ntiles + tile;
+        gbase[d] = hist_scan[p] + (top_done ? block_sums[p / kScanTile] : s_top[p / kScanTile]);
+    }
+    __syncthreads();
+    uint32_t* wc = cnt + w * radix;
+    const uint64_t lt = lanemask_lt();
 #pragma unroll
     for (int s = 0; s < IPT; ++s) {
         const uint32_t idx = wbase + s * kWave + lane;
@@ -929,6 +983,7 @@ aboria_status launch_build_radix_ipt(aboria_ctx* ctx, aboria_cells* c, const voi
     uint32_t* k0 = (c->passes % 2 == 1) ? c->keys : c->keys_alt;
     uint32_t* kin = k0;
     uint32_t* vin = nullptr;
+    const uint32_t* top_scanned = c->block_sums;  // exclusive prefixes of the last pass's scan-block totals
     using Row = VecN<T, Pitch<D>::value>;
     const Row* pay = nullptr;  // position rows in the order of kin (after a radix pass)
     if (n > 0) {
@@ -937,11 +992,11 @@ aboria_status launch_build_radix_ipt(aboria_ctx* ctx, aboria_cells* c, const voi
         if (c->passes > 0) {  // cell ids with the first pass's digit histogram
             const int shift0 = c->low_bits;
             if (c->nsys == 1)
-                hipLaunchKernelGGL((k_cell_ids_hist<T, D, false, IPT>), dim3(ntiles), dim3(kBlock),
+                hipLaunchKernelGGL((k_cell_ids_hist<T, D, false, IPT>), dim3(ntiles), dim3(IdsThreads<IPT>::value),
                                    radix * sizeof(uint32_t), st, (const T*)x, n, sp, c->sys_part_dev, c->nsys, k0,
                                    ctx->d_flag, c->gen, shift0, c->digit_bits, c->hist, ntiles);
             else
-                hipLaunchKernelGGL((k_cell_ids_hist<T, D, true, IPT>), dim3(ntiles), dim3(kBlock),
+                hipLaunchKernelGGL((k_cell_ids_hist<T, D, true, IPT>), dim3(ntiles), dim3(IdsThreads<IPT>::value),
                                    radix * sizeof(uint32_t), st, (const T*)x, n, sp, c->sys_part_dev, c->nsys, k0,
                                    ctx->d_flag, c->gen, shift0, c->digit_bits, c->hist, ntiles);
         } else {
@@ -977,21 +1032,24 @@ aboria_status launch_build_radix_ipt(aboria_ctx* ctx, aboria_cells* c, const voi
         Row* pout = reinterpret_cast<Row*>(c->work);
         const size_t lds_bytes = (6 * (size_t)radix + 2 * (size_t)kSortTile) * sizeof(uint32_t) +
                                  (payload ? (size_t)kSortTile * sizeof(Row) : 0);
-        const bool shuffle = ntiles <= 512 && lds_bytes <= (size_t)ctx->lds_per_block;
+        const bool shuffle = ntiles <= 512 && lds_bytes + (kTopInline + 4) * sizeof(uint32_t) <= (size_t)ctx->lds_per_block;
         for (int p = 0; p < c->passes; ++p) {
             const int shift = c->low_bits + p * c->digit_bits;
             if (p > 0)  // the first pass's histogram came with the cell ids
                 hipLaunchKernelGGL(k_radix_hist<IPT>, dim3(ntiles), dim3(kBlock), radix * sizeof(uint32_t), st, kin,
                                    n, shift, c->digit_bits, c->hist, ntiles);
-            aboria_status s = scan_exclusive_u32(ctx, c->hist, c->hist, (int64_t)radix * ntiles, c->block_sums,
-                                                 c->nblock_sums);
+            const int64_t hl = (int64_t)radix * ntiles;
+            const int top_done = scan_block_count(hl) > kTopInline ? 1 : 0;
+            aboria_status s = top_done ? scan_exclusive_u32(ctx, c->hist, c->hist, hl, c->block_sums, c->nblock_sums)
+                                       : scan_local_u32(ctx, c->hist, c->hist, hl, c->block_sums, c->nblock_sums);
             if (s != ABORIA_OK) return s;
+            top_scanned = top_done ? c->block_sums : c->block_sums + c->nblock_sums;
             const int pm = (shuffle ? 1 : 0) | (payload ? 2 : 0);
             const size_t lds_sel = shuffle ? lds_bytes : 6 * (size_t)radix * sizeof(uint32_t);
 #define LS(F, SH, PL)                                                                                          \
     hipLaunchKernelGGL((k_radix_scatter<T, D, F, SH, PL, IPT>), dim3(ntiles), dim3(kBlock), lds_sel, st, kin, vin, \
                        (const T*)x, (const Row*)pay, kout, vout, pout, n, shift, c->digit_bits, c->hist,       \
-                       c->block_sums, ntiles)
+                       c->block_sums, ntiles, top_done, c->block_sums + c->nblock_sums)
             if (p == 0) {
                 switch (pm) {
                     case 0: LS(true, false, false); break;
@@ -1027,11 +1085,11 @@ aboria_status launch_build_radix_ipt(aboria_ctx* ctx, aboria_cells* c, const voi
         hipLaunchKernelGGL((k_bucket_finalize<T, D, IPT, kStageable>), dim3(nbuckets), dim3(kBlock),
                            6 * R * sizeof(uint32_t) + stage_bytes, st, kin, vin, n, c->low_bits, (uint32_t)c->ncells,
                            (const T*)x, (T*)c->xs, c->keys, c->perm, c->off, direct ? c->hist : nullptr,
-                           c->block_sums, (uint32_t)c->ntiles, 1u << c->digit_bits, pay);
+                           top_scanned, (uint32_t)c->ntiles, 1u << c->digit_bits, pay);
     else
         hipLaunchKernelGGL((k_bucket_finalize<T, D, IPT, false>), dim3(nbuckets), dim3(kBlock), 6 * R * sizeof(uint32_t),
                            st, kin, vin, n, c->low_bits, (uint32_t)c->ncells, (const T*)x, (T*)c->xs, c->keys,
-                           c->perm, c->off, direct ? c->hist : nullptr, c->block_sums, (uint32_t)c->ntiles,
+                           c->perm, c->off, direct ? c->hist : nullptr, top_scanned, (uint32_t)c->ntiles,
                            1u << c->digit_bits, pay);
     ABORIA_HIP(ctx, hipGetLastError());
     return ABORIA_OK;
@@ -1177,7 +1235,8 @@ extern "C" aboria_status aboria_build_cells(aboria_ctx* ctx, aboria_dtype dtype,
                 {&c->work, tsz * 4 * nn},
                 {&c->work2, tsz * 4 * nn},
                 {(void**)&c->hist, sizeof(uint32_t) * (size_t)c->hist_len},
-                {(void**)&c->block_sums, sizeof(uint32_t) * (size_t)c->nblock_sums},
+                // raw block totals, then (second half) the radix pass's scanned copy
+                {(void**)&c->block_sums, sizeof(uint32_t) * 2 * (size_t)c->nblock_sums},
                 {(void**)&c->gen, sizeof(uint32_t) * 2},
             };
             for (auto& a : allocs) {
@@ -1252,11 +1311,16 @@ extern "C" aboria_status aboria_cells_view_get(const aboria_cells* c, aboria_cel
     return ABORIA_OK;
 }
 
-extern "C" aboria_status aboria_cells_destroy(aboria_cells* c) {
-    if (!c) return ABORIA_OK;
+static void release_cells(void* p) {
+    aboria_cells* c = static_cast<aboria_cells*>(p);
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
     free_cells_buffers(c);
     delete c;
+}
+
+extern "C" aboria_status aboria_cells_destroy(aboria_cells* c) {
+    if (!c) return ABORIA_OK;
+    aboria::release_or_defer(release_cells, c);
     return ABORIA_OK;
 }

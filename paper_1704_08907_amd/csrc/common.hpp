@@ -163,6 +163,13 @@ namespace aboria {
 int log_level();
 void log_msg(const char* fmt, ...);
 
+// Releases (hipFree, synchronisation) are not allowed on a thread while it
+// captures a stream: such a call would invalidate the capture.  A release
+// requested then (a cell list, a context or a graph, e.g. from a garbage
+// collector) is queued and runs when the thread's last capture ends.
+bool capture_active_on_thread();
+void release_or_defer(void (*fn)(void*), void* obj);
+
 // The persistent tuning cache (ABORIA_TUNE_CACHE): loaded when a context is
 // created, written after every tuning call.
 void tune_cache_load(aboria_ctx* ctx);

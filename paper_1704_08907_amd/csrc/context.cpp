@@ -8,6 +8,8 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "common.hpp"
 
@@ -77,6 +79,26 @@ int32_t op_nparams(int32_t op) {
     }
 }
 
+namespace {
+thread_local int t_capture_depth = 0;
+thread_local std::vector<std::pair<void (*)(void*), void*>> t_deferred;
+}  // namespace
+
+bool capture_active_on_thread() { return t_capture_depth > 0; }
+
+void release_or_defer(void (*fn)(void*), void* obj) {
+    if (t_capture_depth > 0) t_deferred.emplace_back(fn, obj);
+    else fn(obj);
+}
+
+// Runs the releases queued while this thread captured (after its last capture ended).
+static void run_deferred_releases() {
+    if (t_capture_depth > 0) return;
+    std::vector<std::pair<void (*)(void*), void*>> todo;
+    todo.swap(t_deferred);
+    for (auto& r : todo) r.first(r.second);
+}
+
 }  // namespace aboria
 
 using namespace aboria;
@@ -125,14 +147,19 @@ extern "C" aboria_status aboria_create(int32_t device, void* hip_stream, aboria_
     return ABORIA_OK;
 }
 
-extern "C" aboria_status aboria_destroy(aboria_ctx* ctx) {
-    if (!ctx) return ABORIA_OK;
+static void release_ctx(void* p) {
+    aboria_ctx* ctx = static_cast<aboria_ctx*>(p);
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->d_flag) (void)hipFree(ctx->d_flag);
     if (ctx->h_flag) (void)hipHostFree(ctx->h_flag);
     if (ctx->scratch) (void)hipFree(ctx->scratch);
     delete ctx;
+}
+
+extern "C" aboria_status aboria_destroy(aboria_ctx* ctx) {
+    if (!ctx) return ABORIA_OK;
+    aboria::release_or_defer(release_ctx, ctx);
     return ABORIA_OK;
 }
 
@@ -168,6 +195,7 @@ extern "C" aboria_status aboria_graph_capture_begin(aboria_ctx* ctx) {
     ABORIA_HIP(ctx, hipSetDevice(ctx->device));
     ABORIA_HIP(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
     ctx->capturing = true;
+    ++aboria::t_capture_depth;
     return ABORIA_OK;
 }
 
@@ -176,7 +204,10 @@ extern "C" aboria_status aboria_graph_capture_end(aboria_ctx* ctx, aboria_graph*
     if (!ctx->capturing) return fail(ctx, ABORIA_ERR_INVALID_ARG, "no capture in progress");
     ctx->capturing = false;
     hipGraph_t g = nullptr;
-    ABORIA_HIP(ctx, hipStreamEndCapture(ctx->stream, &g));
+    const hipError_t ec = hipStreamEndCapture(ctx->stream, &g);
+    if (aboria::t_capture_depth > 0) --aboria::t_capture_depth;
+    aboria::run_deferred_releases();
+    ABORIA_HIP(ctx, ec);
     aboria_graph* gr = new (std::nothrow) aboria_graph();
     if (!gr) {
         (void)hipGraphDestroy(g);
@@ -201,12 +232,17 @@ extern "C" aboria_status aboria_graph_launch(aboria_ctx* ctx, const aboria_graph
     return ABORIA_OK;
 }
 
-extern "C" aboria_status aboria_graph_destroy(aboria_graph* graph) {
-    if (!graph) return ABORIA_OK;
+static void release_graph(void* p) {
+    aboria_graph* graph = static_cast<aboria_graph*>(p);
     (void)hipSetDevice(graph->device);
     if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
     if (graph->graph) (void)hipGraphDestroy(graph->graph);
     delete graph;
+}
+
+extern "C" aboria_status aboria_graph_destroy(aboria_graph* graph) {
+    if (!graph) return ABORIA_OK;
+    aboria::release_or_defer(release_graph, graph);
     return ABORIA_OK;
 }
 

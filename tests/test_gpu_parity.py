@@ -468,3 +468,42 @@ def test_graph_replay_matches_eager():
         graph.close()
         gctx.sync()
         gctx.close()
+
+
+@pytest.mark.gpu
+def test_release_during_capture_is_deferred():
+    """A cell list, context or graph released while this thread captures (a
+    garbage collector may do that at any time) must not invalidate the capture:
+    the release waits for the capture's end."""
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        gctx = A.Context(0, stream)
+        other_ctx = A.Context(0, stream)
+        s = syn.spring_cube(n=4096).systems[0]
+        x = to_dev(s.x)
+        box = box_of(s)
+        cells = A.build_cells(gctx, x, [box])
+        spare = A.build_cells(gctx, x, [box])
+        y = torch.empty((x.shape[0], 3), device=dev())
+        A.pair_sum(gctx, cells, "spring", (1.0,), y=y)
+        stream.synchronize()
+        y_ref = y.clone()
+        A.graph_capture_begin(gctx)
+        A.build_cells(gctx, x, [box], cells=cells)
+        old_graph = A.graph_capture_end(gctx)
+        A.graph_capture_begin(gctx)
+        spare.close()          # releases during the capture
+        other_ctx.close()
+        old_graph.close()
+        A.build_cells(gctx, x, [box], cells=cells)
+        A.pair_sum(gctx, cells, "spring", (1.0,), y=y)
+        graph = A.graph_capture_end(gctx)
+        y.zero_()
+        stream.synchronize()
+        A.graph_launch(gctx, graph)
+        stream.synchronize()
+        assert torch.equal(y, y_ref)
+        graph.close()
+        gctx.sync()
+        gctx.close()
+
