@@ -28,8 +28,8 @@ namespace aboria {
 constexpr int kBlock = 256;
 // A sort tile is kBlock * IPT keys, IPT = 16, 8 or 4 chosen per cell list by
 // sort_ipt_for.
-constexpr int kScanIpt = 16;
-constexpr int kScanTile = kBlock * kScanIpt;  // 4096 values per scan block
+constexpr int kScanIpt = 4;
+constexpr int kScanTile = kBlock * kScanIpt;  // 1024 values per scan block
 constexpr int kMaxDigitBits = 10;
 // Scan blocks whose totals a radix pass's consumers prefix-sum themselves in LDS
 // (one value per block of kScanTile histogram entries); a longer histogram keeps
@@ -286,26 +286,57 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* w
     return pre + incl - v;
 }
 
-// out[p] = sum of in[q] for q < p within p's 4096-block; block_sums[b] = block total.
+// block_exclusive_scan for a workgroup of NW waves (wsum holds NW entries).
+template <int NW>
+__device__ __forceinline__ uint32_t block_exclusive_scan_w(uint32_t v, uint32_t* wsum, uint32_t* total) {
+    const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t t = __shfl_up(incl, o, 64);
+        if (lane >= (uint32_t)o) incl += t;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    uint32_t pre = 0, all = 0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+        pre += (uint32_t)q < w ? wsum[q] : 0u;
+        all += wsum[q];
+    }
+    *total = all;
+    __syncthreads();
+    return pre + incl - v;
+}
+
+// out[p] = sum of in[q] for q < p within p's kScanTile-block; block_sums[b] = block
+// total.  Where in and out are 16-byte aligned a thread's four values move as
+// one 16-byte load and store.
 __global__ __launch_bounds__(kBlock) void k_scan_local(const uint32_t* in, uint32_t* out,
                                                        uint32_t len, uint32_t* __restrict__ block_sums) {
+    static_assert(kScanIpt == 4, "one uint4 per thread");
     __shared__ uint32_t wsum[4];
     const uint32_t base = blockIdx.x * kScanTile + threadIdx.x * kScanIpt;
     uint32_t v[kScanIpt];
-    uint32_t tot = 0;
+    const bool aligned = ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15u) == 0;
+    const bool whole = aligned && base + kScanIpt <= len;
+    if (whole) {
+        const uint4 q = *reinterpret_cast<const uint4*>(in + base);
+        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    } else {
 #pragma unroll
-    for (int k = 0; k < kScanIpt; ++k) {
-        uint32_t idx = base + k;
-        v[k] = idx < len ? in[idx] : 0u;
-        tot += v[k];
+        for (int k = 0; k < kScanIpt; ++k) v[k] = base + k < len ? in[base + k] : 0u;
     }
+    const uint32_t tot = v[0] + v[1] + v[2] + v[3];
     uint32_t total;
-    uint32_t ex = block_exclusive_scan(tot, wsum, &total);
+    const uint32_t ex = block_exclusive_scan(tot, wsum, &total);
+    const uint32_t e[kScanIpt] = {ex, ex + v[0], ex + v[0] + v[1], ex + v[0] + v[1] + v[2]};
+    if (whole) {
+        *reinterpret_cast<uint4*>(out + base) = make_uint4(e[0], e[1], e[2], e[3]);
+    } else {
 #pragma unroll
-    for (int k = 0; k < kScanIpt; ++k) {
-        uint32_t idx = base + k;
-        if (idx < len) out[idx] = ex;
-        ex += v[k];
+        for (int k = 0; k < kScanIpt; ++k)
+            if (base + k < len) out[base + k] = e[k];
     }
     if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
 }
@@ -336,7 +367,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_top(uint32_t* __restrict__ bs, 
     }
 }
 
-// out[p] += block_sums[p / 4096]: completes a scan for consumers that need it whole.
+// out[p] += block_sums[p / kScanTile]: completes a scan for consumers that need it whole.
 __global__ __launch_bounds__(kBlock) void k_scan_add(uint32_t* __restrict__ out, uint32_t len,
                                                      const uint32_t* __restrict__ bs) {
     uint32_t p = blockIdx.x * kBlock + threadIdx.x;
@@ -362,7 +393,7 @@ aboria_status scan_exclusive_u32(aboria_ctx* ctx, const uint32_t* in, uint32_t* 
     return ABORIA_OK;
 }
 
-// The first level of scan_exclusive_u32 only: out holds each 4096-block's
+// The first level of scan_exclusive_u32 only: out holds each kScanTile-block's
 // exclusive scan and block_sums the blocks' raw totals.
 aboria_status scan_local_u32(aboria_ctx* ctx, const uint32_t* in, uint32_t* out, int64_t len, uint32_t* block_sums,
                              int64_t nblock_sums) {
@@ -608,8 +639,16 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __rest
 // histogram (hist_scan + block_sums, ntiles tiles) gives each bucket's start
 // directly; otherwise (hist_scan == nullptr) the bounds are found by binary
 // search of the high parts.
+// Threads of a bucket workgroup: eight waves for sort tiles of 2048 keys or
+// more (two workgroups fit a CU's LDS, so sixteen waves hide the bucket's
+// loads), four below.
+template <int IPT>
+struct BucketThreads {
+    static constexpr int value = IPT >= 8 ? 512 : 256;
+};
+
 template <typename T, int D, int IPT, bool STAGE>
-__global__ __launch_bounds__(kBlock) void k_bucket_finalize(const uint32_t* __restrict__ keys_in,
+__global__ __launch_bounds__(BucketThreads<IPT>::value) void k_bucket_finalize(const uint32_t* __restrict__ keys_in,
                                                             const uint32_t* __restrict__ vals_in, uint32_t n,
                                                             int lb, uint32_t ncells, const T* __restrict__ x,
                                                             T* __restrict__ xs, uint32_t* __restrict__ keys_out,
@@ -621,13 +660,16 @@ __global__ __launch_bounds__(kBlock) void k_bucket_finalize(const uint32_t* __re
                                                             const VecN<T, Pitch<D>::value>* __restrict__ pay) {
     constexpr int PITCH = Pitch<D>::value;
     constexpr int kSortTile = kBlock * IPT;
+    constexpr int NT = BucketThreads<IPT>::value;
+    constexpr int NW = NT / kWave;
+    constexpr int KPT = kSortTile / NT;  // keys of a chunk per thread
     extern __shared__ uint32_t lds[];
     const uint32_t R = 1u << lb, mask = R - 1u;
     uint32_t* hist = lds;              // [R]
     uint32_t* base = lds + R;          // [R] running destination base per digit
-    uint32_t* cnt = lds + 2 * R;       // [4][R] per-wave counts of the current chunk
+    uint32_t* cnt = lds + 2 * R;       // [NW][R] per-wave counts of the current chunk
     __shared__ uint32_t s_range[2];
-    __shared__ uint32_t s_wsum[4];
+    __shared__ uint32_t s_wsum[NW];
     const uint32_t bucket = blockIdx.x;
     const uint32_t cell0 = bucket << lb;
     if (threadIdx.x < 2) {
@@ -654,15 +696,15 @@ __global__ __launch_bounds__(kBlock) void k_bucket_finalize(const uint32_t* __re
     __syncthreads();
     const uint32_t b0 = s_range[0], b1 = s_range[1];
     // exclusive scan of hist into base and the offsets of the bucket's cells: each
-    // thread owns a run of R/256 digits (R >= 256) or one
+    // thread owns a run of R/NT digits (R >= NT) or one
     auto scan_hist = [&]() {
-        const uint32_t per = R >= (uint32_t)kBlock ? R / kBlock : 1u;
+        const uint32_t per = R >= (uint32_t)NT ? R / NT : 1u;
         const uint32_t d0 = threadIdx.x * per;
         uint32_t tot = 0;
         if (d0 < R)
             for (uint32_t k = 0; k < per; ++k) tot += hist[d0 + k];
         uint32_t total;
-        uint32_t ex = block_exclusive_scan(tot, s_wsum, &total);
+        uint32_t ex = block_exclusive_scan_w<NW>(tot, s_wsum, &total);
         if (d0 < R) {
             for (uint32_t k = 0; k < per; ++k) {
                 const uint32_t c = cell0 + d0 + k;
@@ -676,9 +718,9 @@ __global__ __launch_bounds__(kBlock) void k_bucket_finalize(const uint32_t* __re
     // per-wave rank counts below; a larger (or empty) one counts its keys first.
     const bool single = b1 > b0 && b1 - b0 <= (uint32_t)kSortTile;
     if (!single) {
-        for (uint32_t d = threadIdx.x; d < R; d += kBlock) hist[d] = 0;
+        for (uint32_t d = threadIdx.x; d < R; d += NT) hist[d] = 0;
         __syncthreads();
-        for (uint32_t i = b0 + threadIdx.x; i < b1; i += kBlock) atomicAdd(&hist[keys_in[i] & mask], 1u);
+        for (uint32_t i = b0 + threadIdx.x; i < b1; i += NT) atomicAdd(&hist[keys_in[i] & mask], 1u);
         __syncthreads();
         scan_hist();
         __syncthreads();
@@ -687,19 +729,17 @@ __global__ __launch_bounds__(kBlock) void k_bucket_finalize(const uint32_t* __re
     uint32_t* wc = cnt + w * R;
     const uint64_t lt = lanemask_lt();
     for (uint32_t chunk = b0; chunk < b1; chunk += kSortTile) {
-        for (uint32_t d = threadIdx.x; d < R; d += kBlock) {
-            cnt[d] = 0;
-            cnt[R + d] = 0;
-            cnt[2 * R + d] = 0;
-            cnt[3 * R + d] = 0;
+        for (uint32_t d = threadIdx.x; d < R; d += NT) {
+#pragma unroll
+            for (int q = 0; q < NW; ++q) cnt[q * R + d] = 0;
         }
         __syncthreads();
-        const uint32_t wbase = chunk + w * (kWave * IPT);
-        uint32_t key[IPT], val[IPT], loc[IPT];
-        VecN<T, PITCH> row[IPT];
+        const uint32_t wbase = chunk + w * (kWave * KPT);
+        uint32_t key[KPT], val[KPT], loc[KPT];
+        VecN<T, PITCH> row[KPT];
         // every load of the chunk first, so they are in flight together
 #pragma unroll
-        for (int st = 0; st < IPT; ++st) {
+        for (int st = 0; st < KPT; ++st) {
             const uint32_t idx = wbase + st * kWave + lane;
             const bool valid = idx < b1;
             key[st] = valid ? keys_in[idx] : 0u;
@@ -707,7 +747,7 @@ __global__ __launch_bounds__(kBlock) void k_bucket_finalize(const uint32_t* __re
             if (pay && valid) row[st] = pay[idx];  // the row travelled with its key through the radix passes
         }
 #pragma unroll
-        for (int st = 0; st < IPT; ++st) {
+        for (int st = 0; st < KPT; ++st) {
             const uint32_t idx = wbase + st * kWave + lane;
             const bool valid = idx < b1;
             const uint32_t k = key[st];
@@ -725,29 +765,36 @@ __global__ __launch_bounds__(kBlock) void k_bucket_finalize(const uint32_t* __re
         }
         __syncthreads();
         if (single) {
-            for (uint32_t d = threadIdx.x; d < R; d += kBlock)
-                hist[d] = cnt[d] + cnt[R + d] + cnt[2 * R + d] + cnt[3 * R + d];
+            for (uint32_t d = threadIdx.x; d < R; d += NT) {
+                uint32_t h = 0;
+#pragma unroll
+                for (int q = 0; q < NW; ++q) h += cnt[q * R + d];
+                hist[d] = h;
+            }
             __syncthreads();
             scan_hist();
             __syncthreads();
         }
-        for (uint32_t d = threadIdx.x; d < R; d += kBlock) {
-            const uint32_t a0 = cnt[d], a1 = cnt[R + d], a2 = cnt[2 * R + d], a3 = cnt[3 * R + d];
-            cnt[d] = base[d];
-            cnt[R + d] = base[d] + a0;
-            cnt[2 * R + d] = base[d] + a0 + a1;
-            cnt[3 * R + d] = base[d] + a0 + a1 + a2;
-            base[d] += a0 + a1 + a2 + a3;
+        for (uint32_t d = threadIdx.x; d < R; d += NT) {
+            // the waves' first destinations of digit d, in wave (= index) order
+            uint32_t run = base[d];
+#pragma unroll
+            for (int q = 0; q < NW; ++q) {
+                const uint32_t a = cnt[q * R + d];
+                cnt[q * R + d] = run;
+                run += a;
+            }
+            base[d] = run;
         }
         __syncthreads();
         if (STAGE && single) {
             // sorted order assembled in LDS, then written as contiguous runs (scattered
             // stores into the bucket's range left partly written lines behind)
-            uint32_t* sk = lds + 6 * R;
+            uint32_t* sk = lds + (2 + NW) * R;  // after hist, base and the NW per-wave counts
             uint32_t* sv = sk + kSortTile;
             VecN<T, PITCH>* srow = reinterpret_cast<VecN<T, PITCH>*>(sv + kSortTile);
 #pragma unroll
-            for (int st = 0; st < IPT; ++st) {
+            for (int st = 0; st < KPT; ++st) {
                 const uint32_t idx = wbase + st * kWave + lane;
                 if (idx < b1) {
                     const uint32_t rel = wc[key[st] & mask] + loc[st];
@@ -760,7 +807,7 @@ __global__ __launch_bounds__(kBlock) void k_bucket_finalize(const uint32_t* __re
             }
             __syncthreads();
             const uint32_t count = b1 - b0;
-            for (uint32_t i = threadIdx.x; i < count; i += kBlock) {
+            for (uint32_t i = threadIdx.x; i < count; i += NT) {
                 if (b0 + i < n) {
                     keys_out[b0 + i] = sk[i];
                     perm_out[b0 + i] = sv[i];
@@ -771,7 +818,7 @@ __global__ __launch_bounds__(kBlock) void k_bucket_finalize(const uint32_t* __re
             continue;
         }
 #pragma unroll
-        for (int st = 0; st < IPT; ++st) {
+        for (int st = 0; st < KPT; ++st) {
             const uint32_t idx = wbase + st * kWave + lane;
             if (idx < b1) {
                 const uint32_t dest = b0 + wc[key[st] & mask] + loc[st];
@@ -1081,13 +1128,15 @@ aboria_status launch_build_radix_ipt(aboria_ctx* ctx, aboria_cells* c, const voi
     constexpr bool kStageable = IPT <= 8 && sizeof(VecN<T, Pitch<D>::value>) <= 16;
     const bool stage = kStageable && pay != nullptr;
     const size_t stage_bytes = (size_t)kSortTile * (2 * sizeof(uint32_t) + sizeof(VecN<T, Pitch<D>::value>));
+    constexpr int kBucketThreads = BucketThreads<IPT>::value;
+    const size_t cnt_bytes = (2 + kBucketThreads / kWave) * (size_t)R * sizeof(uint32_t);
     if (stage)
-        hipLaunchKernelGGL((k_bucket_finalize<T, D, IPT, kStageable>), dim3(nbuckets), dim3(kBlock),
-                           6 * R * sizeof(uint32_t) + stage_bytes, st, kin, vin, n, c->low_bits, (uint32_t)c->ncells,
+        hipLaunchKernelGGL((k_bucket_finalize<T, D, IPT, kStageable>), dim3(nbuckets), dim3(kBucketThreads),
+                           cnt_bytes + stage_bytes, st, kin, vin, n, c->low_bits, (uint32_t)c->ncells,
                            (const T*)x, (T*)c->xs, c->keys, c->perm, c->off, direct ? c->hist : nullptr,
                            top_scanned, (uint32_t)c->ntiles, 1u << c->digit_bits, pay);
     else
-        hipLaunchKernelGGL((k_bucket_finalize<T, D, IPT, false>), dim3(nbuckets), dim3(kBlock), 6 * R * sizeof(uint32_t),
+        hipLaunchKernelGGL((k_bucket_finalize<T, D, IPT, false>), dim3(nbuckets), dim3(kBucketThreads), cnt_bytes,
                            st, kin, vin, n, c->low_bits, (uint32_t)c->ncells, (const T*)x, (T*)c->xs, c->keys,
                            c->perm, c->off, direct ? c->hist : nullptr, top_scanned, (uint32_t)c->ntiles,
                            1u << c->digit_bits, pay);
