@@ -463,22 +463,33 @@ def main():
         xd_t = torch.from_numpy(xd).to(dev)
         wd_t = torch.from_numpy(wd).to(dev)
         yd = torch.empty(xd.shape[0], device=dev)
-        t_dense = timed(lambda: A.dense_sum(ctx, xd_t, xd_t, wd_t, sigma, y=yd), reps=10)
         npair = float(xd.shape[0]) ** 2
+        gyd = torch.from_numpy(syn.SplitMix64(12).normal(xd.shape[0]).astype(np.float32)).to(dev)
+        # the launch plans (targets per lane, workgroup target): the untuned default, then the
+        # dense tuner's choice for each call
+        t_dense0 = timed(lambda: A.dense_sum(ctx, xd_t, xd_t, wd_t, sigma, y=yd), reps=10)
+        t_dense_b0 = timed(lambda: A.dense_sum_backward(ctx, xd_t, xd_t, wd_t, sigma, gyd), reps=5)
+        t_mq0 = timed(lambda: A.dense_sum(ctx, xd_t, xd_t, wd_t, 0.1, y=yd, kernel="multiquadric"), reps=10)
+        plan_g = A.autotune_dense(ctx, xd_t, xd_t, wd_t, sigma)
+        plan_gb = A.autotune_dense(ctx, xd_t, xd_t, wd_t, sigma, gy=gyd)
+        plan_mq = A.autotune_dense(ctx, xd_t, xd_t, wd_t, 0.1, kernel="multiquadric")
+        t_dense = timed(lambda: A.dense_sum(ctx, xd_t, xd_t, wd_t, sigma, y=yd), reps=10)
         # per pair: 2 sub, 1 mul, 1 fma, 1 fma (and the exp2)
         extra["dense_gaussian_n65536"] = {"ms": t_dense, "pairs_per_s": npair / (t_dense * 1e-3),
-                                          "valu_frac": npair * 5 / (t_dense * 1e-3) / 1e12 / VALU_PEAK_TOPS}
+                                          "valu_frac": npair * 5 / (t_dense * 1e-3) / 1e12 / VALU_PEAK_TOPS,
+                                          "plan": A.dense_plan_name(plan_g), "ms_untuned": t_dense0}
         # its adjoint with targets = sources: K^T gy plus the target and source position gradients
-        gyd = torch.from_numpy(syn.SplitMix64(12).normal(xd.shape[0]).astype(np.float32)).to(dev)
         t_dense_b = timed(lambda: A.dense_sum_backward(ctx, xd_t, xd_t, wd_t, sigma, gyd), reps=5)
         # passes over the N^2 pairs: K^T gy with the source gradient, then the target gradient
         extra["dense_gaussian_n65536_adjoint"] = {"ms": t_dense_b, "pair_passes": 2,
-                                                  "pairs_per_s": 2 * npair / (t_dense_b * 1e-3)}
+                                                  "pairs_per_s": 2 * npair / (t_dense_b * 1e-3),
+                                                  "plan": A.dense_plan_name(plan_gb), "ms_untuned": t_dense_b0}
         # the multiquadric basis of the RBF example, c = 0.1 (per pair: 2 sub, mul, fma, add of c^2,
         # fma, and the sqrt)
         t_mq = timed(lambda: A.dense_sum(ctx, xd_t, xd_t, wd_t, 0.1, y=yd, kernel="multiquadric"), reps=10)
         extra["dense_multiquadric_n65536"] = {"ms": t_mq, "pairs_per_s": npair / (t_mq * 1e-3),
-                                              "valu_frac": npair * 6 / (t_mq * 1e-3) / 1e12 / VALU_PEAK_TOPS}
+                                              "valu_frac": npair * 6 / (t_mq * 1e-3) / 1e12 / VALU_PEAK_TOPS,
+                                              "plan": A.dense_plan_name(plan_mq), "ms_untuned": t_mq0}
         del xd_t, wd_t, yd, gyd
         # soft sphere N = 2^18 forward + adjoint (energy gradient)
         w4 = syn.soft_sphere_cube()

@@ -391,8 +391,8 @@ aboria_status aboria_graph_destroy(aboria_graph* graph);
  *
  * Persistence: when the environment variable ABORIA_TUNE_CACHE names a file
  * at aboria_create, the context loads the choices stored there for this
- * device architecture, and every aboria_autotune and aboria_autotune_cells
- * rewrites the file with the context's choices (JSON, one entry per line,
+ * device architecture, and every aboria_autotune, aboria_autotune_cells and
+ * aboria_autotune_dense rewrites the file with the context's choices (JSON, one entry per line,
  * variants by name; written to a temporary file and renamed).  Contexts that
  * tune concurrently with the same file keep the last writer's entries.
  * ABORIA_LOG=1 prints errors and tuning decisions to stderr. */
@@ -417,6 +417,31 @@ aboria_status aboria_autotune_cells(aboria_ctx* ctx, aboria_dtype dtype, int32_t
                                     const int64_t* offsets_host, const void* x, aboria_op op,
                                     const double* params_host, int32_t nparams, const void* a, int32_t na,
                                     const void* gy, int32_t ny, aboria_box* boxes_out, double* factor_host);
+
+/* Dense-sum launch tuning (Sections 1 and 1.1, the kernel sums of
+ * aboria_dense_sum): times the launch plans -- targets kept per lane (2, 4, or
+ * for float 8) and the number of workgroups the source split aims for (1024,
+ * 2048, 4096) -- of aboria_dense_sum (gy == NULL) or of
+ * aboria_dense_sum_backward computing all three gradients (gy given) on the
+ * caller's arrays, and makes later calls with the same direction, kernel,
+ * dtype, d and size buckets (floor log2 of n_target and n_source) use the
+ * fastest.  scratch receives the outputs: y[n_target] for the forward,
+ * gxt[n_target][d] then gxs[n_source][d] then gw[n_source] (contiguous) for
+ * the backward.  A plan changes the split of the source range, so results
+ * move by rounding only.  *choice_host (may be NULL) receives the plan, named
+ * by aboria_dense_plan_name.  Persisted like aboria_autotune's choices;
+ * synchronises; not capturable.  Errors as for aboria_dense_sum, and
+ * INVALID_ARG when there are no pairs to time. */
+aboria_status aboria_autotune_dense(aboria_ctx* ctx, aboria_dtype dtype, aboria_kernel kernel,
+                                    const double* params_host, int32_t nparams, int32_t d, int64_t n_target,
+                                    const void* xt, int64_t n_source, const void* xs, const void* w,
+                                    const void* gy, void* scratch, int32_t* choice_host);
+/* Name of a dense launch plan ("" when out of range); static storage. */
+const char* aboria_dense_plan_name(int32_t plan);
+/* Forces dense launch plan `plan` for later dense sums on ctx (-1: the tuned
+ * choice, else plan 0); a float-only plan runs plan 0 in float64.
+ * INVALID_ARG for an unknown plan. */
+aboria_status aboria_set_dense_plan(aboria_ctx* ctx, int32_t plan);
 
 /* Without tuning or a forced variant, a sum on a cell list whose systems all
  * have at most 2048 particles tests all pairs of each system at the minimum

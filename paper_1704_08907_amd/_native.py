@@ -54,7 +54,8 @@ EXPORTS = ["aboria_create", "aboria_destroy", "aboria_set_stream", "aboria_last_
            "aboria_set_variant", "aboria_op_ny", "aboria_op_na", "aboria_set_build_strategy",
            "aboria_build_neighbours", "aboria_neighbour_capacity", "aboria_integrate",
            "aboria_dense_sum_backward", "aboria_autotune_cells", "aboria_pair_sum_and_backward",
-           "aboria_dense_sum_noalloc", "aboria_md_step", "aboria_cells_reorder", "aboria_selected_variant"]
+           "aboria_dense_sum_noalloc", "aboria_md_step", "aboria_cells_reorder", "aboria_selected_variant",
+           "aboria_autotune_dense", "aboria_dense_plan_name", "aboria_set_dense_plan"]
 
 
 def lib():
@@ -80,6 +81,10 @@ def lib():
             "aboria_pair_list": ([P, P, I64, P, P, C.POINTER(I64)], I32),
             "aboria_dense_sum": ([P, I32, I32, C.POINTER(C.c_double), I32, I32, I64, P, I64, P, P, P], I32),
             "aboria_selected_variant": ([P, P, I32, I32, C.POINTER(I32)], I32),
+            "aboria_autotune_dense": ([P, I32, I32, C.POINTER(C.c_double), I32, I32, I64, P, I64, P, P, P, P,
+                                       C.POINTER(I32)], I32),
+            "aboria_dense_plan_name": ([I32], C.c_char_p),
+            "aboria_set_dense_plan": ([P, I32], I32),
             "aboria_md_step": ([P, P, I32, C.POINTER(C.c_double), I32, C.c_double, P, P, P, P], I32),
             "aboria_cells_reorder": ([P, P, I32, C.POINTER(P), C.POINTER(I32)], I32),
             "aboria_dense_sum_noalloc": ([P, I32, I32, C.POINTER(C.c_double), I32, I32, I64, P, I64, P, P, P], I32),
@@ -170,6 +175,10 @@ class Context:
         """Force a neighbour-sum variant for later calls (-1 = tuned / default)."""
         self.check(lib().aboria_set_variant(self.handle, v), "set_variant")
         self.forced_variant = int(v)
+
+    def set_dense_plan(self, plan: int):
+        """Force a dense-sum launch plan for later calls (-1 = tuned / default)."""
+        self.check(lib().aboria_set_dense_plan(self.handle, int(plan)), "set_dense_plan")
 
     def close(self):
         if getattr(self, "handle", None):
@@ -423,6 +432,32 @@ def dense_sum(ctx: Context, xt: torch.Tensor, xs: torch.Tensor, w: torch.Tensor,
                                 _ptr(xt), int(xs.shape[0]), _ptr(xs), _ptr(w), _ptr(y))
     ctx.check(st, "dense_sum")
     return y
+
+
+def autotune_dense(ctx: Context, xt: torch.Tensor, xs: torch.Tensor, w: torch.Tensor, sigma: float,
+                   gy: Optional[torch.Tensor] = None, kernel: str = "gaussian") -> int:
+    """aboria_autotune_dense: times the dense launch plans of the forward (gy None) or the
+    backward and caches the fastest; returns the chosen plan."""
+    _check_dev(xt, "xt")
+    _check_dev(xs, "xs", xt.dtype)
+    _check_dev(w, "w", xt.dtype)
+    d, nt, ns = int(xt.shape[1]), int(xt.shape[0]), int(xs.shape[0])
+    if gy is not None:
+        _check_dev(gy, "gy", xt.dtype)
+        scratch = torch.empty(d * nt + (d + 1) * ns, dtype=xt.dtype, device=xt.device)
+    else:
+        scratch = torch.empty(nt, dtype=xt.dtype, device=xt.device)
+    arr, npar = _params([sigma])
+    out = C.c_int32(-1)
+    st = lib().aboria_autotune_dense(ctx.handle, _dtype_code(xt), KERNELS[kernel], arr, npar, d, nt, _ptr(xt), ns,
+                                     _ptr(xs), _ptr(w), _ptr(gy) if gy is not None else None, _ptr(scratch),
+                                     C.byref(out))
+    ctx.check(st, "autotune_dense")
+    return int(out.value)
+
+
+def dense_plan_name(plan: int) -> str:
+    return lib().aboria_dense_plan_name(int(plan)).decode()
 
 
 def dense_sum_noalloc(ctx: Context, xt: torch.Tensor, xs: torch.Tensor, w: torch.Tensor, sigma: float,

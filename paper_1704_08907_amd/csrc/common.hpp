@@ -104,6 +104,13 @@ struct aboria_ctx {
         double factor;
     };
     std::vector<std::pair<uint64_t, CellsChoice>> cells_cache;
+    // dense-sum tuner results: key -> targets per lane and workgroup target of the launch
+    struct DenseChoice {
+        int32_t ti;
+        int32_t wg;
+    };
+    std::vector<std::pair<uint64_t, DenseChoice>> dense_cache;
+    int32_t dense_plan_forced = -1;  // the dense tuner's current trial (-1: none)
     std::string arch;        // the device's architecture name (keys the persistent cache)
     std::string cache_path;  // ABORIA_TUNE_CACHE at creation ("" = no persistent cache)
 };

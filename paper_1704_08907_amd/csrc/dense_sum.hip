@@ -193,7 +193,52 @@ __global__ __launch_bounds__(256) void k_dense_reduce2(const T* __restrict__ ypa
 
 namespace {
 
-constexpr int kTargetsPerThread = 4;
+// Launch shapes of the dense sum: targets kept per lane and the number of
+// workgroups the source split aims for (the split count is that over the
+// target blocks, at most one per source tile).  Plan 0 is the untuned default;
+// eight targets per lane are float only (float64 would hold twice the
+// registers).  aboria_autotune_dense times them.
+struct DensePlan {
+    int32_t ti;
+    int32_t wg;
+    const char* name;
+};
+constexpr DensePlan kDensePlans[] = {
+    {4, 2048, "4 targets per lane, 2048 workgroups"}, {2, 2048, "2 targets per lane, 2048 workgroups"},
+    {8, 2048, "8 targets per lane, 2048 workgroups"}, {4, 4096, "4 targets per lane, 4096 workgroups"},
+    {8, 4096, "8 targets per lane, 4096 workgroups"}, {2, 1024, "2 targets per lane, 1024 workgroups"},
+    {4, 1024, "4 targets per lane, 1024 workgroups"}, {8, 1024, "8 targets per lane, 1024 workgroups"},
+};
+constexpr int32_t kNumDensePlans = sizeof(kDensePlans) / sizeof(kDensePlans[0]);
+
+bool dense_plan_ok(int32_t p, int dtype) {
+    return p >= 0 && p < kNumDensePlans && (dtype == ABORIA_F32 || kDensePlans[p].ti <= 4);
+}
+
+// Tuning key: direction, kernel, dtype, d and the size buckets (floor log2) of
+// the targets and sources.
+uint64_t dense_key(bool backward, int kernel, int dtype, int d, int64_t nt, int64_t ns) {
+    uint64_t k = backward ? 1u : 0u;
+    k = k * 4 + (uint64_t)kernel;
+    k = k * 4 + (uint64_t)dtype;
+    k = k * 4 + (uint64_t)d;
+    k = k * 64 + (uint64_t)std::floor(std::log2((double)nt + 1.0));
+    k = k * 64 + (uint64_t)std::floor(std::log2((double)ns + 1.0));
+    return k;
+}
+
+// The plan a call uses: the tuner's current trial, else the cached choice for
+// its key, else plan 0.
+int32_t dense_plan_for(const aboria_ctx* ctx, uint64_t key, int dtype) {
+    if (ctx->dense_plan_forced >= 0) return ctx->dense_plan_forced;
+    for (const auto& kv : ctx->dense_cache) {
+        if (kv.first != key) continue;
+        for (int32_t p = 0; p < kNumDensePlans; ++p)
+            if (kDensePlans[p].ti == kv.second.ti && kDensePlans[p].wg == kv.second.wg && dense_plan_ok(p, dtype))
+                return p;
+    }
+    return 0;
+}
 
 // Kernel constants: Gaussian prm = sigma, multiquadric prm = c.
 struct KernelPlan {
@@ -271,13 +316,14 @@ aboria_status noalloc_scratch(aboria_ctx* ctx, void** out) {
 template <typename T, int D, int KERN, int MODE>
 aboria_status launch_dense(aboria_ctx* ctx, uint32_t nt, const void* xt, uint32_t ns, const void* xs, const void* w,
                            const KernelPlan& kp, const void* mult, void* out, void* out2, void* part,
-                           size_t part_cap) {
+                           size_t part_cap, int32_t plan) {
     constexpr int OUT = dense_out<MODE, D>();
-    const uint32_t per_block = kDenseBlock * kTargetsPerThread;
+    const DensePlan& pl = kDensePlans[dense_plan_ok(plan, sizeof(T) == 4 ? ABORIA_F32 : ABORIA_F64) ? plan : 0];
+    const uint32_t per_block = kDenseBlock * (uint32_t)pl.ti;
     const uint32_t tblocks = (nt + per_block - 1) / per_block;
     const uint32_t ntiles = std::max<uint32_t>((ns + kDenseTile - 1) / kDenseTile, 1);
     // enough workgroups to fill 256 CUs several times over
-    uint32_t nsplit = std::max<uint32_t>(1, (2048 + tblocks - 1) / tblocks);
+    uint32_t nsplit = std::max<uint32_t>(1, ((uint32_t)pl.wg + tblocks - 1) / tblocks);
     nsplit = std::min(nsplit, ntiles);
     const size_t split_bytes = sizeof(T) * (size_t)nt * OUT;
     if (part) {
@@ -296,9 +342,17 @@ aboria_status launch_dense(aboria_ctx* ctx, uint32_t nt, const void* xt, uint32_
         if (st != ABORIA_OK) return st;
         part = ctx->scratch;
     }
-    hipLaunchKernelGGL((k_dense<T, D, kTargetsPerThread, KERN, MODE>), dim3(tblocks, nsplit), dim3(kDenseBlock), 0,
-                       ctx->stream, (const T*)xt, nt, (const T*)xs, (const T*)w, ns, (T)kp.sc, (T)kp.c2, jchunk,
-                       (T*)part);
+#define ABORIA_DENSE_LAUNCH(TI)                                                                            \
+    hipLaunchKernelGGL((k_dense<T, D, TI, KERN, MODE>), dim3(tblocks, nsplit), dim3(kDenseBlock), 0, ctx->stream, \
+                       (const T*)xt, nt, (const T*)xs, (const T*)w, ns, (T)kp.sc, (T)kp.c2, jchunk, (T*)part)
+    if (pl.ti == 2) {
+        ABORIA_DENSE_LAUNCH(2);
+    } else if (pl.ti == 8) {
+        if constexpr (sizeof(T) == 4) ABORIA_DENSE_LAUNCH(8);
+    } else {
+        ABORIA_DENSE_LAUNCH(4);
+    }
+#undef ABORIA_DENSE_LAUNCH
     if constexpr (MODE == kSumGrad)
         hipLaunchKernelGGL((k_dense_reduce2<T, D>), dim3((nt + 255) / 256), dim3(256), 0, ctx->stream,
                            (const T*)part, nt, nsplit, (const T*)mult, (T)kp.C, (T*)out, (T*)out2);
@@ -312,42 +366,42 @@ aboria_status launch_dense(aboria_ctx* ctx, uint32_t nt, const void* xt, uint32_
 template <typename T, int D, int MODE>
 aboria_status launch_kernel(aboria_ctx* ctx, int kernel, uint32_t nt, const void* xt, uint32_t ns, const void* xs,
                             const void* w, double prm, const void* mult, void* out, void* out2, void* part,
-                            size_t part_cap) {
+                            size_t part_cap, int32_t plan) {
     const KernelPlan kp = plan_kernel<T>(kernel, prm);
     if (kernel == ABORIA_K_GAUSSIAN)
         return launch_dense<T, D, ABORIA_K_GAUSSIAN, MODE>(ctx, nt, xt, ns, xs, w, kp, mult, out, out2, part,
-                                                            part_cap);
+                                                            part_cap, plan);
     return launch_dense<T, D, ABORIA_K_MULTIQUADRIC, MODE>(ctx, nt, xt, ns, xs, w, kp, mult, out, out2, part,
-                                                            part_cap);
+                                                            part_cap, plan);
 }
 
 template <int MODE>
 aboria_status dispatch(aboria_ctx* ctx, int dtype, int d, int kernel, uint32_t nt, const void* xt, uint32_t ns,
                        const void* xs, const void* w, double prm, const void* mult, void* out,
-                       void* out2 = nullptr, void* part = nullptr, size_t part_cap = 0) {
+                       void* out2 = nullptr, void* part = nullptr, size_t part_cap = 0, int32_t plan = 0) {
     if (dtype == ABORIA_F32) {
         switch (d) {
             case 1:
                 return launch_kernel<float, 1, MODE>(ctx, kernel, nt, xt, ns, xs, w, prm, mult, out, out2, part,
-                                                     part_cap);
+                                                     part_cap, plan);
             case 2:
                 return launch_kernel<float, 2, MODE>(ctx, kernel, nt, xt, ns, xs, w, prm, mult, out, out2, part,
-                                                     part_cap);
+                                                     part_cap, plan);
             default:
                 return launch_kernel<float, 3, MODE>(ctx, kernel, nt, xt, ns, xs, w, prm, mult, out, out2, part,
-                                                     part_cap);
+                                                     part_cap, plan);
         }
     }
     switch (d) {
         case 1:
             return launch_kernel<double, 1, MODE>(ctx, kernel, nt, xt, ns, xs, w, prm, mult, out, out2, part,
-                                                  part_cap);
+                                                  part_cap, plan);
         case 2:
             return launch_kernel<double, 2, MODE>(ctx, kernel, nt, xt, ns, xs, w, prm, mult, out, out2, part,
-                                                  part_cap);
+                                                  part_cap, plan);
         default:
             return launch_kernel<double, 3, MODE>(ctx, kernel, nt, xt, ns, xs, w, prm, mult, out, out2, part,
-                                                  part_cap);
+                                                  part_cap, plan);
     }
 }
 
@@ -400,8 +454,9 @@ extern "C" aboria_status aboria_dense_sum(aboria_ctx* ctx, aboria_dtype dtype, a
         aboria_status st =
             check_dense_sum(ctx, dtype, kernel, params_host, nparams, d, n_target, xt, n_source, xs, w, y);
         if (st != ABORIA_OK || n_target == 0) return st;
+        const int32_t plan = dense_plan_for(ctx, dense_key(false, kernel, dtype, d, n_target, n_source), dtype);
         return dispatch<kSum>(ctx, dtype, d, kernel, (uint32_t)n_target, xt, (uint32_t)n_source, xs, w,
-                              params_host[0], nullptr, y);
+                              params_host[0], nullptr, y, nullptr, nullptr, 0, plan);
     } catch (...) {
         return fail(ctx, ABORIA_ERR_OUT_OF_MEMORY, "host exception in dense_sum");
     }
@@ -423,8 +478,9 @@ extern "C" aboria_status aboria_dense_sum_noalloc(aboria_ctx* ctx, aboria_dtype 
                             std::to_string(kNoAllocScratchBytes / tsz) + " targets at most)");
         void* part = nullptr;
         if ((st = noalloc_scratch(ctx, &part)) != ABORIA_OK) return st;
+        const int32_t plan = dense_plan_for(ctx, dense_key(false, kernel, dtype, d, n_target, n_source), dtype);
         return dispatch<kSum>(ctx, dtype, d, kernel, (uint32_t)n_target, xt, (uint32_t)n_source, xs, w,
-                              params_host[0], nullptr, y, nullptr, part, kNoAllocScratchBytes);
+                              params_host[0], nullptr, y, nullptr, part, kNoAllocScratchBytes, plan);
     } catch (...) {
         return fail(ctx, ABORIA_ERR_OUT_OF_MEMORY, "host exception in dense_sum_noalloc");
     }
@@ -467,23 +523,113 @@ extern "C" aboria_status aboria_dense_sum_backward(aboria_ctx* ctx, aboria_dtype
         }
         const double prm = params_host[0];
         const uint32_t t32 = (uint32_t)n_target, s32 = (uint32_t)n_source;
+        const int32_t plan = dense_plan_for(ctx, dense_key(true, kernel, dtype, d, n_target, n_source), dtype);
         // dL/dw = K^T gy (the forward sum over the targets, seen from the sources) and the
         // source-position gradient sum over the same pairs with the same weights gy: one
         // pass when both are requested
         if (gw && gxs) {
-            if ((st = dispatch<kSumGrad>(ctx, dtype, d, kernel, s32, xs, t32, xt, gy, prm, w, gw, gxs)) != ABORIA_OK)
+            if ((st = dispatch<kSumGrad>(ctx, dtype, d, kernel, s32, xs, t32, xt, gy, prm, w, gw, gxs, nullptr, 0,
+                                         plan)) != ABORIA_OK)
                 return st;
         } else if (gw) {
-            if ((st = dispatch<kSum>(ctx, dtype, d, kernel, s32, xs, t32, xt, gy, prm, nullptr, gw)) != ABORIA_OK)
+            if ((st = dispatch<kSum>(ctx, dtype, d, kernel, s32, xs, t32, xt, gy, prm, nullptr, gw, nullptr, nullptr,
+                                     0, plan)) != ABORIA_OK)
                 return st;
         } else if (gxs) {
-            if ((st = dispatch<kGrad>(ctx, dtype, d, kernel, s32, xs, t32, xt, gy, prm, w, gxs)) != ABORIA_OK)
+            if ((st = dispatch<kGrad>(ctx, dtype, d, kernel, s32, xs, t32, xt, gy, prm, w, gxs, nullptr, nullptr, 0,
+                                      plan)) != ABORIA_OK)
                 return st;
         }
-        if (gxt && (st = dispatch<kGrad>(ctx, dtype, d, kernel, t32, xt, s32, xs, w, prm, gy, gxt)) != ABORIA_OK)
+        if (gxt && (st = dispatch<kGrad>(ctx, dtype, d, kernel, t32, xt, s32, xs, w, prm, gy, gxt, nullptr, nullptr,
+                                         0, plan)) != ABORIA_OK)
             return st;
         return ABORIA_OK;
     } catch (...) {
         return fail(ctx, ABORIA_ERR_OUT_OF_MEMORY, "host exception in dense_sum_backward");
+    }
+}
+
+extern "C" aboria_status aboria_set_dense_plan(aboria_ctx* ctx, int32_t plan) {
+    if (!ctx) return ABORIA_ERR_INVALID_ARG;
+    if (plan < -1 || plan >= kNumDensePlans) return fail(ctx, ABORIA_ERR_INVALID_ARG, "no such dense plan");
+    ctx->dense_plan_forced = plan;
+    return ABORIA_OK;
+}
+
+extern "C" const char* aboria_dense_plan_name(int32_t plan) {
+    return plan >= 0 && plan < kNumDensePlans ? kDensePlans[plan].name : "";
+}
+
+extern "C" aboria_status aboria_autotune_dense(aboria_ctx* ctx, aboria_dtype dtype, aboria_kernel kernel,
+                                               const double* params_host, int32_t nparams, int32_t d,
+                                               int64_t n_target, const void* xt, int64_t n_source, const void* xs,
+                                               const void* w, const void* gy, void* scratch, int32_t* choice_host) {
+    if (!ctx) return ABORIA_ERR_INVALID_ARG;
+    if (ctx->capturing) return fail(ctx, ABORIA_ERR_UNSUPPORTED, "autotune cannot be captured");
+    try {
+        aboria_status st = check_common(ctx, dtype, kernel, params_host, nparams, d, n_target, n_source);
+        if (st != ABORIA_OK) return st;
+        if (n_target == 0 || n_source == 0) return fail(ctx, ABORIA_ERR_INVALID_ARG, "nothing to time: no pairs");
+        if (!xt || !xs || !w || !scratch) return fail(ctx, ABORIA_ERR_INVALID_ARG, "NULL array");
+        const bool backward = gy != nullptr;
+        const size_t tsz = dtype == ABORIA_F32 ? 4 : 8;
+        char* sc = static_cast<char*>(scratch);
+        void* gxt = sc;
+        void* gxs = sc + tsz * (size_t)d * (size_t)n_target;
+        void* gw = sc + tsz * (size_t)d * (size_t)(n_target + n_source);
+        auto run = [&]() {
+            return backward ? aboria_dense_sum_backward(ctx, dtype, kernel, params_host, nparams, d, n_target, xt,
+                                                        n_source, xs, w, gy, gxt, gxs, gw)
+                            : aboria_dense_sum(ctx, dtype, kernel, params_host, nparams, d, n_target, xt, n_source,
+                                               xs, w, scratch);
+        };
+        ABORIA_HIP(ctx, hipSetDevice(ctx->device));
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+            if (e0) (void)hipEventDestroy(e0);
+            return hip_fail(ctx, hipGetLastError(), "hipEventCreate");
+        }
+        double best_ms = INFINITY;
+        int32_t best = 0;
+        const int32_t forced_before = ctx->dense_plan_forced;
+        for (int32_t p = 0; p < kNumDensePlans && st == ABORIA_OK; ++p) {
+            if (!dense_plan_ok(p, dtype)) continue;
+            ctx->dense_plan_forced = p;
+            if ((st = run()) != ABORIA_OK) break;  // warm-up
+            (void)hipEventRecord(e0, ctx->stream);
+            for (int rep = 0; rep < 3 && st == ABORIA_OK; ++rep) st = run();
+            (void)hipEventRecord(e1, ctx->stream);
+            if (hipEventSynchronize(e1) != hipSuccess) {
+                st = hip_fail(ctx, hipGetLastError(), "timing a dense plan");
+                break;
+            }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            log_msg("autotune_dense: %s %.4f ms", kDensePlans[p].name, ms / 3.0);
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = p;
+            }
+        }
+        ctx->dense_plan_forced = forced_before;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (st != ABORIA_OK) return st;
+        const uint64_t key = dense_key(backward, kernel, dtype, d, n_target, n_source);
+        const aboria_ctx::DenseChoice ch{kDensePlans[best].ti, kDensePlans[best].wg};
+        bool found = false;
+        for (auto& kv : ctx->dense_cache)
+            if (kv.first == key) {
+                kv.second = ch;
+                found = true;
+            }
+        if (!found) ctx->dense_cache.emplace_back(key, ch);
+        tune_cache_save(ctx);
+        log_msg("autotune_dense: %s chosen", kDensePlans[best].name);
+        if (choice_host) *choice_host = best;
+        return ABORIA_OK;
+    } catch (...) {
+        ctx->dense_plan_forced = -1;
+        return fail(ctx, ABORIA_ERR_OUT_OF_MEMORY, "host exception in autotune_dense");
     }
 }

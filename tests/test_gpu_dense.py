@@ -126,3 +126,43 @@ def test_backward_in_a_graph_and_edge_cases():
         assert e.value.status == "INVALID_ARG"
         gctx.sync()
         gctx.close()
+
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_every_dense_plan_matches_oracle(prec):
+    """Every launch plan of the dense tuner (targets per lane, workgroup target),
+    forced in turn, against the oracle, forward and backward, on sizes whose
+    target blocks and source splits have ragged ends; then the tuner's choice
+    serves plain calls."""
+    tctx = A.Context(0)
+    xt, xs, w, gy = inputs(3, prec, 5000 + 37, 9000 + 11, 900)
+    xt_d, xs_d, w_d, gy_d = to_dev(xt), to_dev(xs), to_dev(w), to_dev(gy)
+    tol = TOL_F32 if prec == "f32" else TOL_F64
+    yo, so = oracle.dense_sum("gaussian", 0.15, xt, xs, w)
+    ref = oracle.dense_backward("gaussian", 0.15, xt, xs, w, gy)
+    nplans = 0
+    while A.dense_plan_name(nplans):
+        nplans += 1
+    assert nplans >= 6
+    for p in range(nplans):
+        name = A.dense_plan_name(p)
+        print("dense plan", p, name, prec, flush=True)
+        tctx.set_dense_plan(p)  # a float-only plan runs the default one in float64
+        y = A.dense_sum(tctx, xt_d, xs_d, w_d, 0.15)
+        close(y.cpu().numpy(), yo, so, tol, "forward, plan %s" % name)
+        gxt, gxs, gw = A.dense_sum_backward(tctx, xt_d, xs_d, w_d, 0.15, gy_d)
+        close(gxt.cpu().numpy(), ref[0], ref[3], tol, "gxt, plan %s" % name)
+        close(gxs.cpu().numpy(), ref[1], ref[4], tol, "gxs, plan %s" % name)
+        close(gw.cpu().numpy(), ref[2], ref[5], tol, "gw, plan %s" % name)
+    tctx.set_dense_plan(-1)
+    plan = A.autotune_dense(tctx, xt_d, xs_d, w_d, 0.15)
+    planb = A.autotune_dense(tctx, xt_d, xs_d, w_d, 0.15, gy=gy_d)
+    assert 0 <= plan < nplans and 0 <= planb < nplans
+    tctx.set_dense_plan(plan)
+    y_forced = A.dense_sum(tctx, xt_d, xs_d, w_d, 0.15)
+    tctx.set_dense_plan(-1)
+    y = A.dense_sum(tctx, xt_d, xs_d, w_d, 0.15)  # the cached choice
+    torch.cuda.synchronize()
+    assert torch.equal(y, y_forced)
+    tctx.close()
