@@ -217,6 +217,8 @@ def main():
         """Cells of the cube at a search reach per dimension, the tuned variants and the step forms."""
         st = {"reach": reach}
         box = A.BoxSpec(3, s.lo, s.hi, s.periodic, s.cutoff, None, reach)
+        # the radix build's shape (sort tile, bucket bits) for this grid, then its cells
+        st["build_shape"] = list(A.autotune_build(ctx, x, [box]))
         cells = A.build_cells(ctx, x, [box])
         st["box"], st["cells"] = box, cells
         # box-search baseline: the autotuner's fastest mapping without a neighbour list
@@ -422,7 +424,8 @@ def main():
                  "fused_gy_known_pairs_per_s": pairs / (t_fused * 1e-3),
                  "step_algorithmic_bytes": step_bytes,
                  "step_hbm_frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                 "build_ms": t_build, "build_counting_ms": t_build_counting, "fwd_ms": t_fwd, "bwd_ms": t_bwd,
+                 "build_ms": t_build, "build_shape_keys_per_thread_bucket_bits": chosen["build_shape"],
+                 "build_counting_ms": t_build_counting, "fwd_ms": t_fwd, "bwd_ms": t_bwd,
                  "box_search_fwd_ms": t_fwd_search, "box_search_bwd_ms": t_bwd_search,
                  "recorded_masks_fwd_ms": t_fwd_mask, "recorded_masks_bwd_ms": t_bwd_mask,
                  "neighbour_list_record_ms": t_nbr, "replay_fwd_ms": t_fwd_list, "replay_bwd_ms": t_bwd_list,
@@ -553,6 +556,7 @@ def main():
         g5 = torch.from_numpy(w5.extra["gy"]).to(dev)
         # cell size tuned for this batch (rebuild + spring forward)
         boxes5, f5 = A.autotune_cells(ctx, x5, boxes5, off5, "spring", (1.0,))
+        shape5 = A.autotune_build(ctx, x5, boxes5, off5)
         c5 = A.build_cells(ctx, x5, boxes5, off5)
         y5 = torch.empty((x5.shape[0], 3), device=dev)
         gx5 = torch.empty((x5.shape[0], 3), device=dev)
@@ -592,6 +596,7 @@ def main():
         # variant policy, timed the same way
         boxes_s, f_s = A.autotune_cells(ctx, x, [A.BoxSpec(3, s.lo, s.hi, s.periodic, s.cutoff)], [0, n],
                                         "spring", (1.0,))
+        A.autotune_build(ctx, x, boxes_s, [0, n])
         c_s = A.build_cells(ctx, x, boxes_s, [0, n])
         g_s = torch.ones((n, 1), device=dev)
         sv_s = (A.autotune(ctx, c_s, "spring", (1.0,)), A.autotune(ctx, c_s, "soft_sphere", (), gy=g_s))
@@ -612,7 +617,7 @@ def main():
         c_s.close()
         ctx.sync()
         extra["batch_512_systems"] = {"ms": m5, "particles": int(x5.shape[0]), "pairs": p5,
-                                      "cell_scale_factor": f5,
+                                      "cell_scale_factor": f5, "build_shape_keys_per_thread_bucket_bits": list(shape5),
                                       "pairs_per_s": p5 / (m5 * 1e-3), "step_forms_ms": t5,
                                       "single_cube_same_step": {"ms": m_s, "pairs": pairs,
                                                                 "pairs_per_s": pairs / (m_s * 1e-3),
@@ -626,6 +631,7 @@ def main():
         s6 = w6.systems[0]
         box6 = A.BoxSpec(2, s6.lo, s6.hi, s6.periodic, s6.cutoff)
         x6 = torch.from_numpy(s6.x).to(dev)
+        shape6 = A.autotune_build(ctx, x6, [box6])
         v6 = torch.from_numpy(w6.extra["v"]).to(dev)
         f6 = torch.empty_like(x6)
         c6 = A.build_cells(ctx, x6, [box6])
@@ -673,6 +679,7 @@ def main():
                                              "particle_updates_per_s": s6.n / (t6 * 1e-3),
                                              "step_forms_ms": forms6,
                                              "build_ms_random_order": t_build6,
+                                             "build_shape_keys_per_thread_bucket_bits": list(shape6),
                                              "build_ms_cell_order": t_build6_sorted}
         # the small correctness workload (N = 1000, d = 2, periodic unit square, r = 0.1, spring, float64):
         # build + forward + adjoint as a graph, with the tuned box search and with the single-cell

@@ -55,7 +55,8 @@ EXPORTS = ["aboria_create", "aboria_destroy", "aboria_set_stream", "aboria_last_
            "aboria_build_neighbours", "aboria_neighbour_capacity", "aboria_integrate",
            "aboria_dense_sum_backward", "aboria_autotune_cells", "aboria_pair_sum_and_backward",
            "aboria_dense_sum_noalloc", "aboria_md_step", "aboria_cells_reorder", "aboria_selected_variant",
-           "aboria_autotune_dense", "aboria_dense_plan_name", "aboria_set_dense_plan"]
+           "aboria_autotune_dense", "aboria_dense_plan_name", "aboria_set_dense_plan", "aboria_set_build_shape",
+           "aboria_autotune_build"]
 
 
 def lib():
@@ -85,6 +86,8 @@ def lib():
                                        C.POINTER(I32)], I32),
             "aboria_dense_plan_name": ([I32], C.c_char_p),
             "aboria_set_dense_plan": ([P, I32], I32),
+            "aboria_set_build_shape": ([P, I32, I32], I32),
+            "aboria_autotune_build": ([P, I32, I32, P, C.POINTER(I64), P, C.POINTER(I32), C.POINTER(I32)], I32),
             "aboria_md_step": ([P, P, I32, C.POINTER(C.c_double), I32, C.c_double, P, P, P, P], I32),
             "aboria_cells_reorder": ([P, P, I32, C.POINTER(P), C.POINTER(I32)], I32),
             "aboria_dense_sum_noalloc": ([P, I32, I32, C.POINTER(C.c_double), I32, I32, I64, P, I64, P, P, P], I32),
@@ -179,6 +182,10 @@ class Context:
     def set_dense_plan(self, plan: int):
         """Force a dense-sum launch plan for later calls (-1 = tuned / default)."""
         self.check(lib().aboria_set_dense_plan(self.handle, int(plan)), "set_dense_plan")
+
+    def set_build_shape(self, ipt: int = 0, low_bits: int = 0):
+        """Radix build shape for cell lists created later (0 = rule / tuned)."""
+        self.check(lib().aboria_set_build_shape(self.handle, int(ipt), int(low_bits)), "set_build_shape")
 
     def close(self):
         if getattr(self, "handle", None):
@@ -278,6 +285,25 @@ def build_cells(ctx: Context, x: torch.Tensor, boxes: Sequence[BoxSpec], offsets
         cells.builds += 1
         return cells
     return Cells(ctx, h, n, boxes[0].d, x.dtype, nsys, boxes, list(offsets))
+
+
+def autotune_build(ctx: Context, x: torch.Tensor, boxes: Sequence[BoxSpec],
+                   offsets: Optional[Sequence[int]] = None) -> tuple:
+    """aboria_autotune_build: times the radix build shapes for these boxes and caches the
+    fastest; returns (keys per thread, bucket bits)."""
+    _check_dev(x, "x")
+    boxes = list(boxes)
+    nsys = len(boxes)
+    if offsets is None:
+        if nsys != 1:
+            raise ValueError("offsets are required for more than one system")
+        offsets = [0, int(x.shape[0])]
+    arr_b = (Box * nsys)(*[b.to_c() for b in boxes])
+    arr_o = (C.c_int64 * (nsys + 1))(*[int(o) for o in offsets])
+    ipt, lb = C.c_int32(0), C.c_int32(0)
+    ctx.check(lib().aboria_autotune_build(ctx.handle, _dtype_code(x), nsys, arr_b, arr_o, _ptr(x), C.byref(ipt),
+                                          C.byref(lb)), "autotune_build")
+    return int(ipt.value), int(lb.value)
 
 
 def op_ny(op: str, d: int) -> int:

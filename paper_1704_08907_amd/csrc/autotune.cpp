@@ -48,7 +48,7 @@ void tune_cache_load(aboria_ctx* ctx) {
     if (!f) return;
     char line[1024];
     bool arch_ok = false;
-    int nv = 0, nc = 0, nd = 0;
+    int nv = 0, nc = 0, nd = 0, nb = 0;
     while (std::fgets(line, sizeof line, f)) {
         const char* a = std::strstr(line, "\"arch\": \"");
         if (a) {
@@ -76,11 +76,14 @@ void tune_cache_load(aboria_ctx* ctx) {
         } else if (std::sscanf(line, " {\"key\": %llu, \"dense_plan\": [%d, %d]}", &key, &m0, &m1) == 3) {
             ctx->dense_cache.emplace_back((uint64_t)key, aboria_ctx::DenseChoice{m0, m1});
             ++nd;
+        } else if (std::sscanf(line, " {\"key\": %llu, \"build\": [%d, %d]}", &key, &m0, &m1) == 3) {
+            ctx->build_cache.emplace_back((uint64_t)key, aboria_ctx::BuildShape{m0, m1});
+            ++nb;
         }
     }
     std::fclose(f);
-    log_msg("tune cache %s: %d variant, %d cell-size and %d dense entries for %s", ctx->cache_path.c_str(), nv, nc,
-            nd, ctx->arch.c_str());
+    log_msg("tune cache %s: %d variant, %d cell-size, %d dense and %d build entries for %s", ctx->cache_path.c_str(),
+            nv, nc, nd, nb, ctx->arch.c_str());
 }
 
 void tune_cache_save(aboria_ctx* ctx) {
@@ -107,6 +110,11 @@ void tune_cache_save(aboria_ctx* ctx) {
         std::fprintf(f, "{\"key\": %" PRIu64 ", \"dense_plan\": [%d, %d]}%s\n", ctx->dense_cache[i].first,
                      ctx->dense_cache[i].second.ti, ctx->dense_cache[i].second.wg,
                      i + 1 < ctx->dense_cache.size() ? "," : "");
+    std::fprintf(f, "],\n\"build\": [\n");
+    for (size_t i = 0; i < ctx->build_cache.size(); ++i)
+        std::fprintf(f, "{\"key\": %" PRIu64 ", \"build\": [%d, %d]}%s\n", ctx->build_cache[i].first,
+                     ctx->build_cache[i].second.ipt, ctx->build_cache[i].second.low_bits,
+                     i + 1 < ctx->build_cache.size() ? "," : "");
     std::fprintf(f, "]}\n");
     const bool ok = std::fclose(f) == 0;
     if (!ok || std::rename(tmp.c_str(), ctx->cache_path.c_str()) != 0)

@@ -1013,6 +1013,17 @@ aboria_status launch_build_counting(aboria_ctx* ctx, aboria_cells* c, const void
 // in the same time with 4096- or 2048-key tiles but 25 % faster with 2048 on
 // cells of half the width; 2^18 particles build 22 % faster with 1024-key
 // tiles; 5.8 M particles in 512 systems are fastest with 4096.
+// Key of the radix build-shape cache: d, dtype, batch and the size buckets
+// (floor log2) of the particles and the cells.
+uint64_t build_key(int32_t d, int32_t dtype, bool batch, int64_t n, int64_t ncells) {
+    uint64_t k = (uint64_t)d;
+    k = k * 4 + (uint64_t)dtype;
+    k = k * 2 + (uint64_t)batch;
+    k = k * 64 + (uint64_t)std::floor(std::log2((double)n + 1.0));
+    k = k * 64 + (uint64_t)std::floor(std::log2((double)ncells + 1.0));
+    return k;
+}
+
 int sort_ipt_for(int64_t n) {
     if (n >= (int64_t)512 * kBlock * 16) return 16;
     if (n >= (int64_t)512 * kBlock * 8) return 8;
@@ -1261,10 +1272,19 @@ extern "C" aboria_status aboria_build_cells(aboria_ctx* ctx, aboria_dtype dtype,
             // the bucket pass sorts the low bits (8 to 10 of them); LDS-ranked
             // radix passes of at most 10 bits sort the rest first
             c->low_bits = std::min(bits, std::max(8, std::min(bits - kMaxDigitBits, kMaxDigitBits)));
+            c->sort_ipt = sort_ipt_for(n);
+            // a forced shape, else the tuned one for this size, replaces the rule
+            aboria_ctx::BuildShape shape = ctx->build_forced;
+            if (shape.ipt == 0 && shape.low_bits == 0) {
+                const uint64_t bkey = build_key(d, dtype, nsys > 1, n, total_cells);
+                for (const auto& kv : ctx->build_cache)
+                    if (kv.first == bkey) shape = kv.second;
+            }
+            if (shape.ipt == 4 || shape.ipt == 8 || shape.ipt == 16) c->sort_ipt = shape.ipt;
+            if (shape.low_bits >= 8 && shape.low_bits <= kMaxDigitBits) c->low_bits = std::min(bits, shape.low_bits);
             const int high = bits - c->low_bits;
             c->passes = (high + kMaxDigitBits - 1) / kMaxDigitBits;
             c->digit_bits = c->passes > 0 ? (high + c->passes - 1) / c->passes : 1;
-            c->sort_ipt = sort_ipt_for(n);
             c->ntiles = (n + (int64_t)kBlock * c->sort_ipt - 1) / ((int64_t)kBlock * c->sort_ipt);
             c->hist_len = ((int64_t)1 << c->digit_bits) * std::max<int64_t>(c->ntiles, 1);
             c->nblock_sums = std::max<int64_t>(std::max(scan_block_count(c->hist_len),
@@ -1372,4 +1392,93 @@ extern "C" aboria_status aboria_cells_destroy(aboria_cells* c) {
     if (!c) return ABORIA_OK;
     aboria::release_or_defer(release_cells, c);
     return ABORIA_OK;
+}
+
+extern "C" aboria_status aboria_set_build_shape(aboria_ctx* ctx, int32_t ipt, int32_t low_bits) {
+    if (!ctx) return ABORIA_ERR_INVALID_ARG;
+    if (ipt != 0 && ipt != 4 && ipt != 8 && ipt != 16)
+        return fail(ctx, ABORIA_ERR_INVALID_ARG, "keys per thread must be 0, 4, 8 or 16");
+    if (low_bits != 0 && (low_bits < 8 || low_bits > kMaxDigitBits))
+        return fail(ctx, ABORIA_ERR_INVALID_ARG, "bucket bits must be 0 or 8 to 10");
+    ctx->build_forced = aboria_ctx::BuildShape{ipt, low_bits};
+    return ABORIA_OK;
+}
+
+extern "C" aboria_status aboria_autotune_build(aboria_ctx* ctx, aboria_dtype dtype, int32_t nsys,
+                                               const aboria_box* boxes_host, const int64_t* offsets_host,
+                                               const void* x, int32_t* ipt_out, int32_t* low_bits_out) {
+    if (!ctx) return ABORIA_ERR_INVALID_ARG;
+    if (ctx->capturing) return fail(ctx, ABORIA_ERR_UNSUPPORTED, "autotune cannot be captured");
+    if (nsys < 1 || !boxes_host || !offsets_host) return fail(ctx, ABORIA_ERR_INVALID_ARG, "need boxes and offsets");
+    const aboria_ctx::BuildShape forced_before = ctx->build_forced;
+    const int32_t strategy_before = ctx->build_strategy;
+    try {
+        ABORIA_HIP(ctx, hipSetDevice(ctx->device));
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+            if (e0) (void)hipEventDestroy(e0);
+            return hip_fail(ctx, hipGetLastError(), "hipEventCreate");
+        }
+        ctx->build_strategy = ABORIA_BUILD_RADIX;
+        aboria_status st = ABORIA_OK;
+        double best_ms = INFINITY;
+        aboria_ctx::BuildShape best{0, 0};
+        int64_t ncells = 0, n = offsets_host[nsys];
+        const int32_t ipts[] = {4, 8, 16};
+        const int32_t lows[] = {8, 9, 10};
+        int32_t last_bits = -1;
+        for (int32_t ipt : ipts) {
+            for (int32_t lb : lows) {
+                if (st != ABORIA_OK) break;
+                ctx->build_forced = aboria_ctx::BuildShape{ipt, lb};
+                aboria_cells* c = nullptr;
+                st = aboria_build_cells(ctx, dtype, nsys, boxes_host, offsets_host, x, &c);
+                if (st != ABORIA_OK) break;
+                ncells = c->ncells;
+                if (c->low_bits != lb && lb != lows[0]) {  // fewer key bits than lb: a smaller lb's shape
+                    (void)aboria_cells_destroy(c);
+                    continue;
+                }
+                last_bits = c->key_bits;
+                (void)hipEventRecord(e0, ctx->stream);
+                for (int rep = 0; rep < 5 && st == ABORIA_OK; ++rep)
+                    st = aboria_build_cells(ctx, dtype, nsys, boxes_host, offsets_host, x, &c);
+                (void)hipEventRecord(e1, ctx->stream);
+                if (hipEventSynchronize(e1) != hipSuccess) st = hip_fail(ctx, hipGetLastError(), "timing a build");
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                (void)aboria_cells_destroy(c);
+                if (st != ABORIA_OK) break;
+                log_msg("autotune_build: %d keys per thread, %d bucket bits: %.4f ms", ipt, lb, ms / 5.0);
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = aboria_ctx::BuildShape{ipt, lb};
+                }
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        ctx->build_forced = forced_before;
+        ctx->build_strategy = strategy_before;
+        if (st != ABORIA_OK) return st;
+        if (best.ipt == 0) return fail(ctx, ABORIA_ERR_INVALID_ARG, "no build shape could be timed");
+        const uint64_t key = build_key(boxes_host[0].d, dtype, nsys > 1, n, ncells);
+        bool found = false;
+        for (auto& kv : ctx->build_cache)
+            if (kv.first == key) {
+                kv.second = best;
+                found = true;
+            }
+        if (!found) ctx->build_cache.emplace_back(key, best);
+        tune_cache_save(ctx);
+        log_msg("autotune_build: %d keys per thread, %d bucket bits chosen (%d key bits)", best.ipt, best.low_bits,
+                last_bits);
+        if (ipt_out) *ipt_out = best.ipt;
+        if (low_bits_out) *low_bits_out = best.low_bits;
+        return ABORIA_OK;
+    } catch (...) {
+        ctx->build_forced = forced_before;
+        ctx->build_strategy = strategy_before;
+        return fail(ctx, ABORIA_ERR_OUT_OF_MEMORY, "host exception in autotune_build");
+    }
 }

@@ -111,6 +111,14 @@ struct aboria_ctx {
     };
     std::vector<std::pair<uint64_t, DenseChoice>> dense_cache;
     int32_t dense_plan_forced = -1;  // the dense tuner's current trial (-1: none)
+    // radix build shape: keys per thread of a sort tile (4, 8, 16) and the key bits
+    // the bucket pass sorts (8 to 10); 0 = the built-in rule
+    struct BuildShape {
+        int32_t ipt;
+        int32_t low_bits;
+    };
+    std::vector<std::pair<uint64_t, BuildShape>> build_cache;
+    BuildShape build_forced{0, 0};
     std::string arch;        // the device's architecture name (keys the persistent cache)
     std::string cache_path;  // ABORIA_TUNE_CACHE at creation ("" = no persistent cache)
 };

@@ -67,3 +67,54 @@ def test_many_small_systems_rows_gathered(ctx):
         if b in (0, 1, 31, 63):
             check_system(g, s.x, keys, perm, off, xs, b * nb, base_cell)
         base_cell += int(g.ncells)
+
+
+@pytest.mark.parametrize("ipt", [4, 8, 16])
+@pytest.mark.parametrize("low_bits", [8, 9, 10])
+def test_every_build_shape_is_bit_exact(ipt, low_bits):
+    """Every radix build shape the tuner may pick (keys per thread of a sort tile,
+    bits sorted per bucket) gives the oracle's cell list, on the spring cube's
+    headline grid (cells r/3 wide along x: 158 x 52 x 52, one radix pass or two)
+    and on a batch of uneven systems."""
+    sctx = A.Context(0)
+    sctx.set_build_shape(ipt, low_bits)
+    print("build shape", ipt, low_bits, flush=True)
+    s = syn.spring_cube().systems[0]
+    box = A.BoxSpec(3, s.lo, s.hi, s.periodic, s.cutoff, None, [3, 1, 1])
+    cells = A.build_cells(sctx, to_dev(s.x), [box])
+    cells2 = A.build_cells(sctx, to_dev(s.x), [box], cells=cells)  # a rebuild keeps the shape
+    sctx.sync()
+    g = oracle.grid_of(s, reach=(3, 1, 1))
+    check_system(g, s.x, *cells_state(cells2))
+    cells.close()
+    w = syn.batch_cubes(nsys=24, nmax=16384)
+    xb = np.concatenate([t.x for t in w.systems])
+    offsets = np.concatenate([[0], np.cumsum([t.n for t in w.systems])]).tolist()
+    cb = A.build_cells(sctx, to_dev(xb), [box_of(t) for t in w.systems], offsets)
+    sctx.sync()
+    keys, perm, off, xs = cells_state(cb)
+    base_cell = 0
+    for b, t in enumerate(w.systems):
+        gb = oracle.grid_of(t)
+        if b in (0, 7, 23):
+            check_system(gb, t.x, keys, perm, off, xs, offsets[b], base_cell)
+        base_cell += int(gb.ncells)
+    cb.close()
+    sctx.close()
+
+
+def test_build_tuner_picks_a_shape_later_builds_use():
+    tctx = A.Context(0)
+    s = syn.spring_cube(n=1 << 18).systems[0]
+    box = box_of(s)
+    ipt, lb = A.autotune_build(tctx, to_dev(s.x), [box])
+    assert ipt in (4, 8, 16) and 8 <= lb <= 10
+    cells = A.build_cells(tctx, to_dev(s.x), [box])
+    tctx.sync()
+    check_system(oracle.grid_of(s), s.x, *cells_state(cells))
+    with pytest.raises(A.AboriaError):
+        tctx.set_build_shape(5, 0)
+    with pytest.raises(A.AboriaError):
+        tctx.set_build_shape(0, 11)
+    cells.close()
+    tctx.close()
