@@ -114,7 +114,7 @@ typedef struct aboria_cells_view {
     int32_t nsys;                   /* number of independent systems              */
     int32_t d;
     int32_t dtype;                  /* aboria_dtype                               */
-    int32_t reserved;
+    int32_t sort_ipt;               /* RADIX build: keys per thread of a sort tile */
     int64_t n;                      /* total particles                            */
     int64_t ncells;                 /* total cells over all systems               */
     const uint32_t* perm;           /* device [n]: sorted slot -> original index  */
@@ -122,7 +122,7 @@ typedef struct aboria_cells_view {
     const uint32_t* cell_offsets;   /* device [ncells + 1]: first slot of a cell  */
     const void* x_sorted;           /* device [n][pitch]: positions in cell order */
     int32_t x_pitch;                /* elements per sorted position (4 for d = 3) */
-    int32_t reserved2;
+    int32_t bucket_bits;            /* RADIX build: key bits sorted per bucket     */
     const int32_t* ncell_host;      /* host [nsys][3]: cells per dimension        */
     const uint32_t* cell_base_host; /* host [nsys + 1]: first global cell id      */
     const int64_t* sys_offsets_host;/* host [nsys + 1]: first particle of a system */

@@ -38,10 +38,10 @@ class Box(C.Structure):
 
 
 class CellsView(C.Structure):
-    _fields_ = [("nsys", C.c_int32), ("d", C.c_int32), ("dtype", C.c_int32), ("reserved", C.c_int32),
+    _fields_ = [("nsys", C.c_int32), ("d", C.c_int32), ("dtype", C.c_int32), ("sort_ipt", C.c_int32),
                 ("n", C.c_int64), ("ncells", C.c_int64), ("perm", C.c_void_p), ("keys", C.c_void_p),
                 ("cell_offsets", C.c_void_p), ("x_sorted", C.c_void_p), ("x_pitch", C.c_int32),
-                ("reserved2", C.c_int32), ("ncell_host", C.POINTER(C.c_int32)),
+                ("bucket_bits", C.c_int32), ("ncell_host", C.POINTER(C.c_int32)),
                 ("cell_base_host", C.POINTER(C.c_uint32)), ("sys_offsets_host", C.POINTER(C.c_int64))]
 
 

@@ -1374,6 +1374,8 @@ extern "C" aboria_status aboria_cells_view_get(const aboria_cells* c, aboria_cel
     out->cell_offsets = c->off;
     out->x_sorted = c->xs;
     out->x_pitch = c->pitch;
+    out->sort_ipt = c->sort_ipt;
+    out->bucket_bits = c->low_bits;
     out->ncell_host = c->ncell_host.data();
     out->cell_base_host = c->cell_base.data();
     out->sys_offsets_host = c->sys_off.data();

@@ -145,3 +145,46 @@ def test_tuning_persists_across_contexts(tmp_path):
             os.environ.pop("ABORIA_TUNE_CACHE", None)
         else:
             os.environ["ABORIA_TUNE_CACHE"] = old
+
+
+def test_dense_and_build_tuning_persist(tmp_path):
+    # the dense launch plan and the radix build shape go to the ABORIA_TUNE_CACHE file
+    # too, and a new context uses them without tuning again
+    import json
+    import os
+    path = str(tmp_path / "tune2.json")
+    old = os.environ.get("ABORIA_TUNE_CACHE")
+    os.environ["ABORIA_TUNE_CACHE"] = path
+    try:
+        c1 = A.Context(0)
+        s = syn.spring_cube(n=60000).systems[0]
+        x_d = to_dev(s.x)
+        ipt, lb = A.autotune_build(c1, x_d, [box_of(s)])
+        rng = syn.SplitMix64(5)
+        xt = to_dev(syn.uniform_positions(rng, 3000, [0.0] * 2, [1.0] * 2, "f32"))
+        w = to_dev(rng.normal(3000).astype("float32"))
+        plan = A.autotune_dense(c1, xt, xt, w, 0.2)
+        c1.sync()
+        doc = json.load(open(path))
+        assert [e["build"] for e in doc["build"]] == [[ipt, lb]]
+        name = A.dense_plan_name(plan)
+        ti, wg = int(name.split()[0]), int(name.split()[-2])
+        assert [e["dense_plan"] for e in doc["dense"]] == [[ti, wg]]
+        c2 = A.Context(0)
+        cells = A.build_cells(c2, x_d, [box_of(s)])
+        v = cells.view()
+        assert (v.sort_ipt, v.bucket_bits) == (ipt, lb)  # 2^15 cells: more key bits than any bucket takes
+        y2 = A.dense_sum(c2, xt, xt, w, 0.2)
+        c2.set_dense_plan(plan)
+        y2f = A.dense_sum(c2, xt, xt, w, 0.2)
+        torch.cuda.synchronize()
+        assert torch.equal(y2, y2f)
+        cells.close()
+        for c in (c1, c2):
+            c.close()
+    finally:
+        if old is None:
+            os.environ.pop("ABORIA_TUNE_CACHE", None)
+        else:
+            os.environ["ABORIA_TUNE_CACHE"] = old
+
