@@ -424,7 +424,7 @@ def main():
                  "fused_gy_known_pairs_per_s": pairs / (t_fused * 1e-3),
                  "step_algorithmic_bytes": step_bytes,
                  "step_hbm_frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                 "build_ms": t_build, "build_shape_keys_per_thread_bucket_bits": chosen["build_shape"],
+                 "build_ms": t_build, "build_shape_keys_per_thread_bucket_bits_shuffle": chosen["build_shape"],
                  "build_counting_ms": t_build_counting, "fwd_ms": t_fwd, "bwd_ms": t_bwd,
                  "box_search_fwd_ms": t_fwd_search, "box_search_bwd_ms": t_bwd_search,
                  "recorded_masks_fwd_ms": t_fwd_mask, "recorded_masks_bwd_ms": t_bwd_mask,
@@ -617,7 +617,7 @@ def main():
         c_s.close()
         ctx.sync()
         extra["batch_512_systems"] = {"ms": m5, "particles": int(x5.shape[0]), "pairs": p5,
-                                      "cell_scale_factor": f5, "build_shape_keys_per_thread_bucket_bits": list(shape5),
+                                      "cell_scale_factor": f5, "build_shape_keys_per_thread_bucket_bits_shuffle": list(shape5),
                                       "pairs_per_s": p5 / (m5 * 1e-3), "step_forms_ms": t5,
                                       "single_cube_same_step": {"ms": m_s, "pairs": pairs,
                                                                 "pairs_per_s": pairs / (m_s * 1e-3),
@@ -679,7 +679,7 @@ def main():
                                              "particle_updates_per_s": s6.n / (t6 * 1e-3),
                                              "step_forms_ms": forms6,
                                              "build_ms_random_order": t_build6,
-                                             "build_shape_keys_per_thread_bucket_bits": list(shape6),
+                                             "build_shape_keys_per_thread_bucket_bits_shuffle": list(shape6),
                                              "build_ms_cell_order": t_build6_sorted}
         # the small correctness workload (N = 1000, d = 2, periodic unit square, r = 0.1, spring, float64):
         # build + forward + adjoint as a graph, with the tuned box search and with the single-cell

@@ -199,22 +199,23 @@ aboria_status aboria_cells_destroy(aboria_cells* cells);
 
 /* Shape of the RADIX build (Section 2.2.1's sort into cell order): keys per
  * thread of a sort tile of 256 threads (4, 8 or 16: tiles of 1024 to 4096
- * keys) and the key bits the last pass sorts per bucket of cells in LDS (8 to
- * 10; the radix passes take the remaining high bits).  The shape does not
- * change the cell list, only the work mapping of its build.
- * aboria_set_build_shape fixes it for cell lists created later on ctx (0 for
- * either value: the built-in rule, or the tuned shape for that size);
- * INVALID_ARG for other values.  aboria_autotune_build creates a cell list for
- * the boxes at each shape, times five rebuilds of each with HIP events and
- * caches the fastest for cell lists of the same d, dtype, batch and size
- * buckets (floor log2 of the particles and of the cells), which later
- * creations use; *ipt_out and *low_bits_out (may be NULL) receive it.
- * Persisted like aboria_autotune's choices; arguments as for
+ * keys), the key bits the last pass sorts per bucket of cells in LDS (8 to 10;
+ * the radix passes take the remaining high bits) and whether a radix pass
+ * shuffles its tile into digit order in LDS before writing (1: where the LDS
+ * fits, 2: never).  The shape does not change the cell list, only the work
+ * mapping of its build.  aboria_set_build_shape fixes it for cell lists
+ * created later on ctx (0 for a value: the built-in rule, or the tuned shape
+ * for that size); INVALID_ARG for other values.  aboria_autotune_build creates
+ * a cell list for the boxes at each shape, times five rebuilds of each with HIP
+ * events and caches the fastest for cell lists of the same d, dtype, batch and
+ * size buckets (floor log2 of the particles and of the cells), which later
+ * creations use; *ipt_out, *low_bits_out and *shuffle_out (may be NULL)
+ * receive it.  Persisted like aboria_autotune's choices; arguments as for
  * aboria_build_cells; allocates and synchronises, so it cannot be captured. */
-aboria_status aboria_set_build_shape(aboria_ctx* ctx, int32_t ipt, int32_t low_bits);
+aboria_status aboria_set_build_shape(aboria_ctx* ctx, int32_t ipt, int32_t low_bits, int32_t shuffle);
 aboria_status aboria_autotune_build(aboria_ctx* ctx, aboria_dtype dtype, int32_t nsys, const aboria_box* boxes_host,
                                     const int64_t* offsets_host, const void* x, int32_t* ipt_out,
-                                    int32_t* low_bits_out);
+                                    int32_t* low_bits_out, int32_t* shuffle_out);
 
 /* ---- neighbour sums (Section 3: eq. (1) and the velocity-update listing) ----
  *

@@ -86,8 +86,9 @@ def lib():
                                        C.POINTER(I32)], I32),
             "aboria_dense_plan_name": ([I32], C.c_char_p),
             "aboria_set_dense_plan": ([P, I32], I32),
-            "aboria_set_build_shape": ([P, I32, I32], I32),
-            "aboria_autotune_build": ([P, I32, I32, P, C.POINTER(I64), P, C.POINTER(I32), C.POINTER(I32)], I32),
+            "aboria_set_build_shape": ([P, I32, I32, I32], I32),
+            "aboria_autotune_build": ([P, I32, I32, P, C.POINTER(I64), P, C.POINTER(I32), C.POINTER(I32),
+                                       C.POINTER(I32)], I32),
             "aboria_md_step": ([P, P, I32, C.POINTER(C.c_double), I32, C.c_double, P, P, P, P], I32),
             "aboria_cells_reorder": ([P, P, I32, C.POINTER(P), C.POINTER(I32)], I32),
             "aboria_dense_sum_noalloc": ([P, I32, I32, C.POINTER(C.c_double), I32, I32, I64, P, I64, P, P, P], I32),
@@ -183,9 +184,11 @@ class Context:
         """Force a dense-sum launch plan for later calls (-1 = tuned / default)."""
         self.check(lib().aboria_set_dense_plan(self.handle, int(plan)), "set_dense_plan")
 
-    def set_build_shape(self, ipt: int = 0, low_bits: int = 0):
-        """Radix build shape for cell lists created later (0 = rule / tuned)."""
-        self.check(lib().aboria_set_build_shape(self.handle, int(ipt), int(low_bits)), "set_build_shape")
+    def set_build_shape(self, ipt: int = 0, low_bits: int = 0, shuffle: int = 0):
+        """Radix build shape for cell lists created later (0 = rule / tuned; shuffle 1 = on
+        where it fits, 2 = off)."""
+        self.check(lib().aboria_set_build_shape(self.handle, int(ipt), int(low_bits), int(shuffle)),
+                   "set_build_shape")
 
     def close(self):
         if getattr(self, "handle", None):
@@ -290,7 +293,7 @@ def build_cells(ctx: Context, x: torch.Tensor, boxes: Sequence[BoxSpec], offsets
 def autotune_build(ctx: Context, x: torch.Tensor, boxes: Sequence[BoxSpec],
                    offsets: Optional[Sequence[int]] = None) -> tuple:
     """aboria_autotune_build: times the radix build shapes for these boxes and caches the
-    fastest; returns (keys per thread, bucket bits)."""
+    fastest; returns (keys per thread, bucket bits, shuffle)."""
     _check_dev(x, "x")
     boxes = list(boxes)
     nsys = len(boxes)
@@ -300,10 +303,10 @@ def autotune_build(ctx: Context, x: torch.Tensor, boxes: Sequence[BoxSpec],
         offsets = [0, int(x.shape[0])]
     arr_b = (Box * nsys)(*[b.to_c() for b in boxes])
     arr_o = (C.c_int64 * (nsys + 1))(*[int(o) for o in offsets])
-    ipt, lb = C.c_int32(0), C.c_int32(0)
+    ipt, lb, sh = C.c_int32(0), C.c_int32(0), C.c_int32(0)
     ctx.check(lib().aboria_autotune_build(ctx.handle, _dtype_code(x), nsys, arr_b, arr_o, _ptr(x), C.byref(ipt),
-                                          C.byref(lb)), "autotune_build")
-    return int(ipt.value), int(lb.value)
+                                          C.byref(lb), C.byref(sh)), "autotune_build")
+    return int(ipt.value), int(lb.value), int(sh.value)
 
 
 def op_ny(op: str, d: int) -> int:

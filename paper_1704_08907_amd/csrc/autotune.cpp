@@ -76,8 +76,8 @@ void tune_cache_load(aboria_ctx* ctx) {
         } else if (std::sscanf(line, " {\"key\": %llu, \"dense_plan\": [%d, %d]}", &key, &m0, &m1) == 3) {
             ctx->dense_cache.emplace_back((uint64_t)key, aboria_ctx::DenseChoice{m0, m1});
             ++nd;
-        } else if (std::sscanf(line, " {\"key\": %llu, \"build\": [%d, %d]}", &key, &m0, &m1) == 3) {
-            ctx->build_cache.emplace_back((uint64_t)key, aboria_ctx::BuildShape{m0, m1});
+        } else if (std::sscanf(line, " {\"key\": %llu, \"build\": [%d, %d, %d]}", &key, &m0, &m1, &m2) == 4) {
+            ctx->build_cache.emplace_back((uint64_t)key, aboria_ctx::BuildShape{m0, m1, m2});
             ++nb;
         }
     }
@@ -112,9 +112,9 @@ void tune_cache_save(aboria_ctx* ctx) {
                      i + 1 < ctx->dense_cache.size() ? "," : "");
     std::fprintf(f, "],\n\"build\": [\n");
     for (size_t i = 0; i < ctx->build_cache.size(); ++i)
-        std::fprintf(f, "{\"key\": %" PRIu64 ", \"build\": [%d, %d]}%s\n", ctx->build_cache[i].first,
+        std::fprintf(f, "{\"key\": %" PRIu64 ", \"build\": [%d, %d, %d]}%s\n", ctx->build_cache[i].first,
                      ctx->build_cache[i].second.ipt, ctx->build_cache[i].second.low_bits,
-                     i + 1 < ctx->build_cache.size() ? "," : "");
+                     ctx->build_cache[i].second.shuffle, i + 1 < ctx->build_cache.size() ? "," : "");
     std::fprintf(f, "]}\n");
     const bool ok = std::fclose(f) == 0;
     if (!ok || std::rename(tmp.c_str(), ctx->cache_path.c_str()) != 0)

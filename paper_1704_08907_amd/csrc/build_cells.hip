@@ -1090,7 +1090,8 @@ aboria_status launch_build_radix_ipt(aboria_ctx* ctx, aboria_cells* c, const voi
         Row* pout = reinterpret_cast<Row*>(c->work);
         const size_t lds_bytes = (6 * (size_t)radix + 2 * (size_t)kSortTile) * sizeof(uint32_t) +
                                  (payload ? (size_t)kSortTile * sizeof(Row) : 0);
-        const bool shuffle = ntiles <= 512 && lds_bytes + (kTopInline + 4) * sizeof(uint32_t) <= (size_t)ctx->lds_per_block;
+        const bool fits = lds_bytes + (kTopInline + 4) * sizeof(uint32_t) <= (size_t)ctx->lds_per_block;
+        const bool shuffle = fits && (c->shuffle_pref == 1 || (c->shuffle_pref == 0 && ntiles <= 512));
         for (int p = 0; p < c->passes; ++p) {
             const int shift = c->low_bits + p * c->digit_bits;
             if (p > 0)  // the first pass's histogram came with the cell ids
@@ -1275,13 +1276,14 @@ extern "C" aboria_status aboria_build_cells(aboria_ctx* ctx, aboria_dtype dtype,
             c->sort_ipt = sort_ipt_for(n);
             // a forced shape, else the tuned one for this size, replaces the rule
             aboria_ctx::BuildShape shape = ctx->build_forced;
-            if (shape.ipt == 0 && shape.low_bits == 0) {
+            if (shape.ipt == 0 && shape.low_bits == 0 && shape.shuffle == 0) {
                 const uint64_t bkey = build_key(d, dtype, nsys > 1, n, total_cells);
                 for (const auto& kv : ctx->build_cache)
                     if (kv.first == bkey) shape = kv.second;
             }
             if (shape.ipt == 4 || shape.ipt == 8 || shape.ipt == 16) c->sort_ipt = shape.ipt;
             if (shape.low_bits >= 8 && shape.low_bits <= kMaxDigitBits) c->low_bits = std::min(bits, shape.low_bits);
+            if (shape.shuffle == 1 || shape.shuffle == 2) c->shuffle_pref = shape.shuffle;
             const int high = bits - c->low_bits;
             c->passes = (high + kMaxDigitBits - 1) / kMaxDigitBits;
             c->digit_bits = c->passes > 0 ? (high + c->passes - 1) / c->passes : 1;
@@ -1396,19 +1398,21 @@ extern "C" aboria_status aboria_cells_destroy(aboria_cells* c) {
     return ABORIA_OK;
 }
 
-extern "C" aboria_status aboria_set_build_shape(aboria_ctx* ctx, int32_t ipt, int32_t low_bits) {
+extern "C" aboria_status aboria_set_build_shape(aboria_ctx* ctx, int32_t ipt, int32_t low_bits, int32_t shuffle) {
     if (!ctx) return ABORIA_ERR_INVALID_ARG;
     if (ipt != 0 && ipt != 4 && ipt != 8 && ipt != 16)
         return fail(ctx, ABORIA_ERR_INVALID_ARG, "keys per thread must be 0, 4, 8 or 16");
     if (low_bits != 0 && (low_bits < 8 || low_bits > kMaxDigitBits))
         return fail(ctx, ABORIA_ERR_INVALID_ARG, "bucket bits must be 0 or 8 to 10");
-    ctx->build_forced = aboria_ctx::BuildShape{ipt, low_bits};
+    if (shuffle < 0 || shuffle > 2) return fail(ctx, ABORIA_ERR_INVALID_ARG, "shuffle must be 0, 1 or 2");
+    ctx->build_forced = aboria_ctx::BuildShape{ipt, low_bits, shuffle};
     return ABORIA_OK;
 }
 
 extern "C" aboria_status aboria_autotune_build(aboria_ctx* ctx, aboria_dtype dtype, int32_t nsys,
                                                const aboria_box* boxes_host, const int64_t* offsets_host,
-                                               const void* x, int32_t* ipt_out, int32_t* low_bits_out) {
+                                               const void* x, int32_t* ipt_out, int32_t* low_bits_out,
+                                               int32_t* shuffle_out) {
     if (!ctx) return ABORIA_ERR_INVALID_ARG;
     if (ctx->capturing) return fail(ctx, ABORIA_ERR_UNSUPPORTED, "autotune cannot be captured");
     if (nsys < 1 || !boxes_host || !offsets_host) return fail(ctx, ABORIA_ERR_INVALID_ARG, "need boxes and offsets");
@@ -1424,15 +1428,15 @@ extern "C" aboria_status aboria_autotune_build(aboria_ctx* ctx, aboria_dtype dty
         ctx->build_strategy = ABORIA_BUILD_RADIX;
         aboria_status st = ABORIA_OK;
         double best_ms = INFINITY;
-        aboria_ctx::BuildShape best{0, 0};
+        aboria_ctx::BuildShape best{0, 0, 0};
         int64_t ncells = 0, n = offsets_host[nsys];
         const int32_t ipts[] = {4, 8, 16};
         const int32_t lows[] = {8, 9, 10};
         int32_t last_bits = -1;
         for (int32_t ipt : ipts) {
-            for (int32_t lb : lows) {
+            for (int32_t lb : lows) for (int32_t sh = 1; sh <= 2; ++sh) {
                 if (st != ABORIA_OK) break;
-                ctx->build_forced = aboria_ctx::BuildShape{ipt, lb};
+                ctx->build_forced = aboria_ctx::BuildShape{ipt, lb, sh};
                 aboria_cells* c = nullptr;
                 st = aboria_build_cells(ctx, dtype, nsys, boxes_host, offsets_host, x, &c);
                 if (st != ABORIA_OK) break;
@@ -1451,10 +1455,11 @@ extern "C" aboria_status aboria_autotune_build(aboria_ctx* ctx, aboria_dtype dty
                 (void)hipEventElapsedTime(&ms, e0, e1);
                 (void)aboria_cells_destroy(c);
                 if (st != ABORIA_OK) break;
-                log_msg("autotune_build: %d keys per thread, %d bucket bits: %.4f ms", ipt, lb, ms / 5.0);
+                log_msg("autotune_build: %d keys per thread, %d bucket bits, shuffle %s: %.4f ms", ipt, lb,
+                        sh == 1 ? "on" : "off", ms / 5.0);
                 if (ms < best_ms) {
                     best_ms = ms;
-                    best = aboria_ctx::BuildShape{ipt, lb};
+                    best = aboria_ctx::BuildShape{ipt, lb, sh};
                 }
             }
         }
@@ -1473,10 +1478,11 @@ extern "C" aboria_status aboria_autotune_build(aboria_ctx* ctx, aboria_dtype dty
             }
         if (!found) ctx->build_cache.emplace_back(key, best);
         tune_cache_save(ctx);
-        log_msg("autotune_build: %d keys per thread, %d bucket bits chosen (%d key bits)", best.ipt, best.low_bits,
-                last_bits);
+        log_msg("autotune_build: %d keys per thread, %d bucket bits, shuffle %s chosen (%d key bits)", best.ipt,
+                best.low_bits, best.shuffle == 1 ? "on" : "off", last_bits);
         if (ipt_out) *ipt_out = best.ipt;
         if (low_bits_out) *low_bits_out = best.low_bits;
+        if (shuffle_out) *shuffle_out = best.shuffle;
         return ABORIA_OK;
     } catch (...) {
         ctx->build_forced = forced_before;

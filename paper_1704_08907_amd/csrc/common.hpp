@@ -116,9 +116,10 @@ struct aboria_ctx {
     struct BuildShape {
         int32_t ipt;
         int32_t low_bits;
+        int32_t shuffle;  // the scatter's LDS shuffle: 0 = rule, 1 = where it fits, 2 = never
     };
     std::vector<std::pair<uint64_t, BuildShape>> build_cache;
-    BuildShape build_forced{0, 0};
+    BuildShape build_forced{0, 0, 0};
     std::string arch;        // the device's architecture name (keys the persistent cache)
     std::string cache_path;  // ABORIA_TUNE_CACHE at creation ("" = no persistent cache)
 };
@@ -154,6 +155,7 @@ struct aboria_cells {
     int32_t digit_bits = 0;
     int32_t low_bits = 0;      // bits sorted by the per-bucket pass
     int32_t sort_ipt = 16;     // keys per thread of a sort tile (tile = 256 * sort_ipt keys)
+    int32_t shuffle_pref = 0;  // radix scatter's LDS shuffle: 0 = rule, 1 = where it fits, 2 = never
     int64_t ntiles = 0;
     int64_t hist_len = 0;
     int64_t nblock_sums = 0;

@@ -69,16 +69,17 @@ def test_many_small_systems_rows_gathered(ctx):
         base_cell += int(g.ncells)
 
 
+@pytest.mark.parametrize("shuffle", [1, 2])
 @pytest.mark.parametrize("ipt", [4, 8, 16])
 @pytest.mark.parametrize("low_bits", [8, 9, 10])
-def test_every_build_shape_is_bit_exact(ipt, low_bits):
+def test_every_build_shape_is_bit_exact(ipt, low_bits, shuffle):
     """Every radix build shape the tuner may pick (keys per thread of a sort tile,
-    bits sorted per bucket) gives the oracle's cell list, on the spring cube's
-    headline grid (cells r/3 wide along x: 158 x 52 x 52, one radix pass or two)
-    and on a batch of uneven systems."""
+    bits sorted per bucket, the scatter's LDS shuffle on or off) gives the
+    oracle's cell list, on the spring cube's headline grid (cells r/3 wide along
+    x: 158 x 52 x 52, one radix pass or two) and on a batch of uneven systems."""
     sctx = A.Context(0)
-    sctx.set_build_shape(ipt, low_bits)
-    print("build shape", ipt, low_bits, flush=True)
+    sctx.set_build_shape(ipt, low_bits, shuffle)
+    print("build shape", ipt, low_bits, shuffle, flush=True)
     s = syn.spring_cube().systems[0]
     box = A.BoxSpec(3, s.lo, s.hi, s.periodic, s.cutoff, None, [3, 1, 1])
     cells = A.build_cells(sctx, to_dev(s.x), [box])
@@ -107,8 +108,8 @@ def test_build_tuner_picks_a_shape_later_builds_use():
     tctx = A.Context(0)
     s = syn.spring_cube(n=1 << 18).systems[0]
     box = box_of(s)
-    ipt, lb = A.autotune_build(tctx, to_dev(s.x), [box])
-    assert ipt in (4, 8, 16) and 8 <= lb <= 10
+    ipt, lb, sh = A.autotune_build(tctx, to_dev(s.x), [box])
+    assert ipt in (4, 8, 16) and 8 <= lb <= 10 and sh in (1, 2)
     cells = A.build_cells(tctx, to_dev(s.x), [box])
     tctx.sync()
     check_system(oracle.grid_of(s), s.x, *cells_state(cells))
@@ -116,5 +117,7 @@ def test_build_tuner_picks_a_shape_later_builds_use():
         tctx.set_build_shape(5, 0)
     with pytest.raises(A.AboriaError):
         tctx.set_build_shape(0, 11)
+    with pytest.raises(A.AboriaError):
+        tctx.set_build_shape(0, 0, 3)
     cells.close()
     tctx.close()

@@ -159,14 +159,14 @@ def test_dense_and_build_tuning_persist(tmp_path):
         c1 = A.Context(0)
         s = syn.spring_cube(n=60000).systems[0]
         x_d = to_dev(s.x)
-        ipt, lb = A.autotune_build(c1, x_d, [box_of(s)])
+        ipt, lb, sh = A.autotune_build(c1, x_d, [box_of(s)])
         rng = syn.SplitMix64(5)
         xt = to_dev(syn.uniform_positions(rng, 3000, [0.0] * 2, [1.0] * 2, "f32"))
         w = to_dev(rng.normal(3000).astype("float32"))
         plan = A.autotune_dense(c1, xt, xt, w, 0.2)
         c1.sync()
         doc = json.load(open(path))
-        assert [e["build"] for e in doc["build"]] == [[ipt, lb]]
+        assert [e["build"] for e in doc["build"]] == [[ipt, lb, sh]]
         name = A.dense_plan_name(plan)
         ti, wg = int(name.split()[0]), int(name.split()[-2])
         assert [e["dense_plan"] for e in doc["dense"]] == [[ti, wg]]
