@@ -342,6 +342,10 @@ def main():
     t_bwd_search = timed_graph(lambda: A.pair_sum_backward(ctx, cells, "spring", (1.0,), gy, gx=gx))
     ctx.set_variant(mask_variant)  # each forward records the masks the adjoints then replay
     t_fwd_mask = timed_graph(lambda: A.pair_sum(ctx, cells, "spring", (1.0,), y=y))
+    # the half stencil (each pair tested once, the partner reads the recorded bit): forward only
+    ctx.set_variant(next(v for v in range(A.variant_count()) if "half stencil" in A.variant_name(v)))
+    t_fwd_half = timed_graph(lambda: A.pair_sum(ctx, cells, "spring", (1.0,), y=y))
+    ctx.set_variant(mask_variant)
     t_bwd_mask = timed_graph(lambda: A.pair_sum_backward(ctx, cells, "spring", (1.0,), gy, gx=gx))
     ctx.set_variant(-1)
     per_variant = {}  # on the paper's lattice (reach 1), where every variant applies
@@ -428,6 +432,7 @@ def main():
                  "build_counting_ms": t_build_counting, "fwd_ms": t_fwd, "bwd_ms": t_bwd,
                  "box_search_fwd_ms": t_fwd_search, "box_search_bwd_ms": t_bwd_search,
                  "recorded_masks_fwd_ms": t_fwd_mask, "recorded_masks_bwd_ms": t_bwd_mask,
+                 "half_stencil_fwd_ms": t_fwd_half,
                  "neighbour_list_record_ms": t_nbr, "replay_fwd_ms": t_fwd_list, "replay_bwd_ms": t_bwd_list,
                  "build_hbm_frac": build_bytes / (t_build * 1e-3) / 1e9 / HBM_PEAK_GBS,
                  "roofline_per_call": {k: {q: v for q, v in roof(k).items()

@@ -951,6 +951,8 @@ void launch_lane_fused(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& 
 template <typename T, int D, int OP, bool BATCH>
 void launch_mask_fwd(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, T* y);
 template <typename T, int D, int OP, bool BATCH>
+void launch_half_fwd(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, T* y);
+template <typename T, int D, int OP, bool BATCH>
 void launch_mask_bwd(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, const T* gy_s, T* gx,
                      T* ga);
 template <typename T, int D, int OP, bool BATCH, int MODE>

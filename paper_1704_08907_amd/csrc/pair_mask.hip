@@ -313,6 +313,251 @@ __global__ __launch_bounds__(256) void k_lane_mask(const T* __restrict__ xs, con
     }
 }
 
+// ---------------------------------------------------------------------------
+// Half stencil (Newton's third law for the pair test).  The pair test is
+// symmetric bit for bit: a partner's dx is fl(x_i - x_j) + s = -(fl(x_j - x_i)
+// + (-s)), so d2 and the decision are the same from both ends.  Each unordered
+// pair is therefore tested once:
+//   k_half_upper  lane i tests the upper half of its stencil -- the rows with
+//                 dz > 0, or dz = 0 and dy > 0, and the part of its own row
+//                 ahead of it (its own cell's later slots and the cells after
+//                 it along x, including a forward wrap) -- adds those summands
+//                 into a partial sum (cell order) and records the rows' bits as
+//                 the recording forward does (a row over kMaskBits candidates
+//                 records all ones);
+//   k_half_mirror lane j walks the lower half cell by cell; for each
+//                 candidate i it reads the bit that i's upper row holds at
+//                 j's position (computed from i's cell), and for a set bit
+//                 (or a position beyond the record) runs the pair test and the
+//                 summand in j's frame, exactly as the full-stencil forward
+//                 would; then adds the partial sum.
+// The summands are those of the full-stencil kernels; the sum runs lower half
+// first, then the partial, so it differs from them by rounding order only.
+// Requires reach 1 in y and z and a grid at least 2 m + 1 cells wide in x.
+// The records it leaves are not full-stencil records (status none).
+template <typename T, int D, int OP, bool BATCH, bool OFF32>
+__global__ __launch_bounds__(256) void k_half_upper(const T* __restrict__ xs, const uint32_t* __restrict__ off,
+                                                    uint32_t n, const SysParams<T>* __restrict__ sp,
+                                                    const uint32_t* __restrict__ sys_part, int nsys,
+                                                    const T* __restrict__ a_s, OpArgs<T> q, T* __restrict__ yh,
+                                                    uint32_t* __restrict__ masks, uint32_t* __restrict__ status) {
+    using Op = PairOp<T, D, OP>;
+    constexpr int NY = Op::NY;
+    constexpr int PITCH = Pitch<D>::value;
+    constexpr int NR = D == 1 ? 1 : (D == 2 ? 3 : 9);
+    constexpr int C = NR / 2;  // the particle's own row
+    const uint32_t first = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x;
+    const uint32_t s = first + threadIdx.x;
+    const int b = system_of_row<BATCH>(sys_part, nsys, first, s);
+    if (s >= n) return;
+    const SysParams<T> P = sp[b];
+    T xi[D];
+    load_point<T, D>(xs, s, xi);
+    const T ai = OpShape<OP, D>::NA ? a_s[s] : T(0);
+    const T r = P.r, r2 = P.r2;
+    T acc[NY];
+#pragma unroll
+    for (int k = 0; k < NY; ++k) acc[k] = T(0);
+    auto visit = [&](uint32_t j, const T* dx, T d2) {
+        const T aj = OpShape<OP, D>::NA ? load_row<T, 1, OFF32>(a_s, j).v[0] : T(0);
+        Op::fwd(q, r, dx, d2, ai, aj, acc);
+    };
+    // candidates [ja, jb) as the recording forward scans them: two per iteration,
+    // each bit shifted into rec from the bottom
+    auto scan_s = [&](auto shift_tag, uint32_t ja, uint32_t jb, const T* sh, uint64_t& rec) {
+        constexpr bool SHIFT = decltype(shift_tag)::value;
+        uint32_t j = ja;
+        for (; j + 1 < jb; j += 2) {
+            const VecN<T, PITCH> xa = load_row<T, PITCH, OFF32>(xs, j);
+            const VecN<T, PITCH> xb = load_row_at<T, PITCH, OFF32>(xs, j, 1);
+            T dx[D], d2;
+            const bool oa = pair_test<T, D, SHIFT>(xa.v, xi, sh, r2, dx, &d2);
+            if (oa) visit(j, dx, d2);
+            const bool ob = pair_test<T, D, SHIFT>(xb.v, xi, sh, r2, dx, &d2);
+            if (ob) visit(j + 1, dx, d2);
+            rec = (rec << 2) | (oa ? 2u : 0u) | (ob ? 1u : 0u);
+        }
+        if (j < jb) {
+            const VecN<T, PITCH> xa = load_row<T, PITCH, OFF32>(xs, j);
+            T dx[D], d2;
+            const bool oa = pair_test<T, D, SHIFT>(xa.v, xi, sh, r2, dx, &d2);
+            if (oa) visit(j, dx, d2);
+            rec = (rec << 1) | (oa ? 1u : 0u);
+        }
+    };
+    auto scan = [&](uint32_t ja, uint32_t jb, const T* sh, uint64_t& rec) {
+        bool lane_shift = false;
+#pragma unroll
+        for (int k = 0; k < D; ++k) lane_shift |= sh[k] != T(0);
+        // the image shift's adds only where some lane of the wave needs them
+        if (__ballot(lane_shift) != 0ull) scan_s(std::integral_constant<bool, true>(), ja, jb, sh, rec);
+        else scan_s(std::integral_constant<bool, false>(), ja, jb, sh, rec);
+    };
+    uint64_t rec = 0;
+    uint32_t pos = 0;
+    int cur = 0;
+    for_each_piece<T, D>(
+        P, off, n, xi,
+        [&](int row) {
+            rec = 0;
+            pos = 0;
+            cur = row;
+        },
+        [&](uint32_t j0, uint32_t j1, const T* sh) {
+            if (cur < C) return;
+            j1 = max(j1, j0);
+            const uint32_t len = j1 - j0;
+            if (cur == C) {
+                if (sh[0] == T(0)) {  // the main run: its slots after s are ahead
+                    scan(min(max(s + 1u, j0), j1), j1, sh, rec);
+                    pos += len;
+                    return;
+                }
+                if (sh[0] < T(0)) {  // a backward wrap: all behind (zeros keep the positions)
+                    rec = len >= 64u ? 0ull : (rec << len);
+                    pos += len;
+                    return;
+                }
+            }
+            scan(j0, j1, sh, rec);
+            pos += len;
+        },
+        [&](int row) {
+            if (row < C) return;
+            uint64_t m;
+            if (pos > (uint32_t)kMaskBits) {
+                m = ~0ull;  // positions past the record: the mirror pass tests every candidate
+            } else {
+                const uint64_t rev = ((uint64_t)__builtin_bitreverse32((uint32_t)rec) << 32) |
+                                     __builtin_bitreverse32((uint32_t)(rec >> 32));
+                m = pos == 0u ? 0ull : rev >> (64u - pos);
+            }
+            masks[(size_t)(2 * row) * n + s] = (uint32_t)m;
+            masks[(size_t)(2 * row + 1) * n + s] = (uint32_t)(m >> 32);
+        });
+    status[s] = kGenNone;  // not a full-stencil record: a replaying adjoint tests instead
+#pragma unroll
+    for (int k = 0; k < NY; ++k) yh[(size_t)s * 4 + k] = acc[k];
+}
+
+template <typename T, int D, int OP, bool BATCH, bool OFF32>
+__global__ __launch_bounds__(256) void k_half_mirror(const T* __restrict__ xs, const uint32_t* __restrict__ off,
+                                                     const uint32_t* __restrict__ perm, uint32_t n,
+                                                     const SysParams<T>* __restrict__ sp,
+                                                     const uint32_t* __restrict__ sys_part, int nsys,
+                                                     const T* __restrict__ a_s, OpArgs<T> q,
+                                                     const T* __restrict__ yh, const uint32_t* __restrict__ masks,
+                                                     T* __restrict__ y) {
+    using Op = PairOp<T, D, OP>;
+    constexpr int NY = Op::NY;
+    constexpr int PITCH = Pitch<D>::value;
+    constexpr int NR = D == 1 ? 1 : (D == 2 ? 3 : 9);
+    constexpr int C = NR / 2;
+    const uint32_t first = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x;
+    const uint32_t s = first + threadIdx.x;
+    const int b = system_of_row<BATCH>(sys_part, nsys, first, s);
+    if (s >= n) return;
+    const SysParams<T> P = sp[b];
+    T xj[D];
+    load_point<T, D>(xs, s, xj);
+    const T aj = OpShape<OP, D>::NA ? a_s[s] : T(0);
+    const T r = P.r, r2 = P.r2;
+    T acc[NY];
+#pragma unroll
+    for (int k = 0; k < NY; ++k) acc[k] = T(0);
+    int32_t c[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        T fr;
+        c[k] = cell_coord(P, k, xj[k], &fr);
+    }
+    const int32_t M = P.reach[0];
+    const int32_t nx = P.n[0];
+    const int32_t zr = D >= 3 ? 1 : 0, yr = D >= 2 ? 1 : 0;
+    // this particle's own x-row: the row of every partner's upper stencil row that reaches it
+    const uint32_t rb_own = P.cell_base + (uint32_t)nx * ((uint32_t)c[1] + (uint32_t)P.n[1] * (uint32_t)c[2]);
+#pragma unroll 1
+    for (int32_t dz = -zr; dz <= 0; ++dz) {
+        int32_t cz = 0;
+        T sz = T(0);
+        if (D >= 3 && !wrap_cell(c[2] + dz, P.n[2], P.periodic[2], P.L[2], &cz, &sz)) continue;
+#pragma unroll 1
+        for (int32_t dy = -yr; dy <= yr; ++dy) {
+            const int row = (dz + zr) * (2 * yr + 1) + (dy + yr);
+            if (row > C) break;  // the upper half belongs to k_half_upper
+            int32_t cy = 0;
+            T sy = T(0);
+            if (D >= 2 && !wrap_cell(c[1] + dy, P.n[1], P.periodic[1], P.L[1], &cy, &sy)) continue;
+            const int hr = NR - 1 - row;  // the partners' row that covers this particle's x-row
+            const uint32_t rb = P.cell_base + (uint32_t)nx * ((uint32_t)cy + (uint32_t)P.n[1] * (uint32_t)cz);
+            const int32_t o_end = row == C ? 0 : M;
+#pragma unroll 1
+            for (int32_t o = -M; o <= o_end; ++o) {
+                int32_t cx;
+                T sx = T(0);
+                if (!wrap_cell(c[0] + o, nx, P.periodic[0], P.L[0], &cx, &sx)) continue;
+                const uint32_t i0 = off[rb + cx];
+                uint32_t i1 = min(off[rb + cx + 1], n);
+                if (row == C && o == 0) i1 = min(i1, s);  // own cell: the slots before s
+                if (i1 <= i0) continue;
+                // position of this particle in the row hr of a partner in cell cx: that
+                // row's main run starts at cell max(cx - M, 0) of the own x-row, its
+                // wrapped remainder (if any) follows it
+                const int32_t a0 = max(cx - M, 0), b0 = min(cx + M, nx - 1);
+                uint32_t pos;
+                if (c[0] >= a0 && c[0] <= b0) {
+                    pos = s - off[rb_own + a0];
+                } else {
+                    const int32_t a1 = cx - M < 0 ? cx - M + nx : 0;
+                    pos = (min(off[rb_own + b0 + 1], n) - off[rb_own + a0]) + (s - off[rb_own + a1]);
+                }
+                const T sh[3] = {sx, sy, sz};
+                const size_t wrow = (size_t)(2 * hr + (pos >= 32u ? 1 : 0)) * n;
+                const uint32_t bit = pos & 31u;
+                auto pair = [&](uint32_t i) {
+                    const VecN<T, PITCH> xi = load_row<T, PITCH, OFF32>(xs, i);
+                    T dx[D], d2;
+                    if (pair_test<T, D, true>(xi.v, xj, sh, r2, dx, &d2)) {
+                        const T ai = OpShape<OP, D>::NA ? load_row<T, 1, OFF32>(a_s, i).v[0] : T(0);
+                        Op::fwd(q, r, dx, d2, aj, ai, acc);
+                    }
+                };
+                const bool all = pos >= (uint32_t)kMaskBits;  // past the record: test every candidate
+                uint32_t i = i0;
+                for (; i + 1 < i1; i += 2) {  // two partners' bits per iteration, their loads together
+                    const uint32_t wa = all ? 1u : masks[wrow + i] >> bit;
+                    const uint32_t wb = all ? 1u : masks[wrow + i + 1] >> bit;
+                    if (wa & 1u) pair(i);
+                    if (wb & 1u) pair(i + 1);
+                }
+                if (i < i1 && (all || ((masks[wrow + i] >> bit) & 1u))) pair(i);
+            }
+        }
+    }
+    const uint32_t o = perm[s];
+#pragma unroll
+    for (int k = 0; k < NY; ++k) y[(size_t)o * NY + k] = acc[k] + yh[(size_t)s * 4 + k];
+}
+
+template <typename T, int D, int OP, bool BATCH>
+void launch_half_fwd(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, T* y) {
+    const uint32_t n = (uint32_t)c->n;
+    const SysParams<T>* sp = reinterpret_cast<const SysParams<T>*>(c->params_dev);
+    const dim3 grid((n + 255) / 256);
+    T* yh = reinterpret_cast<T*>(c->work2);  // [n][4] partial sums in cell order
+    if (off32_rows<T>(n)) {
+        hipLaunchKernelGGL((k_half_upper<T, D, OP, BATCH, true>), grid, dim3(256), 0, ctx->stream, (const T*)c->xs,
+                           c->off, n, sp, c->sys_part_dev, c->nsys, a_s, q, yh, c->masks, c->mask_status);
+        hipLaunchKernelGGL((k_half_mirror<T, D, OP, BATCH, true>), grid, dim3(256), 0, ctx->stream, (const T*)c->xs,
+                           c->off, c->perm, n, sp, c->sys_part_dev, c->nsys, a_s, q, (const T*)yh, c->masks, y);
+    } else {
+        hipLaunchKernelGGL((k_half_upper<T, D, OP, BATCH, false>), grid, dim3(256), 0, ctx->stream, (const T*)c->xs,
+                           c->off, n, sp, c->sys_part_dev, c->nsys, a_s, q, yh, c->masks, c->mask_status);
+        hipLaunchKernelGGL((k_half_mirror<T, D, OP, BATCH, false>), grid, dim3(256), 0, ctx->stream, (const T*)c->xs,
+                           c->off, c->perm, n, sp, c->sys_part_dev, c->nsys, a_s, q, (const T*)yh, c->masks, y);
+    }
+}
+
 template <typename T, int D, int OP, bool BATCH>
 void launch_mask_fwd(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, T* y) {
     const uint32_t n = (uint32_t)c->n;
@@ -346,6 +591,8 @@ void launch_mask_bwd(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q,
 
 #define ABORIA_INST(T, D, OP, BATCH)                                                                          \
     template void launch_mask_fwd<T, D, OP, BATCH>(aboria_ctx*, const aboria_cells*, const OpArgs<T>&,        \
+                                                   const T*, T*);                                             \
+    template void launch_half_fwd<T, D, OP, BATCH>(aboria_ctx*, const aboria_cells*, const OpArgs<T>&,        \
                                                    const T*, T*);                                             \
     template void launch_mask_bwd<T, D, OP, BATCH>(aboria_ctx*, const aboria_cells*, const OpArgs<T>&,        \
                                                    const T*, const T*, T*, T*);

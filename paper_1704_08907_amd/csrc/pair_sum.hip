@@ -88,7 +88,7 @@ aboria_status gather(aboria_ctx* ctx, const aboria_cells* c, const void* src, in
 struct Variant {
     int kind;   // 0 = lane per particle, 2 = recorded neighbour list, 3 = all pairs,
                 // 5 = flattened pruned search, 6 = lane per particle with recorded
-                // accepted-pair masks
+                // accepted-pair masks, 7 = half stencil (forward; the adjoint is kind 0's)
     int block;  // threads per workgroup
     const char* name;
 };
@@ -99,6 +99,7 @@ const Variant kVariants[] = {
     {3, 256, "lane per particle over all particles of its system (minimum image; small systems)"},
     {5, 256, "lane per particle, flattened box search over pruned slot ranges listed in LDS"},
     {6, 256, "lane per particle, forward records accepted-pair bit masks per stencil row, adjoint replays them"},
+    {7, 256, "lane per particle, half stencil: each pair tested once, the partner reads the recorded bit"},
 };
 
 // Modes of the flattened kernel (pair_flat.hpp).
@@ -121,8 +122,19 @@ bool rows_reach1(const aboria_cells* c) { return max_reach(c, 1) == 1 && max_rea
 
 // Variants with their own box-search loops, written for the 3^d stencil: the
 // mask variant for its rows, the others for every cell of it.
+// Every system's grid at least 2 m + 1 cells wide in x (m its x reach): each x
+// offset of a stencil row is then one distinct cell.
+bool wide_x(const aboria_cells* c) {
+    for (int32_t b = 0; b < c->nsys; ++b) {
+        const int32_t m = c->boxes[(size_t)b].reach[0] == 0 ? 1 : c->boxes[(size_t)b].reach[0];
+        if (c->ncell_host[(size_t)b * 3] < 2 * m + 1) return false;
+    }
+    return true;
+}
+
 bool reach_ok(const Variant& v, const aboria_cells* c) {
     if (v.kind == 6) return rows_reach1(c);
+    if (v.kind == 7) return rows_reach1(c) && wide_x(c);
     return true;
 }
 
@@ -137,6 +149,7 @@ template <typename T, int D, int OP, bool BATCH>
 void launch_fwd_variant(aboria_ctx* ctx, const aboria_cells* c, const OpArgs<T>& q, const T* a_s, T* y,
                         const Variant& v) {
     if (v.kind == 6) launch_mask_fwd<T, D, OP, BATCH>(ctx, c, q, a_s, y);
+    else if (v.kind == 7) launch_half_fwd<T, D, OP, BATCH>(ctx, c, q, a_s, y);
     else if (v.kind == 5) launch_flat<T, D, OP, BATCH, kFlatModeFwd>(ctx, c, q, a_s, nullptr, y, nullptr, nullptr);
     else if (v.kind == 3) launch_all_fwd<T, D, OP, BATCH>(ctx, c, q, a_s, y);
     else if (v.kind == 2) launch_nbr_fwd<T, D, OP, BATCH>(ctx, c, q, a_s, y);
@@ -239,8 +252,11 @@ aboria_status check_variant(aboria_ctx* ctx, const aboria_cells* c, int variant)
     if (variant_of(variant).kind == 3 && largest_system(c) > kAllPairsMaxSystem)
         return fail(ctx, ABORIA_ERR_INVALID_ARG, "the all-pairs variant takes systems of at most 16384 particles");
     if (!reach_ok(variant_of(variant), c))
-        return fail(ctx, ABORIA_ERR_INVALID_ARG, "the variant needs reach 1 in every dimension but x");
-    if (variant_of(variant).kind == 6) return ensure_masks(ctx, c);
+        return fail(ctx, ABORIA_ERR_INVALID_ARG,
+                    variant_of(variant).kind == 7
+                        ? "the variant needs reach 1 in every dimension but x and at least 2 m + 1 cells in x"
+                        : "the variant needs reach 1 in every dimension but x");
+    if (variant_of(variant).kind == 6 || variant_of(variant).kind == 7) return ensure_masks(ctx, c);
     return ABORIA_OK;
 }
 
