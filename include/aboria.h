@@ -480,7 +480,12 @@ const char* aboria_variant_name(int32_t variant);
  * sum with it on a cell list allocates 2 * 3^(d-1) + 1 words per particle,
  * owned and freed with the cell list (so that first call cannot be captured);
  * INVALID_ARG if the list has m > 1.  Sums that overlap on one cell list with
- * this variant race on its record. */
+ * this variant race on its record.  The half-stencil variant (Section 3's eq.
+ * (1) forward with each unordered pair tested once, Newton's third law for the
+ * pair test) uses the same record for the upper half of each stencil and
+ * leaves it marked as not replayable; its adjoint is the plain lane kernel's;
+ * it needs reach 1 in y and z and a grid of at least 2 m + 1 cells in x
+ * (INVALID_ARG otherwise). */
 aboria_status aboria_set_variant(aboria_ctx* ctx, int32_t variant);
 
 /* The variant a sum on these cells with this operator would use now (forced,
