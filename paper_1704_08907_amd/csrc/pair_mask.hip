@@ -17,7 +17,8 @@
 //
 // Replayed pairs are visited in box-search order with dx and d2 recomputed by
 // the same pair test, so forward and adjoint equal the plain lane kernels' bit
-// for bit.
+// for bit.  The half-stencil forward below uses the same record layout for the
+// upper half of each stencil.
 #include "pair_common.hpp"
 
 namespace aboria {
