@@ -171,7 +171,7 @@ extern "C" aboria_status aboria_autotune(aboria_ctx* ctx, const aboria_cells* ce
         };
         for (int32_t v = 0; v < variant_count() && st == ABORIA_OK; ++v) {
             if (!variant_usable(v, cells)) continue;
-            if (!variant_worth_timing(v, cells)) continue;
+            if (!variant_worth_timing(v, cells, gy != nullptr)) continue;
             st = run(v);  // warm-up
             if (st != ABORIA_OK) break;
             std::vector<float> times;

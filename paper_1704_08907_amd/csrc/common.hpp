@@ -229,7 +229,7 @@ int32_t variant_count();
 const char* variant_name(int32_t v);
 bool variant_needs_list(int32_t v);  // replays a recorded neighbour list
 bool variant_usable(int32_t v, const aboria_cells* c);  // its requirements hold for these cells
-bool variant_worth_timing(int32_t v, const aboria_cells* c);  // the tuner times it on these cells
+bool variant_worth_timing(int32_t v, const aboria_cells* c, bool backward);  // the tuner times it on these cells
 int32_t list_variant();              // the variant that replays the list
 int32_t default_variant(const aboria_cells* c);  // the variant of an untuned sum
 int32_t pick_variant(aboria_ctx* ctx, const aboria_cells* cells, int32_t op, bool backward);

@@ -268,12 +268,14 @@ const char* variant_name(int32_t v) { return (v >= 0 && v < kNumVariants) ? kVar
 
 bool variant_needs_list(int32_t v) { return v >= 0 && v < kNumVariants && kVariants[v].kind == 2; }
 
-bool variant_worth_timing(int32_t v, const aboria_cells* c) {
+bool variant_worth_timing(int32_t v, const aboria_cells* c, bool backward) {
     (void)c;
     if (v < 0 || v >= kNumVariants) return false;
     // the mask-recording pair pays only across a forward and its adjoint, which the
     // tuner times separately: callers select it for both calls
     if (kVariants[v].kind == 6) return false;
+    // the half stencil's adjoint is variant 0's
+    if (kVariants[v].kind == 7 && backward) return false;
     return true;
 }
 
