@@ -88,6 +88,106 @@ __device__ __forceinline__ void for_each_piece(const SysParams<T>& P, const uint
     }
 }
 
+constexpr int kBlockWaves = 4;  // waves of a 256-thread workgroup
+constexpr int kWindow = 128;    // slots of a wave's LDS window
+
+// The walk of for_each_piece on grids at least 2 m + 1 cells wide, with each
+// row's main run (the cells up to m away in x, clipped to the grid) read from
+// the wave's LDS window wb when the runs of all its lanes fit in it: lo is the
+// first lane's run start and hi the last lane's run end; if every lane's run
+// lies in [lo, hi) and hi - lo <= kWindow, the lanes copy those slots with
+// coalesced loads and win(j0, j1, sh, wb, lo) scans the run from LDS.  The
+// wrapped remainder, and the runs of rows that do not fit, go to piece(j0, j1,
+// sh) as in for_each_piece.  Rows, pieces and slot ranges are those of
+// for_each_piece in the same order, so sums and records are identical.  All
+// lanes of the wave that are still running take part in every row (no lane
+// skips ahead), so the copy and the window reads stay in step.
+template <typename T, int D, typename Begin, typename Piece, typename End, typename Win>
+__device__ __forceinline__ void staged_rows(const SysParams<T>& P, const uint32_t* __restrict__ off, uint32_t n,
+                                            const T* xi, const T* __restrict__ xs, char* wb, Begin&& begin,
+                                            Piece&& piece, End&& end, Win&& win) {
+    constexpr int PITCH = Pitch<D>::value;
+    constexpr uint32_t RB = (uint32_t)sizeof(VecN<T, PITCH>);
+    const uint64_t act = __ballot(true);
+    const uint32_t nact = (uint32_t)__popcll(act);
+    const uint32_t rank =
+        __builtin_amdgcn_mbcnt_hi((uint32_t)(act >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0u));
+    int32_t c[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        T fr;
+        c[k] = cell_coord(P, k, xi[k], &fr);
+    }
+    const int32_t M = P.reach[0];
+    const int32_t nx = P.n[0];
+    const int32_t a0 = max(c[0] - M, 0), b0 = min(c[0] + M, nx - 1);
+    int32_t a1 = 0, b1 = -1;
+    T s1 = T(0);
+    if (P.periodic[0]) {
+        if (c[0] - M < 0) { a1 = c[0] - M + nx; b1 = nx - 1; s1 = -P.L[0]; }
+        else if (c[0] + M >= nx) { a1 = 0; b1 = c[0] + M - nx; s1 = P.L[0]; }
+    }
+    const int32_t zr = D >= 3 ? 1 : 0, yr = D >= 2 ? 1 : 0;
+#pragma unroll 1
+    for (int32_t dz = -zr; dz <= zr; ++dz) {
+#pragma unroll 1
+        for (int32_t dy = -yr; dy <= yr; ++dy) {
+            int32_t cz = 0, cy = 0;
+            T sz = T(0), sy = T(0);
+            const bool ez = D < 3 || wrap_cell(c[2] + dz, P.n[2], P.periodic[2], P.L[2], &cz, &sz);
+            const bool ey = D < 2 || wrap_cell(c[1] + dy, P.n[1], P.periodic[1], P.L[1], &cy, &sy);
+            const bool ex = ez && ey;
+            const int row = (dz + zr) * (2 * yr + 1) + (dy + yr);
+            uint32_t rowbase = 0, jm0 = 0, jm1 = 0;
+            if (ex) {
+                rowbase = P.cell_base + (uint32_t)nx * ((uint32_t)cy + (uint32_t)P.n[1] * (uint32_t)cz);
+                jm0 = off[rowbase + a0];
+                jm1 = max(min(off[rowbase + b0 + 1], n), jm0);
+            }
+            const bool has = jm1 > jm0;
+            const uint64_t hb = __ballot(has);
+            bool staged = false;
+            uint32_t lo = 0;
+            if (hb != 0ull) {
+                lo = __builtin_amdgcn_readlane(jm0, __builtin_ctzll(hb));
+                const uint32_t hi = __builtin_amdgcn_readlane(jm1, 63 - __builtin_clzll(hb));
+                const bool inside = !has || (jm0 >= lo && jm1 <= hi);
+                // all inside: the first lane's run gives lo < hi
+                staged = __ballot(!inside) == 0ull && hi - lo <= (uint32_t)kWindow;
+                if (staged) {
+                    // two slots per lane first, both loads in flight together (a full
+                    // wave covers the window with them), then any rest
+                    using Row = VecN<T, PITCH>;
+                    const char* const src = reinterpret_cast<const char*>(xs) + (size_t)lo * RB;
+                    const uint32_t cnt = hi - lo, t1 = rank + nact;  // cnt >= 1
+                    const Row ra = *reinterpret_cast<const Row*>(src + (size_t)min(rank, cnt - 1u) * RB);
+                    const Row rb = *reinterpret_cast<const Row*>(src + (size_t)min(t1, cnt - 1u) * RB);
+                    keep_issued<PITCH>(ra.v);
+                    keep_issued<PITCH>(rb.v);
+                    if (rank < cnt) *reinterpret_cast<Row*>(wb + rank * RB) = ra;
+                    if (t1 < cnt) *reinterpret_cast<Row*>(wb + t1 * RB) = rb;
+                    for (uint32_t t = t1 + nact; t < cnt; t += nact)
+                        *reinterpret_cast<Row*>(wb + t * RB) = *reinterpret_cast<const Row*>(src + (size_t)t * RB);
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                }
+            }
+            if (ex) {
+                begin(row);
+                T sh[3] = {T(0), sy, sz};
+                if (staged) win(jm0, jm1, sh, wb, lo);
+                else piece(jm0, jm1, sh);
+                if (b1 >= a1) {
+                    sh[0] = s1;
+                    piece(off[rowbase + a1], min(off[rowbase + b1 + 1], n), sh);
+                }
+                end(row);
+            }
+        }
+    }
+}
+
 // MODE 0: forward sum + record.  MODE 1: adjoint from the record (gy_s gathered
 // into cell order, rows padded as gradient rows).
 template <typename T, int D, int OP, bool BATCH, bool OFF32, int MODE>
@@ -195,34 +295,105 @@ __global__ __launch_bounds__(256) void k_lane_mask(const T* __restrict__ xs, con
                 rec = (rec << 1) | (oa ? 1u : 0u);
             }
         };
+        // candidates [ja, jb) as scan takes them, read from the wave's LDS window
+        // that holds slots [lo, lo + kWindow) (byte offsets from the window start).
+        // An empty run may lie outside the window (its offsets would wrap), so it
+        // returns at once.
+        auto scan_window = [&](auto shift_tag, uint32_t ja, uint32_t jb, const T* sh, uint64_t& rec,
+                               const char* wb, uint32_t lo) {
+            constexpr bool SHIFT = decltype(shift_tag)::value;
+            constexpr uint32_t RB = (uint32_t)sizeof(VecN<T, PITCH>);
+            if (jb <= ja) return;
+            const uint32_t oend = (jb - lo) * RB;
+            const uint32_t olast = oend >= 3u * RB ? oend - 3u * RB : 0u;
+            uint32_t o = (ja - lo) * RB;
+            uint32_t rlo = (uint32_t)rec, rhi = (uint32_t)(rec >> 32);
+            for (; o < olast; o += 4u * RB) {
+                const char* const pj = wb + o;
+                const VecN<T, PITCH> xa = *reinterpret_cast<const VecN<T, PITCH>*>(pj);
+                const VecN<T, PITCH> xb = *reinterpret_cast<const VecN<T, PITCH>*>(pj + RB);
+                const VecN<T, PITCH> xc = *reinterpret_cast<const VecN<T, PITCH>*>(pj + 2u * RB);
+                const VecN<T, PITCH> xd = *reinterpret_cast<const VecN<T, PITCH>*>(pj + 3u * RB);
+                const uint32_t jj = lo + o / RB;
+                T dx[D], d2;
+                const bool oa = pair_test<T, D, SHIFT>(xa.v, xi, sh, r2, dx, &d2);
+                if (oa) visit(jj, dx, d2);
+                const bool ob = pair_test<T, D, SHIFT>(xb.v, xi, sh, r2, dx, &d2);
+                if (ob) visit(jj + 1, dx, d2);
+                const bool oc = pair_test<T, D, SHIFT>(xc.v, xi, sh, r2, dx, &d2);
+                if (oc) visit(jj + 2, dx, d2);
+                const bool od = pair_test<T, D, SHIFT>(xd.v, xi, sh, r2, dx, &d2);
+                if (od) visit(jj + 3, dx, d2);
+                rhi = (rhi << 4) | (rlo >> 28);
+                rlo = (rlo << 4) | (oa ? 8u : 0u) | (ob ? 4u : 0u) | (oc ? 2u : 0u) | (od ? 1u : 0u);
+            }
+            rec = ((uint64_t)rhi << 32) | rlo;
+            for (; o + RB < oend; o += 2u * RB) {
+                const VecN<T, PITCH> xa = *reinterpret_cast<const VecN<T, PITCH>*>(wb + o);
+                const VecN<T, PITCH> xb = *reinterpret_cast<const VecN<T, PITCH>*>(wb + o + RB);
+                const uint32_t jj = lo + o / RB;
+                T dx[D], d2;
+                const bool oa = pair_test<T, D, SHIFT>(xa.v, xi, sh, r2, dx, &d2);
+                if (oa) visit(jj, dx, d2);
+                const bool ob = pair_test<T, D, SHIFT>(xb.v, xi, sh, r2, dx, &d2);
+                if (ob) visit(jj + 1, dx, d2);
+                rec = (rec << 2) | (oa ? 2u : 0u) | (ob ? 1u : 0u);
+            }
+            if (o < oend) {
+                const VecN<T, PITCH> xa = *reinterpret_cast<const VecN<T, PITCH>*>(wb + o);
+                T dx[D], d2;
+                const bool oa = pair_test<T, D, SHIFT>(xa.v, xi, sh, r2, dx, &d2);
+                if (oa) visit(lo + o / RB, dx, d2);
+                rec = (rec << 1) | (oa ? 1u : 0u);
+            }
+        };
         uint64_t rec = 0;  // the current row's bits, most recent lowest
         uint32_t pos = 0;  // candidates of the current row so far
-        for_each_piece<T, D>(
-            P, off, n, xi,
-            [&](int) {
-                rec = 0;
-                pos = 0;
-            },
-            [&](uint32_t j0, uint32_t j1, const T* sh) {
-                bool lane_shift = false;
+        auto begin_row = [&](int) {
+            rec = 0;
+            pos = 0;
+        };
+        auto piece = [&](uint32_t j0, uint32_t j1, const T* sh) {
+            bool lane_shift = false;
 #pragma unroll
-                for (int k = 0; k < D; ++k) lane_shift |= sh[k] != T(0);
-                j1 = max(j1, j0);
-                if (__ballot(lane_shift) != 0ull) scan(std::integral_constant<bool, true>(), j0, j1, sh, rec);
-                else scan(std::integral_constant<bool, false>(), j0, j1, sh, rec);
-                pos += j1 - j0;
-            },
-            [&](int row) {
-                overflow |= pos > (uint32_t)kMaskBits;
-                // c <= 64 bits shifted in put row position k at bit c - 1 - k;
-                // reversed and shifted down by 64 - c it lands at bit k
-                const uint32_t c = min(pos, (uint32_t)kMaskBits);
-                const uint64_t rev = ((uint64_t)__builtin_bitreverse32((uint32_t)rec) << 32) |
-                                     __builtin_bitreverse32((uint32_t)(rec >> 32));
-                const uint64_t m = c == 0u ? 0ull : rev >> (64u - c);
-                masks[(size_t)(2 * row) * n + s] = (uint32_t)m;
-                masks[(size_t)(2 * row + 1) * n + s] = (uint32_t)(m >> 32);
-            });
+            for (int k = 0; k < D; ++k) lane_shift |= sh[k] != T(0);
+            j1 = max(j1, j0);
+            if (__ballot(lane_shift) != 0ull) scan(std::integral_constant<bool, true>(), j0, j1, sh, rec);
+            else scan(std::integral_constant<bool, false>(), j0, j1, sh, rec);
+            pos += j1 - j0;
+        };
+        auto end_row = [&](int row) {
+            overflow |= pos > (uint32_t)kMaskBits;
+            // c <= 64 bits shifted in put row position k at bit c - 1 - k;
+            // reversed and shifted down by 64 - c it lands at bit k
+            const uint32_t c = min(pos, (uint32_t)kMaskBits);
+            const uint64_t rev = ((uint64_t)__builtin_bitreverse32((uint32_t)rec) << 32) |
+                                 __builtin_bitreverse32((uint32_t)(rec >> 32));
+            const uint64_t m = c == 0u ? 0ull : rev >> (64u - c);
+            masks[(size_t)(2 * row) * n + s] = (uint32_t)m;
+            masks[(size_t)(2 * row + 1) * n + s] = (uint32_t)(m >> 32);
+        };
+        if constexpr (sizeof(T) == 4 && OFF32) {
+            if (__ballot(P.n[0] < 2 * P.reach[0] + 1) == 0ull) {
+                // Every grid of the wave is at least 2 m + 1 cells wide: each row's main
+                // runs are staged in LDS (below); otherwise the plain walk.
+                __shared__ VecN<T, PITCH> win[kBlockWaves][kWindow];
+                staged_rows<T, D>(P, off, n, xi, xs, reinterpret_cast<char*>(&win[threadIdx.x >> 6][0]), begin_row,
+                                  piece, end_row, [&](uint32_t j0, uint32_t j1, const T* sh, const char* wb,
+                                                      uint32_t lo) {
+                                      j1 = max(j1, j0);
+                                      if (__ballot(sh[1] != T(0) || sh[2] != T(0)) != 0ull)
+                                          scan_window(std::integral_constant<bool, true>(), j0, j1, sh, rec, wb, lo);
+                                      else
+                                          scan_window(std::integral_constant<bool, false>(), j0, j1, sh, rec, wb, lo);
+                                      pos += j1 - j0;
+                                  });
+            } else {
+                for_each_piece<T, D>(P, off, n, xi, begin_row, piece, end_row);
+            }
+        } else {
+            for_each_piece<T, D>(P, off, n, xi, begin_row, piece, end_row);
+        }
         status[s] = overflow ? kGenNone : gen[0];
         const uint32_t o = perm[s];
 #pragma unroll
