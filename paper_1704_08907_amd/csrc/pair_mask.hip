@@ -96,18 +96,21 @@ constexpr int kWindow = 128;    // slots of a wave's LDS window
 // the wave's LDS window wb when the runs of all its lanes fit in it: lo is the
 // first lane's run start and hi the last lane's run end; if every lane's run
 // lies in [lo, hi) and hi - lo <= kWindow, the lanes copy those slots with
-// coalesced loads and win(j0, j1, sh, wb, lo) scans the run from LDS.  The
+// coalesced loads and win(j0, j1, sh, wb, lo) scans the run from LDS (with
+// G > 0 the rows of a second array ys, G elements each, are copied too and
+// follow the first array's kWindow rows in the window).  The
 // wrapped remainder, and the runs of rows that do not fit, go to piece(j0, j1,
 // sh) as in for_each_piece.  Rows, pieces and slot ranges are those of
 // for_each_piece in the same order, so sums and records are identical.  All
 // lanes of the wave that are still running take part in every row (no lane
 // skips ahead), so the copy and the window reads stay in step.
-template <typename T, int D, typename Begin, typename Piece, typename End, typename Win>
+template <typename T, int D, int G, typename Begin, typename Piece, typename End, typename Win>
 __device__ __forceinline__ void staged_rows(const SysParams<T>& P, const uint32_t* __restrict__ off, uint32_t n,
-                                            const T* xi, const T* __restrict__ xs, char* wb, Begin&& begin,
-                                            Piece&& piece, End&& end, Win&& win) {
+                                            const T* xi, const T* __restrict__ xs, const T* __restrict__ ys,
+                                            char* wb, Begin&& begin, Piece&& piece, End&& end, Win&& win) {
     constexpr int PITCH = Pitch<D>::value;
     constexpr uint32_t RB = (uint32_t)sizeof(VecN<T, PITCH>);
+    constexpr uint32_t RG = (uint32_t)sizeof(VecN<T, (G > 0 ? G : 1)>);
     const uint64_t act = __ballot(true);
     const uint32_t nact = (uint32_t)__popcll(act);
     const uint32_t rank =
@@ -168,6 +171,20 @@ __device__ __forceinline__ void staged_rows(const SysParams<T>& P, const uint32_
                     if (t1 < cnt) *reinterpret_cast<Row*>(wb + t1 * RB) = rb;
                     for (uint32_t t = t1 + nact; t < cnt; t += nact)
                         *reinterpret_cast<Row*>(wb + t * RB) = *reinterpret_cast<const Row*>(src + (size_t)t * RB);
+                    if constexpr (G > 0) {
+                        // the second array's rows, after the first array's window
+                        using RowG = VecN<T, G>;
+                        const char* const sg = reinterpret_cast<const char*>(ys) + (size_t)lo * RG;
+                        char* const wg = wb + (uint32_t)kWindow * RB;
+                        const RowG ga = *reinterpret_cast<const RowG*>(sg + (size_t)min(rank, cnt - 1u) * RG);
+                        const RowG gb = *reinterpret_cast<const RowG*>(sg + (size_t)min(t1, cnt - 1u) * RG);
+                        keep_issued<G>(ga.v);
+                        keep_issued<G>(gb.v);
+                        if (rank < cnt) *reinterpret_cast<RowG*>(wg + rank * RG) = ga;
+                        if (t1 < cnt) *reinterpret_cast<RowG*>(wg + t1 * RG) = gb;
+                        for (uint32_t t = t1 + nact; t < cnt; t += nact)
+                            *reinterpret_cast<RowG*>(wg + t * RG) = *reinterpret_cast<const RowG*>(sg + (size_t)t * RG);
+                    }
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                     __builtin_amdgcn_wave_barrier();
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -378,7 +395,8 @@ __global__ __launch_bounds__(256) void k_lane_mask(const T* __restrict__ xs, con
                 // Every grid of the wave is at least 2 m + 1 cells wide: each row's main
                 // runs are staged in LDS (below); otherwise the plain walk.
                 __shared__ VecN<T, PITCH> win[kBlockWaves][kWindow];
-                staged_rows<T, D>(P, off, n, xi, xs, reinterpret_cast<char*>(&win[threadIdx.x >> 6][0]), begin_row,
+                staged_rows<T, D, 0>(P, off, n, xi, xs, nullptr, reinterpret_cast<char*>(&win[threadIdx.x >> 6][0]),
+                                     begin_row,
                                   piece, end_row, [&](uint32_t j0, uint32_t j1, const T* sh, const char* wb,
                                                       uint32_t lo) {
                                       j1 = max(j1, j0);
@@ -413,7 +431,20 @@ __global__ __launch_bounds__(256) void k_lane_mask(const T* __restrict__ xs, con
         // record in turn (one-word bit operations)
         // (one form for shifted and unshifted pieces: a specialised no-shift form
         // took three more registers, seven waves per SIMD, for no gain)
-        auto replay = [&](uint32_t j0, uint64_t bits64, const T* sh) {
+        // (from HBM, or with WIN from the wave's LDS window, whose xs rows for slots
+        // [lo, lo + kWindow) are followed by the gy rows of the same slots)
+        auto replay = [&](auto win_tag, uint32_t j0, uint64_t bits64, const T* sh, const char* wb, uint32_t lo) {
+            constexpr bool WIN = decltype(win_tag)::value;
+            constexpr uint32_t RBX = (uint32_t)sizeof(VecN<T, PITCH>), RBG = (uint32_t)sizeof(VecN<T, GP>);
+            auto ldx = [&](uint32_t j) {
+                if constexpr (WIN) return *reinterpret_cast<const VecN<T, PITCH>*>(wb + (j - lo) * RBX);
+                else return load_row<T, PITCH, OFF32>(xs, j);
+            };
+            auto ldg = [&](uint32_t j) {
+                if constexpr (WIN)
+                    return *reinterpret_cast<const VecN<T, GP>*>(wb + (uint32_t)kWindow * RBX + (j - lo) * RBG);
+                else return load_row<T, GP, OFF32>(gy_s, j);
+            };
 #pragma unroll 1
             for (uint32_t h = 0; h < 2u; ++h) {
                 uint32_t bits = h ? (uint32_t)(bits64 >> 32) : (uint32_t)bits64;
@@ -427,12 +458,12 @@ __global__ __launch_bounds__(256) void k_lane_mask(const T* __restrict__ xs, con
                     const bool vc = bits != 0u;
                     const uint32_t jc = vc ? base + (uint32_t)__builtin_ctz(bits) : ja;
                     bits &= bits - 1u;
-                    const VecN<T, PITCH> xa = load_row<T, PITCH, OFF32>(xs, ja);
-                    const VecN<T, GP> ga_ = load_row<T, GP, OFF32>(gy_s, ja);
-                    const VecN<T, PITCH> xb = load_row<T, PITCH, OFF32>(xs, jb);
-                    const VecN<T, GP> gb_ = load_row<T, GP, OFF32>(gy_s, jb);
-                    const VecN<T, PITCH> xc = load_row<T, PITCH, OFF32>(xs, jc);
-                    const VecN<T, GP> gc_ = load_row<T, GP, OFF32>(gy_s, jc);
+                    const VecN<T, PITCH> xa = ldx(ja);
+                    const VecN<T, GP> ga_ = ldg(ja);
+                    const VecN<T, PITCH> xb = ldx(jb);
+                    const VecN<T, GP> gb_ = ldg(jb);
+                    const VecN<T, PITCH> xc = ldx(jc);
+                    const VecN<T, GP> gc_ = ldg(jc);
                     T dx[D], d2;
                     (void)pair_test<T, D, true>(xa.v, xi, sh, r2, dx, &d2);
                     pair(ja, dx, d2, ga_.v);
@@ -454,21 +485,42 @@ __global__ __launch_bounds__(256) void k_lane_mask(const T* __restrict__ xs, con
         if (status[s] == gen[0]) {
             uint64_t m = 0;    // the current row's record
             uint32_t pos = 0;  // row position of the next piece's first candidate
-            for_each_piece<T, D>(
-                P, off, n, xi,
-                [&](int row) {
-                    m = (uint64_t)masks[(size_t)(2 * row) * n + s] |
-                        ((uint64_t)masks[(size_t)(2 * row + 1) * n + s] << 32);
-                    pos = 0;
-                },
-                [&](uint32_t j0, uint32_t j1, const T* sh) {
-                    const uint32_t len = j1 > j0 ? j1 - j0 : 0u;
-                    uint64_t bits = pos < 64u ? m >> pos : 0ull;
-                    if (len < 64u) bits &= (1ull << len) - 1ull;
-                    pos += len;
-                    replay(j0, bits, sh);
-                },
-                [&](int) {});
+            auto begin_row = [&](int row) {
+                m = (uint64_t)masks[(size_t)(2 * row) * n + s] | ((uint64_t)masks[(size_t)(2 * row + 1) * n + s] << 32);
+                pos = 0;
+            };
+            // the record's bits of the piece [j0, j1) (a piece past 64 candidates keeps none)
+            auto piece_bits = [&](uint32_t j0, uint32_t j1) {
+                const uint32_t len = j1 > j0 ? j1 - j0 : 0u;
+                uint64_t bits = pos < 64u ? m >> pos : 0ull;
+                if (len < 64u) bits &= (1ull << len) - 1ull;
+                pos += len;
+                return bits;
+            };
+            auto piece = [&](uint32_t j0, uint32_t j1, const T* sh) {
+                const uint64_t bits = piece_bits(j0, j1);
+                replay(std::integral_constant<bool, false>(), j0, bits, sh, nullptr, 0u);
+            };
+            auto end_row = [&](int) {};
+            if constexpr (sizeof(T) == 4 && OFF32) {
+                if (__ballot(P.n[0] < 2 * P.reach[0] + 1) == 0ull) {
+                    // as in the forward: each row's main runs from the wave's LDS window
+                    // (positions, then the gy rows)
+                    constexpr int kWinRows = kWindow * (int)(sizeof(VecN<T, PITCH>) + sizeof(VecN<T, GP>)) /
+                                             (int)sizeof(VecN<T, 4>);
+                    __shared__ VecN<T, 4> win[kBlockWaves][kWinRows];
+                    staged_rows<T, D, GP>(P, off, n, xi, xs, gy_s, reinterpret_cast<char*>(&win[threadIdx.x >> 6][0]),
+                                          begin_row, piece, end_row,
+                                          [&](uint32_t j0, uint32_t j1, const T* sh, const char* wb, uint32_t lo) {
+                                              const uint64_t bits = piece_bits(j0, j1);
+                                              replay(std::integral_constant<bool, true>(), j0, bits, sh, wb, lo);
+                                          });
+                } else {
+                    for_each_piece<T, D>(P, off, n, xi, begin_row, piece, end_row);
+                }
+            } else {
+                for_each_piece<T, D>(P, off, n, xi, begin_row, piece, end_row);
+            }
         } else {
             // no record: the plain row search (not its deferred form, whose
             // registers would lower the replay's occupancy)
