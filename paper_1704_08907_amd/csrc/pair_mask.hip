@@ -428,13 +428,13 @@ __global__ __launch_bounds__(256) void k_lane_mask(const T* __restrict__ xs, con
         };
         // the accepted pairs of one piece, bits64 bit k = its k-th slot from j0: popped
         // three per iteration (their loads overlap), each 32-bit half of the piece's
-        // record in turn (one-word bit operations)
-        // (one form for shifted and unshifted pieces: a specialised no-shift form
-        // took three more registers, seven waves per SIMD, for no gain)
-        // (from HBM, or with WIN from the wave's LDS window, whose xs rows for slots
-        // [lo, lo + kWindow) are followed by the gy rows of the same slots)
-        auto replay = [&](auto win_tag, uint32_t j0, uint64_t bits64, const T* sh, const char* wb, uint32_t lo) {
+        // record in turn (one-word bit operations), from HBM or, with WIN, from the
+        // wave's LDS window, whose xs rows for slots [lo, lo + kWindow) are followed
+        // by the gy rows of the same slots
+        auto replay_s = [&](auto win_tag, auto shift_tag, uint32_t j0, uint64_t bits64, const T* sh, const char* wb,
+                            uint32_t lo) {
             constexpr bool WIN = decltype(win_tag)::value;
+            constexpr bool SHIFT = decltype(shift_tag)::value;
             constexpr uint32_t RBX = (uint32_t)sizeof(VecN<T, PITCH>), RBG = (uint32_t)sizeof(VecN<T, GP>);
             auto ldx = [&](uint32_t j) {
                 if constexpr (WIN) return *reinterpret_cast<const VecN<T, PITCH>*>(wb + (j - lo) * RBX);
@@ -465,22 +465,32 @@ __global__ __launch_bounds__(256) void k_lane_mask(const T* __restrict__ xs, con
                     const VecN<T, PITCH> xc = ldx(jc);
                     const VecN<T, GP> gc_ = ldg(jc);
                     T dx[D], d2;
-                    (void)pair_test<T, D, true>(xa.v, xi, sh, r2, dx, &d2);
+                    (void)pair_test<T, D, SHIFT>(xa.v, xi, sh, r2, dx, &d2);
                     pair(ja, dx, d2, ga_.v);
                     keep_issued<D>(xb.v);
                     keep_issued<NY>(gb_.v);
                     keep_issued<D>(xc.v);
                     keep_issued<NY>(gc_.v);
                     if (vb) {
-                        (void)pair_test<T, D, true>(xb.v, xi, sh, r2, dx, &d2);
+                        (void)pair_test<T, D, SHIFT>(xb.v, xi, sh, r2, dx, &d2);
                         pair(jb, dx, d2, gb_.v);
                     }
                     if (vc) {
-                        (void)pair_test<T, D, true>(xc.v, xi, sh, r2, dx, &d2);
+                        (void)pair_test<T, D, SHIFT>(xc.v, xi, sh, r2, dx, &d2);
                         pair(jc, dx, d2, gc_.v);
                     }
                 }
             }
+        };
+        // the image shift's adds only where some lane of the wave needs them
+        auto replay = [&](auto win_tag, uint32_t j0, uint64_t bits64, const T* sh, const char* wb, uint32_t lo) {
+            bool lane_shift = false;
+#pragma unroll
+            for (int k = 0; k < D; ++k) lane_shift |= sh[k] != T(0);
+            if (__ballot(lane_shift) != 0ull)
+                replay_s(win_tag, std::integral_constant<bool, true>(), j0, bits64, sh, wb, lo);
+            else
+                replay_s(win_tag, std::integral_constant<bool, false>(), j0, bits64, sh, wb, lo);
         };
         if (status[s] == gen[0]) {
             uint64_t m = 0;    // the current row's record
