@@ -17,8 +17,11 @@
 //
 // Replayed pairs are visited in box-search order with dx and d2 recomputed by
 // the same pair test, so forward and adjoint equal the plain lane kernels' bit
-// for bit.  The half-stencil forward below uses the same record layout for the
-// upper half of each stencil.
+// for bit.  Both read each row's main run through a per-wave LDS window
+// (staged_rows): the wave copies the slots its lanes' runs span once, with
+// coalesced loads, instead of every lane gathering its candidates or pairs
+// from HBM.  The half-stencil forward below uses the same record layout for
+// the upper half of each stencil.
 #include "pair_common.hpp"
 
 namespace aboria {
@@ -395,17 +398,16 @@ __global__ __launch_bounds__(256) void k_lane_mask(const T* __restrict__ xs, con
                 // Every grid of the wave is at least 2 m + 1 cells wide: each row's main
                 // runs are staged in LDS (below); otherwise the plain walk.
                 __shared__ VecN<T, PITCH> win[kBlockWaves][kWindow];
+                auto win_piece = [&](uint32_t j0, uint32_t j1, const T* sh, const char* wb, uint32_t lo) {
+                    j1 = max(j1, j0);
+                    if (__ballot(sh[1] != T(0) || sh[2] != T(0)) != 0ull)
+                        scan_window(std::integral_constant<bool, true>(), j0, j1, sh, rec, wb, lo);
+                    else
+                        scan_window(std::integral_constant<bool, false>(), j0, j1, sh, rec, wb, lo);
+                    pos += j1 - j0;
+                };
                 staged_rows<T, D, 0>(P, off, n, xi, xs, nullptr, reinterpret_cast<char*>(&win[threadIdx.x >> 6][0]),
-                                     begin_row,
-                                  piece, end_row, [&](uint32_t j0, uint32_t j1, const T* sh, const char* wb,
-                                                      uint32_t lo) {
-                                      j1 = max(j1, j0);
-                                      if (__ballot(sh[1] != T(0) || sh[2] != T(0)) != 0ull)
-                                          scan_window(std::integral_constant<bool, true>(), j0, j1, sh, rec, wb, lo);
-                                      else
-                                          scan_window(std::integral_constant<bool, false>(), j0, j1, sh, rec, wb, lo);
-                                      pos += j1 - j0;
-                                  });
+                                     begin_row, piece, end_row, win_piece);
             } else {
                 for_each_piece<T, D>(P, off, n, xi, begin_row, piece, end_row);
             }
