@@ -321,39 +321,118 @@ __device__ __forceinline__ bool pair_test(const T* xj, const T* xi, const T* sh,
     return d2 > T(0) && d2 < r2;
 }
 
+// LDS windows of the lane-per-particle kernels.  The lanes of a wave are 64
+// consecutive particles in cell order, so for one stencil row their main runs
+// (the cells up to m away along x) overlap almost entirely, and in slot space
+// their union is one range: from the first lane's run start to the last lane's
+// run end (also when the wave spans the end of one x-row and the start of the
+// next, which are adjacent slots).  When every lane's run lies in that range
+// and it has at most kWindow slots, the wave copies it once into a window of
+// its own with coalesced loads and the lanes read their candidates from LDS.
+constexpr int kBlockWaves = 4;  // waves of a 256-thread workgroup
+constexpr int kWindow = 128;    // slots of a wave's LDS window
+
+// Bytes of one window: kWindow position rows and, with G > 0, as many rows of G
+// elements.
+template <typename T, int D, int G>
+struct WindowBytes {
+    static constexpr uint32_t value =
+        (uint32_t)kWindow *
+        (uint32_t)(sizeof(VecN<T, Pitch<D>::value>) + (G > 0 ? sizeof(VecN<T, (G > 0 ? G : 1)>) : 0));
+};
+
+// Copies slots [lo, lo + cnt) of xs (and, with G > 0, of ys, G elements a row,
+// after the kWindow position rows) into the wave's window wb; rank and nact
+// number the wave's running lanes.  1 <= cnt <= kWindow.
+template <typename T, int D, int G>
+__device__ __forceinline__ void stage_window(const T* __restrict__ xs, const T* __restrict__ ys, char* wb, uint32_t lo,
+                                             uint32_t cnt, uint32_t rank, uint32_t nact) {
+    constexpr int PITCH = Pitch<D>::value;
+    constexpr uint32_t RB = (uint32_t)sizeof(VecN<T, PITCH>);
+    // two slots per lane first, both loads in flight together (a full wave
+    // covers the window with them), then any rest
+    using Row = VecN<T, PITCH>;
+    const char* const src = reinterpret_cast<const char*>(xs) + (size_t)lo * RB;
+    const uint32_t t1 = rank + nact;
+    const Row ra = *reinterpret_cast<const Row*>(src + (size_t)min(rank, cnt - 1u) * RB);
+    const Row rb = *reinterpret_cast<const Row*>(src + (size_t)min(t1, cnt - 1u) * RB);
+    keep_issued<PITCH>(ra.v);
+    keep_issued<PITCH>(rb.v);
+    if (rank < cnt) *reinterpret_cast<Row*>(wb + rank * RB) = ra;
+    if (t1 < cnt) *reinterpret_cast<Row*>(wb + t1 * RB) = rb;
+    for (uint32_t t = t1 + nact; t < cnt; t += nact)
+        *reinterpret_cast<Row*>(wb + t * RB) = *reinterpret_cast<const Row*>(src + (size_t)t * RB);
+    if constexpr (G > 0) {
+        using RowG = VecN<T, (G > 0 ? G : 1)>;
+        constexpr uint32_t RG = (uint32_t)sizeof(RowG);
+        const char* const sg = reinterpret_cast<const char*>(ys) + (size_t)lo * RG;
+        char* const wg = wb + (uint32_t)kWindow * RB;
+        const RowG ga = *reinterpret_cast<const RowG*>(sg + (size_t)min(rank, cnt - 1u) * RG);
+        const RowG gb = *reinterpret_cast<const RowG*>(sg + (size_t)min(t1, cnt - 1u) * RG);
+        keep_issued<G>(ga.v);
+        keep_issued<G>(gb.v);
+        if (rank < cnt) *reinterpret_cast<RowG*>(wg + rank * RG) = ga;
+        if (t1 < cnt) *reinterpret_cast<RowG*>(wg + t1 * RG) = gb;
+        for (uint32_t t = t1 + nact; t < cnt; t += nact)
+            *reinterpret_cast<RowG*>(wg + t * RG) = *reinterpret_cast<const RowG*>(sg + (size_t)t * RG);
+    }
+    // the wave's own LDS operations complete in order
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The window of a staged row as the scans read it: slot j's position row at
+// wb + (j - lo) * RB, its aux row after the kWindow position rows.
+struct WinRef {
+    const char* wb;
+    uint32_t lo;
+};
+
 // One contiguous slot range [j0, j1) of candidates with one image shift:
 // visit(j, dx, d2, shifted) for the accepted ones, shifted = the lane's shift
 // is nonzero in some dimension.  Two candidates are loaded per iteration so
 // their loads overlap.  With NAUX > 0 the candidates' rows of aux (NAUX
 // elements, padded as gradient rows) are loaded with their positions and
 // passed as a fifth argument, so an accepted pair never waits for them.
-template <typename T, int D, bool SHIFT, bool OFF32, int NAUX = 0, typename Visit>
+template <typename T, int D, bool SHIFT, bool OFF32, int NAUX = 0, bool WIN = false, typename Visit>
 __device__ __forceinline__ void scan_range(const T* __restrict__ xs, uint32_t j0, uint32_t j1, const T* xi,
                                            const T* sh, T r2, bool shifted, Visit& visit,
-                                           const T* __restrict__ aux = nullptr) {
+                                           const T* __restrict__ aux = nullptr, WinRef w = WinRef{nullptr, 0u}) {
     constexpr int PITCH = Pitch<D>::value;
     constexpr int AP = NAUX > 0 ? GyPitch<NAUX>::value : 1;
+    constexpr uint32_t RB = (uint32_t)sizeof(VecN<T, PITCH>), RA = (uint32_t)sizeof(VecN<T, AP>);
+    // slot j's rows: from HBM, or with WIN from the window (j inside it)
+    auto ldx = [&](uint32_t jj, uint32_t k) {
+        if constexpr (WIN) return *reinterpret_cast<const VecN<T, PITCH>*>(w.wb + (jj - w.lo + k) * RB);
+        else return load_row_at<T, PITCH, OFF32>(xs, jj, k);
+    };
+    auto lda = [&](uint32_t jj, uint32_t k) {
+        if constexpr (WIN)
+            return *reinterpret_cast<const VecN<T, AP>*>(w.wb + (uint32_t)kWindow * RB + (jj - w.lo + k) * RA);
+        else return load_row_at<T, AP, OFF32>(aux, jj, k);
+    };
     auto call = [&](uint32_t jj, const T* dx, T d2, const VecN<T, AP>& av) {
         if constexpr (NAUX > 0) visit(jj, dx, d2, shifted, av.v);
         else visit(jj, dx, d2, shifted);
     };
     uint32_t j = j0;
     for (; j + 1 < j1; j += 2) {
-        const VecN<T, PITCH> a = load_row<T, PITCH, OFF32>(xs, j);
-        const VecN<T, PITCH> b = load_row_at<T, PITCH, OFF32>(xs, j, 1);
+        const VecN<T, PITCH> a = ldx(j, 0u);
+        const VecN<T, PITCH> b = ldx(j, 1u);
         VecN<T, AP> aa{}, ab{};
         if constexpr (NAUX > 0) {
-            aa = load_row<T, AP, OFF32>(aux, j);
-            ab = load_row_at<T, AP, OFF32>(aux, j, 1);
+            aa = lda(j, 0u);
+            ab = lda(j, 1u);
         }
         T dx[D], d2;
         if (pair_test<T, D, SHIFT>(a.v, xi, sh, r2, dx, &d2)) call(j, dx, d2, aa);
         if (pair_test<T, D, SHIFT>(b.v, xi, sh, r2, dx, &d2)) call(j + 1, dx, d2, ab);
     }
     if (j < j1) {
-        const VecN<T, PITCH> a = load_row<T, PITCH, OFF32>(xs, j);
+        const VecN<T, PITCH> a = ldx(j, 0u);
         VecN<T, AP> aa{};
-        if constexpr (NAUX > 0) aa = load_row<T, AP, OFF32>(aux, j);
+        if constexpr (NAUX > 0) aa = lda(j, 0u);
         T dx[D], d2;
         if (pair_test<T, D, SHIFT>(a.v, xi, sh, r2, dx, &d2)) call(j, dx, d2, aa);
     }
@@ -374,12 +453,22 @@ constexpr bool kDeferAdjoint = OP == ABORIA_OP_SPRING || OP == ABORIA_OP_EXP_FOR
 // as many times per chunk as the busiest lane has accepted pairs, instead of
 // once per candidate that any lane of the wave accepts.  The pairs and their
 // order are those of scan_range, so the sums are bit for bit the same.
-template <typename T, int D, bool SHIFT, bool OFF32, int NAUX, typename Visit>
+template <typename T, int D, bool SHIFT, bool OFF32, int NAUX, bool WIN = false, typename Visit>
 __device__ __forceinline__ void scan_range_deferred(const T* __restrict__ xs, const T* __restrict__ aux,
                                                     uint32_t j0, uint32_t j1, const T* xi, const T* sh, T r2,
-                                                    bool shifted, Visit& visit) {
+                                                    bool shifted, Visit& visit, WinRef w = WinRef{nullptr, 0u}) {
     constexpr int PITCH = Pitch<D>::value;
     constexpr int AP = GyPitch<NAUX>::value;
+    constexpr uint32_t RB = (uint32_t)sizeof(VecN<T, PITCH>), RA = (uint32_t)sizeof(VecN<T, AP>);
+    auto ldx = [&](uint32_t jj, uint32_t k) {
+        if constexpr (WIN) return *reinterpret_cast<const VecN<T, PITCH>*>(w.wb + (jj - w.lo + k) * RB);
+        else return load_row_at<T, PITCH, OFF32>(xs, jj, k);
+    };
+    auto lda = [&](uint32_t jj) {
+        if constexpr (WIN)
+            return *reinterpret_cast<const VecN<T, AP>*>(w.wb + (uint32_t)kWindow * RB + (jj - w.lo) * RA);
+        else return load_row<T, AP, OFF32>(aux, jj);
+    };
     for (uint32_t c0 = j0; c0 < j1; c0 += 32u) {
         const uint32_t c1 = min(c0 + 32u, j1);
         // each test's bit is shifted in from the bottom (the first candidate ends
@@ -387,14 +476,14 @@ __device__ __forceinline__ void scan_range_deferred(const T* __restrict__ xs, co
         uint32_t mask = 0u;
         uint32_t j = c0;
         for (; j + 1 < c1; j += 2) {
-            const VecN<T, PITCH> a = load_row<T, PITCH, OFF32>(xs, j);
-            const VecN<T, PITCH> b = load_row_at<T, PITCH, OFF32>(xs, j, 1);
+            const VecN<T, PITCH> a = ldx(j, 0u);
+            const VecN<T, PITCH> b = ldx(j, 1u);
             T dx[D], d2;
             mask = (mask << 1) | (pair_test<T, D, SHIFT>(a.v, xi, sh, r2, dx, &d2) ? 1u : 0u);
             mask = (mask << 1) | (pair_test<T, D, SHIFT>(b.v, xi, sh, r2, dx, &d2) ? 1u : 0u);
         }
         if (j < c1) {
-            const VecN<T, PITCH> a = load_row<T, PITCH, OFF32>(xs, j);
+            const VecN<T, PITCH> a = ldx(j, 0u);
             T dx[D], d2;
             mask = (mask << 1) | (pair_test<T, D, SHIFT>(a.v, xi, sh, r2, dx, &d2) ? 1u : 0u);
         }
@@ -406,10 +495,10 @@ __device__ __forceinline__ void scan_range_deferred(const T* __restrict__ xs, co
             const bool vb = mask != 0u;
             const uint32_t jb = vb ? c0 + (uint32_t)__builtin_ctz(mask) : ja;
             mask &= mask - 1u;
-            const VecN<T, PITCH> a = load_row<T, PITCH, OFF32>(xs, ja);
-            const VecN<T, AP> ava = load_row<T, AP, OFF32>(aux, ja);
-            const VecN<T, PITCH> b = load_row<T, PITCH, OFF32>(xs, jb);
-            const VecN<T, AP> avb = load_row<T, AP, OFF32>(aux, jb);
+            const VecN<T, PITCH> a = ldx(ja, 0u);
+            const VecN<T, AP> ava = lda(ja);
+            const VecN<T, PITCH> b = ldx(jb, 0u);
+            const VecN<T, AP> avb = lda(jb);
             T dx[D], d2;
             (void)pair_test<T, D, SHIFT>(a.v, xi, sh, r2, dx, &d2);
             visit(ja, dx, d2, shifted, ava.v);
@@ -468,7 +557,7 @@ __device__ __forceinline__ bool wrap_cell(int32_t v, int32_t n, int32_t periodic
 // lane of the wave runs the loop without the shift additions (adding zero is
 // exact, so both loops give the canonical dx).  flat_loop visits the accepted
 // neighbours in this same order.
-template <typename T, int D, bool OFF32, int NAUX, typename Visit>
+template <typename T, int D, bool OFF32, int NAUX, typename Visit, bool STAGE = false>
 __device__ __forceinline__ void neighbour_loop_aux(const SysParams<T>& P, const T* __restrict__ xs,
                                                    const T* __restrict__ aux, const uint32_t* __restrict__ off,
                                                    uint32_t n, const T* xi, Visit&& visit) {
@@ -489,24 +578,82 @@ __device__ __forceinline__ void neighbour_loop_aux(const SysParams<T>& P, const 
         else if (c[0] + M >= nx) { a1 = 0; b1 = c[0] + M - nx; s1 = P.L[0]; }
     }
     const T r2 = P.r2;
-    auto piece = [&](uint32_t ca, uint32_t cb, const T* sh) {
-        const uint32_t j0 = off[ca];
-        const uint32_t j1 = min(off[cb + 1], n);
+    // the candidates [j0, j1), from HBM or (WIN) from the window w
+    auto piece_j = [&](auto win_tag, uint32_t j0, uint32_t j1, const T* sh, WinRef w) {
+        constexpr bool WIN = decltype(win_tag)::value;
         bool lane_shift = false;
 #pragma unroll
         for (int k = 0; k < D; ++k) lane_shift |= sh[k] != T(0);
         if constexpr (NAUX > 0) {
             if (__ballot(lane_shift) != 0ull)
-                scan_range_deferred<T, D, true, OFF32, NAUX>(xs, aux, j0, j1, xi, sh, r2, lane_shift, visit);
+                scan_range_deferred<T, D, true, OFF32, NAUX, WIN>(xs, aux, j0, j1, xi, sh, r2, lane_shift, visit, w);
             else
-                scan_range_deferred<T, D, false, OFF32, NAUX>(xs, aux, j0, j1, xi, sh, r2, false, visit);
+                scan_range_deferred<T, D, false, OFF32, NAUX, WIN>(xs, aux, j0, j1, xi, sh, r2, false, visit, w);
         } else {
             if (__ballot(lane_shift) != 0ull)
-                scan_range<T, D, true, OFF32>(xs, j0, j1, xi, sh, r2, lane_shift, visit);
+                scan_range<T, D, true, OFF32, 0, WIN>(xs, j0, j1, xi, sh, r2, lane_shift, visit, nullptr, w);
             else
-                scan_range<T, D, false, OFF32>(xs, j0, j1, xi, sh, r2, false, visit);
+                scan_range<T, D, false, OFF32, 0, WIN>(xs, j0, j1, xi, sh, r2, false, visit, nullptr, w);
         }
     };
+    auto piece = [&](uint32_t ca, uint32_t cb, const T* sh) {
+        piece_j(std::integral_constant<bool, false>(), off[ca], min(off[cb + 1], n), sh, WinRef{nullptr, 0u});
+    };
+    if constexpr (STAGE && sizeof(T) == 4 && OFF32) {
+        // Every grid of the wave at least 2 m + 1 cells wide, one reach in y and z
+        // for all its lanes, workgroups of at most kBlockWaves waves: each row's
+        // main runs are read through the wave's LDS window when they fit in it.
+        const int32_t zl = D >= 3 ? P.reach[2] : 0, yl = D >= 2 ? P.reach[1] : 0;
+        const int32_t zr = __builtin_amdgcn_readfirstlane(zl), yr = __builtin_amdgcn_readfirstlane(yl);
+        if (__ballot(!wide || zl != zr || yl != yr) == 0ull && blockDim.x <= 64u * kBlockWaves) {
+            constexpr int G = NAUX > 0 ? GyPitch<NAUX>::value : 0;
+            __shared__ VecN<T, 4> win[kBlockWaves][WindowBytes<T, D, G>::value / sizeof(VecN<T, 4>)];
+            char* const wb = reinterpret_cast<char*>(&win[threadIdx.x >> 6][0]);
+            const uint64_t act = __ballot(true);
+            const uint32_t nact = (uint32_t)__popcll(act);
+            const uint32_t rank =
+                __builtin_amdgcn_mbcnt_hi((uint32_t)(act >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0u));
+#pragma unroll 1
+            for (int32_t dz = -zr; dz <= zr; ++dz) {
+#pragma unroll 1
+                for (int32_t dy = -yr; dy <= yr; ++dy) {
+                    int32_t cz = 0, cy = 0;
+                    T sz = T(0), sy = T(0);
+                    const bool ez = D < 3 || wrap_cell(c[2] + dz, P.n[2], P.periodic[2], P.L[2], &cz, &sz);
+                    const bool ey = D < 2 || wrap_cell(c[1] + dy, P.n[1], P.periodic[1], P.L[1], &cy, &sy);
+                    const bool ex = ez && ey;
+                    uint32_t rowbase = 0, jm0 = 0, jm1 = 0;
+                    if (ex) {
+                        rowbase = P.cell_base + (uint32_t)nx * ((uint32_t)cy + (uint32_t)P.n[1] * (uint32_t)cz);
+                        jm0 = off[rowbase + a0];
+                        jm1 = max(min(off[rowbase + b0 + 1], n), jm0);
+                    }
+                    const bool has = jm1 > jm0;
+                    const uint64_t hb = __ballot(has);
+                    bool staged = false;
+                    uint32_t lo = 0;
+                    if (hb != 0ull) {
+                        lo = __builtin_amdgcn_readlane(jm0, __builtin_ctzll(hb));
+                        const uint32_t hi = __builtin_amdgcn_readlane(jm1, 63 - __builtin_clzll(hb));
+                        const bool inside = !has || (jm0 >= lo && jm1 <= hi);
+                        // all inside: the first lane's run gives lo < hi
+                        staged = __ballot(!inside) == 0ull && hi - lo <= (uint32_t)kWindow;
+                        if (staged) stage_window<T, D, G>(xs, aux, wb, lo, hi - lo, rank, nact);
+                    }
+                    if (ex) {
+                        T sh[3] = {T(0), sy, sz};
+                        if (staged) piece_j(std::integral_constant<bool, true>(), jm0, jm1, sh, WinRef{wb, lo});
+                        else piece_j(std::integral_constant<bool, false>(), jm0, jm1, sh, WinRef{nullptr, 0u});
+                        if (b1 >= a1) {
+                            sh[0] = s1;
+                            piece(rowbase + a1, rowbase + b1, sh);
+                        }
+                    }
+                }
+            }
+            return;
+        }
+    }
     const int32_t zr = D >= 3 ? P.reach[2] : 0, yr = D >= 2 ? P.reach[1] : 0;
     for (int32_t dz = -zr; dz <= zr; ++dz) {
         int32_t cz = 0;
@@ -535,12 +682,30 @@ __device__ __forceinline__ void neighbour_loop_aux(const SysParams<T>& P, const 
     }
 }
 
+// neighbour_loop_aux with each row's main runs read through the wave's LDS
+// window where they fit (same pairs, same order, same sums).
+template <typename T, int D, bool OFF32, int NAUX, typename Visit>
+__device__ __forceinline__ void neighbour_loop_aux_staged(const SysParams<T>& P, const T* __restrict__ xs,
+                                                          const T* __restrict__ aux,
+                                                          const uint32_t* __restrict__ off, uint32_t n, const T* xi,
+                                                          Visit&& visit) {
+    neighbour_loop_aux<T, D, OFF32, NAUX, Visit, true>(P, xs, aux, off, n, xi, visit);
+}
+
 // The box search without prefetched per-candidate rows: visit(j, dx, d2, shifted).
 template <typename T, int D, bool OFF32 = false, typename Visit>
 __device__ __forceinline__ void neighbour_loop(const SysParams<T>& P, const T* __restrict__ xs,
                                                const uint32_t* __restrict__ off, uint32_t n, const T* xi,
                                                Visit&& visit) {
     neighbour_loop_aux<T, D, OFF32, 0>(P, xs, nullptr, off, n, xi, visit);
+}
+
+// neighbour_loop with each row's main runs read through the wave's LDS window.
+template <typename T, int D, bool OFF32 = false, typename Visit>
+__device__ __forceinline__ void neighbour_loop_staged(const SysParams<T>& P, const T* __restrict__ xs,
+                                                      const uint32_t* __restrict__ off, uint32_t n, const T* xi,
+                                                      Visit&& visit) {
+    neighbour_loop_aux<T, D, OFF32, 0, Visit, true>(P, xs, nullptr, off, n, xi, visit);
 }
 
 // ---------------------------------------------------------------------------

@@ -41,14 +41,14 @@ __global__ __launch_bounds__(256) void k_lane_bwd(const T* __restrict__ xs, cons
             const T aj = OpShape<OP, D>::NA ? load_row<T, 1, OFF32>(a_s, j).v[0] : T(0);
             Op::bwd(q, r, dx, d2, ai, aj, gyi, gyj, accx, acca);
         };
-        neighbour_loop_aux<T, D, OFF32, NY>(P, xs, gy_s, off, n, xi, visit);
+        neighbour_loop_aux_staged<T, D, OFF32, NY>(P, xs, gy_s, off, n, xi, visit);
     } else {
         auto visit = [&](uint32_t j, const T* dx, T d2, bool) {
             T gyj[NY];
             load_gy<T, NY, OFF32>(gy_s, j, gyj);
             Op::bwd(q, r, dx, d2, ai, T(0), gyi, gyj, accx, acca);
         };
-        neighbour_loop<T, D, OFF32>(P, xs, off, n, xi, visit);
+        neighbour_loop_staged<T, D, OFF32>(P, xs, off, n, xi, visit);
     }
     const uint32_t o = perm[s];
 #pragma unroll
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(256) void k_lane_fused(const T* __restrict__ xs, co
             Op::fwd(q, r, dx, d2, ai, aj, acc);
             Op::bwd(q, r, dx, d2, ai, aj, gyi, gyj, accx, acca);
         };
-        neighbour_loop_aux<T, D, OFF32, NY>(P, xs, gy_s, off, n, xi, visit);
+        neighbour_loop_aux_staged<T, D, OFF32, NY>(P, xs, gy_s, off, n, xi, visit);
     } else {
         auto visit = [&](uint32_t j, const T* dx, T d2, bool) {
             T gyj[NY];
@@ -99,7 +99,7 @@ __global__ __launch_bounds__(256) void k_lane_fused(const T* __restrict__ xs, co
             Op::fwd(q, r, dx, d2, ai, T(0), acc);
             Op::bwd(q, r, dx, d2, ai, T(0), gyi, gyj, accx, acca);
         };
-        neighbour_loop<T, D, OFF32>(P, xs, off, n, xi, visit);
+        neighbour_loop_staged<T, D, OFF32>(P, xs, off, n, xi, visit);
     }
     const uint32_t o = perm[s];
 #pragma unroll

@@ -29,7 +29,7 @@ __global__ __launch_bounds__(256) void k_lane_fwd(const T* __restrict__ xs, cons
         const T aj = OpShape<OP, D>::NA ? load_row<T, 1, OFF32>(a_s, j).v[0] : T(0);
         Op::fwd(q, r, dx, d2, ai, aj, acc);
     };
-    neighbour_loop<T, D, OFF32>(P, xs, off, n, xi, visit);
+    neighbour_loop_staged<T, D, OFF32>(P, xs, off, n, xi, visit);
     const uint32_t o = perm[s];
 #pragma unroll
     for (int k = 0; k < NY; ++k) y[(size_t)o * NY + k] = acc[k];

@@ -91,9 +91,6 @@ __device__ __forceinline__ void for_each_piece(const SysParams<T>& P, const uint
     }
 }
 
-constexpr int kBlockWaves = 4;  // waves of a 256-thread workgroup
-constexpr int kWindow = 128;    // slots of a wave's LDS window
-
 // The walk of for_each_piece on grids at least 2 m + 1 cells wide, with each
 // row's main run (the cells up to m away in x, clipped to the grid) read from
 // the wave's LDS window wb when the runs of all its lanes fit in it: lo is the
@@ -111,9 +108,6 @@ template <typename T, int D, int G, typename Begin, typename Piece, typename End
 __device__ __forceinline__ void staged_rows(const SysParams<T>& P, const uint32_t* __restrict__ off, uint32_t n,
                                             const T* xi, const T* __restrict__ xs, const T* __restrict__ ys,
                                             char* wb, Begin&& begin, Piece&& piece, End&& end, Win&& win) {
-    constexpr int PITCH = Pitch<D>::value;
-    constexpr uint32_t RB = (uint32_t)sizeof(VecN<T, PITCH>);
-    constexpr uint32_t RG = (uint32_t)sizeof(VecN<T, (G > 0 ? G : 1)>);
     const uint64_t act = __ballot(true);
     const uint32_t nact = (uint32_t)__popcll(act);
     const uint32_t rank =
@@ -160,38 +154,7 @@ __device__ __forceinline__ void staged_rows(const SysParams<T>& P, const uint32_
                 const bool inside = !has || (jm0 >= lo && jm1 <= hi);
                 // all inside: the first lane's run gives lo < hi
                 staged = __ballot(!inside) == 0ull && hi - lo <= (uint32_t)kWindow;
-                if (staged) {
-                    // two slots per lane first, both loads in flight together (a full
-                    // wave covers the window with them), then any rest
-                    using Row = VecN<T, PITCH>;
-                    const char* const src = reinterpret_cast<const char*>(xs) + (size_t)lo * RB;
-                    const uint32_t cnt = hi - lo, t1 = rank + nact;  // cnt >= 1
-                    const Row ra = *reinterpret_cast<const Row*>(src + (size_t)min(rank, cnt - 1u) * RB);
-                    const Row rb = *reinterpret_cast<const Row*>(src + (size_t)min(t1, cnt - 1u) * RB);
-                    keep_issued<PITCH>(ra.v);
-                    keep_issued<PITCH>(rb.v);
-                    if (rank < cnt) *reinterpret_cast<Row*>(wb + rank * RB) = ra;
-                    if (t1 < cnt) *reinterpret_cast<Row*>(wb + t1 * RB) = rb;
-                    for (uint32_t t = t1 + nact; t < cnt; t += nact)
-                        *reinterpret_cast<Row*>(wb + t * RB) = *reinterpret_cast<const Row*>(src + (size_t)t * RB);
-                    if constexpr (G > 0) {
-                        // the second array's rows, after the first array's window
-                        using RowG = VecN<T, G>;
-                        const char* const sg = reinterpret_cast<const char*>(ys) + (size_t)lo * RG;
-                        char* const wg = wb + (uint32_t)kWindow * RB;
-                        const RowG ga = *reinterpret_cast<const RowG*>(sg + (size_t)min(rank, cnt - 1u) * RG);
-                        const RowG gb = *reinterpret_cast<const RowG*>(sg + (size_t)min(t1, cnt - 1u) * RG);
-                        keep_issued<G>(ga.v);
-                        keep_issued<G>(gb.v);
-                        if (rank < cnt) *reinterpret_cast<RowG*>(wg + rank * RG) = ga;
-                        if (t1 < cnt) *reinterpret_cast<RowG*>(wg + t1 * RG) = gb;
-                        for (uint32_t t = t1 + nact; t < cnt; t += nact)
-                            *reinterpret_cast<RowG*>(wg + t * RG) = *reinterpret_cast<const RowG*>(sg + (size_t)t * RG);
-                    }
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                }
+                if (staged) stage_window<T, D, G>(xs, ys, wb, lo, hi - lo, rank, nact);
             }
             if (ex) {
                 begin(row);
