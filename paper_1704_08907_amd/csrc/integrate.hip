@@ -54,8 +54,8 @@ __global__ __launch_bounds__(256) void k_integrate(T* __restrict__ x, T* __restr
 }
 
 // The force of every particle by the box search (the lane-per-particle row
-// search, summands in its order), then the particle's Euler update as the
-// epilogue.  In place (SORTED = false): x[o], v[o] with o = perm[s]; the
+// search, summands in its order, rows through the wave's LDS window), then
+// the particle's Euler update as the epilogue.  In place (SORTED = false): x[o], v[o] with o = perm[s]; the
 // search reads the cell-ordered snapshot xs, never x, so updating x in place
 // is safe.  SORTED: the particle in slot s starts from xs[s] (the exact copy of
 // its position) and v[perm[s]], and its new position and velocity go to
@@ -82,7 +82,7 @@ __global__ __launch_bounds__(256) void k_md_step(const T* __restrict__ xs, const
     for (int k = 0; k < D; ++k) acc[k] = T(0);
     const T r = P.r;
     auto visit = [&](uint32_t, const T* dx, T d2, bool) { Op::fwd(q, r, dx, d2, T(0), T(0), acc); };
-    neighbour_loop<T, D, OFF32>(P, xs, off, n, xi, visit);
+    neighbour_loop_staged<T, D, OFF32>(P, xs, off, n, xi, visit);
     const uint32_t o = perm[s];
 #pragma unroll
     for (int k = 0; k < D; ++k) {

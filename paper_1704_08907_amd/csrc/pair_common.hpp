@@ -599,7 +599,7 @@ __device__ __forceinline__ void neighbour_loop_aux(const SysParams<T>& P, const 
     auto piece = [&](uint32_t ca, uint32_t cb, const T* sh) {
         piece_j(std::integral_constant<bool, false>(), off[ca], min(off[cb + 1], n), sh, WinRef{nullptr, 0u});
     };
-    if constexpr (STAGE && sizeof(T) == 4 && OFF32) {
+    if constexpr (STAGE && OFF32) {
         // Every grid of the wave at least 2 m + 1 cells wide, one reach in y and z
         // for all its lanes, workgroups of at most kBlockWaves waves: each row's
         // main runs are read through the wave's LDS window when they fit in it.
