@@ -229,17 +229,27 @@ __global__ __launch_bounds__(256) void k_lane_mask(const T* __restrict__ xs, con
                     const VecN<T, PITCH> xc = *reinterpret_cast<const VecN<T, PITCH>*>(pj + 2u * RB);
                     const VecN<T, PITCH> xd = *reinterpret_cast<const VecN<T, PITCH>*>(pj + 3u * RB);
                     const uint32_t jj = o / RB;
-                    T dx[D], d2;
-                    const bool oa = pair_test<T, D, SHIFT>(xa.v, xi, sh, r2, dx, &d2);
-                    if (oa) visit(jj, dx, d2);
-                    const bool ob = pair_test<T, D, SHIFT>(xb.v, xi, sh, r2, dx, &d2);
-                    if (ob) visit(jj + 1, dx, d2);
-                    const bool oc = pair_test<T, D, SHIFT>(xc.v, xi, sh, r2, dx, &d2);
-                    if (oc) visit(jj + 2, dx, d2);
-                    const bool od = pair_test<T, D, SHIFT>(xd.v, xi, sh, r2, dx, &d2);
-                    if (od) visit(jj + 3, dx, d2);
+                    // the record moves up four places first; each accepted candidate
+                    // then sets its bit inside the branch that adds its summand
                     hi = (hi << 4) | (lo >> 28);
-                    lo = (lo << 4) | (oa ? 8u : 0u) | (ob ? 4u : 0u) | (oc ? 2u : 0u) | (od ? 1u : 0u);
+                    lo <<= 4;
+                    T dx[D], d2;
+                    if (pair_test<T, D, SHIFT>(xa.v, xi, sh, r2, dx, &d2)) {
+                        visit(jj, dx, d2);
+                        lo |= 8u;
+                    }
+                    if (pair_test<T, D, SHIFT>(xb.v, xi, sh, r2, dx, &d2)) {
+                        visit(jj + 1, dx, d2);
+                        lo |= 4u;
+                    }
+                    if (pair_test<T, D, SHIFT>(xc.v, xi, sh, r2, dx, &d2)) {
+                        visit(jj + 2, dx, d2);
+                        lo |= 2u;
+                    }
+                    if (pair_test<T, D, SHIFT>(xd.v, xi, sh, r2, dx, &d2)) {
+                        visit(jj + 3, dx, d2);
+                        lo |= 1u;
+                    }
                 }
                 rec = ((uint64_t)hi << 32) | lo;
                 j = o / RB;
@@ -298,17 +308,27 @@ __global__ __launch_bounds__(256) void k_lane_mask(const T* __restrict__ xs, con
                 const VecN<T, PITCH> xc = *reinterpret_cast<const VecN<T, PITCH>*>(pj + 2u * RB);
                 const VecN<T, PITCH> xd = *reinterpret_cast<const VecN<T, PITCH>*>(pj + 3u * RB);
                 const uint32_t jj = lo + o / RB;
-                T dx[D], d2;
-                const bool oa = pair_test<T, D, SHIFT>(xa.v, xi, sh, r2, dx, &d2);
-                if (oa) visit(jj, dx, d2);
-                const bool ob = pair_test<T, D, SHIFT>(xb.v, xi, sh, r2, dx, &d2);
-                if (ob) visit(jj + 1, dx, d2);
-                const bool oc = pair_test<T, D, SHIFT>(xc.v, xi, sh, r2, dx, &d2);
-                if (oc) visit(jj + 2, dx, d2);
-                const bool od = pair_test<T, D, SHIFT>(xd.v, xi, sh, r2, dx, &d2);
-                if (od) visit(jj + 3, dx, d2);
+                // the record moves up four places first; each accepted candidate then
+                // sets its bit inside the branch that adds its summand
                 rhi = (rhi << 4) | (rlo >> 28);
-                rlo = (rlo << 4) | (oa ? 8u : 0u) | (ob ? 4u : 0u) | (oc ? 2u : 0u) | (od ? 1u : 0u);
+                rlo <<= 4;
+                T dx[D], d2;
+                if (pair_test<T, D, SHIFT>(xa.v, xi, sh, r2, dx, &d2)) {
+                    visit(jj, dx, d2);
+                    rlo |= 8u;
+                }
+                if (pair_test<T, D, SHIFT>(xb.v, xi, sh, r2, dx, &d2)) {
+                    visit(jj + 1, dx, d2);
+                    rlo |= 4u;
+                }
+                if (pair_test<T, D, SHIFT>(xc.v, xi, sh, r2, dx, &d2)) {
+                    visit(jj + 2, dx, d2);
+                    rlo |= 2u;
+                }
+                if (pair_test<T, D, SHIFT>(xd.v, xi, sh, r2, dx, &d2)) {
+                    visit(jj + 3, dx, d2);
+                    rlo |= 1u;
+                }
             }
             rec = ((uint64_t)rhi << 32) | rlo;
             for (; o + RB < oend; o += 2u * RB) {
