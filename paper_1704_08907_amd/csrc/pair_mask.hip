@@ -421,48 +421,51 @@ __global__ __launch_bounds__(256) void k_lane_mask(const T* __restrict__ xs, con
             constexpr bool WIN = decltype(win_tag)::value;
             constexpr bool SHIFT = decltype(shift_tag)::value;
             constexpr uint32_t RBX = (uint32_t)sizeof(VecN<T, PITCH>), RBG = (uint32_t)sizeof(VecN<T, GP>);
-            auto ldx = [&](uint32_t j) {
-                if constexpr (WIN) return *reinterpret_cast<const VecN<T, PITCH>*>(wb + (j - lo) * RBX);
-                else return load_row<T, PITCH, OFF32>(xs, j);
-            };
-            auto ldg = [&](uint32_t j) {
-                if constexpr (WIN)
-                    return *reinterpret_cast<const VecN<T, GP>*>(wb + (uint32_t)kWindow * RBX + (j - lo) * RBG);
-                else return load_row<T, GP, OFF32>(gy_s, j);
-            };
 #pragma unroll 1
             for (uint32_t h = 0; h < 2u; ++h) {
                 uint32_t bits = h ? (uint32_t)(bits64 >> 32) : (uint32_t)bits64;
                 const uint32_t base = j0 + 32u * h;
+                // rows of the half's bit k: slot base + k, at window row base - lo + k
+                // (the window addresses of bit 0 formed once per half)
+                const char* const px = wb + (base - lo) * RBX;
+                const char* const pg = wb + (uint32_t)kWindow * RBX + (base - lo) * RBG;
+                auto ldx = [&](uint32_t k) {
+                    if constexpr (WIN) return *reinterpret_cast<const VecN<T, PITCH>*>(px + k * RBX);
+                    else return load_row<T, PITCH, OFF32>(xs, base + k);
+                };
+                auto ldg = [&](uint32_t k) {
+                    if constexpr (WIN) return *reinterpret_cast<const VecN<T, GP>*>(pg + k * RBG);
+                    else return load_row<T, GP, OFF32>(gy_s, base + k);
+                };
                 while (bits != 0u) {
-                    const uint32_t ja = base + (uint32_t)__builtin_ctz(bits);
+                    const uint32_t ka = (uint32_t)__builtin_ctz(bits);
                     bits &= bits - 1u;
                     const bool vb = bits != 0u;
-                    const uint32_t jb = vb ? base + (uint32_t)__builtin_ctz(bits) : ja;
+                    const uint32_t kb = vb ? (uint32_t)__builtin_ctz(bits) : ka;
                     bits &= bits - 1u;
                     const bool vc = bits != 0u;
-                    const uint32_t jc = vc ? base + (uint32_t)__builtin_ctz(bits) : ja;
+                    const uint32_t kc = vc ? (uint32_t)__builtin_ctz(bits) : ka;
                     bits &= bits - 1u;
-                    const VecN<T, PITCH> xa = ldx(ja);
-                    const VecN<T, GP> ga_ = ldg(ja);
-                    const VecN<T, PITCH> xb = ldx(jb);
-                    const VecN<T, GP> gb_ = ldg(jb);
-                    const VecN<T, PITCH> xc = ldx(jc);
-                    const VecN<T, GP> gc_ = ldg(jc);
+                    const VecN<T, PITCH> xa = ldx(ka);
+                    const VecN<T, GP> ga_ = ldg(ka);
+                    const VecN<T, PITCH> xb = ldx(kb);
+                    const VecN<T, GP> gb_ = ldg(kb);
+                    const VecN<T, PITCH> xc = ldx(kc);
+                    const VecN<T, GP> gc_ = ldg(kc);
                     T dx[D], d2;
                     (void)pair_test<T, D, SHIFT>(xa.v, xi, sh, r2, dx, &d2);
-                    pair(ja, dx, d2, ga_.v);
+                    pair(base + ka, dx, d2, ga_.v);
                     keep_issued<D>(xb.v);
                     keep_issued<NY>(gb_.v);
                     keep_issued<D>(xc.v);
                     keep_issued<NY>(gc_.v);
                     if (vb) {
                         (void)pair_test<T, D, SHIFT>(xb.v, xi, sh, r2, dx, &d2);
-                        pair(jb, dx, d2, gb_.v);
+                        pair(base + kb, dx, d2, gb_.v);
                     }
                     if (vc) {
                         (void)pair_test<T, D, SHIFT>(xc.v, xi, sh, r2, dx, &d2);
-                        pair(jc, dx, d2, gc_.v);
+                        pair(base + kc, dx, d2, gc_.v);
                     }
                 }
             }
