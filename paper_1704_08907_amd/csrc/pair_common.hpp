@@ -464,11 +464,6 @@ __device__ __forceinline__ void scan_range_deferred(const T* __restrict__ xs, co
         if constexpr (WIN) return *reinterpret_cast<const VecN<T, PITCH>*>(w.wb + (jj - w.lo + k) * RB);
         else return load_row_at<T, PITCH, OFF32>(xs, jj, k);
     };
-    auto lda = [&](uint32_t jj) {
-        if constexpr (WIN)
-            return *reinterpret_cast<const VecN<T, AP>*>(w.wb + (uint32_t)kWindow * RB + (jj - w.lo) * RA);
-        else return load_row<T, AP, OFF32>(aux, jj);
-    };
     for (uint32_t c0 = j0; c0 < j1; c0 += 32u) {
         const uint32_t c1 = min(c0 + 32u, j1);
         // each test's bit is shifted in from the bottom (the first candidate ends
@@ -488,17 +483,30 @@ __device__ __forceinline__ void scan_range_deferred(const T* __restrict__ xs, co
             mask = (mask << 1) | (pair_test<T, D, SHIFT>(a.v, xi, sh, r2, dx, &d2) ? 1u : 0u);
         }
         mask = __builtin_bitreverse32(mask) >> (32u - (c1 - c0));
+        // the chunk's bit k is slot c0 + k; with WIN its window rows are at fixed
+        // offsets from those of bit 0, formed once per chunk
+        const char* const pxw = WIN ? w.wb + (c0 - w.lo) * RB : nullptr;
+        const char* const paw = WIN ? w.wb + (uint32_t)kWindow * RB + (c0 - w.lo) * RA : nullptr;
+        auto ldxk = [&](uint32_t k) {
+            if constexpr (WIN) return *reinterpret_cast<const VecN<T, PITCH>*>(pxw + k * RB);
+            else return load_row<T, PITCH, OFF32>(xs, c0 + k);
+        };
+        auto ldak = [&](uint32_t k) {
+            if constexpr (WIN) return *reinterpret_cast<const VecN<T, AP>*>(paw + k * RA);
+            else return load_row<T, AP, OFF32>(aux, c0 + k);
+        };
         // two accepted pairs per iteration, so their four loads overlap
         while (mask != 0u) {
-            const uint32_t ja = c0 + (uint32_t)__builtin_ctz(mask);
+            const uint32_t ka = (uint32_t)__builtin_ctz(mask);
             mask &= mask - 1u;
             const bool vb = mask != 0u;
-            const uint32_t jb = vb ? c0 + (uint32_t)__builtin_ctz(mask) : ja;
+            const uint32_t kb = vb ? (uint32_t)__builtin_ctz(mask) : ka;
             mask &= mask - 1u;
-            const VecN<T, PITCH> a = ldx(ja, 0u);
-            const VecN<T, AP> ava = lda(ja);
-            const VecN<T, PITCH> b = ldx(jb, 0u);
-            const VecN<T, AP> avb = lda(jb);
+            const uint32_t ja = c0 + ka, jb = c0 + kb;
+            const VecN<T, PITCH> a = ldxk(ka);
+            const VecN<T, AP> ava = ldak(ka);
+            const VecN<T, PITCH> b = ldxk(kb);
+            const VecN<T, AP> avb = ldak(kb);
             T dx[D], d2;
             (void)pair_test<T, D, SHIFT>(a.v, xi, sh, r2, dx, &d2);
             visit(ja, dx, d2, shifted, ava.v);
