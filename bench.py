@@ -49,8 +49,7 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 # Algorithmic VALU lane-operations (transcendental instructions -- exp2, sqrt, rsqrt -- issue
-# to their own unit and are counted only inside the per-pair figures below, as the SURVEY
-# unit table does).  Per candidate of the box search: 3 sub, 1 mul, 2 fma, 1 compare.  Per
+# to their own unit and are counted only inside the per-pair figures below).  Per candidate of the box search: 3 sub, 1 mul, 2 fma, 1 compare.  Per
 # accepted pair of the spring forward: about 12 (the reciprocal square root and the force).
 # Per replayed pair: its displacement and squared distance again (3 sub, 1 mul, 2 fma).  Per
 # pair of the spring adjoint: 3 sub for w, 3 for w.dx, 1 for g, 3 mul for w_par's factor and
